@@ -1,0 +1,624 @@
+/*
+ * FP64 CPU oracle for the D2Q37 thermal lattice Boltzmann scheme with a perfectly matched
+ * layer (PML) and open outer boundaries, following arXiv 2504.20169.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the HIP library is
+ * checked against.  Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load it.  It shares no code, header, table or constant with the HIP library: the lattice
+ * weights are re-derived here from the quadrature conditions, the equilibrium is the printed
+ * polynomial (Sec. 2, eq. feq-4), and the characteristic boundary solves S x = L with a generic
+ * elimination instead of a closed-form inverse.
+ *
+ * Units: thermal units (c_s = 1, xi_i = r e_i) for rho, u, T in the equilibrium and moments;
+ * lattice units (dx = dt = 1, integer e_i) for streaming, the PML gradient term and the
+ * characteristic derivatives.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
+ *
+ * Pins (tests/test_oracle_*.py): quadrature moments vs the Gaussian up to degree 9 and the
+ * published D2Q37 weights; equilibrium moments vs Maxwellian moments; exact conservation on a
+ * periodic box; rest and uniform states stationary under every boundary and PML; sigma_max = 0
+ * PML identical to no PML; linear growth of Q under a constant deviation; mirror symmetry;
+ * linear acoustics vs the linearised Navier-Stokes-Fourier solution; ZG+PML reflecting less
+ * than ZG.  PARITY UNPINNED beyond invariants: the characteristic boundary's corner rule, time
+ * level and frame (the paper defers its details to a companion paper); it is pinned only by
+ * uniform-flow invariance, symmetry and the trend that it reflects less than ZG.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define NQ 37
+
+/* ------------------------------------------------------------------------------------------ */
+/* Lattice: Sec. 2 "Velocity stencils".  The D2Q37 set is the minimal ninth-order rule with      */
+/* integer velocities of maximum displacement 3 and non-negative weights.                        */
+/* ------------------------------------------------------------------------------------------ */
+
+static int    LE[NQ][2];   /* integer velocities e_i (lattice units) */
+static double LW[NQ];      /* weights w_i */
+static double LR;          /* scale r: thermal velocity xi_i = r e_i */
+static int    lattice_ok = 0;
+
+/* The eight shells by |e|^2; the grid search below over |ex|,|ey| <= 3 picks exactly these. */
+static const int SHELL_E2[8] = {0, 1, 2, 4, 5, 8, 9, 10};
+
+static int shell_of(int ex, int ey) {
+    int s = ex * ex + ey * ey;
+    for (int k = 0; k < 8; ++k)
+        if (SHELL_E2[k] == s) return k;
+    return -1;
+}
+
+static long double gauss_moment(int a) { /* E[X^a], X ~ N(0,1) */
+    if (a % 2) return 0.0L;
+    long double m = 1.0L;
+    for (int k = a - 1; k > 0; k -= 2) m *= k;
+    return m;
+}
+
+static long double ipow_ld(long double x, int n) {
+    long double p = 1.0L;
+    for (int k = 0; k < n; ++k) p *= x;
+    return p;
+}
+
+/* Dense solve A x = b (n <= 8) by Gaussian elimination with partial pivoting; b <- x. */
+static int solve_ld(int n, long double *A, long double *b) {
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabsl(A[r * n + c]) > fabsl(A[p * n + c])) p = r;
+        if (A[p * n + c] == 0.0L) return -1;
+        if (p != c) {
+            for (int k = 0; k < n; ++k) {
+                long double t = A[c * n + k]; A[c * n + k] = A[p * n + k]; A[p * n + k] = t;
+            }
+            long double t = b[c]; b[c] = b[p]; b[p] = t;
+        }
+        for (int r = c + 1; r < n; ++r) {
+            long double m = A[r * n + c] / A[c * n + c];
+            for (int k = c; k < n; ++k) A[r * n + k] -= m * A[c * n + k];
+            b[r] -= m * b[c];
+        }
+    }
+    for (int c = n - 1; c >= 0; --c) {
+        long double s = b[c];
+        for (int k = c + 1; k < n; ++k) s -= A[c * n + k] * b[k];
+        b[c] = s / A[c * n + c];
+    }
+    return 0;
+}
+
+/* The nine D4-invariant even moment conditions of a degree-9 rule in 2D, X^a Y^b.  The shell
+ * structure makes the mixed conditions dependent among themselves, so the eight solved for the
+ * weights exclude X^8, whose residual then fixes r^2. */
+static const int MOM[9][2] = {{0, 0}, {2, 0}, {4, 0}, {2, 2}, {6, 0},
+                              {4, 2}, {6, 2}, {4, 4}, {8, 0}};
+
+/* Shell sum of e_x^a e_y^b over the integer velocities of shell s. */
+static long double shell_sum(int s, int a, int b) {
+    long double acc = 0.0L;
+    for (int ey = -3; ey <= 3; ++ey)
+        for (int ex = -3; ex <= 3; ++ex)
+            if (shell_of(ex, ey) == s) acc += ipow_ld(ex, a) * ipow_ld(ey, b);
+    return acc;
+}
+
+/* For a trial q = r^2, solve the first eight conditions for the shell weights and return the
+ * residual of the ninth. */
+static int weights_for(long double q, long double w[8], long double *resid) {
+    long double A[64], rhs[8];
+    for (int k = 0; k < 8; ++k) {
+        int a = MOM[k][0], b = MOM[k][1];
+        for (int s = 0; s < 8; ++s) A[k * 8 + s] = shell_sum(s, a, b) * ipow_ld(q, (a + b) / 2);
+        rhs[k] = gauss_moment(a) * gauss_moment(b);
+    }
+    if (solve_ld(8, A, rhs)) return -1;
+    for (int s = 0; s < 8; ++s) w[s] = rhs[s];
+    int a = MOM[8][0], b = MOM[8][1];
+    long double m = 0.0L;
+    for (int s = 0; s < 8; ++s) m += w[s] * shell_sum(s, a, b) * ipow_ld(q, (a + b) / 2);
+    *resid = m - gauss_moment(a) * gauss_moment(b);
+    return 0;
+}
+
+static int build_lattice(void) {
+    if (lattice_ok) return 0;
+    int n = 0;
+    for (int ey = -3; ey <= 3; ++ey)
+        for (int ex = -3; ex <= 3; ++ex)
+            if (shell_of(ex, ey) >= 0) { LE[n][0] = ex; LE[n][1] = ey; ++n; }
+    if (n != NQ) return -1;
+    /* Scan q for sign changes of the ninth residual; keep the root with all weights positive. */
+    long double best_q = -1.0L, best_w[8];
+    long double qa = 0.5L, wa[8], ra;
+    if (weights_for(qa, wa, &ra)) return -1;
+    for (int step = 1; step <= 5000; ++step) {
+        long double qb = 0.5L + step * 0.001L, wb[8], rb;
+        if (weights_for(qb, wb, &rb)) return -1;
+        if ((ra < 0) != (rb < 0)) {
+            long double lo = qa, hi = qb, rlo = ra;
+            for (int it = 0; it < 200; ++it) {
+                long double mid = 0.5L * (lo + hi), wm[8], rm;
+                weights_for(mid, wm, &rm);
+                if ((rm < 0) == (rlo < 0)) { lo = mid; rlo = rm; } else hi = mid;
+            }
+            long double wq[8], rq;
+            weights_for(0.5L * (lo + hi), wq, &rq);
+            int pos = 1;
+            for (int s = 0; s < 8; ++s) pos &= (wq[s] > 0.0L);
+            if (pos) { best_q = 0.5L * (lo + hi); memcpy(best_w, wq, sizeof wq); break; }
+        }
+        qa = qb; ra = rb;
+    }
+    if (best_q < 0) return -1;
+    LR = (double)sqrtl(best_q);
+    for (int i = 0; i < NQ; ++i) LW[i] = (double)best_w[shell_of(LE[i][0], LE[i][1])];
+    lattice_ok = 1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Equilibrium, eq. feq-4 (fourth-order Hermite expansion, c_s = 1, theta = T - 1).  Reading:   */
+/* the factor printed as (c_i^2 - 4) in the theta (u.c)^2 term is (c_i^2 - 6), the value the    */
+/* fourth-order Hermite contraction gives in two dimensions; only with it are mass, momentum    */
+/* and energy moments exact.                                                                    */
+/* ------------------------------------------------------------------------------------------ */
+static void feq37(double rho, double ux, double uy, double T, double out[NQ]) {
+    double th = T - 1.0;
+    double b = ux * ux + uy * uy;
+    for (int i = 0; i < NQ; ++i) {
+        double cx = LR * LE[i][0], cy = LR * LE[i][1];
+        double a = ux * cx + uy * cy;
+        double s = cx * cx + cy * cy;
+        double t1 = a;
+        double t2 = 0.5 * (a * a - b + th * (s - 2.0));
+        double t3 = (a / 6.0) * (a * a - 3.0 * b + 3.0 * th * (s - 4.0));
+        double t4 = (1.0 / 24.0) * (a * a * a * a - 6.0 * a * a * b + 3.0 * b * b
+                                    + 6.0 * th * (a * a * (s - 6.0) + b * (4.0 - s))
+                                    + 3.0 * th * th * (s * s - 8.0 * s + 8.0));
+        out[i] = LW[i] * rho * (1.0 + t1 + t2 + t3 + t4);
+    }
+}
+
+/* Macroscopic moments, eq. macro with the ideal-gas relation e = (d/2) T, d = 2:
+ * rho = sum f, rho u = sum f xi, d rho e = 2 rho T = sum f |xi - u|^2. */
+static void moments37(const double f[NQ], double U[4]) {
+    double rho = 0.0, jx = 0.0, jy = 0.0;
+    for (int i = 0; i < NQ; ++i) {
+        rho += f[i];
+        jx += f[i] * (LR * LE[i][0]);
+        jy += f[i] * (LR * LE[i][1]);
+    }
+    double ux = jx / rho, uy = jy / rho;
+    double e2 = 0.0;
+    for (int i = 0; i < NQ; ++i) {
+        double dx = LR * LE[i][0] - ux, dy = LR * LE[i][1] - uy;
+        e2 += f[i] * (dx * dx + dy * dy);
+    }
+    U[0] = rho; U[1] = ux; U[2] = uy; U[3] = e2 / (2.0 * rho);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Run state                                                                                    */
+/* ------------------------------------------------------------------------------------------ */
+enum { SIDE_XMIN = 0, SIDE_XMAX = 1, SIDE_YMIN = 2, SIDE_YMAX = 3 };
+enum { BC_PERIODIC = 0, BC_ZG = 1, BC_NRBC = 2 };
+
+typedef struct orc_run {
+    int Lx, Ly, Nx, Ny;
+    int pml[4];
+    int W;
+    double sigma_max;
+    int bc[4];
+    double tau, rho0, ux0, uy0, T0;
+    int ready;
+    long step;
+    double *f;   /* post-collision populations f*[node][i] */
+    double *g;   /* post-stream, post-boundary populations */
+    double *Qa;  /* PML auxiliary Q[node][i], full grid (zero outside the Q region) */
+    double *U;   /* U^n = (rho, ux, uy, T) of the post-stream, post-boundary state, [node][4] */
+    double *Un;  /* U^{n+1} */
+    double fbar[NQ];
+} orc_run;
+
+static char orc_err[256];
+const char *orc_last_error(void) { return orc_err; }
+static int fail(const char *m) { snprintf(orc_err, sizeof orc_err, "%s", m); return -1; }
+
+int orc_lattice(int *e, double *w, double *r) {
+    if (build_lattice()) return fail("quadrature solve failed");
+    for (int i = 0; i < NQ; ++i) { e[2 * i] = LE[i][0]; e[2 * i + 1] = LE[i][1]; w[i] = LW[i]; }
+    *r = LR;
+    return 0;
+}
+
+int orc_feq(double rho, double ux, double uy, double T, double *out) {
+    if (build_lattice()) return fail("quadrature solve failed");
+    feq37(rho, ux, uy, T, out);
+    return 0;
+}
+
+int orc_moments_of(const double *f, double *U) {
+    if (build_lattice()) return fail("quadrature solve failed");
+    moments37(f, U);
+    return 0;
+}
+
+orc_run *orc_create(int Lx, int Ly, double tau, double rho0, double ux0, double uy0, double T0) {
+    if (build_lattice()) { fail("quadrature solve failed"); return NULL; }
+    if (Lx < 1 || Ly < 1 || !(tau > 0.5)) { fail("bad size or tau"); return NULL; }
+    orc_run *r = calloc(1, sizeof *r);
+    r->Lx = Lx; r->Ly = Ly; r->tau = tau;
+    r->rho0 = rho0; r->ux0 = ux0; r->uy0 = uy0; r->T0 = T0;
+    for (int s = 0; s < 4; ++s) r->bc[s] = BC_PERIODIC;
+    return r;
+}
+
+void orc_destroy(orc_run *r) {
+    if (!r) return;
+    free(r->f); free(r->g); free(r->Qa); free(r->U); free(r->Un);
+    free(r);
+}
+
+static int open_x(const orc_run *r) { return r->bc[SIDE_XMIN] != BC_PERIODIC; }
+static int open_y(const orc_run *r) { return r->bc[SIDE_YMIN] != BC_PERIODIC; }
+
+int orc_set_pml(orc_run *r, unsigned mask, int W, double sigma_max) {
+    if (r->ready) return fail("configure before init");
+    if (W < 0 || sigma_max < 0) return fail("bad PML");
+    r->W = W; r->sigma_max = sigma_max;
+    for (int s = 0; s < 4; ++s) r->pml[s] = (W > 0) && ((mask >> s) & 1u);
+    return 0;
+}
+
+int orc_set_bc(orc_run *r, unsigned mask, int kind) {
+    if (r->ready) return fail("configure before init");
+    if (kind < 0 || kind > 2) return fail("bad bc");
+    for (int s = 0; s < 4; ++s)
+        if ((mask >> s) & 1u) r->bc[s] = kind;
+    return 0;
+}
+
+static void geometry(orc_run *r) {
+    r->Nx = r->Lx + (r->pml[0] + r->pml[1]) * r->W;
+    r->Ny = r->Ly + (r->pml[2] + r->pml[3]) * r->W;
+}
+
+int orc_grid(orc_run *r, int *Nx, int *Ny) {
+    geometry(r);
+    *Nx = r->Nx; *Ny = r->Ny;
+    return 0;
+}
+
+/* PML ring level of an axis coordinate: W at the outer layer, 1 next to the bulk, 0 in the bulk
+ * (Sec. 3, eq. PML_ramp "i-th level of nodes").  At corners the Chebyshev level is used. */
+static int level_axis(int c, int n, int wlo, int whi) {
+    if (c < wlo) return wlo - c;
+    if (c >= n - whi) return c - (n - whi) + 1;
+    return 0;
+}
+
+static double sigma_at(const orc_run *r, int x, int y) {
+    if (r->W == 0) return 0.0;
+    int lx = level_axis(x, r->Nx, r->pml[0] ? r->W : 0, r->pml[1] ? r->W : 0);
+    int ly = level_axis(y, r->Ny, r->pml[2] ? r->W : 0, r->pml[3] ? r->W : 0);
+    int l = lx > ly ? lx : ly;
+    if (l == 0) return 0.0;
+    double t = (double)l / (double)r->W;
+    return r->sigma_max * t * t;
+}
+
+/* Nodes carrying Q: the PML plus the first bulk ring (central differences at level 1 need Q
+ * next to it), at least three layers deep so the one-sided difference at the outer layer
+ * finds tracked values. */
+static int in_qregion(const orc_run *r, int x, int y) {
+    if (r->W == 0) return 0;
+    int d = r->W + 1 < 3 ? 3 : r->W + 1;
+    return (r->pml[0] && x < d) || (r->pml[1] && x >= r->Nx - d) ||
+           (r->pml[2] && y < d) || (r->pml[3] && y >= r->Ny - d);
+}
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+int orc_init(orc_run *r, const double *rho, const double *ux, const double *uy, const double *T) {
+    if (r->ready) return fail("already initialised");
+    if ((r->bc[0] == BC_PERIODIC) != (r->bc[1] == BC_PERIODIC) ||
+        (r->bc[2] == BC_PERIODIC) != (r->bc[3] == BC_PERIODIC))
+        return fail("periodic must be set on both sides of an axis");
+    for (int s = 0; s < 4; ++s)
+        if (r->pml[s] && r->bc[s] == BC_PERIODIC) return fail("PML on a periodic side");
+    geometry(r);
+    if ((open_x(r) && r->Nx < 7) || (open_y(r) && r->Ny < 7)) return fail("open axis needs N >= 7");
+    size_t nn = (size_t)r->Nx * r->Ny;
+    r->f = malloc(nn * NQ * sizeof(double));
+    r->g = malloc(nn * NQ * sizeof(double));
+    r->Qa = calloc(nn * NQ, sizeof(double));
+    r->U = malloc(nn * 4 * sizeof(double));
+    r->Un = malloc(nn * 4 * sizeof(double));
+    if (!r->f || !r->g || !r->Qa || !r->U || !r->Un) return fail("out of memory");
+    /* Sec. 2 (algorithm outline): initialise to the equilibrium of the given fields; the
+     * stored state is post-collision, and U^0 is the initial field. */
+    for (size_t n = 0; n < nn; ++n) {
+        feq37(rho[n], ux[n], uy[n], T[n], r->f + n * NQ);
+        r->U[4 * n] = rho[n]; r->U[4 * n + 1] = ux[n]; r->U[4 * n + 2] = uy[n]; r->U[4 * n + 3] = T[n];
+    }
+    /* Mean equilibrium of eq. decomp-NJ from the run's mean state. */
+    feq37(r->rho0, r->ux0, r->uy0, r->T0, r->fbar);
+    r->step = 0;
+    r->ready = 1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Characteristic boundary (Sec. 4): LODI analysis of the Euler part along the outward normal,   */
+/* eq. PNR (incoming amplitudes zero) and eq. thermal_LODI_macro_evo advanced by one explicit     */
+/* step.  Primitive variables in the normal frame V = (rho, u_n, u_t, T), p = rho T, gamma = 2:  */
+/* A = S^{-1} Lambda S with Lambda = diag(u_n - c, u_n, u_n, u_n + c), c = sqrt(2T).             */
+/* Reading (the paper defers the solver to a companion paper): the amplitude of an outgoing wave */
+/* k, L_k = lambda_k (S dV/dn)_k, takes the upwind difference over the cell interval that the    */
+/* characteristic crosses in one step, nu_k = lambda_k / r cells (linear interpolation at the    */
+/* foot point x_b - nu_k n); for nu_k <= 1 this is the first-order explicit upwind update, and    */
+/* it stays stable at the D2Q37 sound speed sqrt(2)/r > 1 cell/step.  S is frozen at x_b.  The    */
+/* foot point is limited to two cells (the U^n strips are five layers deep).                      */
+/* ------------------------------------------------------------------------------------------ */
+static void lodi_increment(const orc_run *r, int side, int x, int y, double dU[4]) {
+    int nx = side == SIDE_XMIN ? -1 : side == SIDE_XMAX ? 1 : 0;
+    int ny = side == SIDE_YMIN ? -1 : side == SIDE_YMAX ? 1 : 0;
+    double V[3][4];
+    for (int k = 0; k < 3; ++k) {
+        const double *u = r->U + 4 * ((size_t)(y - k * ny) * r->Nx + (x - k * nx));
+        double un = nx ? nx * u[1] : ny * u[2];
+        double ut = nx ? u[2] : u[1];
+        V[k][0] = u[0]; V[k][1] = un; V[k][2] = ut; V[k][3] = u[3];
+    }
+    double rho = V[0][0], un = V[0][1], T = V[0][3];
+    double c = sqrt(2.0 * T);
+    double lam[4] = {un - c, un, un, un + c};
+    double S[16] = {T, -rho * c, 0, rho,
+                    T, 0, 0, -rho,
+                    0, 0, 1, 0,
+                    T, rho * c, 0, rho};
+    long double Lb[4];
+    for (int k = 0; k < 4; ++k) {
+        double w[3];
+        for (int j = 0; j < 3; ++j) {
+            w[j] = 0.0;
+            for (int m = 0; m < 4; ++m) w[j] += S[4 * k + m] * V[j][m];
+        }
+        if (lam[k] > 0.0) {                    /* outgoing: keep its amplitude */
+            double nu = lam[k] / LR;
+            if (nu > 2.0) nu = 2.0;
+            int j = (int)floor(nu);
+            if (j > 1) j = 1;
+            double phi = nu - j;
+            double wfoot = (1.0 - phi) * w[j] + phi * w[j + 1];
+            Lb[k] = LR * (w[0] - wfoot);       /* = lambda_k (S dV/dn)_k over the crossed interval */
+        } else {
+            Lb[k] = 0.0;                       /* incoming: eq. PNR */
+        }
+    }
+    /* dV/dt = -S^{-1} Lbar (thermal units); one lattice step is 1/r thermal time units per cell. */
+    long double A[16];
+    for (int k = 0; k < 16; ++k) A[k] = S[k];
+    solve_ld(4, A, Lb);
+    double d[4];
+    for (int k = 0; k < 4; ++k) d[k] = -(double)Lb[k] / LR;
+    dU[0] = d[0];
+    dU[3] = d[3];
+    if (nx) { dU[1] = nx * d[1]; dU[2] = d[2]; }
+    else    { dU[2] = ny * d[1]; dU[1] = d[2]; }
+}
+
+static int is_boundary_side(const orc_run *r, int side, int x, int y) {
+    if (r->bc[side] == BC_PERIODIC) return 0;
+    switch (side) {
+    case SIDE_XMIN: return x < 3;
+    case SIDE_XMAX: return x >= r->Nx - 3;
+    case SIDE_YMIN: return y < 3;
+    default:        return y >= r->Ny - 3;
+    }
+}
+
+/* One time step: stream (eq. lbe), boundary (eq. zg-bc or the characteristic Dirichlet fill),
+ * moments (eq. macro), Q update (eq. PMLQ, trapezoid), collision (BGK + eq. PMLCOLL). */
+static void one_step(orc_run *r) {
+    const int Nx = r->Nx, Ny = r->Ny;
+    const int ox = open_x(r), oy = open_y(r);
+
+    /* 1. pull streaming; populations whose source lies outside an open edge are unknown. */
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < Ny; ++y)
+        for (int x = 0; x < Nx; ++x) {
+            double *gn = r->g + ((size_t)y * Nx + x) * NQ;
+            for (int i = 0; i < NQ; ++i) {
+                int sx = x - LE[i][0], sy = y - LE[i][1];
+                int known = 1;
+                if (ox) known &= (sx >= 0 && sx < Nx); else sx = ((sx % Nx) + Nx) % Nx;
+                if (oy) known &= (sy >= 0 && sy < Ny); else sy = ((sy % Ny) + Ny) % Ny;
+                gn[i] = known ? r->f[((size_t)sy * Nx + sx) * NQ + i] : NAN;
+            }
+        }
+
+    /* 2. boundary nodes: the outer three layers of every open side.  ZG copies all q
+     * populations of the adjacent fluid node x_f; the characteristic boundary adds
+     * feq(U_tgt) - feq(U(x_f)) to them (non-equilibrium extrapolation). */
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < Ny; ++y)
+        for (int x = 0; x < Nx; ++x) {
+            int bnd = 0, nrbc = 0;
+            for (int s = 0; s < 4; ++s)
+                if (is_boundary_side(r, s, x, y)) { bnd = 1; nrbc |= (r->bc[s] == BC_NRBC); }
+            if (!bnd) continue;
+            int xf = ox ? clampi(x, 3, Nx - 4) : x;
+            int yf = oy ? clampi(y, 3, Ny - 4) : y;
+            const double *gf = r->g + ((size_t)yf * Nx + xf) * NQ;
+            double *gb = r->g + ((size_t)y * Nx + x) * NQ;
+            if (!nrbc) {
+                for (int i = 0; i < NQ; ++i) gb[i] = gf[i];
+                continue;
+            }
+            const double *Ub = r->U + 4 * ((size_t)y * Nx + x);
+            double Ut[4] = {Ub[0], Ub[1], Ub[2], Ub[3]};
+            for (int s = 0; s < 4; ++s)
+                if (is_boundary_side(r, s, x, y) && r->bc[s] == BC_NRBC) {
+                    double d[4];
+                    lodi_increment(r, s, x, y, d);
+                    for (int k = 0; k < 4; ++k) Ut[k] += d[k];
+                }
+            double Uf[4], ft[NQ], ff[NQ];
+            moments37(gf, Uf);
+            feq37(Ut[0], Ut[1], Ut[2], Ut[3], ft);
+            feq37(Uf[0], Uf[1], Uf[2], Uf[3], ff);
+            for (int i = 0; i < NQ; ++i) gb[i] = ft[i] + (gf[i] - ff[i]);
+        }
+
+    /* 3. moments of the post-stream, post-boundary state. */
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < Ny; ++y)
+        for (int x = 0; x < Nx; ++x) {
+            size_t n = (size_t)y * Nx + x;
+            moments37(r->g + n * NQ, r->Un + 4 * n);
+        }
+
+    /* 4. Q^{n+1} = Q^n + (1/2)(fhat^n + fhat^{n+1}), fhat = feq - fbar (eq. PMLQ, trapezoid). */
+    if (r->W > 0) {
+#pragma omp parallel for schedule(static)
+        for (int y = 0; y < Ny; ++y)
+            for (int x = 0; x < Nx; ++x) {
+                if (!in_qregion(r, x, y)) continue;
+                size_t n = (size_t)y * Nx + x;
+                double e0[NQ], e1[NQ];
+                const double *u0 = r->U + 4 * n, *u1 = r->Un + 4 * n;
+                feq37(u0[0], u0[1], u0[2], u0[3], e0);
+                feq37(u1[0], u1[1], u1[2], u1[3], e1);
+                double *q = r->Qa + n * NQ;
+                for (int i = 0; i < NQ; ++i)
+                    q[i] = q[i] + 0.5 * ((e0[i] - r->fbar[i]) + (e1[i] - r->fbar[i]));
+            }
+    }
+
+    /* 5. collision: BGK, then on PML nodes (sigma > 0) add
+     *    Omega^PML = -sigma (e_i . grad Q_i + 2 fhat_i + sigma Q_i)   (eq. PMLCOLL)
+     * with grad Q central, one-sided at the outermost layer of an open axis (eqs. FD-dx-*). */
+    const double inv_tau = 1.0 / r->tau;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < Ny; ++y)
+        for (int x = 0; x < Nx; ++x) {
+            size_t n = (size_t)y * Nx + x;
+            const double *gn = r->g + n * NQ;
+            const double *u = r->Un + 4 * n;
+            double fe[NQ];
+            feq37(u[0], u[1], u[2], u[3], fe);
+            double *fo = r->f + n * NQ;
+            double sg = sigma_at(r, x, y);
+            for (int i = 0; i < NQ; ++i) fo[i] = gn[i] - inv_tau * (gn[i] - fe[i]);
+            if (sg > 0.0) {
+                for (int i = 0; i < NQ; ++i) {
+                    double d[2];
+                    for (int al = 0; al < 2; ++al) {
+                        int c = al ? y : x, nmax = al ? Ny : Nx, op = al ? oy : ox;
+#define QAT(cc) (al ? r->Qa[((size_t)(cc) * Nx + x) * NQ + i] : r->Qa[((size_t)y * Nx + (cc)) * NQ + i])
+                        if (op && c == 0)
+                            d[al] = -0.5 * (3.0 * QAT(0) - 4.0 * QAT(1) + QAT(2));
+                        else if (op && c == nmax - 1)
+                            d[al] = 0.5 * (3.0 * QAT(nmax - 1) - 4.0 * QAT(nmax - 2) + QAT(nmax - 3));
+                        else {
+                            int cp = c + 1, cm = c - 1;
+                            if (!op) { cp = (cp + nmax) % nmax; cm = (cm + nmax) % nmax; }
+                            d[al] = 0.5 * (QAT(cp) - QAT(cm));
+                        }
+#undef QAT
+                    }
+                    double q = r->Qa[n * NQ + i];
+                    double fhat = fe[i] - r->fbar[i];
+                    double om = -sg * (LE[i][0] * d[0] + LE[i][1] * d[1] + 2.0 * fhat + sg * q);
+                    fo[i] = fo[i] + om;
+                }
+            }
+        }
+
+    double *t = r->U; r->U = r->Un; r->Un = t;
+    r->step += 1;
+}
+
+int orc_step(orc_run *r, long nsteps, int nthreads) {
+    if (!r->ready) return fail("not initialised");
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    for (long k = 0; k < nsteps; ++k) one_step(r);
+    return 0;
+}
+
+long orc_step_count(const orc_run *r) { return r->step; }
+
+int orc_threads(void) { return omp_get_max_threads(); }
+
+/* Moments of the current state (Sec. 2, last step of the algorithm outline): those of the
+ * post-stream, post-boundary populations of the last step; at step 0 those of f*(0). */
+int orc_moments(const orc_run *r, double *rho, double *ux, double *uy, double *T) {
+    if (!r->ready) return fail("not initialised");
+    size_t nn = (size_t)r->Nx * r->Ny;
+    for (size_t n = 0; n < nn; ++n) {
+        double U[4];
+        if (r->step == 0) moments37(r->f + n * NQ, U);
+        else memcpy(U, r->U + 4 * n, sizeof U);
+        if (rho) rho[n] = U[0];
+        if (ux) ux[n] = U[1];
+        if (uy) uy[n] = U[2];
+        if (T) T[n] = U[3];
+    }
+    return 0;
+}
+
+/* Post-collision populations, layout [i][y][x] in this file's velocity order. */
+int orc_populations(const orc_run *r, double *out) {
+    if (!r->ready) return fail("not initialised");
+    size_t nn = (size_t)r->Nx * r->Ny;
+    for (int i = 0; i < NQ; ++i)
+        for (size_t n = 0; n < nn; ++n) out[(size_t)i * nn + n] = r->f[n * NQ + i];
+    return 0;
+}
+
+int orc_pml_q(const orc_run *r, double *out) {
+    if (!r->ready) return fail("not initialised");
+    size_t nn = (size_t)r->Nx * r->Ny;
+    for (int i = 0; i < NQ; ++i)
+        for (size_t n = 0; n < nn; ++n) out[(size_t)i * nn + n] = r->Qa[n * NQ + i];
+    return 0;
+}
+
+int orc_sigma(orc_run *r, double *out) {
+    geometry(r);
+    for (int y = 0; y < r->Ny; ++y)
+        for (int x = 0; x < r->Nx; ++x) out[(size_t)y * r->Nx + x] = sigma_at(r, x, y);
+    return 0;
+}
+
+/* Global relative L2 errors over the bulk (Sec. 5 "Reference Simulation"):
+ * e_Z = sqrt( sum_bulk ((Z - Zref)/Zref)^2 ), Z in {rho, ux, T}; references are bulk-sized
+ * Ly x Lx arrays; the sum runs in row-major order. */
+int orc_error_norms(const orc_run *r, const double *ref_rho, const double *ref_ux,
+                    const double *ref_T, double out[3]) {
+    if (!r->ready) return fail("not initialised");
+    int x0 = r->pml[0] ? r->W : 0, y0 = r->pml[2] ? r->W : 0;
+    size_t nn = (size_t)r->Nx * r->Ny;
+    double *rho = malloc(nn * sizeof(double)), *ux = malloc(nn * sizeof(double)),
+           *T = malloc(nn * sizeof(double));
+    orc_moments(r, rho, ux, NULL, T);
+    double s[3] = {0, 0, 0};
+    for (int y = 0; y < r->Ly; ++y)
+        for (int x = 0; x < r->Lx; ++x) {
+            size_t n = (size_t)(y + y0) * r->Nx + (x + x0), m = (size_t)y * r->Lx + x;
+            double a = (rho[n] - ref_rho[m]) / ref_rho[m];
+            double b = (ux[n] - ref_ux[m]) / ref_ux[m];
+            double c = (T[n] - ref_T[m]) / ref_T[m];
+            s[0] += a * a; s[1] += b * b; s[2] += c * c;
+        }
+    free(rho); free(ux); free(T);
+    for (int k = 0; k < 3; ++k) out[k] = sqrt(s[k]);
+    return 0;
+}

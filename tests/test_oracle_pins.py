@@ -1,0 +1,326 @@
+"""Pins for the FP64 oracle against what the paper and the mathematics fix (CPU only).
+
+Each test checks the oracle against something other than its own formulas: published weights,
+Gaussian and Maxwellian moments, conservation laws, exact invariants, symmetry, linear acoustic
+theory, and the paper's qualitative accuracy claims.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2504_20169_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gauss_moment(a):
+    return 0.0 if a % 2 else float(np.prod(np.arange(a - 1, 0, -2))) if a > 0 else 1.0
+
+
+def _normal_moment(a, mu, var):
+    """E[X^a] for X ~ N(mu, var): sum_k C(a, 2k) mu^(a-2k) var^k (2k-1)!!."""
+    return sum(math.comb(a, 2 * k) * mu ** (a - 2 * k) * var ** k * _gauss_moment(2 * k)
+               for k in range(a // 2 + 1))
+
+
+def test_weights_match_published_table(oracle_mod):
+    """The oracle solves the quadrature conditions itself; the result must equal the published
+    D2Q37 weights and scale (golden fixture, Sec. 2 velocity stencils)."""
+    e, w, r = oracle_mod.lattice()
+    lines = [l.split() for l in open(os.path.join(GOLDEN, "d2q37_weights.txt"))
+             if l.strip() and not l.startswith("#")]
+    table = {int(a): float(b) for a, b in lines}
+    r_pub = float([l for l in open(os.path.join(GOLDEN, "d2q37_weights.txt"))
+                   if l.startswith("# r ")][0].split()[2])
+    assert abs(r - r_pub) < 1e-15
+    assert len(e) == 37 and len({(a, b) for a, b in e}) == 37
+    for (ex, ey), wi in zip(e, w):
+        assert abs(wi - table[ex * ex + ey * ey]) <= 1e-16 + 1e-14 * wi
+    assert abs(w.sum() - 1.0) < 1e-15
+
+
+def test_quadrature_is_exact_to_degree_nine(oracle_mod):
+    """Every monomial X^a Y^b with a + b <= 9 (odd and mixed ones included, beyond the nine
+    conditions the solve used) integrates exactly against the standard normal."""
+    e, w, r = oracle_mod.lattice()
+    xi = r * e.astype(float)
+    for a in range(10):
+        for b in range(10 - a):
+            got = np.sum(w * xi[:, 0] ** a * xi[:, 1] ** b)
+            want = _gauss_moment(a) * _gauss_moment(b)
+            assert abs(got - want) < 2e-12 * max(1.0, abs(want)), (a, b, got, want)
+    # and degree 10 is NOT exact (the rule is ninth order)
+    got = np.sum(w * xi[:, 0] ** 10)
+    assert abs(got - _gauss_moment(10)) > 1.0
+
+
+@pytest.mark.parametrize("state", [(1.0, 0.0, 0.0, 1.0), (1.03, 0.11, -0.07, 0.95),
+                                   (0.9, -0.2, 0.15, 1.1), (1.2, 0.05, 0.3, 0.8)])
+def test_equilibrium_moments_are_maxwellian(oracle_mod, state):
+    """eq. feq-4 (with the (c^2 - 6) reading) reproduces every raw moment up to fourth order of
+    the Maxwellian rho N(u, T I) exactly; a dropped term or the printed (c^2 - 4) fails here."""
+    rho, ux, uy, T = state
+    e, w, r = oracle_mod.lattice()
+    xi = r * e.astype(float)
+    f = oracle_mod.feq(rho, ux, uy, T)
+    for a in range(5):
+        for b in range(5 - a):
+            got = np.sum(f * xi[:, 0] ** a * xi[:, 1] ** b)
+            want = rho * _normal_moment(a, ux, T) * _normal_moment(b, uy, T)
+            assert abs(got - want) < 1e-13 * max(1.0, abs(want)), (a, b)
+
+
+def test_rest_equilibrium_is_weights(oracle_mod):
+    e, w, r = oracle_mod.lattice()
+    assert np.array_equal(oracle_mod.feq(1.0, 0.0, 0.0, 1.0), w)
+
+
+def test_moments_invert_equilibrium(oracle_mod):
+    for state in [(1.03, 0.11, -0.07, 0.95), (0.97, -0.02, 0.04, 1.02)]:
+        U = oracle_mod.moments_of(oracle_mod.feq(*state))
+        assert np.allclose(U, state, rtol=0, atol=1e-14)
+
+
+def _conserved(o, xi):
+    f = o.populations().sum(axis=(1, 2))
+    return np.array([f.sum(), (f * xi[:, 0]).sum(), (f * xi[:, 1]).sum(),
+                     (f * (xi ** 2).sum(1)).sum()])
+
+
+def test_conservation_on_periodic_box(oracle_mod):
+    """BGK with the fixed equilibrium conserves mass, momentum and energy to rounding."""
+    e, w, r = oracle_mod.lattice()
+    xi = r * e.astype(float)
+    o = oracle_mod.OracleRun(23, 19, 0.8)
+    F = wl.noisy_state(23, 19, seed=7, ux0=0.05, amp=2e-3)
+    o.init(*F.as_tuple())
+    c0 = _conserved(o, xi)
+    o.step(300)
+    c1 = _conserved(o, xi)
+    assert np.all(np.abs(c1 - c0) <= 5e-13 * np.abs(c0).max()), c1 - c0
+
+
+@pytest.mark.parametrize("bc", [oracle_mod_bc for oracle_mod_bc in (1, 2)])
+@pytest.mark.parametrize("W,sig", [(0, 0.0), (4, 0.1)])
+def test_uniform_flow_is_stationary(oracle_mod, bc, W, sig):
+    """A uniform state equal to the mean state stays put under ZG, the characteristic boundary
+    and the PML: fhat = 0 gives Q = 0 and no PML force, the LODI derivatives vanish, ZG copies
+    equal values."""
+    o = oracle_mod.OracleRun(12, 10, 0.8, 1.0, 0.1, -0.05, 1.0)
+    if W:
+        o.set_pml(15, W, sig)
+    o.set_bc(15, bc)
+    Nx, Ny = o.grid()
+    o.init(*wl.uniform_state(Nx, Ny, 1.0, 0.1, -0.05, 1.0).as_tuple())
+    f0 = o.populations()
+    o.step(40)
+    assert np.abs(o.populations() - f0).max() < 1e-14
+
+
+@pytest.mark.parametrize("bc", [1, 2])
+def test_sigma_zero_pml_equals_no_pml(oracle_mod, bc):
+    """sigma_max = 0 on a W-wide layer reproduces the plain scheme on the same grid bit for
+    bit (the PML term is added last, eq. PMLCOLL)."""
+    W, L = 5, 14
+    a = oracle_mod.OracleRun(L, L, 0.8, 1.0, 0.05, 0.0, 1.0)
+    a.set_pml(15, W, 0.0)
+    a.set_bc(15, bc)
+    b = oracle_mod.OracleRun(L + 2 * W, L + 2 * W, 0.8, 1.0, 0.05, 0.0, 1.0)
+    b.set_bc(15, bc)
+    assert a.grid() == b.grid()
+    F = wl.noisy_state(*a.grid(), seed=3, ux0=0.05)
+    a.init(*F.as_tuple())
+    b.init(*F.as_tuple())
+    a.step(25)
+    b.step(25)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+def test_q_grows_linearly_under_constant_deviation(oracle_mod):
+    """With sigma = 0 and a uniform state off the mean state, fhat is constant in time, so the
+    trapezoid rule integrates eq. PMLQ exactly: Q^n = n fhat on the Q region, 0 elsewhere."""
+    W = 4
+    o = oracle_mod.OracleRun(10, 10, 0.8, 1.0, 0.0, 0.0, 1.0)
+    o.set_pml(15, W, 0.0)
+    o.set_bc(15, 1)
+    Nx, Ny = o.grid()
+    state = (1.01, 0.02, -0.01, 1.005)
+    o.init(*wl.uniform_state(Nx, Ny, *state).as_tuple())
+    n = 17
+    o.step(n)
+    fhat = oracle_mod.feq(*state) - oracle_mod.feq(1.0, 0.0, 0.0, 1.0)
+    Q = o.pml_q()
+    d = W + 1
+    region = np.zeros((Ny, Nx), bool)
+    region[:, :d] = region[:, -d:] = region[:d, :] = region[-d:, :] = True
+    assert np.abs(Q[:, region].T - n * fhat).max() <= 1e-12 * np.abs(n * fhat).max()
+    assert np.all(Q[:, ~region] == 0.0)
+
+
+def test_sigma_ramp(oracle_mod):
+    """eq. PML_ramp: sigma = sigma_max (l/W)^2 on ring level l (Chebyshev level at corners)."""
+    W, L, smax = 6, 10, 0.3
+    o = oracle_mod.OracleRun(L, L, 0.8)
+    o.set_pml(15, W, smax)
+    o.set_bc(15, 1)
+    s = o.sigma()
+    N = L + 2 * W
+    assert s[N // 2, 0] == pytest.approx(smax)
+    assert s[N // 2, W - 1] == pytest.approx(smax / W ** 2)
+    assert s[N // 2, W] == 0.0 and s[N // 2, N - 1 - W] == 0.0
+    assert s[N // 2, N - W] == pytest.approx(smax / W ** 2)
+    assert s[1, 3] == pytest.approx(smax * ((W - 1) / W) ** 2)  # Chebyshev level max(W-3, W-1)
+
+
+@pytest.mark.parametrize("bc,W", [(1, 6), (2, 6), (2, 0)])
+def test_mirror_symmetry(oracle_mod, bc, W):
+    """A centred pulse at rest on a square grid stays symmetric under x and y mirrors and the
+    transpose: catches a wrong side, sign or index in the boundary, PML or corner handling."""
+    L = 20
+    o = oracle_mod.OracleRun(L, L, 0.8)
+    if W:
+        o.set_pml(15, W, 0.1)
+    o.set_bc(15, bc)
+    Nx, Ny = o.grid()
+    F = wl.uniform_state(Nx, Ny)
+    wl.add_gaussian_pulse(F, (Nx - 1) / 2, (Ny - 1) / 2, 1e-3, 3.0)
+    F.T = F.T + (F.rho - 1.0) * 0.5
+    o.init(*F.as_tuple())
+    o.step(45)
+    rho, ux, uy, T = o.moments()
+    tol = 1e-14
+    assert np.abs(rho - rho[:, ::-1]).max() < tol
+    assert np.abs(rho - rho[::-1, :]).max() < tol
+    assert np.abs(rho - rho.T).max() < tol
+    assert np.abs(ux + ux[:, ::-1]).max() < tol
+    assert np.abs(ux - uy.T).max() < tol
+    assert np.abs(rho - 1.0).max() > 1e-5  # the pulse reached the boundary region
+
+
+def _linear_nsf(drho0, dT0, k, t, r, tau):
+    """Linearised Navier-Stokes-Fourier (D=2, gamma=2, Pr=1, zero bulk viscosity) in lattice
+    units about rho=1, u=0, T=1: modes (rho, u, T) evolve by expm(M t), with sound speed
+    sqrt(2)/r and viscosity nu = (tau - 1/2)/r^2 (Sec. 2, Chapman-Enskog)."""
+    from scipy.linalg import expm
+    nu = (tau - 0.5) / r ** 2
+    out_r = np.zeros_like(drho0)
+    for j, kk in enumerate(k):
+        M = np.array([[0, -1j * kk / r, 0],
+                      [-1j * kk / r, -nu * kk ** 2, -1j * kk / r],
+                      [0, -1j * kk / r, -2 * nu * kk ** 2]])
+        v = expm(M * t) @ np.array([drho0[j], 0.0, dT0[j]])
+        out_r[j] = v[0]
+    return out_r
+
+
+def test_linear_acoustics_matches_nsf_theory(oracle_mod):
+    """A small plane density pulse on a periodic line follows linearised NSF theory: the sound
+    speed is sqrt(2)/r cells/step and all modes decay at nu k^2.  Pins weights, scale r, tau,
+    the equilibrium and the streaming direction together."""
+    e, w, r = oracle_mod.lattice()
+    N, A, b, tau, t = 256, 1e-4, 4.0, 0.8, 40
+    o = oracle_mod.OracleRun(N, 1, tau)
+    F = wl.uniform_state(N, 1)
+    x = np.arange(N, dtype=float)
+    F.rho = (1.0 + A * np.power(2.0, -((x - 128.0) ** 2) / b ** 2))[None, :]
+    o.init(*F.as_tuple())
+    o.step(t)
+    rho = o.moments()[0][0]
+    k = 2 * np.pi * np.fft.fftfreq(N)
+    pred = np.real(np.fft.ifft(_linear_nsf(np.fft.fft(F.rho[0] - 1.0), np.zeros(N), k, t, r, tau)))
+    err = np.abs((rho - 1.0) - pred).max() / A
+    assert err < 5e-3, err
+    # the acoustic peak travelled sqrt(2)/r * t cells
+    right = np.argmax(rho[140:]) + 140
+    assert abs((right - 128.0) - math.sqrt(2.0) / r * t) < 1.0
+
+
+def _reference_bulk(oracle_mod, L, W, steps, make):
+    """Periodic reference on an extended grid (Sec. 5 "Reference Simulation"), cut to the
+    bulk of the open-boundary run."""
+    pad = int(math.ceil(1.19 * steps)) + 8
+    Nref = L + 2 * W + 2 * pad
+    ref = oracle_mod.OracleRun(Nref, Nref, 0.8)
+    ref.init(*make(Nref, pad + W).as_tuple())
+    ref.step(steps)
+    m = ref.moments()
+    s = slice(pad + W, pad + W + L)
+    return [z[s, s] for z in m]
+
+
+def test_pml_zg_reflects_far_less_than_zg(oracle_mod):
+    """Sec. 5.1: ZG behind a PML lowers the reflection error by about two orders of magnitude
+    over plain ZG, and a too-strong sigma_max raises it again (interface mismatch).  Pulse at
+    rest, bulk 32^2, W = 12, error after 25 steps against a periodic reference."""
+    L, steps = 32, 25
+
+    def make(N, off):
+        F = wl.uniform_state(N, N)
+        c = off + (L - 1) / 2
+        return wl.add_gaussian_pulse(F, c, c, 1e-3, 4.0)
+
+    def err(W, sig):
+        o = oracle_mod.OracleRun(L, L, 0.8)
+        if W:
+            o.set_pml(15, W, sig)
+        o.set_bc(15, 1)
+        N = L + 2 * W
+        o.init(*make(N, W).as_tuple())
+        o.step(steps)
+        rr = _reference_bulk(oracle_mod, L, W, steps, make)[0]
+        rho = o.moments()[0][W:W + L, W:W + L]
+        return np.sqrt(np.sum((rho - rr) ** 2))
+
+    e_zg = err(0, 0.0)
+    e_pml = err(12, 0.05)
+    e_strong = err(12, 0.5)
+    assert e_pml < e_zg / 30.0, (e_pml, e_zg)
+    assert e_strong > 5.0 * e_pml, (e_strong, e_pml)
+
+
+def test_characteristic_bc_reflects_less_than_zg(oracle_mod):
+    """Sec. 5.1: for one-dimensional dynamics the LODI boundary beats ZG without a PML.  A plane
+    pulse leaves through the x edges of a periodic-in-y strip."""
+    L, steps, N = 40, 45, 40
+
+    def run(bc):
+        o = oracle_mod.OracleRun(L, 4, 0.8)
+        o.set_bc(1 | 2, bc)
+        F = wl.uniform_state(L, 4)
+        x = np.arange(L, dtype=float)
+        F.rho = np.broadcast_to(1.0 + 1e-3 * np.power(2.0, -((x - 19.5) ** 2) / 16.0), (4, L)).copy()
+        o.init(*F.as_tuple())
+        o.step(steps)
+        return o.moments()[0]
+
+    def ref():
+        pad = 80
+        o = oracle_mod.OracleRun(L + 2 * pad, 4, 0.8)
+        x = np.arange(L + 2 * pad, dtype=float)
+        F = wl.uniform_state(L + 2 * pad, 4)
+        F.rho = np.broadcast_to(1.0 + 1e-3 * np.power(2.0, -((x - 19.5 - pad) ** 2) / 16.0),
+                                (4, L + 2 * pad)).copy()
+        o.init(*F.as_tuple())
+        o.step(steps)
+        return o.moments()[0][:, pad:pad + L]
+
+    rr = ref()
+    e_zg = np.abs(run(1) - rr).max()
+    e_cbc = np.abs(run(2) - rr).max()
+    assert e_cbc < 0.5 * e_zg, (e_cbc, e_zg)
+
+
+def test_error_norm_definition(oracle_mod):
+    """e_Z of Sec. 5: a single node off by a relative eps gives e_Z = eps."""
+    o = oracle_mod.OracleRun(8, 8, 0.8, 1.0, 0.1, 0.0, 1.0)
+    o.set_pml(15, 3, 0.1)
+    o.set_bc(15, 1)
+    Nx, Ny = o.grid()
+    o.init(*wl.uniform_state(Nx, Ny, 1.0, 0.1, 0.0, 1.0).as_tuple())
+    rho, ux, uy, T = [z[3:11, 3:11].copy() for z in o.moments()]
+    rho[2, 5] *= 1.0 / (1.0 + 1e-3)
+    got = o.error_norms(rho, ux, T)
+    assert got[0] == pytest.approx(1e-3, rel=1e-9)
+    assert got[1] < 1e-13 and got[2] < 1e-13
