@@ -1,0 +1,219 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D2Q37 thermal lattice Boltzmann library with a
+ * perfectly matched layer (PML) and open outer boundaries, after arXiv 2504.20169.
+ *
+ * One time step follows Sec. 2 (algorithm outline) and Secs. 3-4:
+ *   pull streaming  f_i(x, n+1) = f*_i(x - e_i, n)                      (eq. lbe)
+ *   outer boundary  zero-gradient copy from x_f (eq. zg-bc), or the characteristic
+ *                   non-reflecting fill feq(U_tgt) + f^neq(x_f) (eqs. PNR,
+ *                   thermal_LODI_macro_evo and the non-equilibrium extrapolation)
+ *   moments         rho, u, T (eq. macro, e = (d/2) T)
+ *   PML auxiliary   Q^{n+1} = Q^n + (fhat^n + fhat^{n+1})/2 (eq. PMLQ, trapezoid rule)
+ *   collision       f* = f - (f - feq)/tau - sigma (e.grad Q + 2 fhat + sigma Q)
+ *                   (BGK with eq. feq-4 and eq. PMLCOLL; sigma ramp eq. PML_ramp)
+ *
+ * Units: rho, u, T in thermal units (sound-speed unit c_s = 1, xi_i = r e_i with the D2Q37
+ * scale r = 1.19698...); lengths and times in lattice units (one cell, one step).
+ *
+ * Grid: the bulk is nx x ny; every side carrying a PML of width W adds W layers, so the full
+ * grid is Nx = nx + W*(#PML x-sides), Ny likewise.  The outermost 3 layers of an open side are
+ * its boundary nodes (and, with a PML, also its PML levels W, W-1, W-2).  Host field arrays are
+ * row-major [Ny][Nx] float64; population arrays are [37][Ny][Nx] float64 in the order returned
+ * by lbm_velocities().
+ *
+ * Conventions: every call returns an lbm_status; no exception or abort crosses the ABI.
+ * lbm_last_error() returns a thread-local message for the last failure.  Configuration order:
+ * lbm_create -> lbm_set_pml / lbm_set_bc -> lbm_init_fields -> lbm_step...; setters after
+ * lbm_init_fields return LBM_ERR_STATE.  A handle is used by one host thread at a time.  Work
+ * is enqueued on the run's HIP stream; device faults surface at the next synchronising call
+ * (lbm_moments, lbm_populations, lbm_error_norms, lbm_check, lbm_synchronize).  Host arrays
+ * are caller-owned and copied; device memory is library-owned, obtained through the optional
+ * allocator hook.
+ */
+#ifndef PAPER_2504_20169_LBM_H
+#define PAPER_2504_20169_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_run *lbm_handle;
+typedef struct lbm_group *lbm_group_handle;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_ERR_ARG = 1,         /* invalid argument (message says which) */
+    LBM_ERR_STATE = 2,       /* call not allowed in the handle's current state */
+    LBM_ERR_OOM = 3,         /* device allocation failed */
+    LBM_ERR_DEVICE = 4,      /* a HIP call failed */
+    LBM_ERR_UNSTABLE = 5,    /* lbm_check found a non-finite value, rho <= 0 or T <= 0 */
+    LBM_ERR_UNSUPPORTED = 6
+} lbm_status;
+
+/* Population storage.  LBM_F64 stores f - fbar in float64 and computes in float64.
+ * LBM_F32_DEV stores f - fbar in float32 and computes in float32.  LBM_F16_DEV stores
+ * (f - fbar) * s in float16 with a per-run power-of-two scale s, computing in float32.  fbar
+ * is the mean equilibrium feq(rho0, u0, T0) of eq. decomp-NJ (the rest weights w_i when the
+ * mean state is rho0 = T0 = 1, u0 = 0).  The characteristic boundary and the error norms
+ * always compute in float64. */
+typedef enum { LBM_F64 = 0, LBM_F32_DEV = 1, LBM_F16_DEV = 2 } lbm_storage;
+
+/* Side masks. */
+enum { LBM_XMIN = 1, LBM_XMAX = 2, LBM_YMIN = 4, LBM_YMAX = 8, LBM_ALL = 15 };
+
+/* Outer-edge treatment of a side.  PERIODIC must be set on both sides of an axis. */
+typedef enum { LBM_BC_PERIODIC = 0, LBM_BC_ZG = 1, LBM_BC_NRBC = 2 } lbm_bc;
+
+/* Optional device allocator: alloc returns device memory of at least `bytes` (256-byte
+ * aligned) or NULL; free releases it.  Used for every device buffer of a run or group. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} lbm_allocator;
+
+typedef struct {
+    int32_t nx, ny;              /* bulk size, >= 1 */
+    double tau;                  /* BGK relaxation time, > 0.5 (Sec. 2) */
+    double rho0, ux0, uy0, T0;   /* mean state: fbar, PML target and deviation reference */
+    int32_t storage;             /* lbm_storage */
+    double f16_scale;            /* LBM_F16_DEV: scale s (power of two); 0 = chosen at init */
+    const lbm_allocator *allocator; /* NULL = hipMalloc / hipFree */
+    void *stream;                /* hipStream_t to enqueue on; NULL = a stream the run owns */
+} lbm_desc;
+
+/* Kernel tile shape (set by lbm_set_launch or lbm_autotune).  bulk_tx in {64,128,256}
+ * nodes along x, bulk_ty rows per block with bulk_tx*bulk_ty = 256; graph_steps: steps per
+ * captured HIP graph in lbm_step (even, 0 disables graphs). */
+typedef struct {
+    int32_t bulk_tx, bulk_ty;
+    int32_t graph_steps;
+} lbm_launch;
+
+/* Create a run (Sec. 2).  Validates the descriptor (LBM_ERR_ARG: tau <= 0.5, size < 1,
+ * non-finite mean state, rho0 <= 0, T0 <= 0, unknown storage).  No device memory is touched
+ * until lbm_init_fields.  *out receives the handle (caller owns it until lbm_destroy). */
+lbm_status lbm_create(const lbm_desc *desc, lbm_handle *out);
+
+/* PML of width W on the sides in side_mask with ramp sigma(l) = sigma_max (l/W)^2 on ring
+ * level l = 1..W (eq. PML_ramp; Chebyshev level at corners).  W = 0 removes it.  Errors:
+ * LBM_ERR_ARG for W < 0, sigma_max < 0 or non-finite; LBM_ERR_STATE after init. */
+lbm_status lbm_set_pml(lbm_handle h, unsigned side_mask, int32_t W, double sigma_max);
+
+/* Outer-edge treatment for the sides in side_mask (Sec. 4).  Default: periodic on all
+ * sides.  Errors: LBM_ERR_ARG for an unknown kind; LBM_ERR_STATE after init.  Consistency
+ * (periodic on both sides of an axis, no PML on a periodic side, N >= 7 on an open axis) is
+ * checked by lbm_init_fields. */
+lbm_status lbm_set_bc(lbm_handle h, unsigned side_mask, lbm_bc kind);
+
+/* Full grid size (bulk plus PML layers) for the current configuration. */
+lbm_status lbm_grid(lbm_handle h, int32_t *Nx, int32_t *Ny);
+
+/* Node counts of the run's kernel classes for the current configuration: out[0] interior
+ * nodes updated by the branch-free bulk kernel, out[1] frame nodes (boundary layers, PML and
+ * moment strips) updated by the frame kernel, out[2] PML Q-region nodes (phase A). */
+lbm_status lbm_node_classes(lbm_handle h, int64_t out[3]);
+
+/* Bytes of device memory the run holds once initialised (populations, PML Q, moment strips,
+ * descriptor), for admission control. */
+lbm_status lbm_footprint(lbm_handle h, size_t *bytes);
+
+/* Allocate device state and set f*(x, 0) = feq(rho, u, T)(x), Q = 0 (Sec. 2 algorithm
+ * outline; eq. PMLQ).  rho, ux, uy, T: host float64 [Ny][Nx], copied.  Errors: LBM_ERR_ARG
+ * for NULL, non-finite, rho <= 0 or T <= 0 inputs or an inconsistent configuration;
+ * LBM_ERR_OOM; LBM_ERR_STATE if already initialised.  Synchronises the stream. */
+lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux,
+                           const double *uy, const double *T);
+
+/* Advance nsteps >= 0 time steps, asynchronously on the run's stream. */
+lbm_status lbm_step(lbm_handle h, int64_t nsteps);
+
+/* Steps taken since init. */
+lbm_status lbm_step_count(lbm_handle h, int64_t *steps);
+
+#define LBM_DEVICE_PTRS 1u
+/* Moments (rho, ux, uy, T) of the post-stream, post-boundary populations of the last step
+ * (Sec. 2; eq. macro); after 0 steps those of f*(0).  Each output is [Ny][Nx] float64; NULL
+ * skips it.  flags & LBM_DEVICE_PTRS: outputs are device pointers (stream-ordered), else host
+ * pointers (the call synchronises). */
+lbm_status lbm_moments(lbm_handle h, double *rho, double *ux, double *uy, double *T,
+                       unsigned flags);
+
+/* Post-collision populations f*(x, n) as float64 [37][Ny][Nx] host array (fbar + stored
+ * deviation), in lbm_velocities() order.  Synchronises. */
+lbm_status lbm_populations(lbm_handle h, double *f);
+
+/* PML auxiliary field Q (eq. PMLQ) as float64 [37][Ny][Nx] host array, zero outside the Q
+ * region.  Synchronises. */
+lbm_status lbm_pml_q(lbm_handle h, double *Q);
+
+/* The library's D2Q37 velocity order: e[2*i], e[2*i+1] integer lattice vector of
+ * population i; w[i] its weight; *r the thermal scale (xi = r e).  Host only; any pointer
+ * may be NULL. */
+lbm_status lbm_velocities(int32_t *e, double *w, double *r);
+
+/* Global relative L2 errors of Sec. 5 (Reference Simulation) over the bulk,
+ * e_Z = sqrt(sum ((Z - Zref)/Zref)^2) for Z = rho, ux, T, accumulated in float64 in a fixed
+ * order.  ref_*: host float64 [ny][nx] bulk arrays.  out[3] host.  Synchronises. */
+lbm_status lbm_error_norms(lbm_handle h, const double *ref_rho, const double *ref_ux,
+                           const double *ref_T, double out[3]);
+
+/* Scan the current state for non-finite values, rho <= 0 or T <= 0: LBM_OK or
+ * LBM_ERR_UNSTABLE.  Synchronises. */
+lbm_status lbm_check(lbm_handle h);
+
+/* Wait for the run's stream. */
+lbm_status lbm_synchronize(lbm_handle h);
+
+/* Tile shape; takes effect at the next lbm_step.  LBM_ERR_ARG for unsupported shapes. */
+lbm_status lbm_set_launch(lbm_handle h, const lbm_launch *cfg);
+lbm_status lbm_get_launch(lbm_handle h, lbm_launch *cfg);
+
+/* Time every supported bulk tile shape on a scratch copy of this run's geometry (the run's
+ * own state is untouched) and keep the fastest; if cache_path is non-NULL the choice is read
+ * from / appended to that text file keyed by (Nx, Ny, storage).  *chosen may be NULL. */
+lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path,
+                        lbm_launch *chosen);
+
+/* Per-kernel-class timing with HIP events on the run's stream (the wall time of the
+ * boundary/PML kernels vs the bulk kernel; Sec. 5 "Computational Cost").  Enabling it makes
+ * lbm_step launch eagerly (no graphs).  lbm_profile_read synchronises and returns the summed
+ * milliseconds and launch counts since the last reset: ms[0] bulk, ms[1] boundary/PML frame,
+ * ms[2] PML phase A; launches[0..2] likewise. */
+lbm_status lbm_profile(lbm_handle h, int enable);
+lbm_status lbm_profile_read(lbm_handle h, double ms[3], int64_t launches[3], int reset);
+
+/* Checkpoint: write / read the full state (populations, Q, moment strips, step count,
+ * configuration) to a binary file with a header and checksum.  lbm_load needs a handle
+ * created and configured identically and initialised (any fields). */
+lbm_status lbm_save(lbm_handle h, const char *path);
+lbm_status lbm_load(lbm_handle h, const char *path);
+
+void lbm_destroy(lbm_handle h);
+
+const char *lbm_last_error(void);
+
+/* ---- Batched runs: one launch per kernel class advances many independent runs ---------- */
+
+/* A group advances its runs together on one stream; it does not own the runs.  Runs keep
+ * their own state; a run may belong to one group at a time. */
+lbm_status lbm_group_create(void *stream, const lbm_allocator *allocator,
+                            lbm_group_handle *out);
+lbm_status lbm_group_add(lbm_group_handle g, lbm_handle h);
+lbm_status lbm_group_remove(lbm_group_handle g, lbm_handle h);
+/* Advance every member: run k by steps[k] steps (steps may be NULL: all by nsteps), in
+ * member order as added; the group issues max(steps) batched steps and a run stops after its
+ * own count.  Asynchronous. */
+lbm_status lbm_group_step(lbm_group_handle g, const int64_t *steps, int64_t nsteps);
+lbm_status lbm_group_size(lbm_group_handle g, int32_t *n);
+lbm_status lbm_group_synchronize(lbm_group_handle g);
+void lbm_group_destroy(lbm_group_handle g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_2504_20169_LBM_H */

@@ -1,0 +1,1038 @@
+// C ABI (include/lbm.h) and host runtime: run handles, geometry and tile classification,
+// device buffers through the allocator hook, step sequencing with HIP graphs, per-class
+// timing, batched groups, autotuning and checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(LBM_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t elem_size(int storage) { return storage == ST_F64 ? 8 : storage == ST_F32 ? 4 : 2; }
+size_t compute_size(int storage) { return storage == ST_F64 ? 8 : 4; }
+long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
+
+struct DeviceMem {
+    const lbm_allocator *alloc = nullptr;
+    std::vector<void *> ptrs;
+    void *get(size_t bytes) {
+        void *p = nullptr;
+        bytes = (size_t)round_up((long long)std::max<size_t>(bytes, 256), 256);
+        if (alloc && alloc->alloc) p = alloc->alloc(bytes, alloc->ctx);
+        else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+        if (p) ptrs.push_back(p);
+        return p;
+    }
+    void put(void *p) {
+        if (!p) return;
+        auto it = std::find(ptrs.begin(), ptrs.end(), p);
+        if (it != ptrs.end()) ptrs.erase(it);
+        if (alloc && alloc->free) alloc->free(p, alloc->ctx);
+        else (void)hipFree(p);
+    }
+    void release_all() {
+        for (void *p : ptrs) {
+            if (alloc && alloc->free) alloc->free(p, alloc->ctx);
+            else (void)hipFree(p);
+        }
+        ptrs.clear();
+    }
+};
+
+int tx_index(int tx) { return tx == 64 ? 0 : tx == 128 ? 1 : 2; }
+
+}  // namespace
+
+struct lbm_run {
+    lbm_desc desc{};
+    lbm_allocator alloc_copy{};
+    int pml[4] = {0, 0, 0, 0};
+    int W = 0;
+    double sigma_max = 0.0;
+    int bc[4] = {BC_PERIODIC, BC_PERIODIC, BC_PERIODIC, BC_PERIODIC};
+    bool inited = false;
+    RunDev hd{};
+    RunDev *dd = nullptr;
+    RunDev **dptr = nullptr;
+    int *dprefix = nullptr;   // bulk[2], frame[2], q[2]
+    int nblocks[3] = {0, 0, 0};
+    double fbar[NQ];
+    double *fbar_d = nullptr;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;     // stream in use (the group's while in a group)
+    lbm_launch launch{64, 4, 32};
+    int64_t steps = 0;
+    DeviceMem mem;
+    hipGraphExec_t graph = nullptr;
+    int graph_G = 0;
+    int graph_tx = 0;
+    bool graph_failed = false;
+    bool prof = false;
+    struct Ev { hipEvent_t a, b; int cls; };
+    std::vector<Ev> pending;
+    std::vector<hipEvent_t> pool;
+    double prof_ms[3] = {0, 0, 0};
+    int64_t prof_n[3] = {0, 0, 0};
+    lbm_group *group = nullptr;
+    size_t footprint = 0;
+};
+
+struct lbm_group {
+    hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    lbm_allocator alloc_copy{};
+    DeviceMem mem;
+    std::vector<lbm_run *> members;
+    bool dirty = true;
+    int storage = -1;
+    int tx = 64;
+    RunDev **druns = nullptr;
+    int *dprefix = nullptr;
+    long long *dlimits = nullptr;
+    long long *hlimits = nullptr;     // pinned
+    hipEvent_t upload_done = nullptr;
+    bool upload_pending = false;
+    int blocks[3] = {0, 0, 0};
+    size_t cap = 0;
+};
+
+namespace {
+
+// ---- geometry ------------------------------------------------------------------------------
+lbm_status setup_geometry(lbm_run *h, RunDev &R) {
+    const lbm_desc &d = h->desc;
+    R.Wxm = h->pml[XMIN] ? h->W : 0;
+    R.Wxp = h->pml[XMAX] ? h->W : 0;
+    R.Wym = h->pml[YMIN] ? h->W : 0;
+    R.Wyp = h->pml[YMAX] ? h->W : 0;
+    R.Nx = d.nx + R.Wxm + R.Wxp;
+    R.Ny = d.ny + R.Wym + R.Wyp;
+    R.W = h->W;
+    for (int s = 0; s < 4; ++s) R.bc[s] = h->bc[s];
+    if ((h->bc[XMIN] == BC_PERIODIC) != (h->bc[XMAX] == BC_PERIODIC) ||
+        (h->bc[YMIN] == BC_PERIODIC) != (h->bc[YMAX] == BC_PERIODIC))
+        return fail(LBM_ERR_ARG, "periodic must be set on both sides of an axis");
+    for (int s = 0; s < 4; ++s)
+        if (h->pml[s] && h->W > 0 && h->bc[s] == BC_PERIODIC)
+            return fail(LBM_ERR_ARG, "PML on a periodic side");
+    R.open_x = h->bc[XMIN] != BC_PERIODIC;
+    R.open_y = h->bc[YMIN] != BC_PERIODIC;
+    if ((R.open_x && R.Nx < 7) || (R.open_y && R.Ny < 7))
+        return fail(LBM_ERR_ARG, "an open axis needs at least 7 nodes (3 boundary + 1 + 3)");
+    if ((long long)R.Nx * R.Ny > (1LL << 30)) return fail(LBM_ERR_ARG, "grid too large");
+    R.qd = std::max(h->W + 1, 3);
+    int depth[4];
+    for (int s = 0; s < 4; ++s) {
+        int g = 3;
+        if (h->bc[s] == BC_NRBC) g = std::max(g, 5);
+        if (h->pml[s] && h->W > 0) g = std::max(g, R.qd);
+        depth[s] = g;
+    }
+    R.gxm = std::min(depth[XMIN], R.Nx);
+    R.gxp = std::min(depth[XMAX], R.Nx - R.gxm);
+    R.gym = std::min(depth[YMIN], R.Ny);
+    R.gyp = std::min(depth[YMAX], R.Ny - R.gym);
+    R.fx0 = R.gxm; R.fx1 = R.Nx - R.gxp;
+    R.fy0 = R.gym; R.fy1 = R.Ny - R.gyp;
+    long long fast = (long long)std::max(0, R.fx1 - R.fx0) * std::max(0, R.fy1 - R.fy0);
+    R.frame_n = (int)((long long)R.Nx * R.Ny - fast);
+    R.has_q = h->W > 0 && (h->pml[0] || h->pml[1] || h->pml[2] || h->pml[3]);
+    R.pitch = (int)round_up(R.Nx, 64);
+    R.plane = round_up((long long)R.pitch * R.Ny, 64);
+    R.qplane = round_up(std::max(R.frame_n, 1), 64);
+    for (int k = 0; k < 3; ++k) {
+        int tx = 64 << k, ty = 256 / tx;
+        if (fast > 0) {
+            int xa = (R.fx0 / tx) * tx;
+            R.tiles_x[k] = (R.fx1 - xa + tx - 1) / tx;
+            R.tiles_y[k] = (R.fy1 - R.fy0 + ty - 1) / ty;
+        } else {
+            R.tiles_x[k] = 0;
+            R.tiles_y[k] = 0;
+        }
+    }
+    return LBM_OK;
+}
+
+// Mean-state Hermite coefficients of the equilibrium (see lbm_kernels.hip).
+void fill_constants(lbm_run *h, RunDev &R) {
+    const lbm_desc &d = h->desc;
+    R.storage = d.storage;
+    R.omega = 1.0 / d.tau;
+    R.rho0 = d.rho0; R.u0x = d.ux0; R.u0y = d.uy0; R.T0 = d.T0;
+    R.th0 = d.T0 - 1.0;
+    R.b0 = d.ux0 * d.ux0 + d.uy0 * d.uy0;
+    R.r0x = LAT_R * d.ux0; R.r0y = LAT_R * d.uy0;
+    R.sigma_max = h->sigma_max;
+    R.inv_W2 = h->W > 0 ? 1.0 / ((double)h->W * h->W) : 0.0;
+    const double th0 = R.th0, b0 = R.b0;
+    const double k0 = 1.0 - 0.5 * b0 - th0 + 0.125 * b0 * b0 + th0 * b0 + th0 * th0;
+    const double k1 = 1.0 - 0.5 * b0 - 2.0 * th0;
+    const double k2a = 0.5 - 0.25 * b0 - 1.5 * th0;
+    const double k2s = 0.5 * th0 - 0.25 * th0 * b0 - th0 * th0;
+    double E0[NSHELL];
+    for (int s = 0; s < NSHELL; ++s) {
+        double sv = LAT_R2 * SHELL_E2[s];
+        E0[s] = k0 + k2s * sv + 0.125 * th0 * th0 * sv * sv;
+        R.E2_0[s] = k2a + 0.25 * th0 * sv;
+        R.O1_0[s] = k1 + 0.5 * th0 * sv;
+    }
+    R.H0rest = k0;
+    h->fbar[0] = SHELL_W[0] * d.rho0 * k0;
+    for (int p = 0; p < NPAIR; ++p) {
+        int sh = PSH[p];
+        double a0 = PEX[p] * R.r0x + PEY[p] * R.r0y;
+        R.H0e[p] = E0[sh] + R.E2_0[sh] * a0 * a0 + a0 * a0 * a0 * a0 / 24.0;
+        R.H0o[p] = a0 * (R.O1_0[sh] + a0 * a0 / 6.0);
+        h->fbar[1 + 2 * p] = SHELL_W[sh] * d.rho0 * (R.H0e[p] + R.H0o[p]);
+        h->fbar[2 + 2 * p] = SHELL_W[sh] * d.rho0 * (R.H0e[p] - R.H0o[p]);
+    }
+    R.omega_f = (float)R.omega; R.rho0_f = (float)R.rho0; R.u0x_f = (float)R.u0x;
+    R.u0y_f = (float)R.u0y; R.th0_f = (float)R.th0; R.b0_f = (float)R.b0;
+    R.r0x_f = (float)R.r0x; R.r0y_f = (float)R.r0y; R.T0_f = (float)R.T0;
+    R.H0rest_f = (float)R.H0rest;
+    for (int p = 0; p < NPAIR; ++p) { R.H0e_f[p] = (float)R.H0e[p]; R.H0o_f[p] = (float)R.H0o[p]; }
+    for (int s = 0; s < NSHELL; ++s) { R.E2_0_f[s] = (float)R.E2_0[s]; R.O1_0_f[s] = (float)R.O1_0[s]; }
+    R.scale = 1.0; R.inv_scale = 1.0;
+}
+
+void set_scale(RunDev &R, double s) {
+    R.scale = s; R.inv_scale = 1.0 / s;
+    R.scale_f = (float)s; R.inv_scale_f = (float)(1.0 / s);
+}
+
+size_t footprint_of(const RunDev &R, int storage) {
+    size_t b = 2 * (size_t)NQ * R.plane * elem_size(storage);
+    if (R.has_q) b += (size_t)NQ * R.qplane * compute_size(storage);
+    b += 2 * 4 * (size_t)R.qplane * sizeof(double);
+    b += sizeof(RunDev) + 256 * 3 + NQ * sizeof(double);
+    return b;
+}
+
+void compute_blocks(const RunDev &R, int tx, int nb[3]) {
+    int k = tx_index(tx);
+    nb[0] = R.tiles_x[k] * R.tiles_y[k];
+    nb[1] = (R.frame_n + FRAME_BLOCK - 1) / FRAME_BLOCK;
+    nb[2] = R.has_q ? nb[1] : 0;
+}
+
+lbm_status upload_prefix(lbm_run *h) {
+    compute_blocks(h->hd, h->launch.bulk_tx, h->nblocks);
+    int pre[6] = {0, h->nblocks[0], 0, h->nblocks[1], 0, h->nblocks[2]};
+    HIP_TRY(hipMemcpyAsync(h->dprefix, pre, sizeof pre, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+LaunchSet single_set(lbm_run *h) {
+    LaunchSet L;
+    L.runs = h->dptr;
+    L.bulk_prefix = h->dprefix;
+    L.frame_prefix = h->dprefix + 2;
+    L.q_prefix = h->dprefix + 4;
+    L.nruns = 1;
+    L.bulk_blocks = h->nblocks[0];
+    L.frame_blocks = h->nblocks[1];
+    L.q_blocks = h->nblocks[2];
+    return L;
+}
+
+hipEvent_t take_event(lbm_run *h) {
+    if (!h->pool.empty()) {
+        hipEvent_t e = h->pool.back();
+        h->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+// One step of a launch set: phase A, frame, bulk, flip.
+lbm_status enqueue_step(const LaunchSet &L, int storage, int tx, hipStream_t s, lbm_run *prof) {
+    hipEvent_t ev[6] = {};
+    if (prof)
+        for (int k = 0; k < 6; ++k) ev[k] = take_event(prof);
+    if (prof && L.q_blocks > 0) HIP_TRY(hipEventRecord(ev[4], s));
+    HIP_TRY(launch_phase_a(L, storage, s));
+    if (prof && L.q_blocks > 0) HIP_TRY(hipEventRecord(ev[5], s));
+    if (prof) HIP_TRY(hipEventRecord(ev[2], s));
+    HIP_TRY(launch_frame(L, storage, s));
+    if (prof) HIP_TRY(hipEventRecord(ev[3], s));
+    if (prof && L.bulk_blocks > 0) HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(launch_bulk(L, storage, tx, s));
+    if (prof && L.bulk_blocks > 0) HIP_TRY(hipEventRecord(ev[1], s));
+    HIP_TRY(launch_flip(L, s));
+    if (prof) {
+        if (L.bulk_blocks > 0) prof->pending.push_back({ev[0], ev[1], 0});
+        else { prof->pool.push_back(ev[0]); prof->pool.push_back(ev[1]); }
+        prof->pending.push_back({ev[2], ev[3], 1});
+        if (L.q_blocks > 0) prof->pending.push_back({ev[4], ev[5], 2});
+        else { prof->pool.push_back(ev[4]); prof->pool.push_back(ev[5]); }
+    }
+    return LBM_OK;
+}
+
+void drop_graph(lbm_run *h) {
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+    h->graph_G = 0;
+}
+
+lbm_status build_graph(lbm_run *h, int G) {
+    drop_graph(h);
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        h->graph_failed = true;
+        return LBM_OK;
+    }
+    LaunchSet L = single_set(h);
+    lbm_status st = LBM_OK;
+    for (int k = 0; k < G && st == LBM_OK; ++k)
+        st = enqueue_step(L, h->desc.storage, h->launch.bulk_tx, h->stream, nullptr);
+    hipError_t e = hipStreamEndCapture(h->stream, &g);
+    if (st != LBM_OK || e != hipSuccess || !g) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        h->graph_failed = true;
+        return LBM_OK;
+    }
+    e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        h->graph = nullptr;
+        h->graph_failed = true;
+        return LBM_OK;
+    }
+    h->graph_G = G;
+    h->graph_tx = h->launch.bulk_tx;
+    return LBM_OK;
+}
+
+bool finite_all(const double *a, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+uint64_t fnv1a(const void *p, size_t n, uint64_t h) {
+    const unsigned char *c = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ULL; }
+    return h;
+}
+
+// Refresh the host copy of the device-updated fields (par, step, limit).
+lbm_status pull_state(lbm_run *h) {
+    RunDev tmp;
+    HIP_TRY(hipMemcpyAsync(&tmp, h->dd, sizeof(RunDev), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->hd.par = tmp.par;
+    h->hd.step = tmp.step;
+    h->hd.limit = tmp.limit;
+    return LBM_OK;
+}
+
+}  // namespace
+
+// ============================================================================================
+// C ABI
+// ============================================================================================
+extern "C" {
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+lbm_status lbm_velocities(int32_t *e, double *w, double *r) {
+    for (int i = 0; i < NQ; ++i) {
+        if (e) { e[2 * i] = ex_of(i); e[2 * i + 1] = ey_of(i); }
+        if (w) w[i] = SHELL_W[shell_of(i)];
+    }
+    if (r) *r = LAT_R;
+    return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_desc *desc, lbm_handle *out) {
+    if (!desc || !out) return fail(LBM_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    const lbm_desc &d = *desc;
+    if (d.nx < 1 || d.ny < 1) return fail(LBM_ERR_ARG, "bulk size must be >= 1");
+    if (!(d.tau > 0.5) || !std::isfinite(d.tau)) return fail(LBM_ERR_ARG, "tau must be > 0.5");
+    if (!std::isfinite(d.rho0) || !std::isfinite(d.ux0) || !std::isfinite(d.uy0) ||
+        !std::isfinite(d.T0) || !(d.rho0 > 0) || !(d.T0 > 0))
+        return fail(LBM_ERR_ARG, "mean state must be finite with rho0 > 0 and T0 > 0");
+    if (d.storage < LBM_F64 || d.storage > LBM_F16_DEV) return fail(LBM_ERR_ARG, "unknown storage");
+    if (d.storage == LBM_F16_DEV && d.f16_scale != 0.0) {
+        int ex;
+        double m = std::frexp(d.f16_scale, &ex);
+        if (!(d.f16_scale > 0) || m != 0.5) return fail(LBM_ERR_ARG, "f16_scale must be a power of two");
+    }
+    lbm_run *h = new lbm_run();
+    h->desc = d;
+    if (d.allocator) {
+        h->alloc_copy = *d.allocator;
+        h->desc.allocator = &h->alloc_copy;
+        h->mem.alloc = &h->alloc_copy;
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_pml(lbm_handle h, unsigned mask, int32_t W, double sigma_max) {
+    if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+    if (h->inited) return fail(LBM_ERR_STATE, "configure before lbm_init_fields");
+    if (W < 0 || !(sigma_max >= 0) || !std::isfinite(sigma_max)) return fail(LBM_ERR_ARG, "W >= 0 and finite sigma_max >= 0 required");
+    if (mask & ~15u) return fail(LBM_ERR_ARG, "bad side mask");
+    h->W = W;
+    h->sigma_max = sigma_max;
+    for (int s = 0; s < 4; ++s) h->pml[s] = (mask >> s) & 1u;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_bc(lbm_handle h, unsigned mask, lbm_bc kind) {
+    if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+    if (h->inited) return fail(LBM_ERR_STATE, "configure before lbm_init_fields");
+    if (kind < LBM_BC_PERIODIC || kind > LBM_BC_NRBC) return fail(LBM_ERR_ARG, "unknown boundary kind");
+    if (mask & ~15u) return fail(LBM_ERR_ARG, "bad side mask");
+    for (int s = 0; s < 4; ++s)
+        if ((mask >> s) & 1u) h->bc[s] = kind;
+    return LBM_OK;
+}
+
+lbm_status lbm_grid(lbm_handle h, int32_t *Nx, int32_t *Ny) {
+    if (!h || !Nx || !Ny) return fail(LBM_ERR_ARG, "NULL argument");
+    int wx = (h->pml[XMIN] ? h->W : 0) + (h->pml[XMAX] ? h->W : 0);
+    int wy = (h->pml[YMIN] ? h->W : 0) + (h->pml[YMAX] ? h->W : 0);
+    *Nx = h->desc.nx + wx;
+    *Ny = h->desc.ny + wy;
+    return LBM_OK;
+}
+
+lbm_status lbm_footprint(lbm_handle h, size_t *bytes) {
+    if (!h || !bytes) return fail(LBM_ERR_ARG, "NULL argument");
+    RunDev R{};
+    lbm_status st = setup_geometry(h, R);
+    if (st != LBM_OK) return st;
+    *bytes = footprint_of(R, h->desc.storage);
+    return LBM_OK;
+}
+
+lbm_status lbm_node_classes(lbm_handle h, int64_t out[3]) {
+    if (!h || !out) return fail(LBM_ERR_ARG, "NULL argument");
+    RunDev R{};
+    lbm_status st = setup_geometry(h, R);
+    if (st != LBM_OK) return st;
+    out[0] = (int64_t)std::max(0, R.fx1 - R.fx0) * std::max(0, R.fy1 - R.fy0);
+    out[1] = R.frame_n;
+    int64_t q = 0;
+    if (R.has_q)
+        for (int y = 0; y < R.Ny; ++y)
+            for (int x = 0; x < R.Nx; ++x)
+                q += (R.Wxm > 0 && x < R.qd) || (R.Wxp > 0 && x >= R.Nx - R.qd) ||
+                     (R.Wym > 0 && y < R.qd) || (R.Wyp > 0 && y >= R.Ny - R.qd);
+    out[2] = q;
+    return LBM_OK;
+}
+
+lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux, const double *uy,
+                           const double *T) {
+    if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+    if (h->inited) return fail(LBM_ERR_STATE, "already initialised");
+    if (!rho || !ux || !uy || !T) return fail(LBM_ERR_ARG, "NULL field");
+    RunDev R{};
+    lbm_status st = setup_geometry(h, R);
+    if (st != LBM_OK) return st;
+    const size_t nn = (size_t)R.Nx * R.Ny;
+    if (!finite_all(rho, nn) || !finite_all(ux, nn) || !finite_all(uy, nn) || !finite_all(T, nn))
+        return fail(LBM_ERR_ARG, "non-finite initial field");
+    for (size_t i = 0; i < nn; ++i)
+        if (!(rho[i] > 0) || !(T[i] > 0)) return fail(LBM_ERR_ARG, "initial rho and T must be > 0");
+    fill_constants(h, R);
+    if (h->desc.stream) {
+        h->stream = (hipStream_t)h->desc.stream;
+    } else {
+        HIP_TRY(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
+        h->stream = h->own_stream;
+    }
+    const int storage = h->desc.storage;
+    const size_t es = elem_size(storage), cs = compute_size(storage);
+    h->footprint = footprint_of(R, storage);
+    for (int b = 0; b < 2; ++b) {
+        R.f[b] = h->mem.get((size_t)NQ * R.plane * es);
+        R.U[b] = (double *)h->mem.get(4 * (size_t)R.qplane * sizeof(double));
+        if (!R.f[b] || !R.U[b]) { h->mem.release_all(); return fail(LBM_ERR_OOM, "device allocation failed"); }
+    }
+    R.Q = R.has_q ? h->mem.get((size_t)NQ * R.qplane * cs) : nullptr;
+    h->dd = (RunDev *)h->mem.get(sizeof(RunDev));
+    h->dptr = (RunDev **)h->mem.get(sizeof(RunDev *));
+    h->dprefix = (int *)h->mem.get(6 * sizeof(int));
+    h->fbar_d = (double *)h->mem.get(NQ * sizeof(double));
+    if ((R.has_q && !R.Q) || !h->dd || !h->dptr || !h->dprefix || !h->fbar_d) {
+        h->mem.release_all();
+        return fail(LBM_ERR_OOM, "device allocation failed");
+    }
+    for (int b = 0; b < 2; ++b) {
+        HIP_TRY(hipMemsetAsync(R.f[b], 0, (size_t)NQ * R.plane * es, h->stream));
+        HIP_TRY(hipMemsetAsync(R.U[b], 0, 4 * (size_t)R.qplane * sizeof(double), h->stream));
+    }
+    if (R.Q) HIP_TRY(hipMemsetAsync(R.Q, 0, (size_t)NQ * R.qplane * cs, h->stream));
+    R.par = 0; R.step = 0; R.limit = 0;
+    set_scale(R, 1.0);
+    if (storage == ST_F16 && h->desc.f16_scale > 0) set_scale(R, h->desc.f16_scale);
+    h->hd = R;
+    HIP_TRY(hipMemcpyAsync(h->dd, &h->hd, sizeof(RunDev), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->dptr, &h->dd, sizeof(RunDev *), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->fbar_d, h->fbar, sizeof h->fbar, hipMemcpyHostToDevice, h->stream));
+    // fields to the device
+    double *dfield = (double *)h->mem.get(4 * nn * sizeof(double));
+    if (!dfield) { h->mem.release_all(); return fail(LBM_ERR_OOM, "device allocation failed"); }
+    const double *src[4] = {rho, ux, uy, T};
+    for (int k = 0; k < 4; ++k)
+        HIP_TRY(hipMemcpyAsync(dfield + k * nn, src[k], nn * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    if (storage == ST_F16 && !(h->desc.f16_scale > 0)) {
+        // Per-run power-of-two scale: the largest initial deviation maps to about 2^10, leaving
+        // 2^5 headroom below the float16 maximum for growth.
+        int nb = (int)((nn + 255) / 256);
+        float *dmax = (float *)h->mem.get(nb * sizeof(float));
+        if (!dmax) { h->mem.release_all(); return fail(LBM_ERR_OOM, "device allocation failed"); }
+        HIP_TRY(launch_init(h->dd, storage, R.Nx, R.Ny, dfield, dfield + nn, dfield + 2 * nn,
+                            dfield + 3 * nn, dmax, h->stream));
+        std::vector<float> hm(nb);
+        HIP_TRY(hipMemcpyAsync(hm.data(), dmax, nb * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        h->mem.put(dmax);
+        float m = 0.0f;
+        for (float v : hm) m = std::max(m, v);
+        double s = m > 0 ? std::ldexp(1.0, (int)std::floor(std::log2(1024.0 / m))) : std::ldexp(1.0, 20);
+        s = std::min(std::max(s, std::ldexp(1.0, -10)), std::ldexp(1.0, 60));
+        set_scale(h->hd, s);
+        HIP_TRY(hipMemcpyAsync(h->dd, &h->hd, sizeof(RunDev), hipMemcpyHostToDevice, h->stream));
+    }
+    HIP_TRY(launch_init(h->dd, storage, R.Nx, R.Ny, dfield, dfield + nn, dfield + 2 * nn, dfield + 3 * nn,
+                        nullptr, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->mem.put(dfield);
+    lbm_status ps = upload_prefix(h);
+    if (ps != LBM_OK) return ps;
+    h->inited = true;
+    h->steps = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_handle h, int64_t n) {
+    if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+    if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
+    if (h->group) return fail(LBM_ERR_STATE, "run is in a group; step it with lbm_group_step");
+    if (n < 0) return fail(LBM_ERR_ARG, "nsteps < 0");
+    if (n == 0) return LBM_OK;
+    HIP_TRY(launch_set_limit(h->dd, (long long)(h->steps + n), h->stream));
+    LaunchSet L = single_set(h);
+    int64_t left = n;
+    const int G = h->launch.graph_steps;
+    if (!h->prof && G > 0 && !h->graph_failed && n >= G) {
+        if (!h->graph || h->graph_G != G || h->graph_tx != h->launch.bulk_tx) {
+            lbm_status st = build_graph(h, G);
+            if (st != LBM_OK) return st;
+        }
+        if (h->graph) {
+            while (left >= G) {
+                HIP_TRY(hipGraphLaunch(h->graph, h->stream));
+                left -= G;
+            }
+        }
+    }
+    for (int64_t k = 0; k < left; ++k) {
+        lbm_status st = enqueue_step(L, h->desc.storage, h->launch.bulk_tx, h->stream, h->prof ? h : nullptr);
+        if (st != LBM_OK) return st;
+    }
+    h->steps += n;
+    return LBM_OK;
+}
+
+lbm_status lbm_step_count(lbm_handle h, int64_t *steps) {
+    if (!h || !steps) return fail(LBM_ERR_ARG, "NULL argument");
+    *steps = h->steps;
+    return LBM_OK;
+}
+
+lbm_status lbm_synchronize(lbm_handle h) {
+    if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+    if (!h->inited) return LBM_OK;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_handle h, double *rho, double *ux, double *uy, double *T, unsigned flags) {
+    if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+    if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
+    const RunDev &R = h->hd;
+    const size_t nn = (size_t)R.Nx * R.Ny;
+    if (flags & LBM_DEVICE_PTRS) {
+        HIP_TRY(launch_moments(h->dd, h->desc.storage, R.Nx, R.Ny, rho, ux, uy, T, h->stream));
+        return LBM_OK;
+    }
+    double *tmp = (double *)h->mem.get(4 * nn * sizeof(double));
+    if (!tmp) return fail(LBM_ERR_OOM, "device allocation failed");
+    double *d[4] = {tmp, tmp + nn, tmp + 2 * nn, tmp + 3 * nn};
+    double *o[4] = {rho, ux, uy, T};
+    hipError_t e = launch_moments(h->dd, h->desc.storage, R.Nx, R.Ny, o[0] ? d[0] : nullptr,
+                                  o[1] ? d[1] : nullptr, o[2] ? d[2] : nullptr, o[3] ? d[3] : nullptr,
+                                  h->stream);
+    for (int k = 0; k < 4 && e == hipSuccess; ++k)
+        if (o[k]) e = hipMemcpyAsync(o[k], d[k], nn * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    h->mem.put(tmp);
+    if (e != hipSuccess) return fail(LBM_ERR_DEVICE, std::string("lbm_moments: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+lbm_status lbm_populations(lbm_handle h, double *f) {
+    if (!h || !f) return fail(LBM_ERR_ARG, "NULL argument");
+    if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
+    const RunDev &R = h->hd;
+    const size_t n = (size_t)NQ * R.Nx * R.Ny;
+    double *tmp = (double *)h->mem.get(n * sizeof(double));
+    if (!tmp) return fail(LBM_ERR_OOM, "device allocation failed");
+    hipError_t e = launch_export_f(h->dd, h->desc.storage, R.Nx, R.Ny, h->fbar_d, tmp, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(f, tmp, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    h->mem.put(tmp);
+    if (e != hipSuccess) return fail(LBM_ERR_DEVICE, std::string("lbm_populations: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+lbm_status lbm_pml_q(lbm_handle h, double *Q) {
+    if (!h || !Q) return fail(LBM_ERR_ARG, "NULL argument");
+    if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
+    const RunDev &R = h->hd;
+    const size_t n = (size_t)NQ * R.Nx * R.Ny;
+    if (!R.has_q) { std::memset(Q, 0, n * sizeof(double)); return LBM_OK; }
+    double *tmp = (double *)h->mem.get(n * sizeof(double));
+    if (!tmp) return fail(LBM_ERR_OOM, "device allocation failed");
+    hipError_t e = hipMemsetAsync(tmp, 0, n * sizeof(double), h->stream);
+    if (e == hipSuccess) e = launch_export_q(h->dd, h->desc.storage, R.frame_n, tmp, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(Q, tmp, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    h->mem.put(tmp);
+    if (e != hipSuccess) return fail(LBM_ERR_DEVICE, std::string("lbm_pml_q: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+lbm_status lbm_error_norms(lbm_handle h, const double *ref_rho, const double *ref_ux,
+                           const double *ref_T, double out[3]) {
+    if (!h || !ref_rho || !ref_ux || !ref_T || !out) return fail(LBM_ERR_ARG, "NULL argument");
+    if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
+    const RunDev &R = h->hd;
+    const size_t nn = (size_t)R.Nx * R.Ny, nb = (size_t)h->desc.nx * h->desc.ny;
+    const int ly = h->desc.ny;
+    double *tmp = (double *)h->mem.get((3 * nn + 3 * nb + 3 * (size_t)ly + 3) * sizeof(double));
+    if (!tmp) return fail(LBM_ERR_OOM, "device allocation failed");
+    double *m = tmp, *refs = tmp + 3 * nn, *part = refs + 3 * nb, *dout = part + 3 * (size_t)ly;
+    hipError_t e = launch_moments(h->dd, h->desc.storage, R.Nx, R.Ny, m, m + nn, nullptr, m + 2 * nn, h->stream);
+    const double *src[3] = {ref_rho, ref_ux, ref_T};
+    for (int k = 0; k < 3 && e == hipSuccess; ++k)
+        e = hipMemcpyAsync(refs + k * nb, src[k], nb * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = launch_err_rows(m, m + nn, m + 2 * nn, R.Nx, R.Wxm, R.Wym, h->desc.nx, ly, refs, refs + nb,
+                            refs + 2 * nb, part, h->stream);
+    if (e == hipSuccess) e = launch_err_final(part, ly, dout, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dout, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    h->mem.put(tmp);
+    if (e != hipSuccess) return fail(LBM_ERR_DEVICE, std::string("lbm_error_norms: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+lbm_status lbm_check(lbm_handle h) {
+    if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+    if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
+    int *flag = (int *)h->mem.get(sizeof(int));
+    if (!flag) return fail(LBM_ERR_OOM, "device allocation failed");
+    int hf = 0;
+    hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), h->stream);
+    if (e == hipSuccess) e = launch_check(h->dd, h->desc.storage, h->hd.Nx, h->hd.Ny, flag, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    h->mem.put(flag);
+    if (e != hipSuccess) return fail(LBM_ERR_DEVICE, std::string("lbm_check: ") + hipGetErrorString(e));
+    if (hf) return fail(LBM_ERR_UNSTABLE, "non-finite value, rho <= 0 or T <= 0 in the state");
+    return LBM_OK;
+}
+
+lbm_status lbm_set_launch(lbm_handle h, const lbm_launch *cfg) {
+    if (!h || !cfg) return fail(LBM_ERR_ARG, "NULL argument");
+    if (!(cfg->bulk_tx == 64 || cfg->bulk_tx == 128 || cfg->bulk_tx == 256) ||
+        cfg->bulk_tx * cfg->bulk_ty != 256)
+        return fail(LBM_ERR_ARG, "bulk tile must be 64x4, 128x2 or 256x1");
+    if (cfg->graph_steps < 0 || (cfg->graph_steps & 1)) return fail(LBM_ERR_ARG, "graph_steps must be even and >= 0");
+    if (h->group) return fail(LBM_ERR_STATE, "run is in a group");
+    h->launch = *cfg;
+    if (h->inited) return upload_prefix(h);
+    return LBM_OK;
+}
+
+lbm_status lbm_get_launch(lbm_handle h, lbm_launch *cfg) {
+    if (!h || !cfg) return fail(LBM_ERR_ARG, "NULL argument");
+    *cfg = h->launch;
+    return LBM_OK;
+}
+
+lbm_status lbm_profile(lbm_handle h, int enable) {
+    if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+    h->prof = enable != 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_profile_read(lbm_handle h, double ms[3], int64_t launches[3], int reset) {
+    if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+    if (h->inited) HIP_TRY(hipStreamSynchronize(h->stream));
+    for (auto &ev : h->pending) {
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, ev.a, ev.b));
+        h->prof_ms[ev.cls] += t;
+        h->prof_n[ev.cls] += 1;
+        h->pool.push_back(ev.a);
+        h->pool.push_back(ev.b);
+    }
+    h->pending.clear();
+    for (int k = 0; k < 3; ++k) {
+        if (ms) ms[k] = h->prof_ms[k];
+        if (launches) launches[k] = h->prof_n[k];
+        if (reset) { h->prof_ms[k] = 0; h->prof_n[k] = 0; }
+    }
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_handle h) {
+    if (!h) return;
+    if (h->group) lbm_group_remove(h->group, h);
+    if (h->inited) (void)hipStreamSynchronize(h->stream);
+    drop_graph(h);
+    for (auto &ev : h->pending) { (void)hipEventDestroy(ev.a); (void)hipEventDestroy(ev.b); }
+    for (auto e : h->pool) (void)hipEventDestroy(e);
+    h->mem.release_all();
+    if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+    delete h;
+}
+
+// ---- checkpoint -----------------------------------------------------------------------------
+namespace {
+struct CkptHeader {
+    char magic[8];
+    int32_t version, Nx, Ny, storage, W, pml[4], bc[4], par;
+    int64_t steps, plane, qplane;
+    double tau, rho0, ux0, uy0, T0, sigma_max, scale;
+    uint64_t checksum;
+};
+}  // namespace
+
+lbm_status lbm_save(lbm_handle h, const char *path) {
+    if (!h || !path) return fail(LBM_ERR_ARG, "NULL argument");
+    if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
+    lbm_status st = pull_state(h);
+    if (st != LBM_OK) return st;
+    const RunDev &R = h->hd;
+    const int storage = h->desc.storage;
+    size_t fb = (size_t)NQ * R.plane * elem_size(storage);
+    size_t qb = R.has_q ? (size_t)NQ * R.qplane * compute_size(storage) : 0;
+    size_t ub = 4 * (size_t)R.qplane * sizeof(double);
+    std::vector<char> buf(2 * fb + qb + 2 * ub);
+    char *p = buf.data();
+    for (int b = 0; b < 2; ++b) { HIP_TRY(hipMemcpy(p, R.f[b], fb, hipMemcpyDeviceToHost)); p += fb; }
+    if (qb) { HIP_TRY(hipMemcpy(p, R.Q, qb, hipMemcpyDeviceToHost)); p += qb; }
+    for (int b = 0; b < 2; ++b) { HIP_TRY(hipMemcpy(p, R.U[b], ub, hipMemcpyDeviceToHost)); p += ub; }
+    CkptHeader hdr{};
+    std::memcpy(hdr.magic, "LBMPML01", 8);
+    hdr.version = 1; hdr.Nx = R.Nx; hdr.Ny = R.Ny; hdr.storage = storage; hdr.W = h->W;
+    for (int s = 0; s < 4; ++s) { hdr.pml[s] = h->pml[s]; hdr.bc[s] = h->bc[s]; }
+    hdr.par = R.par; hdr.steps = h->steps; hdr.plane = R.plane; hdr.qplane = R.qplane;
+    hdr.tau = h->desc.tau; hdr.rho0 = h->desc.rho0; hdr.ux0 = h->desc.ux0; hdr.uy0 = h->desc.uy0;
+    hdr.T0 = h->desc.T0; hdr.sigma_max = h->sigma_max; hdr.scale = R.scale;
+    hdr.checksum = fnv1a(buf.data(), buf.size(), 1469598103934665603ULL);
+    FILE *fp = std::fopen(path, "wb");
+    if (!fp) return fail(LBM_ERR_ARG, std::string("cannot open ") + path);
+    bool ok = std::fwrite(&hdr, sizeof hdr, 1, fp) == 1 && std::fwrite(buf.data(), 1, buf.size(), fp) == buf.size();
+    ok = (std::fclose(fp) == 0) && ok;
+    if (!ok) return fail(LBM_ERR_ARG, std::string("write failed: ") + path);
+    return LBM_OK;
+}
+
+lbm_status lbm_load(lbm_handle h, const char *path) {
+    if (!h || !path) return fail(LBM_ERR_ARG, "NULL argument");
+    if (!h->inited) return fail(LBM_ERR_STATE, "initialise the handle before lbm_load");
+    if (h->group) return fail(LBM_ERR_STATE, "run is in a group");
+    FILE *fp = std::fopen(path, "rb");
+    if (!fp) return fail(LBM_ERR_ARG, std::string("cannot open ") + path);
+    CkptHeader hdr{};
+    if (std::fread(&hdr, sizeof hdr, 1, fp) != 1 || std::memcmp(hdr.magic, "LBMPML01", 8) != 0) {
+        std::fclose(fp);
+        return fail(LBM_ERR_ARG, "not a checkpoint file");
+    }
+    RunDev &R = h->hd;
+    const int storage = h->desc.storage;
+    bool same = hdr.Nx == R.Nx && hdr.Ny == R.Ny && hdr.storage == storage && hdr.W == h->W &&
+                hdr.plane == R.plane && hdr.qplane == R.qplane && hdr.tau == h->desc.tau &&
+                hdr.rho0 == h->desc.rho0 && hdr.ux0 == h->desc.ux0 && hdr.uy0 == h->desc.uy0 &&
+                hdr.T0 == h->desc.T0 && hdr.sigma_max == h->sigma_max;
+    for (int s = 0; s < 4; ++s) same = same && hdr.pml[s] == h->pml[s] && hdr.bc[s] == h->bc[s];
+    if (!same) { std::fclose(fp); return fail(LBM_ERR_ARG, "checkpoint configuration differs from the handle's"); }
+    size_t fb = (size_t)NQ * R.plane * elem_size(storage);
+    size_t qb = R.has_q ? (size_t)NQ * R.qplane * compute_size(storage) : 0;
+    size_t ub = 4 * (size_t)R.qplane * sizeof(double);
+    std::vector<char> buf(2 * fb + qb + 2 * ub);
+    bool ok = std::fread(buf.data(), 1, buf.size(), fp) == buf.size();
+    std::fclose(fp);
+    if (!ok) return fail(LBM_ERR_ARG, "truncated checkpoint");
+    if (fnv1a(buf.data(), buf.size(), 1469598103934665603ULL) != hdr.checksum)
+        return fail(LBM_ERR_ARG, "checkpoint checksum mismatch");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    char *p = buf.data();
+    for (int b = 0; b < 2; ++b) { HIP_TRY(hipMemcpy(R.f[b], p, fb, hipMemcpyHostToDevice)); p += fb; }
+    if (qb) { HIP_TRY(hipMemcpy(R.Q, p, qb, hipMemcpyHostToDevice)); p += qb; }
+    for (int b = 0; b < 2; ++b) { HIP_TRY(hipMemcpy(R.U[b], p, ub, hipMemcpyHostToDevice)); p += ub; }
+    R.par = hdr.par;
+    R.step = hdr.steps;
+    R.limit = hdr.steps;
+    set_scale(R, hdr.scale);
+    HIP_TRY(hipMemcpy(h->dd, &R, sizeof(RunDev), hipMemcpyHostToDevice));
+    h->steps = hdr.steps;
+    return LBM_OK;
+}
+
+// ---- autotune -------------------------------------------------------------------------------
+lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path, lbm_launch *chosen) {
+    if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+    if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
+    if (h->group) return fail(LBM_ERR_STATE, "run is in a group");
+    if (steps < 1) steps = 10;
+    const RunDev &R = h->hd;
+    if (cache_path) {
+        FILE *fp = std::fopen(cache_path, "r");
+        if (fp) {
+            int nx, ny, st, tx;
+            while (std::fscanf(fp, "%d %d %d %d", &nx, &ny, &st, &tx) == 4) {
+                if (nx == R.Nx && ny == R.Ny && st == h->desc.storage) {
+                    std::fclose(fp);
+                    lbm_launch c = h->launch;
+                    c.bulk_tx = tx; c.bulk_ty = 256 / tx;
+                    lbm_status s2 = lbm_set_launch(h, &c);
+                    if (chosen) *chosen = h->launch;
+                    return s2;
+                }
+            }
+            std::fclose(fp);
+        }
+    }
+    // scratch run with the same geometry at the mean state
+    lbm_desc d = h->desc;
+    d.stream = (void *)h->stream;
+    lbm_handle s = nullptr;
+    lbm_status st = lbm_create(&d, &s);
+    if (st != LBM_OK) return st;
+    s->W = h->W; s->sigma_max = h->sigma_max;
+    for (int k = 0; k < 4; ++k) { s->pml[k] = h->pml[k]; s->bc[k] = h->bc[k]; }
+    const size_t nn = (size_t)R.Nx * R.Ny;
+    std::vector<double> f1(nn, d.rho0), f2(nn, d.ux0), f3(nn, d.uy0), f4(nn, d.T0);
+    st = lbm_init_fields(s, f1.data(), f2.data(), f3.data(), f4.data());
+    if (st != LBM_OK) { lbm_destroy(s); return st; }
+    int best_tx = h->launch.bulk_tx;
+    float best = 1e30f;
+    hipEvent_t a = nullptr, b = nullptr;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    for (int tx : {64, 128, 256}) {
+        lbm_launch c{tx, 256 / tx, 0};
+        if (lbm_set_launch(s, &c) != LBM_OK) continue;
+        lbm_step(s, 2);
+        (void)hipEventRecord(a, s->stream);
+        lbm_step(s, steps);
+        (void)hipEventRecord(b, s->stream);
+        (void)hipEventSynchronize(b);
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (ms < best) { best = ms; best_tx = tx; }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    lbm_destroy(s);
+    lbm_launch c = h->launch;
+    c.bulk_tx = best_tx; c.bulk_ty = 256 / best_tx;
+    st = lbm_set_launch(h, &c);
+    if (st == LBM_OK && cache_path) {
+        FILE *fp = std::fopen(cache_path, "a");
+        if (fp) { std::fprintf(fp, "%d %d %d %d\n", R.Nx, R.Ny, h->desc.storage, best_tx); std::fclose(fp); }
+    }
+    if (chosen) *chosen = h->launch;
+    return st;
+}
+
+// ---- groups ---------------------------------------------------------------------------------
+lbm_status lbm_group_create(void *stream, const lbm_allocator *allocator, lbm_group_handle *out) {
+    if (!out) return fail(LBM_ERR_ARG, "NULL argument");
+    lbm_group *g = new lbm_group();
+    if (allocator) { g->alloc_copy = *allocator; g->mem.alloc = &g->alloc_copy; }
+    if (stream) g->stream = (hipStream_t)stream;
+    else {
+        if (hipStreamCreateWithFlags(&g->own_stream, hipStreamNonBlocking) != hipSuccess) {
+            delete g;
+            return fail(LBM_ERR_DEVICE, "hipStreamCreate failed");
+        }
+        g->stream = g->own_stream;
+    }
+    if (hipHostMalloc((void **)&g->hlimits, 4096 * sizeof(long long), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&g->upload_done, hipEventDisableTiming) != hipSuccess) {
+        if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
+        delete g;
+        return fail(LBM_ERR_DEVICE, "group setup failed");
+    }
+    *out = g;
+    return LBM_OK;
+}
+
+lbm_status lbm_group_add(lbm_group_handle g, lbm_handle h) {
+    if (!g || !h) return fail(LBM_ERR_ARG, "NULL argument");
+    if (!h->inited) return fail(LBM_ERR_STATE, "initialise the run before adding it");
+    if (h->group) return fail(LBM_ERR_STATE, "run already in a group");
+    if (g->storage >= 0 && g->storage != h->desc.storage) return fail(LBM_ERR_ARG, "all runs of a group share one storage");
+    if (g->members.size() >= 4096) return fail(LBM_ERR_ARG, "group full (4096 runs)");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->storage = h->desc.storage;
+    g->members.push_back(h);
+    h->group = g;
+    h->stream = g->stream;
+    g->dirty = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_group_remove(lbm_group_handle g, lbm_handle h) {
+    if (!g || !h) return fail(LBM_ERR_ARG, "NULL argument");
+    auto it = std::find(g->members.begin(), g->members.end(), h);
+    if (it == g->members.end()) return fail(LBM_ERR_ARG, "run is not in this group");
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->members.erase(it);
+    h->group = nullptr;
+    h->stream = h->own_stream ? h->own_stream : (hipStream_t)h->desc.stream;
+    if (g->members.empty()) g->storage = -1;
+    g->dirty = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_group_size(lbm_group_handle g, int32_t *n) {
+    if (!g || !n) return fail(LBM_ERR_ARG, "NULL argument");
+    *n = (int32_t)g->members.size();
+    return LBM_OK;
+}
+
+lbm_status lbm_group_synchronize(lbm_group_handle g) {
+    if (!g) return fail(LBM_ERR_ARG, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return LBM_OK;
+}
+
+static lbm_status group_rebuild(lbm_group *g) {
+    const size_t n = g->members.size();
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    if (n > g->cap) {
+        g->mem.put(g->druns); g->mem.put(g->dprefix); g->mem.put(g->dlimits);
+        size_t cap = std::max<size_t>(n, 64);
+        g->druns = (RunDev **)g->mem.get(cap * sizeof(RunDev *));
+        g->dprefix = (int *)g->mem.get(3 * (cap + 1) * sizeof(int));
+        g->dlimits = (long long *)g->mem.get(cap * sizeof(long long));
+        if (!g->druns || !g->dprefix || !g->dlimits) return fail(LBM_ERR_OOM, "device allocation failed");
+        g->cap = cap;
+    }
+    std::vector<RunDev *> ptrs(n);
+    std::vector<int> pre(3 * (g->cap + 1), 0);
+    int tot[3] = {0, 0, 0};
+    for (size_t k = 0; k < n; ++k) {
+        lbm_run *h = g->members[k];
+        ptrs[k] = h->dd;
+        int nb[3];
+        compute_blocks(h->hd, g->tx, nb);
+        for (int c = 0; c < 3; ++c) { pre[c * (g->cap + 1) + k] = tot[c]; tot[c] += nb[c]; }
+    }
+    for (int c = 0; c < 3; ++c) pre[c * (g->cap + 1) + n] = tot[c];
+    if (n) HIP_TRY(hipMemcpy(g->druns, ptrs.data(), n * sizeof(RunDev *), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(g->dprefix, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice));
+    for (int c = 0; c < 3; ++c) g->blocks[c] = tot[c];
+    g->dirty = false;
+    return LBM_OK;
+}
+
+lbm_status lbm_group_step(lbm_group_handle g, const int64_t *steps, int64_t nsteps) {
+    if (!g) return fail(LBM_ERR_ARG, "NULL argument");
+    const size_t n = g->members.size();
+    if (n == 0) return LBM_OK;
+    if (g->dirty) {
+        lbm_status st = group_rebuild(g);
+        if (st != LBM_OK) return st;
+    }
+    int64_t K = 0;
+    for (size_t k = 0; k < n; ++k) {
+        int64_t s = steps ? steps[k] : nsteps;
+        if (s < 0) return fail(LBM_ERR_ARG, "negative step count");
+        K = std::max(K, s);
+    }
+    if (K == 0) return LBM_OK;
+    if (g->upload_pending) HIP_TRY(hipEventSynchronize(g->upload_done));
+    for (size_t k = 0; k < n; ++k) g->hlimits[k] = g->members[k]->steps + (steps ? steps[k] : nsteps);
+    HIP_TRY(hipMemcpyAsync(g->dlimits, g->hlimits, n * sizeof(long long), hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipEventRecord(g->upload_done, g->stream));
+    g->upload_pending = true;
+    HIP_TRY(launch_set_limits(g->druns, g->dlimits, (int)n, g->stream));
+    LaunchSet L;
+    L.runs = g->druns;
+    L.bulk_prefix = g->dprefix;
+    L.frame_prefix = g->dprefix + (g->cap + 1);
+    L.q_prefix = g->dprefix + 2 * (g->cap + 1);
+    L.nruns = (int)n;
+    L.bulk_blocks = g->blocks[0];
+    L.frame_blocks = g->blocks[1];
+    L.q_blocks = g->blocks[2];
+    for (int64_t k = 0; k < K; ++k) {
+        lbm_status st = enqueue_step(L, g->storage, g->tx, g->stream, nullptr);
+        if (st != LBM_OK) return st;
+    }
+    for (size_t k = 0; k < n; ++k) g->members[k]->steps += steps ? steps[k] : nsteps;
+    return LBM_OK;
+}
+
+void lbm_group_destroy(lbm_group_handle g) {
+    if (!g) return;
+    (void)hipStreamSynchronize(g->stream);
+    for (lbm_run *h : g->members) {
+        h->group = nullptr;
+        h->stream = h->own_stream ? h->own_stream : (hipStream_t)h->desc.stream;
+    }
+    g->mem.release_all();
+    if (g->hlimits) (void)hipHostFree(g->hlimits);
+    if (g->upload_done) (void)hipEventDestroy(g->upload_done);
+    if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
+    delete g;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal structures shared by the kernels (lbm_kernels.hip) and the runtime (lbm_capi.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_lattice.h"
+
+namespace lbm {
+
+enum Side { XMIN = 0, XMAX = 1, YMIN = 2, YMAX = 3 };
+enum Bc { BC_PERIODIC = 0, BC_ZG = 1, BC_NRBC = 2 };
+enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2 };
+
+// Device descriptor of one run.  Lives in device memory (one per run); kernels receive an
+// array of pointers to descriptors, so a single run and a batch share every kernel.
+//
+// Grid: Nx x Ny nodes, population plane p stored at f[par] + p * plane, row pitch `pitch`.
+// Frame: the nodes outside the fast interior rectangle [fx0,fx1) x [fy0,fy1), i.e. a frame of
+// depth gxm/gxp/gym/gyp on the four sides.  Frame nodes are numbered bottom strip, top strip,
+// left strip, right strip (row-major inside each strip); Q and the moment strips U use that
+// numbering, so a frame thread touches its own Q/U entries with unit stride.
+struct alignas(256) RunDev {
+    int Nx, Ny, pitch, storage;
+    long long plane;          // elements per population plane of f
+    long long qplane;         // elements per component plane of Q and U
+    int gxm, gxp, gym, gyp;   // frame depths
+    int Wxm, Wxp, Wym, Wyp;   // PML width per side (0 if none)
+    int W, qd, open_x, open_y;
+    int bc[4];
+    int fx0, fx1, fy0, fy1;   // fast rectangle
+    int frame_n, has_q, pad1, pad2;
+    int tiles_x[3], tiles_y[3];   // bulk tiles for tile widths 64, 128, 256
+    // state
+    void *f[2];
+    void *Q;                  // [37][qplane] in the compute type
+    double *U[2];             // [4][qplane]: rho, ux, uy, T (absolute values)
+    int par, pad0;
+    long long step, limit;    // a run is active while step < limit
+    // constants (double and float copies)
+    double omega, rho0, u0x, u0y, T0, th0, b0, r0x, r0y, sigma_max, inv_W2, scale, inv_scale;
+    double H0rest, H0e[NPAIR], H0o[NPAIR], E2_0[NSHELL], O1_0[NSHELL];
+    float omega_f, rho0_f, u0x_f, u0y_f, th0_f, b0_f, r0x_f, r0y_f, T0_f, scale_f, inv_scale_f;
+    float H0rest_f, H0e_f[NPAIR], H0o_f[NPAIR], E2_0_f[NSHELL], O1_0_f[NSHELL];
+};
+
+// Launch decomposition of a set of runs: prefix[k] = first block of run k, prefix[n] = total.
+struct LaunchSet {
+    RunDev *const *runs;      // device array of descriptor pointers
+    const int *bulk_prefix;   // device
+    const int *frame_prefix;  // device
+    const int *q_prefix;      // device
+    int nruns;
+    int bulk_blocks, frame_blocks, q_blocks;
+};
+
+constexpr int FRAME_BLOCK = 256;
+
+// Kernel launchers (lbm_kernels.hip).  All enqueue on `s` and return the HIP status of the
+// launch.
+hipError_t launch_phase_a(const LaunchSet &L, int storage, hipStream_t s);
+hipError_t launch_frame(const LaunchSet &L, int storage, hipStream_t s);
+hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, hipStream_t s);
+hipError_t launch_flip(const LaunchSet &L, hipStream_t s);
+hipError_t launch_set_limit(RunDev *run, long long limit, hipStream_t s);
+hipError_t launch_set_limits(RunDev *const *runs, const long long *limits, int n, hipStream_t s);
+hipError_t launch_init(RunDev *run, int storage, int Nx, int Ny, const double *rho,
+                       const double *ux, const double *uy, const double *T, float *absmax,
+                       hipStream_t s);
+hipError_t launch_moments(RunDev *run, int storage, int Nx, int Ny, double *rho, double *ux,
+                          double *uy, double *T, hipStream_t s);
+hipError_t launch_export_f(RunDev *run, int storage, int Nx, int Ny, const double *fbar,
+                           double *out, hipStream_t s);
+hipError_t launch_export_q(RunDev *run, int storage, int frame_n, double *out, hipStream_t s);
+hipError_t launch_check(RunDev *run, int storage, int Nx, int Ny, int *flag, hipStream_t s);
+hipError_t launch_err_rows(const double *rho, const double *ux, const double *T, int Nx,
+                           int x0, int y0, int lx, int ly, const double *rr, const double *ru,
+                           const double *rt, double *partials, hipStream_t s);
+hipError_t launch_err_final(const double *partials, int nrows, double *out, hipStream_t s);
+
+// Host helpers shared with the runtime.
+void frame_xy_host(const RunDev &R, int t, int *x, int *y);
+
+}  // namespace lbm

@@ -1,0 +1,796 @@
+// HIP kernels (gfx950, wave64) for the D2Q37 thermal LBM with PML and open boundaries.
+//
+// Every kernel takes an array of run descriptors, so one launch advances one run or a batch of
+// uneven runs.  Per step:
+//   k_phase_a  (PML runs) Q-region nodes: pull + boundary + moments -> U^{n+1};
+//              Q^{n+1} = Q^n + (fhat^n + fhat^{n+1})/2                         (eq. PMLQ)
+//   k_frame    frame nodes (boundary layers, PML, moment strips): pull + boundary fill +
+//              moments, U^{n+1} strip write, BGK + Omega^PML                 (eqs. PMLCOLL,
+//              zg-bc, PNR / LODI)
+//   k_bulk     interior nodes: branch-free pull + moments + BGK                 (eq. lbe)
+//   k_flip     swap the population and moment-strip buffers of active runs
+// The collision is a per-node projection streaming 2 x 37 values through HBM: no MFMA; the pull
+// reads are coalesced row segments shifted by e_i (each source value read exactly once).
+//
+// Arithmetic is in deviation form: the stored populations are d_i = f_i - fbar_i with
+// fbar = feq(rho0, u0, T0), and the equilibrium deviation feq(U) - fbar is evaluated from
+// differences of its Hermite coefficients, so float32 storage and arithmetic keep their
+// relative precision on the (small) deviations.  With theta = T - 1, a = u.xi, s = |xi|^2,
+// b = |u|^2, the fourth-order equilibrium (eq. feq-4 with the (c^2 - 6) reading) is
+//   feq_i = w_i rho H(a, s),
+//   H = E0(s) + E2(s) a^2 + a^4/24 + a (O1(s) + a^2/6),
+//   E0 = k0 + k2s s + theta^2 s^2/8,  E2 = k2a + theta s/4,  O1 = k1 + theta s/2,
+//   k0 = 1 - b/2 - theta + b^2/8 + theta b + theta^2,  k1 = 1 - b/2 - 2 theta,
+//   k2a = 1/2 - b/4 - 3 theta/2,  k2s = theta/2 - theta b/4 - theta^2,
+// and feq(U) - fbar = w (drho H0 + rho dH) with dH = H(U) - H(U0) expanded in products of
+// deviations.
+#include <type_traits>
+#include <utility>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+// ------------------------------------------------------------------------------------------
+// helpers
+// ------------------------------------------------------------------------------------------
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+template <class S> struct Traits;
+template <> struct Traits<double> { using C = double; };
+template <> struct Traits<float> { using C = float; };
+template <> struct Traits<_Float16> { using C = float; };
+
+__device__ __forceinline__ double ld_s(const double *p, double) { return *p; }
+__device__ __forceinline__ float ld_s(const float *p, float) { return *p; }
+__device__ __forceinline__ float ld_s(const _Float16 *p, float inv) { return (float)(*p) * inv; }
+__device__ __forceinline__ void st_s(double *p, double v, double) { *p = v; }
+__device__ __forceinline__ void st_s(float *p, float v, float) { *p = v; }
+__device__ __forceinline__ void st_s(_Float16 *p, float v, float sc) { *p = (_Float16)(v * sc); }
+
+// Run constants in the compute type.
+template <class C> struct K {
+    C omega, rho0, u0x, u0y, th0, b0, r0x, r0y, c2Tb0, scale, inv_scale;
+};
+
+template <class C> __device__ __forceinline__ K<C> load_k(const RunDev &R) {
+    K<C> k;
+    if constexpr (std::is_same<C, double>::value) {
+        k.omega = R.omega; k.rho0 = R.rho0; k.u0x = R.u0x; k.u0y = R.u0y; k.th0 = R.th0;
+        k.b0 = R.b0; k.r0x = R.r0x; k.r0y = R.r0y; k.c2Tb0 = 2.0 * R.T0 + R.b0;
+        k.scale = R.scale; k.inv_scale = R.inv_scale;
+    } else {
+        k.omega = R.omega_f; k.rho0 = R.rho0_f; k.u0x = R.u0x_f; k.u0y = R.u0y_f; k.th0 = R.th0_f;
+        k.b0 = R.b0_f; k.r0x = R.r0x_f; k.r0y = R.r0y_f; k.c2Tb0 = 2.0f * R.T0_f + R.b0_f;
+        k.scale = R.scale_f; k.inv_scale = R.inv_scale_f;
+    }
+    return k;
+}
+
+template <class C> __device__ __forceinline__ C cH0e(const RunDev &R, int p) {
+    if constexpr (std::is_same<C, double>::value) return R.H0e[p]; else return R.H0e_f[p];
+}
+template <class C> __device__ __forceinline__ C cH0o(const RunDev &R, int p) {
+    if constexpr (std::is_same<C, double>::value) return R.H0o[p]; else return R.H0o_f[p];
+}
+template <class C> __device__ __forceinline__ C cE2_0(const RunDev &R, int s) {
+    if constexpr (std::is_same<C, double>::value) return R.E2_0[s]; else return R.E2_0_f[s];
+}
+template <class C> __device__ __forceinline__ C cO1_0(const RunDev &R, int s) {
+    if constexpr (std::is_same<C, double>::value) return R.O1_0[s]; else return R.O1_0_f[s];
+}
+template <class C> __device__ __forceinline__ C cH0rest(const RunDev &R) {
+    if constexpr (std::is_same<C, double>::value) return R.H0rest; else return R.H0rest_f;
+}
+
+// Blocks of one launch are dealt round-robin to the 8 XCDs; remap so that consecutive tiles
+// (neighbours sharing cache lines at their edges) run on the same XCD and its L2.
+__device__ __forceinline__ int xcd_swizzle(int b, int n) {
+    int per = n >> 3, rem = n & 7, xcd = b & 7, loc = b >> 3;
+    return xcd < rem ? xcd * (per + 1) + loc : rem * (per + 1) + (xcd - rem) * per + loc;
+}
+
+__device__ __forceinline__ int find_run(const int *prefix, int nruns, int b) {
+    int lo = 0, hi = nruns;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__host__ __device__ __forceinline__ void frame_xy(const RunDev &R, int t, int &x, int &y) {
+    int Fb = R.gym * R.Nx, Ft = R.gyp * R.Nx, H = R.Ny - R.gym - R.gyp, Fl = H * R.gxm;
+    if (t < Fb) { y = t / R.Nx; x = t - y * R.Nx; }
+    else if (t < Fb + Ft) { t -= Fb; int r = t / R.Nx; y = R.Ny - R.gyp + r; x = t - r * R.Nx; }
+    else if (t < Fb + Ft + Fl) { t -= Fb + Ft; int r = t / R.gxm; y = R.gym + r; x = t - r * R.gxm; }
+    else { t -= Fb + Ft + Fl; int r = t / R.gxp; y = R.gym + r; x = R.Nx - R.gxp + (t - r * R.gxp); }
+}
+
+void frame_xy_host(const RunDev &R, int t, int *x, int *y) { frame_xy(R, t, *x, *y); }
+
+__device__ __forceinline__ int fidx(const RunDev &R, int x, int y) {
+    if (y < R.gym) return y * R.Nx + x;
+    if (y >= R.Ny - R.gyp) return (R.gym + y - (R.Ny - R.gyp)) * R.Nx + x;
+    int H = R.Ny - R.gym - R.gyp, base = (R.gym + R.gyp) * R.Nx, yy = y - R.gym;
+    if (x < R.gxm) return base + yy * R.gxm + x;
+    if (x >= R.Nx - R.gxp) return base + H * R.gxm + yy * R.gxp + (x - (R.Nx - R.gxp));
+    return -1;
+}
+
+__device__ __forceinline__ bool in_q(const RunDev &R, int x, int y) {
+    return (R.Wxm > 0 && x < R.qd) || (R.Wxp > 0 && x >= R.Nx - R.qd) ||
+           (R.Wym > 0 && y < R.qd) || (R.Wyp > 0 && y >= R.Ny - R.qd);
+}
+
+// eq. PML_ramp on the Chebyshev ring level.
+__device__ __forceinline__ double sigma_at(const RunDev &R, int x, int y) {
+    int lx = x < R.Wxm ? R.Wxm - x : (x >= R.Nx - R.Wxp ? x - (R.Nx - R.Wxp) + 1 : 0);
+    int ly = y < R.Wym ? R.Wym - y : (y >= R.Ny - R.Wyp ? y - (R.Ny - R.Wyp) + 1 : 0);
+    int l = lx > ly ? lx : ly;
+    return l > 0 ? R.sigma_max * (double)(l * l) * R.inv_W2 : 0.0;
+}
+
+// ------------------------------------------------------------------------------------------
+// moments (eq. macro) in deviation form
+// ------------------------------------------------------------------------------------------
+template <class C> struct Mom { C drho, dux, duy, dT, rho; };
+
+template <class C>
+__device__ __forceinline__ Mom<C> moments(const C (&g)[NQ], const K<C> &k) {
+    C s = g[0], jx = C(0), jy = C(0), e2 = C(0);
+    static_for<0, NPAIR>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        C a = g[1 + 2 * p], b = g[2 + 2 * p];
+        C sp = a + b, dp = a - b;
+        s += sp;
+        if constexpr (PEX[p] == 1) jx += dp;
+        else if constexpr (PEX[p] == -1) jx -= dp;
+        else if constexpr (PEX[p] != 0) jx += C(PEX[p]) * dp;
+        if constexpr (PEY[p] == 1) jy += dp;
+        else if constexpr (PEY[p] == -1) jy -= dp;
+        else if constexpr (PEY[p] != 0) jy += C(PEY[p]) * dp;
+        if constexpr (SHELL_E2[PSH[p]] == 1) e2 += sp;
+        else e2 += C(SHELL_E2[PSH[p]]) * sp;
+    });
+    Mom<C> m;
+    m.drho = s;
+    m.rho = k.rho0 + s;
+    C inv = C(1) / m.rho;
+    C Jx = C(LAT_R) * jx, Jy = C(LAT_R) * jy, E = C(LAT_R2) * e2;
+    m.dux = (Jx - s * k.u0x) * inv;
+    m.duy = (Jy - s * k.u0y) * inv;
+    C t = E - s * k.c2Tb0 - C(2) * m.rho * (k.u0x * m.dux + k.u0y * m.duy) -
+          m.rho * (m.dux * m.dux + m.duy * m.duy);
+    m.dT = C(0.5) * t * inv;
+    return m;
+}
+
+// ------------------------------------------------------------------------------------------
+// equilibrium deviation feq(U) - fbar
+// ------------------------------------------------------------------------------------------
+template <class C> struct Eq {
+    C drho, rho, Rdux, Rduy, dT, dk0, dk1, dk2a, dk2s, dth2;
+};
+
+template <class C>
+__device__ __forceinline__ Eq<C> eq_coef(C drho, C dux, C duy, C dT, const K<C> &k) {
+    Eq<C> q;
+    q.drho = drho;
+    q.rho = k.rho0 + drho;
+    q.Rdux = C(LAT_R) * dux;
+    q.Rduy = C(LAT_R) * duy;
+    q.dT = dT;
+    C ux = k.u0x + dux, uy = k.u0y + duy, th = k.th0 + dT;
+    C b = ux * ux + uy * uy;
+    C db = dux * (C(2) * k.u0x + dux) + duy * (C(2) * k.u0y + duy);
+    C dth2 = dT * (th + k.th0);
+    C dthb = dT * b + k.th0 * db;
+    C db2 = db * (b + k.b0);
+    q.dk0 = -C(0.5) * db - dT + C(0.125) * db2 + dthb + dth2;
+    q.dk1 = -C(0.5) * db - C(2) * dT;
+    q.dk2a = -C(0.25) * db - C(1.5) * dT;
+    q.dk2s = C(0.5) * dT - C(0.25) * dthb - dth2;
+    q.dth2 = dth2;
+    return q;
+}
+
+// Calls emit(i, feq_i - fbar_i) for i = 0..36 with compile-time i.
+template <class C, class F>
+__device__ __forceinline__ void for_each_feq(const Eq<C> &q, const RunDev &R, const K<C> &k,
+                                             F &&emit) {
+    emit(std::integral_constant<int, 0>{},
+         C(SHELL_W[0]) * (q.drho * cH0rest<C>(R) + q.rho * q.dk0));
+    C dE0 = C(0), dE2 = C(0), dO1 = C(0), E2_0 = C(0), O1_0 = C(0);
+    static_for<0, NPAIR>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int sh = PSH[p];
+        if constexpr (p == 0 || PSH[p - 1] != sh) {
+            constexpr double sv = LAT_R2 * SHELL_E2[sh];
+            dE0 = q.dk0 + q.dk2s * C(sv) + q.dth2 * C(0.125 * sv * sv);
+            dE2 = q.dk2a + q.dT * C(0.25 * sv);
+            dO1 = q.dk1 + q.dT * C(0.5 * sv);
+            E2_0 = cE2_0<C>(R, sh);
+            O1_0 = cO1_0<C>(R, sh);
+        }
+        constexpr int ex = PEX[p], ey = PEY[p];
+        C a0, da;
+        if constexpr (ey == 0) { a0 = C(ex) * k.r0x; da = C(ex) * q.Rdux; }
+        else if constexpr (ex == 0) { a0 = C(ey) * k.r0y; da = C(ey) * q.Rduy; }
+        else { a0 = C(ex) * k.r0x + C(ey) * k.r0y; da = C(ex) * q.Rdux + C(ey) * q.Rduy; }
+        C a = a0 + da;
+        C A2 = a * a, A02 = a0 * a0;
+        C dA2 = da * (a + a0);
+        C dEv = dE0 + dE2 * A2 + E2_0 * dA2 + dA2 * (A2 + A02) * C(1.0 / 24.0);
+        C dOd = dO1 * a + O1_0 * da + da * (A2 + a * a0 + A02) * C(1.0 / 6.0);
+        C Tev = q.drho * cH0e<C>(R, p) + q.rho * dEv;
+        C Tod = q.drho * cH0o<C>(R, p) + q.rho * dOd;
+        constexpr double w = SHELL_W[sh];
+        emit(std::integral_constant<int, 1 + 2 * p>{}, C(w) * (Tev + Tod));
+        emit(std::integral_constant<int, 2 + 2 * p>{}, C(w) * (Tev - Tod));
+    });
+}
+
+// ------------------------------------------------------------------------------------------
+// characteristic boundary (float64 always)
+// ------------------------------------------------------------------------------------------
+// LODI along the outward normal of `side` for boundary node (x, y): primitive variables
+// V = (rho, u_n, u_t, T), A = S^{-1} Lambda S, Lambda = diag(u_n - c, u_n, u_n, u_n + c),
+// c = sqrt(2T) (p = rho T, gamma = 2).  Incoming amplitudes are zero (eq. PNR); an outgoing
+// amplitude takes the upwind difference over the interval its characteristic crosses in one
+// step (nu = lambda/r cells, foot point limited to two cells).  Adds the one-step increment
+// dV = -S^{-1} Lbar (eq. thermal_LODI_macro_evo) to Ut in the global frame.
+__device__ void lodi_add(const RunDev &R, const double *Uc, int side, int x, int y, int t,
+                         double Ut[4]) {
+    const long long qp = R.qplane;
+    int nx = side == XMIN ? -1 : (side == XMAX ? 1 : 0);
+    int ny = side == YMIN ? -1 : (side == YMAX ? 1 : 0);
+    double V[3][4];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        int jj = j == 0 ? t : fidx(R, x - j * nx, y - j * ny);
+        if (jj < 0) jj = t;
+        double rho = Uc[jj], ux = Uc[qp + jj], uy = Uc[2 * qp + jj], T = Uc[3 * qp + jj];
+        V[j][0] = rho;
+        V[j][1] = nx ? nx * ux : ny * uy;
+        V[j][2] = nx ? uy : ux;
+        V[j][3] = T;
+    }
+    double rho = V[0][0], un = V[0][1], T = V[0][3];
+    double c = sqrt(2.0 * T);
+    double lam[4] = {un - c, un, un, un + c};
+    double L[4][4] = {{T, -rho * c, 0.0, rho}, {T, 0.0, 0.0, -rho}, {0.0, 0.0, 1.0, 0.0},
+                      {T, rho * c, 0.0, rho}};
+    double D[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double w[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            w[j] = L[k][0] * V[j][0] + L[k][1] * V[j][1] + L[k][2] * V[j][2] + L[k][3] * V[j][3];
+        if (lam[k] > 0.0) {
+            double nu = fmin(lam[k] * (1.0 / LAT_R), 2.0);
+            int j0 = nu >= 1.0 ? 1 : 0;
+            double phi = nu - j0;
+            double wfoot = (1.0 - phi) * w[j0] + phi * w[j0 + 1];
+            D[k] = w[0] - wfoot;
+        } else {
+            D[k] = 0.0;
+        }
+    }
+    // closed-form S^{-1}: columns (1/4T, -1/2rc, 0, 1/4r), (1/2T, 0, 0, -1/2r), e3,
+    // (1/4T, 1/2rc, 0, 1/4r)
+    double dR = -((D[0] + D[3]) / (4.0 * T) + D[1] / (2.0 * T));
+    double dUn = -(D[3] - D[0]) / (2.0 * rho * c);
+    double dUt = -D[2];
+    double dTT = -((D[0] + D[3]) / (4.0 * rho) - D[1] / (2.0 * rho));
+    Ut[0] += dR;
+    Ut[3] += dTT;
+    if (nx) { Ut[1] += nx * dUn; Ut[2] += dUt; }
+    else    { Ut[2] += ny * dUn; Ut[1] += dUt; }
+}
+
+// Non-equilibrium extrapolation: g <- feq(U_tgt) + g(x_f) - feq(U(x_f)).  g holds the pulled
+// populations of x_f (deviation form) on entry.
+template <class C>
+__device__ void nrbc_fill(const RunDev &R, const double *Uc, int x, int y, int t, C (&g)[NQ]) {
+    const long long qp = R.qplane;
+    double Ut[4] = {Uc[t], Uc[qp + t], Uc[2 * qp + t], Uc[3 * qp + t]};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        bool on = s == XMIN ? x < 3 : s == XMAX ? x >= R.Nx - 3 : s == YMIN ? y < 3 : y >= R.Ny - 3;
+        if (on && R.bc[s] == BC_NRBC) lodi_add(R, Uc, s, x, y, t, Ut);
+    }
+    K<double> kd = load_k<double>(R);
+    double gd[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) gd[i] = (double)g[i];
+    Mom<double> mf = moments<double>(gd, kd);
+    Eq<double> ef = eq_coef<double>(mf.drho, mf.dux, mf.duy, mf.dT, kd);
+    Eq<double> et = eq_coef<double>(Ut[0] - R.rho0, Ut[1] - R.u0x, Ut[2] - R.u0y, Ut[3] - R.T0, kd);
+    for_each_feq<double>(ef, R, kd, [&](auto ic, double fe) { gd[decltype(ic)::value] -= fe; });
+    for_each_feq<double>(et, R, kd, [&](auto ic, double fe) {
+        constexpr int i = decltype(ic)::value;
+        g[i] = (C)(gd[i] + fe);
+    });
+}
+
+// Pull of a frame node with the boundary fill: periodic axes wrap, open axes pull at
+// x_f = clamp(x, 3, N-4) (eq. zg-bc copies all q populations of x_f to the boundary node).
+template <class S, class C>
+__device__ __forceinline__ void gather_general(const RunDev &R, const S *src, const double *Uc,
+                                               int x, int y, int t, C inv_scale, C (&g)[NQ]) {
+    int xs = R.open_x ? min(max(x, 3), R.Nx - 4) : x;
+    int ys = R.open_y ? min(max(y, 3), R.Ny - 4) : y;
+    const long long plane = R.plane;
+    const int pitch = R.pitch, Nx = R.Nx, Ny = R.Ny;
+    const bool ox = R.open_x, oy = R.open_y;
+    static_for<0, NQ>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        int sx = xs - ex_of(i), sy = ys - ey_of(i);
+        if (!ox) { while (sx < 0) sx += Nx; while (sx >= Nx) sx -= Nx; }
+        if (!oy) { while (sy < 0) sy += Ny; while (sy >= Ny) sy -= Ny; }
+        g[i] = ld_s(src + (long long)i * plane + (long long)sy * pitch + sx, inv_scale);
+    });
+    bool nr = (R.bc[XMIN] == BC_NRBC && x < 3) || (R.bc[XMAX] == BC_NRBC && x >= Nx - 3) ||
+              (R.bc[YMIN] == BC_NRBC && y < 3) || (R.bc[YMAX] == BC_NRBC && y >= Ny - 3);
+    if (nr) nrbc_fill<C>(R, Uc, x, y, t, g);
+}
+
+// ------------------------------------------------------------------------------------------
+// step kernels
+// ------------------------------------------------------------------------------------------
+template <class S, int TX>
+__global__ __launch_bounds__(256) void k_bulk(RunDev *const *__restrict__ runs,
+                                              const int *__restrict__ prefix, int nruns) {
+    using C = typename Traits<S>::C;
+    constexpr int TY = 256 / TX;
+    const int b = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int j = find_run(prefix, nruns, b);
+    const RunDev &R = *runs[j];
+    if (R.step >= R.limit) return;
+    constexpr int TI = TX == 64 ? 0 : (TX == 128 ? 1 : 2);
+    const int tb = b - prefix[j];
+    const int ty = tb / R.tiles_x[TI], tx = tb - ty * R.tiles_x[TI];
+    const int x = (R.fx0 / TX) * TX + tx * TX + (int)(threadIdx.x % TX);
+    const int y = R.fy0 + ty * TY + (int)(threadIdx.x / TX);
+    if (x < R.fx0 || x >= R.fx1 || y >= R.fy1) return;
+    const K<C> k = load_k<C>(R);
+    const S *src = (const S *)R.f[R.par];
+    S *dst = (S *)R.f[R.par ^ 1];
+    const long long plane = R.plane;
+    const int pitch = R.pitch;
+    const int idx = y * pitch + x;
+    C g[NQ];
+    static_for<0, NQ>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const S *base = src + (long long)i * plane - (ey_of(i) * pitch + ex_of(i));
+        g[i] = ld_s(base + idx, k.inv_scale);
+    });
+    Mom<C> m = moments<C>(g, k);
+    Eq<C> q = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
+    for_each_feq<C>(q, R, k, [&](auto ic, C fe) {
+        constexpr int i = decltype(ic)::value;
+        C out = g[i] + k.omega * (fe - g[i]);
+        st_s(dst + (long long)i * plane + idx, out, k.scale);
+    });
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_frame(RunDev *const *__restrict__ runs,
+                                               const int *__restrict__ prefix, int nruns) {
+    using C = typename Traits<S>::C;
+    const int b = blockIdx.x;
+    const int j = find_run(prefix, nruns, b);
+    const RunDev &R = *runs[j];
+    if (R.step >= R.limit) return;
+    const int t = (b - prefix[j]) * FRAME_BLOCK + (int)threadIdx.x;
+    if (t >= R.frame_n) return;
+    int x, y;
+    frame_xy(R, t, x, y);
+    const K<C> k = load_k<C>(R);
+    const S *src = (const S *)R.f[R.par];
+    S *dst = (S *)R.f[R.par ^ 1];
+    const double *Uc = R.U[R.par];
+    double *Un = R.U[R.par ^ 1];
+    const long long plane = R.plane, qp = R.qplane;
+    C g[NQ];
+    gather_general<S, C>(R, src, Uc, x, y, t, k.inv_scale, g);
+    Mom<C> m = moments<C>(g, k);
+    Un[t] = R.rho0 + (double)m.drho;
+    Un[qp + t] = R.u0x + (double)m.dux;
+    Un[2 * qp + t] = R.u0y + (double)m.duy;
+    Un[3 * qp + t] = R.T0 + (double)m.dT;
+    Eq<C> q = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
+    const long long idx = (long long)y * R.pitch + x;
+    const double sg = R.W > 0 ? sigma_at(R, x, y) : 0.0;
+    if (sg > 0.0) {
+        // grad Q: central, one-sided at the outermost layer of an open axis (eqs. FD-dx-*)
+        const C *Q = (const C *)R.Q;
+        int jx[3], jy[3];
+        C cx[3], cy[3];
+        if (R.open_x && x == 0) {
+            jx[0] = t; jx[1] = fidx(R, 1, y); jx[2] = fidx(R, 2, y);
+            cx[0] = C(-1.5); cx[1] = C(2); cx[2] = C(-0.5);
+        } else if (R.open_x && x == R.Nx - 1) {
+            jx[0] = t; jx[1] = fidx(R, x - 1, y); jx[2] = fidx(R, x - 2, y);
+            cx[0] = C(1.5); cx[1] = C(-2); cx[2] = C(0.5);
+        } else {
+            int xp = x + 1, xm = x - 1;
+            if (xp >= R.Nx) xp -= R.Nx;
+            if (xm < 0) xm += R.Nx;
+            jx[0] = fidx(R, xp, y); jx[1] = fidx(R, xm, y); jx[2] = t;
+            cx[0] = C(0.5); cx[1] = C(-0.5); cx[2] = C(0);
+        }
+        if (R.open_y && y == 0) {
+            jy[0] = t; jy[1] = fidx(R, x, 1); jy[2] = fidx(R, x, 2);
+            cy[0] = C(-1.5); cy[1] = C(2); cy[2] = C(-0.5);
+        } else if (R.open_y && y == R.Ny - 1) {
+            jy[0] = t; jy[1] = fidx(R, x, y - 1); jy[2] = fidx(R, x, y - 2);
+            cy[0] = C(1.5); cy[1] = C(-2); cy[2] = C(0.5);
+        } else {
+            int yp = y + 1, ym = y - 1;
+            if (yp >= R.Ny) yp -= R.Ny;
+            if (ym < 0) ym += R.Ny;
+            jy[0] = fidx(R, x, yp); jy[1] = fidx(R, x, ym); jy[2] = t;
+            cy[0] = C(0.5); cy[1] = C(-0.5); cy[2] = C(0);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (jx[a] < 0) jx[a] = t;
+            if (jy[a] < 0) jy[a] = t;
+        }
+        const C s = (C)sg;
+        for_each_feq<C>(q, R, k, [&](auto ic, C fe) {
+            constexpr int i = decltype(ic)::value;
+            const C *Qi = Q + (long long)i * qp;
+            C out = g[i] + k.omega * (fe - g[i]);
+            C gq = C(0);
+            if constexpr (ex_of(i) != 0)
+                gq += C(ex_of(i)) * (cx[0] * Qi[jx[0]] + cx[1] * Qi[jx[1]] + cx[2] * Qi[jx[2]]);
+            if constexpr (ey_of(i) != 0)
+                gq += C(ey_of(i)) * (cy[0] * Qi[jy[0]] + cy[1] * Qi[jy[1]] + cy[2] * Qi[jy[2]]);
+            out = out - s * (gq + C(2) * fe + s * Qi[t]);
+            st_s(dst + (long long)i * plane + idx, out, k.scale);
+        });
+    } else {
+        for_each_feq<C>(q, R, k, [&](auto ic, C fe) {
+            constexpr int i = decltype(ic)::value;
+            C out = g[i] + k.omega * (fe - g[i]);
+            st_s(dst + (long long)i * plane + idx, out, k.scale);
+        });
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_phase_a(RunDev *const *__restrict__ runs,
+                                                 const int *__restrict__ prefix, int nruns) {
+    using C = typename Traits<S>::C;
+    const int b = blockIdx.x;
+    const int j = find_run(prefix, nruns, b);
+    const RunDev &R = *runs[j];
+    if (R.step >= R.limit || !R.has_q) return;
+    const int t = (b - prefix[j]) * FRAME_BLOCK + (int)threadIdx.x;
+    if (t >= R.frame_n) return;
+    int x, y;
+    frame_xy(R, t, x, y);
+    if (!in_q(R, x, y)) return;
+    const K<C> k = load_k<C>(R);
+    const S *src = (const S *)R.f[R.par];
+    const double *Uc = R.U[R.par];
+    const long long qp = R.qplane;
+    C g[NQ];
+    gather_general<S, C>(R, src, Uc, x, y, t, k.inv_scale, g);
+    Mom<C> m = moments<C>(g, k);
+    Eq<C> q1 = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
+    Eq<C> q0 = eq_coef<C>((C)(Uc[t] - R.rho0), (C)(Uc[qp + t] - R.u0x), (C)(Uc[2 * qp + t] - R.u0y),
+                          (C)(Uc[3 * qp + t] - R.T0), k);
+    C *Q = (C *)R.Q;
+    for_each_feq<C>(q1, R, k, [&](auto ic, C fe) { g[decltype(ic)::value] = fe; });
+    for_each_feq<C>(q0, R, k, [&](auto ic, C fe) {
+        constexpr int i = decltype(ic)::value;
+        C *Qi = Q + (long long)i * qp + t;
+        *Qi = *Qi + C(0.5) * (fe + g[i]);
+    });
+}
+
+__global__ void k_flip(RunDev *const *runs, int nruns) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nruns) return;
+    RunDev *R = runs[j];
+    if (R->step < R->limit) {
+        R->par ^= 1;
+        R->step += 1;
+    }
+}
+
+__global__ void k_set_limit(RunDev *run, long long limit) {
+    if (threadIdx.x == 0) run->limit = limit;
+}
+
+__global__ void k_set_limits(RunDev *const *runs, const long long *limits, int n) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) runs[j]->limit = limits[j];
+}
+
+// ------------------------------------------------------------------------------------------
+// init, export, checks, reductions
+// ------------------------------------------------------------------------------------------
+template <class S>
+__global__ __launch_bounds__(256) void k_init(RunDev *R, const double *rho, const double *ux,
+                                              const double *uy, const double *T, float *absmax) {
+    using C = typename Traits<S>::C;
+    __shared__ float red[256];
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    const int nn = R->Nx * R->Ny;
+    float mx = 0.0f;
+    if (n < nn) {
+        const int y = n / R->Nx, x = n - y * R->Nx;
+        const K<C> k = load_k<C>(*R);
+        Eq<C> q = eq_coef<C>((C)(rho[n] - R->rho0), (C)(ux[n] - R->u0x), (C)(uy[n] - R->u0y),
+                             (C)(T[n] - R->T0), k);
+        S *dst = (S *)R->f[0];
+        const long long idx = (long long)y * R->pitch + x, plane = R->plane;
+        for_each_feq<C>(q, *R, k, [&](auto ic, C fe) {
+            constexpr int i = decltype(ic)::value;
+            if (absmax) mx = fmaxf(mx, fabsf((float)fe));
+            else st_s(dst + (long long)i * plane + idx, fe, k.scale);
+        });
+        if (!absmax) {
+            int t = fidx(*R, x, y);
+            if (t >= 0) {
+                const long long qp = R->qplane;
+                for (int c = 0; c < 2; ++c) {
+                    R->U[c][t] = rho[n];
+                    R->U[c][qp + t] = ux[n];
+                    R->U[c][2 * qp + t] = uy[n];
+                    R->U[c][3 * qp + t] = T[n];
+                }
+            }
+        }
+    }
+    if (absmax) {
+        red[threadIdx.x] = mx;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) absmax[blockIdx.x] = red[0];
+    }
+}
+
+// Moments of the current step (post-stream, post-boundary): re-pull from the previous
+// buffer with the previous moment strips; after 0 steps, moments of f*(0).
+template <class S>
+__global__ __launch_bounds__(256) void k_moments(RunDev *R, double *rho, double *ux, double *uy,
+                                                 double *T) {
+    using C = typename Traits<S>::C;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= R->Nx * R->Ny) return;
+    const int y = n / R->Nx, x = n - y * R->Nx;
+    const K<C> k = load_k<C>(*R);
+    C g[NQ];
+    if (R->step == 0) {
+        const S *src = (const S *)R->f[R->par];
+        const long long idx = (long long)y * R->pitch + x;
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) g[i] = ld_s(src + (long long)i * R->plane + idx, k.inv_scale);
+    } else {
+        int t = fidx(*R, x, y);
+        gather_general<S, C>(*R, (const S *)R->f[R->par ^ 1], R->U[R->par ^ 1], x, y, t < 0 ? 0 : t,
+                             k.inv_scale, g);
+    }
+    Mom<C> m = moments<C>(g, k);
+    if (rho) rho[n] = R->rho0 + (double)m.drho;
+    if (ux) ux[n] = R->u0x + (double)m.dux;
+    if (uy) uy[n] = R->u0y + (double)m.duy;
+    if (T) T[n] = R->T0 + (double)m.dT;
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_export_f(RunDev *R, const double *fbar, double *out) {
+    using C = typename Traits<S>::C;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    const int nn = R->Nx * R->Ny;
+    if (n >= nn) return;
+    const int y = n / R->Nx, x = n - y * R->Nx;
+    const K<C> k = load_k<C>(*R);
+    const S *src = (const S *)R->f[R->par];
+    const long long idx = (long long)y * R->pitch + x;
+    for (int i = 0; i < NQ; ++i)
+        out[(long long)i * nn + n] = fbar[i] + (double)ld_s(src + (long long)i * R->plane + idx, k.inv_scale);
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_export_q(RunDev *R, double *out) {
+    using C = typename Traits<S>::C;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= R->frame_n) return;
+    int x, y;
+    frame_xy(*R, t, x, y);
+    const long long nn = (long long)R->Nx * R->Ny;
+    const C *Q = (const C *)R->Q;
+    for (int i = 0; i < NQ; ++i) out[i * nn + (long long)y * R->Nx + x] = (double)Q[i * R->qplane + t];
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_check(RunDev *R, int *flag) {
+    using C = typename Traits<S>::C;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= R->Nx * R->Ny) return;
+    const int y = n / R->Nx, x = n - y * R->Nx;
+    const K<C> k = load_k<C>(*R);
+    const S *src = (const S *)R->f[R->par];
+    const long long idx = (long long)y * R->pitch + x;
+    C g[NQ];
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        g[i] = ld_s(src + (long long)i * R->plane + idx, k.inv_scale);
+        bad |= !isfinite((double)g[i]);
+    }
+    Mom<C> m = moments<C>(g, k);
+    double rho = R->rho0 + (double)m.drho, T = R->T0 + (double)m.dT;
+    bad |= !(rho > 0.0) || !(T > 0.0) || !isfinite(rho) || !isfinite(T);
+    if (bad) atomicOr(flag, 1);
+}
+
+// Reflection-error sums of one bulk row per block, fixed order (strided per thread, then a
+// tree in LDS): partials[3*row + z].
+__global__ __launch_bounds__(256) void k_err_rows(const double *rho, const double *ux,
+                                                  const double *T, int Nx, int x0, int y0, int lx,
+                                                  const double *rr, const double *ru,
+                                                  const double *rt, double *partials) {
+    __shared__ double red[3][256];
+    const int row = blockIdx.x;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int xb = threadIdx.x; xb < lx; xb += 256) {
+        long long n = (long long)(row + y0) * Nx + (xb + x0), m = (long long)row * lx + xb;
+        double a = (rho[n] - rr[m]) / rr[m], b = (ux[n] - ru[m]) / ru[m], c = (T[n] - rt[m]) / rt[m];
+        s[0] += a * a; s[1] += b * b; s[2] += c * c;
+    }
+    for (int z = 0; z < 3; ++z) red[z][threadIdx.x] = s[z];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int z = 0; z < 3; ++z) red[z][threadIdx.x] += red[z][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) partials[3 * row + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_err_final(const double *partials, int nrows, double *out) {
+    __shared__ double red[3][256];
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int r = threadIdx.x; r < nrows; r += 256)
+        for (int z = 0; z < 3; ++z) s[z] += partials[3 * r + z];
+    for (int z = 0; z < 3; ++z) red[z][threadIdx.x] = s[z];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int z = 0; z < 3; ++z) red[z][threadIdx.x] += red[z][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[threadIdx.x] = sqrt(red[threadIdx.x][0]);
+}
+
+// ------------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------------
+#define LBM_DISPATCH(storage, ...)                                                          \
+    switch (storage) {                                                                      \
+    case ST_F64: { using S = double; __VA_ARGS__; break; }                                  \
+    case ST_F32: { using S = float; __VA_ARGS__; break; }                                   \
+    default: { using S = _Float16; __VA_ARGS__; break; }                                    \
+    }
+
+static inline int blocks_for(long long n) { return (int)((n + 255) / 256); }
+
+hipError_t launch_phase_a(const LaunchSet &L, int storage, hipStream_t s) {
+    if (L.q_blocks <= 0) return hipSuccess;
+    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a<S>), dim3(L.q_blocks), dim3(256), 0, s,
+                                              L.runs, L.q_prefix, L.nruns));
+    return hipGetLastError();
+}
+
+hipError_t launch_frame(const LaunchSet &L, int storage, hipStream_t s) {
+    if (L.frame_blocks <= 0) return hipSuccess;
+    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_frame<S>), dim3(L.frame_blocks), dim3(256), 0, s,
+                                              L.runs, L.frame_prefix, L.nruns));
+    return hipGetLastError();
+}
+
+hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, hipStream_t s) {
+    if (L.bulk_blocks <= 0) return hipSuccess;
+    switch (tx) {
+    case 64:
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 64>), dim3(L.bulk_blocks), dim3(256), 0,
+                                                  s, L.runs, L.bulk_prefix, L.nruns));
+        break;
+    case 128:
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 128>), dim3(L.bulk_blocks), dim3(256), 0,
+                                                  s, L.runs, L.bulk_prefix, L.nruns));
+        break;
+    default:
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 256>), dim3(L.bulk_blocks), dim3(256), 0,
+                                                  s, L.runs, L.bulk_prefix, L.nruns));
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_flip(const LaunchSet &L, hipStream_t s) {
+    hipLaunchKernelGGL(k_flip, dim3((L.nruns + 255) / 256), dim3(256), 0, s, L.runs, L.nruns);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_limit(RunDev *run, long long limit, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_limit, dim3(1), dim3(64), 0, s, run, limit);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_limits(RunDev *const *runs, const long long *limits, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_limits, dim3((n + 255) / 256), dim3(256), 0, s, runs, limits, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(RunDev *run, int storage, int Nx, int Ny, const double *rho,
+                       const double *ux, const double *uy, const double *T, float *absmax,
+                       hipStream_t s) {
+    int nb = blocks_for((long long)Nx * Ny);
+    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_init<S>), dim3(nb), dim3(256), 0, s, run, rho, ux, uy,
+                                              T, absmax));
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(RunDev *run, int storage, int Nx, int Ny, double *rho, double *ux,
+                          double *uy, double *T, hipStream_t s) {
+    int nb = blocks_for((long long)Nx * Ny);
+    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_moments<S>), dim3(nb), dim3(256), 0, s, run, rho, ux,
+                                              uy, T));
+    return hipGetLastError();
+}
+
+hipError_t launch_export_f(RunDev *run, int storage, int Nx, int Ny, const double *fbar,
+                           double *out, hipStream_t s) {
+    int nb = blocks_for((long long)Nx * Ny);
+    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_export_f<S>), dim3(nb), dim3(256), 0, s, run, fbar,
+                                              out));
+    return hipGetLastError();
+}
+
+hipError_t launch_export_q(RunDev *run, int storage, int frame_n, double *out, hipStream_t s) {
+    if (frame_n <= 0) return hipSuccess;
+    int nb = blocks_for(frame_n);
+    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_export_q<S>), dim3(nb), dim3(256), 0, s, run, out));
+    return hipGetLastError();
+}
+
+hipError_t launch_check(RunDev *run, int storage, int Nx, int Ny, int *flag, hipStream_t s) {
+    int nb = blocks_for((long long)Nx * Ny);
+    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_check<S>), dim3(nb), dim3(256), 0, s, run, flag));
+    return hipGetLastError();
+}
+
+hipError_t launch_err_rows(const double *rho, const double *ux, const double *T, int Nx, int x0,
+                           int y0, int lx, int ly, const double *rr, const double *ru,
+                           const double *rt, double *partials, hipStream_t s) {
+    if (ly <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_err_rows, dim3(ly), dim3(256), 0, s, rho, ux, T, Nx, x0, y0, lx, rr, ru, rt,
+                       partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_err_final(const double *partials, int nrows, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_err_final, dim3(1), dim3(256), 0, s, partials, nrows, out);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,82 @@
+"""Shared test helpers: build the same run on the HIP library and on the oracle, compare."""
+import sys
+
+import numpy as np
+
+from paper_2504_20169_amd import lbm
+from paper_2504_20169_amd import workloads as wl
+
+SIDES = {"xmin": 1, "xmax": 2, "ymin": 4, "ymax": 8}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def perm_lib_to_oracle(oracle_mod):
+    """perm[k] = library index of the oracle's velocity k."""
+    e, _, _ = lbm.lbm_velocities()
+    eo, _, _ = oracle_mod.lattice()
+    where = {(int(a), int(b)): i for i, (a, b) in enumerate(e)}
+    return np.array([where[(int(a), int(b))] for a, b in eo])
+
+
+def make_pair(oracle_mod, Lx, Ly, tau=0.8, mean=(1.0, 0.0, 0.0, 1.0), bc=None, pml=None,
+              fields=None, storage="f64", launch=None, stream=None, allocator=None, gpu=True):
+    """bc: dict side->kind ('zg'|'nrbc'|'periodic') or a kind for all sides; pml: (mask, W,
+    sigma).  Returns (gpu_run or None, oracle_run)."""
+    rho0, ux0, uy0, T0 = mean
+    runs = []
+    o = oracle_mod.OracleRun(Lx, Ly, tau, rho0, ux0, uy0, T0)
+    g = lbm.Run(Lx, Ly, tau, rho0, ux0, uy0, T0, storage=storage, stream=stream,
+                allocator=allocator) if gpu else None
+    kinds = {"periodic": 0, "zg": 1, "nrbc": 2}
+    if bc is not None:
+        items = bc.items() if isinstance(bc, dict) else [(s, bc) for s in SIDES]
+        for side, kind in items:
+            o.set_bc(SIDES[side], kinds[kind])
+            if g:
+                g.set_bc(SIDES[side], kind)
+    if pml is not None:
+        mask, W, sig = pml
+        o.set_pml(mask, W, sig)
+        if g:
+            g.set_pml(mask, W, sig)
+    if g and launch:
+        g.set_launch(**launch)
+    Nx, Ny = o.grid()
+    if g:
+        assert g.grid() == (Nx, Ny)
+    F = fields(Nx, Ny) if callable(fields) else fields
+    o.init(*F.as_tuple())
+    if g:
+        g.init(*F.as_tuple())
+    return g, o
+
+
+def rel_errors(g, o, perm, with_f=True):
+    """Relative differences: rho and T relative to max |Z| of the oracle; u relative to the larger
+    of max |u| and the sound speed c_s = 1 (the FP64 oracle forms u = sum f xi / rho from O(c_s)
+    terms, so its own rounding is ~1e-16 c_s whatever the flow speed); populations relative to
+    their weight."""
+    mg = g.moments()
+    mo = o.moments()
+    out = {}
+    for name, a, b in zip(("rho", "ux", "uy", "T"), mg, mo):
+        if name in ("ux", "uy"):
+            scale = max(np.abs(mo[1]).max(), np.abs(mo[2]).max(), 1.0)
+        else:
+            scale = np.abs(b).max()
+        out[name] = float(np.abs(a - b).max() / scale)
+    if with_f:
+        _, w, _ = lbm.lbm_velocities()
+        fg = g.populations()[perm]
+        fo = o.populations()
+        wo = w[perm]
+        out["f"] = float((np.abs(fg - fo).max(axis=(1, 2)) / wo).max())
+    return out
+
+
+def noise(seed, mean=(1.0, 0.0, 0.0, 1.0), amp=1e-3):
+    return lambda Nx, Ny: wl.noisy_state(Nx, Ny, seed, *mean, amp=amp)

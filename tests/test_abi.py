@@ -1,0 +1,100 @@
+"""The C-ABI library loads, exports every symbol include/lbm.h declares, and validates its
+arguments on the host (no device work in these tests)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2504_20169_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    lib = lbm.load()
+    names = _declared()
+    assert len(names) >= 30
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(lbm.EXPORTED) == names
+
+
+def test_velocity_table_matches_oracle(oracle_mod):
+    e, w, r = lbm.lbm_velocities()
+    eo, wo, ro = oracle_mod.lattice()
+    assert abs(r - ro) < 1e-15
+    lib = {(int(a), int(b)): wi for (a, b), wi in zip(e, w)}
+    orc = {(int(a), int(b)): wi for (a, b), wi in zip(eo, wo)}
+    assert set(lib) == set(orc)
+    for k in lib:
+        assert abs(lib[k] - orc[k]) <= 1e-16 + 1e-14 * orc[k]
+    # library order: rest first, then +e/-e pairs
+    assert tuple(e[0]) == (0, 0)
+    for p in range(18):
+        assert tuple(e[1 + 2 * p]) == tuple(-e[2 + 2 * p])
+
+
+@pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.3), dict(nx=0), dict(ny=-1),
+                                dict(rho0=0.0), dict(T0=-1.0), dict(storage=7),
+                                dict(rho0=float("nan")), dict(storage="f16", f16_scale=3.0)])
+def test_create_rejects_bad_descriptor(kw):
+    args = dict(nx=16, ny=16, tau=0.8)
+    args.update(kw)
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Run(**args)
+    assert ei.value.status == lbm.LBM_ERR_ARG
+
+
+def test_setters_validate_and_grid():
+    r = lbm.Run(20, 10, 0.8)
+    with pytest.raises(lbm.LbmError):
+        r.set_pml(lbm.LBM_ALL, -1, 0.1)
+    with pytest.raises(lbm.LbmError):
+        r.set_pml(lbm.LBM_ALL, 4, -0.1)
+    with pytest.raises(lbm.LbmError):
+        r.set_bc(16, "zg")
+    r.set_bc(lbm.LBM_ALL, "zg")
+    r.set_pml(lbm.LBM_XMIN | lbm.LBM_YMAX, 5, 0.1)
+    assert r.grid() == (25, 15)
+    assert r.footprint() > 2 * 37 * 25 * 15 * 8
+    with pytest.raises(lbm.LbmError) as ei:
+        r.step(1)
+    assert ei.value.status == lbm.LBM_ERR_STATE
+
+
+def test_init_rejects_inconsistent_configuration():
+    # PML on a periodic side / one-sided periodic / too small open axis are caught before any
+    # device allocation.
+    cases = []
+    r = lbm.Run(16, 16, 0.8)
+    r.set_pml(lbm.LBM_ALL, 4, 0.1)           # sides still periodic
+    cases.append(r)
+    r = lbm.Run(16, 16, 0.8)
+    r.set_bc(lbm.LBM_XMIN, "zg")             # x periodic on one side only
+    cases.append(r)
+    r = lbm.Run(5, 16, 0.8)
+    r.set_bc(lbm.LBM_XMIN | lbm.LBM_XMAX, "nrbc")  # open x with 5 nodes
+    cases.append(r)
+    for r in cases:
+        Nx, Ny = r.grid()
+        with pytest.raises(lbm.LbmError) as ei:
+            r.init(np.ones((Ny, Nx)), 0.0, 0.0, 1.0)
+        assert ei.value.status == lbm.LBM_ERR_ARG
+
+
+def test_init_rejects_bad_fields():
+    r = lbm.Run(8, 8, 0.8)
+    f = np.ones((8, 8))
+    bad = f.copy()
+    bad[3, 3] = np.nan
+    with pytest.raises(lbm.LbmError):
+        r.init(bad, 0.0, 0.0, 1.0)
+    with pytest.raises(lbm.LbmError):
+        r.init(f, 0.0, 0.0, -f)

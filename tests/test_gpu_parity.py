@@ -1,0 +1,197 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle, element by element.
+
+Bar: FP64 storage matches to 1e-12 relative (rho, T relative to max |Z|; u relative to max |u|;
+populations relative to their weight).  Cases span several tiles with ragged tails, every
+boundary kind, PML on all or some sides, corners, mean flow, tiny grids and the full-size grids
+in the launch configuration the benchmark times.
+"""
+import numpy as np
+import pytest
+
+from paper_2504_20169_amd import lbm
+from paper_2504_20169_amd import workloads as wl
+from _helpers import make_pair, noise, perm_lib_to_oracle, rel_errors, say
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def perm(oracle_mod):
+    return perm_lib_to_oracle(oracle_mod)
+
+
+def _assert_parity(err, tol=TOL):
+    bad = {k: v for k, v in err.items() if not v <= tol}
+    assert not bad, err
+
+
+def test_plain_method_config(oracle_mod, perm):
+    """64^2 bulk + 8-cell PML (80^2), quadratic ramp sigma_max = 0.1, ZG, rest state, Gaussian
+    pulse A = 1e-3, b = 4 at the centre, 200 steps: the full workload, every node compared."""
+    spec = wl.pulse_box(64, 8, 0.1, 200, "zg")
+    say("case plain 80x80 ZG+PML 200 steps")
+    g, o = make_pair(oracle_mod, 64, 64, bc="zg", pml=(15, 8, 0.1), fields=spec.fields)
+    g.step(200)
+    o.step(200)
+    _assert_parity(rel_errors(g, o, perm))
+
+
+@pytest.mark.parametrize("case", [
+    dict(name="nrbc_pml_flow", Lx=70, Ly=45, bc="nrbc", pml=(15, 6, 0.05), mean=(1.0, 0.1, 0.0, 1.0), steps=80),
+    dict(name="zg_pml_flow_diag", Lx=50, Ly=66, bc="zg", pml=(15, 5, 0.08), mean=(1.0, 0.05, -0.04, 1.0), steps=60),
+    dict(name="periodic_ragged", Lx=67, Ly=61, bc="periodic", pml=None, mean=(1.0, 0.02, 0.01, 1.0), steps=100),
+    dict(name="step_geometry", Lx=60, Ly=20, bc={"xmin": "nrbc", "xmax": "nrbc", "ymin": "periodic", "ymax": "periodic"},
+         pml=(3, 10, 0.1), mean=(1.0, 0.05, 0.0, 1.0), steps=90),
+    dict(name="mixed_sides", Lx=41, Ly=37, bc={"xmin": "zg", "xmax": "nrbc", "ymin": "nrbc", "ymax": "zg"},
+         pml=(2 | 4, 5, 0.1), mean=(1.0, 0.06, 0.03, 1.02), steps=50),
+    dict(name="tiny_open", Lx=7, Ly=7, bc="nrbc", pml=None, mean=(1.0, 0.0, 0.0, 1.0), steps=20),
+    dict(name="tiny_periodic", Lx=3, Ly=5, bc="periodic", pml=None, mean=(1.0, 0.0, 0.0, 1.0), steps=20),
+    dict(name="thin_pml_w1", Lx=30, Ly=28, bc="zg", pml=(15, 1, 0.1), mean=(1.0, 0.0, 0.0, 1.0), steps=40),
+    dict(name="thin_pml_w2_nrbc", Lx=30, Ly=28, bc="nrbc", pml=(15, 2, 0.1), mean=(1.0, 0.03, 0.0, 1.0), steps=40),
+    dict(name="x_periodic_y_open", Lx=33, Ly=40, bc={"xmin": "periodic", "xmax": "periodic", "ymin": "zg", "ymax": "nrbc"},
+         pml=(4 | 8, 7, 0.05), mean=(1.0, 0.0, 0.04, 0.98), steps=60),
+])
+def test_parity_cases(oracle_mod, perm, case):
+    say("case", case["name"])
+    g, o = make_pair(oracle_mod, case["Lx"], case["Ly"], bc=case["bc"], pml=case["pml"],
+                     mean=case["mean"], fields=noise(11, case["mean"]))
+    g.step(case["steps"])
+    o.step(case["steps"])
+    _assert_parity(rel_errors(g, o, perm))
+
+
+def test_vortex_pulse_workload_small(oracle_mod, perm):
+    """The vortex + pulse workload (Mach 0.1, NRBC, PML) at a reduced bulk, 300 steps."""
+    spec = wl.vortex_pulse(L=96, W=12, sigma_max=0.0015, mach=0.1, steps=300, bc="nrbc",
+                           radius=8.0)
+    say("case vortex_pulse 120^2 NRBC 300 steps")
+    g, o = make_pair(oracle_mod, 96, 96, bc="nrbc", pml=(15, 12, 0.0015),
+                     mean=(1.0, 0.1, 0.0, 1.0), fields=spec.fields)
+    g.step(300)
+    o.step(300)
+    _assert_parity(rel_errors(g, o, perm))
+
+
+def test_moments_at_step_zero(oracle_mod, perm):
+    g, o = make_pair(oracle_mod, 20, 18, bc="nrbc", pml=(15, 3, 0.1), fields=noise(4))
+    _assert_parity(rel_errors(g, o, perm))
+
+
+def test_pml_q_matches_oracle(oracle_mod, perm):
+    g, o = make_pair(oracle_mod, 24, 20, bc="nrbc", pml=(15, 5, 0.1), mean=(1.0, 0.05, 0.0, 1.0),
+                     fields=noise(5, (1.0, 0.05, 0.0, 1.0)))
+    g.step(30)
+    o.step(30)
+    qg = g.pml_q()[perm]
+    qo = o.pml_q()
+    assert np.abs(qg - qo).max() <= TOL * max(np.abs(qo).max(), 1e-30)
+
+
+@pytest.mark.parametrize("bc", ["zg", "nrbc"])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_sigma_zero_pml_bitwise_equals_plain(bc, storage):
+    """sigma_max = 0 with W > 0 reproduces W = 0 on the same grid bit for bit."""
+    W, L = 6, 40
+    F = wl.noisy_state(L + 2 * W, L + 2 * W, 9, 1.0, 0.04, 0.0, 1.0)
+    a = lbm.Run(L, L, 0.8, 1.0, 0.04, 0.0, 1.0, storage=storage)
+    a.set_bc(15, bc)
+    a.set_pml(15, W, 0.0)
+    b = lbm.Run(L + 2 * W, L + 2 * W, 0.8, 1.0, 0.04, 0.0, 1.0, storage=storage)
+    b.set_bc(15, bc)
+    a.init(*F.as_tuple())
+    b.init(*F.as_tuple())
+    a.step(37)
+    b.step(37)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+def test_tile_shapes_and_graphs_bitwise_identical():
+    F = wl.noisy_state(150, 140, 3, 1.0, 0.05, 0.0, 1.0)
+    outs = []
+    for tx, gs in ((64, 0), (128, 8), (256, 32), (64, 32)):
+        r = lbm.Run(134, 124, 0.8, 1.0, 0.05, 0.0, 1.0)
+        r.set_bc(15, "nrbc")
+        r.set_pml(15, 8, 0.05)
+        r.set_launch(bulk_tx=tx, graph_steps=gs)
+        r.init(*F.as_tuple())
+        r.step(41)
+        outs.append(r.populations())
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+
+
+def test_conservation_on_gpu():
+    e, w, rr = lbm.lbm_velocities()
+    xi = rr * e.astype(float)
+    r = lbm.Run(130, 70, 0.8)
+    r.init(*wl.noisy_state(130, 70, 8, 1.0, 0.03, -0.02, 1.0, amp=2e-3).as_tuple())
+
+    def cons():
+        f = r.populations().sum(axis=(1, 2))
+        return np.array([f.sum(), (f * xi[:, 0]).sum(), (f * xi[:, 1]).sum(), (f * (xi ** 2).sum(1)).sum()])
+
+    c0 = cons()
+    r.step(500)
+    c1 = cons()
+    assert np.all(np.abs(c1 - c0) <= 1e-12 * np.abs(c0).max()), c1 - c0
+
+
+def test_error_norms_match_oracle(oracle_mod, perm):
+    mean = (1.0, 0.05, 0.0, 1.0)
+    g, o = make_pair(oracle_mod, 30, 26, bc="nrbc", pml=(15, 4, 0.1), mean=mean, fields=noise(6, mean))
+    g.step(25)
+    o.step(25)
+    ref = wl.noisy_state(30, 26, 99, *mean)
+    eg = g.error_norms(ref.rho, ref.ux, ref.T)
+    eo = o.error_norms(ref.rho, ref.ux, ref.T)
+    assert np.allclose(eg, eo, rtol=1e-12, atol=0)
+
+
+def test_check_flags_blow_up_and_passes_stable():
+    r = lbm.Run(40, 40, 0.8)
+    r.set_bc(15, "zg")
+    r.set_pml(15, 8, 50.0)  # host-chosen absurd absorption: the state overflows to inf/nan
+    r.init(*wl.noisy_state(56, 56, 1).as_tuple())
+    assert r.check() == lbm.LBM_OK
+    r.step(200)
+    assert r.check() == lbm.LBM_ERR_UNSTABLE
+
+
+def test_checkpoint_roundtrip_bitwise(tmp_path):
+    def make():
+        r = lbm.Run(60, 50, 0.8, 1.0, 0.05, 0.0, 1.0)
+        r.set_bc(15, "nrbc")
+        r.set_pml(15, 6, 0.05)
+        r.init(*wl.noisy_state(72, 62, 2, 1.0, 0.05, 0.0, 1.0).as_tuple())
+        return r
+    a = make()
+    a.step(30)
+    b = make()
+    b.step(12)
+    b.save(tmp_path / "ck.bin")
+    c = make()
+    c.load(tmp_path / "ck.bin")
+    c.step(18)
+    assert c.step_count == 30
+    assert np.array_equal(a.populations(), c.populations())
+    assert all(np.array_equal(x, y) for x, y in zip(a.moments(), c.moments()))
+
+
+@pytest.mark.parametrize("which", ["vortex_1088", "pulses_4224"])
+def test_full_size_grids_in_bench_launch(oracle_mod, perm, which):
+    """The full grids of the benchmark workloads (1024^2 + 32 PML with NRBC; 4096^2 + 64 PML with
+    ZG), default launch configuration, noisy state so every node and path is distinct; a few
+    steps compared node by node (moments everywhere; populations on the smaller grid)."""
+    if which == "vortex_1088":
+        L, W, bc, sig, mean, steps = 1024, 32, "nrbc", 0.0015, (1.0, 0.1, 0.0, 1.0), 4
+    else:
+        L, W, bc, sig, mean, steps = 4096, 64, "zg", 0.01, (1.0, 0.05, 0.0, 1.0), 2
+    say("case full", which)
+    g, o = make_pair(oracle_mod, L, L, bc=bc, pml=(15, W, sig), mean=mean,
+                     fields=noise(21, mean, 5e-4))
+    g.step(steps)
+    o.step(steps)
+    err = rel_errors(g, o, perm, with_f=(which == "vortex_1088"))
+    say(which, err)
+    _assert_parity(err)
