@@ -44,10 +44,14 @@ def make_run(lbm, wl, storage, stream, alloc, L, W, sigma, mach, bc):
 
 
 def time_run(torch, r, steps, warmup, profile):
+    """Time `steps` steps after `warmup`.  Unprofiled: HIP-graph replays with the boundary/PML
+    chains on side streams beside the bulk kernel.  Profiled: the kernel classes in order on the
+    run's stream, bracketed by HIP events (per-class launch durations)."""
+    r.profile(False)
     r.step(warmup)
     r.synchronize()
-    r.profile(profile)
     if profile:
+        r.profile(True)
         r.profile_read(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -60,6 +64,17 @@ def time_run(torch, r, steps, warmup, profile):
         ms, n = r.profile_read(reset=True)
         r.profile(False)
     return dt, ms, n
+
+
+def serve_trace(jobs, rate, scale, storage, tick):
+    from paper_2504_20169_amd import workloads as wl
+    from paper_2504_20169_amd.serve import Engine, GpuBackend, jobs_from_trace
+    trace = wl.poisson_trace(jobs, rate=rate, seed=5)
+    be = GpuBackend(storage=storage)
+    eng = Engine(be, int(200e9), tick_steps=tick)
+    rep = eng.run_trace(jobs_from_trace(trace, scale))
+    be.close()
+    return rep
 
 
 def cpu_baseline(wl, L, W, sigma, mach, bc, steps):
@@ -91,6 +106,12 @@ def main():
     ap.add_argument("--storages", default="f64,f32,f16")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--prof-steps", type=int, default=500,
+                    help="steps of the separate profiled pass that times each kernel class")
+    ap.add_argument("--serve-jobs", type=int, default=24, help="0 skips the serving trace")
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-scale", type=float, default=0.1,
+                    help="multiplier on the trace's step counts (1000-20000)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -127,7 +148,8 @@ def main():
                            args.mach, args.bc)
         Nx, Ny = r.grid()
         n_bulk, n_frame, n_q = r.node_classes()
-        dt, ms, n = time_run(torch, r, args.steps, args.warmup, profile=True)
+        dt, _, _ = time_run(torch, r, args.steps, args.warmup, profile=False)
+        _, ms, n = time_run(torch, r, args.prof_steps, 5, profile=True)
         st = r.check()
         nodes = Nx * Ny
         mlups = nodes * args.steps / dt / 1e6
@@ -144,6 +166,7 @@ def main():
             bulk_kernel_gbs=bulk_bytes / (bulk_ms * 1e-3) / 1e9 if bulk_ms > 0 else None,
             bulk_nodes=n_bulk, frame_nodes=n_frame, q_nodes=n_q, bulk_bytes_per_launch=bulk_bytes,
             boundary_cost_ratio=(ms[1] + ms[2]) / max(ms[0], 1e-9),
+            profiled_ms_per_step=sum(ms) / max(n[1], 1),
             stable=(st == lbm.LBM_OK))
         if storage != "f64" and "f64" in results:
             rho_ref, ux_ref, uy_ref, T_ref = results["f64"]["_moments"]
@@ -189,12 +212,19 @@ def main():
             "traffic": None,
             "bytes_per_launch": R["bulk_bytes_per_launch"],
             "avg_launch_ms": round(R["bulk_kernel_ms"], 5),
+            "timing": "HIP events around each k_bulk launch on the run's stream, %d-step profiled pass "
+                      "(kernel classes in order)" % args.prof_steps,
         },
         "variants": {},
     }
     for s, v in results.items():
         v = {k: (round(x, 6) if isinstance(x, float) else x) for k, x in v.items() if not k.startswith("_")}
         line["variants"][s] = v
+    if args.serve_jobs > 0:
+        _log("bench: serving trace")
+        line["serving"] = serve_trace(args.serve_jobs, args.serve_rate, args.serve_scale, "f32", 200)
+        line["serving"].update(trace="%d Poisson arrivals at %.0f/s, steps x%.2g, FP32 storage, "
+                                     "HBM budget 200 GB" % (args.serve_jobs, args.serve_rate, args.serve_scale))
     if not args.no_cpu:
         _log("bench: cpu baseline (oracle)")
         mlups_cpu, cores, dt_cpu = cpu_baseline(wl, args.L, args.W, args.sigma, args.mach, args.bc,

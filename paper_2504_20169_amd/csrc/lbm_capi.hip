@@ -64,6 +64,35 @@ struct DeviceMem {
 
 int tx_index(int tx) { return tx == 64 ? 0 : tx == 128 ? 1 : 2; }
 
+// Side streams and events of the per-step fork/join: the bulk kernel runs on the main stream
+// while the boundary/PML chain of the frame (side stream 1) and of the characteristic ring
+// (side stream 2) runs beside it.  All streams keep the default priority.
+struct StepStreams {
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, a_done[2] = {nullptr, nullptr}, f_done[2] = {nullptr, nullptr};
+    bool ok = false;
+    hipError_t create() {
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&a_done[k], hipEventDisableTiming);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&f_done[k], hipEventDisableTiming);
+        ok = e == hipSuccess;
+        return e;
+    }
+    void destroy() {
+        for (int k = 0; k < 2; ++k) {
+            if (side[k]) (void)hipStreamDestroy(side[k]);
+            if (a_done[k]) (void)hipEventDestroy(a_done[k]);
+            if (f_done[k]) (void)hipEventDestroy(f_done[k]);
+            side[k] = nullptr; a_done[k] = f_done[k] = nullptr;
+        }
+        if (fork) (void)hipEventDestroy(fork);
+        fork = nullptr;
+        ok = false;
+    }
+};
+
 }  // namespace
 
 struct lbm_run {
@@ -77,8 +106,8 @@ struct lbm_run {
     RunDev hd{};
     RunDev *dd = nullptr;
     RunDev **dptr = nullptr;
-    int *dprefix = nullptr;   // bulk[2], frame[2], q[2]
-    int nblocks[3] = {0, 0, 0};
+    int *dprefix = nullptr;   // [NCLS][2] prefix arrays of the single-run launch set
+    int nblocks[NCLS] = {0, 0, 0, 0, 0};
     double fbar[NQ];
     double *fbar_d = nullptr;
     hipStream_t own_stream = nullptr;
@@ -98,6 +127,7 @@ struct lbm_run {
     int64_t prof_n[3] = {0, 0, 0};
     lbm_group *group = nullptr;
     size_t footprint = 0;
+    StepStreams ss;
 };
 
 struct lbm_group {
@@ -115,8 +145,9 @@ struct lbm_group {
     long long *hlimits = nullptr;     // pinned
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
-    int blocks[3] = {0, 0, 0};
+    int blocks[NCLS] = {0, 0, 0, 0, 0};
     size_t cap = 0;
+    StepStreams ss;
 };
 
 namespace {
@@ -155,6 +186,11 @@ lbm_status setup_geometry(lbm_run *h, RunDev &R) {
     R.gxp = std::min(depth[XMAX], R.Nx - R.gxm);
     R.gym = std::min(depth[YMIN], R.Ny);
     R.gyp = std::min(depth[YMAX], R.Ny - R.gym);
+    R.rxm = h->bc[XMIN] == BC_NRBC ? 3 : 0;
+    R.rxp = h->bc[XMAX] == BC_NRBC ? 3 : 0;
+    R.rym = h->bc[YMIN] == BC_NRBC ? 3 : 0;
+    R.ryp = h->bc[YMAX] == BC_NRBC ? 3 : 0;
+    R.ring_n = (R.rym + R.ryp) * R.Nx + (R.Ny - R.rym - R.ryp) * (R.rxm + R.rxp);
     R.fx0 = R.gxm; R.fx1 = R.Nx - R.gxp;
     R.fy0 = R.gym; R.fy1 = R.Ny - R.gyp;
     long long fast = (long long)std::max(0, R.fx1 - R.fx0) * std::max(0, R.fy1 - R.fy0);
@@ -163,6 +199,10 @@ lbm_status setup_geometry(lbm_run *h, RunDev &R) {
     R.pitch = (int)round_up(R.Nx, 64);
     R.plane = round_up((long long)R.pitch * R.Ny, 64);
     R.qplane = round_up(std::max(R.frame_n, 1), 64);
+    // kernels address a population plane with a 32-bit byte offset
+    if ((unsigned long long)R.plane * elem_size(d.storage) >= (1ULL << 32) ||
+        (unsigned long long)R.qplane * 4 * sizeof(double) >= (1ULL << 32))
+        return fail(LBM_ERR_ARG, "grid too large: one population plane must stay below 4 GiB");
     for (int k = 0; k < 3; ++k) {
         int tx = 64 << k, ty = 256 / tx;
         if (fast > 0) {
@@ -232,16 +272,19 @@ size_t footprint_of(const RunDev &R, int storage) {
     return b;
 }
 
-void compute_blocks(const RunDev &R, int tx, int nb[3]) {
+void compute_blocks(const RunDev &R, int tx, int nb[NCLS]) {
     int k = tx_index(tx);
-    nb[0] = R.tiles_x[k] * R.tiles_y[k];
-    nb[1] = (R.frame_n + FRAME_BLOCK - 1) / FRAME_BLOCK;
-    nb[2] = R.has_q ? nb[1] : 0;
+    nb[CLS_BULK] = R.tiles_x[k] * R.tiles_y[k];
+    nb[CLS_FRAME] = (R.frame_n + FRAME_BLOCK - 1) / FRAME_BLOCK;
+    nb[CLS_RING] = (R.ring_n + FRAME_BLOCK - 1) / FRAME_BLOCK;
+    nb[CLS_Q] = R.has_q ? nb[CLS_FRAME] : 0;
+    nb[CLS_QRING] = R.has_q ? nb[CLS_RING] : 0;
 }
 
 lbm_status upload_prefix(lbm_run *h) {
     compute_blocks(h->hd, h->launch.bulk_tx, h->nblocks);
-    int pre[6] = {0, h->nblocks[0], 0, h->nblocks[1], 0, h->nblocks[2]};
+    int pre[2 * NCLS];
+    for (int c = 0; c < NCLS; ++c) { pre[2 * c] = 0; pre[2 * c + 1] = h->nblocks[c]; }
     HIP_TRY(hipMemcpyAsync(h->dprefix, pre, sizeof pre, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     return LBM_OK;
@@ -250,14 +293,31 @@ lbm_status upload_prefix(lbm_run *h) {
 LaunchSet single_set(lbm_run *h) {
     LaunchSet L;
     L.runs = h->dptr;
-    L.bulk_prefix = h->dprefix;
-    L.frame_prefix = h->dprefix + 2;
-    L.q_prefix = h->dprefix + 4;
+    for (int c = 0; c < NCLS; ++c) {
+        L.prefix[c] = h->dprefix + 2 * c;
+        L.blocks[c] = h->nblocks[c];
+    }
     L.nruns = 1;
-    L.bulk_blocks = h->nblocks[0];
-    L.frame_blocks = h->nblocks[1];
-    L.q_blocks = h->nblocks[2];
     return L;
+}
+
+// Fold finished timing-event pairs into the totals and return them to the pool, so the number
+// of live events stays bounded by the steps in flight.
+void harvest_events(lbm_run *h, bool wait) {
+    size_t k = 0;
+    for (; k < h->pending.size(); ++k) {
+        auto &ev = h->pending[k];
+        if (!wait && hipEventQuery(ev.b) != hipSuccess) break;
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, ev.a, ev.b) == hipSuccess) {
+            h->prof_ms[ev.cls] += t;
+            h->prof_n[ev.cls] += 1;
+        }
+        h->pool.push_back(ev.a);
+        h->pool.push_back(ev.b);
+    }
+    (void)hipGetLastError();
+    h->pending.erase(h->pending.begin(), h->pending.begin() + k);
 }
 
 hipEvent_t take_event(lbm_run *h) {
@@ -271,26 +331,60 @@ hipEvent_t take_event(lbm_run *h) {
     return e;
 }
 
-// One step of a launch set: phase A, frame, bulk, flip.
-lbm_status enqueue_step(const LaunchSet &L, int storage, int tx, hipStream_t s, lbm_run *prof) {
+// One step of a launch set.  Dependencies: both phase-A kernels (Q of the frame and of the
+// ring) before both frame kernels (grad Q reads neighbours across the two sets); the bulk
+// kernel depends on none of them; the flip waits for everything.  With side streams the
+// chains run beside the bulk kernel.  With `prof` the classes run in order on one stream and
+// HIP events bracket the bulk kernel (class 0), the frame kernels (class 1) and the phase-A
+// kernels (class 2).
+lbm_status enqueue_step(const LaunchSet &L, int storage, int tx, hipStream_t s, StepStreams *ss,
+                        lbm_run *prof) {
+    const bool has_q = L.blocks[CLS_Q] + L.blocks[CLS_QRING] > 0;
+    const bool has_b = L.blocks[CLS_BULK] > 0;
     hipEvent_t ev[6] = {};
-    if (prof)
+    if (prof) {
+        harvest_events(prof, false);
         for (int k = 0; k < 6; ++k) ev[k] = take_event(prof);
-    if (prof && L.q_blocks > 0) HIP_TRY(hipEventRecord(ev[4], s));
-    HIP_TRY(launch_phase_a(L, storage, s));
-    if (prof && L.q_blocks > 0) HIP_TRY(hipEventRecord(ev[5], s));
-    if (prof) HIP_TRY(hipEventRecord(ev[2], s));
-    HIP_TRY(launch_frame(L, storage, s));
-    if (prof) HIP_TRY(hipEventRecord(ev[3], s));
-    if (prof && L.bulk_blocks > 0) HIP_TRY(hipEventRecord(ev[0], s));
-    HIP_TRY(launch_bulk(L, storage, tx, s));
-    if (prof && L.bulk_blocks > 0) HIP_TRY(hipEventRecord(ev[1], s));
+    }
+    // Timed (profiled) steps run every kernel class in order on one stream, so each class's
+    // events bracket that class alone.
+    if (!ss || !ss->ok || prof) {
+        if (prof && has_q) HIP_TRY(hipEventRecord(ev[4], s));
+        HIP_TRY(launch_phase_a(L, storage, false, s));
+        HIP_TRY(launch_phase_a(L, storage, true, s));
+        if (prof && has_q) HIP_TRY(hipEventRecord(ev[5], s));
+        if (prof) HIP_TRY(hipEventRecord(ev[2], s));
+        HIP_TRY(launch_frame(L, storage, false, s));
+        HIP_TRY(launch_frame(L, storage, true, s));
+        if (prof) HIP_TRY(hipEventRecord(ev[3], s));
+        if (prof && has_b) HIP_TRY(hipEventRecord(ev[0], s));
+        HIP_TRY(launch_bulk(L, storage, tx, s));
+        if (prof && has_b) HIP_TRY(hipEventRecord(ev[1], s));
+    } else {
+        hipStream_t s1 = ss->side[0], s2 = ss->side[1];
+        HIP_TRY(hipEventRecord(ss->fork, s));
+        HIP_TRY(hipStreamWaitEvent(s1, ss->fork, 0));
+        HIP_TRY(hipStreamWaitEvent(s2, ss->fork, 0));
+        HIP_TRY(launch_phase_a(L, storage, false, s1));
+        HIP_TRY(hipEventRecord(ss->a_done[0], s1));
+        HIP_TRY(launch_phase_a(L, storage, true, s2));
+        HIP_TRY(hipEventRecord(ss->a_done[1], s2));
+        HIP_TRY(hipStreamWaitEvent(s1, ss->a_done[1], 0));
+        HIP_TRY(hipStreamWaitEvent(s2, ss->a_done[0], 0));
+        HIP_TRY(launch_frame(L, storage, false, s1));
+        HIP_TRY(hipEventRecord(ss->f_done[0], s1));
+        HIP_TRY(launch_frame(L, storage, true, s2));
+        HIP_TRY(hipEventRecord(ss->f_done[1], s2));
+        HIP_TRY(launch_bulk(L, storage, tx, s));
+        HIP_TRY(hipStreamWaitEvent(s, ss->f_done[0], 0));
+        HIP_TRY(hipStreamWaitEvent(s, ss->f_done[1], 0));
+    }
     HIP_TRY(launch_flip(L, s));
     if (prof) {
-        if (L.bulk_blocks > 0) prof->pending.push_back({ev[0], ev[1], 0});
+        if (has_b) prof->pending.push_back({ev[0], ev[1], 0});
         else { prof->pool.push_back(ev[0]); prof->pool.push_back(ev[1]); }
         prof->pending.push_back({ev[2], ev[3], 1});
-        if (L.q_blocks > 0) prof->pending.push_back({ev[4], ev[5], 2});
+        if (has_q) prof->pending.push_back({ev[4], ev[5], 2});
         else { prof->pool.push_back(ev[4]); prof->pool.push_back(ev[5]); }
     }
     return LBM_OK;
@@ -313,7 +407,7 @@ lbm_status build_graph(lbm_run *h, int G) {
     LaunchSet L = single_set(h);
     lbm_status st = LBM_OK;
     for (int k = 0; k < G && st == LBM_OK; ++k)
-        st = enqueue_step(L, h->desc.storage, h->launch.bulk_tx, h->stream, nullptr);
+        st = enqueue_step(L, h->desc.storage, h->launch.bulk_tx, h->stream, &h->ss, nullptr);
     hipError_t e = hipStreamEndCapture(h->stream, &g);
     if (st != LBM_OK || e != hipSuccess || !g) {
         (void)hipGetLastError();
@@ -477,6 +571,7 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux, co
         HIP_TRY(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
         h->stream = h->own_stream;
     }
+    HIP_TRY(h->ss.create());
     const int storage = h->desc.storage;
     const size_t es = elem_size(storage), cs = compute_size(storage);
     h->footprint = footprint_of(R, storage);
@@ -488,7 +583,7 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux, co
     R.Q = R.has_q ? h->mem.get((size_t)NQ * R.qplane * cs) : nullptr;
     h->dd = (RunDev *)h->mem.get(sizeof(RunDev));
     h->dptr = (RunDev **)h->mem.get(sizeof(RunDev *));
-    h->dprefix = (int *)h->mem.get(6 * sizeof(int));
+    h->dprefix = (int *)h->mem.get(2 * NCLS * sizeof(int));
     h->fbar_d = (double *)h->mem.get(NQ * sizeof(double));
     if ((R.has_q && !R.Q) || !h->dd || !h->dptr || !h->dprefix || !h->fbar_d) {
         h->mem.release_all();
@@ -565,7 +660,8 @@ lbm_status lbm_step(lbm_handle h, int64_t n) {
         }
     }
     for (int64_t k = 0; k < left; ++k) {
-        lbm_status st = enqueue_step(L, h->desc.storage, h->launch.bulk_tx, h->stream, h->prof ? h : nullptr);
+        lbm_status st = enqueue_step(L, h->desc.storage, h->launch.bulk_tx, h->stream, &h->ss,
+                                     h->prof ? h : nullptr);
         if (st != LBM_OK) return st;
     }
     h->steps += n;
@@ -709,15 +805,7 @@ lbm_status lbm_profile(lbm_handle h, int enable) {
 lbm_status lbm_profile_read(lbm_handle h, double ms[3], int64_t launches[3], int reset) {
     if (!h) return fail(LBM_ERR_ARG, "NULL handle");
     if (h->inited) HIP_TRY(hipStreamSynchronize(h->stream));
-    for (auto &ev : h->pending) {
-        float t = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&t, ev.a, ev.b));
-        h->prof_ms[ev.cls] += t;
-        h->prof_n[ev.cls] += 1;
-        h->pool.push_back(ev.a);
-        h->pool.push_back(ev.b);
-    }
-    h->pending.clear();
+    harvest_events(h, true);
     for (int k = 0; k < 3; ++k) {
         if (ms) ms[k] = h->prof_ms[k];
         if (launches) launches[k] = h->prof_n[k];
@@ -734,6 +822,7 @@ void lbm_destroy(lbm_handle h) {
     for (auto &ev : h->pending) { (void)hipEventDestroy(ev.a); (void)hipEventDestroy(ev.b); }
     for (auto e : h->pool) (void)hipEventDestroy(e);
     h->mem.release_all();
+    h->ss.destroy();
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
     delete h;
 }
@@ -902,7 +991,8 @@ lbm_status lbm_group_create(void *stream, const lbm_allocator *allocator, lbm_gr
         }
         g->stream = g->own_stream;
     }
-    if (hipHostMalloc((void **)&g->hlimits, 4096 * sizeof(long long), hipHostMallocDefault) != hipSuccess ||
+    if (g->ss.create() != hipSuccess ||
+        hipHostMalloc((void **)&g->hlimits, 4096 * sizeof(long long), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&g->upload_done, hipEventDisableTiming) != hipSuccess) {
         if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
         delete g;
@@ -960,25 +1050,25 @@ static lbm_status group_rebuild(lbm_group *g) {
         g->mem.put(g->druns); g->mem.put(g->dprefix); g->mem.put(g->dlimits);
         size_t cap = std::max<size_t>(n, 64);
         g->druns = (RunDev **)g->mem.get(cap * sizeof(RunDev *));
-        g->dprefix = (int *)g->mem.get(3 * (cap + 1) * sizeof(int));
+        g->dprefix = (int *)g->mem.get(NCLS * (cap + 1) * sizeof(int));
         g->dlimits = (long long *)g->mem.get(cap * sizeof(long long));
         if (!g->druns || !g->dprefix || !g->dlimits) return fail(LBM_ERR_OOM, "device allocation failed");
         g->cap = cap;
     }
     std::vector<RunDev *> ptrs(n);
-    std::vector<int> pre(3 * (g->cap + 1), 0);
-    int tot[3] = {0, 0, 0};
+    std::vector<int> pre(NCLS * (g->cap + 1), 0);
+    int tot[NCLS] = {0, 0, 0, 0, 0};
     for (size_t k = 0; k < n; ++k) {
         lbm_run *h = g->members[k];
         ptrs[k] = h->dd;
-        int nb[3];
+        int nb[NCLS];
         compute_blocks(h->hd, g->tx, nb);
-        for (int c = 0; c < 3; ++c) { pre[c * (g->cap + 1) + k] = tot[c]; tot[c] += nb[c]; }
+        for (int c = 0; c < NCLS; ++c) { pre[c * (g->cap + 1) + k] = tot[c]; tot[c] += nb[c]; }
     }
-    for (int c = 0; c < 3; ++c) pre[c * (g->cap + 1) + n] = tot[c];
+    for (int c = 0; c < NCLS; ++c) pre[c * (g->cap + 1) + n] = tot[c];
     if (n) HIP_TRY(hipMemcpy(g->druns, ptrs.data(), n * sizeof(RunDev *), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(g->dprefix, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice));
-    for (int c = 0; c < 3; ++c) g->blocks[c] = tot[c];
+    for (int c = 0; c < NCLS; ++c) g->blocks[c] = tot[c];
     g->dirty = false;
     return LBM_OK;
 }
@@ -1006,15 +1096,13 @@ lbm_status lbm_group_step(lbm_group_handle g, const int64_t *steps, int64_t nste
     HIP_TRY(launch_set_limits(g->druns, g->dlimits, (int)n, g->stream));
     LaunchSet L;
     L.runs = g->druns;
-    L.bulk_prefix = g->dprefix;
-    L.frame_prefix = g->dprefix + (g->cap + 1);
-    L.q_prefix = g->dprefix + 2 * (g->cap + 1);
+    for (int c = 0; c < NCLS; ++c) {
+        L.prefix[c] = g->dprefix + c * (g->cap + 1);
+        L.blocks[c] = g->blocks[c];
+    }
     L.nruns = (int)n;
-    L.bulk_blocks = g->blocks[0];
-    L.frame_blocks = g->blocks[1];
-    L.q_blocks = g->blocks[2];
     for (int64_t k = 0; k < K; ++k) {
-        lbm_status st = enqueue_step(L, g->storage, g->tx, g->stream, nullptr);
+        lbm_status st = enqueue_step(L, g->storage, g->tx, g->stream, &g->ss, nullptr);
         if (st != LBM_OK) return st;
     }
     for (size_t k = 0; k < n; ++k) g->members[k]->steps += steps ? steps[k] : nsteps;
@@ -1029,6 +1117,7 @@ void lbm_group_destroy(lbm_group_handle g) {
         h->stream = h->own_stream ? h->own_stream : (hipStream_t)h->desc.stream;
     }
     g->mem.release_all();
+    g->ss.destroy();
     if (g->hlimits) (void)hipHostFree(g->hlimits);
     if (g->upload_done) (void)hipEventDestroy(g->upload_done);
     if (g->own_stream) (void)hipStreamDestroy(g->own_stream);

@@ -19,7 +19,9 @@ enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2 };
 // Frame: the nodes outside the fast interior rectangle [fx0,fx1) x [fy0,fy1), i.e. a frame of
 // depth gxm/gxp/gym/gyp on the four sides.  Frame nodes are numbered bottom strip, top strip,
 // left strip, right strip (row-major inside each strip); Q and the moment strips U use that
-// numbering, so a frame thread touches its own Q/U entries with unit stride.
+// numbering, so a frame thread touches its own Q/U entries with unit stride.  The ring is the
+// same construction with depth 3 on characteristic (NRBC) sides only: the boundary nodes that
+// need the FP64 characteristic fill, handled by their own kernel instances.
 struct alignas(256) RunDev {
     int Nx, Ny, pitch, storage;
     long long plane;          // elements per population plane of f
@@ -29,7 +31,8 @@ struct alignas(256) RunDev {
     int W, qd, open_x, open_y;
     int bc[4];
     int fx0, fx1, fy0, fy1;   // fast rectangle
-    int frame_n, has_q, pad1, pad2;
+    int frame_n, has_q, ring_n, pad1;
+    int rxm, rxp, rym, ryp;   // characteristic-boundary ring depths (3 on NRBC sides, else 0)
     int tiles_x[3], tiles_y[3];   // bulk tiles for tile widths 64, 128, 256
     // state
     void *f[2];
@@ -45,21 +48,21 @@ struct alignas(256) RunDev {
 };
 
 // Launch decomposition of a set of runs: prefix[k] = first block of run k, prefix[n] = total.
+enum Cls { CLS_BULK = 0, CLS_FRAME = 1, CLS_RING = 2, CLS_Q = 3, CLS_QRING = 4, NCLS = 5 };
 struct LaunchSet {
     RunDev *const *runs;      // device array of descriptor pointers
-    const int *bulk_prefix;   // device
-    const int *frame_prefix;  // device
-    const int *q_prefix;      // device
+    const int *prefix[NCLS];  // device prefix arrays per class
+    int blocks[NCLS];         // total blocks per class
     int nruns;
-    int bulk_blocks, frame_blocks, q_blocks;
 };
 
 constexpr int FRAME_BLOCK = 256;
 
 // Kernel launchers (lbm_kernels.hip).  All enqueue on `s` and return the HIP status of the
 // launch.
-hipError_t launch_phase_a(const LaunchSet &L, int storage, hipStream_t s);
-hipError_t launch_frame(const LaunchSet &L, int storage, hipStream_t s);
+// ring = false: frame nodes off the characteristic ring; ring = true: the ring only.
+hipError_t launch_phase_a(const LaunchSet &L, int storage, bool ring, hipStream_t s);
+hipError_t launch_frame(const LaunchSet &L, int storage, bool ring, hipStream_t s);
 hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, hipStream_t s);
 hipError_t launch_flip(const LaunchSet &L, hipStream_t s);
 hipError_t launch_set_limit(RunDev *run, long long limit, hipStream_t s);
@@ -78,7 +81,5 @@ hipError_t launch_err_rows(const double *rho, const double *ux, const double *T,
                            const double *rt, double *partials, hipStream_t s);
 hipError_t launch_err_final(const double *partials, int nrows, double *out, hipStream_t s);
 
-// Host helpers shared with the runtime.
-void frame_xy_host(const RunDev &R, int t, int *x, int *y);
 
 }  // namespace lbm

@@ -2,15 +2,19 @@
 //
 // Every kernel takes an array of run descriptors, so one launch advances one run or a batch of
 // uneven runs.  Per step:
-//   k_phase_a  (PML runs) Q-region nodes: pull + boundary + moments -> U^{n+1};
-//              Q^{n+1} = Q^n + (fhat^n + fhat^{n+1})/2                         (eq. PMLQ)
-//   k_frame    frame nodes (boundary layers, PML, moment strips): pull + boundary fill +
-//              moments, U^{n+1} strip write, BGK + Omega^PML                 (eqs. PMLCOLL,
-//              zg-bc, PNR / LODI)
-//   k_bulk     interior nodes: branch-free pull + moments + BGK                 (eq. lbe)
-//   k_flip     swap the population and moment-strip buffers of active runs
-// The collision is a per-node projection streaming 2 x 37 values through HBM: no MFMA; the pull
-// reads are coalesced row segments shifted by e_i (each source value read exactly once).
+//   k_phase_a<NR>  PML Q-region nodes: pull + boundary + moments -> U^{n+1};
+//                  Q^{n+1} = Q^n + (fhat^n + fhat^{n+1})/2                      (eq. PMLQ)
+//   k_frame<NR>    frame nodes (boundary layers, PML, moment strips): pull + boundary fill +
+//                  moments, U^{n+1} strip write, BGK + Omega^PML      (eqs. PMLCOLL, zg-bc,
+//                  PNR / thermal_LODI_macro_evo)
+//   k_bulk         interior nodes: branch-free pull + moments + BGK             (eq. lbe)
+//   k_flip         swap the population and moment-strip buffers of active runs
+// NR = true instances cover only the 3-deep ring of characteristic-boundary nodes (FP64 LODI
+// fill); NR = false instances skip those nodes and carry none of that code, which keeps their
+// register budget low.  The collision is a per-node projection streaming 2 x 37 values
+// through HBM: no MFMA.  Pulls are coalesced row segments shifted by e_i (each source value is
+// read exactly once); descriptors are read through the constant address space (scalar
+// loads) and populations through global pointers with one 32-bit byte offset per lane.
 //
 // Arithmetic is in deviation form: the stored populations are d_i = f_i - fbar_i with
 // fbar = feq(rho0, u0, T0), and the equilibrium deviation feq(U) - fbar is evaluated from
@@ -29,7 +33,12 @@
 
 #include "lbm_internal.h"
 
+#define GLOBAL __attribute__((address_space(1)))
+#define CONSTANT __attribute__((address_space(4)))
+
 namespace lbm {
+
+using CRun = const CONSTANT RunDev;
 
 // ------------------------------------------------------------------------------------------
 // helpers
@@ -47,19 +56,29 @@ template <> struct Traits<double> { using C = double; };
 template <> struct Traits<float> { using C = float; };
 template <> struct Traits<_Float16> { using C = float; };
 
-__device__ __forceinline__ double ld_s(const double *p, double) { return *p; }
-__device__ __forceinline__ float ld_s(const float *p, float) { return *p; }
-__device__ __forceinline__ float ld_s(const _Float16 *p, float inv) { return (float)(*p) * inv; }
-__device__ __forceinline__ void st_s(double *p, double v, double) { *p = v; }
-__device__ __forceinline__ void st_s(float *p, float v, float) { *p = v; }
-__device__ __forceinline__ void st_s(_Float16 *p, float v, float sc) { *p = (_Float16)(v * sc); }
+// element at byte offset `off` from a uniform base
+template <class T>
+__device__ __forceinline__ const GLOBAL T *at(const GLOBAL T *base, unsigned off) {
+    return (const GLOBAL T *)((const GLOBAL char *)base + off);
+}
+template <class T>
+__device__ __forceinline__ GLOBAL T *at(GLOBAL T *base, unsigned off) {
+    return (GLOBAL T *)((GLOBAL char *)base + off);
+}
+
+__device__ __forceinline__ double cvt_in(double v, double) { return v; }
+__device__ __forceinline__ float cvt_in(float v, float) { return v; }
+__device__ __forceinline__ float cvt_in(_Float16 v, float inv) { return (float)v * inv; }
+__device__ __forceinline__ double cvt_out(double v, double, double *) { return v; }
+__device__ __forceinline__ float cvt_out(float v, float, float *) { return v; }
+__device__ __forceinline__ _Float16 cvt_out(float v, float sc, _Float16 *) { return (_Float16)(v * sc); }
 
 // Run constants in the compute type.
 template <class C> struct K {
     C omega, rho0, u0x, u0y, th0, b0, r0x, r0y, c2Tb0, scale, inv_scale;
 };
 
-template <class C> __device__ __forceinline__ K<C> load_k(const RunDev &R) {
+template <class C> __device__ __forceinline__ K<C> load_k(CRun &R) {
     K<C> k;
     if constexpr (std::is_same<C, double>::value) {
         k.omega = R.omega; k.rho0 = R.rho0; k.u0x = R.u0x; k.u0y = R.u0y; k.th0 = R.th0;
@@ -73,19 +92,19 @@ template <class C> __device__ __forceinline__ K<C> load_k(const RunDev &R) {
     return k;
 }
 
-template <class C> __device__ __forceinline__ C cH0e(const RunDev &R, int p) {
+template <class C> __device__ __forceinline__ C cH0e(CRun &R, int p) {
     if constexpr (std::is_same<C, double>::value) return R.H0e[p]; else return R.H0e_f[p];
 }
-template <class C> __device__ __forceinline__ C cH0o(const RunDev &R, int p) {
+template <class C> __device__ __forceinline__ C cH0o(CRun &R, int p) {
     if constexpr (std::is_same<C, double>::value) return R.H0o[p]; else return R.H0o_f[p];
 }
-template <class C> __device__ __forceinline__ C cE2_0(const RunDev &R, int s) {
+template <class C> __device__ __forceinline__ C cE2_0(CRun &R, int s) {
     if constexpr (std::is_same<C, double>::value) return R.E2_0[s]; else return R.E2_0_f[s];
 }
-template <class C> __device__ __forceinline__ C cO1_0(const RunDev &R, int s) {
+template <class C> __device__ __forceinline__ C cO1_0(CRun &R, int s) {
     if constexpr (std::is_same<C, double>::value) return R.O1_0[s]; else return R.O1_0_f[s];
 }
-template <class C> __device__ __forceinline__ C cH0rest(const RunDev &R) {
+template <class C> __device__ __forceinline__ C cH0rest(CRun &R) {
     if constexpr (std::is_same<C, double>::value) return R.H0rest; else return R.H0rest_f;
 }
 
@@ -97,25 +116,38 @@ __device__ __forceinline__ int xcd_swizzle(int b, int n) {
 }
 
 __device__ __forceinline__ int find_run(const int *prefix, int nruns, int b) {
+    const CONSTANT int *p = (const CONSTANT int *)prefix;
     int lo = 0, hi = nruns;
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
-        if (prefix[mid] <= b) lo = mid; else hi = mid;
+        if (p[mid] <= b) lo = mid; else hi = mid;
     }
     return lo;
 }
 
-__host__ __device__ __forceinline__ void frame_xy(const RunDev &R, int t, int &x, int &y) {
-    int Fb = R.gym * R.Nx, Ft = R.gyp * R.Nx, H = R.Ny - R.gym - R.gyp, Fl = H * R.gxm;
-    if (t < Fb) { y = t / R.Nx; x = t - y * R.Nx; }
-    else if (t < Fb + Ft) { t -= Fb; int r = t / R.Nx; y = R.Ny - R.gyp + r; x = t - r * R.Nx; }
-    else if (t < Fb + Ft + Fl) { t -= Fb + Ft; int r = t / R.gxm; y = R.gym + r; x = t - r * R.gxm; }
-    else { t -= Fb + Ft + Fl; int r = t / R.gxp; y = R.gym + r; x = R.Nx - R.gxp + (t - r * R.gxp); }
+__device__ __forceinline__ CRun &run_of(RunDev *const *runs, int j) {
+    return *(CRun *)(((RunDev *const CONSTANT *)runs)[j]);
 }
 
-void frame_xy_host(const RunDev &R, int t, int *x, int *y) { frame_xy(R, t, *x, *y); }
+// Strip numbering of a frame of depths (dxm, dxp, dym, dyp): bottom strip, top strip, left
+// strip, right strip.
+__device__ __forceinline__ void strip_xy(int Nx, int Ny, int dxm, int dxp, int dym, int dyp, int t,
+                                         int &x, int &y) {
+    int Fb = dym * Nx, Ft = dyp * Nx, H = Ny - dym - dyp, Fl = H * dxm;
+    if (t < Fb) { y = t / Nx; x = t - y * Nx; }
+    else if (t < Fb + Ft) { t -= Fb; int r = t / Nx; y = Ny - dyp + r; x = t - r * Nx; }
+    else if (t < Fb + Ft + Fl) { t -= Fb + Ft; int r = t / dxm; y = dym + r; x = t - r * dxm; }
+    else { t -= Fb + Ft + Fl; int r = t / dxp; y = dym + r; x = Nx - dxp + (t - r * dxp); }
+}
 
-__device__ __forceinline__ int fidx(const RunDev &R, int x, int y) {
+__device__ __forceinline__ void frame_xy(CRun &R, int t, int &x, int &y) {
+    strip_xy(R.Nx, R.Ny, R.gxm, R.gxp, R.gym, R.gyp, t, x, y);
+}
+__device__ __forceinline__ void ring_xy(CRun &R, int t, int &x, int &y) {
+    strip_xy(R.Nx, R.Ny, R.rxm, R.rxp, R.rym, R.ryp, t, x, y);
+}
+
+__device__ __forceinline__ int fidx(CRun &R, int x, int y) {
     if (y < R.gym) return y * R.Nx + x;
     if (y >= R.Ny - R.gyp) return (R.gym + y - (R.Ny - R.gyp)) * R.Nx + x;
     int H = R.Ny - R.gym - R.gyp, base = (R.gym + R.gyp) * R.Nx, yy = y - R.gym;
@@ -124,13 +156,19 @@ __device__ __forceinline__ int fidx(const RunDev &R, int x, int y) {
     return -1;
 }
 
-__device__ __forceinline__ bool in_q(const RunDev &R, int x, int y) {
+__device__ __forceinline__ bool in_q(CRun &R, int x, int y) {
     return (R.Wxm > 0 && x < R.qd) || (R.Wxp > 0 && x >= R.Nx - R.qd) ||
            (R.Wym > 0 && y < R.qd) || (R.Wyp > 0 && y >= R.Ny - R.qd);
 }
 
+// Characteristic-boundary node: within the outer 3 layers of an NRBC side.
+__device__ __forceinline__ bool in_ring(CRun &R, int x, int y) {
+    return (R.rxm > 0 && x < 3) || (R.rxp > 0 && x >= R.Nx - 3) ||
+           (R.rym > 0 && y < 3) || (R.ryp > 0 && y >= R.Ny - 3);
+}
+
 // eq. PML_ramp on the Chebyshev ring level.
-__device__ __forceinline__ double sigma_at(const RunDev &R, int x, int y) {
+__device__ __forceinline__ double sigma_at(CRun &R, int x, int y) {
     int lx = x < R.Wxm ? R.Wxm - x : (x >= R.Nx - R.Wxp ? x - (R.Nx - R.Wxp) + 1 : 0);
     int ly = y < R.Wym ? R.Wym - y : (y >= R.Ny - R.Wyp ? y - (R.Ny - R.Wyp) + 1 : 0);
     int l = lx > ly ? lx : ly;
@@ -177,6 +215,7 @@ __device__ __forceinline__ Mom<C> moments(const C (&g)[NQ], const K<C> &k) {
 // ------------------------------------------------------------------------------------------
 template <class C> struct Eq {
     C drho, rho, Rdux, Rduy, dT, dk0, dk1, dk2a, dk2s, dth2;
+    C dE0, dE2, dO1;   // current shell
 };
 
 template <class C>
@@ -198,42 +237,75 @@ __device__ __forceinline__ Eq<C> eq_coef(C drho, C dux, C duy, C dT, const K<C> 
     q.dk2a = -C(0.25) * db - C(1.5) * dT;
     q.dk2s = C(0.5) * dT - C(0.25) * dthb - dth2;
     q.dth2 = dth2;
+    q.dE0 = q.dE2 = q.dO1 = C(0);
     return q;
+}
+
+template <class C>
+__device__ __forceinline__ C feq_rest(const Eq<C> &q, CRun &R) {
+    return C(SHELL_W[0]) * (q.drho * cH0rest<C>(R) + q.rho * q.dk0);
+}
+
+// Shell coefficient deviations (computed once per shell).
+template <class C, int sh>
+__device__ __forceinline__ void eq_shell(Eq<C> &q) {
+    constexpr double sv = LAT_R2 * SHELL_E2[sh];
+    q.dE0 = q.dk0 + q.dk2s * C(sv) + q.dth2 * C(0.125 * sv * sv);
+    q.dE2 = q.dk2a + q.dT * C(0.25 * sv);
+    q.dO1 = q.dk1 + q.dT * C(0.5 * sv);
+}
+
+// feq - fbar of the pair p: (+e_p, -e_p).
+template <class C, int p>
+__device__ __forceinline__ void eq_pair(const Eq<C> &q, CRun &R, const K<C> &k, C &fp, C &fm) {
+    constexpr int sh = PSH[p];
+    constexpr int ex = PEX[p], ey = PEY[p];
+    C a0, da;
+    if constexpr (ey == 0) { a0 = C(ex) * k.r0x; da = C(ex) * q.Rdux; }
+    else if constexpr (ex == 0) { a0 = C(ey) * k.r0y; da = C(ey) * q.Rduy; }
+    else { a0 = C(ex) * k.r0x + C(ey) * k.r0y; da = C(ex) * q.Rdux + C(ey) * q.Rduy; }
+    const C E2_0 = cE2_0<C>(R, sh), O1_0 = cO1_0<C>(R, sh);
+    C a = a0 + da;
+    C A2 = a * a, A02 = a0 * a0;
+    C dA2 = da * (a + a0);
+    C dEv = q.dE0 + q.dE2 * A2 + E2_0 * dA2 + dA2 * (A2 + A02) * C(1.0 / 24.0);
+    C dOd = q.dO1 * a + O1_0 * da + da * (A2 + a * a0 + A02) * C(1.0 / 6.0);
+    C Tev = q.drho * cH0e<C>(R, p) + q.rho * dEv;
+    C Tod = q.drho * cH0o<C>(R, p) + q.rho * dOd;
+    constexpr double w = SHELL_W[sh];
+    fp = C(w) * (Tev + Tod);
+    fm = C(w) * (Tev - Tod);
 }
 
 // Calls emit(i, feq_i - fbar_i) for i = 0..36 with compile-time i.
 template <class C, class F>
-__device__ __forceinline__ void for_each_feq(const Eq<C> &q, const RunDev &R, const K<C> &k,
-                                             F &&emit) {
-    emit(std::integral_constant<int, 0>{},
-         C(SHELL_W[0]) * (q.drho * cH0rest<C>(R) + q.rho * q.dk0));
-    C dE0 = C(0), dE2 = C(0), dO1 = C(0), E2_0 = C(0), O1_0 = C(0);
+__device__ __forceinline__ void for_each_feq(Eq<C> q, CRun &R, const K<C> &k, F &&emit) {
+    emit(std::integral_constant<int, 0>{}, feq_rest<C>(q, R));
     static_for<0, NPAIR>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
-        constexpr int sh = PSH[p];
-        if constexpr (p == 0 || PSH[p - 1] != sh) {
-            constexpr double sv = LAT_R2 * SHELL_E2[sh];
-            dE0 = q.dk0 + q.dk2s * C(sv) + q.dth2 * C(0.125 * sv * sv);
-            dE2 = q.dk2a + q.dT * C(0.25 * sv);
-            dO1 = q.dk1 + q.dT * C(0.5 * sv);
-            E2_0 = cE2_0<C>(R, sh);
-            O1_0 = cO1_0<C>(R, sh);
+        if constexpr (p == 0 || PSH[p - 1] != PSH[p]) eq_shell<C, PSH[p]>(q);
+        C fp, fm;
+        eq_pair<C, p>(q, R, k, fp, fm);
+        emit(std::integral_constant<int, 1 + 2 * p>{}, fp);
+        emit(std::integral_constant<int, 2 + 2 * p>{}, fm);
+    });
+}
+
+// Two equilibria in one pass: emit(i, feq_a_i - fbar_i, feq_b_i - fbar_i).
+template <class C, class F>
+__device__ __forceinline__ void for_each_feq2(Eq<C> qa, Eq<C> qb, CRun &R, const K<C> &k, F &&emit) {
+    emit(std::integral_constant<int, 0>{}, feq_rest<C>(qa, R), feq_rest<C>(qb, R));
+    static_for<0, NPAIR>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        if constexpr (p == 0 || PSH[p - 1] != PSH[p]) {
+            eq_shell<C, PSH[p]>(qa);
+            eq_shell<C, PSH[p]>(qb);
         }
-        constexpr int ex = PEX[p], ey = PEY[p];
-        C a0, da;
-        if constexpr (ey == 0) { a0 = C(ex) * k.r0x; da = C(ex) * q.Rdux; }
-        else if constexpr (ex == 0) { a0 = C(ey) * k.r0y; da = C(ey) * q.Rduy; }
-        else { a0 = C(ex) * k.r0x + C(ey) * k.r0y; da = C(ex) * q.Rdux + C(ey) * q.Rduy; }
-        C a = a0 + da;
-        C A2 = a * a, A02 = a0 * a0;
-        C dA2 = da * (a + a0);
-        C dEv = dE0 + dE2 * A2 + E2_0 * dA2 + dA2 * (A2 + A02) * C(1.0 / 24.0);
-        C dOd = dO1 * a + O1_0 * da + da * (A2 + a * a0 + A02) * C(1.0 / 6.0);
-        C Tev = q.drho * cH0e<C>(R, p) + q.rho * dEv;
-        C Tod = q.drho * cH0o<C>(R, p) + q.rho * dOd;
-        constexpr double w = SHELL_W[sh];
-        emit(std::integral_constant<int, 1 + 2 * p>{}, C(w) * (Tev + Tod));
-        emit(std::integral_constant<int, 2 + 2 * p>{}, C(w) * (Tev - Tod));
+        C ap, am, bp, bm;
+        eq_pair<C, p>(qa, R, k, ap, am);
+        eq_pair<C, p>(qb, R, k, bp, bm);
+        emit(std::integral_constant<int, 1 + 2 * p>{}, ap, bp);
+        emit(std::integral_constant<int, 2 + 2 * p>{}, am, bm);
     });
 }
 
@@ -246,9 +318,9 @@ __device__ __forceinline__ void for_each_feq(const Eq<C> &q, const RunDev &R, co
 // amplitude takes the upwind difference over the interval its characteristic crosses in one
 // step (nu = lambda/r cells, foot point limited to two cells).  Adds the one-step increment
 // dV = -S^{-1} Lbar (eq. thermal_LODI_macro_evo) to Ut in the global frame.
-__device__ void lodi_add(const RunDev &R, const double *Uc, int side, int x, int y, int t,
+__device__ void lodi_add(CRun &R, const GLOBAL double *Uc, int side, int x, int y, int t,
                          double Ut[4]) {
-    const long long qp = R.qplane;
+    const unsigned qp = (unsigned)R.qplane;
     int nx = side == XMIN ? -1 : (side == XMAX ? 1 : 0);
     int ny = side == YMIN ? -1 : (side == YMAX ? 1 : 0);
     double V[3][4];
@@ -278,7 +350,8 @@ __device__ void lodi_add(const RunDev &R, const double *Uc, int side, int x, int
             double nu = fmin(lam[k] * (1.0 / LAT_R), 2.0);
             int j0 = nu >= 1.0 ? 1 : 0;
             double phi = nu - j0;
-            double wfoot = (1.0 - phi) * w[j0] + phi * w[j0 + 1];
+            double wa = j0 ? w[1] : w[0], wb = j0 ? w[2] : w[1];
+            double wfoot = (1.0 - phi) * wa + phi * wb;
             D[k] = w[0] - wfoot;
         } else {
             D[k] = 0.0;
@@ -299,8 +372,8 @@ __device__ void lodi_add(const RunDev &R, const double *Uc, int side, int x, int
 // Non-equilibrium extrapolation: g <- feq(U_tgt) + g(x_f) - feq(U(x_f)).  g holds the pulled
 // populations of x_f (deviation form) on entry.
 template <class C>
-__device__ void nrbc_fill(const RunDev &R, const double *Uc, int x, int y, int t, C (&g)[NQ]) {
-    const long long qp = R.qplane;
+__device__ void nrbc_fill(CRun &R, const GLOBAL double *Uc, int x, int y, int t, C (&g)[NQ]) {
+    const unsigned qp = (unsigned)R.qplane;
     double Ut[4] = {Uc[t], Uc[qp + t], Uc[2 * qp + t], Uc[3 * qp + t]};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -308,23 +381,27 @@ __device__ void nrbc_fill(const RunDev &R, const double *Uc, int x, int y, int t
         if (on && R.bc[s] == BC_NRBC) lodi_add(R, Uc, s, x, y, t, Ut);
     }
     K<double> kd = load_k<double>(R);
-    double gd[NQ];
+    Mom<double> mf;
+    if constexpr (std::is_same<C, double>::value) {
+        mf = moments<double>(g, kd);
+    } else {
+        double gd[NQ];
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) gd[i] = (double)g[i];
-    Mom<double> mf = moments<double>(gd, kd);
+        for (int i = 0; i < NQ; ++i) gd[i] = (double)g[i];
+        mf = moments<double>(gd, kd);
+    }
     Eq<double> ef = eq_coef<double>(mf.drho, mf.dux, mf.duy, mf.dT, kd);
     Eq<double> et = eq_coef<double>(Ut[0] - R.rho0, Ut[1] - R.u0x, Ut[2] - R.u0y, Ut[3] - R.T0, kd);
-    for_each_feq<double>(ef, R, kd, [&](auto ic, double fe) { gd[decltype(ic)::value] -= fe; });
-    for_each_feq<double>(et, R, kd, [&](auto ic, double fe) {
+    for_each_feq2<double>(et, ef, R, kd, [&](auto ic, double ft, double ff) {
         constexpr int i = decltype(ic)::value;
-        g[i] = (C)(gd[i] + fe);
+        g[i] = (C)((double)g[i] + (ft - ff));
     });
 }
 
 // Pull of a frame node with the boundary fill: periodic axes wrap, open axes pull at
 // x_f = clamp(x, 3, N-4) (eq. zg-bc copies all q populations of x_f to the boundary node).
-template <class S, class C>
-__device__ __forceinline__ void gather_general(const RunDev &R, const S *src, const double *Uc,
+template <class S, class C, bool NR>
+__device__ __forceinline__ void gather_general(CRun &R, const GLOBAL S *src, const GLOBAL double *Uc,
                                                int x, int y, int t, C inv_scale, C (&g)[NQ]) {
     int xs = R.open_x ? min(max(x, 3), R.Nx - 4) : x;
     int ys = R.open_y ? min(max(y, 3), R.Ny - 4) : y;
@@ -336,11 +413,10 @@ __device__ __forceinline__ void gather_general(const RunDev &R, const S *src, co
         int sx = xs - ex_of(i), sy = ys - ey_of(i);
         if (!ox) { while (sx < 0) sx += Nx; while (sx >= Nx) sx -= Nx; }
         if (!oy) { while (sy < 0) sy += Ny; while (sy >= Ny) sy -= Ny; }
-        g[i] = ld_s(src + (long long)i * plane + (long long)sy * pitch + sx, inv_scale);
+        const GLOBAL S *base = src + (long long)i * plane;
+        g[i] = cvt_in(*at(base, (unsigned)(sy * pitch + sx) * (unsigned)sizeof(S)), inv_scale);
     });
-    bool nr = (R.bc[XMIN] == BC_NRBC && x < 3) || (R.bc[XMAX] == BC_NRBC && x >= Nx - 3) ||
-              (R.bc[YMIN] == BC_NRBC && y < 3) || (R.bc[YMAX] == BC_NRBC && y >= Ny - 3);
-    if (nr) nrbc_fill<C>(R, Uc, x, y, t, g);
+    if constexpr (NR) nrbc_fill<C>(R, Uc, x, y, t, g);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -351,68 +427,78 @@ __global__ __launch_bounds__(256) void k_bulk(RunDev *const *__restrict__ runs,
                                               const int *__restrict__ prefix, int nruns) {
     using C = typename Traits<S>::C;
     constexpr int TY = 256 / TX;
+    constexpr int TI = TX == 64 ? 0 : (TX == 128 ? 1 : 2);
     const int b = xcd_swizzle(blockIdx.x, gridDim.x);
     const int j = find_run(prefix, nruns, b);
-    const RunDev &R = *runs[j];
+    CRun &R = run_of(runs, j);
     if (R.step >= R.limit) return;
-    constexpr int TI = TX == 64 ? 0 : (TX == 128 ? 1 : 2);
-    const int tb = b - prefix[j];
+    const int tb = b - ((const CONSTANT int *)prefix)[j];
     const int ty = tb / R.tiles_x[TI], tx = tb - ty * R.tiles_x[TI];
     const int x = (R.fx0 / TX) * TX + tx * TX + (int)(threadIdx.x % TX);
     const int y = R.fy0 + ty * TY + (int)(threadIdx.x / TX);
     if (x < R.fx0 || x >= R.fx1 || y >= R.fy1) return;
     const K<C> k = load_k<C>(R);
-    const S *src = (const S *)R.f[R.par];
-    S *dst = (S *)R.f[R.par ^ 1];
+    const GLOBAL S *src = (const GLOBAL S *)R.f[R.par];
+    GLOBAL S *dst = (GLOBAL S *)R.f[R.par ^ 1];
     const long long plane = R.plane;
     const int pitch = R.pitch;
-    const int idx = y * pitch + x;
+    const unsigned off = (unsigned)(y * pitch + x) * (unsigned)sizeof(S);
     C g[NQ];
     static_for<0, NQ>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        const S *base = src + (long long)i * plane - (ey_of(i) * pitch + ex_of(i));
-        g[i] = ld_s(base + idx, k.inv_scale);
+        const GLOBAL S *base = src + ((long long)i * plane - (ey_of(i) * pitch + ex_of(i)));
+        g[i] = cvt_in(*at(base, off), k.inv_scale);
     });
     Mom<C> m = moments<C>(g, k);
     Eq<C> q = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
     for_each_feq<C>(q, R, k, [&](auto ic, C fe) {
         constexpr int i = decltype(ic)::value;
         C out = g[i] + k.omega * (fe - g[i]);
-        st_s(dst + (long long)i * plane + idx, out, k.scale);
+        *at(dst + (long long)i * plane, off) = cvt_out(out, k.scale, (S *)nullptr);
     });
 }
 
-template <class S>
+template <class S, bool NR>
 __global__ __launch_bounds__(256) void k_frame(RunDev *const *__restrict__ runs,
                                                const int *__restrict__ prefix, int nruns) {
     using C = typename Traits<S>::C;
     const int b = blockIdx.x;
     const int j = find_run(prefix, nruns, b);
-    const RunDev &R = *runs[j];
+    CRun &R = run_of(runs, j);
     if (R.step >= R.limit) return;
-    const int t = (b - prefix[j]) * FRAME_BLOCK + (int)threadIdx.x;
-    if (t >= R.frame_n) return;
-    int x, y;
-    frame_xy(R, t, x, y);
+    const int tt = (b - ((const CONSTANT int *)prefix)[j]) * FRAME_BLOCK + (int)threadIdx.x;
+    int x, y, t;
+    if constexpr (NR) {
+        if (tt >= R.ring_n) return;
+        ring_xy(R, tt, x, y);
+        t = fidx(R, x, y);
+        if (t < 0) return;
+    } else {
+        if (tt >= R.frame_n) return;
+        frame_xy(R, tt, x, y);
+        if (in_ring(R, x, y)) return;
+        t = tt;
+    }
     const K<C> k = load_k<C>(R);
-    const S *src = (const S *)R.f[R.par];
-    S *dst = (S *)R.f[R.par ^ 1];
-    const double *Uc = R.U[R.par];
-    double *Un = R.U[R.par ^ 1];
-    const long long plane = R.plane, qp = R.qplane;
+    const GLOBAL S *src = (const GLOBAL S *)R.f[R.par];
+    GLOBAL S *dst = (GLOBAL S *)R.f[R.par ^ 1];
+    const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par];
+    GLOBAL double *Un = (GLOBAL double *)R.U[R.par ^ 1];
+    const long long plane = R.plane;
+    const unsigned qp = (unsigned)R.qplane;
     C g[NQ];
-    gather_general<S, C>(R, src, Uc, x, y, t, k.inv_scale, g);
+    gather_general<S, C, NR>(R, src, Uc, x, y, t, k.inv_scale, g);
     Mom<C> m = moments<C>(g, k);
     Un[t] = R.rho0 + (double)m.drho;
     Un[qp + t] = R.u0x + (double)m.dux;
     Un[2 * qp + t] = R.u0y + (double)m.duy;
     Un[3 * qp + t] = R.T0 + (double)m.dT;
     Eq<C> q = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
-    const long long idx = (long long)y * R.pitch + x;
+    const unsigned off = (unsigned)(y * R.pitch + x) * (unsigned)sizeof(S);
     const double sg = R.W > 0 ? sigma_at(R, x, y) : 0.0;
     if (sg > 0.0) {
         // grad Q: central, one-sided at the outermost layer of an open axis (eqs. FD-dx-*)
-        const C *Q = (const C *)R.Q;
+        const GLOBAL C *Q = (const GLOBAL C *)R.Q;
         int jx[3], jy[3];
         C cx[3], cy[3];
         if (R.open_x && x == 0) {
@@ -449,7 +535,7 @@ __global__ __launch_bounds__(256) void k_frame(RunDev *const *__restrict__ runs,
         const C s = (C)sg;
         for_each_feq<C>(q, R, k, [&](auto ic, C fe) {
             constexpr int i = decltype(ic)::value;
-            const C *Qi = Q + (long long)i * qp;
+            const GLOBAL C *Qi = Q + (long long)i * qp;
             C out = g[i] + k.omega * (fe - g[i]);
             C gq = C(0);
             if constexpr (ex_of(i) != 0)
@@ -457,46 +543,54 @@ __global__ __launch_bounds__(256) void k_frame(RunDev *const *__restrict__ runs,
             if constexpr (ey_of(i) != 0)
                 gq += C(ey_of(i)) * (cy[0] * Qi[jy[0]] + cy[1] * Qi[jy[1]] + cy[2] * Qi[jy[2]]);
             out = out - s * (gq + C(2) * fe + s * Qi[t]);
-            st_s(dst + (long long)i * plane + idx, out, k.scale);
+            *at(dst + (long long)i * plane, off) = cvt_out(out, k.scale, (S *)nullptr);
         });
     } else {
         for_each_feq<C>(q, R, k, [&](auto ic, C fe) {
             constexpr int i = decltype(ic)::value;
             C out = g[i] + k.omega * (fe - g[i]);
-            st_s(dst + (long long)i * plane + idx, out, k.scale);
+            *at(dst + (long long)i * plane, off) = cvt_out(out, k.scale, (S *)nullptr);
         });
     }
 }
 
-template <class S>
+template <class S, bool NR>
 __global__ __launch_bounds__(256) void k_phase_a(RunDev *const *__restrict__ runs,
                                                  const int *__restrict__ prefix, int nruns) {
     using C = typename Traits<S>::C;
     const int b = blockIdx.x;
     const int j = find_run(prefix, nruns, b);
-    const RunDev &R = *runs[j];
+    CRun &R = run_of(runs, j);
     if (R.step >= R.limit || !R.has_q) return;
-    const int t = (b - prefix[j]) * FRAME_BLOCK + (int)threadIdx.x;
-    if (t >= R.frame_n) return;
-    int x, y;
-    frame_xy(R, t, x, y);
+    const int tt = (b - ((const CONSTANT int *)prefix)[j]) * FRAME_BLOCK + (int)threadIdx.x;
+    int x, y, t;
+    if constexpr (NR) {
+        if (tt >= R.ring_n) return;
+        ring_xy(R, tt, x, y);
+        t = fidx(R, x, y);
+        if (t < 0) return;
+    } else {
+        if (tt >= R.frame_n) return;
+        frame_xy(R, tt, x, y);
+        if (in_ring(R, x, y)) return;
+        t = tt;
+    }
     if (!in_q(R, x, y)) return;
     const K<C> k = load_k<C>(R);
-    const S *src = (const S *)R.f[R.par];
-    const double *Uc = R.U[R.par];
-    const long long qp = R.qplane;
+    const GLOBAL S *src = (const GLOBAL S *)R.f[R.par];
+    const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par];
+    const unsigned qp = (unsigned)R.qplane;
     C g[NQ];
-    gather_general<S, C>(R, src, Uc, x, y, t, k.inv_scale, g);
+    gather_general<S, C, NR>(R, src, Uc, x, y, t, k.inv_scale, g);
     Mom<C> m = moments<C>(g, k);
     Eq<C> q1 = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
     Eq<C> q0 = eq_coef<C>((C)(Uc[t] - R.rho0), (C)(Uc[qp + t] - R.u0x), (C)(Uc[2 * qp + t] - R.u0y),
                           (C)(Uc[3 * qp + t] - R.T0), k);
-    C *Q = (C *)R.Q;
-    for_each_feq<C>(q1, R, k, [&](auto ic, C fe) { g[decltype(ic)::value] = fe; });
-    for_each_feq<C>(q0, R, k, [&](auto ic, C fe) {
+    GLOBAL C *Q = (GLOBAL C *)R.Q;
+    for_each_feq2<C>(q1, q0, R, k, [&](auto ic, C fe1, C fe0) {
         constexpr int i = decltype(ic)::value;
-        C *Qi = Q + (long long)i * qp + t;
-        *Qi = *Qi + C(0.5) * (fe + g[i]);
+        GLOBAL C *Qi = Q + (long long)i * qp + t;
+        *Qi = *Qi + C(0.5) * (fe0 + fe1);
     });
 }
 
@@ -523,34 +617,36 @@ __global__ void k_set_limits(RunDev *const *runs, const long long *limits, int n
 // init, export, checks, reductions
 // ------------------------------------------------------------------------------------------
 template <class S>
-__global__ __launch_bounds__(256) void k_init(RunDev *R, const double *rho, const double *ux,
+__global__ __launch_bounds__(256) void k_init(RunDev *Rw, const double *rho, const double *ux,
                                               const double *uy, const double *T, float *absmax) {
     using C = typename Traits<S>::C;
+    CRun &R = *(CRun *)Rw;
     __shared__ float red[256];
     const int n = blockIdx.x * 256 + threadIdx.x;
-    const int nn = R->Nx * R->Ny;
+    const int nn = R.Nx * R.Ny;
     float mx = 0.0f;
     if (n < nn) {
-        const int y = n / R->Nx, x = n - y * R->Nx;
-        const K<C> k = load_k<C>(*R);
-        Eq<C> q = eq_coef<C>((C)(rho[n] - R->rho0), (C)(ux[n] - R->u0x), (C)(uy[n] - R->u0y),
-                             (C)(T[n] - R->T0), k);
-        S *dst = (S *)R->f[0];
-        const long long idx = (long long)y * R->pitch + x, plane = R->plane;
-        for_each_feq<C>(q, *R, k, [&](auto ic, C fe) {
+        const int y = n / R.Nx, x = n - y * R.Nx;
+        const K<C> k = load_k<C>(R);
+        Eq<C> q = eq_coef<C>((C)(rho[n] - R.rho0), (C)(ux[n] - R.u0x), (C)(uy[n] - R.u0y),
+                             (C)(T[n] - R.T0), k);
+        GLOBAL S *dst = (GLOBAL S *)R.f[0];
+        const long long idx = (long long)y * R.pitch + x, plane = R.plane;
+        for_each_feq<C>(q, R, k, [&](auto ic, C fe) {
             constexpr int i = decltype(ic)::value;
             if (absmax) mx = fmaxf(mx, fabsf((float)fe));
-            else st_s(dst + (long long)i * plane + idx, fe, k.scale);
+            else dst[(long long)i * plane + idx] = cvt_out(fe, k.scale, (S *)nullptr);
         });
         if (!absmax) {
-            int t = fidx(*R, x, y);
+            int t = fidx(R, x, y);
             if (t >= 0) {
-                const long long qp = R->qplane;
+                const long long qp = R.qplane;
                 for (int c = 0; c < 2; ++c) {
-                    R->U[c][t] = rho[n];
-                    R->U[c][qp + t] = ux[n];
-                    R->U[c][2 * qp + t] = uy[n];
-                    R->U[c][3 * qp + t] = T[n];
+                    GLOBAL double *U = (GLOBAL double *)R.U[c];
+                    U[t] = rho[n];
+                    U[qp + t] = ux[n];
+                    U[2 * qp + t] = uy[n];
+                    U[3 * qp + t] = T[n];
                 }
             }
         }
@@ -569,75 +665,81 @@ __global__ __launch_bounds__(256) void k_init(RunDev *R, const double *rho, cons
 // Moments of the current step (post-stream, post-boundary): re-pull from the previous
 // buffer with the previous moment strips; after 0 steps, moments of f*(0).
 template <class S>
-__global__ __launch_bounds__(256) void k_moments(RunDev *R, double *rho, double *ux, double *uy,
+__global__ __launch_bounds__(256) void k_moments(RunDev *Rw, double *rho, double *ux, double *uy,
                                                  double *T) {
     using C = typename Traits<S>::C;
+    CRun &R = *(CRun *)Rw;
     const int n = blockIdx.x * 256 + threadIdx.x;
-    if (n >= R->Nx * R->Ny) return;
-    const int y = n / R->Nx, x = n - y * R->Nx;
-    const K<C> k = load_k<C>(*R);
+    if (n >= R.Nx * R.Ny) return;
+    const int y = n / R.Nx, x = n - y * R.Nx;
+    const K<C> k = load_k<C>(R);
     C g[NQ];
-    if (R->step == 0) {
-        const S *src = (const S *)R->f[R->par];
-        const long long idx = (long long)y * R->pitch + x;
+    if (R.step == 0) {
+        const GLOBAL S *src = (const GLOBAL S *)R.f[R.par];
+        const long long idx = (long long)y * R.pitch + x;
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) g[i] = ld_s(src + (long long)i * R->plane + idx, k.inv_scale);
+        for (int i = 0; i < NQ; ++i) g[i] = cvt_in(src[(long long)i * R.plane + idx], k.inv_scale);
     } else {
-        int t = fidx(*R, x, y);
-        gather_general<S, C>(*R, (const S *)R->f[R->par ^ 1], R->U[R->par ^ 1], x, y, t < 0 ? 0 : t,
-                             k.inv_scale, g);
+        int t = fidx(R, x, y);
+        const GLOBAL S *src = (const GLOBAL S *)R.f[R.par ^ 1];
+        const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par ^ 1];
+        if (in_ring(R, x, y)) gather_general<S, C, true>(R, src, Uc, x, y, t < 0 ? 0 : t, k.inv_scale, g);
+        else gather_general<S, C, false>(R, src, Uc, x, y, t < 0 ? 0 : t, k.inv_scale, g);
     }
     Mom<C> m = moments<C>(g, k);
-    if (rho) rho[n] = R->rho0 + (double)m.drho;
-    if (ux) ux[n] = R->u0x + (double)m.dux;
-    if (uy) uy[n] = R->u0y + (double)m.duy;
-    if (T) T[n] = R->T0 + (double)m.dT;
+    if (rho) rho[n] = R.rho0 + (double)m.drho;
+    if (ux) ux[n] = R.u0x + (double)m.dux;
+    if (uy) uy[n] = R.u0y + (double)m.duy;
+    if (T) T[n] = R.T0 + (double)m.dT;
 }
 
 template <class S>
-__global__ __launch_bounds__(256) void k_export_f(RunDev *R, const double *fbar, double *out) {
+__global__ __launch_bounds__(256) void k_export_f(RunDev *Rw, const double *fbar, double *out) {
     using C = typename Traits<S>::C;
+    CRun &R = *(CRun *)Rw;
     const int n = blockIdx.x * 256 + threadIdx.x;
-    const int nn = R->Nx * R->Ny;
+    const int nn = R.Nx * R.Ny;
     if (n >= nn) return;
-    const int y = n / R->Nx, x = n - y * R->Nx;
-    const K<C> k = load_k<C>(*R);
-    const S *src = (const S *)R->f[R->par];
-    const long long idx = (long long)y * R->pitch + x;
+    const int y = n / R.Nx, x = n - y * R.Nx;
+    const K<C> k = load_k<C>(R);
+    const GLOBAL S *src = (const GLOBAL S *)R.f[R.par];
+    const long long idx = (long long)y * R.pitch + x;
     for (int i = 0; i < NQ; ++i)
-        out[(long long)i * nn + n] = fbar[i] + (double)ld_s(src + (long long)i * R->plane + idx, k.inv_scale);
+        out[(long long)i * nn + n] = fbar[i] + (double)cvt_in(src[(long long)i * R.plane + idx], k.inv_scale);
 }
 
 template <class S>
-__global__ __launch_bounds__(256) void k_export_q(RunDev *R, double *out) {
+__global__ __launch_bounds__(256) void k_export_q(RunDev *Rw, double *out) {
     using C = typename Traits<S>::C;
+    CRun &R = *(CRun *)Rw;
     const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= R->frame_n) return;
+    if (t >= R.frame_n) return;
     int x, y;
-    frame_xy(*R, t, x, y);
-    const long long nn = (long long)R->Nx * R->Ny;
-    const C *Q = (const C *)R->Q;
-    for (int i = 0; i < NQ; ++i) out[i * nn + (long long)y * R->Nx + x] = (double)Q[i * R->qplane + t];
+    frame_xy(R, t, x, y);
+    const long long nn = (long long)R.Nx * R.Ny;
+    const GLOBAL C *Q = (const GLOBAL C *)R.Q;
+    for (int i = 0; i < NQ; ++i) out[i * nn + (long long)y * R.Nx + x] = (double)Q[i * R.qplane + t];
 }
 
 template <class S>
-__global__ __launch_bounds__(256) void k_check(RunDev *R, int *flag) {
+__global__ __launch_bounds__(256) void k_check(RunDev *Rw, int *flag) {
     using C = typename Traits<S>::C;
+    CRun &R = *(CRun *)Rw;
     const int n = blockIdx.x * 256 + threadIdx.x;
-    if (n >= R->Nx * R->Ny) return;
-    const int y = n / R->Nx, x = n - y * R->Nx;
-    const K<C> k = load_k<C>(*R);
-    const S *src = (const S *)R->f[R->par];
-    const long long idx = (long long)y * R->pitch + x;
+    if (n >= R.Nx * R.Ny) return;
+    const int y = n / R.Nx, x = n - y * R.Nx;
+    const K<C> k = load_k<C>(R);
+    const GLOBAL S *src = (const GLOBAL S *)R.f[R.par];
+    const long long idx = (long long)y * R.pitch + x;
     C g[NQ];
     bool bad = false;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
-        g[i] = ld_s(src + (long long)i * R->plane + idx, k.inv_scale);
+        g[i] = cvt_in(src[(long long)i * R.plane + idx], k.inv_scale);
         bad |= !isfinite((double)g[i]);
     }
     Mom<C> m = moments<C>(g, k);
-    double rho = R->rho0 + (double)m.drho, T = R->T0 + (double)m.dT;
+    double rho = R.rho0 + (double)m.drho, T = R.T0 + (double)m.dT;
     bad |= !(rho > 0.0) || !(T > 0.0) || !isfinite(rho) || !isfinite(T);
     if (bad) atomicOr(flag, 1);
 }
@@ -693,34 +795,39 @@ __global__ __launch_bounds__(256) void k_err_final(const double *partials, int n
 
 static inline int blocks_for(long long n) { return (int)((n + 255) / 256); }
 
-hipError_t launch_phase_a(const LaunchSet &L, int storage, hipStream_t s) {
-    if (L.q_blocks <= 0) return hipSuccess;
-    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a<S>), dim3(L.q_blocks), dim3(256), 0, s,
-                                              L.runs, L.q_prefix, L.nruns));
+hipError_t launch_phase_a(const LaunchSet &L, int storage, bool ring, hipStream_t s) {
+    if (!ring && L.blocks[CLS_Q] > 0)
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a<S, false>), dim3(L.blocks[CLS_Q]), dim3(256), 0, s,
+                                                 L.runs, L.prefix[CLS_Q], L.nruns));
+    if (ring && L.blocks[CLS_QRING] > 0)
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a<S, true>), dim3(L.blocks[CLS_QRING]), dim3(256), 0,
+                                                 s, L.runs, L.prefix[CLS_QRING], L.nruns));
     return hipGetLastError();
 }
 
-hipError_t launch_frame(const LaunchSet &L, int storage, hipStream_t s) {
-    if (L.frame_blocks <= 0) return hipSuccess;
-    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_frame<S>), dim3(L.frame_blocks), dim3(256), 0, s,
-                                              L.runs, L.frame_prefix, L.nruns));
+hipError_t launch_frame(const LaunchSet &L, int storage, bool ring, hipStream_t s) {
+    if (!ring && L.blocks[CLS_FRAME] > 0)
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_frame<S, false>), dim3(L.blocks[CLS_FRAME]), dim3(256), 0, s,
+                                                 L.runs, L.prefix[CLS_FRAME], L.nruns));
+    if (ring && L.blocks[CLS_RING] > 0)
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_frame<S, true>), dim3(L.blocks[CLS_RING]), dim3(256), 0, s,
+                                                 L.runs, L.prefix[CLS_RING], L.nruns));
     return hipGetLastError();
 }
 
 hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, hipStream_t s) {
-    if (L.bulk_blocks <= 0) return hipSuccess;
+    const int nb = L.blocks[CLS_BULK];
+    if (nb <= 0) return hipSuccess;
+    const int *pre = L.prefix[CLS_BULK];
     switch (tx) {
     case 64:
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 64>), dim3(L.bulk_blocks), dim3(256), 0,
-                                                  s, L.runs, L.bulk_prefix, L.nruns));
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 64>), dim3(nb), dim3(256), 0, s, L.runs, pre, L.nruns));
         break;
     case 128:
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 128>), dim3(L.bulk_blocks), dim3(256), 0,
-                                                  s, L.runs, L.bulk_prefix, L.nruns));
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 128>), dim3(nb), dim3(256), 0, s, L.runs, pre, L.nruns));
         break;
     default:
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 256>), dim3(L.bulk_blocks), dim3(256), 0,
-                                                  s, L.runs, L.bulk_prefix, L.nruns));
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 256>), dim3(nb), dim3(256), 0, s, L.runs, pre, L.nruns));
         break;
     }
     return hipGetLastError();
@@ -746,7 +853,7 @@ hipError_t launch_init(RunDev *run, int storage, int Nx, int Ny, const double *r
                        hipStream_t s) {
     int nb = blocks_for((long long)Nx * Ny);
     LBM_DISPATCH(storage, hipLaunchKernelGGL((k_init<S>), dim3(nb), dim3(256), 0, s, run, rho, ux, uy,
-                                              T, absmax));
+                                             T, absmax));
     return hipGetLastError();
 }
 
@@ -754,7 +861,7 @@ hipError_t launch_moments(RunDev *run, int storage, int Nx, int Ny, double *rho,
                           double *uy, double *T, hipStream_t s) {
     int nb = blocks_for((long long)Nx * Ny);
     LBM_DISPATCH(storage, hipLaunchKernelGGL((k_moments<S>), dim3(nb), dim3(256), 0, s, run, rho, ux,
-                                              uy, T));
+                                             uy, T));
     return hipGetLastError();
 }
 
@@ -762,7 +869,7 @@ hipError_t launch_export_f(RunDev *run, int storage, int Nx, int Ny, const doubl
                            double *out, hipStream_t s) {
     int nb = blocks_for((long long)Nx * Ny);
     LBM_DISPATCH(storage, hipLaunchKernelGGL((k_export_f<S>), dim3(nb), dim3(256), 0, s, run, fbar,
-                                              out));
+                                             out));
     return hipGetLastError();
 }
 

@@ -1,0 +1,262 @@
+"""Serving loop: simulation jobs admitted against an HBM budget, resident on the device and
+advanced together by batched launches (continuous batching), with per-job latency.
+
+Each tick the engine (1) admits waiting jobs in arrival order while they fit the HBM budget and
+the slot limit (a job that does not fit yet does not block smaller ones behind it; a job larger
+than the whole budget is rejected), (2) advances every resident job by up to ``tick_steps``
+steps in one batched call -- jobs admitted this tick share the launches of jobs already running
+-- and (3) retires finished jobs: moments are exported, device memory is released and the
+latency (arrival to result) is recorded.  A job whose state fails the stability check is
+retired with an error and does not disturb the others.
+
+The backend is pluggable: ``GpuBackend`` drives the HIP library through ``lbm.Group``;
+tests use a mock backend to check the scheduling on the CPU.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Any, Optional
+
+import numpy as np
+
+
+@dataclass
+class Job:
+    jid: int
+    L: int
+    W: int
+    steps: int
+    bc: str = "zg"
+    seed: int = 0
+    sigma_max: float = 0.0015
+    mach: float = 0.1
+    arrival: float = 0.0
+    # filled by the engine
+    admitted: Optional[float] = None
+    finished: Optional[float] = None
+    done_steps: int = 0
+    status: str = "queued"          # queued | running | done | failed | rejected
+    result: Any = None
+    handle: Any = field(default=None, repr=False)
+    nbytes: int = 0
+
+    @property
+    def nodes(self):
+        return (self.L + 2 * self.W) ** 2
+
+    @property
+    def latency(self):
+        return None if self.finished is None else self.finished - self.arrival
+
+
+class GpuBackend:
+    """Runs jobs on the HIP library: one lbm.Run per job, all resident runs in one lbm.Group."""
+
+    def __init__(self, storage="f32", stream=None, allocator=None, check_every_tick=True):
+        from paper_2504_20169_amd import lbm
+        self.lbm = lbm
+        self.storage = storage
+        self.stream = stream
+        self.allocator = allocator
+        self.group = lbm.Group(stream=stream, allocator=allocator)
+        self.check_every_tick = check_every_tick
+
+    def _make(self, job: Job):
+        from paper_2504_20169_amd import workloads as wl
+        lbm = self.lbm
+        r = lbm.Run(job.L, job.L, 0.8, 1.0, job.mach, 0.0, 1.0, storage=self.storage,
+                    stream=self.stream, allocator=self.allocator)
+        r.set_bc(lbm.LBM_ALL, job.bc)
+        if job.W > 0:
+            r.set_pml(lbm.LBM_ALL, job.W, job.sigma_max)
+        return r
+
+    def footprint(self, job: Job) -> int:
+        r = self._make(job)
+        b = r.footprint()
+        r.close()
+        return b
+
+    def start(self, job: Job):
+        from paper_2504_20169_amd import workloads as wl
+        r = self._make(job)
+        spec = wl.vortex_pulse(L=job.L, W=job.W, sigma_max=job.sigma_max, mach=job.mach,
+                               bc=job.bc, seed=job.seed, radius=min(16.0, job.L / 8.0))
+        r.init(*spec.fields.as_tuple())
+        self.group.add(r)
+        return r
+
+    def advance(self, handles, steps):
+        if handles:
+            order = {id(r): k for k, r in enumerate(self.group.members)}
+            arr = np.zeros(len(self.group.members), dtype=np.int64)
+            for r, s in zip(handles, steps):
+                arr[order[id(r)]] = s
+            self.group.step(steps=arr)
+
+    def sync(self):
+        self.group.synchronize()
+
+    def healthy(self, r) -> bool:
+        return r.check() == self.lbm.LBM_OK
+
+    def finish(self, r):
+        rho, ux, uy, T = r.moments()
+        self.group.remove(r)
+        r.close()
+        return dict(rho=rho, ux=ux, uy=uy, T=T)
+
+    def drop(self, r):
+        self.group.remove(r)
+        r.close()
+
+    def close(self):
+        self.group.close()
+
+
+class Engine:
+    def __init__(self, backend, hbm_budget: int, max_jobs: int = 1024, tick_steps: int = 200,
+                 clock=time.perf_counter):
+        self.backend = backend
+        self.budget = int(hbm_budget)
+        self.max_jobs = max_jobs
+        self.tick_steps = tick_steps
+        self.clock = clock
+        self.waiting: deque[Job] = deque()
+        self.active: list[Job] = []
+        self.finished: list[Job] = []
+        self.used = 0
+        self.node_updates = 0
+        self.t0 = None
+
+    def submit(self, job: Job):
+        job.nbytes = self.backend.footprint(job)
+        if job.nbytes > self.budget:
+            job.status = "rejected"
+            job.finished = self.clock()
+            self.finished.append(job)
+            return
+        self.waiting.append(job)
+
+    def _admit(self, now):
+        keep = deque()
+        while self.waiting:
+            job = self.waiting.popleft()
+            if len(self.active) < self.max_jobs and self.used + job.nbytes <= self.budget:
+                job.handle = self.backend.start(job)
+                job.admitted = now
+                job.status = "running"
+                self.used += job.nbytes
+                self.active.append(job)
+            else:
+                keep.append(job)
+        self.waiting = keep
+
+    def tick(self):
+        now = self.clock()
+        if self.t0 is None:
+            self.t0 = now
+        self._admit(now)
+        if not self.active:
+            return 0
+        steps = [min(self.tick_steps, j.steps - j.done_steps) for j in self.active]
+        self.backend.advance([j.handle for j in self.active], steps)
+        self.backend.sync()
+        for j, s in zip(self.active, steps):
+            j.done_steps += s
+            self.node_updates += j.nodes * s
+        still = []
+        for j in self.active:
+            if not self.backend.healthy(j.handle):
+                self.backend.drop(j.handle)
+                j.status = "failed"
+            elif j.done_steps >= j.steps:
+                j.result = self.backend.finish(j.handle)
+                j.status = "done"
+            else:
+                still.append(j)
+                continue
+            j.finished = self.clock()
+            j.handle = None
+            self.used -= j.nbytes
+            self.finished.append(j)
+        self.active = still
+        return len(steps)
+
+    def run_trace(self, jobs, realtime=True, log=None):
+        """Feed jobs at their arrival times (seconds from start) and run until all finish."""
+        pending = deque(sorted(jobs, key=lambda j: j.arrival))
+        start = self.clock()
+        for j in pending:
+            j.arrival = start + j.arrival
+        while pending or self.waiting or self.active:
+            now = self.clock()
+            while pending and (pending[0].arrival <= now or not realtime):
+                self.submit(pending.popleft())
+            if not self.active and not self.waiting:
+                if pending and realtime:
+                    time.sleep(max(0.0, min(0.05, pending[0].arrival - self.clock())))
+                continue
+            n = self.tick()
+            if log:
+                log("tick: %d active, %d waiting, %d done, used %.2f GB" % (
+                    n, len(self.waiting), len(self.finished), self.used / 1e9))
+        self.elapsed = self.clock() - start
+        return self.report()
+
+    def report(self):
+        done = [j for j in self.finished if j.status == "done"]
+        lat = np.array([j.latency for j in done]) if done else np.zeros(0)
+        el = getattr(self, "elapsed", None) or ((self.clock() - self.t0) if self.t0 else 0.0)
+        return dict(
+            jobs=len(self.finished), done=len(done),
+            failed=sum(j.status == "failed" for j in self.finished),
+            rejected=sum(j.status == "rejected" for j in self.finished),
+            p50_s=float(np.percentile(lat, 50)) if len(lat) else None,
+            p99_s=float(np.percentile(lat, 99)) if len(lat) else None,
+            mean_s=float(lat.mean()) if len(lat) else None,
+            elapsed_s=el,
+            aggregate_mlups=self.node_updates / el / 1e6 if el > 0 else None,
+        )
+
+
+def jobs_from_trace(trace, scale_steps=1.0, sigma_max=0.0015):
+    """Jobs from workloads.poisson_trace entries (arrival offset, dict)."""
+    out = []
+    for k, (t, d) in enumerate(trace):
+        out.append(Job(jid=k, L=d["L"], W=d["W"], steps=max(1, int(d["steps"] * scale_steps)),
+                       bc=d["bc"], seed=d["seed"], arrival=t, sigma_max=sigma_max))
+    return out
+
+
+def main():
+    import argparse
+    import json
+    import sys
+
+    from paper_2504_20169_amd import workloads as wl
+
+    ap = argparse.ArgumentParser(description="serve a Poisson trace of D2Q37 jobs")
+    ap.add_argument("--jobs", type=int, default=40)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--tick-steps", type=int, default=200)
+    ap.add_argument("--scale-steps", type=float, default=1.0)
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--seed", type=int, default=5)
+    args = ap.parse_args()
+    trace = wl.poisson_trace(args.jobs, rate=args.rate, seed=args.seed)
+    jobs = jobs_from_trace(trace, args.scale_steps)
+    be = GpuBackend(storage=args.storage)
+    eng = Engine(be, int(args.budget_gb * 1e9), tick_steps=args.tick_steps)
+    rep = eng.run_trace(jobs, log=lambda m: print(m, file=sys.stderr, flush=True))
+    rep.update(rate=args.rate, budget_gb=args.budget_gb, storage=args.storage,
+               scale_steps=args.scale_steps)
+    print(json.dumps(rep))
+    be.close()
+
+
+if __name__ == "__main__":
+    main()

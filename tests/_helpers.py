@@ -80,3 +80,26 @@ def rel_errors(g, o, perm, with_f=True):
 
 def noise(seed, mean=(1.0, 0.0, 0.0, 1.0), amp=1e-3):
     return lambda Nx, Ny: wl.noisy_state(Nx, Ny, seed, *mean, amp=amp)
+
+
+def oracle_self_sensitivity(oracle_mod, Lx, Ly, tau=0.8, mean=(1.0, 0.0, 0.0, 1.0), bc=None,
+                            pml=None, fields=None, steps=0):
+    """How far the oracle's own populations and Q move when its input density is perturbed at
+    the rounding level (random relative +-2e-16): the conditioning floor for comparing two
+    FP64 implementations that round differently.  Returns (f rel-to-weight, Q rel-to-max)."""
+    outs = []
+    for k in range(2):
+        def fk(Nx, Ny, k=k):
+            F = fields(Nx, Ny) if callable(fields) else fields
+            if k:
+                u = wl.uniform(77, Nx * Ny).reshape(Ny, Nx)
+                F = wl.Fields(F.rho * (1.0 + (u - 0.5) * 4e-16), F.ux, F.uy, F.T)
+            return F
+        _, o = make_pair(oracle_mod, Lx, Ly, tau, mean, bc, pml, fk, gpu=False)
+        o.step(steps)
+        outs.append((o.populations(), o.pml_q()))
+    _, w, _ = oracle_mod.lattice()
+    df = float((np.abs(outs[1][0] - outs[0][0]).max(axis=(1, 2)) / w).max())
+    qmax = np.abs(outs[0][1]).max()
+    dq = float(np.abs(outs[1][1] - outs[0][1]).max() / qmax) if qmax > 0 else 0.0
+    return df, dq

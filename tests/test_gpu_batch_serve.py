@@ -1,0 +1,98 @@
+"""Batched runs and the serving loop on the GPU: every run's result is bitwise the same alone,
+in a batch of uneven runs, and in the served mix; FP32/FP16 storage errors against the oracle."""
+import numpy as np
+import pytest
+
+from paper_2504_20169_amd import lbm
+from paper_2504_20169_amd import workloads as wl
+from paper_2504_20169_amd.serve import Engine, GpuBackend, Job
+from _helpers import make_pair, say
+
+pytestmark = pytest.mark.gpu
+
+CASES = [  # (L, W, bc, steps)
+    (48, 0, "zg", 37), (64, 8, "nrbc", 51), (40, 4, "zg", 20), (72, 16, "nrbc", 45), (33, 5, "nrbc", 1),
+]
+
+
+def _make(L, W, bc, storage, seed):
+    spec = wl.vortex_pulse(L=L, W=W, sigma_max=0.01, mach=0.1, bc=bc, seed=seed, radius=6.0)
+    r = lbm.Run(L, L, 0.8, 1.0, 0.1, 0.0, 1.0, storage=storage)
+    r.set_bc(lbm.LBM_ALL, bc)
+    if W:
+        r.set_pml(lbm.LBM_ALL, W, 0.01)
+    r.init(*spec.fields.as_tuple())
+    return r
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_batch_equals_alone(storage):
+    alone = []
+    for k, (L, W, bc, n) in enumerate(CASES):
+        r = _make(L, W, bc, storage, 40 + k)
+        r.step(n)
+        alone.append(r.populations())
+        r.close()
+    g = lbm.Group()
+    runs = [_make(L, W, bc, storage, 40 + k) for k, (L, W, bc, n) in enumerate(CASES)]
+    for r in runs:
+        g.add(r)
+    steps = np.array([c[3] for c in CASES])
+    g.step(steps=steps // 2)
+    g.step(steps=steps - steps // 2)
+    g.synchronize()
+    for r, a, c in zip(runs, alone, CASES):
+        assert r.step_count == c[3]
+        assert np.array_equal(r.populations(), a), c
+    # remove one member mid-way; the others continue identically
+    g.remove(runs[1])
+    g.step(nsteps=3)
+    for k in (0, 2, 3, 4):
+        assert runs[k].step_count == CASES[k][3] + 3
+    g.close()
+
+
+def test_served_results_equal_alone():
+    """Jobs arriving while others are on the GPU give bitwise the same moments as alone; a job
+    forced unstable from the host is retired as failed without disturbing the rest."""
+    jobs = [Job(jid=k, L=L, W=W, steps=n * 7, bc=bc, seed=100 + k, sigma_max=0.01, arrival=0.01 * k)
+            for k, (L, W, bc, n) in enumerate(CASES)]
+    bad = Job(jid=99, L=40, W=6, steps=300, bc="zg", seed=7, sigma_max=80.0, arrival=0.0)
+    be = GpuBackend(storage="f32")
+    eng = Engine(be, hbm_budget=int(1e9), tick_steps=16)
+    rep = eng.run_trace(jobs + [bad], realtime=False)
+    be.close()
+    say(rep)
+    st = {j.jid: j.status for j in eng.finished}
+    assert st[99] == "failed"
+    for j in eng.finished:
+        if j.jid == 99:
+            continue
+        assert j.status == "done"
+        ref = GpuBackend(storage="f32")
+        r = ref.start(Job(jid=j.jid, L=j.L, W=j.W, steps=j.steps, bc=j.bc, seed=j.seed, sigma_max=0.01))
+        ref.group.remove(r)
+        r.step(j.steps)
+        rho, ux, uy, T = r.moments()
+        r.close()
+        ref.close()
+        assert np.array_equal(rho, j.result["rho"]) and np.array_equal(ux, j.result["ux"])
+        assert np.array_equal(T, j.result["T"])
+
+
+@pytest.mark.parametrize("storage,tol_rho_u", [("f32", 1e-6), ("f16", 5e-3)])
+def test_reduced_storage_error_vs_oracle(oracle_mod, storage, tol_rho_u):
+    """FP32 / FP16 deviation storage against the FP64 oracle on the vortex + pulse workload
+    (reduced bulk, Mach 0.1, NRBC + PML), 400 steps; errors relative as in the FP64 parity."""
+    spec = wl.vortex_pulse(L=96, W=12, sigma_max=0.0015, mach=0.1, bc="nrbc", radius=8.0)
+    g, o = make_pair(oracle_mod, 96, 96, bc="nrbc", pml=(15, 12, 0.0015), mean=(1.0, 0.1, 0.0, 1.0),
+                     fields=spec.fields, storage=storage)
+    g.step(400)
+    o.step(400)
+    mg, mo = g.moments(), o.moments()
+    e_rho = np.abs(mg[0] - mo[0]).max() / np.abs(mo[0]).max()
+    us = max(np.abs(mo[1]).max(), np.abs(mo[2]).max())
+    e_u = max(np.abs(mg[1] - mo[1]).max(), np.abs(mg[2] - mo[2]).max()) / us
+    e_T = np.abs(mg[3] - mo[3]).max() / np.abs(mo[3]).max()
+    say(storage, "rho %.2e u %.2e T %.2e" % (e_rho, e_u, e_T))
+    assert e_rho < tol_rho_u and e_u < tol_rho_u and e_T < tol_rho_u
