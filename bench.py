@@ -33,9 +33,10 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_run(lbm, wl, storage, stream, alloc, L, W, sigma, mach, bc):
+def make_run(lbm, wl, storage, stream, alloc, L, W, sigma, mach, bc, layout=0):
     spec = wl.vortex_pulse(L=L, W=W, sigma_max=sigma, mach=mach, bc=bc)
-    r = lbm.Run(L, L, 0.8, 1.0, mach, 0.0, 1.0, storage=storage, stream=stream, allocator=alloc)
+    r = lbm.Run(L, L, 0.8, 1.0, mach, 0.0, 1.0, storage=storage, stream=stream, allocator=alloc,
+                layout=layout)
     r.set_bc(lbm.LBM_ALL, bc)
     if W:
         r.set_pml(lbm.LBM_ALL, W, sigma)
@@ -43,26 +44,23 @@ def make_run(lbm, wl, storage, stream, alloc, L, W, sigma, mach, bc):
     return r, spec
 
 
-def time_run(torch, r, steps, warmup, profile):
-    """Time `steps` steps after `warmup`.  Unprofiled: HIP-graph replays with the boundary/PML
-    chains on side streams beside the bulk kernel.  Profiled: the kernel classes in order on the
-    run's stream, bracketed by HIP events (per-class launch durations)."""
-    r.profile(False)
+def time_run(torch, r, steps, warmup, mode):
+    """Time `steps` steps after `warmup`.  mode 2: the normal schedule (boundary/PML chain on a
+    side stream beside the bulk kernel) with HIP events around each bulk launch on its stream.
+    mode 1: the kernel classes in order on the run's stream, events around each class."""
+    r.profile(0)
     r.step(warmup)
     r.synchronize()
-    if profile:
-        r.profile(True)
-        r.profile_read(reset=True)
+    r.profile(mode)
+    r.profile_read(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r.step(steps)
     r.synchronize()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms = n = None
-    if profile:
-        ms, n = r.profile_read(reset=True)
-        r.profile(False)
+    ms, n = r.profile_read(reset=True)
+    r.profile(0)
     return dt, ms, n
 
 
@@ -104,10 +102,12 @@ def main():
     ap.add_argument("--mach", type=float, default=0.1)
     ap.add_argument("--bc", default="nrbc")
     ap.add_argument("--storages", default="f64,f32,f16")
+    ap.add_argument("--layout", type=int, default=0, help="0: row-interleaved, 1: plane per velocity")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--prof-steps", type=int, default=500,
-                    help="steps of the separate profiled pass that times each kernel class")
+                    help="steps of a separate pass that runs the kernel classes in order and times "
+                         "each (0 skips it)")
     ap.add_argument("--serve-jobs", type=int, default=24, help="0 skips the serving trace")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-scale", type=float, default=0.1,
@@ -130,8 +130,10 @@ def main():
         sys.exit(3)
     lbm.load()
     dev = torch.cuda.get_device_properties(0)
-    stream = torch.cuda.Stream()
-    alloc = lbm.torch_allocator()
+    # Runs own their stream (the library forks the boundary/PML chains onto side streams beside
+    # the bulk kernel) and take device memory from hipMalloc.
+    stream = None
+    alloc = None
 
     if args.copy_calibration:
         n = 1 << 30
@@ -145,29 +147,35 @@ def main():
     for storage in args.storages.split(","):
         _log("bench: storage", storage)
         r, spec = make_run(lbm, wl, storage, stream, alloc, args.L, args.W, args.sigma,
-                           args.mach, args.bc)
+                           args.mach, args.bc, args.layout)
         Nx, Ny = r.grid()
         n_bulk, n_frame, n_q = r.node_classes()
-        dt, _, _ = time_run(torch, r, args.steps, args.warmup, profile=False)
-        _, ms, n = time_run(torch, r, args.prof_steps, 5, profile=True)
+        dt, ms_live, n_live = time_run(torch, r, args.steps, args.warmup, mode=2)
+        if args.prof_steps > 0:
+            _, ms, n = time_run(torch, r, args.prof_steps, 5, mode=1)
+        else:
+            ms, n = np.zeros(3), np.zeros(3, dtype=np.int64)
         st = r.check()
         nodes = Nx * Ny
         mlups = nodes * args.steps / dt / 1e6
         alg_bytes_step = BYTES_PER_NODE[storage] * nodes + PML_EXTRA[storage] * n_q
-        bulk_ms = ms[0] / max(n[0], 1)
-        frame_ms = ms[1] / max(n[1], 1)
-        pha_ms = ms[2] / max(n[2], 1)
+        bulk_ms = ms_live[0] / max(n_live[0], 1)
         bulk_bytes = BYTES_PER_NODE[storage] * n_bulk
         results[storage] = dict(
             mlups=mlups, mlups_bulk=args.L * args.L * args.steps / dt / 1e6,
             ms_per_step=dt * 1e3 / args.steps,
             gbs_step=alg_bytes_step / (dt / args.steps) / 1e9,
-            bulk_kernel_ms=bulk_ms, frame_kernel_ms=frame_ms, phase_a_kernel_ms=pha_ms,
+            bulk_kernel_ms=bulk_ms,
             bulk_kernel_gbs=bulk_bytes / (bulk_ms * 1e-3) / 1e9 if bulk_ms > 0 else None,
             bulk_nodes=n_bulk, frame_nodes=n_frame, q_nodes=n_q, bulk_bytes_per_launch=bulk_bytes,
-            boundary_cost_ratio=(ms[1] + ms[2]) / max(ms[0], 1e-9),
-            profiled_ms_per_step=sum(ms) / max(n[1], 1),
             stable=(st == lbm.LBM_OK))
+        if args.prof_steps > 0:
+            results[storage]["in_order"] = dict(
+                steps=args.prof_steps,
+                bulk_kernel_ms=ms[0] / max(n[0], 1), frame_kernel_ms=ms[1] / max(n[1], 1),
+                phase_a_kernel_ms=ms[2] / max(n[2], 1),
+                boundary_cost_ratio=(ms[1] + ms[2]) / max(ms[0], 1e-9),
+                ms_per_step=sum(ms) / max(n[1], 1))
         if storage != "f64" and "f64" in results:
             rho_ref, ux_ref, uy_ref, T_ref = results["f64"]["_moments"]
             rho, ux, uy, T = r.moments()
@@ -199,7 +207,7 @@ def main():
         "config": {
             "workload": "d2q37_vortex_pulse_%dsq_pml%d_%s_mach%.2g" % (args.L, args.W, args.bc, args.mach),
             "bulk": args.L, "pml_width": args.W, "grid": args.L + 2 * args.W, "boundary": args.bc,
-            "sigma_max": args.sigma, "tau": 0.8, "storage": main_s,
+            "sigma_max": args.sigma, "tau": 0.8, "storage": main_s, "layout": args.layout,
             "device": dev.name,
         },
         "roofline": {
@@ -212,14 +220,17 @@ def main():
             "traffic": None,
             "bytes_per_launch": R["bulk_bytes_per_launch"],
             "avg_launch_ms": round(R["bulk_kernel_ms"], 5),
-            "timing": "HIP events around each k_bulk launch on the run's stream, %d-step profiled pass "
-                      "(kernel classes in order)" % args.prof_steps,
+            "timing": "HIP events around each k_bulk launch on its stream inside the timed %d steps "
+                      "(boundary chain on a side stream beside it)" % args.steps,
         },
         "variants": {},
     }
+    def rnd(v):
+        if isinstance(v, dict):
+            return {k: rnd(x) for k, x in v.items() if not k.startswith("_")}
+        return round(v, 6) if isinstance(v, float) else v
     for s, v in results.items():
-        v = {k: (round(x, 6) if isinstance(x, float) else x) for k, x in v.items() if not k.startswith("_")}
-        line["variants"][s] = v
+        line["variants"][s] = rnd(v)
     if args.serve_jobs > 0:
         _log("bench: serving trace")
         line["serving"] = serve_trace(args.serve_jobs, args.serve_rate, args.serve_scale, "f32", 200)

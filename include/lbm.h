@@ -82,7 +82,11 @@ typedef struct {
     int32_t storage;             /* lbm_storage */
     double f16_scale;            /* LBM_F16_DEV: scale s (power of two); 0 = chosen at init */
     const lbm_allocator *allocator; /* NULL = hipMalloc / hipFree */
-    void *stream;                /* hipStream_t to enqueue on; NULL = a stream the run owns */
+    void *stream;                /* hipStream_t to enqueue on; NULL = a stream the run owns (then
+                                    the boundary/PML kernels run on side streams beside the bulk
+                                    kernel; on a caller's stream all kernels run in order) */
+    int32_t layout;              /* population layout in HBM: 0 = the 37 population rows of each
+                                    grid row adjacent (default), 1 = one plane per velocity */
 } lbm_desc;
 
 /* Kernel tile shape (set by lbm_set_launch or lbm_autotune).  bulk_tx in {64,128,256}
@@ -178,11 +182,15 @@ lbm_status lbm_get_launch(lbm_handle h, lbm_launch *cfg);
 lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path,
                         lbm_launch *chosen);
 
-/* Per-kernel-class timing with HIP events on the run's stream (the wall time of the
- * boundary/PML kernels vs the bulk kernel; Sec. 5 "Computational Cost").  Enabling it makes
- * lbm_step launch eagerly (no graphs).  lbm_profile_read synchronises and returns the summed
- * milliseconds and launch counts since the last reset: ms[0] bulk, ms[1] boundary/PML frame,
- * ms[2] PML phase A; launches[0..2] likewise. */
+/* Per-kernel-class timing with HIP events (the wall time of the boundary/PML kernels vs the
+ * bulk kernel; Sec. 5 "Computational Cost").  mode 1: every kernel class runs in order on the
+ * run's stream and events bracket each class: ms[0] bulk, ms[1] boundary/PML frame (phase B),
+ * ms[2] phase A (characteristic fill of the ring and PML auxiliary update).  mode 2: the normal
+ * schedule (boundary chain on a side stream beside the bulk kernel, where the run owns its
+ * stream) with events bracketing the bulk kernel alone, on the stream it runs on; only ms[0]
+ * and launches[0] accumulate.  mode 0 turns timing off.  Any mode other than 0 makes lbm_step
+ * launch eagerly (no graphs); a mode outside 0..2 is LBM_ERR_ARG.  lbm_profile_read
+ * synchronises and returns the summed milliseconds and launch counts since the last reset. */
 lbm_status lbm_profile(lbm_handle h, int enable);
 lbm_status lbm_profile_read(lbm_handle h, double ms[3], int64_t launches[3], int reset);
 

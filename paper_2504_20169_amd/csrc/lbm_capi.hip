@@ -64,31 +64,28 @@ struct DeviceMem {
 
 int tx_index(int tx) { return tx == 64 ? 0 : tx == 128 ? 1 : 2; }
 
-// Side streams and events of the per-step fork/join: the bulk kernel runs on the main stream
-// while the boundary/PML chain of the frame (side stream 1) and of the characteristic ring
-// (side stream 2) runs beside it.  All streams keep the default priority.
+// Grids up to this many nodes step through captured HIP graphs.
+constexpr long long GRAPH_MAX_NODES = 1LL << 18;
+
+// Side stream and events of the per-step fork/join: the bulk kernel runs on the main stream while
+// the boundary chain (phase A, then the frame kernel) runs beside it on the side stream.  Both
+// streams keep the default priority.
 struct StepStreams {
-    hipStream_t side[2] = {nullptr, nullptr};
-    hipEvent_t fork = nullptr, a_done[2] = {nullptr, nullptr}, f_done[2] = {nullptr, nullptr};
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, done = nullptr;
     bool ok = false;
     hipError_t create() {
-        hipError_t e = hipSuccess;
-        for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
+        hipError_t e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-        for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&a_done[k], hipEventDisableTiming);
-        for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&f_done[k], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
         ok = e == hipSuccess;
         return e;
     }
     void destroy() {
-        for (int k = 0; k < 2; ++k) {
-            if (side[k]) (void)hipStreamDestroy(side[k]);
-            if (a_done[k]) (void)hipEventDestroy(a_done[k]);
-            if (f_done[k]) (void)hipEventDestroy(f_done[k]);
-            side[k] = nullptr; a_done[k] = f_done[k] = nullptr;
-        }
+        if (side) (void)hipStreamDestroy(side);
         if (fork) (void)hipEventDestroy(fork);
-        fork = nullptr;
+        if (done) (void)hipEventDestroy(done);
+        side = nullptr; fork = done = nullptr;
         ok = false;
     }
 };
@@ -107,7 +104,7 @@ struct lbm_run {
     RunDev *dd = nullptr;
     RunDev **dptr = nullptr;
     int *dprefix = nullptr;   // [NCLS][2] prefix arrays of the single-run launch set
-    int nblocks[NCLS] = {0, 0, 0, 0, 0};
+    int nblocks[NCLS] = {0, 0, 0, 0};
     double fbar[NQ];
     double *fbar_d = nullptr;
     hipStream_t own_stream = nullptr;
@@ -119,7 +116,7 @@ struct lbm_run {
     int graph_G = 0;
     int graph_tx = 0;
     bool graph_failed = false;
-    bool prof = false;
+    int prof = 0;                     // 0 off, 1 classes in order, 2 bulk kernel in the normal schedule
     struct Ev { hipEvent_t a, b; int cls; };
     std::vector<Ev> pending;
     std::vector<hipEvent_t> pool;
@@ -145,7 +142,7 @@ struct lbm_group {
     long long *hlimits = nullptr;     // pinned
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
-    int blocks[NCLS] = {0, 0, 0, 0, 0};
+    int blocks[NCLS] = {0, 0, 0, 0};
     size_t cap = 0;
     StepStreams ss;
 };
@@ -173,6 +170,8 @@ lbm_status setup_geometry(lbm_run *h, RunDev &R) {
     R.open_y = h->bc[YMIN] != BC_PERIODIC;
     if ((R.open_x && R.Nx < 7) || (R.open_y && R.Ny < 7))
         return fail(LBM_ERR_ARG, "an open axis needs at least 7 nodes (3 boundary + 1 + 3)");
+    if ((!R.open_x && R.Nx < 3) || (!R.open_y && R.Ny < 3))
+        return fail(LBM_ERR_ARG, "a periodic axis needs at least 3 nodes");
     if ((long long)R.Nx * R.Ny > (1LL << 30)) return fail(LBM_ERR_ARG, "grid too large");
     R.qd = std::max(h->W + 1, 3);
     int depth[4];
@@ -196,13 +195,22 @@ lbm_status setup_geometry(lbm_run *h, RunDev &R) {
     long long fast = (long long)std::max(0, R.fx1 - R.fx0) * std::max(0, R.fy1 - R.fy0);
     R.frame_n = (int)((long long)R.Nx * R.Ny - fast);
     R.has_q = h->W > 0 && (h->pml[0] || h->pml[1] || h->pml[2] || h->pml[3]);
-    R.pitch = (int)round_up(R.Nx, 64);
-    R.plane = round_up((long long)R.pitch * R.Ny, 64);
+    const long long row = round_up(R.Nx, 64);
+    if (d.layout == 0) {            // rows: the 37 population rows of a grid row adjacent
+        R.plane = row;
+        R.pitch = (int)(NQ * row);
+        R.fsize = (long long)NQ * row * R.Ny;
+    } else {                        // planes: one padded plane per velocity
+        R.pitch = (int)row;
+        R.plane = round_up(row * R.Ny, 64);
+        R.fsize = (long long)NQ * R.plane;
+    }
     R.qplane = round_up(std::max(R.frame_n, 1), 64);
-    // kernels address a population plane with a 32-bit byte offset
-    if ((unsigned long long)R.plane * elem_size(d.storage) >= (1ULL << 32) ||
-        (unsigned long long)R.qplane * 4 * sizeof(double) >= (1ULL << 32))
-        return fail(LBM_ERR_ARG, "grid too large: one population plane must stay below 4 GiB");
+    R.rplane = round_up(std::max(R.ring_n, 1), 64);
+    // the bulk kernel addresses a tile (at most 4 rows) with a 32-bit byte offset from a
+    // uniform base; the frame arrays use 32-bit element indices
+    if ((unsigned long long)R.qplane * 4 >= (1ULL << 31))
+        return fail(LBM_ERR_ARG, "grid too large: frame arrays must stay below 4 GiB");
     for (int k = 0; k < 3; ++k) {
         int tx = 64 << k, ty = 256 / tx;
         if (fast > 0) {
@@ -265,9 +273,10 @@ void set_scale(RunDev &R, double s) {
 }
 
 size_t footprint_of(const RunDev &R, int storage) {
-    size_t b = 2 * (size_t)NQ * R.plane * elem_size(storage);
+    size_t b = 2 * (size_t)R.fsize * elem_size(storage);
     if (R.has_q) b += (size_t)NQ * R.qplane * compute_size(storage);
     b += 2 * 4 * (size_t)R.qplane * sizeof(double);
+    if (R.ring_n > 0) b += (size_t)NQ * R.rplane * compute_size(storage);
     b += sizeof(RunDev) + 256 * 3 + NQ * sizeof(double);
     return b;
 }
@@ -275,10 +284,11 @@ size_t footprint_of(const RunDev &R, int storage) {
 void compute_blocks(const RunDev &R, int tx, int nb[NCLS]) {
     int k = tx_index(tx);
     nb[CLS_BULK] = R.tiles_x[k] * R.tiles_y[k];
-    nb[CLS_FRAME] = (R.frame_n + FRAME_BLOCK - 1) / FRAME_BLOCK;
-    nb[CLS_RING] = (R.ring_n + FRAME_BLOCK - 1) / FRAME_BLOCK;
-    nb[CLS_Q] = R.has_q ? nb[CLS_FRAME] : 0;
-    nb[CLS_QRING] = R.has_q ? nb[CLS_RING] : 0;
+    const int fb = (R.frame_n + FRAME_BLOCK - 1) / FRAME_BLOCK;
+    const int rb = (R.ring_n + FRAME_BLOCK - 1) / FRAME_BLOCK;
+    nb[CLS_FRAME] = rb + fb;
+    nb[CLS_A] = rb + (R.has_q ? fb : 0);
+    nb[CLS_RING] = rb;
 }
 
 lbm_status upload_prefix(lbm_run *h) {
@@ -331,61 +341,52 @@ hipEvent_t take_event(lbm_run *h) {
     return e;
 }
 
-// One step of a launch set.  Dependencies: both phase-A kernels (Q of the frame and of the
-// ring) before both frame kernels (grad Q reads neighbours across the two sets); the bulk
-// kernel depends on none of them; the flip waits for everything.  With side streams the
-// chains run beside the bulk kernel.  With `prof` the classes run in order on one stream and
-// HIP events bracket the bulk kernel (class 0), the frame kernels (class 1) and the phase-A
-// kernels (class 2).
+// One step of a launch set.  Dependencies: phase A (characteristic fill of the ring, Q update)
+// before the frame kernel (grad Q reads neighbours' Q of the new level); the bulk kernel depends
+// on neither; the flip waits for everything.  With a side stream the boundary chain runs beside
+// the bulk kernel.  Profiling (`prof` non-null): mode 1 runs the classes in order on one stream
+// with HIP events bracketing the bulk kernel (class 0), the frame kernel (class 1) and phase A
+// (class 2); mode 2 keeps the normal schedule and brackets the bulk kernel alone, on its stream.
 lbm_status enqueue_step(const LaunchSet &L, int storage, int tx, hipStream_t s, StepStreams *ss,
                         lbm_run *prof) {
-    const bool has_q = L.blocks[CLS_Q] + L.blocks[CLS_QRING] > 0;
+    const bool has_a = L.blocks[CLS_A] > 0;
+    const bool has_f = L.blocks[CLS_FRAME] > 0;
     const bool has_b = L.blocks[CLS_BULK] > 0;
+    const int mode = prof ? prof->prof : 0;
     hipEvent_t ev[6] = {};
-    if (prof) {
+    if (mode) {
         harvest_events(prof, false);
         for (int k = 0; k < 6; ++k) ev[k] = take_event(prof);
     }
-    // Timed (profiled) steps run every kernel class in order on one stream, so each class's
-    // events bracket that class alone.
-    if (!ss || !ss->ok || prof) {
-        if (prof && has_q) HIP_TRY(hipEventRecord(ev[4], s));
-        HIP_TRY(launch_phase_a(L, storage, false, s));
-        HIP_TRY(launch_phase_a(L, storage, true, s));
-        if (prof && has_q) HIP_TRY(hipEventRecord(ev[5], s));
-        if (prof) HIP_TRY(hipEventRecord(ev[2], s));
-        HIP_TRY(launch_frame(L, storage, false, s));
-        HIP_TRY(launch_frame(L, storage, true, s));
-        if (prof) HIP_TRY(hipEventRecord(ev[3], s));
-        if (prof && has_b) HIP_TRY(hipEventRecord(ev[0], s));
+    const bool classes = mode == 1;
+    if (!ss || !ss->ok || classes) {
+        if (classes && has_a) HIP_TRY(hipEventRecord(ev[4], s));
+        HIP_TRY(launch_phase_a(L, storage, s));
+        if (classes && has_a) HIP_TRY(hipEventRecord(ev[5], s));
+        if (classes && has_f) HIP_TRY(hipEventRecord(ev[2], s));
+        HIP_TRY(launch_frame(L, storage, s));
+        if (classes && has_f) HIP_TRY(hipEventRecord(ev[3], s));
+        if (mode && has_b) HIP_TRY(hipEventRecord(ev[0], s));
         HIP_TRY(launch_bulk(L, storage, tx, s));
-        if (prof && has_b) HIP_TRY(hipEventRecord(ev[1], s));
+        if (mode && has_b) HIP_TRY(hipEventRecord(ev[1], s));
     } else {
-        hipStream_t s1 = ss->side[0], s2 = ss->side[1];
         HIP_TRY(hipEventRecord(ss->fork, s));
-        HIP_TRY(hipStreamWaitEvent(s1, ss->fork, 0));
-        HIP_TRY(hipStreamWaitEvent(s2, ss->fork, 0));
-        HIP_TRY(launch_phase_a(L, storage, false, s1));
-        HIP_TRY(hipEventRecord(ss->a_done[0], s1));
-        HIP_TRY(launch_phase_a(L, storage, true, s2));
-        HIP_TRY(hipEventRecord(ss->a_done[1], s2));
-        HIP_TRY(hipStreamWaitEvent(s1, ss->a_done[1], 0));
-        HIP_TRY(hipStreamWaitEvent(s2, ss->a_done[0], 0));
-        HIP_TRY(launch_frame(L, storage, false, s1));
-        HIP_TRY(hipEventRecord(ss->f_done[0], s1));
-        HIP_TRY(launch_frame(L, storage, true, s2));
-        HIP_TRY(hipEventRecord(ss->f_done[1], s2));
+        HIP_TRY(hipStreamWaitEvent(ss->side, ss->fork, 0));
+        HIP_TRY(launch_phase_a(L, storage, ss->side));
+        HIP_TRY(launch_frame(L, storage, ss->side));
+        HIP_TRY(hipEventRecord(ss->done, ss->side));
+        if (mode && has_b) HIP_TRY(hipEventRecord(ev[0], s));
         HIP_TRY(launch_bulk(L, storage, tx, s));
-        HIP_TRY(hipStreamWaitEvent(s, ss->f_done[0], 0));
-        HIP_TRY(hipStreamWaitEvent(s, ss->f_done[1], 0));
+        if (mode && has_b) HIP_TRY(hipEventRecord(ev[1], s));
+        HIP_TRY(hipStreamWaitEvent(s, ss->done, 0));
     }
     HIP_TRY(launch_flip(L, s));
-    if (prof) {
-        if (has_b) prof->pending.push_back({ev[0], ev[1], 0});
-        else { prof->pool.push_back(ev[0]); prof->pool.push_back(ev[1]); }
-        prof->pending.push_back({ev[2], ev[3], 1});
-        if (has_q) prof->pending.push_back({ev[4], ev[5], 2});
-        else { prof->pool.push_back(ev[4]); prof->pool.push_back(ev[5]); }
+    if (mode) {
+        const bool used[3] = {has_b, classes && has_f, classes && has_a};
+        for (int c = 0; c < 3; ++c) {
+            if (used[c]) prof->pending.push_back({ev[2 * c], ev[2 * c + 1], c});
+            else { prof->pool.push_back(ev[2 * c]); prof->pool.push_back(ev[2 * c + 1]); }
+        }
     }
     return LBM_OK;
 }
@@ -407,7 +408,7 @@ lbm_status build_graph(lbm_run *h, int G) {
     LaunchSet L = single_set(h);
     lbm_status st = LBM_OK;
     for (int k = 0; k < G && st == LBM_OK; ++k)
-        st = enqueue_step(L, h->desc.storage, h->launch.bulk_tx, h->stream, &h->ss, nullptr);
+        st = enqueue_step(L, h->desc.storage, h->launch.bulk_tx, h->stream, nullptr, nullptr);
     hipError_t e = hipStreamEndCapture(h->stream, &g);
     if (st != LBM_OK || e != hipSuccess || !g) {
         (void)hipGetLastError();
@@ -479,6 +480,7 @@ lbm_status lbm_create(const lbm_desc *desc, lbm_handle *out) {
         !std::isfinite(d.T0) || !(d.rho0 > 0) || !(d.T0 > 0))
         return fail(LBM_ERR_ARG, "mean state must be finite with rho0 > 0 and T0 > 0");
     if (d.storage < LBM_F64 || d.storage > LBM_F16_DEV) return fail(LBM_ERR_ARG, "unknown storage");
+    if (d.layout != 0 && d.layout != 1) return fail(LBM_ERR_ARG, "unknown layout");
     if (d.storage == LBM_F16_DEV && d.f16_scale != 0.0) {
         int ex;
         double m = std::frexp(d.f16_scale, &ex);
@@ -571,29 +573,33 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux, co
         HIP_TRY(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
         h->stream = h->own_stream;
     }
-    HIP_TRY(h->ss.create());
+    // Side streams only on a stream the run owns; on a caller's stream every kernel class is
+    // enqueued in order on that stream.
+    if (!h->desc.stream) HIP_TRY(h->ss.create());
     const int storage = h->desc.storage;
     const size_t es = elem_size(storage), cs = compute_size(storage);
     h->footprint = footprint_of(R, storage);
     for (int b = 0; b < 2; ++b) {
-        R.f[b] = h->mem.get((size_t)NQ * R.plane * es);
+        R.f[b] = h->mem.get((size_t)R.fsize * es);
         R.U[b] = (double *)h->mem.get(4 * (size_t)R.qplane * sizeof(double));
         if (!R.f[b] || !R.U[b]) { h->mem.release_all(); return fail(LBM_ERR_OOM, "device allocation failed"); }
     }
     R.Q = R.has_q ? h->mem.get((size_t)NQ * R.qplane * cs) : nullptr;
+    R.G = R.ring_n > 0 ? h->mem.get((size_t)NQ * R.rplane * cs) : nullptr;
     h->dd = (RunDev *)h->mem.get(sizeof(RunDev));
     h->dptr = (RunDev **)h->mem.get(sizeof(RunDev *));
     h->dprefix = (int *)h->mem.get(2 * NCLS * sizeof(int));
     h->fbar_d = (double *)h->mem.get(NQ * sizeof(double));
-    if ((R.has_q && !R.Q) || !h->dd || !h->dptr || !h->dprefix || !h->fbar_d) {
+    if ((R.has_q && !R.Q) || (R.ring_n > 0 && !R.G) || !h->dd || !h->dptr || !h->dprefix || !h->fbar_d) {
         h->mem.release_all();
         return fail(LBM_ERR_OOM, "device allocation failed");
     }
     for (int b = 0; b < 2; ++b) {
-        HIP_TRY(hipMemsetAsync(R.f[b], 0, (size_t)NQ * R.plane * es, h->stream));
+        HIP_TRY(hipMemsetAsync(R.f[b], 0, (size_t)R.fsize * es, h->stream));
         HIP_TRY(hipMemsetAsync(R.U[b], 0, 4 * (size_t)R.qplane * sizeof(double), h->stream));
     }
     if (R.Q) HIP_TRY(hipMemsetAsync(R.Q, 0, (size_t)NQ * R.qplane * cs, h->stream));
+    if (R.G) HIP_TRY(hipMemsetAsync(R.G, 0, (size_t)NQ * R.rplane * cs, h->stream));
     R.par = 0; R.step = 0; R.limit = 0;
     set_scale(R, 1.0);
     if (storage == ST_F16 && h->desc.f16_scale > 0) set_scale(R, h->desc.f16_scale);
@@ -647,7 +653,10 @@ lbm_status lbm_step(lbm_handle h, int64_t n) {
     LaunchSet L = single_set(h);
     int64_t left = n;
     const int G = h->launch.graph_steps;
-    if (!h->prof && G > 0 && !h->graph_failed && n >= G) {
+    // Graphs (captured on the run's stream alone) pay off where launches dominate: small grids.
+    // Larger grids step eagerly with the boundary/PML chains on side streams.
+    const bool small = (long long)h->hd.Nx * h->hd.Ny <= GRAPH_MAX_NODES;
+    if (!h->prof && G > 0 && !h->graph_failed && n >= G && (small || !h->ss.ok)) {
         if (!h->graph || h->graph_G != G || h->graph_tx != h->launch.bulk_tx) {
             lbm_status st = build_graph(h, G);
             if (st != LBM_OK) return st;
@@ -681,9 +690,23 @@ lbm_status lbm_synchronize(lbm_handle h) {
     return LBM_OK;
 }
 
+// The moments of the current step re-pull from the previous buffer; ring nodes take the
+// post-boundary populations of that step, recomputed from the previous buffers.
+static lbm_status refresh_targets(lbm_run *h) {
+    if (h->steps > 0 && h->hd.ring_n > 0) {
+        LaunchSet L = single_set(h);
+        HIP_TRY(launch_nrbc(L, h->desc.storage, 1, h->stream));
+    }
+    return LBM_OK;
+}
+
 lbm_status lbm_moments(lbm_handle h, double *rho, double *ux, double *uy, double *T, unsigned flags) {
     if (!h) return fail(LBM_ERR_ARG, "NULL handle");
     if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
+    {
+        lbm_status st = refresh_targets(h);
+        if (st != LBM_OK) return st;
+    }
     const RunDev &R = h->hd;
     const size_t nn = (size_t)R.Nx * R.Ny;
     if (flags & LBM_DEVICE_PTRS) {
@@ -747,6 +770,10 @@ lbm_status lbm_error_norms(lbm_handle h, const double *ref_rho, const double *re
     double *tmp = (double *)h->mem.get((3 * nn + 3 * nb + 3 * (size_t)ly + 3) * sizeof(double));
     if (!tmp) return fail(LBM_ERR_OOM, "device allocation failed");
     double *m = tmp, *refs = tmp + 3 * nn, *part = refs + 3 * nb, *dout = part + 3 * (size_t)ly;
+    {
+        lbm_status st = refresh_targets(h);
+        if (st != LBM_OK) { h->mem.put(tmp); return st; }
+    }
     hipError_t e = launch_moments(h->dd, h->desc.storage, R.Nx, R.Ny, m, m + nn, nullptr, m + 2 * nn, h->stream);
     const double *src[3] = {ref_rho, ref_ux, ref_T};
     for (int k = 0; k < 3 && e == hipSuccess; ++k)
@@ -798,7 +825,8 @@ lbm_status lbm_get_launch(lbm_handle h, lbm_launch *cfg) {
 
 lbm_status lbm_profile(lbm_handle h, int enable) {
     if (!h) return fail(LBM_ERR_ARG, "NULL handle");
-    h->prof = enable != 0;
+    if (enable < 0 || enable > 2) return fail(LBM_ERR_ARG, "profile mode must be 0, 1 or 2");
+    h->prof = enable;
     return LBM_OK;
 }
 
@@ -831,7 +859,7 @@ void lbm_destroy(lbm_handle h) {
 namespace {
 struct CkptHeader {
     char magic[8];
-    int32_t version, Nx, Ny, storage, W, pml[4], bc[4], par;
+    int32_t version, Nx, Ny, storage, W, pml[4], bc[4], par, layout;
     int64_t steps, plane, qplane;
     double tau, rho0, ux0, uy0, T0, sigma_max, scale;
     uint64_t checksum;
@@ -845,7 +873,7 @@ lbm_status lbm_save(lbm_handle h, const char *path) {
     if (st != LBM_OK) return st;
     const RunDev &R = h->hd;
     const int storage = h->desc.storage;
-    size_t fb = (size_t)NQ * R.plane * elem_size(storage);
+    size_t fb = (size_t)R.fsize * elem_size(storage);
     size_t qb = R.has_q ? (size_t)NQ * R.qplane * compute_size(storage) : 0;
     size_t ub = 4 * (size_t)R.qplane * sizeof(double);
     std::vector<char> buf(2 * fb + qb + 2 * ub);
@@ -856,6 +884,7 @@ lbm_status lbm_save(lbm_handle h, const char *path) {
     CkptHeader hdr{};
     std::memcpy(hdr.magic, "LBMPML01", 8);
     hdr.version = 1; hdr.Nx = R.Nx; hdr.Ny = R.Ny; hdr.storage = storage; hdr.W = h->W;
+    hdr.layout = h->desc.layout;
     for (int s = 0; s < 4; ++s) { hdr.pml[s] = h->pml[s]; hdr.bc[s] = h->bc[s]; }
     hdr.par = R.par; hdr.steps = h->steps; hdr.plane = R.plane; hdr.qplane = R.qplane;
     hdr.tau = h->desc.tau; hdr.rho0 = h->desc.rho0; hdr.ux0 = h->desc.ux0; hdr.uy0 = h->desc.uy0;
@@ -883,12 +912,13 @@ lbm_status lbm_load(lbm_handle h, const char *path) {
     RunDev &R = h->hd;
     const int storage = h->desc.storage;
     bool same = hdr.Nx == R.Nx && hdr.Ny == R.Ny && hdr.storage == storage && hdr.W == h->W &&
+                hdr.layout == h->desc.layout &&
                 hdr.plane == R.plane && hdr.qplane == R.qplane && hdr.tau == h->desc.tau &&
                 hdr.rho0 == h->desc.rho0 && hdr.ux0 == h->desc.ux0 && hdr.uy0 == h->desc.uy0 &&
                 hdr.T0 == h->desc.T0 && hdr.sigma_max == h->sigma_max;
     for (int s = 0; s < 4; ++s) same = same && hdr.pml[s] == h->pml[s] && hdr.bc[s] == h->bc[s];
     if (!same) { std::fclose(fp); return fail(LBM_ERR_ARG, "checkpoint configuration differs from the handle's"); }
-    size_t fb = (size_t)NQ * R.plane * elem_size(storage);
+    size_t fb = (size_t)R.fsize * elem_size(storage);
     size_t qb = R.has_q ? (size_t)NQ * R.qplane * compute_size(storage) : 0;
     size_t ub = 4 * (size_t)R.qplane * sizeof(double);
     std::vector<char> buf(2 * fb + qb + 2 * ub);
@@ -991,7 +1021,7 @@ lbm_status lbm_group_create(void *stream, const lbm_allocator *allocator, lbm_gr
         }
         g->stream = g->own_stream;
     }
-    if (g->ss.create() != hipSuccess ||
+    if ((!stream && g->ss.create() != hipSuccess) ||
         hipHostMalloc((void **)&g->hlimits, 4096 * sizeof(long long), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&g->upload_done, hipEventDisableTiming) != hipSuccess) {
         if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
@@ -1057,7 +1087,7 @@ static lbm_status group_rebuild(lbm_group *g) {
     }
     std::vector<RunDev *> ptrs(n);
     std::vector<int> pre(NCLS * (g->cap + 1), 0);
-    int tot[NCLS] = {0, 0, 0, 0, 0};
+    int tot[NCLS] = {0, 0, 0, 0};
     for (size_t k = 0; k < n; ++k) {
         lbm_run *h = g->members[k];
         ptrs[k] = h->dd;

@@ -15,16 +15,20 @@ enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2 };
 // Device descriptor of one run.  Lives in device memory (one per run); kernels receive an
 // array of pointers to descriptors, so a single run and a batch share every kernel.
 //
-// Grid: Nx x Ny nodes, population plane p stored at f[par] + p * plane, row pitch `pitch`.
+// Grid: Nx x Ny nodes; population i of node (x, y) is f[par][i * plane + y * pitch + x].  With
+// the row layout (default) the 37 population rows of one grid row are adjacent (plane = padded
+// row, pitch = 37 padded rows), which keeps the pulls of a tile inside a few MiB of address
+// space; with the plane layout `plane` is a whole padded plane and `pitch` a padded row.
 // Frame: the nodes outside the fast interior rectangle [fx0,fx1) x [fy0,fy1), i.e. a frame of
 // depth gxm/gxp/gym/gyp on the four sides.  Frame nodes are numbered bottom strip, top strip,
 // left strip, right strip (row-major inside each strip); Q and the moment strips U use that
 // numbering, so a frame thread touches its own Q/U entries with unit stride.  The ring is the
 // same construction with depth 3 on characteristic (NRBC) sides only: the boundary nodes that
-// need the FP64 characteristic fill, handled by their own kernel instances.
+// need the FP64 characteristic fill, handled by the first blocks of the boundary launches.
 struct alignas(256) RunDev {
     int Nx, Ny, pitch, storage;
-    long long plane;          // elements per population plane of f
+    long long plane;          // element stride between populations of one node
+    long long fsize;          // elements of one population buffer
     long long qplane;         // elements per component plane of Q and U
     int gxm, gxp, gym, gyp;   // frame depths
     int Wxm, Wxp, Wym, Wyp;   // PML width per side (0 if none)
@@ -38,6 +42,8 @@ struct alignas(256) RunDev {
     void *f[2];
     void *Q;                  // [37][qplane] in the compute type
     double *U[2];             // [4][qplane]: rho, ux, uy, T (absolute values)
+    void *G;                  // [37][rplane] compute type: post-boundary populations of the ring
+    long long rplane;
     int par, pad0;
     long long step, limit;    // a run is active while step < limit
     // constants (double and float copies)
@@ -48,7 +54,9 @@ struct alignas(256) RunDev {
 };
 
 // Launch decomposition of a set of runs: prefix[k] = first block of run k, prefix[n] = total.
-enum Cls { CLS_BULK = 0, CLS_FRAME = 1, CLS_RING = 2, CLS_Q = 3, CLS_QRING = 4, NCLS = 5 };
+// Classes: the interior tiles; the frame launch (ring blocks, then frame blocks); the phase-A
+// launch (ring blocks, then frame blocks if the run has a PML); the ring alone.
+enum Cls { CLS_BULK = 0, CLS_FRAME = 1, CLS_A = 2, CLS_RING = 3, NCLS = 4 };
 struct LaunchSet {
     RunDev *const *runs;      // device array of descriptor pointers
     const int *prefix[NCLS];  // device prefix arrays per class
@@ -60,10 +68,14 @@ constexpr int FRAME_BLOCK = 256;
 
 // Kernel launchers (lbm_kernels.hip).  All enqueue on `s` and return the HIP status of the
 // launch.
-// ring = false: frame nodes off the characteristic ring; ring = true: the ring only.
-hipError_t launch_phase_a(const LaunchSet &L, int storage, bool ring, hipStream_t s);
-hipError_t launch_frame(const LaunchSet &L, int storage, bool ring, hipStream_t s);
+// Phase A: characteristic fill of the ring and PML auxiliary update; frame: phase B (collision)
+// of every frame node, ring included.
+hipError_t launch_phase_a(const LaunchSet &L, int storage, hipStream_t s);
+hipError_t launch_frame(const LaunchSet &L, int storage, hipStream_t s);
 hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, hipStream_t s);
+// Post-boundary populations of every characteristic-boundary ring node into G, from the buffers
+// of the current step (prev = 0) or of the previous one (prev = 1); no Q update.
+hipError_t launch_nrbc(const LaunchSet &L, int storage, int prev, hipStream_t s);
 hipError_t launch_flip(const LaunchSet &L, hipStream_t s);
 hipError_t launch_set_limit(RunDev *run, long long limit, hipStream_t s);
 hipError_t launch_set_limits(RunDev *const *runs, const long long *limits, int n, hipStream_t s);

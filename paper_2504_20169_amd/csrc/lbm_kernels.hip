@@ -147,13 +147,21 @@ __device__ __forceinline__ void ring_xy(CRun &R, int t, int &x, int &y) {
     strip_xy(R.Nx, R.Ny, R.rxm, R.rxp, R.rym, R.ryp, t, x, y);
 }
 
-__device__ __forceinline__ int fidx(CRun &R, int x, int y) {
-    if (y < R.gym) return y * R.Nx + x;
-    if (y >= R.Ny - R.gyp) return (R.gym + y - (R.Ny - R.gyp)) * R.Nx + x;
-    int H = R.Ny - R.gym - R.gyp, base = (R.gym + R.gyp) * R.Nx, yy = y - R.gym;
-    if (x < R.gxm) return base + yy * R.gxm + x;
-    if (x >= R.Nx - R.gxp) return base + H * R.gxm + yy * R.gxp + (x - (R.Nx - R.gxp));
+// Inverse of strip_xy: strip index of (x, y), or -1 outside the strips.
+__device__ __forceinline__ int strip_idx(int Nx, int Ny, int dxm, int dxp, int dym, int dyp, int x, int y) {
+    if (y < dym) return y * Nx + x;
+    if (y >= Ny - dyp) return (dym + y - (Ny - dyp)) * Nx + x;
+    int H = Ny - dym - dyp, base = (dym + dyp) * Nx, yy = y - dym;
+    if (x < dxm) return base + yy * dxm + x;
+    if (x >= Nx - dxp) return base + H * dxm + yy * dxp + (x - (Nx - dxp));
     return -1;
+}
+
+__device__ __forceinline__ int fidx(CRun &R, int x, int y) {
+    return strip_idx(R.Nx, R.Ny, R.gxm, R.gxp, R.gym, R.gyp, x, y);
+}
+__device__ __forceinline__ int ridx(CRun &R, int x, int y) {
+    return strip_idx(R.Nx, R.Ny, R.rxm, R.rxp, R.rym, R.ryp, x, y);
 }
 
 __device__ __forceinline__ bool in_q(CRun &R, int x, int y) {
@@ -369,17 +377,10 @@ __device__ void lodi_add(CRun &R, const GLOBAL double *Uc, int side, int x, int 
     else    { Ut[2] += ny * dUn; Ut[1] += dUt; }
 }
 
-// Non-equilibrium extrapolation: g <- feq(U_tgt) + g(x_f) - feq(U(x_f)).  g holds the pulled
-// populations of x_f (deviation form) on entry.
+// Non-equilibrium extrapolation: g <- feq(U_tgt) + g(x_f) - feq(U(x_f)), in float64.  g holds the
+// pulled populations of x_f (deviation form) on entry.
 template <class C>
-__device__ void nrbc_fill(CRun &R, const GLOBAL double *Uc, int x, int y, int t, C (&g)[NQ]) {
-    const unsigned qp = (unsigned)R.qplane;
-    double Ut[4] = {Uc[t], Uc[qp + t], Uc[2 * qp + t], Uc[3 * qp + t]};
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        bool on = s == XMIN ? x < 3 : s == XMAX ? x >= R.Nx - 3 : s == YMIN ? y < 3 : y >= R.Ny - 3;
-        if (on && R.bc[s] == BC_NRBC) lodi_add(R, Uc, s, x, y, t, Ut);
-    }
+__device__ __forceinline__ void nrbc_fill(CRun &R, const double (&Ut)[4], C (&g)[NQ]) {
     K<double> kd = load_k<double>(R);
     Mom<double> mf;
     if constexpr (std::is_same<C, double>::value) {
@@ -400,23 +401,75 @@ __device__ void nrbc_fill(CRun &R, const GLOBAL double *Uc, int x, int y, int t,
 
 // Pull of a frame node with the boundary fill: periodic axes wrap, open axes pull at
 // x_f = clamp(x, 3, N-4) (eq. zg-bc copies all q populations of x_f to the boundary node).
-template <class S, class C, bool NR>
-__device__ __forceinline__ void gather_general(CRun &R, const GLOBAL S *src, const GLOBAL double *Uc,
-                                               int x, int y, int t, C inv_scale, C (&g)[NQ]) {
-    int xs = R.open_x ? min(max(x, 3), R.Nx - 4) : x;
-    int ys = R.open_y ? min(max(y, 3), R.Ny - 4) : y;
-    const long long plane = R.plane;
-    const int pitch = R.pitch, Nx = R.Nx, Ny = R.Ny;
-    const bool ox = R.open_x, oy = R.open_y;
+// Pull of x_f = clamp(x, 3, N-4) on open axes (eq. zg-bc copies all q populations of x_f to a
+// boundary node; interior frame nodes are their own x_f), with a single periodic wrap on
+// periodic axes (N >= 3): the 7 source-row and 7 source-column offsets are formed once per
+// node, so each population costs one add.
+template <class S, class C>
+__device__ __forceinline__ void gather_clamped(CRun &R, const GLOBAL S *src, int x, int y,
+                                               C inv_scale, C (&g)[NQ]) {
+    const int Nx = R.Nx, Ny = R.Ny;
+    const int xs = R.open_x ? min(max(x, 3), Nx - 4) : x;
+    const int ys = R.open_y ? min(max(y, 3), Ny - 4) : y;
+    const long long pitch = R.pitch, plane = R.plane;
     static_for<0, NQ>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        int sx = xs - ex_of(i), sy = ys - ey_of(i);
-        if (!ox) { while (sx < 0) sx += Nx; while (sx >= Nx) sx -= Nx; }
-        if (!oy) { while (sy < 0) sy += Ny; while (sy >= Ny) sy -= Ny; }
-        const GLOBAL S *base = src + (long long)i * plane;
-        g[i] = cvt_in(*at(base, (unsigned)(sy * pitch + sx) * (unsigned)sizeof(S)), inv_scale);
+        // identical shifts across populations fold to 7 row and 7 column offsets per node
+        int sy = ys - ey_of(i), sx = xs - ex_of(i);
+        if constexpr (ey_of(i) > 0) sy += sy < 0 ? Ny : 0;
+        if constexpr (ey_of(i) < 0) sy -= sy >= Ny ? Ny : 0;
+        if constexpr (ex_of(i) > 0) sx += sx < 0 ? Nx : 0;
+        if constexpr (ex_of(i) < 0) sx -= sx >= Nx ? Nx : 0;
+        g[i] = cvt_in(src[(long long)i * plane + sy * pitch + sx], inv_scale);
     });
-    if constexpr (NR) nrbc_fill<C>(R, Uc, x, y, t, g);
+}
+
+// Blocks of a run's boundary launches: the characteristic ring first (ring numbering), then the
+// frame (frame numbering).
+__device__ __forceinline__ int ring_blocks(CRun &R) { return (R.ring_n + FRAME_BLOCK - 1) / FRAME_BLOCK; }
+
+// Ring node of characteristic sides: U_tgt = U(x_b) of the last completed level plus the LODI
+// increment of each NRBC side the node lies on (corners add both normals), then the clamped pull
+// of x_f and the non-equilibrium extrapolation.  The result is left in g and stored to G (ring
+// index tt) for the frame kernel.  prev = 1 recomputes those of the last completed step.
+template <class S, class C>
+__device__ __forceinline__ void nrbc_node(CRun &R, int tt, int x, int y, int t, int prev, C inv_scale,
+                                          C (&g)[NQ]) {
+    const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par ^ prev];
+    const unsigned qp = (unsigned)R.qplane;
+    double Ut[4] = {Uc[t], Uc[qp + t], Uc[2 * qp + t], Uc[3 * qp + t]};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        bool on = s == XMIN ? x < 3 : s == XMAX ? x >= R.Nx - 3 : s == YMIN ? y < 3 : y >= R.Ny - 3;
+        if (on && R.bc[s] == BC_NRBC) lodi_add(R, Uc, s, x, y, t, Ut);
+    }
+    gather_clamped<S, C>(R, (const GLOBAL S *)R.f[R.par ^ prev], x, y, inv_scale, g);
+    nrbc_fill<C>(R, Ut, g);
+    GLOBAL C *G = (GLOBAL C *)R.G;
+    const unsigned rp = (unsigned)R.rplane;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) G[i * rp + tt] = g[i];
+}
+
+// Post-boundary populations of every ring node into G, without the rest of phase A (used to
+// refresh G for the moments of the last completed step, prev = 1).
+template <class S>
+__global__ __launch_bounds__(256) void k_nrbc(RunDev *const *__restrict__ runs,
+                                              const int *__restrict__ prefix, int nruns, int prev) {
+    using C = typename Traits<S>::C;
+    const int b = blockIdx.x;
+    const int j = find_run(prefix, nruns, b);
+    CRun &R = run_of(runs, j);
+    if (prev == 0 && R.step >= R.limit) return;
+    const int tt = (b - ((const CONSTANT int *)prefix)[j]) * FRAME_BLOCK + (int)threadIdx.x;
+    if (tt >= R.ring_n) return;
+    int x, y;
+    ring_xy(R, tt, x, y);
+    const int t = fidx(R, x, y);
+    if (t < 0) return;
+    const K<C> k = load_k<C>(R);
+    C g[NQ];
+    nrbc_node<S, C>(R, tt, x, y, t, prev, k.inv_scale, g);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -442,11 +495,15 @@ __global__ __launch_bounds__(256) void k_bulk(RunDev *const *__restrict__ runs,
     GLOBAL S *dst = (GLOBAL S *)R.f[R.par ^ 1];
     const long long plane = R.plane;
     const int pitch = R.pitch;
-    const unsigned off = (unsigned)(y * pitch + x) * (unsigned)sizeof(S);
+    // uniform base at the tile's first row; per-lane 32-bit byte offset inside the tile
+    const int y0 = R.fy0 + ty * TY;
+    const GLOBAL S *src0 = src + (long long)y0 * pitch;
+    GLOBAL S *dst0 = dst + (long long)y0 * pitch;
+    const unsigned off = (unsigned)((y - y0) * pitch + x) * (unsigned)sizeof(S);
     C g[NQ];
     static_for<0, NQ>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        const GLOBAL S *base = src + ((long long)i * plane - (ey_of(i) * pitch + ex_of(i)));
+        const GLOBAL S *base = src0 + ((long long)i * plane - (ey_of(i) * pitch + ex_of(i)));
         g[i] = cvt_in(*at(base, off), k.inv_scale);
     });
     Mom<C> m = moments<C>(g, k);
@@ -454,11 +511,106 @@ __global__ __launch_bounds__(256) void k_bulk(RunDev *const *__restrict__ runs,
     for_each_feq<C>(q, R, k, [&](auto ic, C fe) {
         constexpr int i = decltype(ic)::value;
         C out = g[i] + k.omega * (fe - g[i]);
-        *at(dst + (long long)i * plane, off) = cvt_out(out, k.scale, (S *)nullptr);
+        *at(dst0 + (long long)i * plane, off) = cvt_out(out, k.scale, (S *)nullptr);
     });
 }
 
-template <class S, bool NR>
+// Collision of a frame node (frame index t) from its post-stream, post-boundary populations g:
+// BGK plus, on PML nodes, -sigma (e.grad Q + 2 fhat + sigma Q) (eq. PMLCOLL) with grad Q central
+// and one-sided at the outermost layer of an open axis (eqs. FD-dx-*); the moments go to U.
+// Every load (Q at the node and its neighbours) is issued before the first store.
+template <class S, class C>
+__device__ __forceinline__ void frame_collide(CRun &R, const K<C> &k, const C (&g)[NQ], int x, int y,
+                                              int t) {
+    GLOBAL S *dst = (GLOBAL S *)R.f[R.par ^ 1];
+    GLOBAL double *Un = (GLOBAL double *)R.U[R.par ^ 1];
+    const long long plane = R.plane;
+    const unsigned qp = (unsigned)R.qplane;
+    GLOBAL S *dnode = dst + (long long)y * R.pitch + x;
+    if (R.has_q) {
+        const GLOBAL C *Q = (const GLOBAL C *)R.Q;
+        // d/dalpha Q = cs*Q(x) + c0*Q(j0) + c1*Q(j1): central 0, 1/2, -1/2 at x+1, x-1;
+        // one-sided at the outermost layer (outward normal s): s*(3/2, -2, 1/2) at x, x-s, x-2s
+        int jx0, jx1, jy0, jy1;
+        C cxs, cx0, cx1, cys, cy0, cy1;
+        if (R.open_x && x == 0) {
+            jx0 = fidx(R, 1, y); jx1 = fidx(R, 2, y);
+            cxs = C(-1.5); cx0 = C(2); cx1 = C(-0.5);
+        } else if (R.open_x && x == R.Nx - 1) {
+            jx0 = fidx(R, x - 1, y); jx1 = fidx(R, x - 2, y);
+            cxs = C(1.5); cx0 = C(-2); cx1 = C(0.5);
+        } else {
+            int xp = x + 1, xm = x - 1;
+            if (xp >= R.Nx) xp -= R.Nx;
+            if (xm < 0) xm += R.Nx;
+            jx0 = fidx(R, xp, y); jx1 = fidx(R, xm, y);
+            cxs = C(0); cx0 = C(0.5); cx1 = C(-0.5);
+        }
+        if (R.open_y && y == 0) {
+            jy0 = fidx(R, x, 1); jy1 = fidx(R, x, 2);
+            cys = C(-1.5); cy0 = C(2); cy1 = C(-0.5);
+        } else if (R.open_y && y == R.Ny - 1) {
+            jy0 = fidx(R, x, y - 1); jy1 = fidx(R, x, y - 2);
+            cys = C(1.5); cy0 = C(-2); cy1 = C(0.5);
+        } else {
+            int yp = y + 1, ym = y - 1;
+            if (yp >= R.Ny) yp -= R.Ny;
+            if (ym < 0) ym += R.Ny;
+            jy0 = fidx(R, x, yp); jy1 = fidx(R, x, ym);
+            cys = C(0); cy0 = C(0.5); cy1 = C(-0.5);
+        }
+        // per-lane byte offsets into each Q plane (uniform plane bases + one offset per point)
+        const unsigned ox0 = (unsigned)(jx0 < 0 ? t : jx0) * (unsigned)sizeof(C);
+        const unsigned ox1 = (unsigned)(jx1 < 0 ? t : jx1) * (unsigned)sizeof(C);
+        const unsigned oy0 = (unsigned)(jy0 < 0 ? t : jy0) * (unsigned)sizeof(C);
+        const unsigned oy1 = (unsigned)(jy1 < 0 ? t : jy1) * (unsigned)sizeof(C);
+        const unsigned ot = (unsigned)t * (unsigned)sizeof(C);
+        // sigma = 0 off the layer: the PML term is then -0 * (finite) and leaves BGK's bits
+        const C s = (C)(R.W > 0 ? sigma_at(R, x, y) : 0.0);
+        // P_i = e_i.grad Q_i + sigma Q_i, gathered before any store
+        C P[NQ];
+        static_for<0, NQ>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const GLOBAL C *Qi = Q + (long long)i * qp;
+            const C Qt = *at(Qi, ot);
+            C gq = C(0);
+            if constexpr (ex_of(i) != 0)
+                gq += C(ex_of(i)) * (cxs * Qt + cx0 * *at(Qi, ox0) + cx1 * *at(Qi, ox1));
+            if constexpr (ey_of(i) != 0)
+                gq += C(ey_of(i)) * (cys * Qt + cy0 * *at(Qi, oy0) + cy1 * *at(Qi, oy1));
+            P[i] = gq + s * Qt;
+        });
+        Mom<C> m = moments<C>(g, k);
+        Eq<C> q = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
+        for_each_feq<C>(q, R, k, [&](auto ic, C fe) {
+            constexpr int i = decltype(ic)::value;
+            C out = g[i] + k.omega * (fe - g[i]);
+            out = out - s * (P[i] + C(2) * fe);
+            dnode[(long long)i * plane] = cvt_out(out, k.scale, (S *)nullptr);
+        });
+        Un[t] = R.rho0 + (double)m.drho;
+        Un[qp + t] = R.u0x + (double)m.dux;
+        Un[2 * qp + t] = R.u0y + (double)m.duy;
+        Un[3 * qp + t] = R.T0 + (double)m.dT;
+    } else {
+        Mom<C> m = moments<C>(g, k);
+        Eq<C> q = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
+        for_each_feq<C>(q, R, k, [&](auto ic, C fe) {
+            constexpr int i = decltype(ic)::value;
+            C out = g[i] + k.omega * (fe - g[i]);
+            dnode[(long long)i * plane] = cvt_out(out, k.scale, (S *)nullptr);
+        });
+        Un[t] = R.rho0 + (double)m.drho;
+        Un[qp + t] = R.u0x + (double)m.dux;
+        Un[2 * qp + t] = R.u0y + (double)m.duy;
+        Un[3 * qp + t] = R.T0 + (double)m.dT;
+    }
+}
+
+// Phase B of a step on the frame: ring blocks take the post-boundary populations phase A stored
+// in G; frame blocks pull (periodic wrap, or eq. zg-bc's copy of x_f = clamp(x, 3, N-4) on open
+// axes) and skip ring nodes.
+template <class S>
 __global__ __launch_bounds__(256) void k_frame(RunDev *const *__restrict__ runs,
                                                const int *__restrict__ prefix, int nruns) {
     using C = typename Traits<S>::C;
@@ -466,132 +618,91 @@ __global__ __launch_bounds__(256) void k_frame(RunDev *const *__restrict__ runs,
     const int j = find_run(prefix, nruns, b);
     CRun &R = run_of(runs, j);
     if (R.step >= R.limit) return;
-    const int tt = (b - ((const CONSTANT int *)prefix)[j]) * FRAME_BLOCK + (int)threadIdx.x;
+    const int tb = b - ((const CONSTANT int *)prefix)[j];
+    const int rb = ring_blocks(R);
+    const K<C> k = load_k<C>(R);
     int x, y, t;
-    if constexpr (NR) {
+    C g[NQ];
+    if (tb < rb) {
+        const int tt = tb * FRAME_BLOCK + (int)threadIdx.x;
         if (tt >= R.ring_n) return;
         ring_xy(R, tt, x, y);
         t = fidx(R, x, y);
         if (t < 0) return;
+        const GLOBAL C *G = (const GLOBAL C *)R.G;
+        const unsigned rp = (unsigned)R.rplane;
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) g[i] = G[i * rp + tt];
     } else {
+        const int tt = (tb - rb) * FRAME_BLOCK + (int)threadIdx.x;
         if (tt >= R.frame_n) return;
         frame_xy(R, tt, x, y);
         if (in_ring(R, x, y)) return;
         t = tt;
+        gather_clamped<S, C>(R, (const GLOBAL S *)R.f[R.par], x, y, k.inv_scale, g);
     }
-    const K<C> k = load_k<C>(R);
-    const GLOBAL S *src = (const GLOBAL S *)R.f[R.par];
-    GLOBAL S *dst = (GLOBAL S *)R.f[R.par ^ 1];
-    const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par];
-    GLOBAL double *Un = (GLOBAL double *)R.U[R.par ^ 1];
-    const long long plane = R.plane;
-    const unsigned qp = (unsigned)R.qplane;
-    C g[NQ];
-    gather_general<S, C, NR>(R, src, Uc, x, y, t, k.inv_scale, g);
-    Mom<C> m = moments<C>(g, k);
-    Un[t] = R.rho0 + (double)m.drho;
-    Un[qp + t] = R.u0x + (double)m.dux;
-    Un[2 * qp + t] = R.u0y + (double)m.duy;
-    Un[3 * qp + t] = R.T0 + (double)m.dT;
-    Eq<C> q = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
-    const unsigned off = (unsigned)(y * R.pitch + x) * (unsigned)sizeof(S);
-    const double sg = R.W > 0 ? sigma_at(R, x, y) : 0.0;
-    if (sg > 0.0) {
-        // grad Q: central, one-sided at the outermost layer of an open axis (eqs. FD-dx-*)
-        const GLOBAL C *Q = (const GLOBAL C *)R.Q;
-        int jx[3], jy[3];
-        C cx[3], cy[3];
-        if (R.open_x && x == 0) {
-            jx[0] = t; jx[1] = fidx(R, 1, y); jx[2] = fidx(R, 2, y);
-            cx[0] = C(-1.5); cx[1] = C(2); cx[2] = C(-0.5);
-        } else if (R.open_x && x == R.Nx - 1) {
-            jx[0] = t; jx[1] = fidx(R, x - 1, y); jx[2] = fidx(R, x - 2, y);
-            cx[0] = C(1.5); cx[1] = C(-2); cx[2] = C(0.5);
-        } else {
-            int xp = x + 1, xm = x - 1;
-            if (xp >= R.Nx) xp -= R.Nx;
-            if (xm < 0) xm += R.Nx;
-            jx[0] = fidx(R, xp, y); jx[1] = fidx(R, xm, y); jx[2] = t;
-            cx[0] = C(0.5); cx[1] = C(-0.5); cx[2] = C(0);
-        }
-        if (R.open_y && y == 0) {
-            jy[0] = t; jy[1] = fidx(R, x, 1); jy[2] = fidx(R, x, 2);
-            cy[0] = C(-1.5); cy[1] = C(2); cy[2] = C(-0.5);
-        } else if (R.open_y && y == R.Ny - 1) {
-            jy[0] = t; jy[1] = fidx(R, x, y - 1); jy[2] = fidx(R, x, y - 2);
-            cy[0] = C(1.5); cy[1] = C(-2); cy[2] = C(0.5);
-        } else {
-            int yp = y + 1, ym = y - 1;
-            if (yp >= R.Ny) yp -= R.Ny;
-            if (ym < 0) ym += R.Ny;
-            jy[0] = fidx(R, x, yp); jy[1] = fidx(R, x, ym); jy[2] = t;
-            cy[0] = C(0.5); cy[1] = C(-0.5); cy[2] = C(0);
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (jx[a] < 0) jx[a] = t;
-            if (jy[a] < 0) jy[a] = t;
-        }
-        const C s = (C)sg;
-        for_each_feq<C>(q, R, k, [&](auto ic, C fe) {
-            constexpr int i = decltype(ic)::value;
-            const GLOBAL C *Qi = Q + (long long)i * qp;
-            C out = g[i] + k.omega * (fe - g[i]);
-            C gq = C(0);
-            if constexpr (ex_of(i) != 0)
-                gq += C(ex_of(i)) * (cx[0] * Qi[jx[0]] + cx[1] * Qi[jx[1]] + cx[2] * Qi[jx[2]]);
-            if constexpr (ey_of(i) != 0)
-                gq += C(ey_of(i)) * (cy[0] * Qi[jy[0]] + cy[1] * Qi[jy[1]] + cy[2] * Qi[jy[2]]);
-            out = out - s * (gq + C(2) * fe + s * Qi[t]);
-            *at(dst + (long long)i * plane, off) = cvt_out(out, k.scale, (S *)nullptr);
-        });
-    } else {
-        for_each_feq<C>(q, R, k, [&](auto ic, C fe) {
-            constexpr int i = decltype(ic)::value;
-            C out = g[i] + k.omega * (fe - g[i]);
-            *at(dst + (long long)i * plane, off) = cvt_out(out, k.scale, (S *)nullptr);
-        });
-    }
+    frame_collide<S, C>(R, k, g, x, y, t);
 }
 
-template <class S, bool NR>
+// PML auxiliary update Q += (fhat^n + fhat^{n+1}) / 2 at frame node t (eq. PMLQ, trapezoid rule),
+// fhat^n from the moment strip of the last level, fhat^{n+1} from g.  Loads before stores.
+template <class C>
+__device__ __forceinline__ void q_update(CRun &R, const K<C> &k, const C (&g)[NQ], int t) {
+    const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par];
+    const unsigned qp = (unsigned)R.qplane;
+    GLOBAL C *Q = (GLOBAL C *)R.Q;
+    const double r0 = Uc[t], ux0 = Uc[qp + t], uy0 = Uc[2 * qp + t], T0 = Uc[3 * qp + t];
+    Mom<C> m = moments<C>(g, k);
+    // g is dead from here: Q's loads (uniform plane bases, one 32-bit lane offset) take its
+    // registers; the scheduling barrier keeps them from being hoisted above the moments
+    __builtin_amdgcn_sched_barrier(0);
+    const unsigned ot = (unsigned)t * (unsigned)sizeof(C);
+    C Qv[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) Qv[i] = *at(Q + (long long)i * qp, ot);
+    Eq<C> q1 = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
+    Eq<C> q0 = eq_coef<C>((C)(r0 - R.rho0), (C)(ux0 - R.u0x), (C)(uy0 - R.u0y), (C)(T0 - R.T0), k);
+    for_each_feq2<C>(q1, q0, R, k, [&](auto ic, C fe1, C fe0) {
+        constexpr int i = decltype(ic)::value;
+        *at(Q + (long long)i * qp, ot) = Qv[i] + C(0.5) * (fe0 + fe1);
+    });
+}
+
+// Phase A of a step: ring blocks form the characteristic fill of the ring (into G) and, on PML
+// nodes, update Q from it; frame blocks update Q of the PML nodes off the ring from their pull.
+template <class S>
 __global__ __launch_bounds__(256) void k_phase_a(RunDev *const *__restrict__ runs,
                                                  const int *__restrict__ prefix, int nruns) {
     using C = typename Traits<S>::C;
     const int b = blockIdx.x;
     const int j = find_run(prefix, nruns, b);
     CRun &R = run_of(runs, j);
-    if (R.step >= R.limit || !R.has_q) return;
-    const int tt = (b - ((const CONSTANT int *)prefix)[j]) * FRAME_BLOCK + (int)threadIdx.x;
+    if (R.step >= R.limit) return;
+    const int tb = b - ((const CONSTANT int *)prefix)[j];
+    const int rb = ring_blocks(R);
+    const K<C> k = load_k<C>(R);
     int x, y, t;
-    if constexpr (NR) {
+    C g[NQ];
+    if (tb < rb) {
+        const int tt = tb * FRAME_BLOCK + (int)threadIdx.x;
         if (tt >= R.ring_n) return;
         ring_xy(R, tt, x, y);
         t = fidx(R, x, y);
         if (t < 0) return;
+        nrbc_node<S, C>(R, tt, x, y, t, 0, k.inv_scale, g);
+        if (!R.has_q || !in_q(R, x, y)) return;
+        // keep the fill and the update apart: interleaved, their FP64 temporaries exceed the
+        // register file
+        __builtin_amdgcn_sched_barrier(0);
     } else {
-        if (tt >= R.frame_n) return;
+        const int tt = (tb - rb) * FRAME_BLOCK + (int)threadIdx.x;
+        if (!R.has_q || tt >= R.frame_n) return;
         frame_xy(R, tt, x, y);
-        if (in_ring(R, x, y)) return;
+        if (in_ring(R, x, y) || !in_q(R, x, y)) return;
         t = tt;
+        gather_clamped<S, C>(R, (const GLOBAL S *)R.f[R.par], x, y, k.inv_scale, g);
     }
-    if (!in_q(R, x, y)) return;
-    const K<C> k = load_k<C>(R);
-    const GLOBAL S *src = (const GLOBAL S *)R.f[R.par];
-    const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par];
-    const unsigned qp = (unsigned)R.qplane;
-    C g[NQ];
-    gather_general<S, C, NR>(R, src, Uc, x, y, t, k.inv_scale, g);
-    Mom<C> m = moments<C>(g, k);
-    Eq<C> q1 = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
-    Eq<C> q0 = eq_coef<C>((C)(Uc[t] - R.rho0), (C)(Uc[qp + t] - R.u0x), (C)(Uc[2 * qp + t] - R.u0y),
-                          (C)(Uc[3 * qp + t] - R.T0), k);
-    GLOBAL C *Q = (GLOBAL C *)R.Q;
-    for_each_feq2<C>(q1, q0, R, k, [&](auto ic, C fe1, C fe0) {
-        constexpr int i = decltype(ic)::value;
-        GLOBAL C *Qi = Q + (long long)i * qp + t;
-        *Qi = *Qi + C(0.5) * (fe0 + fe1);
-    });
+    q_update<C>(R, k, g, t);
 }
 
 __global__ void k_flip(RunDev *const *runs, int nruns) {
@@ -680,11 +791,15 @@ __global__ __launch_bounds__(256) void k_moments(RunDev *Rw, double *rho, double
 #pragma unroll
         for (int i = 0; i < NQ; ++i) g[i] = cvt_in(src[(long long)i * R.plane + idx], k.inv_scale);
     } else {
-        int t = fidx(R, x, y);
         const GLOBAL S *src = (const GLOBAL S *)R.f[R.par ^ 1];
-        const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par ^ 1];
-        if (in_ring(R, x, y)) gather_general<S, C, true>(R, src, Uc, x, y, t < 0 ? 0 : t, k.inv_scale, g);
-        else gather_general<S, C, false>(R, src, Uc, x, y, t < 0 ? 0 : t, k.inv_scale, g);
+        if (in_ring(R, x, y)) {   // ring: G, refreshed by the caller for this level
+            const GLOBAL C *G = (const GLOBAL C *)R.G;
+            const unsigned rp = (unsigned)R.rplane, r = (unsigned)ridx(R, x, y);
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) g[i] = G[i * rp + r];
+        } else {
+            gather_clamped<S, C>(R, src, x, y, k.inv_scale, g);
+        }
     }
     Mom<C> m = moments<C>(g, k);
     if (rho) rho[n] = R.rho0 + (double)m.drho;
@@ -795,23 +910,17 @@ __global__ __launch_bounds__(256) void k_err_final(const double *partials, int n
 
 static inline int blocks_for(long long n) { return (int)((n + 255) / 256); }
 
-hipError_t launch_phase_a(const LaunchSet &L, int storage, bool ring, hipStream_t s) {
-    if (!ring && L.blocks[CLS_Q] > 0)
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a<S, false>), dim3(L.blocks[CLS_Q]), dim3(256), 0, s,
-                                                 L.runs, L.prefix[CLS_Q], L.nruns));
-    if (ring && L.blocks[CLS_QRING] > 0)
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a<S, true>), dim3(L.blocks[CLS_QRING]), dim3(256), 0,
-                                                 s, L.runs, L.prefix[CLS_QRING], L.nruns));
+hipError_t launch_phase_a(const LaunchSet &L, int storage, hipStream_t s) {
+    if (L.blocks[CLS_A] > 0)
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a<S>), dim3(L.blocks[CLS_A]), dim3(256), 0, s,
+                                                 L.runs, L.prefix[CLS_A], L.nruns));
     return hipGetLastError();
 }
 
-hipError_t launch_frame(const LaunchSet &L, int storage, bool ring, hipStream_t s) {
-    if (!ring && L.blocks[CLS_FRAME] > 0)
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_frame<S, false>), dim3(L.blocks[CLS_FRAME]), dim3(256), 0, s,
+hipError_t launch_frame(const LaunchSet &L, int storage, hipStream_t s) {
+    if (L.blocks[CLS_FRAME] > 0)
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_frame<S>), dim3(L.blocks[CLS_FRAME]), dim3(256), 0, s,
                                                  L.runs, L.prefix[CLS_FRAME], L.nruns));
-    if (ring && L.blocks[CLS_RING] > 0)
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_frame<S, true>), dim3(L.blocks[CLS_RING]), dim3(256), 0, s,
-                                                 L.runs, L.prefix[CLS_RING], L.nruns));
     return hipGetLastError();
 }
 
@@ -830,6 +939,13 @@ hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, hipStream_t s) {
         LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 256>), dim3(nb), dim3(256), 0, s, L.runs, pre, L.nruns));
         break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_nrbc(const LaunchSet &L, int storage, int prev, hipStream_t s) {
+    if (L.blocks[CLS_RING] > 0)
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_nrbc<S>), dim3(L.blocks[CLS_RING]), dim3(256), 0, s,
+                                                 L.runs, L.prefix[CLS_RING], L.nruns, prev));
     return hipGetLastError();
 }
 

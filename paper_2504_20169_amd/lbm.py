@@ -50,7 +50,7 @@ class lbm_desc(ctypes.Structure):
                 ("rho0", ctypes.c_double), ("ux0", ctypes.c_double), ("uy0", ctypes.c_double),
                 ("T0", ctypes.c_double), ("storage", ctypes.c_int32),
                 ("f16_scale", ctypes.c_double), ("allocator", ctypes.POINTER(lbm_allocator)),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("layout", ctypes.c_int32)]
 
 
 class lbm_launch(ctypes.Structure):
@@ -182,7 +182,7 @@ class Run:
     """One simulation handle (create -> set_pml / set_bc -> init -> step ...)."""
 
     def __init__(self, nx, ny, tau=0.8, rho0=1.0, ux0=0.0, uy0=0.0, T0=1.0, storage="f64",
-                 f16_scale=0.0, stream=None, allocator=None):
+                 f16_scale=0.0, stream=None, allocator=None, layout=0):
         lib = load()
         self._lib = lib
         self._alloc = allocator
@@ -190,7 +190,7 @@ class Run:
                      float(T0), STORAGE[storage] if isinstance(storage, str) else int(storage),
                      float(f16_scale),
                      ctypes.pointer(allocator) if allocator is not None else None,
-                     _stream_ptr(stream))
+                     _stream_ptr(stream), int(layout))
         h = ctypes.c_void_p()
         _check(lib.lbm_create(ctypes.byref(d), ctypes.byref(h)))
         self.h = h
@@ -297,8 +297,10 @@ class Run:
                                       cache_path.encode() if cache_path else None, ctypes.byref(c)))
         return dict(bulk_tx=c.bulk_tx, bulk_ty=c.bulk_ty, graph_steps=c.graph_steps)
 
-    def profile(self, enable=True):
-        _check(self._lib.lbm_profile(self.h, 1 if enable else 0))
+    def profile(self, mode=1):
+        """Event timing: 1 (or True) kernel classes in order, 2 bulk kernel in the normal
+        schedule, 0 (or False) off."""
+        _check(self._lib.lbm_profile(self.h, int(mode)))
 
     def profile_read(self, reset=False):
         ms = np.zeros(3)

@@ -143,6 +143,30 @@ def test_tile_shapes_and_graphs_bitwise_identical():
         assert np.array_equal(outs[0], o)
 
 
+def test_profile_modes_count_launches_and_keep_bits():
+    """Event timing in either mode changes the launch schedule, never the result."""
+    F = wl.noisy_state(150, 140, 3, 1.0, 0.05, 0.0, 1.0)
+    outs = []
+    for mode in (0, 1, 2):
+        r = lbm.Run(134, 124, 0.8, 1.0, 0.05, 0.0, 1.0)
+        r.set_bc(15, "nrbc")
+        r.set_pml(15, 8, 0.05)
+        r.set_launch(graph_steps=8)
+        r.init(*F.as_tuple())
+        r.profile(mode)
+        r.step(23)
+        ms, n = r.profile_read(reset=True)
+        expect = {0: [0, 0, 0], 1: [23, 23, 23], 2: [23, 0, 0]}[mode]
+        assert list(n) == expect, (mode, n)
+        assert all(m > 0 for m, c in zip(ms, n) if c)
+        with pytest.raises(lbm.LbmError):
+            r.profile(3)
+        outs.append(r.populations())
+        r.close()
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+
+
 def test_conservation_on_gpu():
     e, w, rr = lbm.lbm_velocities()
     xi = rr * e.astype(float)
@@ -217,3 +241,54 @@ def test_full_size_grids_in_bench_launch(oracle_mod, perm, which):
     err = rel_errors(g, o, perm, with_f=(which == "vortex_1088"))
     say(which, err)
     _assert_parity(err)
+
+
+def test_torch_stream_and_allocator_interop():
+    """Device memory from PyTorch's caching allocator and work on a PyTorch stream: same bits
+    as the library's own stream and hipMalloc; moments can land in torch tensors."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("PyTorch in this process sees no HIP device")
+    F = wl.noisy_state(60, 56, 12, 1.0, 0.05, 0.0, 1.0)
+    outs = []
+    for use_torch in (False, True):
+        kw = dict(stream=torch.cuda.Stream(), allocator=lbm.torch_allocator()) if use_torch else {}
+        r = lbm.Run(48, 44, 0.8, 1.0, 0.05, 0.0, 1.0, **kw)
+        r.set_bc(15, "nrbc")
+        r.set_pml(15, 6, 0.05)
+        r.init(*F.as_tuple())
+        r.step(70)
+        outs.append(r.populations())
+        if use_torch:
+            rho = torch.empty((56, 60), dtype=torch.float64, device="cuda")
+            r.moments_device(rho=rho.data_ptr())
+            r.synchronize()
+            assert np.array_equal(rho.cpu().numpy(), r.moments()[0])
+        r.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("storage", ["f64", "f16"])
+def test_population_layouts_bitwise_identical(oracle_mod, perm, storage):
+    """The row-interleaved layout (default) and one plane per velocity give the same bits; the
+    row layout also matches the oracle."""
+    mean = (1.0, 0.05, 0.0, 1.0)
+    F = wl.noisy_state(86, 74, 14, *mean)
+    outs = []
+    for layout in (0, 1):
+        r = lbm.Run(70, 58, 0.8, *mean, storage=storage, layout=layout)
+        r.set_bc(15, "nrbc")
+        r.set_pml(15, 8, 0.05)
+        r.init(*F.as_tuple())
+        r.step(45)
+        outs.append((r.populations(), r.moments()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    if storage == "f64":
+        o = oracle_mod.OracleRun(70, 58, 0.8, *mean)
+        o.set_bc(15, 2)
+        o.set_pml(15, 8, 0.05)
+        o.init(*F.as_tuple())
+        o.step(45)
+        mo = o.moments()
+        assert max(np.abs(a - b).max() for a, b in zip(outs[0][1], mo)) < 1e-12
