@@ -33,10 +33,12 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_run(lbm, wl, storage, stream, alloc, L, W, sigma, mach, bc, layout=0):
+def make_run(lbm, wl, storage, stream, alloc, L, W, sigma, mach, bc, layout=0, bulk_tx=64,
+             overlap=0):
     spec = wl.vortex_pulse(L=L, W=W, sigma_max=sigma, mach=mach, bc=bc)
     r = lbm.Run(L, L, 0.8, 1.0, mach, 0.0, 1.0, storage=storage, stream=stream, allocator=alloc,
                 layout=layout)
+    r.set_launch(bulk_tx=bulk_tx, overlap=overlap)
     r.set_bc(lbm.LBM_ALL, bc)
     if W:
         r.set_pml(lbm.LBM_ALL, W, sigma)
@@ -45,9 +47,9 @@ def make_run(lbm, wl, storage, stream, alloc, L, W, sigma, mach, bc, layout=0):
 
 
 def time_run(torch, r, steps, warmup, mode):
-    """Time `steps` steps after `warmup`.  mode 2: the normal schedule (boundary/PML chain on a
-    side stream beside the bulk kernel) with HIP events around each bulk launch on its stream.
-    mode 1: the kernel classes in order on the run's stream, events around each class."""
+    """Time `steps` steps after `warmup`.  mode 2: the configured schedule (in order, or with
+    the boundary/PML chain on a side stream beside the bulk kernel) with HIP events around each
+    bulk launch on its stream.  mode 1: the kernel classes in order, events around each class."""
     r.profile(0)
     r.step(warmup)
     r.synchronize()
@@ -103,6 +105,9 @@ def main():
     ap.add_argument("--bc", default="nrbc")
     ap.add_argument("--storages", default="f64,f32,f16")
     ap.add_argument("--layout", type=int, default=0, help="0: row-interleaved, 1: plane per velocity")
+    ap.add_argument("--bulk-tx", type=int, default=64, help="bulk tile width (64, 128 or 256)")
+    ap.add_argument("--overlap", type=int, default=0,
+                    help="1: boundary/PML chain on a side stream beside the bulk kernel")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--prof-steps", type=int, default=500,
@@ -112,6 +117,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-scale", type=float, default=0.1,
                     help="multiplier on the trace's step counts (1000-20000)")
+    ap.add_argument("--no-copy-bw", dest="copy_bw", action="store_false",
+                    help="skip timing a plain 2 GiB device copy (attainable HBM bandwidth)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -130,8 +137,8 @@ def main():
         sys.exit(3)
     lbm.load()
     dev = torch.cuda.get_device_properties(0)
-    # Runs own their stream (the library forks the boundary/PML chains onto side streams beside
-    # the bulk kernel) and take device memory from hipMalloc.
+    # Runs own their stream (so --overlap 1 can fork the boundary/PML chain onto a side stream)
+    # and take device memory from hipMalloc.
     stream = None
     alloc = None
 
@@ -143,11 +150,27 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
+    # attainable HBM bandwidth on this device: a plain 2 GiB device copy (read + write bytes)
+    copy_gbs = None
+    if args.copy_bw:
+        n = 1 << 31
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2.0 * n * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del a, b
+
     results = {}
     for storage in args.storages.split(","):
         _log("bench: storage", storage)
         r, spec = make_run(lbm, wl, storage, stream, alloc, args.L, args.W, args.sigma,
-                           args.mach, args.bc, args.layout)
+                           args.mach, args.bc, args.layout, args.bulk_tx, args.overlap)
         Nx, Ny = r.grid()
         n_bulk, n_frame, n_q = r.node_classes()
         dt, ms_live, n_live = time_run(torch, r, args.steps, args.warmup, mode=2)
@@ -208,6 +231,7 @@ def main():
             "workload": "d2q37_vortex_pulse_%dsq_pml%d_%s_mach%.2g" % (args.L, args.W, args.bc, args.mach),
             "bulk": args.L, "pml_width": args.W, "grid": args.L + 2 * args.W, "boundary": args.bc,
             "sigma_max": args.sigma, "tau": 0.8, "storage": main_s, "layout": args.layout,
+            "bulk_tx": args.bulk_tx, "overlap": args.overlap,
             "device": dev.name,
         },
         "roofline": {
@@ -220,8 +244,9 @@ def main():
             "traffic": None,
             "bytes_per_launch": R["bulk_bytes_per_launch"],
             "avg_launch_ms": round(R["bulk_kernel_ms"], 5),
-            "timing": "HIP events around each k_bulk launch on its stream inside the timed %d steps "
-                      "(boundary chain on a side stream beside it)" % args.steps,
+            "device_copy_gbs": round(copy_gbs, 1) if copy_gbs else None,
+            "timing": "HIP events around each k_bulk launch on its stream inside the timed %d steps"
+                      % args.steps,
         },
         "variants": {},
     }

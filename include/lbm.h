@@ -82,19 +82,23 @@ typedef struct {
     int32_t storage;             /* lbm_storage */
     double f16_scale;            /* LBM_F16_DEV: scale s (power of two); 0 = chosen at init */
     const lbm_allocator *allocator; /* NULL = hipMalloc / hipFree */
-    void *stream;                /* hipStream_t to enqueue on; NULL = a stream the run owns (then
-                                    the boundary/PML kernels run on side streams beside the bulk
-                                    kernel; on a caller's stream all kernels run in order) */
+    void *stream;                /* hipStream_t to enqueue on; NULL = a stream the run owns (only
+                                    then can lbm_launch.overlap put the boundary/PML kernels on a
+                                    side stream beside the bulk kernel) */
     int32_t layout;              /* population layout in HBM: 0 = the 37 population rows of each
                                     grid row adjacent (default), 1 = one plane per velocity */
 } lbm_desc;
 
-/* Kernel tile shape (set by lbm_set_launch or lbm_autotune).  bulk_tx in {64,128,256}
+/* Launch configuration (set by lbm_set_launch or lbm_autotune).  bulk_tx in {64,128,256}
  * nodes along x, bulk_ty rows per block with bulk_tx*bulk_ty = 256; graph_steps: steps per
- * captured HIP graph in lbm_step (even, 0 disables graphs). */
+ * captured HIP graph in lbm_step (even, 0 disables graphs); overlap: 0 (default) runs the
+ * kernels of a step in order on the run's stream, 1 runs the boundary/PML chain on a side
+ * stream beside the bulk kernel (only for a run that owns its stream; eager launches, no
+ * graphs).  Default {64, 4, 32, 0}. */
 typedef struct {
     int32_t bulk_tx, bulk_ty;
     int32_t graph_steps;
+    int32_t overlap;
 } lbm_launch;
 
 /* Create a run (Sec. 2).  Validates the descriptor (LBM_ERR_ARG: tau <= 0.5, size < 1,
@@ -176,19 +180,19 @@ lbm_status lbm_synchronize(lbm_handle h);
 lbm_status lbm_set_launch(lbm_handle h, const lbm_launch *cfg);
 lbm_status lbm_get_launch(lbm_handle h, lbm_launch *cfg);
 
-/* Time every supported bulk tile shape on a scratch copy of this run's geometry (the run's
- * own state is untouched) and keep the fastest; if cache_path is non-NULL the choice is read
- * from / appended to that text file keyed by (Nx, Ny, storage).  *chosen may be NULL. */
+/* Time every supported bulk tile shape, in order and (for a run that owns its stream)
+ * overlapped, on a scratch copy of this run's geometry (the run's own state is untouched) and
+ * keep the fastest; if cache_path is non-NULL the choice is read from / appended to that text
+ * file, one line "Nx Ny storage bulk_tx overlap" per choice.  *chosen may be NULL. */
 lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path,
                         lbm_launch *chosen);
 
 /* Per-kernel-class timing with HIP events (the wall time of the boundary/PML kernels vs the
  * bulk kernel; Sec. 5 "Computational Cost").  mode 1: every kernel class runs in order on the
  * run's stream and events bracket each class: ms[0] bulk, ms[1] boundary/PML frame (phase B),
- * ms[2] phase A (characteristic fill of the ring and PML auxiliary update).  mode 2: the normal
- * schedule (boundary chain on a side stream beside the bulk kernel, where the run owns its
- * stream) with events bracketing the bulk kernel alone, on the stream it runs on; only ms[0]
- * and launches[0] accumulate.  mode 0 turns timing off.  Any mode other than 0 makes lbm_step
+ * ms[2] phase A (characteristic fill of the ring and PML auxiliary update).  mode 2: the
+ * schedule lbm_launch.overlap selects, with events bracketing the bulk kernel alone, on the
+ * stream it runs on; only ms[0] and launches[0] accumulate.  mode 0 turns timing off.  Any mode other than 0 makes lbm_step
  * launch eagerly (no graphs); a mode outside 0..2 is LBM_ERR_ARG.  lbm_profile_read
  * synchronises and returns the summed milliseconds and launch counts since the last reset. */
 lbm_status lbm_profile(lbm_handle h, int enable);

@@ -64,9 +64,6 @@ struct DeviceMem {
 
 int tx_index(int tx) { return tx == 64 ? 0 : tx == 128 ? 1 : 2; }
 
-// Grids up to this many nodes step through captured HIP graphs.
-constexpr long long GRAPH_MAX_NODES = 1LL << 18;
-
 // Side stream and events of the per-step fork/join: the bulk kernel runs on the main stream while
 // the boundary chain (phase A, then the frame kernel) runs beside it on the side stream.  Both
 // streams keep the default priority.
@@ -109,7 +106,7 @@ struct lbm_run {
     double *fbar_d = nullptr;
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;     // stream in use (the group's while in a group)
-    lbm_launch launch{64, 4, 32};
+    lbm_launch launch{64, 4, 32, 0};
     int64_t steps = 0;
     DeviceMem mem;
     hipGraphExec_t graph = nullptr;
@@ -144,7 +141,6 @@ struct lbm_group {
     bool upload_pending = false;
     int blocks[NCLS] = {0, 0, 0, 0};
     size_t cap = 0;
-    StepStreams ss;
 };
 
 namespace {
@@ -573,9 +569,6 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux, co
         HIP_TRY(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
         h->stream = h->own_stream;
     }
-    // Side streams only on a stream the run owns; on a caller's stream every kernel class is
-    // enqueued in order on that stream.
-    if (!h->desc.stream) HIP_TRY(h->ss.create());
     const int storage = h->desc.storage;
     const size_t es = elem_size(storage), cs = compute_size(storage);
     h->footprint = footprint_of(R, storage);
@@ -653,10 +646,11 @@ lbm_status lbm_step(lbm_handle h, int64_t n) {
     LaunchSet L = single_set(h);
     int64_t left = n;
     const int G = h->launch.graph_steps;
-    // Graphs (captured on the run's stream alone) pay off where launches dominate: small grids.
-    // Larger grids step eagerly with the boundary/PML chains on side streams.
-    const bool small = (long long)h->hd.Nx * h->hd.Ny <= GRAPH_MAX_NODES;
-    if (!h->prof && G > 0 && !h->graph_failed && n >= G && (small || !h->ss.ok)) {
+    // Overlapped steps launch eagerly (stream capture stays single-stream); in-order steps
+    // replay captured graphs of G steps.  The side stream is created on first use.
+    if (h->launch.overlap && !h->desc.stream && !h->ss.ok) HIP_TRY(h->ss.create());
+    const bool overlap = h->launch.overlap && h->ss.ok;
+    if (!h->prof && !overlap && G > 0 && !h->graph_failed && n >= G) {
         if (!h->graph || h->graph_G != G || h->graph_tx != h->launch.bulk_tx) {
             lbm_status st = build_graph(h, G);
             if (st != LBM_OK) return st;
@@ -669,8 +663,8 @@ lbm_status lbm_step(lbm_handle h, int64_t n) {
         }
     }
     for (int64_t k = 0; k < left; ++k) {
-        lbm_status st = enqueue_step(L, h->desc.storage, h->launch.bulk_tx, h->stream, &h->ss,
-                                     h->prof ? h : nullptr);
+        lbm_status st = enqueue_step(L, h->desc.storage, h->launch.bulk_tx, h->stream,
+                                     overlap ? &h->ss : nullptr, h->prof ? h : nullptr);
         if (st != LBM_OK) return st;
     }
     h->steps += n;
@@ -811,6 +805,7 @@ lbm_status lbm_set_launch(lbm_handle h, const lbm_launch *cfg) {
         cfg->bulk_tx * cfg->bulk_ty != 256)
         return fail(LBM_ERR_ARG, "bulk tile must be 64x4, 128x2 or 256x1");
     if (cfg->graph_steps < 0 || (cfg->graph_steps & 1)) return fail(LBM_ERR_ARG, "graph_steps must be even and >= 0");
+    if (cfg->overlap != 0 && cfg->overlap != 1) return fail(LBM_ERR_ARG, "overlap must be 0 or 1");
     if (h->group) return fail(LBM_ERR_STATE, "run is in a group");
     h->launch = *cfg;
     if (h->inited) return upload_prefix(h);
@@ -951,12 +946,14 @@ lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path, lbm
     if (cache_path) {
         FILE *fp = std::fopen(cache_path, "r");
         if (fp) {
-            int nx, ny, st, tx;
-            while (std::fscanf(fp, "%d %d %d %d", &nx, &ny, &st, &tx) == 4) {
+            char line[256];
+            while (std::fgets(line, sizeof line, fp)) {
+                int nx, ny, st, tx, ov;
+                if (std::sscanf(line, "%d %d %d %d %d", &nx, &ny, &st, &tx, &ov) != 5) continue;
                 if (nx == R.Nx && ny == R.Ny && st == h->desc.storage) {
                     std::fclose(fp);
                     lbm_launch c = h->launch;
-                    c.bulk_tx = tx; c.bulk_ty = 256 / tx;
+                    c.bulk_tx = tx; c.bulk_ty = 256 / tx; c.overlap = ov;
                     lbm_status s2 = lbm_set_launch(h, &c);
                     if (chosen) *chosen = h->launch;
                     return s2;
@@ -965,9 +962,8 @@ lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path, lbm
             std::fclose(fp);
         }
     }
-    // scratch run with the same geometry at the mean state
+    // scratch run with the same geometry at the mean state, on a stream of the same kind
     lbm_desc d = h->desc;
-    d.stream = (void *)h->stream;
     lbm_handle s = nullptr;
     lbm_status st = lbm_create(&d, &s);
     if (st != LBM_OK) return st;
@@ -977,32 +973,38 @@ lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path, lbm
     std::vector<double> f1(nn, d.rho0), f2(nn, d.ux0), f3(nn, d.uy0), f4(nn, d.T0);
     st = lbm_init_fields(s, f1.data(), f2.data(), f3.data(), f4.data());
     if (st != LBM_OK) { lbm_destroy(s); return st; }
-    int best_tx = h->launch.bulk_tx;
+    int best_tx = h->launch.bulk_tx, best_ov = h->launch.overlap;
     float best = 1e30f;
     hipEvent_t a = nullptr, b = nullptr;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
-    for (int tx : {64, 128, 256}) {
-        lbm_launch c{tx, 256 / tx, 0};
-        if (lbm_set_launch(s, &c) != LBM_OK) continue;
-        lbm_step(s, 2);
-        (void)hipEventRecord(a, s->stream);
-        lbm_step(s, steps);
-        (void)hipEventRecord(b, s->stream);
-        (void)hipEventSynchronize(b);
-        float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, a, b);
-        if (ms < best) { best = ms; best_tx = tx; }
+    const int nov = d.stream ? 1 : 2;   // overlap needs a stream the run owns
+    for (int ov = 0; ov < nov; ++ov) {
+        for (int tx : {64, 128, 256}) {
+            lbm_launch c{tx, 256 / tx, 0, ov};
+            if (lbm_set_launch(s, &c) != LBM_OK) continue;
+            lbm_step(s, 2);
+            (void)hipEventRecord(a, s->stream);
+            lbm_step(s, steps);
+            (void)hipEventRecord(b, s->stream);
+            (void)hipEventSynchronize(b);
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, a, b);
+            if (ms < best) { best = ms; best_tx = tx; best_ov = ov; }
+        }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     lbm_destroy(s);
     lbm_launch c = h->launch;
-    c.bulk_tx = best_tx; c.bulk_ty = 256 / best_tx;
+    c.bulk_tx = best_tx; c.bulk_ty = 256 / best_tx; c.overlap = best_ov;
     st = lbm_set_launch(h, &c);
     if (st == LBM_OK && cache_path) {
         FILE *fp = std::fopen(cache_path, "a");
-        if (fp) { std::fprintf(fp, "%d %d %d %d\n", R.Nx, R.Ny, h->desc.storage, best_tx); std::fclose(fp); }
+        if (fp) {
+            std::fprintf(fp, "%d %d %d %d %d\n", R.Nx, R.Ny, h->desc.storage, best_tx, best_ov);
+            std::fclose(fp);
+        }
     }
     if (chosen) *chosen = h->launch;
     return st;
@@ -1021,8 +1023,7 @@ lbm_status lbm_group_create(void *stream, const lbm_allocator *allocator, lbm_gr
         }
         g->stream = g->own_stream;
     }
-    if ((!stream && g->ss.create() != hipSuccess) ||
-        hipHostMalloc((void **)&g->hlimits, 4096 * sizeof(long long), hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc((void **)&g->hlimits, 4096 * sizeof(long long), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&g->upload_done, hipEventDisableTiming) != hipSuccess) {
         if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
         delete g;
@@ -1132,7 +1133,7 @@ lbm_status lbm_group_step(lbm_group_handle g, const int64_t *steps, int64_t nste
     }
     L.nruns = (int)n;
     for (int64_t k = 0; k < K; ++k) {
-        lbm_status st = enqueue_step(L, g->storage, g->tx, g->stream, &g->ss, nullptr);
+        lbm_status st = enqueue_step(L, g->storage, g->tx, g->stream, nullptr, nullptr);
         if (st != LBM_OK) return st;
     }
     for (size_t k = 0; k < n; ++k) g->members[k]->steps += steps ? steps[k] : nsteps;
@@ -1147,7 +1148,6 @@ void lbm_group_destroy(lbm_group_handle g) {
         h->stream = h->own_stream ? h->own_stream : (hipStream_t)h->desc.stream;
     }
     g->mem.release_all();
-    g->ss.destroy();
     if (g->hlimits) (void)hipHostFree(g->hlimits);
     if (g->upload_done) (void)hipEventDestroy(g->upload_done);
     if (g->own_stream) (void)hipStreamDestroy(g->own_stream);

@@ -511,24 +511,32 @@ __global__ __launch_bounds__(256) void k_bulk(RunDev *const *__restrict__ runs,
     for_each_feq<C>(q, R, k, [&](auto ic, C fe) {
         constexpr int i = decltype(ic)::value;
         C out = g[i] + k.omega * (fe - g[i]);
-        *at(dst0 + (long long)i * plane, off) = cvt_out(out, k.scale, (S *)nullptr);
+        // FP64/FP32: streaming store (the next reads of these lines are a step away); FP16 rows
+        // of a wave are single cache lines and measure faster as ordinary stores
+        if constexpr (sizeof(S) >= 4)
+            __builtin_nontemporal_store(cvt_out(out, k.scale, (S *)nullptr), at(dst0 + (long long)i * plane, off));
+        else
+            *at(dst0 + (long long)i * plane, off) = cvt_out(out, k.scale, (S *)nullptr);
     });
 }
 
 // Collision of a frame node (frame index t) from its post-stream, post-boundary populations g:
 // BGK plus, on PML nodes, -sigma (e.grad Q + 2 fhat + sigma Q) (eq. PMLCOLL) with grad Q central
 // and one-sided at the outermost layer of an open axis (eqs. FD-dx-*); the moments go to U.
-// Every load (Q at the node and its neighbours) is issued before the first store.
+// The BGK part and -2 sigma fhat are formed first, in place of g; Q at the node and its
+// neighbours is then read a few populations at a time, every read of a group issued before its
+// first use (the pointers are restrict-qualified so later groups may be read ahead of earlier
+// stores): a handful of memory round trips per node instead of one per population.
 template <class S, class C>
 __device__ __forceinline__ void frame_collide(CRun &R, const K<C> &k, const C (&g)[NQ], int x, int y,
-                                              int t) {
-    GLOBAL S *dst = (GLOBAL S *)R.f[R.par ^ 1];
-    GLOBAL double *Un = (GLOBAL double *)R.U[R.par ^ 1];
+                                              int t, const GLOBAL C *__restrict__ Q,
+                                              GLOBAL S *__restrict__ dnode,
+                                              GLOBAL double *__restrict__ Un) {
     const long long plane = R.plane;
     const unsigned qp = (unsigned)R.qplane;
-    GLOBAL S *dnode = dst + (long long)y * R.pitch + x;
+    Mom<C> m = moments<C>(g, k);
+    Eq<C> q = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
     if (R.has_q) {
-        const GLOBAL C *Q = (const GLOBAL C *)R.Q;
         // d/dalpha Q = cs*Q(x) + c0*Q(j0) + c1*Q(j1): central 0, 1/2, -1/2 at x+1, x-1;
         // one-sided at the outermost layer (outward normal s): s*(3/2, -2, 1/2) at x, x-s, x-2s
         int jx0, jx1, jy0, jy1;
@@ -565,46 +573,48 @@ __device__ __forceinline__ void frame_collide(CRun &R, const K<C> &k, const C (&
         const unsigned oy0 = (unsigned)(jy0 < 0 ? t : jy0) * (unsigned)sizeof(C);
         const unsigned oy1 = (unsigned)(jy1 < 0 ? t : jy1) * (unsigned)sizeof(C);
         const unsigned ot = (unsigned)t * (unsigned)sizeof(C);
-        // sigma = 0 off the layer: the PML term is then -0 * (finite) and leaves BGK's bits
+        // sigma = 0 off the layer: the PML terms are then -0 * (finite) and leave BGK's bits
         const C s = (C)(R.W > 0 ? sigma_at(R, x, y) : 0.0);
-        // P_i = e_i.grad Q_i + sigma Q_i, gathered before any store
-        C P[NQ];
-        static_for<0, NQ>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            const GLOBAL C *Qi = Q + (long long)i * qp;
-            const C Qt = *at(Qi, ot);
-            C gq = C(0);
-            if constexpr (ex_of(i) != 0)
-                gq += C(ex_of(i)) * (cxs * Qt + cx0 * *at(Qi, ox0) + cx1 * *at(Qi, ox1));
-            if constexpr (ey_of(i) != 0)
-                gq += C(ey_of(i)) * (cys * Qt + cy0 * *at(Qi, oy0) + cy1 * *at(Qi, oy1));
-            P[i] = gq + s * Qt;
-        });
-        Mom<C> m = moments<C>(g, k);
-        Eq<C> q = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
+        C h[NQ];
         for_each_feq<C>(q, R, k, [&](auto ic, C fe) {
             constexpr int i = decltype(ic)::value;
             C out = g[i] + k.omega * (fe - g[i]);
-            out = out - s * (P[i] + C(2) * fe);
-            dnode[(long long)i * plane] = cvt_out(out, k.scale, (S *)nullptr);
+            h[i] = out - s * (C(2) * fe);
         });
-        Un[t] = R.rho0 + (double)m.drho;
-        Un[qp + t] = R.u0x + (double)m.dux;
-        Un[2 * qp + t] = R.u0y + (double)m.duy;
-        Un[3 * qp + t] = R.T0 + (double)m.dT;
+        constexpr int CH = sizeof(C) == 8 ? 4 : 12;   // populations per group of Q reads
+        static_for<0, (NQ + CH - 1) / CH>([&](auto cc) {
+            constexpr int c0 = decltype(cc)::value * CH;
+            constexpr int c1 = c0 + CH < NQ ? c0 + CH : NQ;
+            C v[c1 - c0][5];
+            static_for<c0, c1>([&](auto ic) {
+                constexpr int i = decltype(ic)::value, l = i - c0;
+                const GLOBAL C *Qi = Q + (long long)i * qp;
+                v[l][0] = *at(Qi, ot);
+                if constexpr (ex_of(i) != 0) { v[l][1] = *at(Qi, ox0); v[l][2] = *at(Qi, ox1); }
+                if constexpr (ey_of(i) != 0) { v[l][3] = *at(Qi, oy0); v[l][4] = *at(Qi, oy1); }
+            });
+            static_for<c0, c1>([&](auto ic) {
+                constexpr int i = decltype(ic)::value, l = i - c0;
+                C gq = C(0);
+                if constexpr (ex_of(i) != 0)
+                    gq += C(ex_of(i)) * (cxs * v[l][0] + cx0 * v[l][1] + cx1 * v[l][2]);
+                if constexpr (ey_of(i) != 0)
+                    gq += C(ey_of(i)) * (cys * v[l][0] + cy0 * v[l][3] + cy1 * v[l][4]);
+                C out = h[i] - s * (gq + s * v[l][0]);
+                __builtin_nontemporal_store(cvt_out(out, k.scale, (S *)nullptr), dnode + (long long)i * plane);
+            });
+        });
     } else {
-        Mom<C> m = moments<C>(g, k);
-        Eq<C> q = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
         for_each_feq<C>(q, R, k, [&](auto ic, C fe) {
             constexpr int i = decltype(ic)::value;
             C out = g[i] + k.omega * (fe - g[i]);
-            dnode[(long long)i * plane] = cvt_out(out, k.scale, (S *)nullptr);
+            __builtin_nontemporal_store(cvt_out(out, k.scale, (S *)nullptr), dnode + (long long)i * plane);
         });
-        Un[t] = R.rho0 + (double)m.drho;
-        Un[qp + t] = R.u0x + (double)m.dux;
-        Un[2 * qp + t] = R.u0y + (double)m.duy;
-        Un[3 * qp + t] = R.T0 + (double)m.dT;
     }
+    Un[t] = R.rho0 + (double)m.drho;
+    Un[qp + t] = R.u0x + (double)m.dux;
+    Un[2 * qp + t] = R.u0y + (double)m.duy;
+    Un[3 * qp + t] = R.T0 + (double)m.dT;
 }
 
 // Phase B of a step on the frame: ring blocks take the post-boundary populations phase A stored
@@ -641,7 +651,9 @@ __global__ __launch_bounds__(256) void k_frame(RunDev *const *__restrict__ runs,
         t = tt;
         gather_clamped<S, C>(R, (const GLOBAL S *)R.f[R.par], x, y, k.inv_scale, g);
     }
-    frame_collide<S, C>(R, k, g, x, y, t);
+    frame_collide<S, C>(R, k, g, x, y, t, (const GLOBAL C *)R.Q,
+                        (GLOBAL S *)R.f[R.par ^ 1] + (long long)y * R.pitch + x,
+                        (GLOBAL double *)R.U[R.par ^ 1]);
 }
 
 // PML auxiliary update Q += (fhat^n + fhat^{n+1}) / 2 at frame node t (eq. PMLQ, trapezoid rule),

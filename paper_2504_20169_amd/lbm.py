@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbm_mi355x.so")
+# LBM_MI355X_LIB may name another build of the same library (same ABI, e.g. other flags).
+LIB_PATH = os.environ.get("LBM_MI355X_LIB") or os.path.join(HERE, "liblbm_mi355x.so")
 
 LBM_OK, LBM_ERR_ARG, LBM_ERR_STATE, LBM_ERR_OOM, LBM_ERR_DEVICE, LBM_ERR_UNSTABLE, \
     LBM_ERR_UNSUPPORTED = range(7)
@@ -55,7 +56,7 @@ class lbm_desc(ctypes.Structure):
 
 class lbm_launch(ctypes.Structure):
     _fields_ = [("bulk_tx", ctypes.c_int32), ("bulk_ty", ctypes.c_int32),
-                ("graph_steps", ctypes.c_int32)]
+                ("graph_steps", ctypes.c_int32), ("overlap", ctypes.c_int32)]
 
 
 class LbmError(RuntimeError):
@@ -282,20 +283,22 @@ class Run:
             _check(st)
         return st
 
-    def set_launch(self, bulk_tx=64, graph_steps=32):
-        c = lbm_launch(int(bulk_tx), 256 // int(bulk_tx), int(graph_steps))
+    def set_launch(self, bulk_tx=64, graph_steps=32, overlap=0):
+        c = lbm_launch(int(bulk_tx), 256 // int(bulk_tx), int(graph_steps), int(overlap))
         _check(self._lib.lbm_set_launch(self.h, ctypes.byref(c)))
 
     def get_launch(self):
         c = lbm_launch()
         _check(self._lib.lbm_get_launch(self.h, ctypes.byref(c)))
-        return dict(bulk_tx=c.bulk_tx, bulk_ty=c.bulk_ty, graph_steps=c.graph_steps)
+        return dict(bulk_tx=c.bulk_tx, bulk_ty=c.bulk_ty, graph_steps=c.graph_steps,
+                    overlap=c.overlap)
 
     def autotune(self, steps=10, cache_path=None):
         c = lbm_launch()
         _check(self._lib.lbm_autotune(self.h, int(steps),
                                       cache_path.encode() if cache_path else None, ctypes.byref(c)))
-        return dict(bulk_tx=c.bulk_tx, bulk_ty=c.bulk_ty, graph_steps=c.graph_steps)
+        return dict(bulk_tx=c.bulk_tx, bulk_ty=c.bulk_ty, graph_steps=c.graph_steps,
+                    overlap=c.overlap)
 
     def profile(self, mode=1):
         """Event timing: 1 (or True) kernel classes in order, 2 bulk kernel in the normal

@@ -69,6 +69,22 @@ def test_setters_validate_and_grid():
     assert ei.value.status == lbm.LBM_ERR_STATE
 
 
+def test_launch_configuration_validated_on_host():
+    r = lbm.Run(20, 10, 0.8)
+    assert r.get_launch() == dict(bulk_tx=64, bulk_ty=4, graph_steps=32, overlap=0)
+    for kw in (dict(bulk_tx=32), dict(graph_steps=3), dict(graph_steps=-2), dict(overlap=2),
+               dict(overlap=-1)):
+        with pytest.raises(lbm.LbmError) as ei:
+            r.set_launch(**kw)
+        assert ei.value.status == lbm.LBM_ERR_ARG, kw
+    r.set_launch(bulk_tx=256, graph_steps=0, overlap=1)
+    assert r.get_launch() == dict(bulk_tx=256, bulk_ty=1, graph_steps=0, overlap=1)
+    with pytest.raises(lbm.LbmError):
+        r.profile(3)
+    r.profile(2)
+    r.profile(0)
+
+
 def test_init_rejects_inconsistent_configuration():
     # PML on a periodic side / one-sided periodic / too small open axis are caught before any
     # device allocation.

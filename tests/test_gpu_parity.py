@@ -128,14 +128,15 @@ def test_sigma_zero_pml_bitwise_equals_plain(bc, storage):
     assert np.array_equal(a.populations(), b.populations())
 
 
-def test_tile_shapes_and_graphs_bitwise_identical():
+def test_tile_shapes_graphs_and_overlap_bitwise_identical():
+    """Tile shape, graph replay and the overlapped schedule change launches, never bits."""
     F = wl.noisy_state(150, 140, 3, 1.0, 0.05, 0.0, 1.0)
     outs = []
-    for tx, gs in ((64, 0), (128, 8), (256, 32), (64, 32)):
+    for tx, gs, ov in ((64, 0, 0), (128, 8, 0), (256, 32, 0), (64, 32, 0), (64, 0, 1), (256, 8, 1)):
         r = lbm.Run(134, 124, 0.8, 1.0, 0.05, 0.0, 1.0)
         r.set_bc(15, "nrbc")
         r.set_pml(15, 8, 0.05)
-        r.set_launch(bulk_tx=tx, graph_steps=gs)
+        r.set_launch(bulk_tx=tx, graph_steps=gs, overlap=ov)
         r.init(*F.as_tuple())
         r.step(41)
         outs.append(r.populations())
@@ -147,11 +148,11 @@ def test_profile_modes_count_launches_and_keep_bits():
     """Event timing in either mode changes the launch schedule, never the result."""
     F = wl.noisy_state(150, 140, 3, 1.0, 0.05, 0.0, 1.0)
     outs = []
-    for mode in (0, 1, 2):
+    for mode, ov in ((0, 0), (1, 0), (2, 0), (2, 1)):
         r = lbm.Run(134, 124, 0.8, 1.0, 0.05, 0.0, 1.0)
         r.set_bc(15, "nrbc")
         r.set_pml(15, 8, 0.05)
-        r.set_launch(graph_steps=8)
+        r.set_launch(graph_steps=8, overlap=ov)
         r.init(*F.as_tuple())
         r.profile(mode)
         r.step(23)
@@ -165,6 +166,33 @@ def test_profile_modes_count_launches_and_keep_bits():
         r.close()
     for o in outs[1:]:
         assert np.array_equal(outs[0], o)
+
+
+def test_autotune_choice_is_valid_cached_and_keeps_bits(tmp_path):
+    F = wl.noisy_state(106, 96, 4, 1.0, 0.05, 0.0, 1.0)
+    cache = str(tmp_path / "tune.txt")
+
+    def make():
+        r = lbm.Run(90, 80, 0.8, 1.0, 0.05, 0.0, 1.0)
+        r.set_bc(15, "nrbc")
+        r.set_pml(15, 8, 0.05)
+        r.init(*F.as_tuple())
+        return r
+
+    ref = make()
+    ref.step(19)
+    a = make()
+    c = a.autotune(steps=4, cache_path=cache)
+    assert c["bulk_tx"] in (64, 128, 256) and c["overlap"] in (0, 1)
+    lines = open(cache).read().split("\n")
+    assert lines[0].split() == ["106", "96", "0", str(c["bulk_tx"]), str(c["overlap"])]
+    a.step(19)
+    assert np.array_equal(a.populations(), ref.populations())
+    b = make()
+    assert b.autotune(steps=4, cache_path=cache) == c      # read back, no new line
+    assert len([l for l in open(cache).read().split("\n") if l]) == 1
+    for r in (ref, a, b):
+        r.close()
 
 
 def test_conservation_on_gpu():
