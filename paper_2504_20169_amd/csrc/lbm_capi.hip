@@ -281,10 +281,10 @@ void compute_blocks(const RunDev &R, int tx, int nb[NCLS]) {
     int k = tx_index(tx);
     nb[CLS_BULK] = R.tiles_x[k] * R.tiles_y[k];
     const int fb = (R.frame_n + FRAME_BLOCK - 1) / FRAME_BLOCK;
-    const int rb = (R.ring_n + FRAME_BLOCK - 1) / FRAME_BLOCK;
+    const int rb = (R.ring_n + RING_BLOCK - 1) / RING_BLOCK;
     nb[CLS_FRAME] = rb + fb;
     nb[CLS_A] = rb + (R.has_q ? fb : 0);
-    nb[CLS_RING] = rb;
+    nb[CLS_RING] = (R.ring_n + FRAME_BLOCK - 1) / FRAME_BLOCK;   // k_nrbc: full blocks
 }
 
 lbm_status upload_prefix(lbm_run *h) {

@@ -65,6 +65,10 @@ struct LaunchSet {
 };
 
 constexpr int FRAME_BLOCK = 256;
+// Ring nodes per block of the boundary launches: one active wave per 256-thread block, so the
+// ring's few, poorly coalesced waves (a 3-wide strip puts ~21 grid rows in one wave) land on
+// different compute units instead of sharing one unit's memory pipeline four at a time.
+constexpr int RING_BLOCK = 64;
 
 // Kernel launchers (lbm_kernels.hip).  All enqueue on `s` and return the HIP status of the
 // launch.

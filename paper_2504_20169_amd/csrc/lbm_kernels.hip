@@ -424,9 +424,9 @@ __device__ __forceinline__ void gather_clamped(CRun &R, const GLOBAL S *src, int
     });
 }
 
-// Blocks of a run's boundary launches: the characteristic ring first (ring numbering), then the
-// frame (frame numbering).
-__device__ __forceinline__ int ring_blocks(CRun &R) { return (R.ring_n + FRAME_BLOCK - 1) / FRAME_BLOCK; }
+// Blocks of a run's boundary launches: the characteristic ring first (ring numbering, RING_BLOCK
+// nodes per block), then the frame (frame numbering, FRAME_BLOCK nodes per block).
+__device__ __forceinline__ int ring_blocks(CRun &R) { return (R.ring_n + RING_BLOCK - 1) / RING_BLOCK; }
 
 // Ring node of characteristic sides: U_tgt = U(x_b) of the last completed level plus the LODI
 // increment of each NRBC side the node lies on (corners add both normals), then the clamped pull
@@ -634,7 +634,8 @@ __global__ __launch_bounds__(256) void k_frame(RunDev *const *__restrict__ runs,
     int x, y, t;
     C g[NQ];
     if (tb < rb) {
-        const int tt = tb * FRAME_BLOCK + (int)threadIdx.x;
+        if ((int)threadIdx.x >= RING_BLOCK) return;
+        const int tt = tb * RING_BLOCK + (int)threadIdx.x;
         if (tt >= R.ring_n) return;
         ring_xy(R, tt, x, y);
         t = fidx(R, x, y);
@@ -696,7 +697,8 @@ __global__ __launch_bounds__(256) void k_phase_a(RunDev *const *__restrict__ run
     int x, y, t;
     C g[NQ];
     if (tb < rb) {
-        const int tt = tb * FRAME_BLOCK + (int)threadIdx.x;
+        if ((int)threadIdx.x >= RING_BLOCK) return;
+        const int tt = tb * RING_BLOCK + (int)threadIdx.x;
         if (tt >= R.ring_n) return;
         ring_xy(R, tt, x, y);
         t = fidx(R, x, y);
