@@ -33,17 +33,15 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_run(lbm, wl, storage, stream, alloc, L, W, sigma, mach, bc, layout=0, bulk_tx=64,
-             overlap=0):
-    spec = wl.vortex_pulse(L=L, W=W, sigma_max=sigma, mach=mach, bc=bc)
-    r = lbm.Run(L, L, 0.8, 1.0, mach, 0.0, 1.0, storage=storage, stream=stream, allocator=alloc,
-                layout=layout)
+def run_from_spec(lbm, spec, storage, stream=None, alloc=None, layout=0, bulk_tx=64, overlap=0):
+    r = lbm.Run(spec.Lx, spec.Ly, spec.tau, spec.rho0, spec.ux0, spec.uy0, spec.T0, storage=storage,
+                stream=stream, allocator=alloc, layout=layout)
     r.set_launch(bulk_tx=bulk_tx, overlap=overlap)
-    r.set_bc(lbm.LBM_ALL, bc)
-    if W:
-        r.set_pml(lbm.LBM_ALL, W, sigma)
+    r.set_bc(lbm.LBM_ALL, spec.bc)
+    if spec.W:
+        r.set_pml(lbm.LBM_ALL, spec.W, spec.sigma_max)
     r.init(*spec.fields.as_tuple())
-    return r, spec
+    return r
 
 
 def time_run(torch, r, steps, warmup, mode):
@@ -75,6 +73,168 @@ def serve_trace(jobs, rate, scale, storage, tick):
     rep = eng.run_trace(jobs_from_trace(trace, scale))
     be.close()
     return rep
+
+
+def measure(torch, lbm, r, spec, storage, steps, warmup, prof_steps):
+    """Timed pass (HIP events around every bulk launch) and, if prof_steps, an in-order pass
+    with per-class events.  Returns the result dict of one run."""
+    Nx, Ny = r.grid()
+    n_bulk, n_frame, n_q = r.node_classes()
+    dt, ms_live, n_live = time_run(torch, r, steps, warmup, mode=2)
+    st = r.check()
+    nodes = Nx * Ny
+    alg_bytes_step = BYTES_PER_NODE[storage] * nodes + PML_EXTRA[storage] * n_q
+    bulk_ms = ms_live[0] / max(n_live[0], 1)
+    bulk_bytes = BYTES_PER_NODE[storage] * n_bulk
+    res = dict(
+        mlups=nodes * steps / dt / 1e6, mlups_bulk=spec.Lx * spec.Ly * steps / dt / 1e6,
+        ms_per_step=dt * 1e3 / steps,
+        gbs_step=alg_bytes_step / (dt / steps) / 1e9,
+        frac_step=alg_bytes_step / (dt / steps) / 1e9 / HBM_PEAK_GBS,
+        bulk_kernel_ms=bulk_ms,
+        bulk_kernel_gbs=bulk_bytes / (bulk_ms * 1e-3) / 1e9 if bulk_ms > 0 else None,
+        bulk_nodes=n_bulk, frame_nodes=n_frame, q_nodes=n_q, bulk_bytes_per_launch=bulk_bytes,
+        steps=steps, stable=(st == lbm.LBM_OK))
+    if res["bulk_kernel_gbs"]:
+        res["bulk_frac"] = res["bulk_kernel_gbs"] / HBM_PEAK_GBS
+    if prof_steps > 0:
+        _, ms, n = time_run(torch, r, prof_steps, 5, mode=1)
+        res["in_order"] = dict(
+            steps=prof_steps,
+            bulk_kernel_ms=ms[0] / max(n[0], 1), frame_kernel_ms=ms[1] / max(n[1], 1),
+            phase_a_kernel_ms=ms[2] / max(n[2], 1),
+            boundary_cost_ratio=(ms[1] + ms[2]) / max(ms[0], 1e-9),
+            ms_per_step=sum(ms) / max(n[1], 1))
+    return res
+
+
+def large_leg(torch, lbm, wl, args):
+    """4096^2 bulk + 64-cell PML (4224^2 nodes), Mach 0.05, 8 seeded pulses, ZG and NRBC, every
+    storage: the largest configuration, where the grid is far larger than the caches."""
+    out = {}
+    for bc in args.large_bcs.split(","):
+        spec = wl.multi_pulse(L=4096, W=64, sigma_max=0.01, mach=0.05, bc=bc)
+        for storage in args.storages.split(","):
+            _log("bench: 4224^2", bc, storage)
+            r = run_from_spec(lbm, spec, storage, layout=args.layout, bulk_tx=args.bulk_tx,
+                              overlap=args.overlap)
+            out["%s_%s" % (bc, storage)] = measure(torch, lbm, r, spec, storage, args.large_steps,
+                                                  20, args.large_steps // 2)
+            r.close()
+            del r
+    return out
+
+
+def batch_leg(torch, lbm, wl, args):
+    """256 uneven FP32 runs (bulk 128..1024, PML 0..32, ZG or NRBC): each run stepped alone with
+    lbm_step, one run after another (the plain single-run path), then all of them in one group
+    (one launch per kernel class and step for the whole batch, replayed from a HIP graph)."""
+    specs = wl.batch_sweep(nruns=args.batch_runs, steps=args.batch_steps, sigma_max=0.0015)
+    runs = [run_from_spec(lbm, sp, "f32") for sp in specs]
+    updates = sum(sp.Nx * sp.Ny for sp in specs) * args.batch_steps
+    for r in runs:
+        r.step(2)
+    for r in runs:
+        r.synchronize()
+    t0 = time.perf_counter()
+    for r in runs:                  # the plain single-run path: one run at a time
+        r.step(args.batch_steps)
+        r.synchronize()
+    t_seq = time.perf_counter() - t0
+    g = lbm.Group()
+    for r in runs:
+        g.add(r)
+    tuned = g.autotune(steps=4)
+    g.step(nsteps=2)
+    g.synchronize()
+    t0 = time.perf_counter()
+    g.step(nsteps=args.batch_steps)
+    g.synchronize()
+    t_grp = time.perf_counter() - t0
+    ok = all(r.check() == lbm.LBM_OK for r in runs)
+    g.close()
+    for r in runs:
+        r.close()
+    return dict(runs=len(specs), steps=args.batch_steps, nodes=sum(sp.Nx * sp.Ny for sp in specs),
+                sequential_mlups=updates / t_seq / 1e6, group_mlups=updates / t_grp / 1e6,
+                speedup=t_seq / t_grp, stable=ok, group_launch=tuned,
+                workload="batch sweep: bulk L in {128,256,512,1024}, W in {0,4,8,16,32}, ZG/NRBC, "
+                         "vortex + pulse, sigma_max 0.0015, FP32 storage")
+
+
+KERNEL_SRC = os.path.join(ROOT, "paper_2504_20169_amd", "csrc", "lbm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bulk_f64_1088sq_nrbc_pmc.txt")
+BULK_F64 = "void lbm::k_bulk<double, 64>(lbm::RunDev* const*, int const*, int)"
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def pmc_means(path, counter):
+    """Mean counter value (KiB per dispatch) per kernel name from a rocprofv3 --pmc CSV."""
+    import csv
+    acc = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] != counter:
+                continue
+            acc.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return acc
+
+
+def pmc_summary(fetch_csv, write_csv, out_path, command):
+    """Text summary of two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE): per-kernel KiB per
+    dispatch, the scale factors from the 1 GiB device copy of --copy-calibration, and the HBM
+    bytes per launch of the FP64 bulk kernel (the roofline's `traffic`)."""
+    fetch, write = pmc_means(fetch_csv, "FETCH_SIZE"), pmc_means(write_csv, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    cf = [v for v in fetch.get(COPY_KERNEL, []) if v > 0.25 * gib_kib]
+    cw = [v for v in write.get(COPY_KERNEL, []) if v > 0.5 * gib_kib]
+    if not cf or not cw:
+        raise SystemExit("no 1 GiB copy dispatch in the counter files (run with --copy-calibration)")
+    sf = gib_kib / (sum(cf) / len(cf))
+    sw = gib_kib / (sum(cw) / len(cw))
+    lines = ["# HBM traffic per dispatch, rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (two passes)",
+             "command: " + command,
+             "kernel_source_sha256: " + kernel_source_hash(),
+             "copy_calibration: 1 GiB device copy reads FETCH_SIZE %.1f KiB, WRITE_SIZE %.1f KiB"
+             % (sum(cf) / len(cf), sum(cw) / len(cw)),
+             "scale: fetch x%.4f, write x%.4f" % (sf, sw), "",
+             "%-72s %8s %14s %14s %14s" % ("kernel", "n", "FETCH KiB", "WRITE KiB", "scaled MB")]
+    for k in sorted(set(fetch) & set(write)):
+        f = sum(fetch[k]) / len(fetch[k])
+        w = sum(write[k]) / len(write[k])
+        lines.append("%-72s %8d %14.1f %14.1f %14.2f" % (k[:72], len(fetch[k]), f, w,
+                                                           (f * sf + w * sw) * 1024 / 1e6))
+    if BULK_F64 in fetch and BULK_F64 in write:
+        f = sum(fetch[BULK_F64]) / len(fetch[BULK_F64]) * sf * 1024
+        w = sum(write[BULK_F64]) / len(write[BULK_F64]) * sw * 1024
+        lines += ["", "traffic_bytes_per_launch: %d" % round(f + w),
+                  "traffic_read_bytes: %d" % round(f), "traffic_write_bytes: %d" % round(w)]
+    with open(out_path, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def recorded_traffic():
+    """HBM bytes per k_bulk<double> launch from the committed counter summary, or None when it
+    is missing or was taken from another version of the kernels."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for ln in f:
+                if ":" in ln:
+                    k, v = ln.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(wl, L, W, sigma, mach, bc, steps):
@@ -113,6 +273,11 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=500,
                     help="steps of a separate pass that runs the kernel classes in order and times "
                          "each (0 skips it)")
+    ap.add_argument("--large-steps", type=int, default=200,
+                    help="timed steps per run of the 4224^2 leg (0 skips it)")
+    ap.add_argument("--large-bcs", default="zg,nrbc")
+    ap.add_argument("--batch-runs", type=int, default=256, help="0 skips the batch sweep")
+    ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--serve-jobs", type=int, default=24, help="0 skips the serving trace")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-scale", type=float, default=0.1,
@@ -121,7 +286,13 @@ def main():
                     help="skip timing a plain 2 GiB device copy (attainable HBM bandwidth)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 1 GiB (HBM counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT"),
+                    help="summarise two rocprofv3 --pmc passes into OUT and exit (no GPU)")
+    ap.add_argument("--pmc-command", default="", help="command line recorded in the summary")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary, command=args.pmc_command)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -167,38 +338,12 @@ def main():
         del a, b
 
     results = {}
+    spec = wl.vortex_pulse(L=args.L, W=args.W, sigma_max=args.sigma, mach=args.mach, bc=args.bc)
     for storage in args.storages.split(","):
         _log("bench: storage", storage)
-        r, spec = make_run(lbm, wl, storage, stream, alloc, args.L, args.W, args.sigma,
-                           args.mach, args.bc, args.layout, args.bulk_tx, args.overlap)
-        Nx, Ny = r.grid()
-        n_bulk, n_frame, n_q = r.node_classes()
-        dt, ms_live, n_live = time_run(torch, r, args.steps, args.warmup, mode=2)
-        if args.prof_steps > 0:
-            _, ms, n = time_run(torch, r, args.prof_steps, 5, mode=1)
-        else:
-            ms, n = np.zeros(3), np.zeros(3, dtype=np.int64)
-        st = r.check()
-        nodes = Nx * Ny
-        mlups = nodes * args.steps / dt / 1e6
-        alg_bytes_step = BYTES_PER_NODE[storage] * nodes + PML_EXTRA[storage] * n_q
-        bulk_ms = ms_live[0] / max(n_live[0], 1)
-        bulk_bytes = BYTES_PER_NODE[storage] * n_bulk
-        results[storage] = dict(
-            mlups=mlups, mlups_bulk=args.L * args.L * args.steps / dt / 1e6,
-            ms_per_step=dt * 1e3 / args.steps,
-            gbs_step=alg_bytes_step / (dt / args.steps) / 1e9,
-            bulk_kernel_ms=bulk_ms,
-            bulk_kernel_gbs=bulk_bytes / (bulk_ms * 1e-3) / 1e9 if bulk_ms > 0 else None,
-            bulk_nodes=n_bulk, frame_nodes=n_frame, q_nodes=n_q, bulk_bytes_per_launch=bulk_bytes,
-            stable=(st == lbm.LBM_OK))
-        if args.prof_steps > 0:
-            results[storage]["in_order"] = dict(
-                steps=args.prof_steps,
-                bulk_kernel_ms=ms[0] / max(n[0], 1), frame_kernel_ms=ms[1] / max(n[1], 1),
-                phase_a_kernel_ms=ms[2] / max(n[2], 1),
-                boundary_cost_ratio=(ms[1] + ms[2]) / max(ms[0], 1e-9),
-                ms_per_step=sum(ms) / max(n[1], 1))
+        r = run_from_spec(lbm, spec, storage, stream, alloc, args.layout, args.bulk_tx, args.overlap)
+        results[storage] = measure(torch, lbm, r, spec, storage, args.steps, args.warmup,
+                                   args.prof_steps)
         if storage != "f64" and "f64" in results:
             rho_ref, ux_ref, uy_ref, T_ref = results["f64"]["_moments"]
             rho, ux, uy, T = r.moments()
@@ -241,10 +386,13 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(R["bulk_kernel_gbs"] / HBM_PEAK_GBS, 4) if R["bulk_kernel_gbs"] else None,
-            "traffic": None,
+            "traffic": recorded_traffic() if main_s == "f64" and args.L == 1024 and args.W == 32
+                       and args.bc == "nrbc" and args.layout == 0 and args.bulk_tx == 64 else None,
             "bytes_per_launch": R["bulk_bytes_per_launch"],
             "avg_launch_ms": round(R["bulk_kernel_ms"], 5),
             "device_copy_gbs": round(copy_gbs, 1) if copy_gbs else None,
+            "frac_of_device_copy": round(R["bulk_kernel_gbs"] / copy_gbs, 4)
+            if copy_gbs and R["bulk_kernel_gbs"] else None,
             "timing": "HIP events around each k_bulk launch on its stream inside the timed %d steps"
                       % args.steps,
         },
@@ -256,6 +404,11 @@ def main():
         return round(v, 6) if isinstance(v, float) else v
     for s, v in results.items():
         line["variants"][s] = rnd(v)
+    if args.large_steps > 0:
+        line["at_4224"] = rnd(large_leg(torch, lbm, wl, args))
+    if args.batch_runs > 0:
+        _log("bench: batch sweep")
+        line["batch"] = rnd(batch_leg(torch, lbm, wl, args))
     if args.serve_jobs > 0:
         _log("bench: serving trace")
         line["serving"] = serve_trace(args.serve_jobs, args.serve_rate, args.serve_scale, "f32", 200)

@@ -220,6 +220,18 @@ lbm_status lbm_group_remove(lbm_group_handle g, lbm_handle h);
  * member order as added; the group issues max(steps) batched steps and a run stops after its
  * own count.  Asynchronous. */
 lbm_status lbm_group_step(lbm_group_handle g, const int64_t *steps, int64_t nsteps);
+/* Launch configuration of the group's batched steps: bulk_tx/bulk_ty as for a run; with
+ * graph_steps = G > 0, lbm_group_step replays a captured HIP graph of G batched steps (runs
+ * past their own count skip every kernel, so one graph serves any mix of counts) and launches
+ * the remainder eagerly; the graph is recaptured after the membership changes.  overlap must
+ * be 0.  Default {64, 4, 32, 0}.  LBM_ERR_ARG for unsupported values. */
+lbm_status lbm_group_set_launch(lbm_group_handle g, const lbm_launch *cfg);
+lbm_status lbm_group_get_launch(lbm_group_handle g, lbm_launch *cfg);
+/* Time every bulk tile shape on a scratch group that holds one scratch run (mean state) per
+ * distinct member geometry (grid, PML, boundaries, storage, layout) and keep the fastest for
+ * this group.  The members' state is untouched; the scratch memory is freed before return.
+ * LBM_ERR_STATE for an empty group.  *chosen may be NULL. */
+lbm_status lbm_group_autotune(lbm_group_handle g, int32_t steps, lbm_launch *chosen);
 lbm_status lbm_group_size(lbm_group_handle g, int32_t *n);
 lbm_status lbm_group_synchronize(lbm_group_handle g);
 void lbm_group_destroy(lbm_group_handle g);

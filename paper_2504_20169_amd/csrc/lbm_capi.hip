@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -132,7 +133,10 @@ struct lbm_group {
     std::vector<lbm_run *> members;
     bool dirty = true;
     int storage = -1;
-    int tx = 64;
+    lbm_launch launch{64, 4, 32, 0};
+    hipGraphExec_t graph = nullptr;   // graph_G batched steps of the current membership
+    int graph_G = 0;
+    bool graph_failed = false;
     RunDev **druns = nullptr;
     int *dprefix = nullptr;
     long long *dlimits = nullptr;
@@ -393,30 +397,36 @@ void drop_graph(lbm_run *h) {
     h->graph_G = 0;
 }
 
-lbm_status build_graph(lbm_run *h, int G) {
-    drop_graph(h);
+// Capture G in-order steps of a launch set on stream s into an executable graph; nullptr if the
+// runtime refuses (the caller then launches eagerly).
+hipGraphExec_t capture_steps(const LaunchSet &L, int storage, int tx, hipStream_t s, int G) {
     hipGraph_t g = nullptr;
-    if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipGetLastError();
-        h->graph_failed = true;
-        return LBM_OK;
+        return nullptr;
     }
-    LaunchSet L = single_set(h);
     lbm_status st = LBM_OK;
-    for (int k = 0; k < G && st == LBM_OK; ++k)
-        st = enqueue_step(L, h->desc.storage, h->launch.bulk_tx, h->stream, nullptr, nullptr);
-    hipError_t e = hipStreamEndCapture(h->stream, &g);
+    for (int k = 0; k < G && st == LBM_OK; ++k) st = enqueue_step(L, storage, tx, s, nullptr, nullptr);
+    hipError_t e = hipStreamEndCapture(s, &g);
     if (st != LBM_OK || e != hipSuccess || !g) {
         (void)hipGetLastError();
         if (g) (void)hipGraphDestroy(g);
-        h->graph_failed = true;
-        return LBM_OK;
+        return nullptr;
     }
-    e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        h->graph = nullptr;
+        return nullptr;
+    }
+    return x;
+}
+
+lbm_status build_graph(lbm_run *h, int G) {
+    drop_graph(h);
+    h->graph = capture_steps(single_set(h), h->desc.storage, h->launch.bulk_tx, h->stream, G);
+    if (!h->graph) {
         h->graph_failed = true;
         return LBM_OK;
     }
@@ -1074,9 +1084,16 @@ lbm_status lbm_group_synchronize(lbm_group_handle g) {
     return LBM_OK;
 }
 
+static void group_drop_graph(lbm_group *g) {
+    if (g->graph) (void)hipGraphExecDestroy(g->graph);
+    g->graph = nullptr;
+    g->graph_G = 0;
+}
+
 static lbm_status group_rebuild(lbm_group *g) {
     const size_t n = g->members.size();
     HIP_TRY(hipStreamSynchronize(g->stream));
+    group_drop_graph(g);
     if (n > g->cap) {
         g->mem.put(g->druns); g->mem.put(g->dprefix); g->mem.put(g->dlimits);
         size_t cap = std::max<size_t>(n, 64);
@@ -1093,7 +1110,7 @@ static lbm_status group_rebuild(lbm_group *g) {
         lbm_run *h = g->members[k];
         ptrs[k] = h->dd;
         int nb[NCLS];
-        compute_blocks(h->hd, g->tx, nb);
+        compute_blocks(h->hd, g->launch.bulk_tx, nb);
         for (int c = 0; c < NCLS; ++c) { pre[c * (g->cap + 1) + k] = tot[c]; tot[c] += nb[c]; }
     }
     for (int c = 0; c < NCLS; ++c) pre[c * (g->cap + 1) + n] = tot[c];
@@ -1132,12 +1149,107 @@ lbm_status lbm_group_step(lbm_group_handle g, const int64_t *steps, int64_t nste
         L.blocks[c] = g->blocks[c];
     }
     L.nruns = (int)n;
-    for (int64_t k = 0; k < K; ++k) {
-        lbm_status st = enqueue_step(L, g->storage, g->tx, g->stream, nullptr, nullptr);
+    // Runs past their own count skip every kernel, so whole graphs of G batched steps serve any
+    // mix of counts; the remainder is launched eagerly.
+    int64_t left = K;
+    const int G = g->launch.graph_steps;
+    if (G > 0 && !g->graph_failed && K >= G) {
+        if (!g->graph || g->graph_G != G) {
+            group_drop_graph(g);
+            g->graph = capture_steps(L, g->storage, g->launch.bulk_tx, g->stream, G);
+            if (g->graph) g->graph_G = G;
+            else g->graph_failed = true;
+        }
+        if (g->graph) {
+            for (; left >= G; left -= G) HIP_TRY(hipGraphLaunch(g->graph, g->stream));
+        }
+    }
+    for (; left > 0; --left) {
+        lbm_status st = enqueue_step(L, g->storage, g->launch.bulk_tx, g->stream, nullptr, nullptr);
         if (st != LBM_OK) return st;
     }
     for (size_t k = 0; k < n; ++k) g->members[k]->steps += steps ? steps[k] : nsteps;
     return LBM_OK;
+}
+
+lbm_status lbm_group_set_launch(lbm_group_handle g, const lbm_launch *cfg) {
+    if (!g || !cfg) return fail(LBM_ERR_ARG, "NULL argument");
+    if (!(cfg->bulk_tx == 64 || cfg->bulk_tx == 128 || cfg->bulk_tx == 256) ||
+        cfg->bulk_tx * cfg->bulk_ty != 256)
+        return fail(LBM_ERR_ARG, "bulk tile must be 64x4, 128x2 or 256x1");
+    if (cfg->graph_steps < 0 || (cfg->graph_steps & 1)) return fail(LBM_ERR_ARG, "graph_steps must be even and >= 0");
+    if (cfg->overlap != 0) return fail(LBM_ERR_ARG, "groups run their kernels in order (overlap 0)");
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->launch = *cfg;
+    g->graph_failed = false;
+    g->dirty = true;   // block counts depend on the tile width; graphs are recaptured
+    return LBM_OK;
+}
+
+lbm_status lbm_group_get_launch(lbm_group_handle g, lbm_launch *cfg) {
+    if (!g || !cfg) return fail(LBM_ERR_ARG, "NULL argument");
+    *cfg = g->launch;
+    return LBM_OK;
+}
+
+lbm_status lbm_group_autotune(lbm_group_handle g, int32_t steps, lbm_launch *chosen) {
+    if (!g) return fail(LBM_ERR_ARG, "NULL argument");
+    if (g->members.empty()) return fail(LBM_ERR_STATE, "empty group");
+    if (steps < 1) steps = 10;
+    // one scratch run at the mean state per distinct geometry among the members
+    std::vector<lbm_run *> scratch;
+    std::vector<std::array<long long, 12>> keys;
+    lbm_status st = LBM_OK;
+    for (lbm_run *h : g->members) {
+        std::array<long long, 12> key{h->desc.nx, h->desc.ny, h->desc.storage, h->desc.layout, h->W,
+                                      h->pml[0] | h->pml[1] << 1 | h->pml[2] << 2 | h->pml[3] << 3,
+                                      h->bc[0], h->bc[1], h->bc[2], h->bc[3], 0, 0};
+        if (std::find(keys.begin(), keys.end(), key) != keys.end()) continue;
+        keys.push_back(key);
+        lbm_desc d = h->desc;
+        d.stream = (void *)g->stream;
+        lbm_handle s = nullptr;
+        st = lbm_create(&d, &s);
+        if (st != LBM_OK) break;
+        scratch.push_back(s);
+        s->W = h->W; s->sigma_max = h->sigma_max;
+        for (int k = 0; k < 4; ++k) { s->pml[k] = h->pml[k]; s->bc[k] = h->bc[k]; }
+        const size_t nn = (size_t)(h->hd.Nx) * h->hd.Ny;
+        std::vector<double> f1(nn, d.rho0), f2(nn, d.ux0), f3(nn, d.uy0), f4(nn, d.T0);
+        st = lbm_init_fields(s, f1.data(), f2.data(), f3.data(), f4.data());
+        if (st != LBM_OK) break;
+    }
+    lbm_launch best_c = g->launch;
+    if (st == LBM_OK) {
+        lbm_group_handle sg = nullptr;
+        st = lbm_group_create((void *)g->stream, g->mem.alloc, &sg);
+        for (size_t k = 0; st == LBM_OK && k < scratch.size(); ++k) st = lbm_group_add(sg, scratch[k]);
+        float best = 1e30f;
+        hipEvent_t a = nullptr, b = nullptr;
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        for (int tx : {64, 128, 256}) {
+            if (st != LBM_OK) break;
+            lbm_launch c{tx, 256 / tx, 0, 0};
+            if ((st = lbm_group_set_launch(sg, &c)) != LBM_OK) break;
+            if ((st = lbm_group_step(sg, nullptr, 2)) != LBM_OK) break;
+            (void)hipEventRecord(a, g->stream);
+            if ((st = lbm_group_step(sg, nullptr, steps)) != LBM_OK) break;
+            (void)hipEventRecord(b, g->stream);
+            (void)hipEventSynchronize(b);
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, a, b);
+            if (ms < best) { best = ms; best_c = g->launch; best_c.bulk_tx = tx; best_c.bulk_ty = 256 / tx; }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        if (sg) lbm_group_destroy(sg);
+    }
+    for (lbm_run *s : scratch) lbm_destroy(s);
+    if (st != LBM_OK) return st;
+    st = lbm_group_set_launch(g, &best_c);
+    if (chosen) *chosen = g->launch;
+    return st;
 }
 
 void lbm_group_destroy(lbm_group_handle g) {
@@ -1147,6 +1259,7 @@ void lbm_group_destroy(lbm_group_handle g) {
         h->group = nullptr;
         h->stream = h->own_stream ? h->own_stream : (hipStream_t)h->desc.stream;
     }
+    group_drop_graph(g);
     g->mem.release_all();
     if (g->hlimits) (void)hipHostFree(g->hlimits);
     if (g->upload_done) (void)hipEventDestroy(g->upload_done);

@@ -35,7 +35,7 @@ EXPORTED = [
     "lbm_get_launch", "lbm_autotune", "lbm_profile", "lbm_profile_read", "lbm_save",
     "lbm_load", "lbm_destroy", "lbm_last_error", "lbm_group_create", "lbm_group_add",
     "lbm_group_remove", "lbm_group_step", "lbm_group_size", "lbm_group_synchronize",
-    "lbm_group_destroy",
+    "lbm_group_set_launch", "lbm_group_get_launch", "lbm_group_autotune", "lbm_group_destroy",
 ]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -102,6 +102,9 @@ def load():
         "lbm_set_launch": [H, ctypes.POINTER(lbm_launch)],
         "lbm_get_launch": [H, ctypes.POINTER(lbm_launch)],
         "lbm_autotune": [H, ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(lbm_launch)],
+        "lbm_group_set_launch": [H, ctypes.POINTER(lbm_launch)],
+        "lbm_group_get_launch": [H, ctypes.POINTER(lbm_launch)],
+        "lbm_group_autotune": [H, ctypes.c_int32, ctypes.POINTER(lbm_launch)],
         "lbm_profile": [H, ctypes.c_int],
         "lbm_profile_read": [H, dp, i64p, ctypes.c_int],
         "lbm_save": [H, ctypes.c_char_p],
@@ -351,6 +354,22 @@ class Group:
 
     def synchronize(self):
         _check(self._lib.lbm_group_synchronize(self.g))
+
+    def set_launch(self, bulk_tx=64, graph_steps=32):
+        c = lbm_launch(int(bulk_tx), 256 // int(bulk_tx), int(graph_steps), 0)
+        _check(self._lib.lbm_group_set_launch(self.g, ctypes.byref(c)))
+
+    def get_launch(self):
+        c = lbm_launch()
+        _check(self._lib.lbm_group_get_launch(self.g, ctypes.byref(c)))
+        return dict(bulk_tx=c.bulk_tx, bulk_ty=c.bulk_ty, graph_steps=c.graph_steps,
+                    overlap=c.overlap)
+
+    def autotune(self, steps=10):
+        c = lbm_launch()
+        _check(self._lib.lbm_group_autotune(self.g, int(steps), ctypes.byref(c)))
+        return dict(bulk_tx=c.bulk_tx, bulk_ty=c.bulk_ty, graph_steps=c.graph_steps,
+                    overlap=c.overlap)
 
     def size(self):
         n = ctypes.c_int32()

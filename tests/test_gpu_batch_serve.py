@@ -52,6 +52,45 @@ def test_batch_equals_alone(storage):
     g.close()
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_group_graphs_and_autotune_keep_bits(storage):
+    """Graph replays of batched steps (uneven counts, membership change in between) and the
+    group autotuner change launches, never results."""
+    alone = []
+    for k, (L, W, bc, n) in enumerate(CASES):
+        r = _make(L, W, bc, storage, 60 + k)
+        r.step(n + 9)
+        alone.append(r.populations())
+        r.close()
+    g = lbm.Group()
+    runs = [_make(L, W, bc, storage, 60 + k) for k, (L, W, bc, n) in enumerate(CASES)]
+    for r in runs:
+        g.add(r)
+    with pytest.raises(lbm.LbmError):
+        g.set_launch(bulk_tx=64, graph_steps=3)
+    g.set_launch(bulk_tx=128, graph_steps=4)
+    assert g.get_launch() == dict(bulk_tx=128, bulk_ty=2, graph_steps=4, overlap=0)
+    before = [r.populations() for r in runs]
+    c = g.autotune(steps=3)
+    assert c["bulk_tx"] in (64, 128, 256) and c["graph_steps"] == 4
+    for r, b in zip(runs, before):          # scratch runs only: members untouched
+        assert np.array_equal(r.populations(), b)
+    steps = np.array([c[3] for c in CASES])
+    g.step(steps=steps)                     # graphs of 4 batched steps, uneven counts
+    extra = runs.pop(2)
+    g.remove(extra)                         # membership change: graph recaptured
+    extra.step(9)
+    g.step(nsteps=9)
+    g.synchronize()
+    runs.insert(2, extra)
+    for r, a, cs in zip(runs, alone, CASES):
+        assert r.step_count == cs[3] + 9
+        assert np.array_equal(r.populations(), a), cs
+    g.close()
+    for r in runs:
+        r.close()
+
+
 def test_served_results_equal_alone():
     """Jobs arriving while others are on the GPU give bitwise the same moments as alone; a job
     forced unstable from the host is retired as failed without disturbing the rest."""
