@@ -162,16 +162,21 @@ def batch_leg(torch, lbm, wl, args):
                          "vortex + pulse, sigma_max 0.0015, FP32 storage")
 
 
-KERNEL_SRC = os.path.join(ROOT, "paper_2504_20169_amd", "csrc", "lbm_kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2504_20169_amd", "csrc", n)
+              for n in ("lbm_kernels.hip", "lbm_capi.hip", "lbm_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bulk_f64_1088sq_nrbc_pmc.txt")
 BULK_F64 = "void lbm::k_bulk<double, 64>(lbm::RunDev* const*, int const*, int)"
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources and of the runtime that lays out their data."""
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in KERNEL_SRC:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def pmc_means(path, counter):

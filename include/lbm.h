@@ -87,6 +87,10 @@ typedef struct {
                                     side stream beside the bulk kernel) */
     int32_t layout;              /* population layout in HBM: 0 = the 37 population rows of each
                                     grid row adjacent (default), 1 = one plane per velocity */
+    int32_t row_pad;             /* layout 0: extra elements after each population row (rows
+                                    are first rounded up to 64 elements); 0 = automatic (64 for
+                                    FP64 and FP32 storage, none for FP16: the fastest measured on
+                                    large grids), -1 = none, 1..4096 = that many elements */
 } lbm_desc;
 
 /* Launch configuration (set by lbm_set_launch or lbm_autotune).  bulk_tx in {64,128,256}

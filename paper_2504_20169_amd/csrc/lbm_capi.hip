@@ -195,7 +195,11 @@ lbm_status setup_geometry(lbm_run *h, RunDev &R) {
     long long fast = (long long)std::max(0, R.fx1 - R.fx0) * std::max(0, R.fy1 - R.fy0);
     R.frame_n = (int)((long long)R.Nx * R.Ny - fast);
     R.has_q = h->W > 0 && (h->pml[0] || h->pml[1] || h->pml[2] || h->pml[3]);
-    const long long row = round_up(R.Nx, 64);
+    // Padding each population row past the 64-element rounding staggers the 74 row streams of a
+    // bulk tile across HBM channels: +4% bulk bandwidth at 4224^2 in FP64 and FP32 (64 elements);
+    // FP16 measured best without it.
+    const int pad = d.row_pad > 0 ? d.row_pad : d.row_pad < 0 ? 0 : (d.storage == ST_F16 ? 0 : 64);
+    const long long row = round_up(R.Nx, 64) + (d.layout == 0 ? pad : 0);
     if (d.layout == 0) {            // rows: the 37 population rows of a grid row adjacent
         R.plane = row;
         R.pitch = (int)(NQ * row);
@@ -487,6 +491,7 @@ lbm_status lbm_create(const lbm_desc *desc, lbm_handle *out) {
         return fail(LBM_ERR_ARG, "mean state must be finite with rho0 > 0 and T0 > 0");
     if (d.storage < LBM_F64 || d.storage > LBM_F16_DEV) return fail(LBM_ERR_ARG, "unknown storage");
     if (d.layout != 0 && d.layout != 1) return fail(LBM_ERR_ARG, "unknown layout");
+    if (d.row_pad < -1 || d.row_pad > 4096) return fail(LBM_ERR_ARG, "row_pad must be in -1..4096");
     if (d.storage == LBM_F16_DEV && d.f16_scale != 0.0) {
         int ex;
         double m = std::frexp(d.f16_scale, &ex);

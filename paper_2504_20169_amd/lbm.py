@@ -51,7 +51,8 @@ class lbm_desc(ctypes.Structure):
                 ("rho0", ctypes.c_double), ("ux0", ctypes.c_double), ("uy0", ctypes.c_double),
                 ("T0", ctypes.c_double), ("storage", ctypes.c_int32),
                 ("f16_scale", ctypes.c_double), ("allocator", ctypes.POINTER(lbm_allocator)),
-                ("stream", ctypes.c_void_p), ("layout", ctypes.c_int32)]
+                ("stream", ctypes.c_void_p), ("layout", ctypes.c_int32),
+                ("row_pad", ctypes.c_int32)]
 
 
 class lbm_launch(ctypes.Structure):
@@ -186,7 +187,7 @@ class Run:
     """One simulation handle (create -> set_pml / set_bc -> init -> step ...)."""
 
     def __init__(self, nx, ny, tau=0.8, rho0=1.0, ux0=0.0, uy0=0.0, T0=1.0, storage="f64",
-                 f16_scale=0.0, stream=None, allocator=None, layout=0):
+                 f16_scale=0.0, stream=None, allocator=None, layout=0, row_pad=0):
         lib = load()
         self._lib = lib
         self._alloc = allocator
@@ -194,7 +195,7 @@ class Run:
                      float(T0), STORAGE[storage] if isinstance(storage, str) else int(storage),
                      float(f16_scale),
                      ctypes.pointer(allocator) if allocator is not None else None,
-                     _stream_ptr(stream), int(layout))
+                     _stream_ptr(stream), int(layout), int(row_pad))
         h = ctypes.c_void_p()
         _check(lib.lbm_create(ctypes.byref(d), ctypes.byref(h)))
         self.h = h

@@ -1,0 +1,155 @@
+"""The paper's accuracy-versus-cost study on the one-dimensional density step (Sec. 5.1), run on
+the HIP library.
+
+Setup (Sec. 5.1): bulk Lx x Ly = 200 x 20, periodic along y, artificial boundaries on the two x
+sides; background velocity Mach 0.05 along +x, T = 1, density plateau rho1 = 1.05 between two
+tanh fronts of steepness s = 0.5 on a rho0 = 1 background; the mean equilibrium of the PML is
+taken at (rho0, u0, T0).  Each configuration is a boundary (ZG, or the perfectly non-reflecting
+LODI boundary) with or without a PML of width W on both x sides, with the D2Q37 sigma_max of the
+paper's Table "Values of sigma_max used for the density step test case".
+
+Reference (Sec. 5, Reference Simulation): the same initial data embedded in a fully periodic
+grid extended on both x sides far enough that no wave wraps round into the bulk window during
+the run.  Errors: e_Z(n) = sqrt(sum_bulk ((Z - Zref)/Zref)^2) at sampled steps n (lbm_error_norms,
+FP64 on the device), their mean over the samples ebar_Z, C_Z = ebar_Z / ebar_Z(ZG without PML),
+and C_t = t_BC / t_BC(ZG without PML), t_BC the event-timed wall time of the boundary and PML
+kernels (phase A and the frame kernel).
+
+Reading: the printed right-hand branch of the step profile does not meet the left-hand branch at
+x = Lx/2; it is taken as the mirror image of the left branch, rho1 - (rho1-rho0)/2 (tanh(s (x -
+3Lx/4)) + 1), so the plateau is rho1 and both far ends are rho0.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+# D2Q37 sigma_max from the paper's density-step table, by boundary and PML width
+SIGMA_D2Q37 = {("zg", 10): 0.35, ("zg", 20): 0.175, ("zg", 40): 0.10,
+               ("nrbc", 10): 0.001, ("nrbc", 20): 0.10, ("nrbc", 40): 0.06}
+
+
+def step_profile(xb, Lx, rho0=1.0, rho1=1.05, s=0.5):
+    """Density at bulk coordinate xb (cells, 0 = first bulk column)."""
+    xb = np.asarray(xb, dtype=np.float64)
+    left = rho1 + 0.5 * (rho1 - rho0) * (np.tanh(s * (xb - 0.25 * Lx)) - 1.0)
+    right = rho1 - 0.5 * (rho1 - rho0) * (np.tanh(s * (xb - 0.75 * Lx)) + 1.0)
+    return np.where(xb <= 0.5 * Lx, left, right)
+
+
+def step_fields(Lx, Ly, x_offset, Nx, mach=0.05, rho0=1.0, rho1=1.05, s=0.5):
+    """(rho, ux, uy, T) on an Nx x Ly grid whose bulk window starts at column x_offset; outside
+    [0, Lx) in bulk coordinates the density is rho0."""
+    xb = np.arange(Nx, dtype=np.float64) - x_offset
+    rho = np.where((xb >= 0) & (xb < Lx), step_profile(xb, Lx, rho0, rho1, s), rho0)
+    rho = np.broadcast_to(rho, (Ly, Nx)).copy()
+    return rho, np.full((Ly, Nx), mach), np.zeros((Ly, Nx)), np.ones((Ly, Nx))
+
+
+def _make(lbm, Lx, Ly, bc, W, sigma, mach, storage, fields, tau):
+    r = lbm.Run(Lx, Ly, tau, 1.0, mach, 0.0, 1.0, storage=storage)
+    r.set_bc(lbm.LBM_YMIN | lbm.LBM_YMAX, "periodic")
+    r.set_bc(lbm.LBM_XMIN | lbm.LBM_XMAX, bc)
+    if W > 0:
+        r.set_pml(lbm.LBM_XMIN | lbm.LBM_XMAX, W, sigma)
+    r.init(*fields)
+    return r
+
+
+def density_step_study(steps=600, sample=10, Lx=200, Ly=20, mach=0.05, tau=0.8,
+                       widths=(0, 10, 20, 40), bcs=("zg", "nrbc"), storage="f64", configs=None):
+    """Run every (boundary, W, sigma_max) configuration and the periodic reference in lock step.
+    configs: list of (bc, W, sigma_max); default: bcs x widths with the paper's D2Q37 table.
+    Returns a list of dicts (bc, W, sigma_max, stable, ebar_rho, ebar_ux, emax_*, t_bc_ms, and
+    C_rho, C_ux, C_t against ZG without PML when that configuration is in the list) and the
+    reference's grid width."""
+    from paper_2504_20169_amd import lbm
+
+    if configs is None:
+        configs = [(bc, W, SIGMA_D2Q37.get((bc, W), 0.0) if W > 0 else 0.0)
+                   for bc in bcs for W in widths]
+    # sound travels sqrt(2)/r = 1.18 cells per step; D2Q37 carries signals up to 3 cells per step
+    ext = int(math.ceil(3.0 * steps)) + 16
+    Nref = Lx + 2 * ext
+    ref = _make(lbm, Nref, Ly, "periodic", 0, 0.0, mach, storage,
+                step_fields(Lx, Ly, ext, Nref, mach), tau)
+    runs = []
+    for bc, W, s in configs:
+        r = _make(lbm, Lx, Ly, bc, W, s, mach, storage, step_fields(Lx, Ly, W, Lx + 2 * W, mach), tau)
+        r.profile(1)
+        runs.append((bc, W, s, r, []))
+    done = 0
+    while done < steps:
+        n = min(sample, steps - done)
+        ref.step(n)
+        for run in runs:
+            run[3].step(n)
+        done += n
+        rho, ux, _, T = ref.moments()
+        win = (slice(None), slice(ext, ext + Lx))
+        for run in runs:
+            run[4].append(run[3].error_norms(rho[win], ux[win], T[win]))
+    out = []
+    for bc, W, s, r, errs in runs:
+        ms, n = r.profile_read()
+        e = np.array(errs)
+        ok = r.check() == lbm.LBM_OK and np.all(np.isfinite(e))
+        out.append(dict(bc=bc, W=W, sigma_max=s, stable=bool(ok),
+                        ebar_rho=float(e[:, 0].mean()), ebar_ux=float(e[:, 1].mean()),
+                        emax_rho=float(e[:, 0].max()), emax_ux=float(e[:, 1].max()),
+                        t_bc_ms=float(ms[1] + ms[2]), steps=steps))
+        r.close()
+    ref.close()
+    base = next((d for d in out if d["bc"] == "zg" and d["W"] == 0), None)
+    if base is not None:
+        for d in out:
+            d["C_rho"] = d["ebar_rho"] / base["ebar_rho"]
+            d["C_ux"] = d["ebar_ux"] / base["ebar_ux"]
+            d["C_t"] = d["t_bc_ms"] / base["t_bc_ms"] if base["t_bc_ms"] > 0 else None
+    return out, Nref
+
+
+def sigma_scan(steps=600, sigmas=None, widths=(10, 20, 40), bcs=("zg", "nrbc"), storage="f64"):
+    """The paper tunes sigma_max per boundary and width by a parameter scan; the same scan for
+    this implementation.  Returns (rows, best): every configuration's result, and per (bc, W) the
+    stable sigma_max with the lowest mean density error."""
+    if sigmas is None:
+        sigmas = [0.0005, 0.001, 0.002, 0.005, 0.01, 0.02, 0.05, 0.1, 0.175, 0.35, 0.6]
+    configs = [("zg", 0, 0.0), ("nrbc", 0, 0.0)]
+    configs += [(bc, W, s) for bc in bcs for W in widths for s in sigmas]
+    rows, _ = density_step_study(steps=steps, storage=storage, configs=configs)
+    best = {}
+    for d in rows:
+        if d["W"] == 0 or not d["stable"]:
+            continue
+        k = (d["bc"], d["W"])
+        if k not in best or d["ebar_rho"] < best[k]["ebar_rho"]:
+            best[k] = d
+    return rows, best
+
+
+def main():
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser(description="density-step accuracy vs cost study (Sec. 5.1)")
+    ap.add_argument("--steps", type=int, default=600)
+    ap.add_argument("--sample", type=int, default=10)
+    ap.add_argument("--storage", default="f64")
+    ap.add_argument("--scan", action="store_true", help="also scan sigma_max per boundary and W")
+    args = ap.parse_args()
+    t0 = time.perf_counter()
+    rows, nref = density_step_study(args.steps, args.sample, storage=args.storage)
+    for d in rows:
+        print(json.dumps(d))
+    if args.scan:
+        _, best = sigma_scan(args.steps, storage=args.storage)
+        for (bc, W), d in sorted(best.items()):
+            print(json.dumps(dict(scan_best=True, **d)))
+    print(json.dumps(dict(reference_grid=[nref, 20], seconds=time.perf_counter() - t0)))
+
+
+if __name__ == "__main__":
+    main()

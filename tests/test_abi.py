@@ -43,7 +43,8 @@ def test_velocity_table_matches_oracle(oracle_mod):
 
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.3), dict(nx=0), dict(ny=-1),
                                 dict(rho0=0.0), dict(T0=-1.0), dict(storage=7),
-                                dict(rho0=float("nan")), dict(storage="f16", f16_scale=3.0)])
+                                dict(rho0=float("nan")), dict(storage="f16", f16_scale=3.0),
+                                dict(layout=2), dict(row_pad=-2), dict(row_pad=5000)])
 def test_create_rejects_bad_descriptor(kw):
     args = dict(nx=16, ny=16, tau=0.8)
     args.update(kw)
@@ -83,6 +84,19 @@ def test_launch_configuration_validated_on_host():
         r.profile(3)
     r.profile(2)
     r.profile(0)
+
+
+def test_row_padding_in_footprint():
+    """Population rows are padded by 64 elements by default for FP64/FP32 storage, not FP16."""
+    def fp(**kw):
+        r = lbm.Run(100, 50, 0.8, **kw)
+        return r.footprint()
+    rows = 2 * 37 * 50  # two buffers x 37 population rows per grid row x Ny
+    assert fp(row_pad=0) - fp(row_pad=-1) == rows * 64 * 8
+    assert fp(row_pad=10) - fp(row_pad=-1) == rows * 10 * 8
+    assert fp(storage="f32") - fp(storage="f32", row_pad=-1) == rows * 64 * 4
+    assert fp(storage="f16") == fp(storage="f16", row_pad=-1)
+    assert fp(layout=1, row_pad=10) == fp(layout=1, row_pad=-1)
 
 
 def test_init_rejects_inconsistent_configuration():
