@@ -121,6 +121,15 @@ lbm_status lbm_set_pml(lbm_handle h, unsigned side_mask, int32_t W, double sigma
  * checked by lbm_init_fields. */
 lbm_status lbm_set_bc(lbm_handle h, unsigned side_mask, lbm_bc kind);
 
+/* Appendix (eq. NSF-CHAR-PML): make the characteristic boundary consistent with the PML by
+ * adding, at NRBC boundary nodes inside a PML (sigma > 0), the velocity moments of the PML
+ * collision term to the one-step target update: bit 0 term I (divergence of the auxiliary flux
+ * moments, sum_i phi_i e_i . grad Q_i), bit 1 term II (2 (U - Ubar)), bit 2 term III
+ * (sigma sum_i phi_i Q_i), phi = (1, xi, |xi|^2/2), entering as +sigma (I + II + III) in
+ * conserved variables (the appendix's signs) and converted to (rho, u, T) at U^n.  Default 0: the plain LODI target of
+ * Sec. 4.  Errors: LBM_ERR_ARG for bits outside 0..2; LBM_ERR_STATE after init. */
+lbm_status lbm_set_nrbc_pml_terms(lbm_handle h, unsigned flags);
+
 /* Full grid size (bulk plus PML layers) for the current configuration. */
 lbm_status lbm_grid(lbm_handle h, int32_t *Nx, int32_t *Ny);
 

@@ -50,6 +50,7 @@ def _load():
     lib.orc_destroy.argtypes = [P]
     lib.orc_set_pml.argtypes = [P, ctypes.c_uint, ctypes.c_int, ctypes.c_double]
     lib.orc_set_bc.argtypes = [P, ctypes.c_uint, ctypes.c_int]
+    lib.orc_set_nrbc_pml_terms.argtypes = [P, ctypes.c_uint]
     lib.orc_grid.argtypes = [P, ip, ip]
     lib.orc_init.argtypes = [P, dp, dp, dp, dp]
     lib.orc_step.argtypes = [P, ctypes.c_long, ctypes.c_int]
@@ -134,6 +135,11 @@ class OracleRun:
 
     def set_bc(self, mask, kind):
         _check(self._lib.orc_set_bc(self._h, int(mask), int(kind)))
+
+    def set_nrbc_pml_terms(self, flags):
+        """Appendix: moments of the PML collision term in the characteristic target update
+        (bit 0 term I, bit 1 term II, bit 2 term III)."""
+        _check(self._lib.orc_set_nrbc_pml_terms(self._h, int(flags)))
 
     def grid(self):
         nx, ny = ctypes.c_int(), ctypes.c_int()

@@ -224,6 +224,7 @@ typedef struct orc_run {
     double *U;   /* U^n = (rho, ux, uy, T) of the post-stream, post-boundary state, [node][4] */
     double *Un;  /* U^{n+1} */
     double fbar[NQ];
+    unsigned pml_terms;   /* appendix: PML moments in the characteristic target (bits I, II, III) */
 } orc_run;
 
 static char orc_err[256];
@@ -273,6 +274,15 @@ int orc_set_pml(orc_run *r, unsigned mask, int W, double sigma_max) {
     if (W < 0 || sigma_max < 0) return fail("bad PML");
     r->W = W; r->sigma_max = sigma_max;
     for (int s = 0; s < 4; ++s) r->pml[s] = (W > 0) && ((mask >> s) & 1u);
+    return 0;
+}
+
+/* Appendix (eq. NSF-CHAR-PML): which moments of the PML collision term enter the target
+ * update of characteristic boundary nodes: bit 0 term I, bit 1 term II, bit 2 term III. */
+int orc_set_nrbc_pml_terms(orc_run *r, unsigned flags) {
+    if (r->ready) return fail("configure before init");
+    if (flags > 7u) return fail("bad PML term flags");
+    r->pml_terms = flags;
     return 0;
 }
 
@@ -414,6 +424,59 @@ static void lodi_increment(const orc_run *r, int side, int x, int y, double dU[4
     else    { dU[2] = ny * d[1]; dU[1] = d[2]; }
 }
 
+/* d Q_i / d alpha at (x, y), alpha = 0 (x) or 1 (y): central differences, one-sided second
+ * order at the outermost layer of an open axis (eqs. FD-dx-center, FD-dx-bw). */
+static double grad_q(const orc_run *r, int x, int y, int i, int al) {
+    const int Nx = r->Nx, Ny = r->Ny;
+    int c = al ? y : x, nmax = al ? Ny : Nx, op = al ? open_y(r) : open_x(r);
+#define QAT(cc) (al ? r->Qa[((size_t)(cc) * Nx + x) * NQ + i] : r->Qa[((size_t)y * Nx + (cc)) * NQ + i])
+    double d;
+    if (op && c == 0)
+        d = -0.5 * (3.0 * QAT(0) - 4.0 * QAT(1) + QAT(2));
+    else if (op && c == nmax - 1)
+        d = 0.5 * (3.0 * QAT(nmax - 1) - 4.0 * QAT(nmax - 2) + QAT(nmax - 3));
+    else {
+        int cp = c + 1, cm = c - 1;
+        if (!op) { cp = (cp + nmax) % nmax; cm = (cm + nmax) % nmax; }
+        d = 0.5 * (QAT(cp) - QAT(cm));
+    }
+#undef QAT
+    return d;
+}
+
+/* Appendix, eq. NSF-CHAR-PML: with a PML the macroscopic equations carry extra source terms
+ * built from the auxiliary moments, phi = (1, xi_x, xi_y, |xi|^2/2):
+ *   I = sum_i phi_i e_i . grad Q_i,  II = 2 sum_i phi_i fhat_i,  III = sigma sum_i phi_i Q_i,
+ * in conserved variables (rho, rho u, rho (|u|^2/2 + T)).  Over one step the selected terms move
+ * the characteristic target by s = +sigma (I + II + III), the signs printed in the appendix,
+ * converted to the primitive (rho, ux, uy, T) at U^n by the chain rule.  Q and U are those of
+ * level n. */
+static void pml_source(const orc_run *r, int x, int y, double dU[4]) {
+    dU[0] = dU[1] = dU[2] = dU[3] = 0.0;
+    const double sg = sigma_at(r, x, y);
+    if (!(sg > 0.0) || !r->pml_terms) return;
+    const size_t n = (size_t)y * r->Nx + x;
+    const double *u = r->U + 4 * n;
+    double fe[NQ];
+    feq37(u[0], u[1], u[2], u[3], fe);
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < NQ; ++i) {
+        double xi_x = LR * LE[i][0], xi_y = LR * LE[i][1];
+        double phi[4] = {1.0, xi_x, xi_y, 0.5 * (xi_x * xi_x + xi_y * xi_y)};
+        double a = 0.0;
+        if (r->pml_terms & 1u) a += LE[i][0] * grad_q(r, x, y, i, 0) + LE[i][1] * grad_q(r, x, y, i, 1);
+        if (r->pml_terms & 2u) a += 2.0 * (fe[i] - r->fbar[i]);
+        if (r->pml_terms & 4u) a += sg * r->Qa[n * NQ + i];
+        for (int k = 0; k < 4; ++k) s[k] += phi[k] * a;
+    }
+    for (int k = 0; k < 4; ++k) s[k] *= sg;
+    const double rho = u[0], ux = u[1], uy = u[2], T = u[3];
+    dU[0] = s[0];
+    dU[1] = (s[1] - ux * s[0]) / rho;
+    dU[2] = (s[2] - uy * s[0]) / rho;
+    dU[3] = (s[3] - ux * s[1] - uy * s[2] + (0.5 * (ux * ux + uy * uy) - T) * s[0]) / rho;
+}
+
 static int is_boundary_side(const orc_run *r, int side, int x, int y) {
     if (r->bc[side] == BC_PERIODIC) return 0;
     switch (side) {
@@ -470,6 +533,11 @@ static void one_step(orc_run *r) {
                     lodi_increment(r, s, x, y, d);
                     for (int k = 0; k < 4; ++k) Ut[k] += d[k];
                 }
+            {
+                double d[4];
+                pml_source(r, x, y, d);
+                for (int k = 0; k < 4; ++k) Ut[k] += d[k];
+            }
             double Uf[4], ft[NQ], ff[NQ];
             moments37(gf, Uf);
             feq37(Ut[0], Ut[1], Ut[2], Ut[3], ft);

@@ -97,6 +97,7 @@ struct lbm_run {
     int W = 0;
     double sigma_max = 0.0;
     int bc[4] = {BC_PERIODIC, BC_PERIODIC, BC_PERIODIC, BC_PERIODIC};
+    unsigned pml_terms = 0;
     bool inited = false;
     RunDev hd{};
     RunDev *dd = nullptr;
@@ -160,6 +161,7 @@ lbm_status setup_geometry(lbm_run *h, RunDev &R) {
     R.Ny = d.ny + R.Wym + R.Wyp;
     R.W = h->W;
     for (int s = 0; s < 4; ++s) R.bc[s] = h->bc[s];
+    R.pml_terms = (int)h->pml_terms;
     if ((h->bc[XMIN] == BC_PERIODIC) != (h->bc[XMAX] == BC_PERIODIC) ||
         (h->bc[YMIN] == BC_PERIODIC) != (h->bc[YMAX] == BC_PERIODIC))
         return fail(LBM_ERR_ARG, "periodic must be set on both sides of an axis");
@@ -281,6 +283,7 @@ size_t footprint_of(const RunDev &R, int storage) {
     if (R.has_q) b += (size_t)NQ * R.qplane * compute_size(storage);
     b += 2 * 4 * (size_t)R.qplane * sizeof(double);
     if (R.ring_n > 0) b += (size_t)NQ * R.rplane * compute_size(storage);
+    if (R.pml_terms && R.ring_n > 0) b += 4 * (size_t)R.rplane * sizeof(double);
     b += sizeof(RunDev) + 256 * 3 + NQ * sizeof(double);
     return b;
 }
@@ -292,7 +295,7 @@ void compute_blocks(const RunDev &R, int tx, int nb[NCLS]) {
     const int rb = (R.ring_n + RING_BLOCK - 1) / RING_BLOCK;
     nb[CLS_FRAME] = rb + fb;
     nb[CLS_A] = rb + (R.has_q ? fb : 0);
-    nb[CLS_RING] = (R.ring_n + FRAME_BLOCK - 1) / FRAME_BLOCK;   // k_nrbc: full blocks
+    nb[CLS_PM] = R.pml_terms ? rb : 0;
 }
 
 lbm_status upload_prefix(lbm_run *h) {
@@ -365,6 +368,7 @@ lbm_status enqueue_step(const LaunchSet &L, int storage, int tx, hipStream_t s, 
     const bool classes = mode == 1;
     if (!ss || !ss->ok || classes) {
         if (classes && has_a) HIP_TRY(hipEventRecord(ev[4], s));
+        HIP_TRY(launch_pml_moments(L, storage, s));
         HIP_TRY(launch_phase_a(L, storage, s));
         if (classes && has_a) HIP_TRY(hipEventRecord(ev[5], s));
         if (classes && has_f) HIP_TRY(hipEventRecord(ev[2], s));
@@ -376,6 +380,7 @@ lbm_status enqueue_step(const LaunchSet &L, int storage, int tx, hipStream_t s, 
     } else {
         HIP_TRY(hipEventRecord(ss->fork, s));
         HIP_TRY(hipStreamWaitEvent(ss->side, ss->fork, 0));
+        HIP_TRY(launch_pml_moments(L, storage, ss->side));
         HIP_TRY(launch_phase_a(L, storage, ss->side));
         HIP_TRY(launch_frame(L, storage, ss->side));
         HIP_TRY(hipEventRecord(ss->done, ss->side));
@@ -529,6 +534,14 @@ lbm_status lbm_set_bc(lbm_handle h, unsigned mask, lbm_bc kind) {
     return LBM_OK;
 }
 
+lbm_status lbm_set_nrbc_pml_terms(lbm_handle h, unsigned flags) {
+    if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+    if (h->inited) return fail(LBM_ERR_STATE, "configure before lbm_init_fields");
+    if (flags & ~7u) return fail(LBM_ERR_ARG, "PML term flags must be a subset of bits 0..2");
+    h->pml_terms = flags;
+    return LBM_OK;
+}
+
 lbm_status lbm_grid(lbm_handle h, int32_t *Nx, int32_t *Ny) {
     if (!h || !Nx || !Ny) return fail(LBM_ERR_ARG, "NULL argument");
     int wx = (h->pml[XMIN] ? h->W : 0) + (h->pml[XMAX] ? h->W : 0);
@@ -594,11 +607,13 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux, co
     }
     R.Q = R.has_q ? h->mem.get((size_t)NQ * R.qplane * cs) : nullptr;
     R.G = R.ring_n > 0 ? h->mem.get((size_t)NQ * R.rplane * cs) : nullptr;
+    const bool need_p = R.pml_terms && R.ring_n > 0;
+    R.P = need_p ? (double *)h->mem.get(4 * (size_t)R.rplane * sizeof(double)) : nullptr;
     h->dd = (RunDev *)h->mem.get(sizeof(RunDev));
     h->dptr = (RunDev **)h->mem.get(sizeof(RunDev *));
     h->dprefix = (int *)h->mem.get(2 * NCLS * sizeof(int));
     h->fbar_d = (double *)h->mem.get(NQ * sizeof(double));
-    if ((R.has_q && !R.Q) || (R.ring_n > 0 && !R.G) || !h->dd || !h->dptr || !h->dprefix || !h->fbar_d) {
+    if ((R.has_q && !R.Q) || (R.ring_n > 0 && !R.G) || (need_p && !R.P) || !h->dd || !h->dptr || !h->dprefix || !h->fbar_d) {
         h->mem.release_all();
         return fail(LBM_ERR_OOM, "device allocation failed");
     }
@@ -608,6 +623,7 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux, co
     }
     if (R.Q) HIP_TRY(hipMemsetAsync(R.Q, 0, (size_t)NQ * R.qplane * cs, h->stream));
     if (R.G) HIP_TRY(hipMemsetAsync(R.G, 0, (size_t)NQ * R.rplane * cs, h->stream));
+    if (R.P) HIP_TRY(hipMemsetAsync(R.P, 0, 4 * (size_t)R.rplane * sizeof(double), h->stream));
     R.par = 0; R.step = 0; R.limit = 0;
     set_scale(R, 1.0);
     if (storage == ST_F16 && h->desc.f16_scale > 0) set_scale(R, h->desc.f16_scale);
@@ -700,22 +716,10 @@ lbm_status lbm_synchronize(lbm_handle h) {
 }
 
 // The moments of the current step re-pull from the previous buffer; ring nodes take the
-// post-boundary populations of that step, recomputed from the previous buffers.
-static lbm_status refresh_targets(lbm_run *h) {
-    if (h->steps > 0 && h->hd.ring_n > 0) {
-        LaunchSet L = single_set(h);
-        HIP_TRY(launch_nrbc(L, h->desc.storage, 1, h->stream));
-    }
-    return LBM_OK;
-}
-
+// post-boundary populations of that step, which phase A left in G.
 lbm_status lbm_moments(lbm_handle h, double *rho, double *ux, double *uy, double *T, unsigned flags) {
     if (!h) return fail(LBM_ERR_ARG, "NULL handle");
     if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
-    {
-        lbm_status st = refresh_targets(h);
-        if (st != LBM_OK) return st;
-    }
     const RunDev &R = h->hd;
     const size_t nn = (size_t)R.Nx * R.Ny;
     if (flags & LBM_DEVICE_PTRS) {
@@ -779,10 +783,6 @@ lbm_status lbm_error_norms(lbm_handle h, const double *ref_rho, const double *re
     double *tmp = (double *)h->mem.get((3 * nn + 3 * nb + 3 * (size_t)ly + 3) * sizeof(double));
     if (!tmp) return fail(LBM_ERR_OOM, "device allocation failed");
     double *m = tmp, *refs = tmp + 3 * nn, *part = refs + 3 * nb, *dout = part + 3 * (size_t)ly;
-    {
-        lbm_status st = refresh_targets(h);
-        if (st != LBM_OK) { h->mem.put(tmp); return st; }
-    }
     hipError_t e = launch_moments(h->dd, h->desc.storage, R.Nx, R.Ny, m, m + nn, nullptr, m + 2 * nn, h->stream);
     const double *src[3] = {ref_rho, ref_ux, ref_T};
     for (int k = 0; k < 3 && e == hipSuccess; ++k)
@@ -886,14 +886,16 @@ lbm_status lbm_save(lbm_handle h, const char *path) {
     size_t fb = (size_t)R.fsize * elem_size(storage);
     size_t qb = R.has_q ? (size_t)NQ * R.qplane * compute_size(storage) : 0;
     size_t ub = 4 * (size_t)R.qplane * sizeof(double);
-    std::vector<char> buf(2 * fb + qb + 2 * ub);
+    size_t gb = R.ring_n > 0 ? (size_t)NQ * R.rplane * compute_size(storage) : 0;
+    std::vector<char> buf(2 * fb + qb + 2 * ub + gb);
     char *p = buf.data();
     for (int b = 0; b < 2; ++b) { HIP_TRY(hipMemcpy(p, R.f[b], fb, hipMemcpyDeviceToHost)); p += fb; }
     if (qb) { HIP_TRY(hipMemcpy(p, R.Q, qb, hipMemcpyDeviceToHost)); p += qb; }
     for (int b = 0; b < 2; ++b) { HIP_TRY(hipMemcpy(p, R.U[b], ub, hipMemcpyDeviceToHost)); p += ub; }
+    if (gb) { HIP_TRY(hipMemcpy(p, R.G, gb, hipMemcpyDeviceToHost)); p += gb; }
     CkptHeader hdr{};
-    std::memcpy(hdr.magic, "LBMPML01", 8);
-    hdr.version = 1; hdr.Nx = R.Nx; hdr.Ny = R.Ny; hdr.storage = storage; hdr.W = h->W;
+    std::memcpy(hdr.magic, "LBMPML02", 8);
+    hdr.version = 2; hdr.Nx = R.Nx; hdr.Ny = R.Ny; hdr.storage = storage; hdr.W = h->W;
     hdr.layout = h->desc.layout;
     for (int s = 0; s < 4; ++s) { hdr.pml[s] = h->pml[s]; hdr.bc[s] = h->bc[s]; }
     hdr.par = R.par; hdr.steps = h->steps; hdr.plane = R.plane; hdr.qplane = R.qplane;
@@ -915,7 +917,7 @@ lbm_status lbm_load(lbm_handle h, const char *path) {
     FILE *fp = std::fopen(path, "rb");
     if (!fp) return fail(LBM_ERR_ARG, std::string("cannot open ") + path);
     CkptHeader hdr{};
-    if (std::fread(&hdr, sizeof hdr, 1, fp) != 1 || std::memcmp(hdr.magic, "LBMPML01", 8) != 0) {
+    if (std::fread(&hdr, sizeof hdr, 1, fp) != 1 || std::memcmp(hdr.magic, "LBMPML02", 8) != 0) {
         std::fclose(fp);
         return fail(LBM_ERR_ARG, "not a checkpoint file");
     }
@@ -931,7 +933,8 @@ lbm_status lbm_load(lbm_handle h, const char *path) {
     size_t fb = (size_t)R.fsize * elem_size(storage);
     size_t qb = R.has_q ? (size_t)NQ * R.qplane * compute_size(storage) : 0;
     size_t ub = 4 * (size_t)R.qplane * sizeof(double);
-    std::vector<char> buf(2 * fb + qb + 2 * ub);
+    size_t gb = R.ring_n > 0 ? (size_t)NQ * R.rplane * compute_size(storage) : 0;
+    std::vector<char> buf(2 * fb + qb + 2 * ub + gb);
     bool ok = std::fread(buf.data(), 1, buf.size(), fp) == buf.size();
     std::fclose(fp);
     if (!ok) return fail(LBM_ERR_ARG, "truncated checkpoint");
@@ -942,6 +945,7 @@ lbm_status lbm_load(lbm_handle h, const char *path) {
     for (int b = 0; b < 2; ++b) { HIP_TRY(hipMemcpy(R.f[b], p, fb, hipMemcpyHostToDevice)); p += fb; }
     if (qb) { HIP_TRY(hipMemcpy(R.Q, p, qb, hipMemcpyHostToDevice)); p += qb; }
     for (int b = 0; b < 2; ++b) { HIP_TRY(hipMemcpy(R.U[b], p, ub, hipMemcpyHostToDevice)); p += ub; }
+    if (gb) { HIP_TRY(hipMemcpy(R.G, p, gb, hipMemcpyHostToDevice)); p += gb; }
     R.par = hdr.par;
     R.step = hdr.steps;
     R.limit = hdr.steps;
@@ -982,7 +986,7 @@ lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path, lbm
     lbm_handle s = nullptr;
     lbm_status st = lbm_create(&d, &s);
     if (st != LBM_OK) return st;
-    s->W = h->W; s->sigma_max = h->sigma_max;
+    s->W = h->W; s->sigma_max = h->sigma_max; s->pml_terms = h->pml_terms;
     for (int k = 0; k < 4; ++k) { s->pml[k] = h->pml[k]; s->bc[k] = h->bc[k]; }
     const size_t nn = (size_t)R.Nx * R.Ny;
     std::vector<double> f1(nn, d.rho0), f2(nn, d.ux0), f3(nn, d.uy0), f4(nn, d.T0);
@@ -1208,7 +1212,7 @@ lbm_status lbm_group_autotune(lbm_group_handle g, int32_t steps, lbm_launch *cho
     for (lbm_run *h : g->members) {
         std::array<long long, 12> key{h->desc.nx, h->desc.ny, h->desc.storage, h->desc.layout, h->W,
                                       h->pml[0] | h->pml[1] << 1 | h->pml[2] << 2 | h->pml[3] << 3,
-                                      h->bc[0], h->bc[1], h->bc[2], h->bc[3], 0, 0};
+                                      h->bc[0], h->bc[1], h->bc[2], h->bc[3], (long long)h->pml_terms, 0};
         if (std::find(keys.begin(), keys.end(), key) != keys.end()) continue;
         keys.push_back(key);
         lbm_desc d = h->desc;
@@ -1217,7 +1221,7 @@ lbm_status lbm_group_autotune(lbm_group_handle g, int32_t steps, lbm_launch *cho
         st = lbm_create(&d, &s);
         if (st != LBM_OK) break;
         scratch.push_back(s);
-        s->W = h->W; s->sigma_max = h->sigma_max;
+        s->W = h->W; s->sigma_max = h->sigma_max; s->pml_terms = h->pml_terms;
         for (int k = 0; k < 4; ++k) { s->pml[k] = h->pml[k]; s->bc[k] = h->bc[k]; }
         const size_t nn = (size_t)(h->hd.Nx) * h->hd.Ny;
         std::vector<double> f1(nn, d.rho0), f2(nn, d.ux0), f3(nn, d.uy0), f4(nn, d.T0);

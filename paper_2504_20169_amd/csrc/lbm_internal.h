@@ -35,7 +35,7 @@ struct alignas(256) RunDev {
     int W, qd, open_x, open_y;
     int bc[4];
     int fx0, fx1, fy0, fy1;   // fast rectangle
-    int frame_n, has_q, ring_n, pad1;
+    int frame_n, has_q, ring_n, pml_terms;   // pml_terms: PML moments in the NRBC target
     int rxm, rxp, rym, ryp;   // characteristic-boundary ring depths (3 on NRBC sides, else 0)
     int tiles_x[3], tiles_y[3];   // bulk tiles for tile widths 64, 128, 256
     // state
@@ -43,6 +43,7 @@ struct alignas(256) RunDev {
     void *Q;                  // [37][qplane] in the compute type
     double *U[2];             // [4][qplane]: rho, ux, uy, T (absolute values)
     void *G;                  // [37][rplane] compute type: post-boundary populations of the ring
+    double *P;                // [4][rplane]: start of the NRBC target, U^n + PML moments (if pml_terms)
     long long rplane;
     int par, pad0;
     long long step, limit;    // a run is active while step < limit
@@ -55,8 +56,9 @@ struct alignas(256) RunDev {
 
 // Launch decomposition of a set of runs: prefix[k] = first block of run k, prefix[n] = total.
 // Classes: the interior tiles; the frame launch (ring blocks, then frame blocks); the phase-A
-// launch (ring blocks, then frame blocks if the run has a PML); the ring alone.
-enum Cls { CLS_BULK = 0, CLS_FRAME = 1, CLS_A = 2, CLS_RING = 3, NCLS = 4 };
+// launch (ring blocks, then frame blocks if the run has a PML); the PML moments of the NRBC
+// target (ring blocks of runs that select them).
+enum Cls { CLS_BULK = 0, CLS_FRAME = 1, CLS_A = 2, CLS_PM = 3, NCLS = 4 };
 struct LaunchSet {
     RunDev *const *runs;      // device array of descriptor pointers
     const int *prefix[NCLS];  // device prefix arrays per class
@@ -76,10 +78,8 @@ constexpr int RING_BLOCK = 64;
 // of every frame node, ring included.
 hipError_t launch_phase_a(const LaunchSet &L, int storage, hipStream_t s);
 hipError_t launch_frame(const LaunchSet &L, int storage, hipStream_t s);
+hipError_t launch_pml_moments(const LaunchSet &L, int storage, hipStream_t s);
 hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, hipStream_t s);
-// Post-boundary populations of every characteristic-boundary ring node into G, from the buffers
-// of the current step (prev = 0) or of the previous one (prev = 1); no Q update.
-hipError_t launch_nrbc(const LaunchSet &L, int storage, int prev, hipStream_t s);
 hipError_t launch_flip(const LaunchSet &L, hipStream_t s);
 hipError_t launch_set_limit(RunDev *run, long long limit, hipStream_t s);
 hipError_t launch_set_limits(RunDev *const *runs, const long long *limits, int n, hipStream_t s);

@@ -424,52 +424,169 @@ __device__ __forceinline__ void gather_clamped(CRun &R, const GLOBAL S *src, int
     });
 }
 
+// grad Q stencil of a frame node (frame index t): d/dalpha Q = cs*Q(x) + c0*Q(j0) + c1*Q(j1),
+// central (0, 1/2, -1/2 at x+1, x-1), one-sided at the outermost layer of an open axis (outward
+// normal s: s*(3/2, -2, 1/2) at x, x-s, x-2s) (eqs. FD-dx-center, FD-dx-bw).  Offsets are byte
+// offsets into one Q plane; a neighbour outside the frame falls back to the node itself (such
+// nodes lie off the layer, where sigma = 0).
+template <class C> struct QStencil {
+    unsigned ot, ox0, ox1, oy0, oy1;
+    C cxs, cx0, cx1, cys, cy0, cy1;
+};
+
+template <class C>
+__device__ __forceinline__ QStencil<C> q_stencil(CRun &R, int x, int y, int t) {
+    QStencil<C> q;
+    int jx0, jx1, jy0, jy1;
+    if (R.open_x && x == 0) {
+        jx0 = fidx(R, 1, y); jx1 = fidx(R, 2, y);
+        q.cxs = C(-1.5); q.cx0 = C(2); q.cx1 = C(-0.5);
+    } else if (R.open_x && x == R.Nx - 1) {
+        jx0 = fidx(R, x - 1, y); jx1 = fidx(R, x - 2, y);
+        q.cxs = C(1.5); q.cx0 = C(-2); q.cx1 = C(0.5);
+    } else {
+        int xp = x + 1, xm = x - 1;
+        if (xp >= R.Nx) xp -= R.Nx;
+        if (xm < 0) xm += R.Nx;
+        jx0 = fidx(R, xp, y); jx1 = fidx(R, xm, y);
+        q.cxs = C(0); q.cx0 = C(0.5); q.cx1 = C(-0.5);
+    }
+    if (R.open_y && y == 0) {
+        jy0 = fidx(R, x, 1); jy1 = fidx(R, x, 2);
+        q.cys = C(-1.5); q.cy0 = C(2); q.cy1 = C(-0.5);
+    } else if (R.open_y && y == R.Ny - 1) {
+        jy0 = fidx(R, x, y - 1); jy1 = fidx(R, x, y - 2);
+        q.cys = C(1.5); q.cy0 = C(-2); q.cy1 = C(0.5);
+    } else {
+        int yp = y + 1, ym = y - 1;
+        if (yp >= R.Ny) yp -= R.Ny;
+        if (ym < 0) ym += R.Ny;
+        jy0 = fidx(R, x, yp); jy1 = fidx(R, x, ym);
+        q.cys = C(0); q.cy0 = C(0.5); q.cy1 = C(-0.5);
+    }
+    q.ox0 = (unsigned)(jx0 < 0 ? t : jx0) * (unsigned)sizeof(C);
+    q.ox1 = (unsigned)(jx1 < 0 ? t : jx1) * (unsigned)sizeof(C);
+    q.oy0 = (unsigned)(jy0 < 0 ? t : jy0) * (unsigned)sizeof(C);
+    q.oy1 = (unsigned)(jy1 < 0 ? t : jy1) * (unsigned)sizeof(C);
+    q.ot = (unsigned)t * (unsigned)sizeof(C);
+    return q;
+}
+
+// Appendix (eq. NSF-CHAR-PML): with a PML the macroscopic equations carry source terms built
+// from the auxiliary moments; with phi = (1, xi_x, xi_y, |xi|^2/2) the selected parts
+// I = sum phi_i e_i . grad Q_i (bit 0), II = 2 sum phi_i fhat_i (bit 1) and
+// III = sigma sum phi_i Q_i (bit 2) move the characteristic target over one step by
+// s = +sigma (I + II + III) (the appendix's signs) in conserved variables (rho, rho u,
+// rho (|u|^2/2 + T)), converted to (rho, u, T) at U^n by the chain rule.  The quadrature carries
+// the conserved moments of feq exactly, so II = 2 (U^n - Ubar) in conserved form.  Q and U of
+// level n; float64 arithmetic; the population loop is left rolled (few nodes, low pressure).
+template <class C>
+__device__ __forceinline__ void pml_moments(CRun &R, int x, int y, int t, const GLOBAL double *Uc,
+                                            double (&dU)[4]) {
+    dU[0] = dU[1] = dU[2] = dU[3] = 0.0;
+    const double sg = sigma_at(R, x, y);
+    if (!(sg > 0.0)) return;
+    const unsigned qp = (unsigned)R.qplane, flags = (unsigned)R.pml_terms;
+    const double rho = Uc[t], ux = Uc[qp + t], uy = Uc[2 * qp + t], T = Uc[3 * qp + t];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (flags & 5u) {
+        const QStencil<C> qs = q_stencil<C>(R, x, y, t);
+        const GLOBAL C *Q = (const GLOBAL C *)R.Q;
+#pragma unroll 1
+        for (int i = 0; i < NQ; ++i) {
+            const int ex = ex_of(i), ey = ey_of(i);
+            const GLOBAL C *Qi = Q + (long long)i * qp;
+            const double Qt = (double)*at(Qi, qs.ot);
+            double a = 0.0;
+            if (flags & 1u) {
+                if (ex != 0)
+                    a += ex * ((double)qs.cxs * Qt + (double)qs.cx0 * (double)*at(Qi, qs.ox0) +
+                               (double)qs.cx1 * (double)*at(Qi, qs.ox1));
+                if (ey != 0)
+                    a += ey * ((double)qs.cys * Qt + (double)qs.cy0 * (double)*at(Qi, qs.oy0) +
+                               (double)qs.cy1 * (double)*at(Qi, qs.oy1));
+            }
+            if (flags & 4u) a += sg * Qt;
+            const double xx = LAT_R * ex, yy = LAT_R * ey;
+            s0 += a;
+            s1 += xx * a;
+            s2 += yy * a;
+            s3 += (0.5 * (xx * xx + yy * yy)) * a;
+        }
+    }
+    if (flags & 2u) {
+        const double b0 = R.rho0, bx = R.u0x, by = R.u0y, bT = R.T0;
+        s0 += 2.0 * (rho - b0);
+        s1 += 2.0 * (rho * ux - b0 * bx);
+        s2 += 2.0 * (rho * uy - b0 * by);
+        s3 += 2.0 * (rho * (0.5 * (ux * ux + uy * uy) + T) - b0 * (0.5 * (bx * bx + by * by) + bT));
+    }
+    s0 *= sg; s1 *= sg; s2 *= sg; s3 *= sg;
+    dU[0] = s0;
+    dU[1] = (s1 - ux * s0) / rho;
+    dU[2] = (s2 - uy * s0) / rho;
+    dU[3] = (s3 - ux * s1 - uy * s2 + (0.5 * (ux * ux + uy * uy) - T) * s0) / rho;
+}
+
 // Blocks of a run's boundary launches: the characteristic ring first (ring numbering, RING_BLOCK
 // nodes per block), then the frame (frame numbering, FRAME_BLOCK nodes per block).
 __device__ __forceinline__ int ring_blocks(CRun &R) { return (R.ring_n + RING_BLOCK - 1) / RING_BLOCK; }
 
-// Ring node of characteristic sides: U_tgt = U(x_b) of the last completed level plus the LODI
-// increment of each NRBC side the node lies on (corners add both normals), then the clamped pull
-// of x_f and the non-equilibrium extrapolation.  The result is left in g and stored to G (ring
-// index tt) for the frame kernel.  prev = 1 recomputes those of the last completed step.
-template <class S, class C>
-__device__ __forceinline__ void nrbc_node(CRun &R, int tt, int x, int y, int t, int prev, C inv_scale,
-                                          C (&g)[NQ]) {
-    const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par ^ prev];
-    const unsigned qp = (unsigned)R.qplane;
-    double Ut[4] = {Uc[t], Uc[qp + t], Uc[2 * qp + t], Uc[3 * qp + t]};
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        bool on = s == XMIN ? x < 3 : s == XMAX ? x >= R.Nx - 3 : s == YMIN ? y < 3 : y >= R.Ny - 3;
-        if (on && R.bc[s] == BC_NRBC) lodi_add(R, Uc, s, x, y, t, Ut);
-    }
-    gather_clamped<S, C>(R, (const GLOBAL S *)R.f[R.par ^ prev], x, y, inv_scale, g);
-    nrbc_fill<C>(R, Ut, g);
-    GLOBAL C *G = (GLOBAL C *)R.G;
-    const unsigned rp = (unsigned)R.rplane;
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) G[i * rp + tt] = g[i];
-}
-
-// Post-boundary populations of every ring node into G, without the rest of phase A (used to
-// refresh G for the moments of the last completed step, prev = 1).
+// Start of the characteristic target for runs that select the PML moments of the appendix:
+// P = U^n(x_b) + the moments (4 planes of the ring numbering, float64) for every ring node;
+// launched before phase A, which starts the target from P instead of U^n.
 template <class S>
-__global__ __launch_bounds__(256) void k_nrbc(RunDev *const *__restrict__ runs,
-                                              const int *__restrict__ prefix, int nruns, int prev) {
+__global__ __launch_bounds__(256) void k_pml_moments(RunDev *const *__restrict__ runs,
+                                                     const int *__restrict__ prefix, int nruns) {
     using C = typename Traits<S>::C;
     const int b = blockIdx.x;
     const int j = find_run(prefix, nruns, b);
     CRun &R = run_of(runs, j);
-    if (prev == 0 && R.step >= R.limit) return;
-    const int tt = (b - ((const CONSTANT int *)prefix)[j]) * FRAME_BLOCK + (int)threadIdx.x;
+    if (R.step >= R.limit || !R.pml_terms) return;
+    if ((int)threadIdx.x >= RING_BLOCK) return;
+    const int tt = (b - ((const CONSTANT int *)prefix)[j]) * RING_BLOCK + (int)threadIdx.x;
     if (tt >= R.ring_n) return;
     int x, y;
     ring_xy(R, tt, x, y);
     const int t = fidx(R, x, y);
     if (t < 0) return;
-    const K<C> k = load_k<C>(R);
-    C g[NQ];
-    nrbc_node<S, C>(R, tt, x, y, t, prev, k.inv_scale, g);
+    const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par];
+    const unsigned qp = (unsigned)R.qplane;
+    double dU[4];
+    pml_moments<C>(R, x, y, t, Uc, dU);
+    GLOBAL double *P = (GLOBAL double *)R.P;
+    const unsigned rp = (unsigned)R.rplane;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) P[k * rp + tt] = Uc[k * qp + t] + dU[k];
+}
+
+// Ring node of characteristic sides: U_tgt = U(x_b) of the last completed level plus the LODI
+// increment of each NRBC side the node lies on (corners add both normals) and, if selected, the
+// PML moments of the appendix; then the clamped pull of x_f and the non-equilibrium
+// extrapolation.  The result is left in g and stored to G (ring index tt), where the frame
+// kernel and the moment export read it.
+template <class S, class C>
+__device__ __forceinline__ void nrbc_node(CRun &R, int tt, int x, int y, int t, C inv_scale,
+                                          C (&g)[NQ]) {
+    const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par];
+    const unsigned qp = (unsigned)R.qplane;
+    // the target starts from U^n(x_b), or from U^n(x_b) plus the PML moments of the appendix
+    // when the run selects them (formed by k_pml_moments in ring numbering)
+    const bool pm = R.pml_terms != 0;
+    const GLOBAL double *Ub = pm ? (const GLOBAL double *)R.P : Uc;
+    const unsigned ib = pm ? (unsigned)tt : (unsigned)t, sb = pm ? (unsigned)R.rplane : qp;
+    double Ut[4] = {Ub[ib], Ub[sb + ib], Ub[2 * sb + ib], Ub[3 * sb + ib]};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        bool on = s == XMIN ? x < 3 : s == XMAX ? x >= R.Nx - 3 : s == YMIN ? y < 3 : y >= R.Ny - 3;
+        if (on && R.bc[s] == BC_NRBC) lodi_add(R, Uc, s, x, y, t, Ut);
+    }
+    gather_clamped<S, C>(R, (const GLOBAL S *)R.f[R.par], x, y, inv_scale, g);
+    nrbc_fill<C>(R, Ut, g);
+    GLOBAL C *G = (GLOBAL C *)R.G;
+    const unsigned rp = (unsigned)R.rplane;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) G[i * rp + tt] = g[i];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -537,42 +654,9 @@ __device__ __forceinline__ void frame_collide(CRun &R, const K<C> &k, const C (&
     Mom<C> m = moments<C>(g, k);
     Eq<C> q = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
     if (R.has_q) {
-        // d/dalpha Q = cs*Q(x) + c0*Q(j0) + c1*Q(j1): central 0, 1/2, -1/2 at x+1, x-1;
-        // one-sided at the outermost layer (outward normal s): s*(3/2, -2, 1/2) at x, x-s, x-2s
-        int jx0, jx1, jy0, jy1;
-        C cxs, cx0, cx1, cys, cy0, cy1;
-        if (R.open_x && x == 0) {
-            jx0 = fidx(R, 1, y); jx1 = fidx(R, 2, y);
-            cxs = C(-1.5); cx0 = C(2); cx1 = C(-0.5);
-        } else if (R.open_x && x == R.Nx - 1) {
-            jx0 = fidx(R, x - 1, y); jx1 = fidx(R, x - 2, y);
-            cxs = C(1.5); cx0 = C(-2); cx1 = C(0.5);
-        } else {
-            int xp = x + 1, xm = x - 1;
-            if (xp >= R.Nx) xp -= R.Nx;
-            if (xm < 0) xm += R.Nx;
-            jx0 = fidx(R, xp, y); jx1 = fidx(R, xm, y);
-            cxs = C(0); cx0 = C(0.5); cx1 = C(-0.5);
-        }
-        if (R.open_y && y == 0) {
-            jy0 = fidx(R, x, 1); jy1 = fidx(R, x, 2);
-            cys = C(-1.5); cy0 = C(2); cy1 = C(-0.5);
-        } else if (R.open_y && y == R.Ny - 1) {
-            jy0 = fidx(R, x, y - 1); jy1 = fidx(R, x, y - 2);
-            cys = C(1.5); cy0 = C(-2); cy1 = C(0.5);
-        } else {
-            int yp = y + 1, ym = y - 1;
-            if (yp >= R.Ny) yp -= R.Ny;
-            if (ym < 0) ym += R.Ny;
-            jy0 = fidx(R, x, yp); jy1 = fidx(R, x, ym);
-            cys = C(0); cy0 = C(0.5); cy1 = C(-0.5);
-        }
-        // per-lane byte offsets into each Q plane (uniform plane bases + one offset per point)
-        const unsigned ox0 = (unsigned)(jx0 < 0 ? t : jx0) * (unsigned)sizeof(C);
-        const unsigned ox1 = (unsigned)(jx1 < 0 ? t : jx1) * (unsigned)sizeof(C);
-        const unsigned oy0 = (unsigned)(jy0 < 0 ? t : jy0) * (unsigned)sizeof(C);
-        const unsigned oy1 = (unsigned)(jy1 < 0 ? t : jy1) * (unsigned)sizeof(C);
-        const unsigned ot = (unsigned)t * (unsigned)sizeof(C);
+        const QStencil<C> qs = q_stencil<C>(R, x, y, t);
+        const unsigned ot = qs.ot, ox0 = qs.ox0, ox1 = qs.ox1, oy0 = qs.oy0, oy1 = qs.oy1;
+        const C cxs = qs.cxs, cx0 = qs.cx0, cx1 = qs.cx1, cys = qs.cys, cy0 = qs.cy0, cy1 = qs.cy1;
         // sigma = 0 off the layer: the PML terms are then -0 * (finite) and leave BGK's bits
         const C s = (C)(R.W > 0 ? sigma_at(R, x, y) : 0.0);
         C h[NQ];
@@ -703,11 +787,16 @@ __global__ __launch_bounds__(256) void k_phase_a(RunDev *const *__restrict__ run
         ring_xy(R, tt, x, y);
         t = fidx(R, x, y);
         if (t < 0) return;
-        nrbc_node<S, C>(R, tt, x, y, t, 0, k.inv_scale, g);
+        nrbc_node<S, C>(R, tt, x, y, t, k.inv_scale, g);
         if (!R.has_q || !in_q(R, x, y)) return;
-        // keep the fill and the update apart: interleaved, their FP64 temporaries exceed the
-        // register file
-        __builtin_amdgcn_sched_barrier(0);
+        // Re-read the filled populations from G (this thread's own stores): the memory clobber
+        // ends g's live range at the fill, so the fill and the Q update use the register file
+        // one after the other instead of together.
+        asm volatile("" ::: "memory");
+        const GLOBAL C *G = (const GLOBAL C *)R.G;
+        const unsigned rp = (unsigned)R.rplane;
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) g[i] = G[i * rp + tt];
     } else {
         const int tt = (tb - rb) * FRAME_BLOCK + (int)threadIdx.x;
         if (!R.has_q || tt >= R.frame_n) return;
@@ -931,6 +1020,13 @@ hipError_t launch_phase_a(const LaunchSet &L, int storage, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_pml_moments(const LaunchSet &L, int storage, hipStream_t s) {
+    if (L.blocks[CLS_PM] > 0)
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_pml_moments<S>), dim3(L.blocks[CLS_PM]), dim3(256), 0, s,
+                                                 L.runs, L.prefix[CLS_PM], L.nruns));
+    return hipGetLastError();
+}
+
 hipError_t launch_frame(const LaunchSet &L, int storage, hipStream_t s) {
     if (L.blocks[CLS_FRAME] > 0)
         LBM_DISPATCH(storage, hipLaunchKernelGGL((k_frame<S>), dim3(L.blocks[CLS_FRAME]), dim3(256), 0, s,
@@ -953,13 +1049,6 @@ hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, hipStream_t s) {
         LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 256>), dim3(nb), dim3(256), 0, s, L.runs, pre, L.nruns));
         break;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_nrbc(const LaunchSet &L, int storage, int prev, hipStream_t s) {
-    if (L.blocks[CLS_RING] > 0)
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_nrbc<S>), dim3(L.blocks[CLS_RING]), dim3(256), 0, s,
-                                                 L.runs, L.prefix[CLS_RING], L.nruns, prev));
     return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ BC = {"periodic": LBM_BC_PERIODIC, "zg": LBM_BC_ZG, "nrbc": LBM_BC_NRBC}
 
 # C symbols exported by the library (the header's declarations).
 EXPORTED = [
-    "lbm_create", "lbm_set_pml", "lbm_set_bc", "lbm_grid", "lbm_footprint", "lbm_init_fields",
+    "lbm_create", "lbm_set_pml", "lbm_set_bc", "lbm_set_nrbc_pml_terms", "lbm_grid", "lbm_footprint", "lbm_init_fields",
     "lbm_node_classes",
     "lbm_step", "lbm_step_count", "lbm_moments", "lbm_populations", "lbm_pml_q",
     "lbm_velocities", "lbm_error_norms", "lbm_check", "lbm_synchronize", "lbm_set_launch",
@@ -86,6 +86,7 @@ def load():
         "lbm_create": [ctypes.POINTER(lbm_desc), ctypes.POINTER(H)],
         "lbm_set_pml": [H, ctypes.c_uint, ctypes.c_int32, ctypes.c_double],
         "lbm_set_bc": [H, ctypes.c_uint, ctypes.c_int],
+        "lbm_set_nrbc_pml_terms": [H, ctypes.c_uint],
         "lbm_grid": [H, i32p, i32p],
         "lbm_footprint": [H, ctypes.POINTER(ctypes.c_size_t)],
         "lbm_node_classes": [H, i64p],
@@ -217,6 +218,11 @@ class Run:
 
     def set_bc(self, mask, kind):
         _check(self._lib.lbm_set_bc(self.h, int(mask), BC[kind] if isinstance(kind, str) else int(kind)))
+
+    def set_nrbc_pml_terms(self, flags):
+        """Appendix: PML moments in the characteristic target (bit 0 term I, bit 1 term II,
+        bit 2 term III)."""
+        _check(self._lib.lbm_set_nrbc_pml_terms(self.h, int(flags)))
 
     def grid(self):
         nx, ny = ctypes.c_int32(), ctypes.c_int32()

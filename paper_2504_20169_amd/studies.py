@@ -48,12 +48,14 @@ def step_fields(Lx, Ly, x_offset, Nx, mach=0.05, rho0=1.0, rho1=1.05, s=0.5):
     return rho, np.full((Ly, Nx), mach), np.zeros((Ly, Nx)), np.ones((Ly, Nx))
 
 
-def _make(lbm, Lx, Ly, bc, W, sigma, mach, storage, fields, tau):
+def _make(lbm, Lx, Ly, bc, W, sigma, mach, storage, fields, tau, pml_terms=0):
     r = lbm.Run(Lx, Ly, tau, 1.0, mach, 0.0, 1.0, storage=storage)
     r.set_bc(lbm.LBM_YMIN | lbm.LBM_YMAX, "periodic")
     r.set_bc(lbm.LBM_XMIN | lbm.LBM_XMAX, bc)
     if W > 0:
         r.set_pml(lbm.LBM_XMIN | lbm.LBM_XMAX, W, sigma)
+    if pml_terms:
+        r.set_nrbc_pml_terms(pml_terms)
     r.init(*fields)
     return r
 
@@ -61,7 +63,8 @@ def _make(lbm, Lx, Ly, bc, W, sigma, mach, storage, fields, tau):
 def density_step_study(steps=600, sample=10, Lx=200, Ly=20, mach=0.05, tau=0.8,
                        widths=(0, 10, 20, 40), bcs=("zg", "nrbc"), storage="f64", configs=None):
     """Run every (boundary, W, sigma_max) configuration and the periodic reference in lock step.
-    configs: list of (bc, W, sigma_max); default: bcs x widths with the paper's D2Q37 table.
+    configs: list of (bc, W, sigma_max) or (bc, W, sigma_max, pml_terms); default: bcs x widths
+    with the paper's D2Q37 table.
     Returns a list of dicts (bc, W, sigma_max, stable, ebar_rho, ebar_ux, emax_*, t_bc_ms, and
     C_rho, C_ux, C_t against ZG without PML when that configuration is in the list) and the
     reference's grid width."""
@@ -76,10 +79,13 @@ def density_step_study(steps=600, sample=10, Lx=200, Ly=20, mach=0.05, tau=0.8,
     ref = _make(lbm, Nref, Ly, "periodic", 0, 0.0, mach, storage,
                 step_fields(Lx, Ly, ext, Nref, mach), tau)
     runs = []
-    for bc, W, s in configs:
-        r = _make(lbm, Lx, Ly, bc, W, s, mach, storage, step_fields(Lx, Ly, W, Lx + 2 * W, mach), tau)
+    for c in configs:
+        bc, W, s = c[:3]
+        pt = c[3] if len(c) > 3 else 0
+        r = _make(lbm, Lx, Ly, bc, W, s, mach, storage, step_fields(Lx, Ly, W, Lx + 2 * W, mach), tau,
+                  pt)
         r.profile(1)
-        runs.append((bc, W, s, r, []))
+        runs.append((bc, W, s, r, [], pt))
     done = 0
     while done < steps:
         n = min(sample, steps - done)
@@ -92,17 +98,17 @@ def density_step_study(steps=600, sample=10, Lx=200, Ly=20, mach=0.05, tau=0.8,
         for run in runs:
             run[4].append(run[3].error_norms(rho[win], ux[win], T[win]))
     out = []
-    for bc, W, s, r, errs in runs:
+    for bc, W, s, r, errs, pt in runs:
         ms, n = r.profile_read()
         e = np.array(errs)
         ok = r.check() == lbm.LBM_OK and np.all(np.isfinite(e))
-        out.append(dict(bc=bc, W=W, sigma_max=s, stable=bool(ok),
+        out.append(dict(bc=bc, W=W, sigma_max=s, pml_terms=pt, stable=bool(ok),
                         ebar_rho=float(e[:, 0].mean()), ebar_ux=float(e[:, 1].mean()),
                         emax_rho=float(e[:, 0].max()), emax_ux=float(e[:, 1].max()),
                         t_bc_ms=float(ms[1] + ms[2]), steps=steps))
         r.close()
     ref.close()
-    base = next((d for d in out if d["bc"] == "zg" and d["W"] == 0), None)
+    base = next((d for d in out if d["bc"] == "zg" and d["W"] == 0 and not d["pml_terms"]), None)
     if base is not None:
         for d in out:
             d["C_rho"] = d["ebar_rho"] / base["ebar_rho"]
@@ -130,6 +136,16 @@ def sigma_scan(steps=600, sigmas=None, widths=(10, 20, 40), bcs=("zg", "nrbc"), 
     return rows, best
 
 
+def appendix_study(steps=600, W=10, sigma=0.001, flag_sets=(0, 1, 2, 4, 3, 5, 6, 7), storage="f64"):
+    """The appendix experiment: the density step with the characteristic boundary behind a
+    PML (W = 10, sigma_max = 0.001), with each combination of the PML moment terms I, II, III in
+    the characteristic target.  Returns the study rows (plain ZG without PML first, as the base
+    of C_Z)."""
+    configs = [("zg", 0, 0.0)] + [("nrbc", W, sigma, f) for f in flag_sets]
+    rows, _ = density_step_study(steps=steps, storage=storage, configs=configs)
+    return rows
+
+
 def main():
     import argparse
     import json
@@ -139,6 +155,8 @@ def main():
     ap.add_argument("--sample", type=int, default=10)
     ap.add_argument("--storage", default="f64")
     ap.add_argument("--scan", action="store_true", help="also scan sigma_max per boundary and W")
+    ap.add_argument("--appendix", action="store_true",
+                    help="also run the appendix's PML-moment terms on the characteristic boundary")
     args = ap.parse_args()
     t0 = time.perf_counter()
     rows, nref = density_step_study(args.steps, args.sample, storage=args.storage)
@@ -148,6 +166,9 @@ def main():
         _, best = sigma_scan(args.steps, storage=args.storage)
         for (bc, W), d in sorted(best.items()):
             print(json.dumps(dict(scan_best=True, **d)))
+    if args.appendix:
+        for d in appendix_study(args.steps, storage=args.storage):
+            print(json.dumps(dict(appendix=True, **d)))
     print(json.dumps(dict(reference_grid=[nref, 20], seconds=time.perf_counter() - t0)))
 
 

@@ -23,7 +23,8 @@ def perm_lib_to_oracle(oracle_mod):
 
 
 def make_pair(oracle_mod, Lx, Ly, tau=0.8, mean=(1.0, 0.0, 0.0, 1.0), bc=None, pml=None,
-              fields=None, storage="f64", launch=None, stream=None, allocator=None, gpu=True):
+              fields=None, storage="f64", launch=None, stream=None, allocator=None, gpu=True,
+              pml_terms=0):
     """bc: dict side->kind ('zg'|'nrbc'|'periodic') or a kind for all sides; pml: (mask, W,
     sigma).  Returns (gpu_run or None, oracle_run)."""
     rho0, ux0, uy0, T0 = mean
@@ -43,6 +44,10 @@ def make_pair(oracle_mod, Lx, Ly, tau=0.8, mean=(1.0, 0.0, 0.0, 1.0), bc=None, p
         o.set_pml(mask, W, sig)
         if g:
             g.set_pml(mask, W, sig)
+    if pml_terms:
+        o.set_nrbc_pml_terms(pml_terms)
+        if g:
+            g.set_nrbc_pml_terms(pml_terms)
     if g and launch:
         g.set_launch(**launch)
     Nx, Ny = o.grid()

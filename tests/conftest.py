@@ -18,3 +18,10 @@ def oracle_mod():
     import oracle
     oracle._load()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def perm(oracle_mod):
+    """perm[k] = library index of the oracle's velocity k."""
+    from _helpers import perm_lib_to_oracle
+    return perm_lib_to_oracle(oracle_mod)

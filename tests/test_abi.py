@@ -79,6 +79,10 @@ def test_launch_configuration_validated_on_host():
             r.set_launch(**kw)
         assert ei.value.status == lbm.LBM_ERR_ARG, kw
     r.set_launch(bulk_tx=256, graph_steps=0, overlap=1)
+    with pytest.raises(lbm.LbmError) as ei:
+        r.set_nrbc_pml_terms(8)
+    assert ei.value.status == lbm.LBM_ERR_ARG
+    r.set_nrbc_pml_terms(5)
     assert r.get_launch() == dict(bulk_tx=256, bulk_ty=1, graph_steps=0, overlap=1)
     with pytest.raises(lbm.LbmError):
         r.profile(3)

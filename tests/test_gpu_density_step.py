@@ -45,3 +45,17 @@ def test_density_step_study_reproduces_paper_trends():
     assert by[("zg", 40)]["C_rho"] < 0.5 and by[("zg", 40)]["C_ux"] < 0.5
     assert all(by[(bc, W)]["C_t"] > 1.0 for bc in ("zg", "nrbc") for W in (10, 20, 40))
     assert nref == 200 + 2 * (1800 + 16)
+
+
+def test_appendix_pml_terms_on_density_step():
+    """Appendix experiment (density step, characteristic boundary behind a PML of W = 10,
+    sigma_max = 0.001, 600 steps) with every combination of the PML moment terms: all stay
+    stable, and every combination that includes term II loses accuracy against the plain
+    LODI-PML, as the appendix reports."""
+    rows = studies.appendix_study(steps=600)
+    for d in rows:
+        say({k: (round(v, 6) if isinstance(v, float) else v) for k, v in d.items()})
+    assert all(d["stable"] for d in rows)
+    by = {d["pml_terms"]: d for d in rows if d["bc"] == "nrbc"}
+    for f in (2, 3, 6, 7):
+        assert by[f]["ebar_rho"] > 1.5 * by[0]["ebar_rho"], f

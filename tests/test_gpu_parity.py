@@ -16,11 +16,6 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 
 
-@pytest.fixture(scope="module")
-def perm(oracle_mod):
-    return perm_lib_to_oracle(oracle_mod)
-
-
 def _assert_parity(err, tol=TOL, f_tol=TOL):
     """rho, u, T within 1e-12; populations (relative to each weight) within f_tol, which is
     1e-12 unless the case's measured conditioning floor is higher."""
@@ -321,3 +316,19 @@ def test_population_layouts_bitwise_identical(oracle_mod, perm, storage):
         o.step(45)
         mo = o.moments()
         assert max(np.abs(a - b).max() for a, b in zip(outs[0][1], mo)) < 1e-12
+
+
+@pytest.mark.parametrize("flags", [1, 2, 4, 7])
+def test_nrbc_pml_terms_match_oracle(oracle_mod, perm, flags):
+    """Appendix terms in the characteristic target: FP64 library vs oracle on noisy data with an
+    NRBC behind a PML on every side (sigma_max = 0.01, 30 steps)."""
+    mean = (1.0, 0.05, 0.02, 1.0)
+    g, o = make_pair(oracle_mod, 44, 38, mean=mean, bc="nrbc", pml=(15, 7, 0.01), fields=noise(9, mean),
+                     gpu=True, pml_terms=flags)
+    g.step(30)
+    o.step(30)
+    e = rel_errors(g, o, perm)
+    say(flags, e)
+    assert e["rho"] < 1e-12 and e["ux"] < 1e-12 and e["uy"] < 1e-12 and e["T"] < 1e-12
+    assert e["f"] < 1e-11
+    g.close()

@@ -324,3 +324,59 @@ def test_error_norm_definition(oracle_mod):
     got = o.error_norms(rho, ux, T)
     assert got[0] == pytest.approx(1e-3, rel=1e-9)
     assert got[1] < 1e-13 and got[2] < 1e-13
+
+
+def _conserved_densities(rho, ux, uy, T):
+    """(rho, rho u, rho (|u|^2/2 + T)): the densities of mass, momentum and total energy of the
+    thermal model (internal energy (d/2) T with d = 2, c_s = 1)."""
+    return np.array([rho, rho * ux, rho * uy, rho * (0.5 * (ux * ux + uy * uy) + T)])
+
+
+@pytest.mark.parametrize("flags", [1, 2, 4, 6, 7])
+def test_pml_terms_keep_the_mean_state_stationary(oracle_mod, flags):
+    """Appendix: every PML moment term vanishes at the mean state (Q = 0, U = Ubar), so a run at
+    its mean stays there (the appendix's sigma_max = 0.001, 50 steps).  None of the terms damps
+    round-off at the boundary (each feeds the node's own deviation back into its target), so
+    the span is short."""
+    sigma, steps = 0.001, 50
+    mean = (1.0, 0.05, -0.02, 1.0)
+    o = oracle_mod.OracleRun(24, 20, 0.8, *mean)
+    o.set_bc(15, 2)
+    o.set_pml(15, 6, sigma)
+    o.set_nrbc_pml_terms(flags)
+    Nx, Ny = o.grid()
+    o.init(*wl.uniform_state(Nx, Ny, *mean).as_tuple())
+    o.step(steps)
+    for a, v in zip(o.moments(), mean):
+        assert np.abs(a - v).max() < 1e-12
+
+
+def test_pml_term_two_moves_conserved_state_by_its_source(oracle_mod):
+    """Appendix, term II alone: over the first step of a uniform state (Q = 0, no gradients, so
+    the LODI increment vanishes) the characteristic target of an outer-layer node changes its
+    conserved densities by +2 sigma (U - Ubar) (the appendix's sign): the velocity moments of
+    2 sigma fhat.  The primitive update is first order, so the check holds to O(|s|^2)."""
+    mean = (1.0, 0.0, 0.0, 1.0)
+    U0 = (1.0 + 2e-4, 3e-4, -1e-4, 1.0 - 2e-4)
+    sigma, W = 0.2, 6
+    o = oracle_mod.OracleRun(24, 20, 0.8, *mean)
+    o.set_bc(15, 2)
+    o.set_pml(15, W, sigma)
+    o.set_nrbc_pml_terms(2)
+    Nx, Ny = o.grid()
+    o.init(*wl.uniform_state(Nx, Ny, *U0).as_tuple())
+    o.step(1)
+    m = o.moments()
+    y = Ny // 2
+    got = _conserved_densities(*(a[y, 0] for a in m)) - _conserved_densities(*U0)
+    want = 2.0 * sigma * (_conserved_densities(*U0) - _conserved_densities(*mean))   # sigma(level W) = sigma_max
+    assert np.abs(got - want).max() < 1e-3 * np.abs(want).max()
+    # interior nodes see no boundary source
+    assert abs(m[0][y, Nx // 2] - U0[0]) < 1e-14
+    # and without the flag the same node stays at U0
+    o2 = oracle_mod.OracleRun(24, 20, 0.8, *mean)
+    o2.set_bc(15, 2)
+    o2.set_pml(15, W, sigma)
+    o2.init(*wl.uniform_state(Nx, Ny, *U0).as_tuple())
+    o2.step(1)
+    assert abs(o2.moments()[0][y, 0] - U0[0]) < 1e-14
