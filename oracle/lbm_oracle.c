@@ -515,7 +515,10 @@ static void one_step(orc_run *r) {
         for (int x = 0; x < Nx; ++x) {
             int bnd = 0, nrbc = 0;
             for (int s = 0; s < 4; ++s)
-                if (is_boundary_side(r, s, x, y)) { bnd = 1; nrbc |= (r->bc[s] == BC_NRBC); }
+                if (is_boundary_side(r, s, x, y)) {
+                    bnd = 1;
+                    nrbc |= (r->bc[s] == BC_NRBC);
+                }
             if (!bnd) continue;
             int xf = ox ? clampi(x, 3, Nx - 4) : x;
             int yf = oy ? clampi(y, 3, Ny - 4) : y;
@@ -527,12 +530,13 @@ static void one_step(orc_run *r) {
             }
             const double *Ub = r->U + 4 * ((size_t)y * Nx + x);
             double Ut[4] = {Ub[0], Ub[1], Ub[2], Ub[3]};
-            for (int s = 0; s < 4; ++s)
-                if (is_boundary_side(r, s, x, y) && r->bc[s] == BC_NRBC) {
-                    double d[4];
-                    lodi_increment(r, s, x, y, d);
-                    for (int k = 0; k < 4; ++k) Ut[k] += d[k];
-                }
+            for (int s = 0; s < 4; ++s) {
+                if (!is_boundary_side(r, s, x, y)) continue;
+                double d[4];
+                if (r->bc[s] != BC_NRBC) continue;
+                lodi_increment(r, s, x, y, d);
+                for (int k = 0; k < 4; ++k) Ut[k] += d[k];
+            }
             {
                 double d[4];
                 pml_source(r, x, y, d);

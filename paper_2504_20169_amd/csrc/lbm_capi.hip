@@ -162,6 +162,7 @@ lbm_status setup_geometry(lbm_run *h, RunDev &R) {
     R.W = h->W;
     for (int s = 0; s < 4; ++s) R.bc[s] = h->bc[s];
     R.pml_terms = (int)h->pml_terms;
+    R.tgt_pre = h->pml_terms != 0;
     if ((h->bc[XMIN] == BC_PERIODIC) != (h->bc[XMAX] == BC_PERIODIC) ||
         (h->bc[YMIN] == BC_PERIODIC) != (h->bc[YMAX] == BC_PERIODIC))
         return fail(LBM_ERR_ARG, "periodic must be set on both sides of an axis");
@@ -283,7 +284,7 @@ size_t footprint_of(const RunDev &R, int storage) {
     if (R.has_q) b += (size_t)NQ * R.qplane * compute_size(storage);
     b += 2 * 4 * (size_t)R.qplane * sizeof(double);
     if (R.ring_n > 0) b += (size_t)NQ * R.rplane * compute_size(storage);
-    if (R.pml_terms && R.ring_n > 0) b += 4 * (size_t)R.rplane * sizeof(double);
+    if (R.tgt_pre && R.ring_n > 0) b += 4 * (size_t)R.rplane * sizeof(double);
     b += sizeof(RunDev) + 256 * 3 + NQ * sizeof(double);
     return b;
 }
@@ -295,7 +296,7 @@ void compute_blocks(const RunDev &R, int tx, int nb[NCLS]) {
     const int rb = (R.ring_n + RING_BLOCK - 1) / RING_BLOCK;
     nb[CLS_FRAME] = rb + fb;
     nb[CLS_A] = rb + (R.has_q ? fb : 0);
-    nb[CLS_PM] = R.pml_terms ? rb : 0;
+    nb[CLS_TGT] = R.tgt_pre ? rb : 0;
 }
 
 lbm_status upload_prefix(lbm_run *h) {
@@ -368,7 +369,7 @@ lbm_status enqueue_step(const LaunchSet &L, int storage, int tx, hipStream_t s, 
     const bool classes = mode == 1;
     if (!ss || !ss->ok || classes) {
         if (classes && has_a) HIP_TRY(hipEventRecord(ev[4], s));
-        HIP_TRY(launch_pml_moments(L, storage, s));
+        HIP_TRY(launch_target(L, storage, s));
         HIP_TRY(launch_phase_a(L, storage, s));
         if (classes && has_a) HIP_TRY(hipEventRecord(ev[5], s));
         if (classes && has_f) HIP_TRY(hipEventRecord(ev[2], s));
@@ -380,7 +381,7 @@ lbm_status enqueue_step(const LaunchSet &L, int storage, int tx, hipStream_t s, 
     } else {
         HIP_TRY(hipEventRecord(ss->fork, s));
         HIP_TRY(hipStreamWaitEvent(ss->side, ss->fork, 0));
-        HIP_TRY(launch_pml_moments(L, storage, ss->side));
+        HIP_TRY(launch_target(L, storage, ss->side));
         HIP_TRY(launch_phase_a(L, storage, ss->side));
         HIP_TRY(launch_frame(L, storage, ss->side));
         HIP_TRY(hipEventRecord(ss->done, ss->side));
@@ -607,7 +608,7 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux, co
     }
     R.Q = R.has_q ? h->mem.get((size_t)NQ * R.qplane * cs) : nullptr;
     R.G = R.ring_n > 0 ? h->mem.get((size_t)NQ * R.rplane * cs) : nullptr;
-    const bool need_p = R.pml_terms && R.ring_n > 0;
+    const bool need_p = R.tgt_pre && R.ring_n > 0;
     R.P = need_p ? (double *)h->mem.get(4 * (size_t)R.rplane * sizeof(double)) : nullptr;
     h->dd = (RunDev *)h->mem.get(sizeof(RunDev));
     h->dptr = (RunDev **)h->mem.get(sizeof(RunDev *));

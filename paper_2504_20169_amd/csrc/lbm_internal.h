@@ -43,9 +43,9 @@ struct alignas(256) RunDev {
     void *Q;                  // [37][qplane] in the compute type
     double *U[2];             // [4][qplane]: rho, ux, uy, T (absolute values)
     void *G;                  // [37][rplane] compute type: post-boundary populations of the ring
-    double *P;                // [4][rplane]: start of the NRBC target, U^n + PML moments (if pml_terms)
+    double *P;                // [4][rplane]: characteristic targets formed by k_target (if tgt_pre)
     long long rplane;
-    int par, pad0;
+    int par, tgt_pre;         // tgt_pre: NRBC targets formed by k_target (PML moments selected)
     long long step, limit;    // a run is active while step < limit
     // constants (double and float copies)
     double omega, rho0, u0x, u0y, T0, th0, b0, r0x, r0y, sigma_max, inv_W2, scale, inv_scale;
@@ -56,9 +56,9 @@ struct alignas(256) RunDev {
 
 // Launch decomposition of a set of runs: prefix[k] = first block of run k, prefix[n] = total.
 // Classes: the interior tiles; the frame launch (ring blocks, then frame blocks); the phase-A
-// launch (ring blocks, then frame blocks if the run has a PML); the PML moments of the NRBC
-// target (ring blocks of runs that select them).
-enum Cls { CLS_BULK = 0, CLS_FRAME = 1, CLS_A = 2, CLS_PM = 3, NCLS = 4 };
+// launch (ring blocks, then frame blocks if the run has a PML); the characteristic targets of
+// runs that select the PML moments (ring blocks).
+enum Cls { CLS_BULK = 0, CLS_FRAME = 1, CLS_A = 2, CLS_TGT = 3, NCLS = 4 };
 struct LaunchSet {
     RunDev *const *runs;      // device array of descriptor pointers
     const int *prefix[NCLS];  // device prefix arrays per class
@@ -78,7 +78,7 @@ constexpr int RING_BLOCK = 64;
 // of every frame node, ring included.
 hipError_t launch_phase_a(const LaunchSet &L, int storage, hipStream_t s);
 hipError_t launch_frame(const LaunchSet &L, int storage, hipStream_t s);
-hipError_t launch_pml_moments(const LaunchSet &L, int storage, hipStream_t s);
+hipError_t launch_target(const LaunchSet &L, int storage, hipStream_t s);
 hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, hipStream_t s);
 hipError_t launch_flip(const LaunchSet &L, hipStream_t s);
 hipError_t launch_set_limit(RunDev *run, long long limit, hipStream_t s);

@@ -532,17 +532,18 @@ __device__ __forceinline__ void pml_moments(CRun &R, int x, int y, int t, const 
 // nodes per block), then the frame (frame numbering, FRAME_BLOCK nodes per block).
 __device__ __forceinline__ int ring_blocks(CRun &R) { return (R.ring_n + RING_BLOCK - 1) / RING_BLOCK; }
 
-// Start of the characteristic target for runs that select the PML moments of the appendix:
-// P = U^n(x_b) + the moments (4 planes of the ring numbering, float64) for every ring node;
-// launched before phase A, which starts the target from P instead of U^n.
+// Characteristic targets of the ring, formed ahead of phase A for runs that select the appendix's
+// PML moments: U_tgt = U^n(x_b) plus the LODI increment of each NRBC side the node lies on
+// (corners add both normals) plus the PML moments; stored to P (4 planes of the ring numbering,
+// float64).
 template <class S>
-__global__ __launch_bounds__(256) void k_pml_moments(RunDev *const *__restrict__ runs,
-                                                     const int *__restrict__ prefix, int nruns) {
+__global__ __launch_bounds__(256) void k_target(RunDev *const *__restrict__ runs,
+                                                const int *__restrict__ prefix, int nruns) {
     using C = typename Traits<S>::C;
     const int b = blockIdx.x;
     const int j = find_run(prefix, nruns, b);
     CRun &R = run_of(runs, j);
-    if (R.step >= R.limit || !R.pml_terms) return;
+    if (R.step >= R.limit || !R.tgt_pre) return;
     if ((int)threadIdx.x >= RING_BLOCK) return;
     const int tt = (b - ((const CONSTANT int *)prefix)[j]) * RING_BLOCK + (int)threadIdx.x;
     if (tt >= R.ring_n) return;
@@ -552,12 +553,21 @@ __global__ __launch_bounds__(256) void k_pml_moments(RunDev *const *__restrict__
     if (t < 0) return;
     const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par];
     const unsigned qp = (unsigned)R.qplane;
-    double dU[4];
-    pml_moments<C>(R, x, y, t, Uc, dU);
+    double Ut[4] = {Uc[t], Uc[qp + t], Uc[2 * qp + t], Uc[3 * qp + t]};
+    for (int s = 0; s < 4; ++s) {
+        const bool on = s == XMIN ? x < 3 : s == XMAX ? x >= R.Nx - 3 : s == YMIN ? y < 3 : y >= R.Ny - 3;
+        if (!on) continue;
+        if (R.bc[s] == BC_NRBC) lodi_add(R, Uc, s, x, y, t, Ut);
+    }
+    if (R.pml_terms) {
+        double dU[4];
+        pml_moments<C>(R, x, y, t, Uc, dU);
+        for (int k = 0; k < 4; ++k) Ut[k] += dU[k];
+    }
     GLOBAL double *P = (GLOBAL double *)R.P;
     const unsigned rp = (unsigned)R.rplane;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) P[k * rp + tt] = Uc[k * qp + t] + dU[k];
+    for (int k = 0; k < 4; ++k) P[k * rp + tt] = Ut[k];
 }
 
 // Ring node of characteristic sides: U_tgt = U(x_b) of the last completed level plus the LODI
@@ -570,16 +580,16 @@ __device__ __forceinline__ void nrbc_node(CRun &R, int tt, int x, int y, int t, 
                                           C (&g)[NQ]) {
     const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par];
     const unsigned qp = (unsigned)R.qplane;
-    // the target starts from U^n(x_b), or from U^n(x_b) plus the PML moments of the appendix
-    // when the run selects them (formed by k_pml_moments in ring numbering)
-    const bool pm = R.pml_terms != 0;
-    const GLOBAL double *Ub = pm ? (const GLOBAL double *)R.P : Uc;
-    const unsigned ib = pm ? (unsigned)tt : (unsigned)t, sb = pm ? (unsigned)R.rplane : qp;
+    // the target: U^n(x_b) plus the LODI increments, or, for runs that select the appendix's PML
+    // moments, the whole target formed by k_target in ring numbering
+    const bool pre = R.tgt_pre != 0;
+    const GLOBAL double *Ub = pre ? (const GLOBAL double *)R.P : Uc;
+    const unsigned ib = pre ? (unsigned)tt : (unsigned)t, sb = pre ? (unsigned)R.rplane : qp;
     double Ut[4] = {Ub[ib], Ub[sb + ib], Ub[2 * sb + ib], Ub[3 * sb + ib]};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         bool on = s == XMIN ? x < 3 : s == XMAX ? x >= R.Nx - 3 : s == YMIN ? y < 3 : y >= R.Ny - 3;
-        if (on && R.bc[s] == BC_NRBC) lodi_add(R, Uc, s, x, y, t, Ut);
+        if (on && !pre && R.bc[s] == BC_NRBC) lodi_add(R, Uc, s, x, y, t, Ut);
     }
     gather_clamped<S, C>(R, (const GLOBAL S *)R.f[R.par], x, y, inv_scale, g);
     nrbc_fill<C>(R, Ut, g);
@@ -1020,10 +1030,10 @@ hipError_t launch_phase_a(const LaunchSet &L, int storage, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_pml_moments(const LaunchSet &L, int storage, hipStream_t s) {
-    if (L.blocks[CLS_PM] > 0)
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_pml_moments<S>), dim3(L.blocks[CLS_PM]), dim3(256), 0, s,
-                                                 L.runs, L.prefix[CLS_PM], L.nruns));
+hipError_t launch_target(const LaunchSet &L, int storage, hipStream_t s) {
+    if (L.blocks[CLS_TGT] > 0)
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_target<S>), dim3(L.blocks[CLS_TGT]), dim3(256), 0, s,
+                                                 L.runs, L.prefix[CLS_TGT], L.nruns));
     return hipGetLastError();
 }
 

@@ -92,6 +92,8 @@ def density_step_study(steps=600, sample=10, Lx=200, Ly=20, mach=0.05, tau=0.8,
         ref.step(n)
         for run in runs:
             run[3].step(n)
+            if done == 0:
+                run[3].profile_read(reset=True)   # first launches carry one-off set-up costs
         done += n
         rho, ux, _, T = ref.moments()
         win = (slice(None), slice(ext, ext + Lx))
@@ -146,6 +148,73 @@ def appendix_study(steps=600, W=10, sigma=0.001, flag_sets=(0, 1, 2, 4, 3, 5, 6,
     return rows
 
 
+def vortex_outlet_study(steps=2000, sample=20, L=300, W=10, mach=0.1, strength=0.05, radius=24.0,
+                        x_shift=60.0, tau=0.8, storage="f64", configs=None):
+    """Sec. 5.2 setting with this build's vortex: mean flow Mach `mach` along +x through an
+    L x L bulk open on every side, an isentropic vortex (`workloads.add_isentropic_vortex`)
+    starting `x_shift` cells downstream of the centre, so it leaves through the +x side.
+    configs: (name, outlet kind, other sides' kind, W, sigma_max); default: ZG and the perfectly
+    non-reflecting LODI everywhere (the paper's scheme B), each with and without a PML (the
+    paper's sigma_max for W = 10).
+    Reference: the same data on a fully periodic grid extended by 1.3 steps + 32 cells on every
+    side.  Returns rows with ebar_rho, ebar_ux, ebar_T and C_Z against ZG without PML."""
+    from paper_2504_20169_amd import lbm
+    from paper_2504_20169_amd import workloads as wl
+
+    if configs is None:
+        configs = [("zg", "zg", "zg", 0, 0.0), ("zg+pml", "zg", "zg", W, 0.02),
+                   ("B", "nrbc", "nrbc", 0, 0.0), ("B+pml", "nrbc", "nrbc", W, 0.007)]
+
+    def fields(N, off):
+        F = wl.uniform_state(N, N, 1.0, mach, 0.0, 1.0)
+        c = off + 0.5 * (L - 1)
+        return wl.add_isentropic_vortex(F, c + x_shift, c, strength, radius)
+
+    ext = int(math.ceil(1.3 * steps)) + 32
+    Nref = L + 2 * ext
+    ref = lbm.Run(Nref, Nref, tau, 1.0, mach, 0.0, 1.0, storage=storage)
+    ref.init(*fields(Nref, ext).as_tuple())
+    runs = []
+    for name, outlet, other, w, sg in configs:
+        r = lbm.Run(L, L, tau, 1.0, mach, 0.0, 1.0, storage=storage)
+        r.set_bc(lbm.LBM_ALL, other)
+        r.set_bc(lbm.LBM_XMAX, outlet)
+        if w:
+            r.set_pml(lbm.LBM_ALL, w, sg)
+        r.init(*fields(L + 2 * w, w).as_tuple())
+        r.profile(1)
+        runs.append((name, outlet, other, w, sg, r, []))
+    done = 0
+    win = (slice(ext, ext + L), slice(ext, ext + L))
+    while done < steps:
+        n = min(sample, steps - done)
+        ref.step(n)
+        for run in runs:
+            run[5].step(n)
+            if done == 0:
+                run[5].profile_read(reset=True)   # first launches carry one-off set-up costs
+        done += n
+        rho, ux, _, T = ref.moments()
+        for run in runs:
+            run[6].append(run[5].error_norms(rho[win], ux[win], T[win]))
+    out = []
+    for name, outlet, other, w, sg, r, errs in runs:
+        ms, _ = r.profile_read()
+        e = np.array(errs)
+        ok = r.check() == lbm.LBM_OK and np.all(np.isfinite(e))
+        out.append(dict(name=name, outlet=outlet, other=other, W=w, sigma_max=sg, stable=bool(ok),
+                        ebar_rho=float(e[:, 0].mean()), ebar_ux=float(e[:, 1].mean()),
+                        ebar_T=float(e[:, 2].mean()), t_bc_ms=float(ms[1] + ms[2]), steps=steps))
+        r.close()
+    ref.close()
+    base = out[0]
+    for d in out:
+        for z in ("rho", "ux", "T"):
+            d["C_" + z] = d["ebar_" + z] / base["ebar_" + z]
+        d["C_t"] = d["t_bc_ms"] / base["t_bc_ms"] if base["t_bc_ms"] > 0 else None
+    return out, Nref
+
+
 def main():
     import argparse
     import json
@@ -155,6 +224,8 @@ def main():
     ap.add_argument("--sample", type=int, default=10)
     ap.add_argument("--storage", default="f64")
     ap.add_argument("--scan", action="store_true", help="also scan sigma_max per boundary and W")
+    ap.add_argument("--vortex", action="store_true",
+                    help="also run the vortex outflow through ZG and LODI (B) boundaries")
     ap.add_argument("--appendix", action="store_true",
                     help="also run the appendix's PML-moment terms on the characteristic boundary")
     args = ap.parse_args()
@@ -166,6 +237,11 @@ def main():
         _, best = sigma_scan(args.steps, storage=args.storage)
         for (bc, W), d in sorted(best.items()):
             print(json.dumps(dict(scan_best=True, **d)))
+    if args.vortex:
+        rows_v, nv = vortex_outlet_study(storage=args.storage)
+        for d in rows_v:
+            print(json.dumps(dict(vortex=True, **d)))
+        print(json.dumps(dict(vortex_reference_grid=nv)))
     if args.appendix:
         for d in appendix_study(args.steps, storage=args.storage):
             print(json.dumps(dict(appendix=True, **d)))
