@@ -1,11 +1,14 @@
-"""FP64 CPU oracle for the D2Q37 thermal LBM + PML + open boundaries (arXiv 2504.20169).
+"""FP64 CPU oracle for the D2Q37 / D2Q17 thermal LBM + PML + open boundaries (arXiv 2504.20169).
 
 TEST INFRASTRUCTURE ONLY: only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
 of ``bench.py`` may import this package.  It shares no code with the HIP library; see the header
 of ``lbm_oracle.c`` for what each function follows and how it is pinned.
 
-Layouts: fields are row-major ``[Ny][Nx]`` float64 arrays; populations are ``[37][Ny][Nx]`` in
-this oracle's own velocity order (``lattice()[0]``), which differs from the library's order.
+Layouts: fields are row-major ``[Ny][Nx]`` float64 arrays; populations are ``[q][Ny][Nx]`` in
+this oracle's own velocity order (``lattice(q)[0]``), which differs from the library's order.
+
+The C source is compiled once per velocity stencil (``-DORC_Q=37`` and ``-DORC_Q=17``); every
+entry point takes the stencil as ``q`` (``lattice=`` for runs), 37 by default.
 """
 from __future__ import annotations
 
@@ -17,31 +20,43 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+_LIBS = {37: os.path.join(_HERE, "liboracle.so"), 17: os.path.join(_HERE, "liboracle17.so")}
+LATTICES = (37, 17)
 
 SIDE_XMIN, SIDE_XMAX, SIDE_YMIN, SIDE_YMAX, SIDE_ALL = 1, 2, 4, 8, 15
 BC_PERIODIC, BC_ZG, BC_NRBC = 0, 1, 2
 
-_lib = None
+_libs = {}
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no FP contraction, no fast-math, OpenMP)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-                               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+def _lib_path(q: int) -> str:
+    if q not in _LIBS:
+        raise ValueError("oracle: velocity stencil must be one of %s, got %r" % (LATTICES, q))
+    return _LIBS[q]
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB):
+def build(force: bool = True) -> list:
+    """Compile the oracle with gcc (-O2, no FP contraction, no fast-math, OpenMP), once per
+    velocity stencil."""
+    out = []
+    for q in LATTICES:
+        path = _lib_path(q)
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                                   "-DORC_Q=%d" % q, "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, path)
+        out.append(path)
+    return out
+
+
+def _load(q: int = 37):
+    if q in _libs:
+        return _libs[q]
+    path = _lib_path(q)
+    if not os.path.exists(path):
         build(force=True)
-    lib = ctypes.CDLL(_LIB)
+    lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     dp = ctypes.POINTER(ctypes.c_double)
     ip = ctypes.POINTER(ctypes.c_int)
@@ -66,7 +81,7 @@ def _load():
     lib.orc_moments_of.argtypes = [dp, dp]
     lib.orc_last_error.restype = ctypes.c_char_p
     lib.orc_threads.restype = ctypes.c_int
-    _lib = lib
+    _libs[q] = lib
     return lib
 
 
@@ -74,31 +89,34 @@ def _dp(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _check(rc: int):
+def _check(rc: int, q: int = 37):
     if rc != 0:
-        raise RuntimeError("oracle: " + _load().orc_last_error().decode())
+        raise RuntimeError("oracle: " + _load(q).orc_last_error().decode())
 
 
-def lattice():
-    """(e [37,2] int, w [37], r) derived by the oracle's own quadrature solve."""
-    lib = _load()
-    e = np.zeros((37, 2), dtype=np.int32)
-    w = np.zeros(37)
+def lattice(q: int = 37):
+    """(e [q,2] int, w [q], r) derived by the oracle's own quadrature solve."""
+    lib = _load(q)
+    e = np.zeros((q, 2), dtype=np.int32)
+    w = np.zeros(q)
     r = ctypes.c_double()
-    _check(lib.orc_lattice(e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(w), ctypes.byref(r)))
+    _check(lib.orc_lattice(e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(w), ctypes.byref(r)), q)
     return e.astype(np.int64), w, r.value
 
 
-def feq(rho, ux, uy, T) -> np.ndarray:
-    out = np.zeros(37)
-    _check(_load().orc_feq(rho, ux, uy, T, _dp(out)))
+def feq(rho, ux, uy, T, q: int = 37) -> np.ndarray:
+    """Equilibrium of the stencil: eq. feq-4 for D2Q37, eq. feq-3 for D2Q17."""
+    out = np.zeros(q)
+    _check(_load(q).orc_feq(rho, ux, uy, T, _dp(out)), q)
     return out
 
 
-def moments_of(f: np.ndarray) -> np.ndarray:
+def moments_of(f: np.ndarray, q: int = 37) -> np.ndarray:
     f = np.ascontiguousarray(f, dtype=np.float64)
+    if f.shape[0] != q:
+        raise ValueError("oracle: expected %d populations, got %d" % (q, f.shape[0]))
     U = np.zeros(4)
-    _check(_load().orc_moments_of(_dp(f), _dp(U)))
+    _check(_load(q).orc_moments_of(_dp(f), _dp(U)), q)
     return U
 
 
@@ -110,14 +128,18 @@ class OracleRun:
     """One oracle simulation.  Mirrors the library's configuration order:
     create -> set_pml / set_bc -> init -> step ..."""
 
-    def __init__(self, Lx, Ly, tau, rho0=1.0, ux0=0.0, uy0=0.0, T0=1.0):
-        lib = _load()
+    def __init__(self, Lx, Ly, tau, rho0=1.0, ux0=0.0, uy0=0.0, T0=1.0, lattice=37):
+        lib = _load(lattice)
+        self.q = int(lattice)
         self._lib = lib
         self._h = lib.orc_create(int(Lx), int(Ly), float(tau), float(rho0), float(ux0),
                                  float(uy0), float(T0))
         if not self._h:
             raise RuntimeError("oracle: " + lib.orc_last_error().decode())
         self.Lx, self.Ly = int(Lx), int(Ly)
+
+    def _ck(self, rc):
+        _check(rc, self.q)
 
     def close(self):
         if self._h:
@@ -131,29 +153,29 @@ class OracleRun:
             pass
 
     def set_pml(self, mask, W, sigma_max):
-        _check(self._lib.orc_set_pml(self._h, int(mask), int(W), float(sigma_max)))
+        self._ck(self._lib.orc_set_pml(self._h, int(mask), int(W), float(sigma_max)))
 
     def set_bc(self, mask, kind):
-        _check(self._lib.orc_set_bc(self._h, int(mask), int(kind)))
+        self._ck(self._lib.orc_set_bc(self._h, int(mask), int(kind)))
 
     def set_nrbc_pml_terms(self, flags):
         """Appendix: moments of the PML collision term in the characteristic target update
         (bit 0 term I, bit 1 term II, bit 2 term III)."""
-        _check(self._lib.orc_set_nrbc_pml_terms(self._h, int(flags)))
+        self._ck(self._lib.orc_set_nrbc_pml_terms(self._h, int(flags)))
 
     def grid(self):
         nx, ny = ctypes.c_int(), ctypes.c_int()
-        _check(self._lib.orc_grid(self._h, ctypes.byref(nx), ctypes.byref(ny)))
+        self._ck(self._lib.orc_grid(self._h, ctypes.byref(nx), ctypes.byref(ny)))
         return nx.value, ny.value
 
     def init(self, rho, ux, uy, T):
         Nx, Ny = self.grid()
         arrs = [np.ascontiguousarray(np.broadcast_to(a, (Ny, Nx)), dtype=np.float64)
                 for a in (rho, ux, uy, T)]
-        _check(self._lib.orc_init(self._h, *[_dp(a) for a in arrs]))
+        self._ck(self._lib.orc_init(self._h, *[_dp(a) for a in arrs]))
 
     def step(self, n, threads=0):
-        _check(self._lib.orc_step(self._h, int(n), int(threads)))
+        self._ck(self._lib.orc_step(self._h, int(n), int(threads)))
 
     @property
     def step_count(self):
@@ -162,29 +184,29 @@ class OracleRun:
     def moments(self):
         Nx, Ny = self.grid()
         out = [np.zeros((Ny, Nx)) for _ in range(4)]
-        _check(self._lib.orc_moments(self._h, *[_dp(a) for a in out]))
+        self._ck(self._lib.orc_moments(self._h, *[_dp(a) for a in out]))
         return out
 
     def populations(self):
         Nx, Ny = self.grid()
-        out = np.zeros((37, Ny, Nx))
-        _check(self._lib.orc_populations(self._h, _dp(out)))
+        out = np.zeros((self.q, Ny, Nx))
+        self._ck(self._lib.orc_populations(self._h, _dp(out)))
         return out
 
     def pml_q(self):
         Nx, Ny = self.grid()
-        out = np.zeros((37, Ny, Nx))
-        _check(self._lib.orc_pml_q(self._h, _dp(out)))
+        out = np.zeros((self.q, Ny, Nx))
+        self._ck(self._lib.orc_pml_q(self._h, _dp(out)))
         return out
 
     def sigma(self):
         Nx, Ny = self.grid()
         out = np.zeros((Ny, Nx))
-        _check(self._lib.orc_sigma(self._h, _dp(out)))
+        self._ck(self._lib.orc_sigma(self._h, _dp(out)))
         return out
 
     def error_norms(self, ref_rho, ref_ux, ref_T):
         refs = [np.ascontiguousarray(a, dtype=np.float64) for a in (ref_rho, ref_ux, ref_T)]
         out = np.zeros(3)
-        _check(self._lib.orc_error_norms(self._h, *[_dp(a) for a in refs], _dp(out)))
+        self._ck(self._lib.orc_error_norms(self._h, *[_dp(a) for a in refs], _dp(out)))
         return out

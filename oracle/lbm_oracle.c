@@ -1,12 +1,13 @@
 /*
- * FP64 CPU oracle for the D2Q37 thermal lattice Boltzmann scheme with a perfectly matched
- * layer (PML) and open outer boundaries, following arXiv 2504.20169.
+ * FP64 CPU oracle for the D2Q37 (and, built with -DORC_Q=17, D2Q17) thermal lattice Boltzmann
+ * scheme with a perfectly matched layer (PML) and open outer boundaries, following
+ * arXiv 2504.20169.
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the HIP library is
  * checked against.  Only the tests, the smoke check and the benchmark's CPU-baseline leg may
  * load it.  It shares no code, header, table or constant with the HIP library: the lattice
  * weights are re-derived here from the quadrature conditions, the equilibrium is the printed
- * polynomial (Sec. 2, eq. feq-4), and the characteristic boundary solves S x = L with a generic
+ * polynomial (Sec. 2, eqs. feq-3 and feq-4), and the characteristic boundary solves S x = L with a generic
  * elimination instead of a closed-form inverse.
  *
  * Units: thermal units (c_s = 1, xi_i = r e_i) for rho, u, T in the equilibrium and moments;
@@ -15,8 +16,9 @@
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
  *
- * Pins (tests/test_oracle_*.py): quadrature moments vs the Gaussian up to degree 9 and the
- * published D2Q37 weights; equilibrium moments vs Maxwellian moments; exact conservation on a
+ * Pins (tests/test_oracle_*.py), for both stencils: quadrature moments vs the Gaussian up to the
+ * rule's degree (9 and 7) and the published D2Q37 / closed-form D2Q17 weights; equilibrium
+ * moments vs Maxwellian moments (to order 4 and 3); exact conservation on a
  * periodic box; rest and uniform states stationary under every boundary and PML; sigma_max = 0
  * PML identical to no PML; linear growth of Q under a constant deviation; mirror symmetry;
  * linear acoustics vs the linearised Navier-Stokes-Fourier solution; ZG+PML reflecting less
@@ -31,11 +33,16 @@
 #include <string.h>
 #include <omp.h>
 
-#define NQ 37
+/* Velocity stencil of this build: ORC_Q = 37 (default) or 17, one shared library each. */
+#ifndef ORC_Q
+#define ORC_Q 37
+#endif
+#define NQ ORC_Q
 
 /* ------------------------------------------------------------------------------------------ */
-/* Lattice: Sec. 2 "Velocity stencils".  The D2Q37 set is the minimal ninth-order rule with      */
-/* integer velocities of maximum displacement 3 and non-negative weights.                        */
+/* Lattice: Sec. 2 "Velocity stencils".  D2Q37 is the minimal ninth-order rule and D2Q17 the     */
+/* minimal seventh-order rule with integer velocities of maximum displacement 3 and non-negative */
+/* weights.                                                                                      */
 /* ------------------------------------------------------------------------------------------ */
 
 static int    LE[NQ][2];   /* integer velocities e_i (lattice units) */
@@ -43,12 +50,20 @@ static double LW[NQ];      /* weights w_i */
 static double LR;          /* scale r: thermal velocity xi_i = r e_i */
 static int    lattice_ok = 0;
 
-/* The eight shells by |e|^2; the grid search below over |ex|,|ey| <= 3 picks exactly these. */
-static const int SHELL_E2[8] = {0, 1, 2, 4, 5, 8, 9, 10};
+/* The shells by |e|^2; the grid search below over |ex|,|ey| <= 3 picks exactly these velocities
+ * (for D2Q17: the rest velocity, the 4 axis and 4 diagonal unit velocities, (+-2,+-2) and the 4
+ * axis velocities of length 3). */
+#if ORC_Q == 17
+#define NS 5
+static const int SHELL_E2[NS] = {0, 1, 2, 8, 9};
+#else
+#define NS 8
+static const int SHELL_E2[NS] = {0, 1, 2, 4, 5, 8, 9, 10};
+#endif
 
 static int shell_of(int ex, int ey) {
     int s = ex * ex + ey * ey;
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < NS; ++k)
         if (SHELL_E2[k] == s) return k;
     return -1;
 }
@@ -93,11 +108,16 @@ static int solve_ld(int n, long double *A, long double *b) {
     return 0;
 }
 
-/* The nine D4-invariant even moment conditions of a degree-9 rule in 2D, X^a Y^b.  The shell
- * structure makes the mixed conditions dependent among themselves, so the eight solved for the
- * weights exclude X^8, whose residual then fixes r^2. */
-static const int MOM[9][2] = {{0, 0}, {2, 0}, {4, 0}, {2, 2}, {6, 0},
-                              {4, 2}, {6, 2}, {4, 4}, {8, 0}};
+/* The D4-invariant even moment conditions X^a Y^b of the rule (degree 9 for D2Q37, 7 for
+ * D2Q17).  The first NS are solved for the shell weights at a trial q = r^2; the residual of the
+ * last fixes q.  For D2Q37 the mixed conditions are dependent among themselves, so X^8 is kept
+ * for the residual. */
+#if ORC_Q == 17
+static const int MOM[NS + 1][2] = {{0, 0}, {2, 0}, {4, 0}, {2, 2}, {6, 0}, {4, 2}};
+#else
+static const int MOM[NS + 1][2] = {{0, 0}, {2, 0}, {4, 0}, {2, 2}, {6, 0},
+                                   {4, 2}, {6, 2}, {4, 4}, {8, 0}};
+#endif
 
 /* Shell sum of e_x^a e_y^b over the integer velocities of shell s. */
 static long double shell_sum(int s, int a, int b) {
@@ -108,20 +128,20 @@ static long double shell_sum(int s, int a, int b) {
     return acc;
 }
 
-/* For a trial q = r^2, solve the first eight conditions for the shell weights and return the
- * residual of the ninth. */
-static int weights_for(long double q, long double w[8], long double *resid) {
-    long double A[64], rhs[8];
-    for (int k = 0; k < 8; ++k) {
+/* For a trial q = r^2, solve the first NS conditions for the shell weights and return the
+ * residual of the last. */
+static int weights_for(long double q, long double w[NS], long double *resid) {
+    long double A[NS * NS], rhs[NS];
+    for (int k = 0; k < NS; ++k) {
         int a = MOM[k][0], b = MOM[k][1];
-        for (int s = 0; s < 8; ++s) A[k * 8 + s] = shell_sum(s, a, b) * ipow_ld(q, (a + b) / 2);
+        for (int s = 0; s < NS; ++s) A[k * NS + s] = shell_sum(s, a, b) * ipow_ld(q, (a + b) / 2);
         rhs[k] = gauss_moment(a) * gauss_moment(b);
     }
-    if (solve_ld(8, A, rhs)) return -1;
-    for (int s = 0; s < 8; ++s) w[s] = rhs[s];
-    int a = MOM[8][0], b = MOM[8][1];
+    if (solve_ld(NS, A, rhs)) return -1;
+    for (int s = 0; s < NS; ++s) w[s] = rhs[s];
+    int a = MOM[NS][0], b = MOM[NS][1];
     long double m = 0.0L;
-    for (int s = 0; s < 8; ++s) m += w[s] * shell_sum(s, a, b) * ipow_ld(q, (a + b) / 2);
+    for (int s = 0; s < NS; ++s) m += w[s] * shell_sum(s, a, b) * ipow_ld(q, (a + b) / 2);
     *resid = m - gauss_moment(a) * gauss_moment(b);
     return 0;
 }
@@ -134,23 +154,23 @@ static int build_lattice(void) {
             if (shell_of(ex, ey) >= 0) { LE[n][0] = ex; LE[n][1] = ey; ++n; }
     if (n != NQ) return -1;
     /* Scan q for sign changes of the ninth residual; keep the root with all weights positive. */
-    long double best_q = -1.0L, best_w[8];
-    long double qa = 0.5L, wa[8], ra;
+    long double best_q = -1.0L, best_w[NS];
+    long double qa = 0.5L, wa[NS], ra;
     if (weights_for(qa, wa, &ra)) return -1;
     for (int step = 1; step <= 5000; ++step) {
-        long double qb = 0.5L + step * 0.001L, wb[8], rb;
+        long double qb = 0.5L + step * 0.001L, wb[NS], rb;
         if (weights_for(qb, wb, &rb)) return -1;
         if ((ra < 0) != (rb < 0)) {
             long double lo = qa, hi = qb, rlo = ra;
             for (int it = 0; it < 200; ++it) {
-                long double mid = 0.5L * (lo + hi), wm[8], rm;
+                long double mid = 0.5L * (lo + hi), wm[NS], rm;
                 weights_for(mid, wm, &rm);
                 if ((rm < 0) == (rlo < 0)) { lo = mid; rlo = rm; } else hi = mid;
             }
-            long double wq[8], rq;
+            long double wq[NS], rq;
             weights_for(0.5L * (lo + hi), wq, &rq);
             int pos = 1;
-            for (int s = 0; s < 8; ++s) pos &= (wq[s] > 0.0L);
+            for (int s = 0; s < NS; ++s) pos &= (wq[s] > 0.0L);
             if (pos) { best_q = 0.5L * (lo + hi); memcpy(best_w, wq, sizeof wq); break; }
         }
         qa = qb; ra = rb;
@@ -163,12 +183,12 @@ static int build_lattice(void) {
 }
 
 /* ------------------------------------------------------------------------------------------ */
-/* Equilibrium, eq. feq-4 (fourth-order Hermite expansion, c_s = 1, theta = T - 1).  Reading:   */
-/* the factor printed as (c_i^2 - 4) in the theta (u.c)^2 term is (c_i^2 - 6), the value the    */
-/* fourth-order Hermite contraction gives in two dimensions; only with it are mass, momentum    */
-/* and energy moments exact.                                                                    */
+/* Equilibrium (c_s = 1, theta = T - 1): eq. feq-4 (fourth-order Hermite expansion) for D2Q37, */
+/* eq. feq-3 (third order) for D2Q17.  Reading for feq-4: the factor printed as (c_i^2 - 4) in */
+/* the theta (u.c)^2 term is (c_i^2 - 6), the value the fourth-order Hermite contraction gives  */
+/* in two dimensions; only with it are mass, momentum and energy moments exact.                 */
 /* ------------------------------------------------------------------------------------------ */
-static void feq37(double rho, double ux, double uy, double T, double out[NQ]) {
+static void feq_q(double rho, double ux, double uy, double T, double out[NQ]) {
     double th = T - 1.0;
     double b = ux * ux + uy * uy;
     for (int i = 0; i < NQ; ++i) {
@@ -178,16 +198,20 @@ static void feq37(double rho, double ux, double uy, double T, double out[NQ]) {
         double t1 = a;
         double t2 = 0.5 * (a * a - b + th * (s - 2.0));
         double t3 = (a / 6.0) * (a * a - 3.0 * b + 3.0 * th * (s - 4.0));
+#if ORC_Q == 17
+        out[i] = LW[i] * rho * (1.0 + t1 + t2 + t3);
+#else
         double t4 = (1.0 / 24.0) * (a * a * a * a - 6.0 * a * a * b + 3.0 * b * b
                                     + 6.0 * th * (a * a * (s - 6.0) + b * (4.0 - s))
                                     + 3.0 * th * th * (s * s - 8.0 * s + 8.0));
         out[i] = LW[i] * rho * (1.0 + t1 + t2 + t3 + t4);
+#endif
     }
 }
 
 /* Macroscopic moments, eq. macro with the ideal-gas relation e = (d/2) T, d = 2:
  * rho = sum f, rho u = sum f xi, d rho e = 2 rho T = sum f |xi - u|^2. */
-static void moments37(const double f[NQ], double U[4]) {
+static void moments_q(const double f[NQ], double U[4]) {
     double rho = 0.0, jx = 0.0, jy = 0.0;
     for (int i = 0; i < NQ; ++i) {
         rho += f[i];
@@ -240,13 +264,13 @@ int orc_lattice(int *e, double *w, double *r) {
 
 int orc_feq(double rho, double ux, double uy, double T, double *out) {
     if (build_lattice()) return fail("quadrature solve failed");
-    feq37(rho, ux, uy, T, out);
+    feq_q(rho, ux, uy, T, out);
     return 0;
 }
 
 int orc_moments_of(const double *f, double *U) {
     if (build_lattice()) return fail("quadrature solve failed");
-    moments37(f, U);
+    moments_q(f, U);
     return 0;
 }
 
@@ -354,11 +378,11 @@ int orc_init(orc_run *r, const double *rho, const double *ux, const double *uy, 
     /* Sec. 2 (algorithm outline): initialise to the equilibrium of the given fields; the
      * stored state is post-collision, and U^0 is the initial field. */
     for (size_t n = 0; n < nn; ++n) {
-        feq37(rho[n], ux[n], uy[n], T[n], r->f + n * NQ);
+        feq_q(rho[n], ux[n], uy[n], T[n], r->f + n * NQ);
         r->U[4 * n] = rho[n]; r->U[4 * n + 1] = ux[n]; r->U[4 * n + 2] = uy[n]; r->U[4 * n + 3] = T[n];
     }
     /* Mean equilibrium of eq. decomp-NJ from the run's mean state. */
-    feq37(r->rho0, r->ux0, r->uy0, r->T0, r->fbar);
+    feq_q(r->rho0, r->ux0, r->uy0, r->T0, r->fbar);
     r->step = 0;
     r->ready = 1;
     return 0;
@@ -373,8 +397,9 @@ int orc_init(orc_run *r, const double *rho, const double *ux, const double *uy, 
 /* k, L_k = lambda_k (S dV/dn)_k, takes the upwind difference over the cell interval that the    */
 /* characteristic crosses in one step, nu_k = lambda_k / r cells (linear interpolation at the    */
 /* foot point x_b - nu_k n); for nu_k <= 1 this is the first-order explicit upwind update, and    */
-/* it stays stable at the D2Q37 sound speed sqrt(2)/r > 1 cell/step.  S is frozen at x_b.  The    */
-/* foot point is limited to two cells (the U^n strips are five layers deep).                      */
+/* it stays stable at sound speeds sqrt(2)/r above 1 cell/step (1.18 for D2Q37; 0.86 for D2Q17). */
+/* S is frozen at x_b.  The foot point is limited to two cells (the U^n strips are five layers   */
+/* deep).                                                                                        */
 /* ------------------------------------------------------------------------------------------ */
 static void lodi_increment(const orc_run *r, int side, int x, int y, double dU[4]) {
     int nx = side == SIDE_XMIN ? -1 : side == SIDE_XMAX ? 1 : 0;
@@ -458,7 +483,7 @@ static void pml_source(const orc_run *r, int x, int y, double dU[4]) {
     const size_t n = (size_t)y * r->Nx + x;
     const double *u = r->U + 4 * n;
     double fe[NQ];
-    feq37(u[0], u[1], u[2], u[3], fe);
+    feq_q(u[0], u[1], u[2], u[3], fe);
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = 0; i < NQ; ++i) {
         double xi_x = LR * LE[i][0], xi_y = LR * LE[i][1];
@@ -543,9 +568,9 @@ static void one_step(orc_run *r) {
                 for (int k = 0; k < 4; ++k) Ut[k] += d[k];
             }
             double Uf[4], ft[NQ], ff[NQ];
-            moments37(gf, Uf);
-            feq37(Ut[0], Ut[1], Ut[2], Ut[3], ft);
-            feq37(Uf[0], Uf[1], Uf[2], Uf[3], ff);
+            moments_q(gf, Uf);
+            feq_q(Ut[0], Ut[1], Ut[2], Ut[3], ft);
+            feq_q(Uf[0], Uf[1], Uf[2], Uf[3], ff);
             for (int i = 0; i < NQ; ++i) gb[i] = ft[i] + (gf[i] - ff[i]);
         }
 
@@ -554,7 +579,7 @@ static void one_step(orc_run *r) {
     for (int y = 0; y < Ny; ++y)
         for (int x = 0; x < Nx; ++x) {
             size_t n = (size_t)y * Nx + x;
-            moments37(r->g + n * NQ, r->Un + 4 * n);
+            moments_q(r->g + n * NQ, r->Un + 4 * n);
         }
 
     /* 4. Q^{n+1} = Q^n + (1/2)(fhat^n + fhat^{n+1}), fhat = feq - fbar (eq. PMLQ, trapezoid). */
@@ -566,8 +591,8 @@ static void one_step(orc_run *r) {
                 size_t n = (size_t)y * Nx + x;
                 double e0[NQ], e1[NQ];
                 const double *u0 = r->U + 4 * n, *u1 = r->Un + 4 * n;
-                feq37(u0[0], u0[1], u0[2], u0[3], e0);
-                feq37(u1[0], u1[1], u1[2], u1[3], e1);
+                feq_q(u0[0], u0[1], u0[2], u0[3], e0);
+                feq_q(u1[0], u1[1], u1[2], u1[3], e1);
                 double *q = r->Qa + n * NQ;
                 for (int i = 0; i < NQ; ++i)
                     q[i] = q[i] + 0.5 * ((e0[i] - r->fbar[i]) + (e1[i] - r->fbar[i]));
@@ -585,7 +610,7 @@ static void one_step(orc_run *r) {
             const double *gn = r->g + n * NQ;
             const double *u = r->Un + 4 * n;
             double fe[NQ];
-            feq37(u[0], u[1], u[2], u[3], fe);
+            feq_q(u[0], u[1], u[2], u[3], fe);
             double *fo = r->f + n * NQ;
             double sg = sigma_at(r, x, y);
             for (int i = 0; i < NQ; ++i) fo[i] = gn[i] - inv_tau * (gn[i] - fe[i]);
@@ -636,7 +661,7 @@ int orc_moments(const orc_run *r, double *rho, double *ux, double *uy, double *T
     size_t nn = (size_t)r->Nx * r->Ny;
     for (size_t n = 0; n < nn; ++n) {
         double U[4];
-        if (r->step == 0) moments37(r->f + n * NQ, U);
+        if (r->step == 0) moments_q(r->f + n * NQ, U);
         else memcpy(U, r->U + 4 * n, sizeof U);
         if (rho) rho[n] = U[0];
         if (ux) ux[n] = U[1];

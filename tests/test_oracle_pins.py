@@ -25,61 +25,84 @@ def _normal_moment(a, mu, var):
                for k in range(a // 2 + 1))
 
 
-def test_weights_match_published_table(oracle_mod):
+LATTICES = pytest.mark.parametrize("q", [37, 17])
+
+
+@LATTICES
+def test_weights_match_published_table(oracle_mod, q):
     """The oracle solves the quadrature conditions itself; the result must equal the published
-    D2Q37 weights and scale (golden fixture, Sec. 2 velocity stencils)."""
-    e, w, r = oracle_mod.lattice()
-    lines = [l.split() for l in open(os.path.join(GOLDEN, "d2q37_weights.txt"))
-             if l.strip() and not l.startswith("#")]
+    D2Q37 weights and the closed-form D2Q17 weights (golden fixtures, Sec. 2 velocity
+    stencils)."""
+    e, w, r = oracle_mod.lattice(q)
+    path = os.path.join(GOLDEN, "d2q%d_weights.txt" % q)
+    lines = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
     table = {int(a): float(b) for a, b in lines}
-    r_pub = float([l for l in open(os.path.join(GOLDEN, "d2q37_weights.txt"))
-                   if l.startswith("# r ")][0].split()[2])
+    r_pub = float([l for l in open(path) if l.startswith("# r ")][0].split()[2])
     assert abs(r - r_pub) < 1e-15
-    assert len(e) == 37 and len({(a, b) for a, b in e}) == 37
+    assert len(e) == q and len({(a, b) for a, b in e}) == q
+    assert {int(a * a + b * b) for a, b in e} == set(table)
     for (ex, ey), wi in zip(e, w):
         assert abs(wi - table[ex * ex + ey * ey]) <= 1e-16 + 1e-14 * wi
     assert abs(w.sum() - 1.0) < 1e-15
 
 
-def test_quadrature_is_exact_to_degree_nine(oracle_mod):
-    """Every monomial X^a Y^b with a + b <= 9 (odd and mixed ones included, beyond the nine
-    conditions the solve used) integrates exactly against the standard normal."""
-    e, w, r = oracle_mod.lattice()
+@pytest.mark.parametrize("q,degree", [(37, 9), (17, 7)])
+def test_quadrature_is_exact_to_its_degree(oracle_mod, q, degree):
+    """Every monomial X^a Y^b with a + b <= 9 for D2Q37 (7 for D2Q17), odd and mixed ones
+    included beyond the conditions the solve used, integrates exactly against the standard
+    normal; the next even degree does not (the rules are ninth and seventh order)."""
+    e, w, r = oracle_mod.lattice(q)
     xi = r * e.astype(float)
-    for a in range(10):
-        for b in range(10 - a):
+    for a in range(degree + 1):
+        for b in range(degree + 1 - a):
             got = np.sum(w * xi[:, 0] ** a * xi[:, 1] ** b)
             want = _gauss_moment(a) * _gauss_moment(b)
             assert abs(got - want) < 2e-12 * max(1.0, abs(want)), (a, b, got, want)
-    # and degree 10 is NOT exact (the rule is ninth order)
-    got = np.sum(w * xi[:, 0] ** 10)
-    assert abs(got - _gauss_moment(10)) > 1.0
+    got = np.sum(w * xi[:, 0] ** (degree + 1))
+    assert abs(got - _gauss_moment(degree + 1)) > 1.0
 
 
 @pytest.mark.parametrize("state", [(1.0, 0.0, 0.0, 1.0), (1.03, 0.11, -0.07, 0.95),
                                    (0.9, -0.2, 0.15, 1.1), (1.2, 0.05, 0.3, 0.8)])
-def test_equilibrium_moments_are_maxwellian(oracle_mod, state):
-    """eq. feq-4 (with the (c^2 - 6) reading) reproduces every raw moment up to fourth order of
-    the Maxwellian rho N(u, T I) exactly; a dropped term or the printed (c^2 - 4) fails here."""
+@pytest.mark.parametrize("q,order", [(37, 4), (17, 3)])
+def test_equilibrium_moments_are_maxwellian(oracle_mod, state, q, order):
+    """eq. feq-4 (with the (c^2 - 6) reading) on D2Q37 reproduces every raw moment up to fourth
+    order of the Maxwellian rho N(u, T I) exactly, eq. feq-3 on D2Q17 every one up to third
+    order; a dropped term, a wrong shell factor or the printed (c^2 - 4) in feq-4 fails here."""
     rho, ux, uy, T = state
-    e, w, r = oracle_mod.lattice()
+    e, w, r = oracle_mod.lattice(q)
     xi = r * e.astype(float)
-    f = oracle_mod.feq(rho, ux, uy, T)
-    for a in range(5):
-        for b in range(5 - a):
+    f = oracle_mod.feq(rho, ux, uy, T, q=q)
+    for a in range(order + 1):
+        for b in range(order + 1 - a):
             got = np.sum(f * xi[:, 0] ** a * xi[:, 1] ** b)
             want = rho * _normal_moment(a, ux, T) * _normal_moment(b, uy, T)
             assert abs(got - want) < 1e-13 * max(1.0, abs(want)), (a, b)
 
 
-def test_rest_equilibrium_is_weights(oracle_mod):
-    e, w, r = oracle_mod.lattice()
-    assert np.array_equal(oracle_mod.feq(1.0, 0.0, 0.0, 1.0), w)
+def test_d2q17_equilibrium_is_third_order_only(oracle_mod):
+    """feq-3 stops at third order: away from rest the fourth moments of the Maxwellian are
+    missed by the O(u^4, theta u^2, theta^2) terms that feq-4 would carry."""
+    rho, ux, uy, T = 1.0, 0.2, 0.0, 1.1
+    e, w, r = oracle_mod.lattice(17)
+    xi = r * e.astype(float)
+    f = oracle_mod.feq(rho, ux, uy, T, q=17)
+    got = np.sum(f * xi[:, 0] ** 4)
+    want = rho * _normal_moment(4, ux, T)
+    miss = ux ** 4 + 6 * (T - 1) * ux ** 2 + 3 * (T - 1) ** 2   # fourth Hermite coefficient
+    assert abs((want - got) - miss) < 1e-12
 
 
-def test_moments_invert_equilibrium(oracle_mod):
+@LATTICES
+def test_rest_equilibrium_is_weights(oracle_mod, q):
+    e, w, r = oracle_mod.lattice(q)
+    assert np.array_equal(oracle_mod.feq(1.0, 0.0, 0.0, 1.0, q=q), w)
+
+
+@LATTICES
+def test_moments_invert_equilibrium(oracle_mod, q):
     for state in [(1.03, 0.11, -0.07, 0.95), (0.97, -0.02, 0.04, 1.02)]:
-        U = oracle_mod.moments_of(oracle_mod.feq(*state))
+        U = oracle_mod.moments_of(oracle_mod.feq(*state, q=q), q=q)
         assert np.allclose(U, state, rtol=0, atol=1e-14)
 
 
@@ -89,11 +112,12 @@ def _conserved(o, xi):
                      (f * (xi ** 2).sum(1)).sum()])
 
 
-def test_conservation_on_periodic_box(oracle_mod):
+@LATTICES
+def test_conservation_on_periodic_box(oracle_mod, q):
     """BGK with the fixed equilibrium conserves mass, momentum and energy to rounding."""
-    e, w, r = oracle_mod.lattice()
+    e, w, r = oracle_mod.lattice(q)
     xi = r * e.astype(float)
-    o = oracle_mod.OracleRun(23, 19, 0.8)
+    o = oracle_mod.OracleRun(23, 19, 0.8, lattice=q)
     F = wl.noisy_state(23, 19, seed=7, ux0=0.05, amp=2e-3)
     o.init(*F.as_tuple())
     c0 = _conserved(o, xi)
@@ -104,11 +128,12 @@ def test_conservation_on_periodic_box(oracle_mod):
 
 @pytest.mark.parametrize("bc", [oracle_mod_bc for oracle_mod_bc in (1, 2)])
 @pytest.mark.parametrize("W,sig", [(0, 0.0), (4, 0.1)])
-def test_uniform_flow_is_stationary(oracle_mod, bc, W, sig):
+@LATTICES
+def test_uniform_flow_is_stationary(oracle_mod, bc, W, sig, q):
     """A uniform state equal to the mean state stays put under ZG, the characteristic boundary
     and the PML: fhat = 0 gives Q = 0 and no PML force, the LODI derivatives vanish, ZG copies
     equal values."""
-    o = oracle_mod.OracleRun(12, 10, 0.8, 1.0, 0.1, -0.05, 1.0)
+    o = oracle_mod.OracleRun(12, 10, 0.8, 1.0, 0.1, -0.05, 1.0, lattice=q)
     if W:
         o.set_pml(15, W, sig)
     o.set_bc(15, bc)
@@ -120,14 +145,15 @@ def test_uniform_flow_is_stationary(oracle_mod, bc, W, sig):
 
 
 @pytest.mark.parametrize("bc", [1, 2])
-def test_sigma_zero_pml_equals_no_pml(oracle_mod, bc):
+@LATTICES
+def test_sigma_zero_pml_equals_no_pml(oracle_mod, bc, q):
     """sigma_max = 0 on a W-wide layer reproduces the plain scheme on the same grid bit for
     bit (the PML term is added last, eq. PMLCOLL)."""
     W, L = 5, 14
-    a = oracle_mod.OracleRun(L, L, 0.8, 1.0, 0.05, 0.0, 1.0)
+    a = oracle_mod.OracleRun(L, L, 0.8, 1.0, 0.05, 0.0, 1.0, lattice=q)
     a.set_pml(15, W, 0.0)
     a.set_bc(15, bc)
-    b = oracle_mod.OracleRun(L + 2 * W, L + 2 * W, 0.8, 1.0, 0.05, 0.0, 1.0)
+    b = oracle_mod.OracleRun(L + 2 * W, L + 2 * W, 0.8, 1.0, 0.05, 0.0, 1.0, lattice=q)
     b.set_bc(15, bc)
     assert a.grid() == b.grid()
     F = wl.noisy_state(*a.grid(), seed=3, ux0=0.05)
@@ -138,11 +164,12 @@ def test_sigma_zero_pml_equals_no_pml(oracle_mod, bc):
     assert np.array_equal(a.populations(), b.populations())
 
 
-def test_q_grows_linearly_under_constant_deviation(oracle_mod):
+@LATTICES
+def test_q_grows_linearly_under_constant_deviation(oracle_mod, q):
     """With sigma = 0 and a uniform state off the mean state, fhat is constant in time, so the
     trapezoid rule integrates eq. PMLQ exactly: Q^n = n fhat on the Q region, 0 elsewhere."""
     W = 4
-    o = oracle_mod.OracleRun(10, 10, 0.8, 1.0, 0.0, 0.0, 1.0)
+    o = oracle_mod.OracleRun(10, 10, 0.8, 1.0, 0.0, 0.0, 1.0, lattice=q)
     o.set_pml(15, W, 0.0)
     o.set_bc(15, 1)
     Nx, Ny = o.grid()
@@ -150,7 +177,7 @@ def test_q_grows_linearly_under_constant_deviation(oracle_mod):
     o.init(*wl.uniform_state(Nx, Ny, *state).as_tuple())
     n = 17
     o.step(n)
-    fhat = oracle_mod.feq(*state) - oracle_mod.feq(1.0, 0.0, 0.0, 1.0)
+    fhat = oracle_mod.feq(*state, q=q) - oracle_mod.feq(1.0, 0.0, 0.0, 1.0, q=q)
     Q = o.pml_q()
     d = W + 1
     region = np.zeros((Ny, Nx), bool)
@@ -175,11 +202,12 @@ def test_sigma_ramp(oracle_mod):
 
 
 @pytest.mark.parametrize("bc,W", [(1, 6), (2, 6), (2, 0)])
-def test_mirror_symmetry(oracle_mod, bc, W):
+@LATTICES
+def test_mirror_symmetry(oracle_mod, bc, W, q):
     """A centred pulse at rest on a square grid stays symmetric under x and y mirrors and the
     transpose: catches a wrong side, sign or index in the boundary, PML or corner handling."""
     L = 20
-    o = oracle_mod.OracleRun(L, L, 0.8)
+    o = oracle_mod.OracleRun(L, L, 0.8, lattice=q)
     if W:
         o.set_pml(15, W, 0.1)
     o.set_bc(15, bc)
@@ -215,34 +243,39 @@ def _linear_nsf(drho0, dT0, k, t, r, tau):
     return out_r
 
 
-def test_linear_acoustics_matches_nsf_theory(oracle_mod):
+@LATTICES
+def test_linear_acoustics_matches_nsf_theory(oracle_mod, q):
     """A small plane density pulse on a periodic line follows linearised NSF theory: the sound
     speed is sqrt(2)/r cells/step and all modes decay at nu k^2.  Pins weights, scale r, tau,
-    the equilibrium and the streaming direction together."""
-    e, w, r = oracle_mod.lattice()
-    N, A, b, tau, t = 256, 1e-4, 4.0, 0.8, 40
-    o = oracle_mod.OracleRun(N, 1, tau)
-    F = wl.uniform_state(N, 1)
-    x = np.arange(N, dtype=float)
-    F.rho = (1.0 + A * np.power(2.0, -((x - 128.0) ** 2) / b ** 2))[None, :]
-    o.init(*F.as_tuple())
-    o.step(t)
-    rho = o.moments()[0][0]
-    k = 2 * np.pi * np.fft.fftfreq(N)
-    pred = np.real(np.fft.ifft(_linear_nsf(np.fft.fft(F.rho[0] - 1.0), np.zeros(N), k, t, r, tau)))
-    err = np.abs((rho - 1.0) - pred).max() / A
-    assert err < 5e-3, err
-    # the acoustic peak travelled sqrt(2)/r * t cells
-    right = np.argmax(rho[140:]) + 140
-    assert abs((right - 128.0) - math.sqrt(2.0) / r * t) < 1.0
+    the equilibrium and the streaming direction together.  The residual is of Burnett order, so
+    it falls like k^2 when the pulse is made twice as wide."""
+    e, w, r = oracle_mod.lattice(q)
+    N, A, tau, t = 256, 1e-4, 0.8, 40
+    errs = {}
+    for b in (4.0, 8.0):
+        o = oracle_mod.OracleRun(N, 1, tau, lattice=q)
+        F = wl.uniform_state(N, 1)
+        x = np.arange(N, dtype=float)
+        F.rho = (1.0 + A * np.power(2.0, -((x - 128.0) ** 2) / b ** 2))[None, :]
+        o.init(*F.as_tuple())
+        o.step(t)
+        rho = o.moments()[0][0]
+        k = 2 * np.pi * np.fft.fftfreq(N)
+        pred = np.real(np.fft.ifft(_linear_nsf(np.fft.fft(F.rho[0] - 1.0), np.zeros(N), k, t, r, tau)))
+        errs[b] = np.abs((rho - 1.0) - pred).max() / A
+        # the acoustic peak travelled sqrt(2)/r * t cells
+        right = np.argmax(rho[140:]) + 140
+        assert abs((right - 128.0) - math.sqrt(2.0) / r * t) < 1.0
+    assert errs[4.0] < 6e-3 and errs[8.0] < 1.5e-3, errs
+    assert errs[4.0] > 2.5 * errs[8.0], errs
 
 
-def _reference_bulk(oracle_mod, L, W, steps, make):
+def _reference_bulk(oracle_mod, L, W, steps, make, q=37):
     """Periodic reference on an extended grid (Sec. 5 "Reference Simulation"), cut to the
     bulk of the open-boundary run."""
     pad = int(math.ceil(1.19 * steps)) + 8
     Nref = L + 2 * W + 2 * pad
-    ref = oracle_mod.OracleRun(Nref, Nref, 0.8)
+    ref = oracle_mod.OracleRun(Nref, Nref, 0.8, lattice=q)
     ref.init(*make(Nref, pad + W).as_tuple())
     ref.step(steps)
     m = ref.moments()
@@ -250,7 +283,8 @@ def _reference_bulk(oracle_mod, L, W, steps, make):
     return [z[s, s] for z in m]
 
 
-def test_pml_zg_reflects_far_less_than_zg(oracle_mod):
+@LATTICES
+def test_pml_zg_reflects_far_less_than_zg(oracle_mod, q):
     """Sec. 5.1: ZG behind a PML lowers the reflection error by about two orders of magnitude
     over plain ZG, and a too-strong sigma_max raises it again (interface mismatch).  Pulse at
     rest, bulk 32^2, W = 12, error after 25 steps against a periodic reference."""
@@ -262,14 +296,14 @@ def test_pml_zg_reflects_far_less_than_zg(oracle_mod):
         return wl.add_gaussian_pulse(F, c, c, 1e-3, 4.0)
 
     def err(W, sig):
-        o = oracle_mod.OracleRun(L, L, 0.8)
+        o = oracle_mod.OracleRun(L, L, 0.8, lattice=q)
         if W:
             o.set_pml(15, W, sig)
         o.set_bc(15, 1)
         N = L + 2 * W
         o.init(*make(N, W).as_tuple())
         o.step(steps)
-        rr = _reference_bulk(oracle_mod, L, W, steps, make)[0]
+        rr = _reference_bulk(oracle_mod, L, W, steps, make, q)[0]
         rho = o.moments()[0][W:W + L, W:W + L]
         return np.sqrt(np.sum((rho - rr) ** 2))
 
@@ -280,13 +314,14 @@ def test_pml_zg_reflects_far_less_than_zg(oracle_mod):
     assert e_strong > 5.0 * e_pml, (e_strong, e_pml)
 
 
-def test_characteristic_bc_reflects_less_than_zg(oracle_mod):
+@LATTICES
+def test_characteristic_bc_reflects_less_than_zg(oracle_mod, q):
     """Sec. 5.1: for one-dimensional dynamics the LODI boundary beats ZG without a PML.  A plane
     pulse leaves through the x edges of a periodic-in-y strip."""
     L, steps, N = 40, 45, 40
 
     def run(bc):
-        o = oracle_mod.OracleRun(L, 4, 0.8)
+        o = oracle_mod.OracleRun(L, 4, 0.8, lattice=q)
         o.set_bc(1 | 2, bc)
         F = wl.uniform_state(L, 4)
         x = np.arange(L, dtype=float)
@@ -297,7 +332,7 @@ def test_characteristic_bc_reflects_less_than_zg(oracle_mod):
 
     def ref():
         pad = 80
-        o = oracle_mod.OracleRun(L + 2 * pad, 4, 0.8)
+        o = oracle_mod.OracleRun(L + 2 * pad, 4, 0.8, lattice=q)
         x = np.arange(L + 2 * pad, dtype=float)
         F = wl.uniform_state(L + 2 * pad, 4)
         F.rho = np.broadcast_to(1.0 + 1e-3 * np.power(2.0, -((x - 19.5 - pad) ** 2) / 16.0),
@@ -332,15 +367,16 @@ def _conserved_densities(rho, ux, uy, T):
     return np.array([rho, rho * ux, rho * uy, rho * (0.5 * (ux * ux + uy * uy) + T)])
 
 
+@LATTICES
 @pytest.mark.parametrize("flags", [1, 2, 4, 6, 7])
-def test_pml_terms_keep_the_mean_state_stationary(oracle_mod, flags):
+def test_pml_terms_keep_the_mean_state_stationary(oracle_mod, flags, q):
     """Appendix: every PML moment term vanishes at the mean state (Q = 0, U = Ubar), so a run at
     its mean stays there (the appendix's sigma_max = 0.001, 50 steps).  None of the terms damps
     round-off at the boundary (each feeds the node's own deviation back into its target), so
     the span is short."""
     sigma, steps = 0.001, 50
     mean = (1.0, 0.05, -0.02, 1.0)
-    o = oracle_mod.OracleRun(24, 20, 0.8, *mean)
+    o = oracle_mod.OracleRun(24, 20, 0.8, *mean, lattice=q)
     o.set_bc(15, 2)
     o.set_pml(15, 6, sigma)
     o.set_nrbc_pml_terms(flags)
@@ -351,7 +387,8 @@ def test_pml_terms_keep_the_mean_state_stationary(oracle_mod, flags):
         assert np.abs(a - v).max() < 1e-12
 
 
-def test_pml_term_two_moves_conserved_state_by_its_source(oracle_mod):
+@LATTICES
+def test_pml_term_two_moves_conserved_state_by_its_source(oracle_mod, q):
     """Appendix, term II alone: over the first step of a uniform state (Q = 0, no gradients, so
     the LODI increment vanishes) the characteristic target of an outer-layer node changes its
     conserved densities by +2 sigma (U - Ubar) (the appendix's sign): the velocity moments of
@@ -359,7 +396,7 @@ def test_pml_term_two_moves_conserved_state_by_its_source(oracle_mod):
     mean = (1.0, 0.0, 0.0, 1.0)
     U0 = (1.0 + 2e-4, 3e-4, -1e-4, 1.0 - 2e-4)
     sigma, W = 0.2, 6
-    o = oracle_mod.OracleRun(24, 20, 0.8, *mean)
+    o = oracle_mod.OracleRun(24, 20, 0.8, *mean, lattice=q)
     o.set_bc(15, 2)
     o.set_pml(15, W, sigma)
     o.set_nrbc_pml_terms(2)
@@ -374,7 +411,7 @@ def test_pml_term_two_moves_conserved_state_by_its_source(oracle_mod):
     # interior nodes see no boundary source
     assert abs(m[0][y, Nx // 2] - U0[0]) < 1e-14
     # and without the flag the same node stays at U0
-    o2 = oracle_mod.OracleRun(24, 20, 0.8, *mean)
+    o2 = oracle_mod.OracleRun(24, 20, 0.8, *mean, lattice=q)
     o2.set_bc(15, 2)
     o2.set_pml(15, W, sigma)
     o2.init(*wl.uniform_state(Nx, Ny, *U0).as_tuple())
