@@ -1,6 +1,7 @@
 /*
- * lbm.h -- C ABI of the MI355X (gfx950) D2Q37 thermal lattice Boltzmann library with a
- * perfectly matched layer (PML) and open outer boundaries, after arXiv 2504.20169.
+ * lbm.h -- C ABI of the MI355X (gfx950) thermal lattice Boltzmann library (D2Q37 or D2Q17
+ * velocity stencil) with a perfectly matched layer (PML) and open outer boundaries, after
+ * arXiv 2504.20169.
  *
  * One time step follows Sec. 2 (algorithm outline) and Secs. 3-4:
  *   pull streaming  f_i(x, n+1) = f*_i(x - e_i, n)                      (eq. lbe)
@@ -10,16 +11,18 @@
  *   moments         rho, u, T (eq. macro, e = (d/2) T)
  *   PML auxiliary   Q^{n+1} = Q^n + (fhat^n + fhat^{n+1})/2 (eq. PMLQ, trapezoid rule)
  *   collision       f* = f - (f - feq)/tau - sigma (e.grad Q + 2 fhat + sigma Q)
- *                   (BGK with eq. feq-4 and eq. PMLCOLL; sigma ramp eq. PML_ramp)
+ *                   (BGK with eq. feq-4 on D2Q37 or eq. feq-3 on D2Q17, and eq. PMLCOLL;
+ *                   sigma ramp eq. PML_ramp)
  *
- * Units: rho, u, T in thermal units (sound-speed unit c_s = 1, xi_i = r e_i with the D2Q37
- * scale r = 1.19698...); lengths and times in lattice units (one cell, one step).
+ * Units: rho, u, T in thermal units (sound-speed unit c_s = 1, xi_i = r e_i with the stencil's
+ * scale, r = 1.19698... for D2Q37 and 1.64343... for D2Q17); lengths and times in lattice
+ * units (one cell, one step).
  *
  * Grid: the bulk is nx x ny; every side carrying a PML of width W adds W layers, so the full
  * grid is Nx = nx + W*(#PML x-sides), Ny likewise.  The outermost 3 layers of an open side are
  * its boundary nodes (and, with a PML, also its PML levels W, W-1, W-2).  Host field arrays are
- * row-major [Ny][Nx] float64; population arrays are [37][Ny][Nx] float64 in the order returned
- * by lbm_velocities().
+ * row-major [Ny][Nx] float64; population arrays are [q][Ny][Nx] float64 (q = 37 or 17) in the
+ * order returned by lbm_velocities().
  *
  * Conventions: every call returns an lbm_status; no exception or abort crosses the ABI.
  * lbm_last_error() returns a thread-local message for the last failure.  Configuration order:
@@ -85,12 +88,14 @@ typedef struct {
     void *stream;                /* hipStream_t to enqueue on; NULL = a stream the run owns (only
                                     then can lbm_launch.overlap put the boundary/PML kernels on a
                                     side stream beside the bulk kernel) */
-    int32_t layout;              /* population layout in HBM: 0 = the 37 population rows of each
+    int32_t layout;              /* population layout in HBM: 0 = the q population rows of each
                                     grid row adjacent (default), 1 = one plane per velocity */
     int32_t row_pad;             /* layout 0: extra elements after each population row (rows
                                     are first rounded up to 64 elements); 0 = automatic (64 for
                                     FP64 and FP32 storage, none for FP16: the fastest measured on
                                     large grids), -1 = none, 1..4096 = that many elements */
+    int32_t lattice;             /* velocity stencil (Sec. 2, "Velocity stencils"): 0 or 37 =
+                                    D2Q37 with eq. feq-4 (default), 17 = D2Q17 with eq. feq-3 */
 } lbm_desc;
 
 /* Launch configuration (set by lbm_set_launch or lbm_autotune).  bulk_tx in {64,128,256}
@@ -106,7 +111,7 @@ typedef struct {
 } lbm_launch;
 
 /* Create a run (Sec. 2).  Validates the descriptor (LBM_ERR_ARG: tau <= 0.5, size < 1,
- * non-finite mean state, rho0 <= 0, T0 <= 0, unknown storage).  No device memory is touched
+ * non-finite mean state, rho0 <= 0, T0 <= 0, unknown storage, layout or lattice).  No device memory is touched
  * until lbm_init_fields.  *out receives the handle (caller owns it until lbm_destroy). */
 lbm_status lbm_create(const lbm_desc *desc, lbm_handle *out);
 
@@ -163,18 +168,19 @@ lbm_status lbm_step_count(lbm_handle h, int64_t *steps);
 lbm_status lbm_moments(lbm_handle h, double *rho, double *ux, double *uy, double *T,
                        unsigned flags);
 
-/* Post-collision populations f*(x, n) as float64 [37][Ny][Nx] host array (fbar + stored
+/* Post-collision populations f*(x, n) as float64 [q][Ny][Nx] host array (fbar + stored
  * deviation), in lbm_velocities() order.  Synchronises. */
 lbm_status lbm_populations(lbm_handle h, double *f);
 
-/* PML auxiliary field Q (eq. PMLQ) as float64 [37][Ny][Nx] host array, zero outside the Q
+/* PML auxiliary field Q (eq. PMLQ) as float64 [q][Ny][Nx] host array, zero outside the Q
  * region.  Synchronises. */
 lbm_status lbm_pml_q(lbm_handle h, double *Q);
 
-/* The library's D2Q37 velocity order: e[2*i], e[2*i+1] integer lattice vector of
- * population i; w[i] its weight; *r the thermal scale (xi = r e).  Host only; any pointer
- * may be NULL. */
-lbm_status lbm_velocities(int32_t *e, double *w, double *r);
+/* The library's velocity order of a stencil (lattice 37 or 0: D2Q37, 17: D2Q17; Sec. 2,
+ * "Velocity stencils"): e[2*i], e[2*i+1] integer lattice vector of population i (e holds 2q
+ * entries); w[i] its weight; *r the thermal scale (xi = r e).  Host only; any pointer may be
+ * NULL.  LBM_ERR_ARG for another lattice. */
+lbm_status lbm_velocities(int32_t lattice, int32_t *e, double *w, double *r);
 
 /* Global relative L2 errors of Sec. 5 (Reference Simulation) over the bulk,
  * e_Z = sqrt(sum ((Z - Zref)/Zref)^2) for Z = rho, ux, T, accumulated in float64 in a fixed
@@ -196,7 +202,7 @@ lbm_status lbm_get_launch(lbm_handle h, lbm_launch *cfg);
 /* Time every supported bulk tile shape, in order and (for a run that owns its stream)
  * overlapped, on a scratch copy of this run's geometry (the run's own state is untouched) and
  * keep the fastest; if cache_path is non-NULL the choice is read from / appended to that text
- * file, one line "Nx Ny storage bulk_tx overlap" per choice.  *chosen may be NULL. */
+ * file, one line "Nx Ny storage lattice bulk_tx overlap" per choice.  *chosen may be NULL. */
 lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path,
                         lbm_launch *chosen);
 

@@ -104,7 +104,9 @@ struct lbm_run {
     RunDev **dptr = nullptr;
     int *dprefix = nullptr;   // [NCLS][2] prefix arrays of the single-run launch set
     int nblocks[NCLS] = {0, 0, 0, 0};
-    double fbar[NQ];
+    const LatticeInfo *lat = &LATTICE_D2Q37;   // velocity stencil
+    const KernelSet *ks = &k37::kernels;       // its kernels
+    double fbar[NQ_MAX];
     double *fbar_d = nullptr;
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;     // stream in use (the group's while in a group)
@@ -134,6 +136,7 @@ struct lbm_group {
     std::vector<lbm_run *> members;
     bool dirty = true;
     int storage = -1;
+    const KernelSet *ks = nullptr;    // stencil of the members (set by the first member)
     lbm_launch launch{64, 4, 32, 0};
     hipGraphExec_t graph = nullptr;   // graph_G batched steps of the current membership
     int graph_G = 0;
@@ -203,14 +206,15 @@ lbm_status setup_geometry(lbm_run *h, RunDev &R) {
     // FP16 measured best without it.
     const int pad = d.row_pad > 0 ? d.row_pad : d.row_pad < 0 ? 0 : (d.storage == ST_F16 ? 0 : 64);
     const long long row = round_up(R.Nx, 64) + (d.layout == 0 ? pad : 0);
-    if (d.layout == 0) {            // rows: the 37 population rows of a grid row adjacent
+    const int nq = h->lat->q;
+    if (d.layout == 0) {            // rows: the q population rows of a grid row adjacent
         R.plane = row;
-        R.pitch = (int)(NQ * row);
-        R.fsize = (long long)NQ * row * R.Ny;
+        R.pitch = (int)(nq * row);
+        R.fsize = (long long)nq * row * R.Ny;
     } else {                        // planes: one padded plane per velocity
         R.pitch = (int)row;
         R.plane = round_up(row * R.Ny, 64);
-        R.fsize = (long long)NQ * R.plane;
+        R.fsize = (long long)nq * R.plane;
     }
     R.qplane = round_up(std::max(R.frame_n, 1), 64);
     R.rplane = round_up(std::max(R.ring_n, 1), 64);
@@ -232,45 +236,49 @@ lbm_status setup_geometry(lbm_run *h, RunDev &R) {
     return LBM_OK;
 }
 
-// Mean-state Hermite coefficients of the equilibrium (see lbm_kernels.hip).
+// Mean-state Hermite coefficients of the equilibrium (see lbm_kernels.hip): fourth order
+// (eq. feq-4) for D2Q37, third order (eq. feq-3) for D2Q17.
 void fill_constants(lbm_run *h, RunDev &R) {
     const lbm_desc &d = h->desc;
+    const LatticeInfo &lt = *h->lat;
+    const bool o4 = lt.order == 4;
     R.storage = d.storage;
     R.omega = 1.0 / d.tau;
     R.rho0 = d.rho0; R.u0x = d.ux0; R.u0y = d.uy0; R.T0 = d.T0;
     R.th0 = d.T0 - 1.0;
     R.b0 = d.ux0 * d.ux0 + d.uy0 * d.uy0;
-    R.r0x = LAT_R * d.ux0; R.r0y = LAT_R * d.uy0;
+    R.r0x = lt.r * d.ux0; R.r0y = lt.r * d.uy0;
     R.sigma_max = h->sigma_max;
     R.inv_W2 = h->W > 0 ? 1.0 / ((double)h->W * h->W) : 0.0;
     const double th0 = R.th0, b0 = R.b0;
-    const double k0 = 1.0 - 0.5 * b0 - th0 + 0.125 * b0 * b0 + th0 * b0 + th0 * th0;
+    const double k0 = o4 ? 1.0 - 0.5 * b0 - th0 + 0.125 * b0 * b0 + th0 * b0 + th0 * th0
+                         : 1.0 - 0.5 * b0 - th0;
     const double k1 = 1.0 - 0.5 * b0 - 2.0 * th0;
-    const double k2a = 0.5 - 0.25 * b0 - 1.5 * th0;
-    const double k2s = 0.5 * th0 - 0.25 * th0 * b0 - th0 * th0;
-    double E0[NSHELL];
-    for (int s = 0; s < NSHELL; ++s) {
-        double sv = LAT_R2 * SHELL_E2[s];
-        E0[s] = k0 + k2s * sv + 0.125 * th0 * th0 * sv * sv;
-        R.E2_0[s] = k2a + 0.25 * th0 * sv;
+    const double k2a = o4 ? 0.5 - 0.25 * b0 - 1.5 * th0 : 0.5;
+    const double k2s = o4 ? 0.5 * th0 - 0.25 * th0 * b0 - th0 * th0 : 0.5 * th0;
+    double E0[NSHELL_MAX];
+    for (int s = 0; s < lt.nshell; ++s) {
+        double sv = lt.r * lt.r * lt.shell_e2[s];
+        E0[s] = k0 + k2s * sv + (o4 ? 0.125 * th0 * th0 * sv * sv : 0.0);
+        R.E2_0[s] = k2a + (o4 ? 0.25 * th0 * sv : 0.0);
         R.O1_0[s] = k1 + 0.5 * th0 * sv;
     }
     R.H0rest = k0;
-    h->fbar[0] = SHELL_W[0] * d.rho0 * k0;
-    for (int p = 0; p < NPAIR; ++p) {
-        int sh = PSH[p];
-        double a0 = PEX[p] * R.r0x + PEY[p] * R.r0y;
-        R.H0e[p] = E0[sh] + R.E2_0[sh] * a0 * a0 + a0 * a0 * a0 * a0 / 24.0;
+    h->fbar[0] = lt.shell_w[0] * d.rho0 * k0;
+    for (int p = 0; p < lt.npair; ++p) {
+        int sh = lt.psh[p];
+        double a0 = lt.pex[p] * R.r0x + lt.pey[p] * R.r0y;
+        R.H0e[p] = E0[sh] + R.E2_0[sh] * a0 * a0 + (o4 ? a0 * a0 * a0 * a0 / 24.0 : 0.0);
         R.H0o[p] = a0 * (R.O1_0[sh] + a0 * a0 / 6.0);
-        h->fbar[1 + 2 * p] = SHELL_W[sh] * d.rho0 * (R.H0e[p] + R.H0o[p]);
-        h->fbar[2 + 2 * p] = SHELL_W[sh] * d.rho0 * (R.H0e[p] - R.H0o[p]);
+        h->fbar[1 + 2 * p] = lt.shell_w[sh] * d.rho0 * (R.H0e[p] + R.H0o[p]);
+        h->fbar[2 + 2 * p] = lt.shell_w[sh] * d.rho0 * (R.H0e[p] - R.H0o[p]);
     }
     R.omega_f = (float)R.omega; R.rho0_f = (float)R.rho0; R.u0x_f = (float)R.u0x;
     R.u0y_f = (float)R.u0y; R.th0_f = (float)R.th0; R.b0_f = (float)R.b0;
     R.r0x_f = (float)R.r0x; R.r0y_f = (float)R.r0y; R.T0_f = (float)R.T0;
     R.H0rest_f = (float)R.H0rest;
-    for (int p = 0; p < NPAIR; ++p) { R.H0e_f[p] = (float)R.H0e[p]; R.H0o_f[p] = (float)R.H0o[p]; }
-    for (int s = 0; s < NSHELL; ++s) { R.E2_0_f[s] = (float)R.E2_0[s]; R.O1_0_f[s] = (float)R.O1_0[s]; }
+    for (int p = 0; p < lt.npair; ++p) { R.H0e_f[p] = (float)R.H0e[p]; R.H0o_f[p] = (float)R.H0o[p]; }
+    for (int s = 0; s < lt.nshell; ++s) { R.E2_0_f[s] = (float)R.E2_0[s]; R.O1_0_f[s] = (float)R.O1_0[s]; }
     R.scale = 1.0; R.inv_scale = 1.0;
 }
 
@@ -279,13 +287,13 @@ void set_scale(RunDev &R, double s) {
     R.scale_f = (float)s; R.inv_scale_f = (float)(1.0 / s);
 }
 
-size_t footprint_of(const RunDev &R, int storage) {
+size_t footprint_of(const RunDev &R, int storage, int nq) {
     size_t b = 2 * (size_t)R.fsize * elem_size(storage);
-    if (R.has_q) b += (size_t)NQ * R.qplane * compute_size(storage);
+    if (R.has_q) b += (size_t)nq * R.qplane * compute_size(storage);
     b += 2 * 4 * (size_t)R.qplane * sizeof(double);
-    if (R.ring_n > 0) b += (size_t)NQ * R.rplane * compute_size(storage);
+    if (R.ring_n > 0) b += (size_t)nq * R.rplane * compute_size(storage);
     if (R.tgt_pre && R.ring_n > 0) b += 4 * (size_t)R.rplane * sizeof(double);
-    b += sizeof(RunDev) + 256 * 3 + NQ * sizeof(double);
+    b += sizeof(RunDev) + 256 * 3 + nq * sizeof(double);
     return b;
 }
 
@@ -310,6 +318,7 @@ lbm_status upload_prefix(lbm_run *h) {
 
 LaunchSet single_set(lbm_run *h) {
     LaunchSet L;
+    L.ks = h->ks;
     L.runs = h->dptr;
     for (int c = 0; c < NCLS; ++c) {
         L.prefix[c] = h->dprefix + 2 * c;
@@ -369,28 +378,28 @@ lbm_status enqueue_step(const LaunchSet &L, int storage, int tx, hipStream_t s, 
     const bool classes = mode == 1;
     if (!ss || !ss->ok || classes) {
         if (classes && has_a) HIP_TRY(hipEventRecord(ev[4], s));
-        HIP_TRY(launch_target(L, storage, s));
-        HIP_TRY(launch_phase_a(L, storage, s));
+        HIP_TRY(L.ks->target(L, storage, s));
+        HIP_TRY(L.ks->phase_a(L, storage, s));
         if (classes && has_a) HIP_TRY(hipEventRecord(ev[5], s));
         if (classes && has_f) HIP_TRY(hipEventRecord(ev[2], s));
-        HIP_TRY(launch_frame(L, storage, s));
+        HIP_TRY(L.ks->frame(L, storage, s));
         if (classes && has_f) HIP_TRY(hipEventRecord(ev[3], s));
         if (mode && has_b) HIP_TRY(hipEventRecord(ev[0], s));
-        HIP_TRY(launch_bulk(L, storage, tx, s));
+        HIP_TRY(L.ks->bulk(L, storage, tx, s));
         if (mode && has_b) HIP_TRY(hipEventRecord(ev[1], s));
     } else {
         HIP_TRY(hipEventRecord(ss->fork, s));
         HIP_TRY(hipStreamWaitEvent(ss->side, ss->fork, 0));
-        HIP_TRY(launch_target(L, storage, ss->side));
-        HIP_TRY(launch_phase_a(L, storage, ss->side));
-        HIP_TRY(launch_frame(L, storage, ss->side));
+        HIP_TRY(L.ks->target(L, storage, ss->side));
+        HIP_TRY(L.ks->phase_a(L, storage, ss->side));
+        HIP_TRY(L.ks->frame(L, storage, ss->side));
         HIP_TRY(hipEventRecord(ss->done, ss->side));
         if (mode && has_b) HIP_TRY(hipEventRecord(ev[0], s));
-        HIP_TRY(launch_bulk(L, storage, tx, s));
+        HIP_TRY(L.ks->bulk(L, storage, tx, s));
         if (mode && has_b) HIP_TRY(hipEventRecord(ev[1], s));
         HIP_TRY(hipStreamWaitEvent(s, ss->done, 0));
     }
-    HIP_TRY(launch_flip(L, s));
+    HIP_TRY(L.ks->flip(L, s));
     if (mode) {
         const bool used[3] = {has_b, classes && has_f, classes && has_a};
         for (int c = 0; c < 3; ++c) {
@@ -477,12 +486,14 @@ extern "C" {
 
 const char *lbm_last_error(void) { return g_err.c_str(); }
 
-lbm_status lbm_velocities(int32_t *e, double *w, double *r) {
-    for (int i = 0; i < NQ; ++i) {
-        if (e) { e[2 * i] = ex_of(i); e[2 * i + 1] = ey_of(i); }
-        if (w) w[i] = SHELL_W[shell_of(i)];
+lbm_status lbm_velocities(int32_t lattice, int32_t *e, double *w, double *r) {
+    if (lattice != 0 && lattice != 37 && lattice != 17) return fail(LBM_ERR_ARG, "lattice must be 37 or 17");
+    const LatticeInfo &lt = lattice == 17 ? LATTICE_D2Q17 : LATTICE_D2Q37;
+    for (int i = 0; i < lt.q; ++i) {
+        if (e) { e[2 * i] = lt.ex(i); e[2 * i + 1] = lt.ey(i); }
+        if (w) w[i] = lt.shell_w[lt.shell(i)];
     }
-    if (r) *r = LAT_R;
+    if (r) *r = lt.r;
     return LBM_OK;
 }
 
@@ -498,6 +509,7 @@ lbm_status lbm_create(const lbm_desc *desc, lbm_handle *out) {
     if (d.storage < LBM_F64 || d.storage > LBM_F16_DEV) return fail(LBM_ERR_ARG, "unknown storage");
     if (d.layout != 0 && d.layout != 1) return fail(LBM_ERR_ARG, "unknown layout");
     if (d.row_pad < -1 || d.row_pad > 4096) return fail(LBM_ERR_ARG, "row_pad must be in -1..4096");
+    if (d.lattice != 0 && d.lattice != 37 && d.lattice != 17) return fail(LBM_ERR_ARG, "lattice must be 37 or 17");
     if (d.storage == LBM_F16_DEV && d.f16_scale != 0.0) {
         int ex;
         double m = std::frexp(d.f16_scale, &ex);
@@ -505,6 +517,9 @@ lbm_status lbm_create(const lbm_desc *desc, lbm_handle *out) {
     }
     lbm_run *h = new lbm_run();
     h->desc = d;
+    h->desc.lattice = d.lattice == 17 ? 17 : 37;
+    h->lat = d.lattice == 17 ? &LATTICE_D2Q17 : &LATTICE_D2Q37;
+    h->ks = d.lattice == 17 ? &k17::kernels : &k37::kernels;
     if (d.allocator) {
         h->alloc_copy = *d.allocator;
         h->desc.allocator = &h->alloc_copy;
@@ -557,7 +572,7 @@ lbm_status lbm_footprint(lbm_handle h, size_t *bytes) {
     RunDev R{};
     lbm_status st = setup_geometry(h, R);
     if (st != LBM_OK) return st;
-    *bytes = footprint_of(R, h->desc.storage);
+    *bytes = footprint_of(R, h->desc.storage, h->lat->q);
     return LBM_OK;
 }
 
@@ -600,20 +615,20 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux, co
     }
     const int storage = h->desc.storage;
     const size_t es = elem_size(storage), cs = compute_size(storage);
-    h->footprint = footprint_of(R, storage);
+    h->footprint = footprint_of(R, storage, h->lat->q);
     for (int b = 0; b < 2; ++b) {
         R.f[b] = h->mem.get((size_t)R.fsize * es);
         R.U[b] = (double *)h->mem.get(4 * (size_t)R.qplane * sizeof(double));
         if (!R.f[b] || !R.U[b]) { h->mem.release_all(); return fail(LBM_ERR_OOM, "device allocation failed"); }
     }
-    R.Q = R.has_q ? h->mem.get((size_t)NQ * R.qplane * cs) : nullptr;
-    R.G = R.ring_n > 0 ? h->mem.get((size_t)NQ * R.rplane * cs) : nullptr;
+    R.Q = R.has_q ? h->mem.get((size_t)h->lat->q * R.qplane * cs) : nullptr;
+    R.G = R.ring_n > 0 ? h->mem.get((size_t)h->lat->q * R.rplane * cs) : nullptr;
     const bool need_p = R.tgt_pre && R.ring_n > 0;
     R.P = need_p ? (double *)h->mem.get(4 * (size_t)R.rplane * sizeof(double)) : nullptr;
     h->dd = (RunDev *)h->mem.get(sizeof(RunDev));
     h->dptr = (RunDev **)h->mem.get(sizeof(RunDev *));
     h->dprefix = (int *)h->mem.get(2 * NCLS * sizeof(int));
-    h->fbar_d = (double *)h->mem.get(NQ * sizeof(double));
+    h->fbar_d = (double *)h->mem.get(h->lat->q * sizeof(double));
     if ((R.has_q && !R.Q) || (R.ring_n > 0 && !R.G) || (need_p && !R.P) || !h->dd || !h->dptr || !h->dprefix || !h->fbar_d) {
         h->mem.release_all();
         return fail(LBM_ERR_OOM, "device allocation failed");
@@ -622,8 +637,8 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux, co
         HIP_TRY(hipMemsetAsync(R.f[b], 0, (size_t)R.fsize * es, h->stream));
         HIP_TRY(hipMemsetAsync(R.U[b], 0, 4 * (size_t)R.qplane * sizeof(double), h->stream));
     }
-    if (R.Q) HIP_TRY(hipMemsetAsync(R.Q, 0, (size_t)NQ * R.qplane * cs, h->stream));
-    if (R.G) HIP_TRY(hipMemsetAsync(R.G, 0, (size_t)NQ * R.rplane * cs, h->stream));
+    if (R.Q) HIP_TRY(hipMemsetAsync(R.Q, 0, (size_t)h->lat->q * R.qplane * cs, h->stream));
+    if (R.G) HIP_TRY(hipMemsetAsync(R.G, 0, (size_t)h->lat->q * R.rplane * cs, h->stream));
     if (R.P) HIP_TRY(hipMemsetAsync(R.P, 0, 4 * (size_t)R.rplane * sizeof(double), h->stream));
     R.par = 0; R.step = 0; R.limit = 0;
     set_scale(R, 1.0);
@@ -631,7 +646,7 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux, co
     h->hd = R;
     HIP_TRY(hipMemcpyAsync(h->dd, &h->hd, sizeof(RunDev), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipMemcpyAsync(h->dptr, &h->dd, sizeof(RunDev *), hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipMemcpyAsync(h->fbar_d, h->fbar, sizeof h->fbar, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->fbar_d, h->fbar, h->lat->q * sizeof(double), hipMemcpyHostToDevice, h->stream));
     // fields to the device
     double *dfield = (double *)h->mem.get(4 * nn * sizeof(double));
     if (!dfield) { h->mem.release_all(); return fail(LBM_ERR_OOM, "device allocation failed"); }
@@ -644,7 +659,7 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux, co
         int nb = (int)((nn + 255) / 256);
         float *dmax = (float *)h->mem.get(nb * sizeof(float));
         if (!dmax) { h->mem.release_all(); return fail(LBM_ERR_OOM, "device allocation failed"); }
-        HIP_TRY(launch_init(h->dd, storage, R.Nx, R.Ny, dfield, dfield + nn, dfield + 2 * nn,
+        HIP_TRY(h->ks->init(h->dd, storage, R.Nx, R.Ny, dfield, dfield + nn, dfield + 2 * nn,
                             dfield + 3 * nn, dmax, h->stream));
         std::vector<float> hm(nb);
         HIP_TRY(hipMemcpyAsync(hm.data(), dmax, nb * sizeof(float), hipMemcpyDeviceToHost, h->stream));
@@ -657,7 +672,7 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux, co
         set_scale(h->hd, s);
         HIP_TRY(hipMemcpyAsync(h->dd, &h->hd, sizeof(RunDev), hipMemcpyHostToDevice, h->stream));
     }
-    HIP_TRY(launch_init(h->dd, storage, R.Nx, R.Ny, dfield, dfield + nn, dfield + 2 * nn, dfield + 3 * nn,
+    HIP_TRY(h->ks->init(h->dd, storage, R.Nx, R.Ny, dfield, dfield + nn, dfield + 2 * nn, dfield + 3 * nn,
                         nullptr, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     h->mem.put(dfield);
@@ -674,7 +689,7 @@ lbm_status lbm_step(lbm_handle h, int64_t n) {
     if (h->group) return fail(LBM_ERR_STATE, "run is in a group; step it with lbm_group_step");
     if (n < 0) return fail(LBM_ERR_ARG, "nsteps < 0");
     if (n == 0) return LBM_OK;
-    HIP_TRY(launch_set_limit(h->dd, (long long)(h->steps + n), h->stream));
+    HIP_TRY(h->ks->set_limit(h->dd, (long long)(h->steps + n), h->stream));
     LaunchSet L = single_set(h);
     int64_t left = n;
     const int G = h->launch.graph_steps;
@@ -724,14 +739,14 @@ lbm_status lbm_moments(lbm_handle h, double *rho, double *ux, double *uy, double
     const RunDev &R = h->hd;
     const size_t nn = (size_t)R.Nx * R.Ny;
     if (flags & LBM_DEVICE_PTRS) {
-        HIP_TRY(launch_moments(h->dd, h->desc.storage, R.Nx, R.Ny, rho, ux, uy, T, h->stream));
+        HIP_TRY(h->ks->moments(h->dd, h->desc.storage, R.Nx, R.Ny, rho, ux, uy, T, h->stream));
         return LBM_OK;
     }
     double *tmp = (double *)h->mem.get(4 * nn * sizeof(double));
     if (!tmp) return fail(LBM_ERR_OOM, "device allocation failed");
     double *d[4] = {tmp, tmp + nn, tmp + 2 * nn, tmp + 3 * nn};
     double *o[4] = {rho, ux, uy, T};
-    hipError_t e = launch_moments(h->dd, h->desc.storage, R.Nx, R.Ny, o[0] ? d[0] : nullptr,
+    hipError_t e = h->ks->moments(h->dd, h->desc.storage, R.Nx, R.Ny, o[0] ? d[0] : nullptr,
                                   o[1] ? d[1] : nullptr, o[2] ? d[2] : nullptr, o[3] ? d[3] : nullptr,
                                   h->stream);
     for (int k = 0; k < 4 && e == hipSuccess; ++k)
@@ -746,10 +761,10 @@ lbm_status lbm_populations(lbm_handle h, double *f) {
     if (!h || !f) return fail(LBM_ERR_ARG, "NULL argument");
     if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
     const RunDev &R = h->hd;
-    const size_t n = (size_t)NQ * R.Nx * R.Ny;
+    const size_t n = (size_t)h->lat->q * R.Nx * R.Ny;
     double *tmp = (double *)h->mem.get(n * sizeof(double));
     if (!tmp) return fail(LBM_ERR_OOM, "device allocation failed");
-    hipError_t e = launch_export_f(h->dd, h->desc.storage, R.Nx, R.Ny, h->fbar_d, tmp, h->stream);
+    hipError_t e = h->ks->export_f(h->dd, h->desc.storage, R.Nx, R.Ny, h->fbar_d, tmp, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(f, tmp, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     h->mem.put(tmp);
@@ -761,12 +776,12 @@ lbm_status lbm_pml_q(lbm_handle h, double *Q) {
     if (!h || !Q) return fail(LBM_ERR_ARG, "NULL argument");
     if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
     const RunDev &R = h->hd;
-    const size_t n = (size_t)NQ * R.Nx * R.Ny;
+    const size_t n = (size_t)h->lat->q * R.Nx * R.Ny;
     if (!R.has_q) { std::memset(Q, 0, n * sizeof(double)); return LBM_OK; }
     double *tmp = (double *)h->mem.get(n * sizeof(double));
     if (!tmp) return fail(LBM_ERR_OOM, "device allocation failed");
     hipError_t e = hipMemsetAsync(tmp, 0, n * sizeof(double), h->stream);
-    if (e == hipSuccess) e = launch_export_q(h->dd, h->desc.storage, R.frame_n, tmp, h->stream);
+    if (e == hipSuccess) e = h->ks->export_q(h->dd, h->desc.storage, R.frame_n, tmp, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(Q, tmp, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     h->mem.put(tmp);
@@ -784,14 +799,14 @@ lbm_status lbm_error_norms(lbm_handle h, const double *ref_rho, const double *re
     double *tmp = (double *)h->mem.get((3 * nn + 3 * nb + 3 * (size_t)ly + 3) * sizeof(double));
     if (!tmp) return fail(LBM_ERR_OOM, "device allocation failed");
     double *m = tmp, *refs = tmp + 3 * nn, *part = refs + 3 * nb, *dout = part + 3 * (size_t)ly;
-    hipError_t e = launch_moments(h->dd, h->desc.storage, R.Nx, R.Ny, m, m + nn, nullptr, m + 2 * nn, h->stream);
+    hipError_t e = h->ks->moments(h->dd, h->desc.storage, R.Nx, R.Ny, m, m + nn, nullptr, m + 2 * nn, h->stream);
     const double *src[3] = {ref_rho, ref_ux, ref_T};
     for (int k = 0; k < 3 && e == hipSuccess; ++k)
         e = hipMemcpyAsync(refs + k * nb, src[k], nb * sizeof(double), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
-        e = launch_err_rows(m, m + nn, m + 2 * nn, R.Nx, R.Wxm, R.Wym, h->desc.nx, ly, refs, refs + nb,
+        e = h->ks->err_rows(m, m + nn, m + 2 * nn, R.Nx, R.Wxm, R.Wym, h->desc.nx, ly, refs, refs + nb,
                             refs + 2 * nb, part, h->stream);
-    if (e == hipSuccess) e = launch_err_final(part, ly, dout, h->stream);
+    if (e == hipSuccess) e = h->ks->err_final(part, ly, dout, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(out, dout, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     h->mem.put(tmp);
@@ -806,7 +821,7 @@ lbm_status lbm_check(lbm_handle h) {
     if (!flag) return fail(LBM_ERR_OOM, "device allocation failed");
     int hf = 0;
     hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), h->stream);
-    if (e == hipSuccess) e = launch_check(h->dd, h->desc.storage, h->hd.Nx, h->hd.Ny, flag, h->stream);
+    if (e == hipSuccess) e = h->ks->check(h->dd, h->desc.storage, h->hd.Nx, h->hd.Ny, flag, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     h->mem.put(flag);
@@ -870,7 +885,7 @@ void lbm_destroy(lbm_handle h) {
 namespace {
 struct CkptHeader {
     char magic[8];
-    int32_t version, Nx, Ny, storage, W, pml[4], bc[4], par, layout;
+    int32_t version, Nx, Ny, storage, W, pml[4], bc[4], par, layout, lattice;
     int64_t steps, plane, qplane;
     double tau, rho0, ux0, uy0, T0, sigma_max, scale;
     uint64_t checksum;
@@ -885,9 +900,9 @@ lbm_status lbm_save(lbm_handle h, const char *path) {
     const RunDev &R = h->hd;
     const int storage = h->desc.storage;
     size_t fb = (size_t)R.fsize * elem_size(storage);
-    size_t qb = R.has_q ? (size_t)NQ * R.qplane * compute_size(storage) : 0;
+    size_t qb = R.has_q ? (size_t)h->lat->q * R.qplane * compute_size(storage) : 0;
     size_t ub = 4 * (size_t)R.qplane * sizeof(double);
-    size_t gb = R.ring_n > 0 ? (size_t)NQ * R.rplane * compute_size(storage) : 0;
+    size_t gb = R.ring_n > 0 ? (size_t)h->lat->q * R.rplane * compute_size(storage) : 0;
     std::vector<char> buf(2 * fb + qb + 2 * ub + gb);
     char *p = buf.data();
     for (int b = 0; b < 2; ++b) { HIP_TRY(hipMemcpy(p, R.f[b], fb, hipMemcpyDeviceToHost)); p += fb; }
@@ -895,9 +910,9 @@ lbm_status lbm_save(lbm_handle h, const char *path) {
     for (int b = 0; b < 2; ++b) { HIP_TRY(hipMemcpy(p, R.U[b], ub, hipMemcpyDeviceToHost)); p += ub; }
     if (gb) { HIP_TRY(hipMemcpy(p, R.G, gb, hipMemcpyDeviceToHost)); p += gb; }
     CkptHeader hdr{};
-    std::memcpy(hdr.magic, "LBMPML02", 8);
-    hdr.version = 2; hdr.Nx = R.Nx; hdr.Ny = R.Ny; hdr.storage = storage; hdr.W = h->W;
-    hdr.layout = h->desc.layout;
+    std::memcpy(hdr.magic, "LBMPML03", 8);
+    hdr.version = 3; hdr.Nx = R.Nx; hdr.Ny = R.Ny; hdr.storage = storage; hdr.W = h->W;
+    hdr.layout = h->desc.layout; hdr.lattice = h->lat->q;
     for (int s = 0; s < 4; ++s) { hdr.pml[s] = h->pml[s]; hdr.bc[s] = h->bc[s]; }
     hdr.par = R.par; hdr.steps = h->steps; hdr.plane = R.plane; hdr.qplane = R.qplane;
     hdr.tau = h->desc.tau; hdr.rho0 = h->desc.rho0; hdr.ux0 = h->desc.ux0; hdr.uy0 = h->desc.uy0;
@@ -918,23 +933,23 @@ lbm_status lbm_load(lbm_handle h, const char *path) {
     FILE *fp = std::fopen(path, "rb");
     if (!fp) return fail(LBM_ERR_ARG, std::string("cannot open ") + path);
     CkptHeader hdr{};
-    if (std::fread(&hdr, sizeof hdr, 1, fp) != 1 || std::memcmp(hdr.magic, "LBMPML02", 8) != 0) {
+    if (std::fread(&hdr, sizeof hdr, 1, fp) != 1 || std::memcmp(hdr.magic, "LBMPML03", 8) != 0) {
         std::fclose(fp);
         return fail(LBM_ERR_ARG, "not a checkpoint file");
     }
     RunDev &R = h->hd;
     const int storage = h->desc.storage;
     bool same = hdr.Nx == R.Nx && hdr.Ny == R.Ny && hdr.storage == storage && hdr.W == h->W &&
-                hdr.layout == h->desc.layout &&
+                hdr.layout == h->desc.layout && hdr.lattice == h->lat->q &&
                 hdr.plane == R.plane && hdr.qplane == R.qplane && hdr.tau == h->desc.tau &&
                 hdr.rho0 == h->desc.rho0 && hdr.ux0 == h->desc.ux0 && hdr.uy0 == h->desc.uy0 &&
                 hdr.T0 == h->desc.T0 && hdr.sigma_max == h->sigma_max;
     for (int s = 0; s < 4; ++s) same = same && hdr.pml[s] == h->pml[s] && hdr.bc[s] == h->bc[s];
     if (!same) { std::fclose(fp); return fail(LBM_ERR_ARG, "checkpoint configuration differs from the handle's"); }
     size_t fb = (size_t)R.fsize * elem_size(storage);
-    size_t qb = R.has_q ? (size_t)NQ * R.qplane * compute_size(storage) : 0;
+    size_t qb = R.has_q ? (size_t)h->lat->q * R.qplane * compute_size(storage) : 0;
     size_t ub = 4 * (size_t)R.qplane * sizeof(double);
-    size_t gb = R.ring_n > 0 ? (size_t)NQ * R.rplane * compute_size(storage) : 0;
+    size_t gb = R.ring_n > 0 ? (size_t)h->lat->q * R.rplane * compute_size(storage) : 0;
     std::vector<char> buf(2 * fb + qb + 2 * ub + gb);
     bool ok = std::fread(buf.data(), 1, buf.size(), fp) == buf.size();
     std::fclose(fp);
@@ -968,9 +983,9 @@ lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path, lbm
         if (fp) {
             char line[256];
             while (std::fgets(line, sizeof line, fp)) {
-                int nx, ny, st, tx, ov;
-                if (std::sscanf(line, "%d %d %d %d %d", &nx, &ny, &st, &tx, &ov) != 5) continue;
-                if (nx == R.Nx && ny == R.Ny && st == h->desc.storage) {
+                int nx, ny, st, q, tx, ov;
+                if (std::sscanf(line, "%d %d %d %d %d %d", &nx, &ny, &st, &q, &tx, &ov) != 6) continue;
+                if (nx == R.Nx && ny == R.Ny && st == h->desc.storage && q == h->lat->q) {
                     std::fclose(fp);
                     lbm_launch c = h->launch;
                     c.bulk_tx = tx; c.bulk_ty = 256 / tx; c.overlap = ov;
@@ -1022,7 +1037,7 @@ lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path, lbm
     if (st == LBM_OK && cache_path) {
         FILE *fp = std::fopen(cache_path, "a");
         if (fp) {
-            std::fprintf(fp, "%d %d %d %d %d\n", R.Nx, R.Ny, h->desc.storage, best_tx, best_ov);
+            std::fprintf(fp, "%d %d %d %d %d %d\n", R.Nx, R.Ny, h->desc.storage, h->lat->q, best_tx, best_ov);
             std::fclose(fp);
         }
     }
@@ -1058,10 +1073,12 @@ lbm_status lbm_group_add(lbm_group_handle g, lbm_handle h) {
     if (!h->inited) return fail(LBM_ERR_STATE, "initialise the run before adding it");
     if (h->group) return fail(LBM_ERR_STATE, "run already in a group");
     if (g->storage >= 0 && g->storage != h->desc.storage) return fail(LBM_ERR_ARG, "all runs of a group share one storage");
+    if (g->ks && g->ks != h->ks) return fail(LBM_ERR_ARG, "all runs of a group share one velocity stencil");
     if (g->members.size() >= 4096) return fail(LBM_ERR_ARG, "group full (4096 runs)");
     HIP_TRY(hipStreamSynchronize(h->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
     g->storage = h->desc.storage;
+    g->ks = h->ks;
     g->members.push_back(h);
     h->group = g;
     h->stream = g->stream;
@@ -1077,7 +1094,7 @@ lbm_status lbm_group_remove(lbm_group_handle g, lbm_handle h) {
     g->members.erase(it);
     h->group = nullptr;
     h->stream = h->own_stream ? h->own_stream : (hipStream_t)h->desc.stream;
-    if (g->members.empty()) g->storage = -1;
+    if (g->members.empty()) { g->storage = -1; g->ks = nullptr; }
     g->dirty = true;
     return LBM_OK;
 }
@@ -1151,8 +1168,9 @@ lbm_status lbm_group_step(lbm_group_handle g, const int64_t *steps, int64_t nste
     HIP_TRY(hipMemcpyAsync(g->dlimits, g->hlimits, n * sizeof(long long), hipMemcpyHostToDevice, g->stream));
     HIP_TRY(hipEventRecord(g->upload_done, g->stream));
     g->upload_pending = true;
-    HIP_TRY(launch_set_limits(g->druns, g->dlimits, (int)n, g->stream));
+    HIP_TRY(g->ks->set_limits(g->druns, g->dlimits, (int)n, g->stream));
     LaunchSet L;
+    L.ks = g->ks;
     L.runs = g->druns;
     for (int c = 0; c < NCLS; ++c) {
         L.prefix[c] = g->dprefix + c * (g->cap + 1);

@@ -16,9 +16,10 @@ enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2 };
 // array of pointers to descriptors, so a single run and a batch share every kernel.
 //
 // Grid: Nx x Ny nodes; population i of node (x, y) is f[par][i * plane + y * pitch + x].  With
-// the row layout (default) the 37 population rows of one grid row are adjacent (plane = padded
-// row, pitch = 37 padded rows), which keeps the pulls of a tile inside a few MiB of address
+// the row layout (default) the q population rows of one grid row are adjacent (plane = padded
+// row, pitch = q padded rows), which keeps the pulls of a tile inside a few MiB of address
 // space; with the plane layout `plane` is a whole padded plane and `pitch` a padded row.
+// Arrays of per-pair and per-shell constants are sized for the largest stencil (D2Q37).
 // Frame: the nodes outside the fast interior rectangle [fx0,fx1) x [fy0,fy1), i.e. a frame of
 // depth gxm/gxp/gym/gyp on the four sides.  Frame nodes are numbered bottom strip, top strip,
 // left strip, right strip (row-major inside each strip); Q and the moment strips U use that
@@ -40,18 +41,18 @@ struct alignas(256) RunDev {
     int tiles_x[3], tiles_y[3];   // bulk tiles for tile widths 64, 128, 256
     // state
     void *f[2];
-    void *Q;                  // [37][qplane] in the compute type
+    void *Q;                  // [q][qplane] in the compute type
     double *U[2];             // [4][qplane]: rho, ux, uy, T (absolute values)
-    void *G;                  // [37][rplane] compute type: post-boundary populations of the ring
+    void *G;                  // [q][rplane] compute type: post-boundary populations of the ring
     double *P;                // [4][rplane]: characteristic targets formed by k_target (if tgt_pre)
     long long rplane;
     int par, tgt_pre;         // tgt_pre: NRBC targets formed by k_target (PML moments selected)
     long long step, limit;    // a run is active while step < limit
     // constants (double and float copies)
     double omega, rho0, u0x, u0y, T0, th0, b0, r0x, r0y, sigma_max, inv_W2, scale, inv_scale;
-    double H0rest, H0e[NPAIR], H0o[NPAIR], E2_0[NSHELL], O1_0[NSHELL];
+    double H0rest, H0e[NPAIR_MAX], H0o[NPAIR_MAX], E2_0[NSHELL_MAX], O1_0[NSHELL_MAX];
     float omega_f, rho0_f, u0x_f, u0y_f, th0_f, b0_f, r0x_f, r0y_f, T0_f, scale_f, inv_scale_f;
-    float H0rest_f, H0e_f[NPAIR], H0o_f[NPAIR], E2_0_f[NSHELL], O1_0_f[NSHELL];
+    float H0rest_f, H0e_f[NPAIR_MAX], H0o_f[NPAIR_MAX], E2_0_f[NSHELL_MAX], O1_0_f[NSHELL_MAX];
 };
 
 // Launch decomposition of a set of runs: prefix[k] = first block of run k, prefix[n] = total.
@@ -59,7 +60,9 @@ struct alignas(256) RunDev {
 // launch (ring blocks, then frame blocks if the run has a PML); the characteristic targets of
 // runs that select the PML moments (ring blocks).
 enum Cls { CLS_BULK = 0, CLS_FRAME = 1, CLS_A = 2, CLS_TGT = 3, NCLS = 4 };
+struct KernelSet;
 struct LaunchSet {
+    const KernelSet *ks;      // kernels of the runs' velocity stencil (one stencil per set)
     RunDev *const *runs;      // device array of descriptor pointers
     const int *prefix[NCLS];  // device prefix arrays per class
     int blocks[NCLS];         // total blocks per class
@@ -72,30 +75,35 @@ constexpr int FRAME_BLOCK = 256;
 // different compute units instead of sharing one unit's memory pipeline four at a time.
 constexpr int RING_BLOCK = 64;
 
-// Kernel launchers (lbm_kernels.hip).  All enqueue on `s` and return the HIP status of the
-// launch.
-// Phase A: characteristic fill of the ring and PML auxiliary update; frame: phase B (collision)
-// of every frame node, ring included.
-hipError_t launch_phase_a(const LaunchSet &L, int storage, hipStream_t s);
-hipError_t launch_frame(const LaunchSet &L, int storage, hipStream_t s);
-hipError_t launch_target(const LaunchSet &L, int storage, hipStream_t s);
-hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, hipStream_t s);
-hipError_t launch_flip(const LaunchSet &L, hipStream_t s);
-hipError_t launch_set_limit(RunDev *run, long long limit, hipStream_t s);
-hipError_t launch_set_limits(RunDev *const *runs, const long long *limits, int n, hipStream_t s);
-hipError_t launch_init(RunDev *run, int storage, int Nx, int Ny, const double *rho,
+// Kernel launchers of one velocity stencil (lbm_kernels.hip, compiled once per stencil).  All
+// enqueue on `s` and return the HIP status of the launch.
+// phase_a: characteristic fill of the ring and PML auxiliary update; frame: phase B (collision)
+// of every frame node, ring included; target: characteristic targets with the PML moments.
+struct KernelSet {
+    int q;
+    hipError_t (*phase_a)(const LaunchSet &L, int storage, hipStream_t s);
+    hipError_t (*frame)(const LaunchSet &L, int storage, hipStream_t s);
+    hipError_t (*target)(const LaunchSet &L, int storage, hipStream_t s);
+    hipError_t (*bulk)(const LaunchSet &L, int storage, int tx, hipStream_t s);
+    hipError_t (*flip)(const LaunchSet &L, hipStream_t s);
+    hipError_t (*set_limit)(RunDev *run, long long limit, hipStream_t s);
+    hipError_t (*set_limits)(RunDev *const *runs, const long long *limits, int n, hipStream_t s);
+    hipError_t (*init)(RunDev *run, int storage, int Nx, int Ny, const double *rho,
                        const double *ux, const double *uy, const double *T, float *absmax,
                        hipStream_t s);
-hipError_t launch_moments(RunDev *run, int storage, int Nx, int Ny, double *rho, double *ux,
+    hipError_t (*moments)(RunDev *run, int storage, int Nx, int Ny, double *rho, double *ux,
                           double *uy, double *T, hipStream_t s);
-hipError_t launch_export_f(RunDev *run, int storage, int Nx, int Ny, const double *fbar,
+    hipError_t (*export_f)(RunDev *run, int storage, int Nx, int Ny, const double *fbar,
                            double *out, hipStream_t s);
-hipError_t launch_export_q(RunDev *run, int storage, int frame_n, double *out, hipStream_t s);
-hipError_t launch_check(RunDev *run, int storage, int Nx, int Ny, int *flag, hipStream_t s);
-hipError_t launch_err_rows(const double *rho, const double *ux, const double *T, int Nx,
+    hipError_t (*export_q)(RunDev *run, int storage, int frame_n, double *out, hipStream_t s);
+    hipError_t (*check)(RunDev *run, int storage, int Nx, int Ny, int *flag, hipStream_t s);
+    hipError_t (*err_rows)(const double *rho, const double *ux, const double *T, int Nx,
                            int x0, int y0, int lx, int ly, const double *rr, const double *ru,
                            const double *rt, double *partials, hipStream_t s);
-hipError_t launch_err_final(const double *partials, int nrows, double *out, hipStream_t s);
+    hipError_t (*err_final)(const double *partials, int nrows, double *out, hipStream_t s);
+};
 
+namespace k37 { extern const KernelSet kernels; }
+namespace k17 { extern const KernelSet kernels; }
 
 }  // namespace lbm

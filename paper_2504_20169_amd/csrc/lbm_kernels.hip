@@ -1,4 +1,6 @@
-// HIP kernels (gfx950, wave64) for the D2Q37 thermal LBM with PML and open boundaries.
+// HIP kernels (gfx950, wave64) for the thermal LBM with PML and open boundaries, compiled once
+// per velocity stencil: LBM_Q = 37 (default; this file) or 17 (lbm_kernels_d2q17.hip), each
+// instance in its own namespace (k37, k17) with its stencil's constants in scope.
 //
 // Every kernel takes an array of run descriptors, so one launch advances one run or a batch of
 // uneven runs.  Per step:
@@ -11,7 +13,7 @@
 //   k_flip         swap the population and moment-strip buffers of active runs
 // NR = true instances cover only the 3-deep ring of characteristic-boundary nodes (FP64 LODI
 // fill); NR = false instances skip those nodes and carry none of that code, which keeps their
-// register budget low.  The collision is a per-node projection streaming 2 x 37 values
+// register budget low.  The collision is a per-node projection streaming 2 x q values
 // through HBM: no MFMA.  Pulls are coalesced row segments shifted by e_i (each source value is
 // read exactly once); descriptors are read through the constant address space (scalar
 // loads) and populations through global pointers with one 32-bit byte offset per lane.
@@ -20,14 +22,16 @@
 // fbar = feq(rho0, u0, T0), and the equilibrium deviation feq(U) - fbar is evaluated from
 // differences of its Hermite coefficients, so float32 storage and arithmetic keep their
 // relative precision on the (small) deviations.  With theta = T - 1, a = u.xi, s = |xi|^2,
-// b = |u|^2, the fourth-order equilibrium (eq. feq-4 with the (c^2 - 6) reading) is
+// b = |u|^2, the fourth-order equilibrium of D2Q37 (eq. feq-4 with the (c^2 - 6) reading) is
 //   feq_i = w_i rho H(a, s),
 //   H = E0(s) + E2(s) a^2 + a^4/24 + a (O1(s) + a^2/6),
 //   E0 = k0 + k2s s + theta^2 s^2/8,  E2 = k2a + theta s/4,  O1 = k1 + theta s/2,
 //   k0 = 1 - b/2 - theta + b^2/8 + theta b + theta^2,  k1 = 1 - b/2 - 2 theta,
 //   k2a = 1/2 - b/4 - 3 theta/2,  k2s = theta/2 - theta b/4 - theta^2,
-// and feq(U) - fbar = w (drho H0 + rho dH) with dH = H(U) - H(U0) expanded in products of
-// deviations.
+// and the third-order equilibrium of D2Q17 (eq. feq-3) drops the fourth-order Hermite term:
+//   H = E0(s) + a^2/2 + a (O1(s) + a^2/6),  E0 = k0 + theta s/2,  k0 = 1 - b/2 - theta,
+// with O1 and k1 as above; feq(U) - fbar = w (drho H0 + rho dH) with dH = H(U) - H(U0)
+// expanded in products of deviations.
 #include <type_traits>
 #include <utility>
 
@@ -36,8 +40,23 @@
 #define GLOBAL __attribute__((address_space(1)))
 #define CONSTANT __attribute__((address_space(4)))
 
-namespace lbm {
+#ifndef LBM_Q
+#define LBM_Q 37
+#endif
+#if LBM_Q == 37
+#define LBM_LATTICE d2q37
+#define LBM_KSET k37
+#elif LBM_Q == 17
+#define LBM_LATTICE d2q17
+#define LBM_KSET k17
+#else
+#error "LBM_Q must be 37 or 17"
+#endif
 
+namespace lbm {
+namespace LBM_KSET {
+
+using namespace ::lbm::LBM_LATTICE;
 using CRun = const CONSTANT RunDev;
 
 // ------------------------------------------------------------------------------------------
@@ -234,17 +253,24 @@ __device__ __forceinline__ Eq<C> eq_coef(C drho, C dux, C duy, C dT, const K<C> 
     q.Rdux = C(LAT_R) * dux;
     q.Rduy = C(LAT_R) * duy;
     q.dT = dT;
-    C ux = k.u0x + dux, uy = k.u0y + duy, th = k.th0 + dT;
-    C b = ux * ux + uy * uy;
     C db = dux * (C(2) * k.u0x + dux) + duy * (C(2) * k.u0y + duy);
-    C dth2 = dT * (th + k.th0);
-    C dthb = dT * b + k.th0 * db;
-    C db2 = db * (b + k.b0);
-    q.dk0 = -C(0.5) * db - dT + C(0.125) * db2 + dthb + dth2;
+    if constexpr (ORDER == 4) {
+        C ux = k.u0x + dux, uy = k.u0y + duy, th = k.th0 + dT;
+        C b = ux * ux + uy * uy;
+        C dth2 = dT * (th + k.th0);
+        C dthb = dT * b + k.th0 * db;
+        C db2 = db * (b + k.b0);
+        q.dk0 = -C(0.5) * db - dT + C(0.125) * db2 + dthb + dth2;
+        q.dk2a = -C(0.25) * db - C(1.5) * dT;
+        q.dk2s = C(0.5) * dT - C(0.25) * dthb - dth2;
+        q.dth2 = dth2;
+    } else {   // third order: k0 = 1 - b/2 - theta, k2a = 1/2, k2s = theta/2
+        q.dk0 = -C(0.5) * db - dT;
+        q.dk2a = C(0);
+        q.dk2s = C(0.5) * dT;
+        q.dth2 = C(0);
+    }
     q.dk1 = -C(0.5) * db - C(2) * dT;
-    q.dk2a = -C(0.25) * db - C(1.5) * dT;
-    q.dk2s = C(0.5) * dT - C(0.25) * dthb - dth2;
-    q.dth2 = dth2;
     q.dE0 = q.dE2 = q.dO1 = C(0);
     return q;
 }
@@ -258,8 +284,13 @@ __device__ __forceinline__ C feq_rest(const Eq<C> &q, CRun &R) {
 template <class C, int sh>
 __device__ __forceinline__ void eq_shell(Eq<C> &q) {
     constexpr double sv = LAT_R2 * SHELL_E2[sh];
-    q.dE0 = q.dk0 + q.dk2s * C(sv) + q.dth2 * C(0.125 * sv * sv);
-    q.dE2 = q.dk2a + q.dT * C(0.25 * sv);
+    if constexpr (ORDER == 4) {
+        q.dE0 = q.dk0 + q.dk2s * C(sv) + q.dth2 * C(0.125 * sv * sv);
+        q.dE2 = q.dk2a + q.dT * C(0.25 * sv);
+    } else {
+        q.dE0 = q.dk0 + q.dk2s * C(sv);
+        q.dE2 = C(0);
+    }
     q.dO1 = q.dk1 + q.dT * C(0.5 * sv);
 }
 
@@ -272,11 +303,15 @@ __device__ __forceinline__ void eq_pair(const Eq<C> &q, CRun &R, const K<C> &k, 
     if constexpr (ey == 0) { a0 = C(ex) * k.r0x; da = C(ex) * q.Rdux; }
     else if constexpr (ex == 0) { a0 = C(ey) * k.r0y; da = C(ey) * q.Rduy; }
     else { a0 = C(ex) * k.r0x + C(ey) * k.r0y; da = C(ex) * q.Rdux + C(ey) * q.Rduy; }
-    const C E2_0 = cE2_0<C>(R, sh), O1_0 = cO1_0<C>(R, sh);
+    const C O1_0 = cO1_0<C>(R, sh);
     C a = a0 + da;
     C A2 = a * a, A02 = a0 * a0;
     C dA2 = da * (a + a0);
-    C dEv = q.dE0 + q.dE2 * A2 + E2_0 * dA2 + dA2 * (A2 + A02) * C(1.0 / 24.0);
+    C dEv;
+    if constexpr (ORDER == 4)
+        dEv = q.dE0 + q.dE2 * A2 + cE2_0<C>(R, sh) * dA2 + dA2 * (A2 + A02) * C(1.0 / 24.0);
+    else   // E2 = 1/2 for every shell and state
+        dEv = q.dE0 + C(0.5) * dA2;
     C dOd = q.dO1 * a + O1_0 * da + da * (A2 + a * a0 + A02) * C(1.0 / 6.0);
     C Tev = q.drho * cH0e<C>(R, p) + q.rho * dEv;
     C Tod = q.drho * cH0o<C>(R, p) + q.rho * dOd;
@@ -285,7 +320,7 @@ __device__ __forceinline__ void eq_pair(const Eq<C> &q, CRun &R, const K<C> &k, 
     fm = C(w) * (Tev - Tod);
 }
 
-// Calls emit(i, feq_i - fbar_i) for i = 0..36 with compile-time i.
+// Calls emit(i, feq_i - fbar_i) for i = 0..NQ-1 with compile-time i.
 template <class C, class F>
 __device__ __forceinline__ void for_each_feq(Eq<C> q, CRun &R, const K<C> &k, F &&emit) {
     emit(std::integral_constant<int, 0>{}, feq_rest<C>(q, R));
@@ -1023,28 +1058,28 @@ __global__ __launch_bounds__(256) void k_err_final(const double *partials, int n
 
 static inline int blocks_for(long long n) { return (int)((n + 255) / 256); }
 
-hipError_t launch_phase_a(const LaunchSet &L, int storage, hipStream_t s) {
+static hipError_t launch_phase_a(const LaunchSet &L, int storage, hipStream_t s) {
     if (L.blocks[CLS_A] > 0)
         LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a<S>), dim3(L.blocks[CLS_A]), dim3(256), 0, s,
                                                  L.runs, L.prefix[CLS_A], L.nruns));
     return hipGetLastError();
 }
 
-hipError_t launch_target(const LaunchSet &L, int storage, hipStream_t s) {
+static hipError_t launch_target(const LaunchSet &L, int storage, hipStream_t s) {
     if (L.blocks[CLS_TGT] > 0)
         LBM_DISPATCH(storage, hipLaunchKernelGGL((k_target<S>), dim3(L.blocks[CLS_TGT]), dim3(256), 0, s,
                                                  L.runs, L.prefix[CLS_TGT], L.nruns));
     return hipGetLastError();
 }
 
-hipError_t launch_frame(const LaunchSet &L, int storage, hipStream_t s) {
+static hipError_t launch_frame(const LaunchSet &L, int storage, hipStream_t s) {
     if (L.blocks[CLS_FRAME] > 0)
         LBM_DISPATCH(storage, hipLaunchKernelGGL((k_frame<S>), dim3(L.blocks[CLS_FRAME]), dim3(256), 0, s,
                                                  L.runs, L.prefix[CLS_FRAME], L.nruns));
     return hipGetLastError();
 }
 
-hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, hipStream_t s) {
+static hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, hipStream_t s) {
     const int nb = L.blocks[CLS_BULK];
     if (nb <= 0) return hipSuccess;
     const int *pre = L.prefix[CLS_BULK];
@@ -1062,22 +1097,22 @@ hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_flip(const LaunchSet &L, hipStream_t s) {
+static hipError_t launch_flip(const LaunchSet &L, hipStream_t s) {
     hipLaunchKernelGGL(k_flip, dim3((L.nruns + 255) / 256), dim3(256), 0, s, L.runs, L.nruns);
     return hipGetLastError();
 }
 
-hipError_t launch_set_limit(RunDev *run, long long limit, hipStream_t s) {
+static hipError_t launch_set_limit(RunDev *run, long long limit, hipStream_t s) {
     hipLaunchKernelGGL(k_set_limit, dim3(1), dim3(64), 0, s, run, limit);
     return hipGetLastError();
 }
 
-hipError_t launch_set_limits(RunDev *const *runs, const long long *limits, int n, hipStream_t s) {
+static hipError_t launch_set_limits(RunDev *const *runs, const long long *limits, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_set_limits, dim3((n + 255) / 256), dim3(256), 0, s, runs, limits, n);
     return hipGetLastError();
 }
 
-hipError_t launch_init(RunDev *run, int storage, int Nx, int Ny, const double *rho,
+static hipError_t launch_init(RunDev *run, int storage, int Nx, int Ny, const double *rho,
                        const double *ux, const double *uy, const double *T, float *absmax,
                        hipStream_t s) {
     int nb = blocks_for((long long)Nx * Ny);
@@ -1086,7 +1121,7 @@ hipError_t launch_init(RunDev *run, int storage, int Nx, int Ny, const double *r
     return hipGetLastError();
 }
 
-hipError_t launch_moments(RunDev *run, int storage, int Nx, int Ny, double *rho, double *ux,
+static hipError_t launch_moments(RunDev *run, int storage, int Nx, int Ny, double *rho, double *ux,
                           double *uy, double *T, hipStream_t s) {
     int nb = blocks_for((long long)Nx * Ny);
     LBM_DISPATCH(storage, hipLaunchKernelGGL((k_moments<S>), dim3(nb), dim3(256), 0, s, run, rho, ux,
@@ -1094,7 +1129,7 @@ hipError_t launch_moments(RunDev *run, int storage, int Nx, int Ny, double *rho,
     return hipGetLastError();
 }
 
-hipError_t launch_export_f(RunDev *run, int storage, int Nx, int Ny, const double *fbar,
+static hipError_t launch_export_f(RunDev *run, int storage, int Nx, int Ny, const double *fbar,
                            double *out, hipStream_t s) {
     int nb = blocks_for((long long)Nx * Ny);
     LBM_DISPATCH(storage, hipLaunchKernelGGL((k_export_f<S>), dim3(nb), dim3(256), 0, s, run, fbar,
@@ -1102,20 +1137,20 @@ hipError_t launch_export_f(RunDev *run, int storage, int Nx, int Ny, const doubl
     return hipGetLastError();
 }
 
-hipError_t launch_export_q(RunDev *run, int storage, int frame_n, double *out, hipStream_t s) {
+static hipError_t launch_export_q(RunDev *run, int storage, int frame_n, double *out, hipStream_t s) {
     if (frame_n <= 0) return hipSuccess;
     int nb = blocks_for(frame_n);
     LBM_DISPATCH(storage, hipLaunchKernelGGL((k_export_q<S>), dim3(nb), dim3(256), 0, s, run, out));
     return hipGetLastError();
 }
 
-hipError_t launch_check(RunDev *run, int storage, int Nx, int Ny, int *flag, hipStream_t s) {
+static hipError_t launch_check(RunDev *run, int storage, int Nx, int Ny, int *flag, hipStream_t s) {
     int nb = blocks_for((long long)Nx * Ny);
     LBM_DISPATCH(storage, hipLaunchKernelGGL((k_check<S>), dim3(nb), dim3(256), 0, s, run, flag));
     return hipGetLastError();
 }
 
-hipError_t launch_err_rows(const double *rho, const double *ux, const double *T, int Nx, int x0,
+static hipError_t launch_err_rows(const double *rho, const double *ux, const double *T, int Nx, int x0,
                            int y0, int lx, int ly, const double *rr, const double *ru,
                            const double *rt, double *partials, hipStream_t s) {
     if (ly <= 0) return hipSuccess;
@@ -1124,9 +1159,18 @@ hipError_t launch_err_rows(const double *rho, const double *ux, const double *T,
     return hipGetLastError();
 }
 
-hipError_t launch_err_final(const double *partials, int nrows, double *out, hipStream_t s) {
+static hipError_t launch_err_final(const double *partials, int nrows, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_err_final, dim3(1), dim3(256), 0, s, partials, nrows, out);
     return hipGetLastError();
 }
 
+// host-side table (the device pass has no host functions to point at)
+#ifndef __HIP_DEVICE_COMPILE__
+const KernelSet kernels = {NQ, launch_phase_a, launch_frame, launch_target, launch_bulk,
+                           launch_flip, launch_set_limit, launch_set_limits, launch_init,
+                           launch_moments, launch_export_f, launch_export_q, launch_check,
+                           launch_err_rows, launch_err_final};
+#endif
+
+}  // namespace LBM_KSET
 }  // namespace lbm

@@ -52,7 +52,7 @@ class lbm_desc(ctypes.Structure):
                 ("T0", ctypes.c_double), ("storage", ctypes.c_int32),
                 ("f16_scale", ctypes.c_double), ("allocator", ctypes.POINTER(lbm_allocator)),
                 ("stream", ctypes.c_void_p), ("layout", ctypes.c_int32),
-                ("row_pad", ctypes.c_int32)]
+                ("row_pad", ctypes.c_int32), ("lattice", ctypes.c_int32)]
 
 
 class lbm_launch(ctypes.Structure):
@@ -97,7 +97,7 @@ def load():
                         ctypes.c_uint],
         "lbm_populations": [H, dp],
         "lbm_pml_q": [H, dp],
-        "lbm_velocities": [i32p, dp, dp],
+        "lbm_velocities": [ctypes.c_int32, i32p, dp, dp],
         "lbm_error_norms": [H, dp, dp, dp, dp],
         "lbm_check": [H],
         "lbm_synchronize": [H],
@@ -144,11 +144,18 @@ def _dp(a):
 
 # ---- same-named functions over the C ABI ------------------------------------------------------
 
-def lbm_velocities():
-    e = np.zeros((37, 2), dtype=np.int32)
-    w = np.zeros(37)
+LATTICES = (37, 17)
+
+
+def lbm_velocities(lattice=37):
+    """(e [q,2], w [q], r) of the library's velocity order for the D2Q37 or D2Q17 stencil."""
+    q = int(lattice)
+    if q not in LATTICES:
+        raise LbmError(LBM_ERR_ARG, "lattice must be 37 or 17")
+    e = np.zeros((q, 2), dtype=np.int32)
+    w = np.zeros(q)
     r = ctypes.c_double()
-    _check(load().lbm_velocities(e.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(w),
+    _check(load().lbm_velocities(q, e.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(w),
                                  ctypes.byref(r)))
     return e.astype(np.int64), w, r.value
 
@@ -188,7 +195,7 @@ class Run:
     """One simulation handle (create -> set_pml / set_bc -> init -> step ...)."""
 
     def __init__(self, nx, ny, tau=0.8, rho0=1.0, ux0=0.0, uy0=0.0, T0=1.0, storage="f64",
-                 f16_scale=0.0, stream=None, allocator=None, layout=0, row_pad=0):
+                 f16_scale=0.0, stream=None, allocator=None, layout=0, row_pad=0, lattice=37):
         lib = load()
         self._lib = lib
         self._alloc = allocator
@@ -196,11 +203,12 @@ class Run:
                      float(T0), STORAGE[storage] if isinstance(storage, str) else int(storage),
                      float(f16_scale),
                      ctypes.pointer(allocator) if allocator is not None else None,
-                     _stream_ptr(stream), int(layout), int(row_pad))
+                     _stream_ptr(stream), int(layout), int(row_pad), int(lattice))
         h = ctypes.c_void_p()
         _check(lib.lbm_create(ctypes.byref(d), ctypes.byref(h)))
         self.h = h
         self.nx, self.ny = int(nx), int(ny)
+        self.q = 17 if int(lattice) == 17 else 37
 
     def close(self):
         if getattr(self, "h", None):
@@ -270,13 +278,13 @@ class Run:
 
     def populations(self):
         Nx, Ny = self.grid()
-        out = np.zeros((37, Ny, Nx))
+        out = np.zeros((self.q, Ny, Nx))
         _check(self._lib.lbm_populations(self.h, _dp(out)))
         return out
 
     def pml_q(self):
         Nx, Ny = self.grid()
-        out = np.zeros((37, Ny, Nx))
+        out = np.zeros((self.q, Ny, Nx))
         _check(self._lib.lbm_pml_q(self.h, _dp(out)))
         return out
 

@@ -14,24 +14,23 @@ def say(*a):
     sys.stdout.flush()
 
 
-def perm_lib_to_oracle(oracle_mod):
-    """perm[k] = library index of the oracle's velocity k."""
-    e, _, _ = lbm.lbm_velocities()
-    eo, _, _ = oracle_mod.lattice()
+def perm_lib_to_oracle(oracle_mod, q=37):
+    """perm[k] = library index of the oracle's velocity k (stencil D2Q37 or D2Q17)."""
+    e, _, _ = lbm.lbm_velocities(q)
+    eo, _, _ = oracle_mod.lattice(q)
     where = {(int(a), int(b)): i for i, (a, b) in enumerate(e)}
     return np.array([where[(int(a), int(b))] for a, b in eo])
 
 
 def make_pair(oracle_mod, Lx, Ly, tau=0.8, mean=(1.0, 0.0, 0.0, 1.0), bc=None, pml=None,
               fields=None, storage="f64", launch=None, stream=None, allocator=None, gpu=True,
-              pml_terms=0):
+              pml_terms=0, lattice=37):
     """bc: dict side->kind ('zg'|'nrbc'|'periodic') or a kind for all sides; pml: (mask, W,
-    sigma).  Returns (gpu_run or None, oracle_run)."""
+    sigma); lattice: 37 or 17.  Returns (gpu_run or None, oracle_run)."""
     rho0, ux0, uy0, T0 = mean
-    runs = []
-    o = oracle_mod.OracleRun(Lx, Ly, tau, rho0, ux0, uy0, T0)
+    o = oracle_mod.OracleRun(Lx, Ly, tau, rho0, ux0, uy0, T0, lattice=lattice)
     g = lbm.Run(Lx, Ly, tau, rho0, ux0, uy0, T0, storage=storage, stream=stream,
-                allocator=allocator) if gpu else None
+                allocator=allocator, lattice=lattice) if gpu else None
     kinds = {"periodic": 0, "zg": 1, "nrbc": 2}
     if bc is not None:
         items = bc.items() if isinstance(bc, dict) else [(s, bc) for s in SIDES]
@@ -75,7 +74,7 @@ def rel_errors(g, o, perm, with_f=True):
             scale = np.abs(b).max()
         out[name] = float(np.abs(a - b).max() / scale)
     if with_f:
-        _, w, _ = lbm.lbm_velocities()
+        _, w, _ = lbm.lbm_velocities(g.q)
         fg = g.populations()[perm]
         fo = o.populations()
         wo = w[perm]
@@ -88,7 +87,7 @@ def noise(seed, mean=(1.0, 0.0, 0.0, 1.0), amp=1e-3):
 
 
 def oracle_self_sensitivity(oracle_mod, Lx, Ly, tau=0.8, mean=(1.0, 0.0, 0.0, 1.0), bc=None,
-                            pml=None, fields=None, steps=0):
+                            pml=None, fields=None, steps=0, lattice=37):
     """How far the oracle's own populations and Q move when its input density is perturbed at
     the rounding level (random relative +-2e-16): the conditioning floor for comparing two
     FP64 implementations that round differently.  Returns (f rel-to-weight, Q rel-to-max)."""
@@ -100,10 +99,10 @@ def oracle_self_sensitivity(oracle_mod, Lx, Ly, tau=0.8, mean=(1.0, 0.0, 0.0, 1.
                 u = wl.uniform(77, Nx * Ny).reshape(Ny, Nx)
                 F = wl.Fields(F.rho * (1.0 + (u - 0.5) * 4e-16), F.ux, F.uy, F.T)
             return F
-        _, o = make_pair(oracle_mod, Lx, Ly, tau, mean, bc, pml, fk, gpu=False)
+        _, o = make_pair(oracle_mod, Lx, Ly, tau, mean, bc, pml, fk, gpu=False, lattice=lattice)
         o.step(steps)
         outs.append((o.populations(), o.pml_q()))
-    _, w, _ = oracle_mod.lattice()
+    _, w, _ = oracle_mod.lattice(lattice)
     df = float((np.abs(outs[1][0] - outs[0][0]).max(axis=(1, 2)) / w).max())
     qmax = np.abs(outs[0][1]).max()
     dq = float(np.abs(outs[1][1] - outs[0][1]).max() / qmax) if qmax > 0 else 0.0

@@ -26,9 +26,10 @@ def test_header_symbols_exported():
     assert sorted(lbm.EXPORTED) == names
 
 
-def test_velocity_table_matches_oracle(oracle_mod):
-    e, w, r = lbm.lbm_velocities()
-    eo, wo, ro = oracle_mod.lattice()
+@pytest.mark.parametrize("q", [37, 17])
+def test_velocity_table_matches_oracle(oracle_mod, q):
+    e, w, r = lbm.lbm_velocities(q)
+    eo, wo, ro = oracle_mod.lattice(q)
     assert abs(r - ro) < 1e-15
     lib = {(int(a), int(b)): wi for (a, b), wi in zip(e, w)}
     orc = {(int(a), int(b)): wi for (a, b), wi in zip(eo, wo)}
@@ -37,14 +38,22 @@ def test_velocity_table_matches_oracle(oracle_mod):
         assert abs(lib[k] - orc[k]) <= 1e-16 + 1e-14 * orc[k]
     # library order: rest first, then +e/-e pairs
     assert tuple(e[0]) == (0, 0)
-    for p in range(18):
+    for p in range((q - 1) // 2):
         assert tuple(e[1 + 2 * p]) == tuple(-e[2 + 2 * p])
+
+
+def test_velocity_table_rejects_other_stencils():
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_velocities(9)
+    assert lbm.load().lbm_velocities(9, None, None, None) == lbm.LBM_ERR_ARG
+    assert lbm.load().lbm_velocities(17, None, None, None) == lbm.LBM_OK
 
 
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.3), dict(nx=0), dict(ny=-1),
                                 dict(rho0=0.0), dict(T0=-1.0), dict(storage=7),
                                 dict(rho0=float("nan")), dict(storage="f16", f16_scale=3.0),
-                                dict(layout=2), dict(row_pad=-2), dict(row_pad=5000)])
+                                dict(layout=2), dict(row_pad=-2), dict(row_pad=5000),
+                                dict(lattice=9), dict(lattice=-1)])
 def test_create_rejects_bad_descriptor(kw):
     args = dict(nx=16, ny=16, tau=0.8)
     args.update(kw)

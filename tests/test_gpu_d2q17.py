@@ -1,0 +1,220 @@
+"""D2Q17 on the GPU (Sec. 2 "Velocity stencils", eq. feq-3): the library's second kernel
+instance against the FP64 oracle built for the same stencil, to the bar of the D2Q37 parity
+(FP64 1e-12 relative; FP32 1e-6 on rho and u), plus the stencil's own invariants on the device
+and its place in batches, checkpoints and the launch options."""
+import numpy as np
+import pytest
+
+from paper_2504_20169_amd import lbm
+from paper_2504_20169_amd import workloads as wl
+from _helpers import make_pair, noise, oracle_self_sensitivity, perm_lib_to_oracle, rel_errors, say
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+Q = 17
+
+
+@pytest.fixture(scope="module")
+def perm17(oracle_mod):
+    return perm_lib_to_oracle(oracle_mod, Q)
+
+
+def _f_tol(oracle_mod, err, **case):
+    """1e-12 on populations unless the oracle itself moves more than that under a rounding-level
+    input perturbation; then 4x that measured floor."""
+    if err.get("f", 0.0) <= TOL:
+        return TOL
+    df, _ = oracle_self_sensitivity(oracle_mod, lattice=Q, **case)
+    say("conditioning floor f=%.2e" % df)
+    return max(TOL, 4.0 * df)
+
+
+def test_plain_method_config(oracle_mod, perm17):
+    """80^2 grid (64^2 bulk + 8-cell PML, sigma_max = 0.1), ZG, pulse at rest, 200 steps."""
+    spec = wl.pulse_box(64, 8, 0.1, 200, "zg")
+    say("case d2q17 plain 80x80 ZG+PML 200 steps")
+    g, o = make_pair(oracle_mod, 64, 64, bc="zg", pml=(15, 8, 0.1), fields=spec.fields, lattice=Q)
+    g.step(200)
+    o.step(200)
+    err = rel_errors(g, o, perm17)
+    say(err)
+    assert all(v <= TOL for v in err.values()), err
+
+
+@pytest.mark.parametrize("case", [
+    dict(name="nrbc_pml_flow", Lx=70, Ly=45, bc="nrbc", pml=(15, 6, 0.05), mean=(1.0, 0.1, 0.0, 1.0), steps=80),
+    dict(name="zg_pml_flow_diag", Lx=50, Ly=66, bc="zg", pml=(15, 5, 0.08), mean=(1.0, 0.05, -0.04, 1.0), steps=60),
+    dict(name="periodic_ragged", Lx=67, Ly=61, bc="periodic", pml=None, mean=(1.0, 0.02, 0.01, 1.0), steps=100),
+    dict(name="step_geometry", Lx=60, Ly=20, bc={"xmin": "nrbc", "xmax": "nrbc", "ymin": "periodic", "ymax": "periodic"},
+         pml=(3, 10, 0.1), mean=(1.0, 0.05, 0.0, 1.0), steps=90),
+    dict(name="mixed_sides", Lx=41, Ly=37, bc={"xmin": "zg", "xmax": "nrbc", "ymin": "nrbc", "ymax": "zg"},
+         pml=(2 | 4, 5, 0.1), mean=(1.0, 0.06, 0.03, 1.02), steps=50),
+    dict(name="tiny_open", Lx=7, Ly=7, bc="nrbc", pml=None, mean=(1.0, 0.0, 0.0, 1.0), steps=20),
+    dict(name="tiny_periodic", Lx=3, Ly=5, bc="periodic", pml=None, mean=(1.0, 0.0, 0.0, 1.0), steps=20),
+    dict(name="thin_pml_w1", Lx=30, Ly=28, bc="zg", pml=(15, 1, 0.1), mean=(1.0, 0.0, 0.0, 1.0), steps=40),
+    dict(name="x_periodic_y_open", Lx=33, Ly=40, bc={"xmin": "periodic", "xmax": "periodic", "ymin": "zg", "ymax": "nrbc"},
+         pml=(4 | 8, 7, 0.05), mean=(1.0, 0.0, 0.04, 0.98), steps=60),
+])
+def test_parity_cases(oracle_mod, perm17, case):
+    say("case d2q17", case["name"])
+    kw = dict(Lx=case["Lx"], Ly=case["Ly"], bc=case["bc"], pml=case["pml"], mean=case["mean"],
+              fields=noise(11, case["mean"]))
+    g, o = make_pair(oracle_mod, lattice=Q, **kw)
+    g.step(case["steps"])
+    o.step(case["steps"])
+    err = rel_errors(g, o, perm17)
+    say(case["name"], err)
+    f_tol = _f_tol(oracle_mod, err, steps=case["steps"], **kw)
+    bad = {k: v for k, v in err.items() if not v <= (f_tol if k == "f" else TOL)}
+    assert not bad, (err, f_tol)
+    g.close()
+
+
+def test_pml_q_matches_oracle(oracle_mod, perm17):
+    kw = dict(Lx=24, Ly=20, bc="nrbc", pml=(15, 5, 0.1), mean=(1.0, 0.05, 0.0, 1.0),
+              fields=noise(5, (1.0, 0.05, 0.0, 1.0)))
+    g, o = make_pair(oracle_mod, lattice=Q, **kw)
+    g.step(30)
+    o.step(30)
+    qg = g.pml_q()[perm17]
+    qo = o.pml_q()
+    err = np.abs(qg - qo).max() / np.abs(qo).max()
+    _, dq = oracle_self_sensitivity(oracle_mod, steps=30, lattice=Q, **kw)
+    say("d2q17 Q rel err %.2e, conditioning floor %.2e" % (err, dq))
+    assert err <= max(TOL, 4.0 * dq)
+
+
+@pytest.mark.parametrize("flags", [2, 7])
+def test_nrbc_pml_terms_match_oracle(oracle_mod, perm17, flags):
+    mean = (1.0, 0.05, 0.02, 1.0)
+    g, o = make_pair(oracle_mod, 44, 38, mean=mean, bc="nrbc", pml=(15, 7, 0.01), fields=noise(9, mean),
+                     pml_terms=flags, lattice=Q)
+    g.step(30)
+    o.step(30)
+    e = rel_errors(g, o, perm17)
+    say("d2q17 terms", flags, e)
+    assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL and e["T"] < TOL
+    assert e["f"] < 1e-11
+
+
+@pytest.mark.parametrize("storage,tol_rho_u", [("f32", 1e-6), ("f16", 5e-3)])
+def test_reduced_storage_error_vs_oracle(oracle_mod, storage, tol_rho_u):
+    """FP32 / FP16 deviation storage on the vortex + pulse workload (reduced bulk, Mach 0.1,
+    NRBC + PML), 400 steps, against the FP64 oracle."""
+    spec = wl.vortex_pulse(L=96, W=12, sigma_max=0.0015, mach=0.1, bc="nrbc", radius=8.0)
+    g, o = make_pair(oracle_mod, 96, 96, bc="nrbc", pml=(15, 12, 0.0015), mean=(1.0, 0.1, 0.0, 1.0),
+                     fields=spec.fields, storage=storage, lattice=Q)
+    g.step(400)
+    o.step(400)
+    mg, mo = g.moments(), o.moments()
+    e_rho = np.abs(mg[0] - mo[0]).max() / np.abs(mo[0]).max()
+    us = max(np.abs(mo[1]).max(), np.abs(mo[2]).max())
+    e_u = max(np.abs(mg[1] - mo[1]).max(), np.abs(mg[2] - mo[2]).max()) / us
+    e_T = np.abs(mg[3] - mo[3]).max() / np.abs(mo[3]).max()
+    say("d2q17", storage, "rho %.2e u %.2e T %.2e" % (e_rho, e_u, e_T))
+    assert e_rho < tol_rho_u and e_u < tol_rho_u and e_T < tol_rho_u
+
+
+def test_full_size_grid_in_bench_launch(oracle_mod, perm17):
+    """1024^2 bulk + 32-cell PML with NRBC (1088^2), default launch, noisy state, 4 steps,
+    every node and population compared."""
+    L, W, mean, steps = 1024, 32, (1.0, 0.1, 0.0, 1.0), 4
+    say("case d2q17 full 1088^2")
+    g, o = make_pair(oracle_mod, L, L, bc="nrbc", pml=(15, W, 0.0015), mean=mean,
+                     fields=noise(21, mean, 5e-4), lattice=Q)
+    g.step(steps)
+    o.step(steps)
+    err = rel_errors(g, o, perm17)
+    say(err)
+    assert all(v <= TOL for v in err.values()), err
+
+
+def test_conservation_on_gpu():
+    e, w, rr = lbm.lbm_velocities(Q)
+    xi = rr * e.astype(float)
+    r = lbm.Run(130, 70, 0.8, lattice=Q)
+    r.init(*wl.noisy_state(130, 70, 8, 1.0, 0.03, -0.02, 1.0, amp=2e-3).as_tuple())
+
+    def cons():
+        f = r.populations().sum(axis=(1, 2))
+        return np.array([f.sum(), (f * xi[:, 0]).sum(), (f * xi[:, 1]).sum(), (f * (xi ** 2).sum(1)).sum()])
+
+    assert r.populations().shape[0] == Q
+    c0 = cons()
+    r.step(500)
+    c1 = cons()
+    assert np.all(np.abs(c1 - c0) <= 1e-12 * np.abs(c0).max()), c1 - c0
+
+
+def test_launch_options_graphs_and_layouts_keep_bits():
+    """Tile widths, graphs, the side-stream schedule and the plane layout change launches and
+    addresses, never the D2Q17 results."""
+    F = wl.noisy_state(146, 136, 3, 1.0, 0.05, 0.0, 1.0)
+    outs = []
+    for kw, launch in [({}, dict(bulk_tx=64, graph_steps=0)), ({}, dict(bulk_tx=128, graph_steps=8)),
+                       ({}, dict(bulk_tx=256, graph_steps=0, overlap=1)), (dict(layout=1), dict(bulk_tx=64)),
+                       (dict(row_pad=-1), dict(bulk_tx=64))]:
+        r = lbm.Run(134, 124, 0.8, 1.0, 0.05, 0.0, 1.0, lattice=Q, **kw)
+        r.set_launch(**launch)
+        r.set_bc(15, "nrbc")
+        r.set_pml(15, 6, 0.05)
+        r.init(*F.as_tuple())
+        r.step(33)
+        outs.append(r.populations())
+        r.close()
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+
+
+def test_group_of_d2q17_runs_equals_alone_and_rejects_mixed_stencils():
+    cases = [(48, 0, "zg", 37), (64, 8, "nrbc", 51), (33, 5, "nrbc", 9)]
+
+    def make(L, W, bc, seed, lattice=Q):
+        spec = wl.vortex_pulse(L=L, W=W, sigma_max=0.01, mach=0.1, bc=bc, seed=seed, radius=6.0)
+        r = lbm.Run(L, L, 0.8, 1.0, 0.1, 0.0, 1.0, storage="f32", lattice=lattice)
+        r.set_bc(lbm.LBM_ALL, bc)
+        if W:
+            r.set_pml(lbm.LBM_ALL, W, 0.01)
+        r.init(*spec.fields.as_tuple())
+        return r
+
+    alone = []
+    for k, (L, W, bc, n) in enumerate(cases):
+        r = make(L, W, bc, 50 + k)
+        r.step(n)
+        alone.append(r.populations())
+        r.close()
+    g = lbm.Group()
+    runs = [make(L, W, bc, 50 + k) for k, (L, W, bc, n) in enumerate(cases)]
+    for r in runs:
+        g.add(r)
+    other = make(40, 0, "zg", 1, lattice=37)
+    with pytest.raises(lbm.LbmError):
+        g.add(other)
+    g.step(steps=np.array([c[3] for c in cases]))
+    g.synchronize()
+    for r, a, c in zip(runs, alone, cases):
+        assert np.array_equal(r.populations(), a), c
+    g.close()
+    other.close()
+
+
+def test_checkpoint_roundtrip_and_stencil_mismatch(tmp_path):
+    def make(lattice=Q):
+        r = lbm.Run(60, 50, 0.8, 1.0, 0.05, 0.0, 1.0, lattice=lattice)
+        r.set_bc(15, "nrbc")
+        r.set_pml(15, 6, 0.05)
+        r.init(*wl.noisy_state(72, 62, 2, 1.0, 0.05, 0.0, 1.0).as_tuple())
+        return r
+    a = make()
+    a.step(30)
+    b = make()
+    b.step(12)
+    b.save(tmp_path / "ck17.bin")
+    c = make()
+    c.load(tmp_path / "ck17.bin")
+    c.step(18)
+    assert np.array_equal(a.populations(), c.populations())
+    d = make(37)
+    with pytest.raises(lbm.LbmError):
+        d.load(tmp_path / "ck17.bin")

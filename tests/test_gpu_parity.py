@@ -180,7 +180,7 @@ def test_autotune_choice_is_valid_cached_and_keeps_bits(tmp_path):
     c = a.autotune(steps=4, cache_path=cache)
     assert c["bulk_tx"] in (64, 128, 256) and c["overlap"] in (0, 1)
     lines = open(cache).read().split("\n")
-    assert lines[0].split() == ["106", "96", "0", str(c["bulk_tx"]), str(c["overlap"])]
+    assert lines[0].split() == ["106", "96", "0", "37", str(c["bulk_tx"]), str(c["overlap"])]
     a.step(19)
     assert np.array_equal(a.populations(), ref.populations())
     b = make()
