@@ -6,7 +6,8 @@ bulk stream-collide): 1024^2 bulk + 32-cell PML on every side (1088^2 grid), cha
 non-reflecting outer boundary, mean flow Mach 0.1 in +x, isentropic vortex (strength 0.05,
 radius 16 cells) plus a Gaussian pulse (A = 1e-3, b = 4) at a seeded position in the central
 quarter; FP64 storage is the headline line, FP32 and FP16 deviation storage are reported beside
-it.  Inputs are synthetic and resident in HBM before timing starts.
+it, and the same workloads run again on the D2Q17 stencil.  Inputs are synthetic and resident in
+HBM before timing starts.
 
 Prints ONE JSON line.  --gpus N > 1 exits with a message: this build runs on one GPU.
 """
@@ -25,8 +26,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_NODE = {"f64": 592, "f32": 296, "f16": 148}   # 2 x 37 populations, read + write
-PML_EXTRA = {"f64": 656, "f32": 328, "f16": 328}        # Q (37) + U (4) read + write
+ELEM = {"f64": 8, "f32": 4, "f16": 2}       # bytes per stored population
+COMPUTE = {"f64": 8, "f32": 4, "f16": 4}    # bytes per Q entry (compute precision)
+
+
+def bytes_per_node(storage, q=37):
+    """Algorithmic bytes of one node update: q populations read and q written."""
+    return 2 * q * ELEM[storage]
+
+
+def pml_extra(storage, q=37):
+    """Extra bytes of a PML Q-region node: Q (q entries) and U (4 doubles) read and written."""
+    return 2 * q * COMPUTE[storage] + 2 * 4 * 8
 
 
 def _log(*a):
@@ -35,7 +46,7 @@ def _log(*a):
 
 def run_from_spec(lbm, spec, storage, stream=None, alloc=None, layout=0, bulk_tx=64, overlap=0):
     r = lbm.Run(spec.Lx, spec.Ly, spec.tau, spec.rho0, spec.ux0, spec.uy0, spec.T0, storage=storage,
-                stream=stream, allocator=alloc, layout=layout)
+                stream=stream, allocator=alloc, layout=layout, lattice=spec.lattice)
     r.set_launch(bulk_tx=bulk_tx, overlap=overlap)
     r.set_bc(lbm.LBM_ALL, spec.bc)
     if spec.W:
@@ -83,9 +94,10 @@ def measure(torch, lbm, r, spec, storage, steps, warmup, prof_steps):
     dt, ms_live, n_live = time_run(torch, r, steps, warmup, mode=2)
     st = r.check()
     nodes = Nx * Ny
-    alg_bytes_step = BYTES_PER_NODE[storage] * nodes + PML_EXTRA[storage] * n_q
+    q = spec.lattice
+    alg_bytes_step = bytes_per_node(storage, q) * nodes + pml_extra(storage, q) * n_q
     bulk_ms = ms_live[0] / max(n_live[0], 1)
-    bulk_bytes = BYTES_PER_NODE[storage] * n_bulk
+    bulk_bytes = bytes_per_node(storage, q) * n_bulk
     res = dict(
         mlups=nodes * steps / dt / 1e6, mlups_bulk=spec.Lx * spec.Ly * steps / dt / 1e6,
         ms_per_step=dt * 1e3 / steps,
@@ -120,6 +132,35 @@ def large_leg(torch, lbm, wl, args):
                               overlap=args.overlap)
             out["%s_%s" % (bc, storage)] = measure(torch, lbm, r, spec, storage, args.large_steps,
                                                   20, args.large_steps // 2)
+            r.close()
+            del r
+    return out
+
+
+def d2q17_leg(torch, lbm, wl, args):
+    """The same workloads on the D2Q17 stencil (Sec. 2; eq. feq-3), 17 populations per node:
+    1024^2 + 32 PML (1088^2) vortex + pulse with NRBC in every storage, and 4096^2 + 64 PML
+    (4224^2) pulses with ZG in FP64 and FP32, where the grid is far larger than the caches."""
+    out = {}
+    spec = wl.vortex_pulse(L=args.L, W=args.W, sigma_max=args.sigma, mach=args.mach, bc=args.bc)
+    spec.lattice = 17
+    for storage in args.storages.split(","):
+        _log("bench: d2q17 1088^2", storage)
+        r = run_from_spec(lbm, spec, storage, layout=args.layout, bulk_tx=args.bulk_tx,
+                          overlap=args.overlap)
+        out["%dsq_%s_%s" % (spec.Nx, args.bc, storage)] = measure(
+            torch, lbm, r, spec, storage, args.d2q17_steps, args.warmup, args.d2q17_steps // 2)
+        r.close()
+        del r
+    if args.large_steps > 0:
+        big = wl.multi_pulse(L=4096, W=64, sigma_max=0.01, mach=0.05, bc="zg")
+        big.lattice = 17
+        for storage in ("f64", "f32"):
+            _log("bench: d2q17 4224^2", storage)
+            r = run_from_spec(lbm, big, storage, layout=args.layout, bulk_tx=args.bulk_tx,
+                              overlap=args.overlap)
+            out["4224sq_zg_%s" % storage] = measure(torch, lbm, r, big, storage, args.large_steps,
+                                                   20, args.large_steps // 2)
             r.close()
             del r
     return out
@@ -163,9 +204,9 @@ def batch_leg(torch, lbm, wl, args):
 
 
 KERNEL_SRC = [os.path.join(ROOT, "paper_2504_20169_amd", "csrc", n)
-              for n in ("lbm_kernels.hip", "lbm_capi.hip", "lbm_internal.h")]
+              for n in ("lbm_kernels.hip", "lbm_capi.hip", "lbm_internal.h", "lbm_lattice.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bulk_f64_1088sq_nrbc_pmc.txt")
-BULK_F64 = "void lbm::k_bulk<double, 64>(lbm::RunDev* const*, int const*, int)"
+BULK_F64 = "void lbm::k37::k_bulk<double, 64>(lbm::RunDev* const*, int const*, int)"
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
@@ -281,6 +322,8 @@ def main():
     ap.add_argument("--large-steps", type=int, default=200,
                     help="timed steps per run of the 4224^2 leg (0 skips it)")
     ap.add_argument("--large-bcs", default="zg,nrbc")
+    ap.add_argument("--d2q17-steps", type=int, default=1000,
+                    help="timed steps of the D2Q17 leg at the main size (0 skips it)")
     ap.add_argument("--batch-runs", type=int, default=256, help="0 skips the batch sweep")
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--serve-jobs", type=int, default=24, help="0 skips the serving trace")
@@ -411,6 +454,8 @@ def main():
         line["variants"][s] = rnd(v)
     if args.large_steps > 0:
         line["at_4224"] = rnd(large_leg(torch, lbm, wl, args))
+    if args.d2q17_steps > 0:
+        line["d2q17"] = rnd(d2q17_leg(torch, lbm, wl, args))
     if args.batch_runs > 0:
         _log("bench: batch sweep")
         line["batch"] = rnd(batch_leg(torch, lbm, wl, args))

@@ -5,8 +5,9 @@ Setup (Sec. 5.1): bulk Lx x Ly = 200 x 20, periodic along y, artificial boundari
 sides; background velocity Mach 0.05 along +x, T = 1, density plateau rho1 = 1.05 between two
 tanh fronts of steepness s = 0.5 on a rho0 = 1 background; the mean equilibrium of the PML is
 taken at (rho0, u0, T0).  Each configuration is a boundary (ZG, or the perfectly non-reflecting
-LODI boundary) with or without a PML of width W on both x sides, with the D2Q37 sigma_max of the
-paper's Table "Values of sigma_max used for the density step test case".
+LODI boundary) with or without a PML of width W on both x sides, with the sigma_max of the
+paper's Table "Values of sigma_max used for the density step test case" for the stencil run
+(D2Q37 or D2Q17).
 
 Reference (Sec. 5, Reference Simulation): the same initial data embedded in a fully periodic
 grid extended on both x sides far enough that no wave wraps round into the bulk window during
@@ -26,9 +27,12 @@ import time
 
 import numpy as np
 
-# D2Q37 sigma_max from the paper's density-step table, by boundary and PML width
+# sigma_max from the paper's density-step table, by stencil, boundary and PML width
 SIGMA_D2Q37 = {("zg", 10): 0.35, ("zg", 20): 0.175, ("zg", 40): 0.10,
                ("nrbc", 10): 0.001, ("nrbc", 20): 0.10, ("nrbc", 40): 0.06}
+SIGMA_D2Q17 = {("zg", 10): 0.33, ("zg", 20): 0.14, ("zg", 40): 0.09,
+               ("nrbc", 10): 0.001, ("nrbc", 20): 0.08, ("nrbc", 40): 0.04}
+SIGMA_TABLE = {37: SIGMA_D2Q37, 17: SIGMA_D2Q17}
 
 
 def step_profile(xb, Lx, rho0=1.0, rho1=1.05, s=0.5):
@@ -48,8 +52,8 @@ def step_fields(Lx, Ly, x_offset, Nx, mach=0.05, rho0=1.0, rho1=1.05, s=0.5):
     return rho, np.full((Ly, Nx), mach), np.zeros((Ly, Nx)), np.ones((Ly, Nx))
 
 
-def _make(lbm, Lx, Ly, bc, W, sigma, mach, storage, fields, tau, pml_terms=0):
-    r = lbm.Run(Lx, Ly, tau, 1.0, mach, 0.0, 1.0, storage=storage)
+def _make(lbm, Lx, Ly, bc, W, sigma, mach, storage, fields, tau, pml_terms=0, lattice=37):
+    r = lbm.Run(Lx, Ly, tau, 1.0, mach, 0.0, 1.0, storage=storage, lattice=lattice)
     r.set_bc(lbm.LBM_YMIN | lbm.LBM_YMAX, "periodic")
     r.set_bc(lbm.LBM_XMIN | lbm.LBM_XMAX, bc)
     if W > 0:
@@ -61,37 +65,44 @@ def _make(lbm, Lx, Ly, bc, W, sigma, mach, storage, fields, tau, pml_terms=0):
 
 
 def density_step_study(steps=600, sample=10, Lx=200, Ly=20, mach=0.05, tau=0.8,
-                       widths=(0, 10, 20, 40), bcs=("zg", "nrbc"), storage="f64", configs=None):
+                       widths=(0, 10, 20, 40), bcs=("zg", "nrbc"), storage="f64", configs=None,
+                       lattice=37):
     """Run every (boundary, W, sigma_max) configuration and the periodic reference in lock step.
     configs: list of (bc, W, sigma_max) or (bc, W, sigma_max, pml_terms); default: bcs x widths
-    with the paper's D2Q37 table.
+    with the paper's table for the stencil (lattice 37 or 17).
     Returns a list of dicts (bc, W, sigma_max, stable, ebar_rho, ebar_ux, emax_*, t_bc_ms, and
     C_rho, C_ux, C_t against ZG without PML when that configuration is in the list) and the
     reference's grid width."""
     from paper_2504_20169_amd import lbm
 
     if configs is None:
-        configs = [(bc, W, SIGMA_D2Q37.get((bc, W), 0.0) if W > 0 else 0.0)
+        table = SIGMA_TABLE[lattice]
+        configs = [(bc, W, table.get((bc, W), 0.0) if W > 0 else 0.0)
                    for bc in bcs for W in widths]
-    # sound travels sqrt(2)/r = 1.18 cells per step; D2Q37 carries signals up to 3 cells per step
+    # sound travels sqrt(2)/r cells per step (1.18 on D2Q37, 0.86 on D2Q17); both stencils carry
+    # signals up to 3 cells per step
     ext = int(math.ceil(3.0 * steps)) + 16
     Nref = Lx + 2 * ext
     ref = _make(lbm, Nref, Ly, "periodic", 0, 0.0, mach, storage,
-                step_fields(Lx, Ly, ext, Nref, mach), tau)
+                step_fields(Lx, Ly, ext, Nref, mach), tau, lattice=lattice)
     runs = []
     for c in configs:
         bc, W, s = c[:3]
         pt = c[3] if len(c) > 3 else 0
         r = _make(lbm, Lx, Ly, bc, W, s, mach, storage, step_fields(Lx, Ly, W, Lx + 2 * W, mach), tau,
-                  pt)
+                  pt, lattice)
         r.profile(1)
         runs.append((bc, W, s, r, [], pt))
     done = 0
     while done < steps:
         n = min(sample, steps - done)
         ref.step(n)
+        ref.synchronize()
         for run in runs:
+            # one run on the device at a time: each run owns a stream, and the per-class event
+            # timings would otherwise include other runs' kernels running concurrently
             run[3].step(n)
+            run[3].synchronize()
             if done == 0:
                 run[3].profile_read(reset=True)   # first launches carry one-off set-up costs
         done += n
@@ -104,7 +115,7 @@ def density_step_study(steps=600, sample=10, Lx=200, Ly=20, mach=0.05, tau=0.8,
         ms, n = r.profile_read()
         e = np.array(errs)
         ok = r.check() == lbm.LBM_OK and np.all(np.isfinite(e))
-        out.append(dict(bc=bc, W=W, sigma_max=s, pml_terms=pt, stable=bool(ok),
+        out.append(dict(bc=bc, W=W, sigma_max=s, pml_terms=pt, lattice=lattice, stable=bool(ok),
                         ebar_rho=float(e[:, 0].mean()), ebar_ux=float(e[:, 1].mean()),
                         emax_rho=float(e[:, 0].max()), emax_ux=float(e[:, 1].max()),
                         t_bc_ms=float(ms[1] + ms[2]), steps=steps))
@@ -119,7 +130,8 @@ def density_step_study(steps=600, sample=10, Lx=200, Ly=20, mach=0.05, tau=0.8,
     return out, Nref
 
 
-def sigma_scan(steps=600, sigmas=None, widths=(10, 20, 40), bcs=("zg", "nrbc"), storage="f64"):
+def sigma_scan(steps=600, sigmas=None, widths=(10, 20, 40), bcs=("zg", "nrbc"), storage="f64",
+               lattice=37):
     """The paper tunes sigma_max per boundary and width by a parameter scan; the same scan for
     this implementation.  Returns (rows, best): every configuration's result, and per (bc, W) the
     stable sigma_max with the lowest mean density error."""
@@ -127,7 +139,7 @@ def sigma_scan(steps=600, sigmas=None, widths=(10, 20, 40), bcs=("zg", "nrbc"), 
         sigmas = [0.0005, 0.001, 0.002, 0.005, 0.01, 0.02, 0.05, 0.1, 0.175, 0.35, 0.6]
     configs = [("zg", 0, 0.0), ("nrbc", 0, 0.0)]
     configs += [(bc, W, s) for bc in bcs for W in widths for s in sigmas]
-    rows, _ = density_step_study(steps=steps, storage=storage, configs=configs)
+    rows, _ = density_step_study(steps=steps, storage=storage, configs=configs, lattice=lattice)
     best = {}
     for d in rows:
         if d["W"] == 0 or not d["stable"]:
@@ -138,19 +150,21 @@ def sigma_scan(steps=600, sigmas=None, widths=(10, 20, 40), bcs=("zg", "nrbc"), 
     return rows, best
 
 
-def appendix_study(steps=600, W=10, sigma=0.001, flag_sets=(0, 1, 2, 4, 3, 5, 6, 7), storage="f64"):
+def appendix_study(steps=600, W=10, sigma=0.001, flag_sets=(0, 1, 2, 4, 3, 5, 6, 7), storage="f64",
+                   lattice=37):
     """The appendix experiment: the density step with the characteristic boundary behind a
     PML (W = 10, sigma_max = 0.001), with each combination of the PML moment terms I, II, III in
     the characteristic target.  Returns the study rows (plain ZG without PML first, as the base
     of C_Z)."""
     configs = [("zg", 0, 0.0)] + [("nrbc", W, sigma, f) for f in flag_sets]
-    rows, _ = density_step_study(steps=steps, storage=storage, configs=configs)
+    rows, _ = density_step_study(steps=steps, storage=storage, configs=configs, lattice=lattice)
     return rows
 
 
 def vortex_outlet_study(steps=2000, sample=20, L=300, W=10, mach=0.1, strength=0.05, radius=24.0,
-                        x_shift=60.0, tau=0.8, storage="f64", configs=None):
-    """Sec. 5.2 setting with this build's vortex: mean flow Mach `mach` along +x through an
+                        x_shift=60.0, tau=0.8, storage="f64", configs=None, lattice=37):
+    """Sec. 5.2 setting with this library's vortex (the paper runs it on D2Q17: lattice=17):
+    mean flow Mach `mach` along +x through an
     L x L bulk open on every side, an isentropic vortex (`workloads.add_isentropic_vortex`)
     starting `x_shift` cells downstream of the centre, so it leaves through the +x side.
     configs: (name, outlet kind, other sides' kind, W, sigma_max); default: ZG and the perfectly
@@ -172,11 +186,11 @@ def vortex_outlet_study(steps=2000, sample=20, L=300, W=10, mach=0.1, strength=0
 
     ext = int(math.ceil(1.3 * steps)) + 32
     Nref = L + 2 * ext
-    ref = lbm.Run(Nref, Nref, tau, 1.0, mach, 0.0, 1.0, storage=storage)
+    ref = lbm.Run(Nref, Nref, tau, 1.0, mach, 0.0, 1.0, storage=storage, lattice=lattice)
     ref.init(*fields(Nref, ext).as_tuple())
     runs = []
     for name, outlet, other, w, sg in configs:
-        r = lbm.Run(L, L, tau, 1.0, mach, 0.0, 1.0, storage=storage)
+        r = lbm.Run(L, L, tau, 1.0, mach, 0.0, 1.0, storage=storage, lattice=lattice)
         r.set_bc(lbm.LBM_ALL, other)
         r.set_bc(lbm.LBM_XMAX, outlet)
         if w:
@@ -189,8 +203,10 @@ def vortex_outlet_study(steps=2000, sample=20, L=300, W=10, mach=0.1, strength=0
     while done < steps:
         n = min(sample, steps - done)
         ref.step(n)
+        ref.synchronize()
         for run in runs:
-            run[5].step(n)
+            run[5].step(n)                        # one run on the device at a time (as above)
+            run[5].synchronize()
             if done == 0:
                 run[5].profile_read(reset=True)   # first launches carry one-off set-up costs
         done += n
@@ -223,6 +239,7 @@ def main():
     ap.add_argument("--steps", type=int, default=600)
     ap.add_argument("--sample", type=int, default=10)
     ap.add_argument("--storage", default="f64")
+    ap.add_argument("--lattice", type=int, default=37, choices=(37, 17))
     ap.add_argument("--scan", action="store_true", help="also scan sigma_max per boundary and W")
     ap.add_argument("--vortex", action="store_true",
                     help="also run the vortex outflow through ZG and LODI (B) boundaries")
@@ -230,20 +247,21 @@ def main():
                     help="also run the appendix's PML-moment terms on the characteristic boundary")
     args = ap.parse_args()
     t0 = time.perf_counter()
-    rows, nref = density_step_study(args.steps, args.sample, storage=args.storage)
+    rows, nref = density_step_study(args.steps, args.sample, storage=args.storage,
+                                    lattice=args.lattice)
     for d in rows:
         print(json.dumps(d))
     if args.scan:
-        _, best = sigma_scan(args.steps, storage=args.storage)
+        _, best = sigma_scan(args.steps, storage=args.storage, lattice=args.lattice)
         for (bc, W), d in sorted(best.items()):
             print(json.dumps(dict(scan_best=True, **d)))
     if args.vortex:
-        rows_v, nv = vortex_outlet_study(storage=args.storage)
+        rows_v, nv = vortex_outlet_study(storage=args.storage, lattice=args.lattice)
         for d in rows_v:
             print(json.dumps(dict(vortex=True, **d)))
         print(json.dumps(dict(vortex_reference_grid=nv)))
     if args.appendix:
-        for d in appendix_study(args.steps, storage=args.storage):
+        for d in appendix_study(args.steps, storage=args.storage, lattice=args.lattice):
             print(json.dumps(dict(appendix=True, **d)))
     print(json.dumps(dict(reference_grid=[nref, 20], seconds=time.perf_counter() - t0)))
 

@@ -137,6 +137,7 @@ class RunSpec:
     T0: float = 1.0
     steps: int = 0
     fields: Fields | None = field(default=None, repr=False)
+    lattice: int = 37  # velocity stencil: 37 (D2Q37) or 17 (D2Q17)
 
     @property
     def Nx(self):

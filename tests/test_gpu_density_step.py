@@ -1,17 +1,19 @@
-"""The density-step study of Sec. 5.1 on the GPU: FP64 parity with the oracle on the study's own
-geometry (periodic along y, open along x, PML on the x sides only), and the paper's qualitative
-accuracy claims on the full 200 x 20 setup."""
+"""The studies of Sec. 5 on the GPU: FP64 parity with the oracle on the density step's own
+geometry (periodic along y, open along x, PML on the x sides only), the paper's qualitative
+accuracy claims on the full 200 x 20 density step for both stencils, and the vortex outflow
+of Sec. 5.2 on D2Q17 (the stencil the paper runs it on)."""
 import numpy as np
 import pytest
 
 from paper_2504_20169_amd import studies, workloads as wl
-from _helpers import make_pair, rel_errors, say
+from _helpers import make_pair, perm_lib_to_oracle, rel_errors, say
 
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("q", [37, 17])
 @pytest.mark.parametrize("bc,W,sigma", [("zg", 10, 0.35), ("nrbc", 0, 0.0), ("nrbc", 20, 0.1)])
-def test_density_step_geometry_parity(oracle_mod, perm, bc, W, sigma):
+def test_density_step_geometry_parity(oracle_mod, bc, W, sigma, q):
     """FP64 library vs oracle on a shortened step (Lx = 80, Ly = 6, 60 steps)."""
     Lx, Ly, mach = 80, 6, 0.05
 
@@ -20,10 +22,10 @@ def test_density_step_geometry_parity(oracle_mod, perm, bc, W, sigma):
 
     bcs = {"xmin": bc, "xmax": bc, "ymin": "periodic", "ymax": "periodic"}
     g, o = make_pair(oracle_mod, Lx, Ly, mean=(1.0, mach, 0.0, 1.0), bc=bcs,
-                     pml=(1 | 2, W, sigma) if W else None, fields=fields)
+                     pml=(1 | 2, W, sigma) if W else None, fields=fields, lattice=q)
     g.step(60)
     o.step(60)
-    e = rel_errors(g, o, perm)
+    e = rel_errors(g, o, perm_lib_to_oracle(oracle_mod, q))
     say(bc, W, e)
     assert e["rho"] < 1e-12 and e["ux"] < 1e-12 and e["uy"] < 1e-12 and e["T"] < 1e-12
     assert e["f"] < 1e-11
@@ -59,3 +61,48 @@ def test_appendix_pml_terms_on_density_step():
     by = {d["pml_terms"]: d for d in rows if d["bc"] == "nrbc"}
     for f in (2, 3, 6, 7):
         assert by[f]["ebar_rho"] > 1.5 * by[0]["ebar_rho"], f
+
+
+def test_density_step_study_d2q17():
+    """Sec. 5.1 on D2Q17 with the paper's D2Q17 sigma_max table, 600 steps: every configuration
+    stays stable; the LODI boundary alone cuts the mean density and velocity errors of plain ZG
+    by about two orders (the paper: regardless of the stencil); ZG behind a 40-cell PML cuts
+    them by more than 5x; at W = 20 the LODI boundary behind the PML is about as accurate as
+    ZG behind it (the paper's Fig. comparing ZG and LODI for D2Q17); and every PML costs more
+    boundary time than plain ZG."""
+    rows, nref = studies.density_step_study(steps=600, lattice=17)
+    for d in rows:
+        say({k: (round(v, 5) if isinstance(v, float) else v) for k, v in d.items()})
+    by = {(d["bc"], d["W"]): d for d in rows}
+    assert all(d["stable"] for d in rows)
+    assert by[("nrbc", 0)]["C_rho"] < 0.05 and by[("nrbc", 0)]["C_ux"] < 0.05
+    assert by[("zg", 40)]["C_rho"] < 0.2 and by[("zg", 40)]["C_ux"] < 0.2
+    ratio = by[("nrbc", 20)]["C_rho"] / by[("zg", 20)]["C_rho"]
+    assert 1.0 / 3.0 < ratio < 3.0, ratio
+    assert all(by[(bc, W)]["C_t"] > 1.0 for bc in ("zg", "nrbc") for W in (10, 20, 40))
+
+
+def test_appendix_pml_terms_on_density_step_d2q17():
+    """The appendix experiment on D2Q17: every combination with term II loses accuracy."""
+    rows = studies.appendix_study(steps=600, lattice=17)
+    for d in rows:
+        say({k: (round(v, 6) if isinstance(v, float) else v) for k, v in d.items()})
+    assert all(d["stable"] for d in rows)
+    by = {d["pml_terms"]: d for d in rows if d["bc"] == "nrbc"}
+    for f in (2, 3, 6, 7):
+        assert by[f]["ebar_rho"] > 1.5 * by[0]["ebar_rho"], f
+
+
+def test_vortex_outflow_d2q17():
+    """Sec. 5.2 on D2Q17 (300^2 bulk, vortex leaving through the +x side, 2000 steps): all four
+    treatments stay stable; ZG behind a PML and the perfectly non-reflecting LODI boundary (the
+    paper's B) each cut plain ZG's density error by more than 2x and are within 2x of each
+    other; B behind a PML is the most accurate of the four."""
+    rows, _ = studies.vortex_outlet_study(steps=2000, sample=100, lattice=17)
+    for d in rows:
+        say({k: (round(v, 5) if isinstance(v, float) else v) for k, v in d.items()})
+    by = {d["name"]: d for d in rows}
+    assert all(d["stable"] for d in rows)
+    assert by["zg+pml"]["C_rho"] < 0.5 and by["B"]["C_rho"] < 0.5
+    assert 0.5 < by["zg+pml"]["C_rho"] / by["B"]["C_rho"] < 2.0
+    assert by["B+pml"]["C_rho"] <= min(by["zg+pml"]["C_rho"], by["B"]["C_rho"])
