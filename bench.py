@@ -266,6 +266,24 @@ def pmc_summary(fetch_csv, write_csv, out_path, command):
     print("\n".join(lines))
 
 
+def stats_summary(stats_csv, out_path, command, note):
+    """Text summary of a rocprofv3 --kernel-trace --stats run (its kernel_stats CSV): calls and
+    average / min / max dispatch duration per kernel."""
+    import csv
+    with open(stats_csv) as f:
+        rows = list(csv.DictReader(f))
+    lines = ["# rocprofv3 --kernel-trace --stats: per-kernel dispatch durations",
+             "command: " + command, note, "",
+             "%-72s %7s %12s %12s %12s %8s" % ("kernel", "calls", "avg_us", "min_us", "max_us", "pct")]
+    for r in rows:
+        lines.append("%-72s %7s %12.2f %12.2f %12.2f %8.2f" % (
+            r["Name"][:72], r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    with open(out_path, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def recorded_traffic():
     """HBM bytes per k_bulk<double> launch from the committed counter summary, or None when it
     is missing or was taken from another version of the kernels."""
@@ -337,9 +355,16 @@ def main():
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT"),
                     help="summarise two rocprofv3 --pmc passes into OUT and exit (no GPU)")
     ap.add_argument("--pmc-command", default="", help="command line recorded in the summary")
+    ap.add_argument("--stats-summary", nargs=2, metavar=("STATS_CSV", "OUT"),
+                    help="summarise a rocprofv3 --kernel-trace --stats CSV into OUT and exit (no GPU)")
+    ap.add_argument("--stats-command", default="", help="command line recorded in the summary")
+    ap.add_argument("--stats-note", default="", help="workload note recorded in the summary")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary, command=args.pmc_command)
+        return
+    if args.stats_summary:
+        stats_summary(*args.stats_summary, command=args.stats_command, note=args.stats_note)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
