@@ -24,7 +24,7 @@ _LIBS = {37: os.path.join(_HERE, "liboracle.so"), 17: os.path.join(_HERE, "libor
 LATTICES = (37, 17)
 
 SIDE_XMIN, SIDE_XMAX, SIDE_YMIN, SIDE_YMAX, SIDE_ALL = 1, 2, 4, 8, 15
-BC_PERIODIC, BC_ZG, BC_NRBC = 0, 1, 2
+BC_PERIODIC, BC_ZG, BC_NRBC, BC_NRBC_A = 0, 1, 2, 3
 
 _libs = {}
 

@@ -24,7 +24,10 @@
  * linear acoustics vs the linearised Navier-Stokes-Fourier solution; ZG+PML reflecting less
  * than ZG.  PARITY UNPINNED beyond invariants: the characteristic boundary's corner rule, time
  * level and frame (the paper defers its details to a companion paper); it is pinned only by
- * uniform-flow invariance, symmetry and the trend that it reflects less than ZG.
+ * uniform-flow invariance, symmetry and the trend that it reflects less than ZG.  Likewise the
+ * readings of CBC (A) (transverse and viscous parts, the sign of eq. CBC-Relax) are pinned only
+ * by uniform-flow invariance, symmetry, its exact reduction to the LODI boundary for plane waves
+ * and the trend that it beats the LODI boundary on a vortex outflow.
  */
 #include <math.h>
 #include <stdint.h>
@@ -231,7 +234,7 @@ static void moments_q(const double f[NQ], double U[4]) {
 /* Run state                                                                                    */
 /* ------------------------------------------------------------------------------------------ */
 enum { SIDE_XMIN = 0, SIDE_XMAX = 1, SIDE_YMIN = 2, SIDE_YMAX = 3 };
-enum { BC_PERIODIC = 0, BC_ZG = 1, BC_NRBC = 2 };
+enum { BC_PERIODIC = 0, BC_ZG = 1, BC_NRBC = 2, BC_NRBC_A = 3 };
 
 typedef struct orc_run {
     int Lx, Ly, Nx, Ny;
@@ -312,7 +315,7 @@ int orc_set_nrbc_pml_terms(orc_run *r, unsigned flags) {
 
 int orc_set_bc(orc_run *r, unsigned mask, int kind) {
     if (r->ready) return fail("configure before init");
-    if (kind < 0 || kind > 2) return fail("bad bc");
+    if (kind < 0 || kind > 3) return fail("bad bc");
     for (int s = 0; s < 4; ++s)
         if ((mask >> s) & 1u) r->bc[s] = kind;
     return 0;
@@ -449,6 +452,165 @@ static void lodi_increment(const orc_run *r, int side, int x, int y, double dU[4
     else    { dU[2] = ny * d[1]; dU[1] = d[2]; }
 }
 
+/* Primitive state (rho, u_a, u_b, T) of node (x, y) with u_a along the unit lattice vector
+ * (ax, ay) and u_b along (bx, by). */
+static void prim_frame(const orc_run *r, int x, int y, int ax, int ay, int bx, int by, double V[4]) {
+    const double *u = r->U + 4 * ((size_t)y * r->Nx + x);
+    V[0] = u[0];
+    V[1] = ax * u[1] + ay * u[2];
+    V[2] = bx * u[1] + by * u[2];
+    V[3] = u[3];
+}
+
+/* Left eigenvectors of the 2-D Euler flux Jacobian along a direction, for primitive variables
+ * (rho, u_along, u_across, T), p = rho T, gamma = 2, c = sqrt(2T): rows for the eigenvalues
+ * u - c, u (entropy), u (shear), u + c. */
+static void left_eig(double rho, double T, double S[16]) {
+    const double c = sqrt(2.0 * T);
+    const double v[16] = {T, -rho * c, 0, rho,
+                          T, 0, 0, -rho,
+                          0, 0, 1, 0,
+                          T, rho * c, 0, rho};
+    memcpy(S, v, sizeof v);
+}
+
+/* x = S^{-1} b for a 4x4 S (generic elimination). */
+static void solve4(const double S[16], const double b[4], double x[4]) {
+    long double A[16], y[4];
+    for (int k = 0; k < 16; ++k) A[k] = S[k];
+    for (int k = 0; k < 4; ++k) y[k] = b[k];
+    solve_ld(4, A, y);
+    for (int k = 0; k < 4; ++k) x[k] = (double)y[k];
+}
+
+/* Increment over one step of the edge characteristics of the states Vn[j - 2 .. j + 2] (normal
+ * frame (rho, u_n, u_t, T)) at Vn[j]: each characteristic variable of the Euler flux along the
+ * edge, with the eigenvectors frozen at Vn[j], moves over the interval its characteristic
+ * crosses in one step (linear interpolation at the foot point, at most 2 cells). */
+static void edge_advect(const double Vn[7][4], int j, double dV[4]) {
+    const double *v = Vn[j];
+    const double rho = v[0], ut = v[2], T = v[3], c = sqrt(2.0 * T);
+    double St[16];
+    left_eig(rho, T, St);
+    const double lam[4] = {ut - c, ut, ut, ut + c};
+    double dW[4];
+    for (int k = 0; k < 4; ++k) {
+        double w[5];
+        for (int m = 0; m < 5; ++m) {
+            const double *u = Vn[j - 2 + m];
+            const double vt[4] = {u[0], u[2], u[1], u[3]};   /* (rho, u_t, u_n, T) */
+            w[m] = 0.0;
+            for (int l = 0; l < 4; ++l) w[m] += St[4 * k + l] * vt[l];
+        }
+        double nu = lam[k] / LR;                             /* cells per step along +t */
+        if (!(nu == nu)) nu = 0.0;
+        if (nu > 2.0) nu = 2.0;
+        if (nu < -2.0) nu = -2.0;
+        const double a = fabs(nu);
+        int i = (int)floor(a);
+        if (i > 1) i = 1;
+        const double phi = a - i;
+        const int sgn = nu > 0.0 ? -1 : 1;                   /* foot point at -nu */
+        /* in differences, so that a state constant along the edge gives exactly zero */
+        dW[k] = -((1.0 - phi) * (w[2] - w[2 + sgn * i]) + phi * (w[2] - w[2 + sgn * (i + 1)]));
+    }
+    double dt[4];
+    solve4(St, dW, dt);
+    dV[0] = dt[0]; dV[1] = dt[2]; dV[2] = dt[1]; dV[3] = dt[3];
+}
+
+/* Characteristic boundary "CBC (A)" (Sec. 4, eq. thermal_CBC_macro_evo; Sec. 5.2, eq. CBC-Relax):
+ * the one-step target of a boundary node on one open side keeps, besides the LODI amplitudes of
+ * its outgoing waves, the transverse (Euler flux along the edge) and viscous parts of the
+ * characteristic system, dU/dt = -S^{-1} (Lbar + T + V), with the incoming amplitudes relaxed.
+ * Readings (the paper defers the solver to a companion paper):
+ *  - transverse part T: the Euler flux along the edge in the edge's own characteristic
+ *    variables, each advected over the interval its characteristic crosses in one step (as the
+ *    normal LODI amplitudes), on the boundary node's own layer (edge_advect);
+ *  - viscous part V: the tangential second derivatives only (the normal viscous fluxes of an
+ *    outflow vanish): nu d2u/dt2 for both velocity components and 2 nu d2T/dt2 (Pr = 1,
+ *    c_p/c_v = 2), nu = (tau - 1/2)/r^2 in lattice units, central differences along the edge,
+ *    taken of the transverse-advected states (advection, then diffusion: an unsplit sum of the
+ *    two explicit parts is unstable once the edge CFL number plus twice the diffusion number
+ *    exceeds one, which the D2Q17 sound speed alone nearly reaches);
+ *  - eq. CBC-Relax with T and V taken as right-hand-side terms: an incoming amplitude is
+ *    (1 - Ma) T_inc + V_inc of them, which leaves it Ma T_inc per step (Ma = |u0|, c_s = 1).
+ * Edge neighbours beyond an open edge's ends repeat the end node.  Returns the increment in the
+ * global frame. */
+static void cbc_a_increment(const orc_run *r, int side, int x, int y, double dU[4]) {
+    const int Nx = r->Nx, Ny = r->Ny;
+    const int nx = side == SIDE_XMIN ? -1 : side == SIDE_XMAX ? 1 : 0;
+    const int ny = side == SIDE_YMIN ? -1 : side == SIDE_YMAX ? 1 : 0;
+    const int tx = nx ? 0 : 1, ty = nx ? 1 : 0;        /* tangent: +y on x sides, +x on y sides */
+    const int nt = nx ? Ny : Nx, ct = nx ? y : x;
+    const int topen = nx ? open_y(r) : open_x(r);
+    /* states along the edge, ct - 3 .. ct + 3, in the normal frame (rho, u_n, u_t, T) */
+    double Vn[7][4];
+    for (int j = -3; j <= 3; ++j) {
+        int c = ct + j;
+        if (topen) c = clampi(c, 0, nt - 1);
+        else c = ((c % nt) + nt) % nt;
+        prim_frame(r, nx ? x : c, nx ? c : y, nx, ny, tx, ty, Vn[j + 3]);
+    }
+    const double rho = Vn[3][0], un = Vn[3][1], T = Vn[3][3];
+    const double c = sqrt(2.0 * T);
+    double S[16];
+    left_eig(rho, T, S);
+    const double lam[4] = {un - c, un, un, un + c};
+    /* 1. LODI amplitudes of the outgoing normal characteristics (as lodi_increment) */
+    double D[4];
+    {
+        double V[3][4];
+        for (int k = 0; k < 3; ++k) prim_frame(r, x - k * nx, y - k * ny, nx, ny, tx, ty, V[k]);
+        for (int k = 0; k < 4; ++k) {
+            double w[3];
+            for (int j = 0; j < 3; ++j) {
+                w[j] = 0.0;
+                for (int m = 0; m < 4; ++m) w[j] += S[4 * k + m] * V[j][m];
+            }
+            D[k] = 0.0;
+            if (lam[k] > 0.0) {
+                double nu = lam[k] / LR;
+                if (nu > 2.0) nu = 2.0;
+                int j = (int)floor(nu);
+                if (j > 1) j = 1;
+                double phi = nu - j;
+                D[k] = (1.0 - phi) * (w[0] - w[j]) + phi * (w[0] - w[j + 1]);
+            }
+        }
+    }
+    /* 2. transverse part at the node and its two edge neighbours, then 3. the viscous part of
+     * the advected states */
+    double Va[3][4], dVT[4];
+    for (int j = -1; j <= 1; ++j) {
+        double d[4];
+        edge_advect(Vn, j + 3, d);
+        for (int m = 0; m < 4; ++m) Va[j + 1][m] = Vn[j + 3][m] + d[m];
+        if (j == 0) memcpy(dVT, d, sizeof d);
+    }
+    double dVV[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!(topen && (ct == 0 || ct == nt - 1))) {
+        const double nuv = (r->tau - 0.5) / (LR * LR);
+        dVV[1] = nuv * (Va[2][1] - 2.0 * Va[1][1] + Va[0][1]);
+        dVV[2] = nuv * (Va[2][2] - 2.0 * Va[1][2] + Va[0][2]);
+        dVV[3] = 2.0 * nuv * (Va[2][3] - 2.0 * Va[1][3] + Va[0][3]);
+    }
+    /* 4. characteristic combination: outgoing waves take LODI + T + V, incoming Ma T */
+    const double ma = sqrt(r->ux0 * r->ux0 + r->uy0 * r->uy0);
+    double dw[4];
+    for (int k = 0; k < 4; ++k) {
+        double a = 0.0, b = 0.0;
+        for (int m = 0; m < 4; ++m) { a += S[4 * k + m] * dVT[m]; b += S[4 * k + m] * dVV[m]; }
+        dw[k] = lam[k] > 0.0 ? -D[k] + a + b : ma * a;
+    }
+    double d[4];
+    solve4(S, dw, d);
+    dU[0] = d[0];
+    dU[3] = d[3];
+    if (nx) { dU[1] = nx * d[1]; dU[2] = d[2]; }
+    else    { dU[2] = ny * d[1]; dU[1] = d[2]; }
+}
+
 /* d Q_i / d alpha at (x, y), alpha = 0 (x) or 1 (y): central differences, one-sided second
  * order at the outermost layer of an open axis (eqs. FD-dx-center, FD-dx-bw). */
 static double grad_q(const orc_run *r, int x, int y, int i, int al) {
@@ -541,8 +703,8 @@ static void one_step(orc_run *r) {
             int bnd = 0, nrbc = 0;
             for (int s = 0; s < 4; ++s)
                 if (is_boundary_side(r, s, x, y)) {
-                    bnd = 1;
-                    nrbc |= (r->bc[s] == BC_NRBC);
+                    bnd += 1;
+                    nrbc |= (r->bc[s] == BC_NRBC || r->bc[s] == BC_NRBC_A);
                 }
             if (!bnd) continue;
             int xf = ox ? clampi(x, 3, Nx - 4) : x;
@@ -558,8 +720,9 @@ static void one_step(orc_run *r) {
             for (int s = 0; s < 4; ++s) {
                 if (!is_boundary_side(r, s, x, y)) continue;
                 double d[4];
-                if (r->bc[s] != BC_NRBC) continue;
-                lodi_increment(r, s, x, y, d);
+                if (r->bc[s] == BC_NRBC_A && bnd == 1) cbc_a_increment(r, s, x, y, d);
+                else if (r->bc[s] == BC_NRBC || r->bc[s] == BC_NRBC_A) lodi_increment(r, s, x, y, d);
+                else continue;
                 for (int k = 0; k < 4; ++k) Ut[k] += d[k];
             }
             {
