@@ -67,8 +67,15 @@ typedef enum { LBM_F64 = 0, LBM_F32_DEV = 1, LBM_F16_DEV = 2 } lbm_storage;
 /* Side masks. */
 enum { LBM_XMIN = 1, LBM_XMAX = 2, LBM_YMIN = 4, LBM_YMAX = 8, LBM_ALL = 15 };
 
-/* Outer-edge treatment of a side.  PERIODIC must be set on both sides of an axis. */
-typedef enum { LBM_BC_PERIODIC = 0, LBM_BC_ZG = 1, LBM_BC_NRBC = 2 } lbm_bc;
+/* Outer-edge treatment of a side.  PERIODIC must be set on both sides of an axis.  NRBC: the
+ * perfectly non-reflecting LODI boundary (Sec. 4, eqs. PNR and thermal_LODI_macro_evo; the
+ * paper's scheme B).  NRBC_A: the characteristic boundary with transverse and viscous terms and
+ * relaxed incoming amplitudes (Sec. 4 eq. thermal_CBC_macro_evo, Sec. 5.2 eq. CBC-Relax; the
+ * paper's CBC (A), which it applies at the outlet): on the nodes of a side that lie on no other
+ * open side; corner nodes take the LODI target of each normal.  Stable on every side with D2Q17;
+ * with D2Q37, whose sound speed exceeds one cell per step, only on outflow sides (on inflow or
+ * tangential-flow sides its round-off grows). */
+typedef enum { LBM_BC_PERIODIC = 0, LBM_BC_ZG = 1, LBM_BC_NRBC = 2, LBM_BC_NRBC_A = 3 } lbm_bc;
 
 /* Optional device allocator: alloc returns device memory of at least `bytes` (256-byte
  * aligned) or NULL; free releases it.  Used for every device buffer of a run or group. */

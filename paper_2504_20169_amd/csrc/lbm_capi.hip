@@ -165,7 +165,11 @@ lbm_status setup_geometry(lbm_run *h, RunDev &R) {
     R.W = h->W;
     for (int s = 0; s < 4; ++s) R.bc[s] = h->bc[s];
     R.pml_terms = (int)h->pml_terms;
-    R.tgt_pre = h->pml_terms != 0;
+    bool cbc_a = false;
+    for (int s = 0; s < 4; ++s) cbc_a = cbc_a || h->bc[s] == BC_NRBC_A;
+    // the appendix's PML moments and CBC (A) need more than the node's own state: their targets
+    // are formed ahead of phase A by k_target
+    R.tgt_pre = h->pml_terms != 0 || cbc_a;
     if ((h->bc[XMIN] == BC_PERIODIC) != (h->bc[XMAX] == BC_PERIODIC) ||
         (h->bc[YMIN] == BC_PERIODIC) != (h->bc[YMAX] == BC_PERIODIC))
         return fail(LBM_ERR_ARG, "periodic must be set on both sides of an axis");
@@ -183,7 +187,7 @@ lbm_status setup_geometry(lbm_run *h, RunDev &R) {
     int depth[4];
     for (int s = 0; s < 4; ++s) {
         int g = 3;
-        if (h->bc[s] == BC_NRBC) g = std::max(g, 5);
+        if (is_char_bc(h->bc[s])) g = std::max(g, 5);
         if (h->pml[s] && h->W > 0) g = std::max(g, R.qd);
         depth[s] = g;
     }
@@ -191,10 +195,10 @@ lbm_status setup_geometry(lbm_run *h, RunDev &R) {
     R.gxp = std::min(depth[XMAX], R.Nx - R.gxm);
     R.gym = std::min(depth[YMIN], R.Ny);
     R.gyp = std::min(depth[YMAX], R.Ny - R.gym);
-    R.rxm = h->bc[XMIN] == BC_NRBC ? 3 : 0;
-    R.rxp = h->bc[XMAX] == BC_NRBC ? 3 : 0;
-    R.rym = h->bc[YMIN] == BC_NRBC ? 3 : 0;
-    R.ryp = h->bc[YMAX] == BC_NRBC ? 3 : 0;
+    R.rxm = is_char_bc(h->bc[XMIN]) ? 3 : 0;
+    R.rxp = is_char_bc(h->bc[XMAX]) ? 3 : 0;
+    R.rym = is_char_bc(h->bc[YMIN]) ? 3 : 0;
+    R.ryp = is_char_bc(h->bc[YMAX]) ? 3 : 0;
     R.ring_n = (R.rym + R.ryp) * R.Nx + (R.Ny - R.rym - R.ryp) * (R.rxm + R.rxp);
     R.fx0 = R.gxm; R.fx1 = R.Nx - R.gxp;
     R.fy0 = R.gym; R.fy1 = R.Ny - R.gyp;
@@ -543,7 +547,7 @@ lbm_status lbm_set_pml(lbm_handle h, unsigned mask, int32_t W, double sigma_max)
 lbm_status lbm_set_bc(lbm_handle h, unsigned mask, lbm_bc kind) {
     if (!h) return fail(LBM_ERR_ARG, "NULL handle");
     if (h->inited) return fail(LBM_ERR_STATE, "configure before lbm_init_fields");
-    if (kind < LBM_BC_PERIODIC || kind > LBM_BC_NRBC) return fail(LBM_ERR_ARG, "unknown boundary kind");
+    if (kind < LBM_BC_PERIODIC || kind > LBM_BC_NRBC_A) return fail(LBM_ERR_ARG, "unknown boundary kind");
     if (mask & ~15u) return fail(LBM_ERR_ARG, "bad side mask");
     for (int s = 0; s < 4; ++s)
         if ((mask >> s) & 1u) h->bc[s] = kind;

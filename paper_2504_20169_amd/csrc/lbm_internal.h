@@ -9,7 +9,10 @@
 namespace lbm {
 
 enum Side { XMIN = 0, XMAX = 1, YMIN = 2, YMAX = 3 };
-enum Bc { BC_PERIODIC = 0, BC_ZG = 1, BC_NRBC = 2 };
+enum Bc { BC_PERIODIC = 0, BC_ZG = 1, BC_NRBC = 2, BC_NRBC_A = 3 };
+
+// Sides with the characteristic fill (the perfectly non-reflecting LODI boundary, or CBC (A)).
+inline __host__ __device__ bool is_char_bc(int b) { return b == BC_NRBC || b == BC_NRBC_A; }
 enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2 };
 
 // Device descriptor of one run.  Lives in device memory (one per run); kernels receive an
@@ -46,7 +49,7 @@ struct alignas(256) RunDev {
     void *G;                  // [q][rplane] compute type: post-boundary populations of the ring
     double *P;                // [4][rplane]: characteristic targets formed by k_target (if tgt_pre)
     long long rplane;
-    int par, tgt_pre;         // tgt_pre: NRBC targets formed by k_target (PML moments selected)
+    int par, tgt_pre;         // tgt_pre: NRBC targets formed by k_target (PML moments or CBC (A))
     long long step, limit;    // a run is active while step < limit
     // constants (double and float copies)
     double omega, rho0, u0x, u0y, T0, th0, b0, r0x, r0y, sigma_max, inv_W2, scale, inv_scale;

@@ -412,6 +412,141 @@ __device__ void lodi_add(CRun &R, const GLOBAL double *Uc, int side, int x, int 
     else    { Ut[2] += ny * dUn; Ut[1] += dUt; }
 }
 
+// Characteristic variables of the Euler flux along one direction for primitive variables
+// v = (rho, u_along, u_across, T) (p = rho T, gamma = 2, c = sqrt(2T)), rows for the eigenvalues
+// u - c, u (entropy), u (shear), u + c, and the inverse map.
+__device__ __forceinline__ void char_fwd(double rho, double T, double c, const double (&v)[4], double (&w)[4]) {
+    w[0] = T * v[0] - rho * c * v[1] + rho * v[3];
+    w[1] = T * v[0] - rho * v[3];
+    w[2] = v[2];
+    w[3] = T * v[0] + rho * c * v[1] + rho * v[3];
+}
+__device__ __forceinline__ void char_inv(double rho, double T, double c, const double (&b)[4], double (&v)[4]) {
+    v[0] = (b[0] + b[3]) / (4.0 * T) + b[1] / (2.0 * T);
+    v[1] = (b[3] - b[0]) / (2.0 * rho * c);
+    v[2] = b[2];
+    v[3] = (b[0] + b[3]) / (4.0 * rho) - b[1] / (2.0 * rho);
+}
+
+// One-step increment, at edge position j (compile-time, 2..4 of 0..6), of the Euler flux along
+// the edge: each characteristic variable of the edge direction, eigenvectors frozen at Vn[j],
+// moves over the interval its characteristic crosses in one step (foot point at most 2 cells
+// away, linear interpolation), written in differences so a state constant along the edge gives
+// exactly zero.  Vn and dV in the normal frame (rho, u_n, u_t, T).
+template <int J>
+__device__ __forceinline__ void edge_advect(const double (&Vn)[7][4], double (&dV)[4]) {
+    const double rho = Vn[J][0], ut = Vn[J][2], T = Vn[J][3], c = sqrt(2.0 * T);
+    double w[5][4];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+        const double vt[4] = {Vn[J - 2 + m][0], Vn[J - 2 + m][2], Vn[J - 2 + m][1], Vn[J - 2 + m][3]};
+        char_fwd(rho, T, c, vt, w[m]);
+    }
+    const double lam[4] = {ut - c, ut, ut, ut + c};
+    double dW[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double nu = lam[k] * (1.0 / LAT_R);
+        if (!(nu == nu)) nu = 0.0;
+        nu = fmin(fmax(nu, -2.0), 2.0);
+        const double a = fabs(nu);
+        const bool far = a >= 1.0, fwd = nu > 0.0;      // foot beyond one cell; foot at -nu
+        const double phi = far ? a - 1.0 : a;
+        const double w1 = fwd ? w[1][k] : w[3][k], w2 = fwd ? w[0][k] : w[4][k];
+        const double wa = far ? w1 : w[2][k], wb = far ? w2 : w1;
+        dW[k] = -((1.0 - phi) * (w[2][k] - wa) + phi * (w[2][k] - wb));
+    }
+    double dt[4];
+    char_inv(rho, T, c, dW, dt);
+    dV[0] = dt[0]; dV[1] = dt[2]; dV[2] = dt[1]; dV[3] = dt[3];
+}
+
+// CBC (A) (Sec. 4 eq. thermal_CBC_macro_evo with eq. CBC-Relax of Sec. 5.2) at node (x, y) of
+// `side`, a node on no other open side: U_tgt += one step of dU/dt = -S^{-1} (Lbar + T + V) in
+// the normal frame, where
+//   - outgoing waves keep their LODI amplitude (upwind over the crossed interval, as lodi_add)
+//     plus the transverse and viscous parts;
+//   - T: the Euler flux along the edge, advected in the edge's characteristics (edge_advect) on
+//     the node's own layer;
+//   - V: tangential second derivatives only (normal viscous fluxes of an outflow vanish),
+//     nu = (tau - 1/2)/r^2 on both velocity components and 2 nu on T (Pr = 1, c_p/c_v = 2),
+//     taken of the transverse-advected states at the node and its edge neighbours (advection,
+//     then diffusion: the unsplit sum of the two explicit parts is unstable);
+//   - eq. CBC-Relax with T and V as right-hand-side terms: an incoming amplitude is
+//     (1 - Ma) T_inc + V_inc of them, leaving it Ma T_inc (Ma = |u0| with c_s = 1).
+// Edge neighbours beyond an open edge's ends repeat the end node.  Float64 throughout.
+__device__ void cbc_a_add(CRun &R, const GLOBAL double *Uc, int side, int x, int y, int t, double Ut[4]) {
+    const unsigned qp = (unsigned)R.qplane;
+    const int nx = side == XMIN ? -1 : (side == XMAX ? 1 : 0);
+    const int ny = side == YMIN ? -1 : (side == YMAX ? 1 : 0);
+    const int nt = nx ? R.Ny : R.Nx, ct = nx ? y : x;
+    const bool topen = nx ? R.open_y : R.open_x;
+    double Vn[7][4];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        int cc = ct + j - 3;
+        if (topen) cc = min(max(cc, 0), nt - 1);
+        else cc = cc < 0 ? cc + nt : (cc >= nt ? cc - nt : cc);
+        int jj = nx ? fidx(R, x, cc) : fidx(R, cc, y);
+        if (jj < 0) jj = t;
+        const double ux = Uc[qp + jj], uy = Uc[2 * qp + jj];
+        Vn[j][0] = Uc[jj];
+        Vn[j][1] = nx ? nx * ux : ny * uy;
+        Vn[j][2] = nx ? uy : ux;
+        Vn[j][3] = Uc[3 * qp + jj];
+    }
+    const double rho = Vn[3][0], un = Vn[3][1], T = Vn[3][3], c = sqrt(2.0 * T);
+    const double lam[4] = {un - c, un, un, un + c};
+    // LODI amplitudes of the outgoing normal characteristics, from x_b, x_b - n, x_b - 2n
+    double wn[3][4];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        int jj = k == 0 ? t : fidx(R, x - k * nx, y - k * ny);
+        if (jj < 0) jj = t;
+        const double ux = Uc[qp + jj], uy = Uc[2 * qp + jj];
+        const double v[4] = {Uc[jj], nx ? nx * ux : ny * uy, nx ? uy : ux, Uc[3 * qp + jj]};
+        char_fwd(rho, T, c, v, wn[k]);
+    }
+    // transverse part at the node and its edge neighbours; viscous part of the advected states
+    double dVT[4], dm[4], dp[4];
+    edge_advect<2>(Vn, dm);
+    edge_advect<3>(Vn, dVT);
+    edge_advect<4>(Vn, dp);
+    double dVV[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!(topen && (ct == 0 || ct == nt - 1))) {
+        const double nuv = (1.0 / R.omega - 0.5) * (1.0 / LAT_R2);
+#pragma unroll
+        for (int m = 1; m < 4; ++m) {
+            const double a0 = Vn[2][m] + dm[m], a1 = Vn[3][m] + dVT[m], a2 = Vn[4][m] + dp[m];
+            dVV[m] = (m == 3 ? 2.0 * nuv : nuv) * (a2 - 2.0 * a1 + a0);
+        }
+    }
+    double aT[4], aV[4];
+    char_fwd(rho, T, c, dVT, aT);
+    char_fwd(rho, T, c, dVV, aV);
+    const double ma = sqrt(R.b0);
+    double dw[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (lam[k] > 0.0) {
+            const double nu = fmin(lam[k] * (1.0 / LAT_R), 2.0);
+            const bool far = nu >= 1.0;
+            const double phi = far ? nu - 1.0 : nu;
+            const double wa = far ? wn[1][k] : wn[0][k], wb = far ? wn[2][k] : wn[1][k];
+            const double D = (1.0 - phi) * (wn[0][k] - wa) + phi * (wn[0][k] - wb);
+            dw[k] = -D + aT[k] + aV[k];
+        } else {
+            dw[k] = ma * aT[k];
+        }
+    }
+    double d[4];
+    char_inv(rho, T, c, dw, d);
+    Ut[0] += d[0];
+    Ut[3] += d[3];
+    if (nx) { Ut[1] += nx * d[1]; Ut[2] += d[2]; }
+    else    { Ut[2] += ny * d[1]; Ut[1] += d[2]; }
+}
+
 // Non-equilibrium extrapolation: g <- feq(U_tgt) + g(x_f) - feq(U(x_f)), in float64.  g holds the
 // pulled populations of x_f (deviation form) on entry.
 template <class C>
@@ -568,8 +703,9 @@ __device__ __forceinline__ void pml_moments(CRun &R, int x, int y, int t, const 
 __device__ __forceinline__ int ring_blocks(CRun &R) { return (R.ring_n + RING_BLOCK - 1) / RING_BLOCK; }
 
 // Characteristic targets of the ring, formed ahead of phase A for runs that select the appendix's
-// PML moments: U_tgt = U^n(x_b) plus the LODI increment of each NRBC side the node lies on
-// (corners add both normals) plus the PML moments; stored to P (4 planes of the ring numbering,
+// PML moments or have a CBC (A) side: U_tgt = U^n(x_b) plus, for each characteristic side the
+// node lies on, the CBC (A) increment (a node on that side only) or the LODI increment (corners
+// add both normals), plus the PML moments; stored to P (4 planes of the ring numbering,
 // float64).
 template <class S>
 __global__ __launch_bounds__(256) void k_target(RunDev *const *__restrict__ runs,
@@ -589,10 +725,19 @@ __global__ __launch_bounds__(256) void k_target(RunDev *const *__restrict__ runs
     const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par];
     const unsigned qp = (unsigned)R.qplane;
     double Ut[4] = {Uc[t], Uc[qp + t], Uc[2 * qp + t], Uc[3 * qp + t]};
+    // open sides whose boundary layers hold the node: CBC (A) applies on one side only, corners
+    // take the LODI target of each characteristic normal
+    bool on[4];
+    int n_open = 0;
     for (int s = 0; s < 4; ++s) {
-        const bool on = s == XMIN ? x < 3 : s == XMAX ? x >= R.Nx - 3 : s == YMIN ? y < 3 : y >= R.Ny - 3;
-        if (!on) continue;
-        if (R.bc[s] == BC_NRBC) lodi_add(R, Uc, s, x, y, t, Ut);
+        on[s] = s == XMIN ? x < 3 : s == XMAX ? x >= R.Nx - 3 : s == YMIN ? y < 3 : y >= R.Ny - 3;
+        on[s] = on[s] && R.bc[s] != BC_PERIODIC;
+        n_open += on[s];
+    }
+    for (int s = 0; s < 4; ++s) {
+        if (!on[s]) continue;
+        if (R.bc[s] == BC_NRBC_A && n_open == 1) cbc_a_add(R, Uc, s, x, y, t, Ut);
+        else if (is_char_bc(R.bc[s])) lodi_add(R, Uc, s, x, y, t, Ut);
     }
     if (R.pml_terms) {
         double dU[4];
@@ -624,6 +769,7 @@ __device__ __forceinline__ void nrbc_node(CRun &R, int tt, int x, int y, int t, 
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         bool on = s == XMIN ? x < 3 : s == XMAX ? x >= R.Nx - 3 : s == YMIN ? y < 3 : y >= R.Ny - 3;
+        // (runs with a CBC (A) side always form their targets ahead: pre is set)
         if (on && !pre && R.bc[s] == BC_NRBC) lodi_add(R, Uc, s, x, y, t, Ut);
     }
     gather_clamped<S, C>(R, (const GLOBAL S *)R.f[R.par], x, y, inv_scale, g);

@@ -168,8 +168,9 @@ def vortex_outlet_study(steps=2000, sample=20, L=300, W=10, mach=0.1, strength=0
     L x L bulk open on every side, an isentropic vortex (`workloads.add_isentropic_vortex`)
     starting `x_shift` cells downstream of the centre, so it leaves through the +x side.
     configs: (name, outlet kind, other sides' kind, W, sigma_max); default: ZG and the perfectly
-    non-reflecting LODI everywhere (the paper's scheme B), each with and without a PML (the
-    paper's sigma_max for W = 10).
+    non-reflecting LODI everywhere (the paper's scheme B), and CBC (A) at the outlet with LODI
+    on the other sides (the paper's setup), each with and without a PML (the paper's sigma_max
+    for W = 10).
     Reference: the same data on a fully periodic grid extended by 1.3 steps + 32 cells on every
     side.  Returns rows with ebar_rho, ebar_ux, ebar_T and C_Z against ZG without PML."""
     from paper_2504_20169_amd import lbm
@@ -177,7 +178,8 @@ def vortex_outlet_study(steps=2000, sample=20, L=300, W=10, mach=0.1, strength=0
 
     if configs is None:
         configs = [("zg", "zg", "zg", 0, 0.0), ("zg+pml", "zg", "zg", W, 0.02),
-                   ("B", "nrbc", "nrbc", 0, 0.0), ("B+pml", "nrbc", "nrbc", W, 0.007)]
+                   ("B", "nrbc", "nrbc", 0, 0.0), ("B+pml", "nrbc", "nrbc", W, 0.007),
+                   ("A", "nrbc_a", "nrbc", 0, 0.0), ("A+pml", "nrbc_a", "nrbc", W, 0.007)]
 
     def fields(N, off):
         F = wl.uniform_state(N, N, 1.0, mach, 0.0, 1.0)

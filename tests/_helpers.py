@@ -31,7 +31,7 @@ def make_pair(oracle_mod, Lx, Ly, tau=0.8, mean=(1.0, 0.0, 0.0, 1.0), bc=None, p
     o = oracle_mod.OracleRun(Lx, Ly, tau, rho0, ux0, uy0, T0, lattice=lattice)
     g = lbm.Run(Lx, Ly, tau, rho0, ux0, uy0, T0, storage=storage, stream=stream,
                 allocator=allocator, lattice=lattice) if gpu else None
-    kinds = {"periodic": 0, "zg": 1, "nrbc": 2}
+    kinds = {"periodic": 0, "zg": 1, "nrbc": 2, "nrbc_a": 3}
     if bc is not None:
         items = bc.items() if isinstance(bc, dict) else [(s, bc) for s in SIDES]
         for side, kind in items:
