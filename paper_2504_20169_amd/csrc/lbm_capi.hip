@@ -362,14 +362,15 @@ hipEvent_t take_event(lbm_run *h) {
     return e;
 }
 
-// One step of a launch set.  Dependencies: phase A (characteristic fill of the ring, Q update)
-// before the frame kernel (grad Q reads neighbours' Q of the new level); the bulk kernel depends
-// on neither; the flip waits for everything.  With a side stream the boundary chain runs beside
-// the bulk kernel.  Profiling (`prof` non-null): mode 1 runs the classes in order on one stream
-// with HIP events bracketing the bulk kernel (class 0), the frame kernel (class 1) and phase A
-// (class 2); mode 2 keeps the normal schedule and brackets the bulk kernel alone, on its stream.
-lbm_status enqueue_step(const LaunchSet &L, int storage, int tx, hipStream_t s, StepStreams *ss,
-                        lbm_run *prof) {
+// Sub-step ks of a batch of steps of a launch set.  Dependencies: the characteristic targets and
+// phase A (characteristic fill of the ring, Q update) before the frame kernel (grad Q reads
+// neighbours' Q of the new level); the bulk kernel depends on neither; the next sub-step waits
+// for everything.  With a side stream the boundary chain runs beside the bulk kernel.
+// Profiling (`prof` non-null): mode 1 runs the classes in order on one stream with HIP events
+// bracketing the bulk kernel (class 0), the frame kernel (class 1) and phase A (class 2); mode 2
+// keeps the normal schedule and brackets the bulk kernel alone, on its stream.
+lbm_status enqueue_substep(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s,
+                           StepStreams *ss, lbm_run *prof) {
     const bool has_a = L.blocks[CLS_A] > 0;
     const bool has_f = L.blocks[CLS_FRAME] > 0;
     const bool has_b = L.blocks[CLS_BULK] > 0;
@@ -382,28 +383,27 @@ lbm_status enqueue_step(const LaunchSet &L, int storage, int tx, hipStream_t s, 
     const bool classes = mode == 1;
     if (!ss || !ss->ok || classes) {
         if (classes && has_a) HIP_TRY(hipEventRecord(ev[4], s));
-        HIP_TRY(L.ks->target(L, storage, s));
-        HIP_TRY(L.ks->phase_a(L, storage, s));
+        HIP_TRY(L.ks->target(L, storage, ks, s));
+        HIP_TRY(L.ks->phase_a(L, storage, ks, s));
         if (classes && has_a) HIP_TRY(hipEventRecord(ev[5], s));
         if (classes && has_f) HIP_TRY(hipEventRecord(ev[2], s));
-        HIP_TRY(L.ks->frame(L, storage, s));
+        HIP_TRY(L.ks->frame(L, storage, ks, s));
         if (classes && has_f) HIP_TRY(hipEventRecord(ev[3], s));
         if (mode && has_b) HIP_TRY(hipEventRecord(ev[0], s));
-        HIP_TRY(L.ks->bulk(L, storage, tx, s));
+        HIP_TRY(L.ks->bulk(L, storage, tx, ks, s));
         if (mode && has_b) HIP_TRY(hipEventRecord(ev[1], s));
     } else {
         HIP_TRY(hipEventRecord(ss->fork, s));
         HIP_TRY(hipStreamWaitEvent(ss->side, ss->fork, 0));
-        HIP_TRY(L.ks->target(L, storage, ss->side));
-        HIP_TRY(L.ks->phase_a(L, storage, ss->side));
-        HIP_TRY(L.ks->frame(L, storage, ss->side));
+        HIP_TRY(L.ks->target(L, storage, ks, ss->side));
+        HIP_TRY(L.ks->phase_a(L, storage, ks, ss->side));
+        HIP_TRY(L.ks->frame(L, storage, ks, ss->side));
         HIP_TRY(hipEventRecord(ss->done, ss->side));
         if (mode && has_b) HIP_TRY(hipEventRecord(ev[0], s));
-        HIP_TRY(L.ks->bulk(L, storage, tx, s));
+        HIP_TRY(L.ks->bulk(L, storage, tx, ks, s));
         if (mode && has_b) HIP_TRY(hipEventRecord(ev[1], s));
         HIP_TRY(hipStreamWaitEvent(s, ss->done, 0));
     }
-    HIP_TRY(L.ks->flip(L, s));
     if (mode) {
         const bool used[3] = {has_b, classes && has_f, classes && has_a};
         for (int c = 0; c < 3; ++c) {
@@ -413,6 +413,21 @@ lbm_status enqueue_step(const LaunchSet &L, int storage, int tx, hipStream_t s, 
     }
     return LBM_OK;
 }
+
+// A batch of nb sub-steps, then one launch that advances every run's step counter and buffer
+// parity by the sub-steps it was active for.
+lbm_status enqueue_batch(const LaunchSet &L, int storage, int tx, int nb, hipStream_t s,
+                         StepStreams *ss, lbm_run *prof) {
+    for (int ks = 0; ks < nb; ++ks) {
+        lbm_status st = enqueue_substep(L, storage, tx, ks, s, ss, prof);
+        if (st != LBM_OK) return st;
+    }
+    HIP_TRY(L.ks->advance(L, nb, s));
+    return LBM_OK;
+}
+
+// Sub-steps per eager batch when graphs are off.
+constexpr int EAGER_BATCH = 32;
 
 void drop_graph(lbm_run *h) {
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
@@ -428,8 +443,7 @@ hipGraphExec_t capture_steps(const LaunchSet &L, int storage, int tx, hipStream_
         (void)hipGetLastError();
         return nullptr;
     }
-    lbm_status st = LBM_OK;
-    for (int k = 0; k < G && st == LBM_OK; ++k) st = enqueue_step(L, storage, tx, s, nullptr, nullptr);
+    lbm_status st = enqueue_batch(L, storage, tx, G, s, nullptr, nullptr);
     hipError_t e = hipStreamEndCapture(s, &g);
     if (st != LBM_OK || e != hipSuccess || !g) {
         (void)hipGetLastError();
@@ -713,10 +727,13 @@ lbm_status lbm_step(lbm_handle h, int64_t n) {
             }
         }
     }
-    for (int64_t k = 0; k < left; ++k) {
-        lbm_status st = enqueue_step(L, h->desc.storage, h->launch.bulk_tx, h->stream,
-                                     overlap ? &h->ss : nullptr, h->prof ? h : nullptr);
+    const int B = G > 0 ? G : EAGER_BATCH;
+    while (left > 0) {
+        const int nb = (int)std::min<int64_t>(left, B);
+        lbm_status st = enqueue_batch(L, h->desc.storage, h->launch.bulk_tx, nb, h->stream,
+                                      overlap ? &h->ss : nullptr, h->prof ? h : nullptr);
         if (st != LBM_OK) return st;
+        left -= nb;
     }
     h->steps += n;
     return LBM_OK;
@@ -1196,9 +1213,12 @@ lbm_status lbm_group_step(lbm_group_handle g, const int64_t *steps, int64_t nste
             for (; left >= G; left -= G) HIP_TRY(hipGraphLaunch(g->graph, g->stream));
         }
     }
-    for (; left > 0; --left) {
-        lbm_status st = enqueue_step(L, g->storage, g->launch.bulk_tx, g->stream, nullptr, nullptr);
+    const int B = G > 0 ? G : EAGER_BATCH;
+    while (left > 0) {
+        const int nb = (int)std::min<int64_t>(left, B);
+        lbm_status st = enqueue_batch(L, g->storage, g->launch.bulk_tx, nb, g->stream, nullptr, nullptr);
         if (st != LBM_OK) return st;
+        left -= nb;
     }
     for (size_t k = 0; k < n; ++k) g->members[k]->steps += steps ? steps[k] : nsteps;
     return LBM_OK;

@@ -84,11 +84,13 @@ constexpr int RING_BLOCK = 64;
 // of every frame node, ring included; target: characteristic targets with the PML moments.
 struct KernelSet {
     int q;
-    hipError_t (*phase_a)(const LaunchSet &L, int storage, hipStream_t s);
-    hipError_t (*frame)(const LaunchSet &L, int storage, hipStream_t s);
-    hipError_t (*target)(const LaunchSet &L, int storage, hipStream_t s);
-    hipError_t (*bulk)(const LaunchSet &L, int storage, int tx, hipStream_t s);
-    hipError_t (*flip)(const LaunchSet &L, hipStream_t s);
+    // step kernels of sub-step ks of a batch (parity par + ks; active while step + ks < limit)
+    hipError_t (*phase_a)(const LaunchSet &L, int storage, int ks, hipStream_t s);
+    hipError_t (*frame)(const LaunchSet &L, int storage, int ks, hipStream_t s);
+    hipError_t (*target)(const LaunchSet &L, int storage, int ks, hipStream_t s);
+    hipError_t (*bulk)(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s);
+    // end of a batch of n sub-steps: step counters and parities advance
+    hipError_t (*advance)(const LaunchSet &L, int n, hipStream_t s);
     hipError_t (*set_limit)(RunDev *run, long long limit, hipStream_t s);
     hipError_t (*set_limits)(RunDev *const *runs, const long long *limits, int n, hipStream_t s);
     hipError_t (*init)(RunDev *run, int storage, int Nx, int Ny, const double *rho,

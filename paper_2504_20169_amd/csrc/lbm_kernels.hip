@@ -10,7 +10,8 @@
 //                  moments, U^{n+1} strip write, BGK + Omega^PML      (eqs. PMLCOLL, zg-bc,
 //                  PNR / thermal_LODI_macro_evo)
 //   k_bulk         interior nodes: branch-free pull + moments + BGK             (eq. lbe)
-//   k_flip         swap the population and moment-strip buffers of active runs
+//   k_advance      end of a batch of steps: advance the step counters and buffer parities
+//                  (the step kernels of sub-step k of a batch use parity par + k)
 // NR = true instances cover only the 3-deep ring of characteristic-boundary nodes (FP64 LODI
 // fill); NR = false instances skip those nodes and carry none of that code, which keeps their
 // register budget low.  The collision is a per-node projection streaming 2 x q values
@@ -146,6 +147,14 @@ __device__ __forceinline__ int find_run(const int *prefix, int nruns, int b) {
 
 __device__ __forceinline__ CRun &run_of(RunDev *const *runs, int j) {
     return *(CRun *)(((RunDev *const CONSTANT *)runs)[j]);
+}
+
+// Steps are launched in batches: sub-step k of a batch sees the run k steps past its descriptor's
+// step counter, whose buffer parity is then par + k, and works only while that stays below the
+// run's limit.  k_advance moves the counters at the end of the batch.  Returns the parity, or -1
+// for a run that is no longer active at sub-step k.
+__device__ __forceinline__ int sub_par(CRun &R, int k) {
+    return R.step + k < R.limit ? ((R.par + k) & 1) : -1;
 }
 
 // Strip numbering of a frame of depths (dxm, dxp, dym, dyp): bottom strip, top strip, left
@@ -709,12 +718,13 @@ __device__ __forceinline__ int ring_blocks(CRun &R) { return (R.ring_n + RING_BL
 // float64).
 template <class S>
 __global__ __launch_bounds__(256) void k_target(RunDev *const *__restrict__ runs,
-                                                const int *__restrict__ prefix, int nruns) {
+                                                const int *__restrict__ prefix, int nruns, int ks) {
     using C = typename Traits<S>::C;
     const int b = blockIdx.x;
     const int j = find_run(prefix, nruns, b);
     CRun &R = run_of(runs, j);
-    if (R.step >= R.limit || !R.tgt_pre) return;
+    const int par = sub_par(R, ks);
+    if (par < 0 || !R.tgt_pre) return;
     if ((int)threadIdx.x >= RING_BLOCK) return;
     const int tt = (b - ((const CONSTANT int *)prefix)[j]) * RING_BLOCK + (int)threadIdx.x;
     if (tt >= R.ring_n) return;
@@ -722,7 +732,7 @@ __global__ __launch_bounds__(256) void k_target(RunDev *const *__restrict__ runs
     ring_xy(R, tt, x, y);
     const int t = fidx(R, x, y);
     if (t < 0) return;
-    const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par];
+    const GLOBAL double *Uc = (const GLOBAL double *)R.U[par];
     const unsigned qp = (unsigned)R.qplane;
     double Ut[4] = {Uc[t], Uc[qp + t], Uc[2 * qp + t], Uc[3 * qp + t]};
     // open sides whose boundary layers hold the node: CBC (A) applies on one side only, corners
@@ -756,9 +766,9 @@ __global__ __launch_bounds__(256) void k_target(RunDev *const *__restrict__ runs
 // extrapolation.  The result is left in g and stored to G (ring index tt), where the frame
 // kernel and the moment export read it.
 template <class S, class C>
-__device__ __forceinline__ void nrbc_node(CRun &R, int tt, int x, int y, int t, C inv_scale,
+__device__ __forceinline__ void nrbc_node(CRun &R, int par, int tt, int x, int y, int t, C inv_scale,
                                           C (&g)[NQ]) {
-    const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par];
+    const GLOBAL double *Uc = (const GLOBAL double *)R.U[par];
     const unsigned qp = (unsigned)R.qplane;
     // the target: U^n(x_b) plus the LODI increments, or, for runs that select the appendix's PML
     // moments, the whole target formed by k_target in ring numbering
@@ -772,7 +782,7 @@ __device__ __forceinline__ void nrbc_node(CRun &R, int tt, int x, int y, int t, 
         // (runs with a CBC (A) side always form their targets ahead: pre is set)
         if (on && !pre && R.bc[s] == BC_NRBC) lodi_add(R, Uc, s, x, y, t, Ut);
     }
-    gather_clamped<S, C>(R, (const GLOBAL S *)R.f[R.par], x, y, inv_scale, g);
+    gather_clamped<S, C>(R, (const GLOBAL S *)R.f[par], x, y, inv_scale, g);
     nrbc_fill<C>(R, Ut, g);
     GLOBAL C *G = (GLOBAL C *)R.G;
     const unsigned rp = (unsigned)R.rplane;
@@ -785,22 +795,23 @@ __device__ __forceinline__ void nrbc_node(CRun &R, int tt, int x, int y, int t, 
 // ------------------------------------------------------------------------------------------
 template <class S, int TX>
 __global__ __launch_bounds__(256) void k_bulk(RunDev *const *__restrict__ runs,
-                                              const int *__restrict__ prefix, int nruns) {
+                                              const int *__restrict__ prefix, int nruns, int ks) {
     using C = typename Traits<S>::C;
     constexpr int TY = 256 / TX;
     constexpr int TI = TX == 64 ? 0 : (TX == 128 ? 1 : 2);
     const int b = xcd_swizzle(blockIdx.x, gridDim.x);
     const int j = find_run(prefix, nruns, b);
     CRun &R = run_of(runs, j);
-    if (R.step >= R.limit) return;
+    const int par = sub_par(R, ks);
+    if (par < 0) return;
     const int tb = b - ((const CONSTANT int *)prefix)[j];
     const int ty = tb / R.tiles_x[TI], tx = tb - ty * R.tiles_x[TI];
     const int x = (R.fx0 / TX) * TX + tx * TX + (int)(threadIdx.x % TX);
     const int y = R.fy0 + ty * TY + (int)(threadIdx.x / TX);
     if (x < R.fx0 || x >= R.fx1 || y >= R.fy1) return;
     const K<C> k = load_k<C>(R);
-    const GLOBAL S *src = (const GLOBAL S *)R.f[R.par];
-    GLOBAL S *dst = (GLOBAL S *)R.f[R.par ^ 1];
+    const GLOBAL S *src = (const GLOBAL S *)R.f[par];
+    GLOBAL S *dst = (GLOBAL S *)R.f[par ^ 1];
     const long long plane = R.plane;
     const int pitch = R.pitch;
     // uniform base at the tile's first row; per-lane 32-bit byte offset inside the tile
@@ -897,12 +908,13 @@ __device__ __forceinline__ void frame_collide(CRun &R, const K<C> &k, const C (&
 // axes) and skip ring nodes.
 template <class S>
 __global__ __launch_bounds__(256) void k_frame(RunDev *const *__restrict__ runs,
-                                               const int *__restrict__ prefix, int nruns) {
+                                               const int *__restrict__ prefix, int nruns, int ks) {
     using C = typename Traits<S>::C;
     const int b = blockIdx.x;
     const int j = find_run(prefix, nruns, b);
     CRun &R = run_of(runs, j);
-    if (R.step >= R.limit) return;
+    const int par = sub_par(R, ks);
+    if (par < 0) return;
     const int tb = b - ((const CONSTANT int *)prefix)[j];
     const int rb = ring_blocks(R);
     const K<C> k = load_k<C>(R);
@@ -925,18 +937,18 @@ __global__ __launch_bounds__(256) void k_frame(RunDev *const *__restrict__ runs,
         frame_xy(R, tt, x, y);
         if (in_ring(R, x, y)) return;
         t = tt;
-        gather_clamped<S, C>(R, (const GLOBAL S *)R.f[R.par], x, y, k.inv_scale, g);
+        gather_clamped<S, C>(R, (const GLOBAL S *)R.f[par], x, y, k.inv_scale, g);
     }
     frame_collide<S, C>(R, k, g, x, y, t, (const GLOBAL C *)R.Q,
-                        (GLOBAL S *)R.f[R.par ^ 1] + (long long)y * R.pitch + x,
-                        (GLOBAL double *)R.U[R.par ^ 1]);
+                        (GLOBAL S *)R.f[par ^ 1] + (long long)y * R.pitch + x,
+                        (GLOBAL double *)R.U[par ^ 1]);
 }
 
 // PML auxiliary update Q += (fhat^n + fhat^{n+1}) / 2 at frame node t (eq. PMLQ, trapezoid rule),
 // fhat^n from the moment strip of the last level, fhat^{n+1} from g.  Loads before stores.
 template <class C>
-__device__ __forceinline__ void q_update(CRun &R, const K<C> &k, const C (&g)[NQ], int t) {
-    const GLOBAL double *Uc = (const GLOBAL double *)R.U[R.par];
+__device__ __forceinline__ void q_update(CRun &R, int par, const K<C> &k, const C (&g)[NQ], int t) {
+    const GLOBAL double *Uc = (const GLOBAL double *)R.U[par];
     const unsigned qp = (unsigned)R.qplane;
     GLOBAL C *Q = (GLOBAL C *)R.Q;
     const double r0 = Uc[t], ux0 = Uc[qp + t], uy0 = Uc[2 * qp + t], T0 = Uc[3 * qp + t];
@@ -960,12 +972,13 @@ __device__ __forceinline__ void q_update(CRun &R, const K<C> &k, const C (&g)[NQ
 // nodes, update Q from it; frame blocks update Q of the PML nodes off the ring from their pull.
 template <class S>
 __global__ __launch_bounds__(256) void k_phase_a(RunDev *const *__restrict__ runs,
-                                                 const int *__restrict__ prefix, int nruns) {
+                                                 const int *__restrict__ prefix, int nruns, int ks) {
     using C = typename Traits<S>::C;
     const int b = blockIdx.x;
     const int j = find_run(prefix, nruns, b);
     CRun &R = run_of(runs, j);
-    if (R.step >= R.limit) return;
+    const int par = sub_par(R, ks);
+    if (par < 0) return;
     const int tb = b - ((const CONSTANT int *)prefix)[j];
     const int rb = ring_blocks(R);
     const K<C> k = load_k<C>(R);
@@ -978,7 +991,7 @@ __global__ __launch_bounds__(256) void k_phase_a(RunDev *const *__restrict__ run
         ring_xy(R, tt, x, y);
         t = fidx(R, x, y);
         if (t < 0) return;
-        nrbc_node<S, C>(R, tt, x, y, t, k.inv_scale, g);
+        nrbc_node<S, C>(R, par, tt, x, y, t, k.inv_scale, g);
         if (!R.has_q || !in_q(R, x, y)) return;
         // Re-read the filled populations from G (this thread's own stores): the memory clobber
         // ends g's live range at the fill, so the fill and the Q update use the register file
@@ -994,19 +1007,21 @@ __global__ __launch_bounds__(256) void k_phase_a(RunDev *const *__restrict__ run
         frame_xy(R, tt, x, y);
         if (in_ring(R, x, y) || !in_q(R, x, y)) return;
         t = tt;
-        gather_clamped<S, C>(R, (const GLOBAL S *)R.f[R.par], x, y, k.inv_scale, g);
+        gather_clamped<S, C>(R, (const GLOBAL S *)R.f[par], x, y, k.inv_scale, g);
     }
-    q_update<C>(R, k, g, t);
+    q_update<C>(R, par, k, g, t);
 }
 
-__global__ void k_flip(RunDev *const *runs, int nruns) {
+// End of a batch of n steps: each run advances by the sub-steps it was active for, min(n,
+// limit - step), and its buffer parity by the same count.
+__global__ void k_advance(RunDev *const *runs, int nruns, int n) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nruns) return;
     RunDev *R = runs[j];
-    if (R->step < R->limit) {
-        R->par ^= 1;
-        R->step += 1;
-    }
+    long long a = R->limit - R->step;
+    a = a < 0 ? 0 : (a > n ? n : a);
+    R->step += a;
+    R->par ^= (int)(a & 1);
 }
 
 __global__ void k_set_limit(RunDev *run, long long limit) {
@@ -1204,47 +1219,47 @@ __global__ __launch_bounds__(256) void k_err_final(const double *partials, int n
 
 static inline int blocks_for(long long n) { return (int)((n + 255) / 256); }
 
-static hipError_t launch_phase_a(const LaunchSet &L, int storage, hipStream_t s) {
+static hipError_t launch_phase_a(const LaunchSet &L, int storage, int ks, hipStream_t s) {
     if (L.blocks[CLS_A] > 0)
         LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a<S>), dim3(L.blocks[CLS_A]), dim3(256), 0, s,
-                                                 L.runs, L.prefix[CLS_A], L.nruns));
+                                                 L.runs, L.prefix[CLS_A], L.nruns, ks));
     return hipGetLastError();
 }
 
-static hipError_t launch_target(const LaunchSet &L, int storage, hipStream_t s) {
+static hipError_t launch_target(const LaunchSet &L, int storage, int ks, hipStream_t s) {
     if (L.blocks[CLS_TGT] > 0)
         LBM_DISPATCH(storage, hipLaunchKernelGGL((k_target<S>), dim3(L.blocks[CLS_TGT]), dim3(256), 0, s,
-                                                 L.runs, L.prefix[CLS_TGT], L.nruns));
+                                                 L.runs, L.prefix[CLS_TGT], L.nruns, ks));
     return hipGetLastError();
 }
 
-static hipError_t launch_frame(const LaunchSet &L, int storage, hipStream_t s) {
+static hipError_t launch_frame(const LaunchSet &L, int storage, int ks, hipStream_t s) {
     if (L.blocks[CLS_FRAME] > 0)
         LBM_DISPATCH(storage, hipLaunchKernelGGL((k_frame<S>), dim3(L.blocks[CLS_FRAME]), dim3(256), 0, s,
-                                                 L.runs, L.prefix[CLS_FRAME], L.nruns));
+                                                 L.runs, L.prefix[CLS_FRAME], L.nruns, ks));
     return hipGetLastError();
 }
 
-static hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, hipStream_t s) {
+static hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s) {
     const int nb = L.blocks[CLS_BULK];
     if (nb <= 0) return hipSuccess;
     const int *pre = L.prefix[CLS_BULK];
     switch (tx) {
     case 64:
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 64>), dim3(nb), dim3(256), 0, s, L.runs, pre, L.nruns));
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 64>), dim3(nb), dim3(256), 0, s, L.runs, pre, L.nruns, ks));
         break;
     case 128:
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 128>), dim3(nb), dim3(256), 0, s, L.runs, pre, L.nruns));
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 128>), dim3(nb), dim3(256), 0, s, L.runs, pre, L.nruns, ks));
         break;
     default:
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 256>), dim3(nb), dim3(256), 0, s, L.runs, pre, L.nruns));
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 256>), dim3(nb), dim3(256), 0, s, L.runs, pre, L.nruns, ks));
         break;
     }
     return hipGetLastError();
 }
 
-static hipError_t launch_flip(const LaunchSet &L, hipStream_t s) {
-    hipLaunchKernelGGL(k_flip, dim3((L.nruns + 255) / 256), dim3(256), 0, s, L.runs, L.nruns);
+static hipError_t launch_advance(const LaunchSet &L, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance, dim3((L.nruns + 255) / 256), dim3(256), 0, s, L.runs, L.nruns, n);
     return hipGetLastError();
 }
 
@@ -1313,7 +1328,7 @@ static hipError_t launch_err_final(const double *partials, int nrows, double *ou
 // host-side table (the device pass has no host functions to point at)
 #ifndef __HIP_DEVICE_COMPILE__
 const KernelSet kernels = {NQ, launch_phase_a, launch_frame, launch_target, launch_bulk,
-                           launch_flip, launch_set_limit, launch_set_limits, launch_init,
+                           launch_advance, launch_set_limit, launch_set_limits, launch_init,
                            launch_moments, launch_export_f, launch_export_q, launch_check,
                            launch_err_rows, launch_err_final};
 #endif
