@@ -304,8 +304,8 @@ size_t footprint_of(const RunDev &R, int storage, int nq) {
 void compute_blocks(const RunDev &R, int tx, int nb[NCLS]) {
     int k = tx_index(tx);
     nb[CLS_BULK] = R.tiles_x[k] * R.tiles_y[k];
-    const int fb = (R.frame_n + FRAME_BLOCK - 1) / FRAME_BLOCK;
-    const int rb = (R.ring_n + RING_BLOCK - 1) / RING_BLOCK;
+    const int fb = frame_block_count(R.frame_n);
+    const int rb = ring_block_count(R.ring_n);
     nb[CLS_FRAME] = rb + fb;
     nb[CLS_A] = rb + (R.has_q ? fb : 0);
     nb[CLS_TGT] = R.tgt_pre ? rb : 0;

@@ -78,6 +78,17 @@ constexpr int FRAME_BLOCK = 256;
 // different compute units instead of sharing one unit's memory pipeline four at a time.
 constexpr int RING_BLOCK = 64;
 
+// Blocks of a run in the boundary launches: ring blocks, then frame blocks, each count rounded up
+// to a multiple of 8.  Blocks are dealt round-robin to the 8 XCDs, so every run's frame blocks
+// then start on the first XCD and can be remapped XCD by XCD (neighbouring strip rows, which
+// share pulled rows and Q planes, on one XCD and its L2); the padding blocks exit at once.
+__host__ __device__ inline int ring_block_count(int ring_n) {
+    return ((ring_n + RING_BLOCK - 1) / RING_BLOCK + 7) & ~7;
+}
+__host__ __device__ inline int frame_block_count(int frame_n) {
+    return ((frame_n + FRAME_BLOCK - 1) / FRAME_BLOCK + 7) & ~7;
+}
+
 // Kernel launchers of one velocity stencil (lbm_kernels.hip, compiled once per stencil).  All
 // enqueue on `s` and return the HIP status of the launch.
 // phase_a: characteristic fill of the ring and PML auxiliary update; frame: phase B (collision)

@@ -708,8 +708,12 @@ __device__ __forceinline__ void pml_moments(CRun &R, int x, int y, int t, const 
 }
 
 // Blocks of a run's boundary launches: the characteristic ring first (ring numbering, RING_BLOCK
-// nodes per block), then the frame (frame numbering, FRAME_BLOCK nodes per block).
-__device__ __forceinline__ int ring_blocks(CRun &R) { return (R.ring_n + RING_BLOCK - 1) / RING_BLOCK; }
+// nodes per block), then the frame (frame numbering, FRAME_BLOCK nodes per block), both counts
+// padded to multiples of 8.  frame_start maps a frame block to its first frame index, XCD by XCD.
+__device__ __forceinline__ int ring_blocks(CRun &R) { return ring_block_count(R.ring_n); }
+__device__ __forceinline__ int frame_start(CRun &R, int fblock) {
+    return xcd_swizzle(fblock, frame_block_count(R.frame_n)) * FRAME_BLOCK;
+}
 
 // Characteristic targets of the ring, formed ahead of phase A for runs that select the appendix's
 // PML moments or have a CBC (A) side: U_tgt = U^n(x_b) plus, for each characteristic side the
@@ -932,7 +936,7 @@ __global__ __launch_bounds__(256) void k_frame(RunDev *const *__restrict__ runs,
 #pragma unroll
         for (int i = 0; i < NQ; ++i) g[i] = G[i * rp + tt];
     } else {
-        const int tt = (tb - rb) * FRAME_BLOCK + (int)threadIdx.x;
+        const int tt = frame_start(R, tb - rb) + (int)threadIdx.x;
         if (tt >= R.frame_n) return;
         frame_xy(R, tt, x, y);
         if (in_ring(R, x, y)) return;
@@ -1002,7 +1006,7 @@ __global__ __launch_bounds__(256) void k_phase_a(RunDev *const *__restrict__ run
 #pragma unroll
         for (int i = 0; i < NQ; ++i) g[i] = G[i * rp + tt];
     } else {
-        const int tt = (tb - rb) * FRAME_BLOCK + (int)threadIdx.x;
+        const int tt = frame_start(R, tb - rb) + (int)threadIdx.x;
         if (!R.has_q || tt >= R.frame_n) return;
         frame_xy(R, tt, x, y);
         if (in_ring(R, x, y) || !in_q(R, x, y)) return;
