@@ -107,7 +107,8 @@ typedef struct {
 
 /* Launch configuration (set by lbm_set_launch or lbm_autotune).  bulk_tx in {64,128,256}
  * nodes along x, bulk_ty rows per block with bulk_tx*bulk_ty = 256; graph_steps: steps per
- * captured HIP graph in lbm_step (even, 0 disables graphs); overlap: 0 (default) runs the
+ * captured HIP graph in lbm_step (even, 0 disables graphs; steps are also launched eagerly in
+ * batches of this many, 32 when 0, each closed by one bookkeeping launch); overlap: 0 (default) runs the
  * kernels of a step in order on the run's stream, 1 runs the boundary/PML chain on a side
  * stream beside the bulk kernel (only for a run that owns its stream; eager launches, no
  * graphs).  Default {64, 4, 32, 0}. */

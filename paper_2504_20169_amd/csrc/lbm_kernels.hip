@@ -4,17 +4,22 @@
 //
 // Every kernel takes an array of run descriptors, so one launch advances one run or a batch of
 // uneven runs.  Per step:
-//   k_phase_a<NR>  PML Q-region nodes: pull + boundary + moments -> U^{n+1};
+//   k_target       (runs with the appendix's PML moments or a CBC (A) side) float64
+//                  characteristic targets of the ring
+//   k_phase_a      ring blocks: float64 characteristic fill of the 3-deep ring of
+//                  characteristic-boundary nodes into G (eqs. PNR / thermal_LODI_macro_evo);
+//                  then for the PML Q-region nodes: pull (ring: G) + moments,
 //                  Q^{n+1} = Q^n + (fhat^n + fhat^{n+1})/2                      (eq. PMLQ)
-//   k_frame<NR>    frame nodes (boundary layers, PML, moment strips): pull + boundary fill +
-//                  moments, U^{n+1} strip write, BGK + Omega^PML      (eqs. PMLCOLL, zg-bc,
-//                  PNR / thermal_LODI_macro_evo)
+//   k_frame        frame nodes (boundary layers, PML, moment strips): pull (ring nodes: G) +
+//                  ZG copy, moments, U^{n+1} strip write, BGK + Omega^PML
+//                                                             (eqs. PMLCOLL, zg-bc)
 //   k_bulk         interior nodes: branch-free pull + moments + BGK             (eq. lbe)
 //   k_advance      end of a batch of steps: advance the step counters and buffer parities
 //                  (the step kernels of sub-step k of a batch use parity par + k)
-// NR = true instances cover only the 3-deep ring of characteristic-boundary nodes (FP64 LODI
-// fill); NR = false instances skip those nodes and carry none of that code, which keeps their
-// register budget low.  The collision is a per-node projection streaming 2 x q values
+// The ring blocks come first in their launches (their float64 chains are the longest) and are
+// block-uniform, so they never share a wave with frame nodes.  (A separate ring launch lowers
+// phase A's registers but measured slower: the ring's latency then adds instead of overlapping.)
+// The collision is a per-node projection streaming 2 x q values
 // through HBM: no MFMA.  Pulls are coalesced row segments shifted by e_i (each source value is
 // read exactly once); descriptors are read through the constant address space (scalar
 // loads) and populations through global pointers with one 32-bit byte offset per lane.
