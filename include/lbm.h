@@ -219,9 +219,13 @@ lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path,
  * run's stream and events bracket each class: ms[0] bulk, ms[1] boundary/PML frame (phase B),
  * ms[2] phase A (characteristic fill of the ring and PML auxiliary update).  mode 2: the
  * schedule lbm_launch.overlap selects, with events bracketing the bulk kernel alone, on the
- * stream it runs on; only ms[0] and launches[0] accumulate.  mode 0 turns timing off.  Any mode other than 0 makes lbm_step
- * launch eagerly (no graphs); a mode outside 0..2 is LBM_ERR_ARG.  lbm_profile_read
- * synchronises and returns the summed milliseconds and launch counts since the last reset. */
+ * stream it runs on; only ms[0] and launches[0] accumulate.  mode 3: as mode 2, but only the
+ * bulk launch of the first step of each batch of steps (one step in lbm_launch.graph_steps, in
+ * 32 when that is 0) is bracketed: a sampled average that leaves the other steps free of
+ * events, which cost a few microseconds per bracketed launch.  mode 0 turns timing off.  Any
+ * mode other than 0 makes lbm_step launch eagerly (no graphs; the same kernel sequence); a mode
+ * outside 0..3 is LBM_ERR_ARG.  lbm_profile_read synchronises and returns the summed
+ * milliseconds and launch counts since the last reset. */
 lbm_status lbm_profile(lbm_handle h, int enable);
 lbm_status lbm_profile_read(lbm_handle h, double ms[3], int64_t launches[3], int reset);
 

@@ -117,7 +117,8 @@ struct lbm_run {
     int graph_G = 0;
     int graph_tx = 0;
     bool graph_failed = false;
-    int prof = 0;                     // 0 off, 1 classes in order, 2 bulk kernel in the normal schedule
+    int prof = 0;                     // 0 off, 1 classes in order, 2 bulk kernel in the normal schedule,
+                                      // 3 as 2 on the first step of each batch only
     struct Ev { hipEvent_t a, b; int cls; };
     std::vector<Ev> pending;
     std::vector<hipEvent_t> pool;
@@ -374,7 +375,9 @@ lbm_status enqueue_substep(const LaunchSet &L, int storage, int tx, int ks, hipS
     const bool has_a = L.blocks[CLS_A] > 0;
     const bool has_f = L.blocks[CLS_FRAME] > 0;
     const bool has_b = L.blocks[CLS_BULK] > 0;
-    const int mode = prof ? prof->prof : 0;
+    // mode 3 samples mode 2 on the first sub-step of each batch only
+    const int pm = prof ? prof->prof : 0;
+    const int mode = pm == 3 ? (ks == 0 ? 2 : 0) : pm;
     hipEvent_t ev[6] = {};
     if (mode) {
         harvest_events(prof, false);
@@ -872,7 +875,7 @@ lbm_status lbm_get_launch(lbm_handle h, lbm_launch *cfg) {
 
 lbm_status lbm_profile(lbm_handle h, int enable) {
     if (!h) return fail(LBM_ERR_ARG, "NULL handle");
-    if (enable < 0 || enable > 2) return fail(LBM_ERR_ARG, "profile mode must be 0, 1 or 2");
+    if (enable < 0 || enable > 3) return fail(LBM_ERR_ARG, "profile mode must be 0, 1, 2 or 3");
     h->prof = enable;
     return LBM_OK;
 }

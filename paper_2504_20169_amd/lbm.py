@@ -320,7 +320,7 @@ class Run:
 
     def profile(self, mode=1):
         """Event timing: 1 (or True) kernel classes in order, 2 bulk kernel in the normal
-        schedule, 0 (or False) off."""
+        schedule, 3 as 2 on the first step of each batch only, 0 (or False) off."""
         _check(self._lib.lbm_profile(self.h, int(mode)))
 
     def profile_read(self, reset=False):

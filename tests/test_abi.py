@@ -94,7 +94,8 @@ def test_launch_configuration_validated_on_host():
     r.set_nrbc_pml_terms(5)
     assert r.get_launch() == dict(bulk_tx=256, bulk_ty=1, graph_steps=0, overlap=1)
     with pytest.raises(lbm.LbmError):
-        r.profile(3)
+        r.profile(4)
+    r.profile(3)
     r.profile(2)
     r.profile(0)
 

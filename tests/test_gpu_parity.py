@@ -140,10 +140,10 @@ def test_tile_shapes_graphs_and_overlap_bitwise_identical():
 
 
 def test_profile_modes_count_launches_and_keep_bits():
-    """Event timing in either mode changes the launch schedule, never the result."""
+    """Event timing in any mode changes the launch schedule, never the result."""
     F = wl.noisy_state(150, 140, 3, 1.0, 0.05, 0.0, 1.0)
     outs = []
-    for mode, ov in ((0, 0), (1, 0), (2, 0), (2, 1)):
+    for mode, ov in ((0, 0), (1, 0), (2, 0), (2, 1), (3, 0)):
         r = lbm.Run(134, 124, 0.8, 1.0, 0.05, 0.0, 1.0)
         r.set_bc(15, "nrbc")
         r.set_pml(15, 8, 0.05)
@@ -152,11 +152,12 @@ def test_profile_modes_count_launches_and_keep_bits():
         r.profile(mode)
         r.step(23)
         ms, n = r.profile_read(reset=True)
-        expect = {0: [0, 0, 0], 1: [23, 23, 23], 2: [23, 0, 0]}[mode]
+        # mode 3: first step of each batch of 8 (batches of 8, 8 and 7 steps)
+        expect = {0: [0, 0, 0], 1: [23, 23, 23], 2: [23, 0, 0], 3: [3, 0, 0]}[mode]
         assert list(n) == expect, (mode, n)
         assert all(m > 0 for m, c in zip(ms, n) if c)
         with pytest.raises(lbm.LbmError):
-            r.profile(3)
+            r.profile(4)
         outs.append(r.populations())
         r.close()
     for o in outs[1:]:
