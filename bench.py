@@ -208,7 +208,7 @@ def batch_leg(torch, lbm, wl, args):
 KERNEL_SRC = [os.path.join(ROOT, "paper_2504_20169_amd", "csrc", n)
               for n in ("lbm_kernels.hip", "lbm_capi.hip", "lbm_internal.h", "lbm_lattice.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bulk_f64_1088sq_nrbc_pmc.txt")
-BULK_F64 = "void lbm::k37::k_bulk<double, 64>(lbm::RunDev* const*, int const*, int)"
+BULK_F64 = "void lbm::k37::k_bulk<double, 64>(lbm::RunDev* const*, int const*, int, int)"
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
