@@ -79,6 +79,30 @@ def test_setters_validate_and_grid():
     assert ei.value.status == lbm.LBM_ERR_STATE
 
 
+@pytest.mark.parametrize("q", [37, 17])
+def test_cbc_a_kind_and_footprint(q):
+    """CBC (A) is boundary kind 3; another kind is refused.  Its targets are formed ahead of the
+    fill, so a run with a CBC (A) side holds four float64 target planes of the ring more than the
+    same run with the LODI boundary."""
+    def run(kind):
+        r = lbm.Run(40, 30, 0.8, lattice=q)
+        r.set_bc(lbm.LBM_ALL, "nrbc")
+        r.set_bc(lbm.LBM_XMAX, kind)
+        return r
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Run(40, 30, 0.8, lattice=q).set_bc(lbm.LBM_XMAX, 4)
+    assert ei.value.status == lbm.LBM_ERR_ARG
+    a, b = run("nrbc_a"), run("nrbc")
+    assert a.grid() == b.grid() == (40, 30)
+    ring = 2 * 3 * 40 + (30 - 6) * 2 * 3                  # 3 layers on every side
+    rplane = (ring + 63) // 64 * 64
+    assert a.footprint() - b.footprint() == 4 * rplane * 8
+    # the stencil sets the population count of every buffer
+    c = lbm.Run(40, 30, 0.8, lattice=37 if q == 17 else 17)
+    c.set_bc(lbm.LBM_ALL, "nrbc")
+    assert (c.footprint() > b.footprint()) == (q == 17)
+
+
 def test_launch_configuration_validated_on_host():
     r = lbm.Run(20, 10, 0.8)
     assert r.get_launch() == dict(bulk_tx=64, bulk_ty=4, graph_steps=32, overlap=0)
