@@ -9,7 +9,7 @@ quarter; FP64 storage is the headline line, FP32 and FP16 deviation storage are 
 it, and the same workloads run again on the D2Q17 stencil.  Inputs are synthetic and resident in
 HBM before timing starts.
 
-Prints ONE JSON line.  --gpus N > 1 exits with a message: this build runs on one GPU.
+Prints ONE JSON line.  --gpus N > 1 exits with a message: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -370,7 +370,7 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+        print("bench.py: the library runs on one GPU only (no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

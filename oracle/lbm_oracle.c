@@ -36,7 +36,7 @@
 #include <string.h>
 #include <omp.h>
 
-/* Velocity stencil of this build: ORC_Q = 37 (default) or 17, one shared library each. */
+/* Velocity stencil of this compilation: ORC_Q = 37 (default) or 17, one shared library each. */
 #ifndef ORC_Q
 #define ORC_Q 37
 #endif
