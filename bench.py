@@ -44,7 +44,7 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_from_spec(lbm, spec, storage, stream=None, alloc=None, layout=0, bulk_tx=64, overlap=0):
+def run_from_spec(lbm, spec, storage, stream=None, alloc=None, layout=0, bulk_tx=64, overlap=2):
     r = lbm.Run(spec.Lx, spec.Ly, spec.tau, spec.rho0, spec.ux0, spec.uy0, spec.T0, storage=storage,
                 stream=stream, allocator=alloc, layout=layout, lattice=spec.lattice)
     r.set_launch(bulk_tx=bulk_tx, overlap=overlap)
@@ -58,7 +58,8 @@ def run_from_spec(lbm, spec, storage, stream=None, alloc=None, layout=0, bulk_tx
 def time_run(torch, r, steps, warmup, mode):
     """Time `steps` steps after `warmup`.  mode 3: the configured schedule with HIP events around
     the bulk launch of the first step of every batch of 32 (a sampled average; events around
-    every launch would add a few microseconds to each step).  mode 2: events around every bulk
+    every launch would add a few microseconds to each step; in the fused schedule that step
+    launches phase A and the bulk kernel apart, the others launch them as one grid).  mode 2: events around every bulk
     launch.  mode 1: the kernel classes in order, events around each class."""
     r.profile(0)
     r.step(warmup)
@@ -88,8 +89,8 @@ def serve_trace(jobs, rate, scale, storage, tick):
 
 
 def measure(torch, lbm, r, spec, storage, steps, warmup, prof_steps):
-    """Timed pass (HIP events around every bulk launch) and, if prof_steps, an in-order pass
-    with per-class events.  Returns the result dict of one run."""
+    """Timed pass (the configured schedule, HIP events around a sample of bulk launches) and, if
+    prof_steps, an in-order pass with per-class events.  Returns the result dict of one run."""
     Nx, Ny = r.grid()
     n_bulk, n_frame, n_q = r.node_classes()
     dt, ms_live, n_live = time_run(torch, r, steps, warmup, mode=3)
@@ -332,8 +333,9 @@ def main():
     ap.add_argument("--storages", default="f64,f32,f16")
     ap.add_argument("--layout", type=int, default=0, help="0: row-interleaved, 1: plane per velocity")
     ap.add_argument("--bulk-tx", type=int, default=64, help="bulk tile width (64, 128 or 256)")
-    ap.add_argument("--overlap", type=int, default=0,
-                    help="1: boundary/PML chain on a side stream beside the bulk kernel")
+    ap.add_argument("--overlap", type=int, default=2,
+                    help="0: kernels in order; 1: boundary/PML chain on a side stream beside the "
+                         "bulk kernel; 2: phase A fused with the bulk tiles in one grid")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--prof-steps", type=int, default=500,
@@ -469,8 +471,11 @@ def main():
             "frac_of_device_copy": round(R["bulk_kernel_gbs"] / copy_gbs, 4)
             if copy_gbs and R["bulk_kernel_gbs"] else None,
             "timing": "HIP events around the k_bulk launch of the first step of every batch of 32 "
-                      "(%d launches) on its stream inside the timed %d steps"
-                      % (R["bulk_launches_timed"], args.steps),
+                      "(%d launches) on its stream inside the timed %d steps%s"
+                      % (R["bulk_launches_timed"], args.steps,
+                         "; that step launches phase A and k_bulk apart, the other steps run the "
+                         "same bulk tiles in one grid with phase A (k_phase_a_bulk)"
+                         if args.overlap == 2 else ""),
         },
         "variants": {},
     }

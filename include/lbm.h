@@ -108,10 +108,13 @@ typedef struct {
 /* Launch configuration (set by lbm_set_launch or lbm_autotune).  bulk_tx in {64,128,256}
  * nodes along x, bulk_ty rows per block with bulk_tx*bulk_ty = 256; graph_steps: steps per
  * captured HIP graph in lbm_step (even, 0 disables graphs; steps are also launched eagerly in
- * batches of this many, 32 when 0, each closed by one bookkeeping launch); overlap: 0 (default) runs the
- * kernels of a step in order on the run's stream, 1 runs the boundary/PML chain on a side
- * stream beside the bulk kernel (only for a run that owns its stream; eager launches, no
- * graphs).  Default {64, 4, 32, 0}. */
+ * batches of this many, 32 when 0, each closed by one bookkeeping launch); overlap: how the
+ * boundary/PML work of a step meets the bulk kernel: 0 runs the kernels of a step in order on
+ * the run's stream; 1 runs the boundary/PML chain on a side stream beside the bulk kernel (only
+ * for a run that owns its stream; eager launches, no graphs); 2 launches phase A (characteristic
+ * fill of the ring, PML Q update) and the bulk tiles as one grid, phase-A blocks first, so they
+ * run beside the streaming tiles (one stream, graphs and groups allowed).  All three give the
+ * same bits.  Default {64, 4, 32, 2}. */
 typedef struct {
     int32_t bulk_tx, bulk_ty;
     int32_t graph_steps;
@@ -219,7 +222,8 @@ lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path,
  * run's stream and events bracket each class: ms[0] bulk, ms[1] boundary/PML frame (phase B),
  * ms[2] phase A (characteristic fill of the ring and PML auxiliary update).  mode 2: the
  * schedule lbm_launch.overlap selects, with events bracketing the bulk kernel alone, on the
- * stream it runs on; only ms[0] and launches[0] accumulate.  mode 3: as mode 2, but only the
+ * stream it runs on (the fused schedule launches phase A and the bulk kernel apart in bracketed
+ * steps); only ms[0] and launches[0] accumulate.  mode 3: as mode 2, but only the
  * bulk launch of the first step of each batch of steps (one step in lbm_launch.graph_steps, in
  * 32 when that is 0) is bracketed: a sampled average that leaves the other steps free of
  * events, which cost a few microseconds per bracketed launch.  mode 0 turns timing off.  Any
@@ -254,8 +258,8 @@ lbm_status lbm_group_step(lbm_group_handle g, const int64_t *steps, int64_t nste
 /* Launch configuration of the group's batched steps: bulk_tx/bulk_ty as for a run; with
  * graph_steps = G > 0, lbm_group_step replays a captured HIP graph of G batched steps (runs
  * past their own count skip every kernel, so one graph serves any mix of counts) and launches
- * the remainder eagerly; the graph is recaptured after the membership changes.  overlap must
- * be 0.  Default {64, 4, 32, 0}.  LBM_ERR_ARG for unsupported values. */
+ * the remainder eagerly; the graph is recaptured after the membership changes.  overlap 0 or 2
+ * (a group runs on one stream).  Default {64, 4, 32, 2}.  LBM_ERR_ARG for unsupported values. */
 lbm_status lbm_group_set_launch(lbm_group_handle g, const lbm_launch *cfg);
 lbm_status lbm_group_get_launch(lbm_group_handle g, lbm_launch *cfg);
 /* Time every bulk tile shape on a scratch group that holds one scratch run (mean state) per

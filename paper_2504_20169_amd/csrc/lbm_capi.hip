@@ -110,12 +110,13 @@ struct lbm_run {
     double *fbar_d = nullptr;
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;     // stream in use (the group's while in a group)
-    lbm_launch launch{64, 4, 32, 0};
+    lbm_launch launch{64, 4, 32, 2};
     int64_t steps = 0;
     DeviceMem mem;
     hipGraphExec_t graph = nullptr;
     int graph_G = 0;
     int graph_tx = 0;
+    int graph_ov = 0;
     bool graph_failed = false;
     int prof = 0;                     // 0 off, 1 classes in order, 2 bulk kernel in the normal schedule,
                                       // 3 as 2 on the first step of each batch only
@@ -138,7 +139,7 @@ struct lbm_group {
     bool dirty = true;
     int storage = -1;
     const KernelSet *ks = nullptr;    // stencil of the members (set by the first member)
-    lbm_launch launch{64, 4, 32, 0};
+    lbm_launch launch{64, 4, 32, 2};
     hipGraphExec_t graph = nullptr;   // graph_G batched steps of the current membership
     int graph_G = 0;
     bool graph_failed = false;
@@ -366,12 +367,14 @@ hipEvent_t take_event(lbm_run *h) {
 // Sub-step ks of a batch of steps of a launch set.  Dependencies: the characteristic targets and
 // phase A (characteristic fill of the ring, Q update) before the frame kernel (grad Q reads
 // neighbours' Q of the new level); the bulk kernel depends on neither; the next sub-step waits
-// for everything.  With a side stream the boundary chain runs beside the bulk kernel.
+// for everything.  With a side stream the boundary chain runs beside the bulk kernel; `fused`
+// launches phase A and the bulk tiles as one grid, so the latency-bound boundary blocks run
+// beside the streaming tiles on one stream (and in graphs).
 // Profiling (`prof` non-null): mode 1 runs the classes in order on one stream with HIP events
 // bracketing the bulk kernel (class 0), the frame kernel (class 1) and phase A (class 2); mode 2
-// keeps the normal schedule and brackets the bulk kernel alone, on its stream.
+// launches the bulk kernel on its own (no fusion) and brackets it alone, on its stream.
 lbm_status enqueue_substep(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s,
-                           StepStreams *ss, lbm_run *prof) {
+                           StepStreams *ss, bool fused, lbm_run *prof) {
     const bool has_a = L.blocks[CLS_A] > 0;
     const bool has_f = L.blocks[CLS_FRAME] > 0;
     const bool has_b = L.blocks[CLS_BULK] > 0;
@@ -384,7 +387,11 @@ lbm_status enqueue_substep(const LaunchSet &L, int storage, int tx, int ks, hipS
         for (int k = 0; k < 6; ++k) ev[k] = take_event(prof);
     }
     const bool classes = mode == 1;
-    if (!ss || !ss->ok || classes) {
+    if (fused && !mode && (!ss || !ss->ok)) {
+        HIP_TRY(L.ks->target(L, storage, ks, s));
+        HIP_TRY(L.ks->phase_a_bulk(L, storage, tx, ks, s));
+        HIP_TRY(L.ks->frame(L, storage, ks, s));
+    } else if (!ss || !ss->ok || classes) {
         if (classes && has_a) HIP_TRY(hipEventRecord(ev[4], s));
         HIP_TRY(L.ks->target(L, storage, ks, s));
         HIP_TRY(L.ks->phase_a(L, storage, ks, s));
@@ -420,9 +427,9 @@ lbm_status enqueue_substep(const LaunchSet &L, int storage, int tx, int ks, hipS
 // A batch of nb sub-steps, then one launch that advances every run's step counter and buffer
 // parity by the sub-steps it was active for.
 lbm_status enqueue_batch(const LaunchSet &L, int storage, int tx, int nb, hipStream_t s,
-                         StepStreams *ss, lbm_run *prof) {
+                         StepStreams *ss, bool fused, lbm_run *prof) {
     for (int ks = 0; ks < nb; ++ks) {
-        lbm_status st = enqueue_substep(L, storage, tx, ks, s, ss, prof);
+        lbm_status st = enqueue_substep(L, storage, tx, ks, s, ss, fused, prof);
         if (st != LBM_OK) return st;
     }
     HIP_TRY(L.ks->advance(L, nb, s));
@@ -440,13 +447,13 @@ void drop_graph(lbm_run *h) {
 
 // Capture G in-order steps of a launch set on stream s into an executable graph; nullptr if the
 // runtime refuses (the caller then launches eagerly).
-hipGraphExec_t capture_steps(const LaunchSet &L, int storage, int tx, hipStream_t s, int G) {
+hipGraphExec_t capture_steps(const LaunchSet &L, int storage, int tx, bool fused, hipStream_t s, int G) {
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipGetLastError();
         return nullptr;
     }
-    lbm_status st = enqueue_batch(L, storage, tx, G, s, nullptr, nullptr);
+    lbm_status st = enqueue_batch(L, storage, tx, G, s, nullptr, fused, nullptr);
     hipError_t e = hipStreamEndCapture(s, &g);
     if (st != LBM_OK || e != hipSuccess || !g) {
         (void)hipGetLastError();
@@ -465,13 +472,15 @@ hipGraphExec_t capture_steps(const LaunchSet &L, int storage, int tx, hipStream_
 
 lbm_status build_graph(lbm_run *h, int G) {
     drop_graph(h);
-    h->graph = capture_steps(single_set(h), h->desc.storage, h->launch.bulk_tx, h->stream, G);
+    h->graph = capture_steps(single_set(h), h->desc.storage, h->launch.bulk_tx, h->launch.overlap == 2,
+                             h->stream, G);
     if (!h->graph) {
         h->graph_failed = true;
         return LBM_OK;
     }
     h->graph_G = G;
     h->graph_tx = h->launch.bulk_tx;
+    h->graph_ov = h->launch.overlap;
     return LBM_OK;
 }
 
@@ -716,10 +725,12 @@ lbm_status lbm_step(lbm_handle h, int64_t n) {
     const int G = h->launch.graph_steps;
     // Overlapped steps launch eagerly (stream capture stays single-stream); in-order steps
     // replay captured graphs of G steps.  The side stream is created on first use.
-    if (h->launch.overlap && !h->desc.stream && !h->ss.ok) HIP_TRY(h->ss.create());
-    const bool overlap = h->launch.overlap && h->ss.ok;
+    if (h->launch.overlap == 1 && !h->desc.stream && !h->ss.ok) HIP_TRY(h->ss.create());
+    const bool overlap = h->launch.overlap == 1 && h->ss.ok;
+    const bool fused = h->launch.overlap == 2;
     if (!h->prof && !overlap && G > 0 && !h->graph_failed && n >= G) {
-        if (!h->graph || h->graph_G != G || h->graph_tx != h->launch.bulk_tx) {
+        if (!h->graph || h->graph_G != G || h->graph_tx != h->launch.bulk_tx ||
+            h->graph_ov != h->launch.overlap) {
             lbm_status st = build_graph(h, G);
             if (st != LBM_OK) return st;
         }
@@ -734,7 +745,7 @@ lbm_status lbm_step(lbm_handle h, int64_t n) {
     while (left > 0) {
         const int nb = (int)std::min<int64_t>(left, B);
         lbm_status st = enqueue_batch(L, h->desc.storage, h->launch.bulk_tx, nb, h->stream,
-                                      overlap ? &h->ss : nullptr, h->prof ? h : nullptr);
+                                      overlap ? &h->ss : nullptr, fused, h->prof ? h : nullptr);
         if (st != LBM_OK) return st;
         left -= nb;
     }
@@ -860,7 +871,7 @@ lbm_status lbm_set_launch(lbm_handle h, const lbm_launch *cfg) {
         cfg->bulk_tx * cfg->bulk_ty != 256)
         return fail(LBM_ERR_ARG, "bulk tile must be 64x4, 128x2 or 256x1");
     if (cfg->graph_steps < 0 || (cfg->graph_steps & 1)) return fail(LBM_ERR_ARG, "graph_steps must be even and >= 0");
-    if (cfg->overlap != 0 && cfg->overlap != 1) return fail(LBM_ERR_ARG, "overlap must be 0 or 1");
+    if (cfg->overlap < 0 || cfg->overlap > 2) return fail(LBM_ERR_ARG, "overlap must be 0, 1 or 2");
     if (h->group) return fail(LBM_ERR_STATE, "run is in a group");
     h->launch = *cfg;
     if (h->inited) return upload_prefix(h);
@@ -1037,8 +1048,8 @@ lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path, lbm
     hipEvent_t a = nullptr, b = nullptr;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
-    const int nov = d.stream ? 1 : 2;   // overlap needs a stream the run owns
-    for (int ov = 0; ov < nov; ++ov) {
+    for (int ov = 0; ov < 3; ++ov) {
+        if (ov == 1 && d.stream) continue;   // the side stream needs a stream the run owns
         for (int tx : {64, 128, 256}) {
             lbm_launch c{tx, 256 / tx, 0, ov};
             if (lbm_set_launch(s, &c) != LBM_OK) continue;
@@ -1208,7 +1219,7 @@ lbm_status lbm_group_step(lbm_group_handle g, const int64_t *steps, int64_t nste
     if (G > 0 && !g->graph_failed && K >= G) {
         if (!g->graph || g->graph_G != G) {
             group_drop_graph(g);
-            g->graph = capture_steps(L, g->storage, g->launch.bulk_tx, g->stream, G);
+            g->graph = capture_steps(L, g->storage, g->launch.bulk_tx, g->launch.overlap == 2, g->stream, G);
             if (g->graph) g->graph_G = G;
             else g->graph_failed = true;
         }
@@ -1219,7 +1230,8 @@ lbm_status lbm_group_step(lbm_group_handle g, const int64_t *steps, int64_t nste
     const int B = G > 0 ? G : EAGER_BATCH;
     while (left > 0) {
         const int nb = (int)std::min<int64_t>(left, B);
-        lbm_status st = enqueue_batch(L, g->storage, g->launch.bulk_tx, nb, g->stream, nullptr, nullptr);
+        lbm_status st = enqueue_batch(L, g->storage, g->launch.bulk_tx, nb, g->stream, nullptr,
+                                      g->launch.overlap == 2, nullptr);
         if (st != LBM_OK) return st;
         left -= nb;
     }
@@ -1233,7 +1245,8 @@ lbm_status lbm_group_set_launch(lbm_group_handle g, const lbm_launch *cfg) {
         cfg->bulk_tx * cfg->bulk_ty != 256)
         return fail(LBM_ERR_ARG, "bulk tile must be 64x4, 128x2 or 256x1");
     if (cfg->graph_steps < 0 || (cfg->graph_steps & 1)) return fail(LBM_ERR_ARG, "graph_steps must be even and >= 0");
-    if (cfg->overlap != 0) return fail(LBM_ERR_ARG, "groups run their kernels in order (overlap 0)");
+    if (cfg->overlap != 0 && cfg->overlap != 2)
+        return fail(LBM_ERR_ARG, "groups run on one stream (overlap 0 or 2)");
     HIP_TRY(hipStreamSynchronize(g->stream));
     g->launch = *cfg;
     g->graph_failed = false;
@@ -1283,9 +1296,10 @@ lbm_status lbm_group_autotune(lbm_group_handle g, int32_t steps, lbm_launch *cho
         hipEvent_t a = nullptr, b = nullptr;
         (void)hipEventCreate(&a);
         (void)hipEventCreate(&b);
-        for (int tx : {64, 128, 256}) {
+        for (int k = 0; k < 6; ++k) {
             if (st != LBM_OK) break;
-            lbm_launch c{tx, 256 / tx, 0, 0};
+            const int tx = 64 << (k % 3), ov = k < 3 ? 0 : 2;
+            lbm_launch c{tx, 256 / tx, 0, ov};
             if ((st = lbm_group_set_launch(sg, &c)) != LBM_OK) break;
             if ((st = lbm_group_step(sg, nullptr, 2)) != LBM_OK) break;
             (void)hipEventRecord(a, g->stream);
@@ -1294,7 +1308,10 @@ lbm_status lbm_group_autotune(lbm_group_handle g, int32_t steps, lbm_launch *cho
             (void)hipEventSynchronize(b);
             float ms = 0.0f;
             (void)hipEventElapsedTime(&ms, a, b);
-            if (ms < best) { best = ms; best_c = g->launch; best_c.bulk_tx = tx; best_c.bulk_ty = 256 / tx; }
+            if (ms < best) {
+                best = ms; best_c = g->launch;
+                best_c.bulk_tx = tx; best_c.bulk_ty = 256 / tx; best_c.overlap = ov;
+            }
         }
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);

@@ -99,6 +99,8 @@ struct KernelSet {
     hipError_t (*phase_a)(const LaunchSet &L, int storage, int ks, hipStream_t s);
     hipError_t (*frame)(const LaunchSet &L, int storage, int ks, hipStream_t s);
     hipError_t (*target)(const LaunchSet &L, int storage, int ks, hipStream_t s);
+    // phase A and the bulk tiles in one launch (phase-A blocks first)
+    hipError_t (*phase_a_bulk)(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s);
     hipError_t (*bulk)(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s);
     // end of a batch of n sub-steps: step counters and parities advance
     hipError_t (*advance)(const LaunchSet &L, int n, hipStream_t s);

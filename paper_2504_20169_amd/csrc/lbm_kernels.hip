@@ -221,34 +221,74 @@ __device__ __forceinline__ double sigma_at(CRun &R, int x, int y) {
 // ------------------------------------------------------------------------------------------
 template <class C> struct Mom { C drho, dux, duy, dT, rho; };
 
+// Moment sums of populations taken pair by pair (pairs in order): s = sum g, j = sum e g,
+// e2 = sum |e|^2 g, then the primitive deviations from them.
+template <class C> struct MomAcc { C s, jx, jy, e2; };
+
 template <class C>
-__device__ __forceinline__ Mom<C> moments(const C (&g)[NQ], const K<C> &k) {
-    C s = g[0], jx = C(0), jy = C(0), e2 = C(0);
-    static_for<0, NPAIR>([&](auto pc) {
-        constexpr int p = decltype(pc)::value;
-        C a = g[1 + 2 * p], b = g[2 + 2 * p];
-        C sp = a + b, dp = a - b;
-        s += sp;
-        if constexpr (PEX[p] == 1) jx += dp;
-        else if constexpr (PEX[p] == -1) jx -= dp;
-        else if constexpr (PEX[p] != 0) jx += C(PEX[p]) * dp;
-        if constexpr (PEY[p] == 1) jy += dp;
-        else if constexpr (PEY[p] == -1) jy -= dp;
-        else if constexpr (PEY[p] != 0) jy += C(PEY[p]) * dp;
-        if constexpr (SHELL_E2[PSH[p]] == 1) e2 += sp;
-        else e2 += C(SHELL_E2[PSH[p]]) * sp;
-    });
+__device__ __forceinline__ MomAcc<C> mom_begin(C g0) { return MomAcc<C>{g0, C(0), C(0), C(0)}; }
+
+template <int p, class C>
+__device__ __forceinline__ void mom_pair(MomAcc<C> &m, C a, C b) {
+    C sp = a + b, dp = a - b;
+    m.s += sp;
+    if constexpr (PEX[p] == 1) m.jx += dp;
+    else if constexpr (PEX[p] == -1) m.jx -= dp;
+    else if constexpr (PEX[p] != 0) m.jx += C(PEX[p]) * dp;
+    if constexpr (PEY[p] == 1) m.jy += dp;
+    else if constexpr (PEY[p] == -1) m.jy -= dp;
+    else if constexpr (PEY[p] != 0) m.jy += C(PEY[p]) * dp;
+    if constexpr (SHELL_E2[PSH[p]] == 1) m.e2 += sp;
+    else m.e2 += C(SHELL_E2[PSH[p]]) * sp;
+}
+
+template <class C>
+__device__ __forceinline__ Mom<C> mom_end(const MomAcc<C> &a, const K<C> &k) {
+    const C s = a.s;
     Mom<C> m;
     m.drho = s;
     m.rho = k.rho0 + s;
     C inv = C(1) / m.rho;
-    C Jx = C(LAT_R) * jx, Jy = C(LAT_R) * jy, E = C(LAT_R2) * e2;
+    C Jx = C(LAT_R) * a.jx, Jy = C(LAT_R) * a.jy, E = C(LAT_R2) * a.e2;
     m.dux = (Jx - s * k.u0x) * inv;
     m.duy = (Jy - s * k.u0y) * inv;
     C t = E - s * k.c2Tb0 - C(2) * m.rho * (k.u0x * m.dux + k.u0y * m.duy) -
           m.rho * (m.dux * m.dux + m.duy * m.duy);
     m.dT = C(0.5) * t * inv;
     return m;
+}
+
+template <class C>
+__device__ __forceinline__ Mom<C> moments(const C (&g)[NQ], const K<C> &k) {
+    MomAcc<C> a = mom_begin<C>(g[0]);
+    static_for<0, NPAIR>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        mom_pair<p>(a, g[1 + 2 * p], g[2 + 2 * p]);
+    });
+    return mom_end<C>(a, k);
+}
+
+// Moments of populations read by get(i) in groups of PC pairs, each group's reads issued
+// together and the groups kept apart, so only one group is held in registers; the same sums
+// in the same order as moments().
+template <int PC, class C, class Get>
+__device__ __forceinline__ Mom<C> moments_streamed(Get &&get, const K<C> &k) {
+    MomAcc<C> a = mom_begin<C>(get(std::integral_constant<int, 0>{}));
+    static_for<0, (NPAIR + PC - 1) / PC>([&](auto cc) {
+        constexpr int P0 = decltype(cc)::value * PC;
+        constexpr int P1 = P0 + PC < NPAIR ? P0 + PC : NPAIR;
+        C v[2 * (P1 - P0)];
+        static_for<0, 2 * (P1 - P0)>([&](auto lc) {
+            constexpr int l = decltype(lc)::value;
+            v[l] = get(std::integral_constant<int, 1 + 2 * P0 + l>{});
+        });
+        static_for<P0, P1>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            mom_pair<p>(a, v[2 * (p - P0)], v[2 * (p - P0) + 1]);
+        });
+        __builtin_amdgcn_sched_barrier(0);
+    });
+    return mom_end<C>(a, k);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -353,6 +393,25 @@ template <class C, class F>
 __device__ __forceinline__ void for_each_feq2(Eq<C> qa, Eq<C> qb, CRun &R, const K<C> &k, F &&emit) {
     emit(std::integral_constant<int, 0>{}, feq_rest<C>(qa, R), feq_rest<C>(qb, R));
     static_for<0, NPAIR>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        if constexpr (p == 0 || PSH[p - 1] != PSH[p]) {
+            eq_shell<C, PSH[p]>(qa);
+            eq_shell<C, PSH[p]>(qb);
+        }
+        C ap, am, bp, bm;
+        eq_pair<C, p>(qa, R, k, ap, am);
+        eq_pair<C, p>(qb, R, k, bp, bm);
+        emit(std::integral_constant<int, 1 + 2 * p>{}, ap, bp);
+        emit(std::integral_constant<int, 2 + 2 * p>{}, am, bm);
+    });
+}
+
+// Pairs [P0, P1) of two equilibria: emit(i, feq_a_i - fbar_i, feq_b_i - fbar_i); the shell
+// coefficients carry over in qa and qb from the pairs before P0 (pairs in order), so a sweep in
+// groups gives the values of for_each_feq2.
+template <int P0, int P1, class C, class F>
+__device__ __forceinline__ void feq2_pairs(Eq<C> &qa, Eq<C> &qb, CRun &R, const K<C> &k, F &&emit) {
+    static_for<P0, P1>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         if constexpr (p == 0 || PSH[p - 1] != PSH[p]) {
             eq_shell<C, PSH[p]>(qa);
@@ -561,50 +620,74 @@ __device__ void cbc_a_add(CRun &R, const GLOBAL double *Uc, int side, int x, int
     else    { Ut[2] += ny * d[1]; Ut[1] += d[2]; }
 }
 
-// Non-equilibrium extrapolation: g <- feq(U_tgt) + g(x_f) - feq(U(x_f)), in float64.  g holds the
-// pulled populations of x_f (deviation form) on entry.
-template <class C>
-__device__ __forceinline__ void nrbc_fill(CRun &R, const double (&Ut)[4], C (&g)[NQ]) {
-    K<double> kd = load_k<double>(R);
-    Mom<double> mf;
-    if constexpr (std::is_same<C, double>::value) {
-        mf = moments<double>(g, kd);
-    } else {
-        double gd[NQ];
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) gd[i] = (double)g[i];
-        mf = moments<double>(gd, kd);
-    }
-    Eq<double> ef = eq_coef<double>(mf.drho, mf.dux, mf.duy, mf.dT, kd);
-    Eq<double> et = eq_coef<double>(Ut[0] - R.rho0, Ut[1] - R.u0x, Ut[2] - R.u0y, Ut[3] - R.T0, kd);
-    for_each_feq2<double>(et, ef, R, kd, [&](auto ic, double ft, double ff) {
-        constexpr int i = decltype(ic)::value;
-        g[i] = (C)((double)g[i] + (ft - ff));
-    });
-}
-
-// Pull of a frame node with the boundary fill: periodic axes wrap, open axes pull at
-// x_f = clamp(x, 3, N-4) (eq. zg-bc copies all q populations of x_f to the boundary node).
 // Pull of x_f = clamp(x, 3, N-4) on open axes (eq. zg-bc copies all q populations of x_f to a
 // boundary node; interior frame nodes are their own x_f), with a single periodic wrap on
-// periodic axes (N >= 3): the 7 source-row and 7 source-column offsets are formed once per
-// node, so each population costs one add.
+// periodic axes (N >= 3): identical shifts across populations fold to 7 source-row and
+// 7 source-column offsets per node, so each population costs one add.
+template <class S, class C, int I>
+__device__ __forceinline__ C pull_one(CRun &R, const GLOBAL S *src, int xs, int ys, C inv_scale) {
+    const int Nx = R.Nx, Ny = R.Ny;
+    int sy = ys - ey_of(I), sx = xs - ex_of(I);
+    if constexpr (ey_of(I) > 0) sy += sy < 0 ? Ny : 0;
+    if constexpr (ey_of(I) < 0) sy -= sy >= Ny ? Ny : 0;
+    if constexpr (ex_of(I) > 0) sx += sx < 0 ? Nx : 0;
+    if constexpr (ex_of(I) < 0) sx -= sx >= Nx ? Nx : 0;
+    return cvt_in(src[(long long)I * R.plane + (long long)sy * R.pitch + sx], inv_scale);
+}
+
+__device__ __forceinline__ int clamp_x(CRun &R, int x) { return R.open_x ? min(max(x, 3), R.Nx - 4) : x; }
+__device__ __forceinline__ int clamp_y(CRun &R, int y) { return R.open_y ? min(max(y, 3), R.Ny - 4) : y; }
+
 template <class S, class C>
 __device__ __forceinline__ void gather_clamped(CRun &R, const GLOBAL S *src, int x, int y,
                                                C inv_scale, C (&g)[NQ]) {
-    const int Nx = R.Nx, Ny = R.Ny;
-    const int xs = R.open_x ? min(max(x, 3), Nx - 4) : x;
-    const int ys = R.open_y ? min(max(y, 3), Ny - 4) : y;
-    const long long pitch = R.pitch, plane = R.plane;
+    const int xs = clamp_x(R, x), ys = clamp_y(R, y);
     static_for<0, NQ>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        // identical shifts across populations fold to 7 row and 7 column offsets per node
-        int sy = ys - ey_of(i), sx = xs - ex_of(i);
-        if constexpr (ey_of(i) > 0) sy += sy < 0 ? Ny : 0;
-        if constexpr (ey_of(i) < 0) sy -= sy >= Ny ? Ny : 0;
-        if constexpr (ex_of(i) > 0) sx += sx < 0 ? Nx : 0;
-        if constexpr (ex_of(i) < 0) sx -= sx >= Nx ? Nx : 0;
-        g[i] = cvt_in(src[(long long)i * plane + sy * pitch + sx], inv_scale);
+        g[i] = pull_one<S, C, i>(R, src, xs, ys, inv_scale);
+    });
+}
+
+// Non-equilibrium extrapolation into G (ring index tt): G <- feq(U_tgt) + g(x_f) - feq(U(x_f)),
+// in float64, g the pulled populations of x_f (deviation form).  Two sweeps keep it in few
+// registers: the moments of the pull first, then the fill a few pairs at a time from a second
+// pull of the same values (cache hits).
+template <class S, class C>
+__device__ __forceinline__ void nrbc_fill(CRun &R, const GLOBAL S *src, int x, int y, C inv_scale,
+                                          const double (&Ut)[4], int tt) {
+    K<double> kd = load_k<double>(R);
+    Mom<double> mf;
+    {
+        const int xs = clamp_x(R, x), ys = clamp_y(R, y);
+        mf = moments_streamed<6, double>(
+            [&](auto ic) { return (double)pull_one<S, C, decltype(ic)::value>(R, src, xs, ys, inv_scale); }, kd);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    Eq<double> ef = eq_coef<double>(mf.drho, mf.dux, mf.duy, mf.dT, kd);
+    Eq<double> et = eq_coef<double>(Ut[0] - R.rho0, Ut[1] - R.u0x, Ut[2] - R.u0y, Ut[3] - R.T0, kd);
+    int xs = clamp_x(R, x), ys = clamp_y(R, y);
+    // recompute the addresses of the second pull instead of keeping those of the first live
+    asm volatile("" : "+v"(xs), "+v"(ys));
+    GLOBAL C *G = (GLOBAL C *)R.G;
+    const unsigned rp = (unsigned)R.rplane;
+    {
+        const C g0 = pull_one<S, C, 0>(R, src, xs, ys, inv_scale);
+        G[tt] = (C)((double)g0 + (feq_rest<double>(et, R) - feq_rest<double>(ef, R)));
+    }
+    constexpr int PC = 3;   // pairs per sweep group
+    static_for<0, (NPAIR + PC - 1) / PC>([&](auto cc) {
+        constexpr int P0 = decltype(cc)::value * PC;
+        constexpr int P1 = P0 + PC < NPAIR ? P0 + PC : NPAIR;
+        C gv[2 * (P1 - P0)];
+        static_for<0, 2 * (P1 - P0)>([&](auto lc) {
+            constexpr int l = decltype(lc)::value;
+            gv[l] = pull_one<S, C, 1 + 2 * P0 + l>(R, src, xs, ys, inv_scale);
+        });
+        feq2_pairs<P0, P1>(et, ef, R, kd, [&](auto ic, double ft, double ff) {
+            constexpr int i = decltype(ic)::value;
+            G[i * rp + tt] = (C)((double)gv[i - 1 - 2 * P0] + (ft - ff));
+        });
+        __builtin_amdgcn_sched_barrier(0);
     });
 }
 
@@ -770,17 +853,14 @@ __global__ __launch_bounds__(256) void k_target(RunDev *const *__restrict__ runs
 }
 
 // Ring node of characteristic sides: U_tgt = U(x_b) of the last completed level plus the LODI
-// increment of each NRBC side the node lies on (corners add both normals) and, if selected, the
-// PML moments of the appendix; then the clamped pull of x_f and the non-equilibrium
-// extrapolation.  The result is left in g and stored to G (ring index tt), where the frame
-// kernel and the moment export read it.
+// increment of each NRBC side the node lies on (corners add both normals) or, for runs that form
+// their targets ahead, the target of k_target; then the clamped pull of x_f and the
+// non-equilibrium extrapolation into G (ring index tt), where the Q update, the frame kernel and
+// the moment export read it.
 template <class S, class C>
-__device__ __forceinline__ void nrbc_node(CRun &R, int par, int tt, int x, int y, int t, C inv_scale,
-                                          C (&g)[NQ]) {
+__device__ __forceinline__ void nrbc_node(CRun &R, int par, int tt, int x, int y, int t, C inv_scale) {
     const GLOBAL double *Uc = (const GLOBAL double *)R.U[par];
     const unsigned qp = (unsigned)R.qplane;
-    // the target: U^n(x_b) plus the LODI increments, or, for runs that select the appendix's PML
-    // moments, the whole target formed by k_target in ring numbering
     const bool pre = R.tgt_pre != 0;
     const GLOBAL double *Ub = pre ? (const GLOBAL double *)R.P : Uc;
     const unsigned ib = pre ? (unsigned)tt : (unsigned)t, sb = pre ? (unsigned)R.rplane : qp;
@@ -791,24 +871,19 @@ __device__ __forceinline__ void nrbc_node(CRun &R, int par, int tt, int x, int y
         // (runs with a CBC (A) side always form their targets ahead: pre is set)
         if (on && !pre && R.bc[s] == BC_NRBC) lodi_add(R, Uc, s, x, y, t, Ut);
     }
-    gather_clamped<S, C>(R, (const GLOBAL S *)R.f[par], x, y, inv_scale, g);
-    nrbc_fill<C>(R, Ut, g);
-    GLOBAL C *G = (GLOBAL C *)R.G;
-    const unsigned rp = (unsigned)R.rplane;
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) G[i * rp + tt] = g[i];
+    nrbc_fill<S, C>(R, (const GLOBAL S *)R.f[par], x, y, inv_scale, Ut, tt);
 }
 
 // ------------------------------------------------------------------------------------------
 // step kernels
 // ------------------------------------------------------------------------------------------
+// Bulk tile b (logical, after the XCD remap) of a launch set.
 template <class S, int TX>
-__global__ __launch_bounds__(256) void k_bulk(RunDev *const *__restrict__ runs,
-                                              const int *__restrict__ prefix, int nruns, int ks) {
+__device__ __forceinline__ void bulk_tile(RunDev *const *__restrict__ runs,
+                                          const int *__restrict__ prefix, int nruns, int ks, int b) {
     using C = typename Traits<S>::C;
     constexpr int TY = 256 / TX;
     constexpr int TI = TX == 64 ? 0 : (TX == 128 ? 1 : 2);
-    const int b = xcd_swizzle(blockIdx.x, gridDim.x);
     const int j = find_run(prefix, nruns, b);
     CRun &R = run_of(runs, j);
     const int par = sub_par(R, ks);
@@ -846,6 +921,12 @@ __global__ __launch_bounds__(256) void k_bulk(RunDev *const *__restrict__ runs,
         else
             *at(dst0 + (long long)i * plane, off) = cvt_out(out, k.scale, (S *)nullptr);
     });
+}
+
+template <class S, int TX>
+__global__ __launch_bounds__(256) void k_bulk(RunDev *const *__restrict__ runs,
+                                              const int *__restrict__ prefix, int nruns, int ks) {
+    bulk_tile<S, TX>(runs, prefix, nruns, ks, xcd_swizzle(blockIdx.x, gridDim.x));
 }
 
 // Collision of a frame node (frame index t) from its post-stream, post-boundary populations g:
@@ -954,36 +1035,50 @@ __global__ __launch_bounds__(256) void k_frame(RunDev *const *__restrict__ runs,
 }
 
 // PML auxiliary update Q += (fhat^n + fhat^{n+1}) / 2 at frame node t (eq. PMLQ, trapezoid rule),
-// fhat^n from the moment strip of the last level, fhat^{n+1} from g.  Loads before stores.
+// fhat^n from the moment strip of the last level, fhat^{n+1} from m, the moments of g^{n+1}.  Q is
+// read a few pairs at a time (each group's reads issued together, the groups kept apart), so the
+// update runs in few registers.
 template <class C>
-__device__ __forceinline__ void q_update(CRun &R, int par, const K<C> &k, const C (&g)[NQ], int t) {
+__device__ __forceinline__ void q_update(CRun &R, int par, const K<C> &k0, const Mom<C> &m, int t) {
+    // the uniform pair terms (e_p . u0 and its square) are formed afresh here: shared with the
+    // ring fill's, they would stay live across it
+    K<C> k = k0;
+    asm volatile("" : "+s"(k.r0x), "+s"(k.r0y));
     const GLOBAL double *Uc = (const GLOBAL double *)R.U[par];
     const unsigned qp = (unsigned)R.qplane;
     GLOBAL C *Q = (GLOBAL C *)R.Q;
     const double r0 = Uc[t], ux0 = Uc[qp + t], uy0 = Uc[2 * qp + t], T0 = Uc[3 * qp + t];
-    Mom<C> m = moments<C>(g, k);
-    // g is dead from here: Q's loads (uniform plane bases, one 32-bit lane offset) take its
-    // registers; the scheduling barrier keeps them from being hoisted above the moments
-    __builtin_amdgcn_sched_barrier(0);
     const unsigned ot = (unsigned)t * (unsigned)sizeof(C);
-    C Qv[NQ];
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) Qv[i] = *at(Q + (long long)i * qp, ot);
     Eq<C> q1 = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
     Eq<C> q0 = eq_coef<C>((C)(r0 - R.rho0), (C)(ux0 - R.u0x), (C)(uy0 - R.u0y), (C)(T0 - R.T0), k);
-    for_each_feq2<C>(q1, q0, R, k, [&](auto ic, C fe1, C fe0) {
-        constexpr int i = decltype(ic)::value;
-        *at(Q + (long long)i * qp, ot) = Qv[i] + C(0.5) * (fe0 + fe1);
+    {
+        const C q = *at(Q, ot);
+        *at(Q, ot) = q + C(0.5) * (feq_rest<C>(q0, R) + feq_rest<C>(q1, R));
+    }
+    constexpr int PC = 4;   // pairs per group of Q reads
+    static_for<0, (NPAIR + PC - 1) / PC>([&](auto cc) {
+        constexpr int P0 = decltype(cc)::value * PC;
+        constexpr int P1 = P0 + PC < NPAIR ? P0 + PC : NPAIR;
+        C Qv[2 * (P1 - P0)];
+        static_for<0, 2 * (P1 - P0)>([&](auto lc) {
+            constexpr int l = decltype(lc)::value;
+            Qv[l] = *at(Q + (long long)(1 + 2 * P0 + l) * qp, ot);
+        });
+        feq2_pairs<P0, P1>(q1, q0, R, k, [&](auto ic, C fe1, C fe0) {
+            constexpr int i = decltype(ic)::value;
+            *at(Q + (long long)i * qp, ot) = Qv[i - 1 - 2 * P0] + C(0.5) * (fe0 + fe1);
+        });
+        __builtin_amdgcn_sched_barrier(0);
     });
 }
 
-// Phase A of a step: ring blocks form the characteristic fill of the ring (into G) and, on PML
-// nodes, update Q from it; frame blocks update Q of the PML nodes off the ring from their pull.
+// Block b of the phase-A class: ring blocks form the characteristic fill of the ring (into G)
+// and, on PML nodes, update Q from it; frame blocks update Q of the PML nodes off the ring from
+// their pull.
 template <class S>
-__global__ __launch_bounds__(256) void k_phase_a(RunDev *const *__restrict__ runs,
-                                                 const int *__restrict__ prefix, int nruns, int ks) {
+__device__ __forceinline__ void phase_a_block(RunDev *const *__restrict__ runs,
+                                              const int *__restrict__ prefix, int nruns, int ks, int b) {
     using C = typename Traits<S>::C;
-    const int b = blockIdx.x;
     const int j = find_run(prefix, nruns, b);
     CRun &R = run_of(runs, j);
     const int par = sub_par(R, ks);
@@ -992,7 +1087,7 @@ __global__ __launch_bounds__(256) void k_phase_a(RunDev *const *__restrict__ run
     const int rb = ring_blocks(R);
     const K<C> k = load_k<C>(R);
     int x, y, t;
-    C g[NQ];
+    Mom<C> m;
     if (tb < rb) {
         if ((int)threadIdx.x >= RING_BLOCK) return;
         const int tt = tb * RING_BLOCK + (int)threadIdx.x;
@@ -1000,25 +1095,49 @@ __global__ __launch_bounds__(256) void k_phase_a(RunDev *const *__restrict__ run
         ring_xy(R, tt, x, y);
         t = fidx(R, x, y);
         if (t < 0) return;
-        nrbc_node<S, C>(R, par, tt, x, y, t, k.inv_scale, g);
+        nrbc_node<S, C>(R, par, tt, x, y, t, k.inv_scale);
         if (!R.has_q || !in_q(R, x, y)) return;
-        // Re-read the filled populations from G (this thread's own stores): the memory clobber
-        // ends g's live range at the fill, so the fill and the Q update use the register file
-        // one after the other instead of together.
-        asm volatile("" ::: "memory");
+        // the moments of the filled populations, read back from G (this thread's own stores);
+        // the opaque index makes the reads form their addresses afresh rather than keep those
+        // of the stores live
+        int tr = tt;
+        asm volatile("" : "+v"(tr) : : "memory");
         const GLOBAL C *G = (const GLOBAL C *)R.G;
         const unsigned rp = (unsigned)R.rplane;
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) g[i] = G[i * rp + tt];
+        m = moments_streamed<6, C>([&](auto ic) { return G[decltype(ic)::value * rp + tr]; }, k);
     } else {
         const int tt = frame_start(R, tb - rb) + (int)threadIdx.x;
         if (!R.has_q || tt >= R.frame_n) return;
         frame_xy(R, tt, x, y);
         if (in_ring(R, x, y) || !in_q(R, x, y)) return;
         t = tt;
+        C g[NQ];
         gather_clamped<S, C>(R, (const GLOBAL S *)R.f[par], x, y, k.inv_scale, g);
+        m = moments<C>(g, k);
     }
-    q_update<C>(R, par, k, g, t);
+    __builtin_amdgcn_sched_barrier(0);
+    q_update<C>(R, par, k, m, t);
+}
+
+// Phase A of a step (eq. PMLQ on the Q region; the characteristic fill of the ring).
+template <class S>
+__global__ __launch_bounds__(256) void k_phase_a(RunDev *const *__restrict__ runs,
+                                                 const int *__restrict__ prefix, int nruns, int ks) {
+    phase_a_block<S>(runs, prefix, nruns, ks, blockIdx.x);
+}
+
+// Phase A and the bulk tiles of a step in one launch: nA phase-A blocks first (their latency-bound
+// waves start first and run beside the streaming bulk tiles), then nB bulk tiles.  nA is a
+// multiple of 8, so the bulk tiles keep their XCD map.  Both paths share one register budget,
+// which the low-register boundary code keeps at the bulk kernel's occupancy.
+template <class S, int TX>
+__global__ __launch_bounds__(256) void k_phase_a_bulk(RunDev *const *__restrict__ runs,
+                                                      const int *__restrict__ preA, int nA,
+                                                      const int *__restrict__ preB, int nB,
+                                                      int nruns, int ks) {
+    const int b = blockIdx.x;
+    if (b < nA) phase_a_block<S>(runs, preA, nruns, ks, b);
+    else bulk_tile<S, TX>(runs, preB, nruns, ks, xcd_swizzle(b - nA, nB));
 }
 
 // End of a batch of n steps: each run advances by the sub-steps it was active for, min(n,
@@ -1267,6 +1386,27 @@ static hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, int ks, h
     return hipGetLastError();
 }
 
+static hipError_t launch_phase_a_bulk(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s) {
+    const int nA = L.blocks[CLS_A], nB = L.blocks[CLS_BULK];
+    if (nA + nB <= 0) return hipSuccess;
+    const int *pa = L.prefix[CLS_A], *pb = L.prefix[CLS_BULK];
+    switch (tx) {
+    case 64:
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a_bulk<S, 64>), dim3(nA + nB), dim3(256), 0, s,
+                                                 L.runs, pa, nA, pb, nB, L.nruns, ks));
+        break;
+    case 128:
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a_bulk<S, 128>), dim3(nA + nB), dim3(256), 0, s,
+                                                 L.runs, pa, nA, pb, nB, L.nruns, ks));
+        break;
+    default:
+        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a_bulk<S, 256>), dim3(nA + nB), dim3(256), 0, s,
+                                                 L.runs, pa, nA, pb, nB, L.nruns, ks));
+        break;
+    }
+    return hipGetLastError();
+}
+
 static hipError_t launch_advance(const LaunchSet &L, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_advance, dim3((L.nruns + 255) / 256), dim3(256), 0, s, L.runs, L.nruns, n);
     return hipGetLastError();
@@ -1336,7 +1476,7 @@ static hipError_t launch_err_final(const double *partials, int nrows, double *ou
 
 // host-side table (the device pass has no host functions to point at)
 #ifndef __HIP_DEVICE_COMPILE__
-const KernelSet kernels = {NQ, launch_phase_a, launch_frame, launch_target, launch_bulk,
+const KernelSet kernels = {NQ, launch_phase_a, launch_frame, launch_target, launch_phase_a_bulk, launch_bulk,
                            launch_advance, launch_set_limit, launch_set_limits, launch_init,
                            launch_moments, launch_export_f, launch_export_q, launch_check,
                            launch_err_rows, launch_err_final};

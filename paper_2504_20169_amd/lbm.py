@@ -301,7 +301,9 @@ class Run:
             _check(st)
         return st
 
-    def set_launch(self, bulk_tx=64, graph_steps=32, overlap=0):
+    def set_launch(self, bulk_tx=64, graph_steps=32, overlap=2):
+        """overlap: 0 kernels in order, 1 boundary/PML chain on a side stream, 2 phase A fused
+        with the bulk tiles in one grid; the same bits in every schedule."""
         c = lbm_launch(int(bulk_tx), 256 // int(bulk_tx), int(graph_steps), int(overlap))
         _check(self._lib.lbm_set_launch(self.h, ctypes.byref(c)))
 
@@ -370,8 +372,10 @@ class Group:
     def synchronize(self):
         _check(self._lib.lbm_group_synchronize(self.g))
 
-    def set_launch(self, bulk_tx=64, graph_steps=32):
-        c = lbm_launch(int(bulk_tx), 256 // int(bulk_tx), int(graph_steps), 0)
+    def set_launch(self, bulk_tx=64, graph_steps=32, overlap=2):
+        """overlap 0 (kernels in order) or 2 (phase A fused with the bulk tiles); a group runs on
+        one stream, so the side-stream schedule (1) is refused."""
+        c = lbm_launch(int(bulk_tx), 256 // int(bulk_tx), int(graph_steps), int(overlap))
         _check(self._lib.lbm_group_set_launch(self.g, ctypes.byref(c)))
 
     def get_launch(self):

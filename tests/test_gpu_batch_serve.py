@@ -52,6 +52,29 @@ def test_batch_equals_alone(storage):
     g.close()
 
 
+@pytest.mark.parametrize("gs", [0, 8])
+def test_batch_fused_schedule_equals_alone(gs):
+    """Phase A fused with the bulk tiles in one grid per step (eager and in graphs), over a batch
+    of uneven runs with and without rings and PMLs: bitwise the runs alone."""
+    alone = []
+    for k, (L, W, bc, n) in enumerate(CASES):
+        r = _make(L, W, bc, "f64", 70 + k)
+        r.step(n)
+        alone.append(r.populations())
+        r.close()
+    g = lbm.Group()
+    runs = [_make(L, W, bc, "f64", 70 + k) for k, (L, W, bc, n) in enumerate(CASES)]
+    for r in runs:
+        g.add(r)
+    g.set_launch(bulk_tx=64, graph_steps=gs, overlap=2)
+    assert g.get_launch()["overlap"] == 2
+    g.step(steps=np.array([c[3] for c in CASES]))
+    g.synchronize()
+    for r, a, c in zip(runs, alone, CASES):
+        assert np.array_equal(r.populations(), a), c
+    g.close()
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_group_graphs_and_autotune_keep_bits(storage):
     """Graph replays of batched steps (uneven counts, membership change in between) and the
@@ -68,8 +91,10 @@ def test_group_graphs_and_autotune_keep_bits(storage):
         g.add(r)
     with pytest.raises(lbm.LbmError):
         g.set_launch(bulk_tx=64, graph_steps=3)
+    with pytest.raises(lbm.LbmError):
+        g.set_launch(bulk_tx=64, graph_steps=4, overlap=1)   # one stream: no side stream
     g.set_launch(bulk_tx=128, graph_steps=4)
-    assert g.get_launch() == dict(bulk_tx=128, bulk_ty=2, graph_steps=4, overlap=0)
+    assert g.get_launch() == dict(bulk_tx=128, bulk_ty=2, graph_steps=4, overlap=2)
     before = [r.populations() for r in runs]
     c = g.autotune(steps=3)
     assert c["bulk_tx"] in (64, 128, 256) and c["graph_steps"] == 4

@@ -94,7 +94,8 @@ def test_cbc_a_launch_options_and_group_keep_bits(storage):
     ref = make(bulk_tx=64, graph_steps=0)
     ref.step(40)
     base = ref.populations()
-    for launch in (dict(bulk_tx=128, graph_steps=8), dict(bulk_tx=256, graph_steps=0, overlap=1)):
+    for launch in (dict(bulk_tx=128, graph_steps=8), dict(bulk_tx=256, graph_steps=0, overlap=1),
+                   dict(bulk_tx=64, graph_steps=8, overlap=2)):
         r = make(**launch)
         r.step(40)
         assert np.array_equal(r.populations(), base), launch

@@ -147,12 +147,13 @@ def test_conservation_on_gpu():
 
 
 def test_launch_options_graphs_and_layouts_keep_bits():
-    """Tile widths, graphs, the side-stream schedule and the plane layout change launches and
-    addresses, never the D2Q17 results."""
+    """Tile widths, graphs, the side-stream and fused schedules and the plane layout change
+    launches and addresses, never the D2Q17 results."""
     F = wl.noisy_state(146, 136, 3, 1.0, 0.05, 0.0, 1.0)
     outs = []
     for kw, launch in [({}, dict(bulk_tx=64, graph_steps=0)), ({}, dict(bulk_tx=128, graph_steps=8)),
                        ({}, dict(bulk_tx=256, graph_steps=0, overlap=1)), (dict(layout=1), dict(bulk_tx=64)),
+                       ({}, dict(bulk_tx=64, graph_steps=0, overlap=2)), ({}, dict(bulk_tx=128, graph_steps=8, overlap=2)),
                        (dict(row_pad=-1), dict(bulk_tx=64))]:
         r = lbm.Run(134, 124, 0.8, 1.0, 0.05, 0.0, 1.0, lattice=Q, **kw)
         r.set_launch(**launch)

@@ -124,10 +124,12 @@ def test_sigma_zero_pml_bitwise_equals_plain(bc, storage):
 
 
 def test_tile_shapes_graphs_and_overlap_bitwise_identical():
-    """Tile shape, graph replay and the overlapped schedule change launches, never bits."""
+    """Tile shape, graph replay and the overlapped schedules (side stream; phase A fused with the
+    bulk tiles) change launches, never bits."""
     F = wl.noisy_state(150, 140, 3, 1.0, 0.05, 0.0, 1.0)
     outs = []
-    for tx, gs, ov in ((64, 0, 0), (128, 8, 0), (256, 32, 0), (64, 32, 0), (64, 0, 1), (256, 8, 1)):
+    for tx, gs, ov in ((64, 0, 0), (128, 8, 0), (256, 32, 0), (64, 32, 0), (64, 0, 1), (256, 8, 1),
+                       (64, 0, 2), (128, 8, 2), (256, 32, 2)):
         r = lbm.Run(134, 124, 0.8, 1.0, 0.05, 0.0, 1.0)
         r.set_bc(15, "nrbc")
         r.set_pml(15, 8, 0.05)
@@ -143,7 +145,7 @@ def test_profile_modes_count_launches_and_keep_bits():
     """Event timing in any mode changes the launch schedule, never the result."""
     F = wl.noisy_state(150, 140, 3, 1.0, 0.05, 0.0, 1.0)
     outs = []
-    for mode, ov in ((0, 0), (1, 0), (2, 0), (2, 1), (3, 0)):
+    for mode, ov in ((0, 0), (1, 0), (2, 0), (2, 1), (3, 0), (1, 2), (2, 2), (3, 2)):
         r = lbm.Run(134, 124, 0.8, 1.0, 0.05, 0.0, 1.0)
         r.set_bc(15, "nrbc")
         r.set_pml(15, 8, 0.05)
@@ -179,7 +181,7 @@ def test_autotune_choice_is_valid_cached_and_keeps_bits(tmp_path):
     ref.step(19)
     a = make()
     c = a.autotune(steps=4, cache_path=cache)
-    assert c["bulk_tx"] in (64, 128, 256) and c["overlap"] in (0, 1)
+    assert c["bulk_tx"] in (64, 128, 256) and c["overlap"] in (0, 1, 2)
     lines = open(cache).read().split("\n")
     assert lines[0].split() == ["106", "96", "0", "37", str(c["bulk_tx"]), str(c["overlap"])]
     a.step(19)
