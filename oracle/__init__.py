@@ -1,4 +1,4 @@
-"""FP64 CPU oracle for the D2Q37 / D2Q17 thermal LBM + PML + open boundaries (arXiv 2504.20169).
+"""FP64 CPU oracle for the D2Q37 / D2Q17 / D2Q9 LBM + PML + open boundaries (arXiv 2504.20169).
 
 TEST INFRASTRUCTURE ONLY: only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
 of ``bench.py`` may import this package.  It shares no code with the HIP library; see the header
@@ -7,7 +7,7 @@ of ``lbm_oracle.c`` for what each function follows and how it is pinned.
 Layouts: fields are row-major ``[Ny][Nx]`` float64 arrays; populations are ``[q][Ny][Nx]`` in
 this oracle's own velocity order (``lattice(q)[0]``), which differs from the library's order.
 
-The C source is compiled once per velocity stencil (``-DORC_Q=37`` and ``-DORC_Q=17``); every
+The C source is compiled once per velocity stencil (``-DORC_Q=37``, ``17`` and ``9``); every
 entry point takes the stencil as ``q`` (``lattice=`` for runs), 37 by default.
 """
 from __future__ import annotations
@@ -20,8 +20,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
-_LIBS = {37: os.path.join(_HERE, "liboracle.so"), 17: os.path.join(_HERE, "liboracle17.so")}
-LATTICES = (37, 17)
+_LIBS = {37: os.path.join(_HERE, "liboracle.so"), 17: os.path.join(_HERE, "liboracle17.so"),
+         9: os.path.join(_HERE, "liboracle9.so")}
+LATTICES = (37, 17, 9)
 
 SIDE_XMIN, SIDE_XMAX, SIDE_YMIN, SIDE_YMAX, SIDE_ALL = 1, 2, 4, 8, 15
 BC_PERIODIC, BC_ZG, BC_NRBC, BC_NRBC_A = 0, 1, 2, 3
@@ -105,7 +106,7 @@ def lattice(q: int = 37):
 
 
 def feq(rho, ux, uy, T, q: int = 37) -> np.ndarray:
-    """Equilibrium of the stencil: eq. feq-4 for D2Q37, eq. feq-3 for D2Q17."""
+    """Equilibrium of the stencil: eq. feq-4 for D2Q37, eq. feq-3 for D2Q17, eq. feq-2 for D2Q9."""
     out = np.zeros(q)
     _check(_load(q).orc_feq(rho, ux, uy, T, _dp(out)), q)
     return out

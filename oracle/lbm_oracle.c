@@ -1,5 +1,5 @@
 /*
- * FP64 CPU oracle for the D2Q37 (and, built with -DORC_Q=17, D2Q17) thermal lattice Boltzmann
+ * FP64 CPU oracle for the D2Q37 (and, built with -DORC_Q=17 or -DORC_Q=9, D2Q17 or D2Q9) lattice Boltzmann
  * scheme with a perfectly matched layer (PML) and open outer boundaries, following
  * arXiv 2504.20169.
  *
@@ -7,7 +7,7 @@
  * checked against.  Only the tests, the smoke check and the benchmark's CPU-baseline leg may
  * load it.  It shares no code, header, table or constant with the HIP library: the lattice
  * weights are re-derived here from the quadrature conditions, the equilibrium is the printed
- * polynomial (Sec. 2, eqs. feq-3 and feq-4), and the characteristic boundary solves S x = L with a generic
+ * polynomial (Sec. 2, eqs. feq-2, feq-3 and feq-4), and the characteristic boundary solves S x = L with a generic
  * elimination instead of a closed-form inverse.
  *
  * Units: thermal units (c_s = 1, xi_i = r e_i) for rho, u, T in the equilibrium and moments;
@@ -16,9 +16,9 @@
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
  *
- * Pins (tests/test_oracle_*.py), for both stencils: quadrature moments vs the Gaussian up to the
- * rule's degree (9 and 7) and the published D2Q37 / closed-form D2Q17 weights; equilibrium
- * moments vs Maxwellian moments (to order 4 and 3); exact conservation on a
+ * Pins (tests/test_oracle_*.py), for every stencil: quadrature moments vs the Gaussian up to the
+ * rule's degree (9, 7 and 5) and the published D2Q37 / closed-form D2Q17 and D2Q9 weights;
+ * equilibrium moments vs Maxwellian moments (to order 4, 3 and 2); exact conservation on a
  * periodic box; rest and uniform states stationary under every boundary and PML; sigma_max = 0
  * PML identical to no PML; linear growth of Q under a constant deviation; mirror symmetry;
  * linear acoustics vs the linearised Navier-Stokes-Fourier solution; ZG+PML reflecting less
@@ -36,15 +36,15 @@
 #include <string.h>
 #include <omp.h>
 
-/* Velocity stencil of this compilation: ORC_Q = 37 (default) or 17, one shared library each. */
+/* Velocity stencil of this compilation: ORC_Q = 37 (default), 17 or 9, one shared library each. */
 #ifndef ORC_Q
 #define ORC_Q 37
 #endif
 #define NQ ORC_Q
 
 /* ------------------------------------------------------------------------------------------ */
-/* Lattice: Sec. 2 "Velocity stencils".  D2Q37 is the minimal ninth-order rule and D2Q17 the     */
-/* minimal seventh-order rule with integer velocities of maximum displacement 3 and non-negative */
+/* Lattice: Sec. 2 "Velocity stencils".  D2Q37, D2Q17 and D2Q9 are the minimal ninth-, seventh- */
+/* and fifth-order rules with integer velocities of maximum displacement 3 and non-negative      */
 /* weights.                                                                                      */
 /* ------------------------------------------------------------------------------------------ */
 
@@ -55,8 +55,12 @@ static int    lattice_ok = 0;
 
 /* The shells by |e|^2; the grid search below over |ex|,|ey| <= 3 picks exactly these velocities
  * (for D2Q17: the rest velocity, the 4 axis and 4 diagonal unit velocities, (+-2,+-2) and the 4
- * axis velocities of length 3). */
-#if ORC_Q == 17
+ * axis velocities of length 3; for D2Q9: the rest velocity and the axis and diagonal unit
+ * velocities). */
+#if ORC_Q == 9
+#define NS 3
+static const int SHELL_E2[NS] = {0, 1, 2};
+#elif ORC_Q == 17
 #define NS 5
 static const int SHELL_E2[NS] = {0, 1, 2, 8, 9};
 #else
@@ -112,10 +116,13 @@ static int solve_ld(int n, long double *A, long double *b) {
 }
 
 /* The D4-invariant even moment conditions X^a Y^b of the rule (degree 9 for D2Q37, 7 for
- * D2Q17).  The first NS are solved for the shell weights at a trial q = r^2; the residual of the
- * last fixes q.  For D2Q37 the mixed conditions are dependent among themselves, so X^8 is kept
- * for the residual. */
-#if ORC_Q == 17
+ * D2Q17, 5 for D2Q9).  The first NS are solved for the shell weights at a trial q = r^2; the
+ * residual of the last fixes q.  For D2Q37 the mixed conditions are dependent among themselves,
+ * so X^8 is kept for the residual; for D2Q9, e_x^4 = e_x^2 on unit velocities, so X^2 and X^4
+ * differ only by the power of q and X^4 is the residual. */
+#if ORC_Q == 9
+static const int MOM[NS + 1][2] = {{0, 0}, {2, 0}, {2, 2}, {4, 0}};
+#elif ORC_Q == 17
 static const int MOM[NS + 1][2] = {{0, 0}, {2, 0}, {4, 0}, {2, 2}, {6, 0}, {4, 2}};
 #else
 static const int MOM[NS + 1][2] = {{0, 0}, {2, 0}, {4, 0}, {2, 2}, {6, 0},
@@ -187,7 +194,8 @@ static int build_lattice(void) {
 
 /* ------------------------------------------------------------------------------------------ */
 /* Equilibrium (c_s = 1, theta = T - 1): eq. feq-4 (fourth-order Hermite expansion) for D2Q37, */
-/* eq. feq-3 (third order) for D2Q17.  Reading for feq-4: the factor printed as (c_i^2 - 4) in */
+/* eq. feq-3 (third order) for D2Q17, eq. feq-2 (second order) for D2Q9, each the one before    */
+/* plus its next Hermite term.  Reading for feq-4: the factor printed as (c_i^2 - 4) in        */
 /* the theta (u.c)^2 term is (c_i^2 - 6), the value the fourth-order Hermite contraction gives  */
 /* in two dimensions; only with it are mass, momentum and energy moments exact.                 */
 /* ------------------------------------------------------------------------------------------ */
@@ -201,7 +209,10 @@ static void feq_q(double rho, double ux, double uy, double T, double out[NQ]) {
         double t1 = a;
         double t2 = 0.5 * (a * a - b + th * (s - 2.0));
         double t3 = (a / 6.0) * (a * a - 3.0 * b + 3.0 * th * (s - 4.0));
-#if ORC_Q == 17
+#if ORC_Q == 9
+        (void)t3;
+        out[i] = LW[i] * rho * (1.0 + t1 + t2);
+#elif ORC_Q == 17
         out[i] = LW[i] * rho * (1.0 + t1 + t2 + t3);
 #else
         double t4 = (1.0 / 24.0) * (a * a * a * a - 6.0 * a * a * b + 3.0 * b * b

@@ -25,13 +25,13 @@ def _normal_moment(a, mu, var):
                for k in range(a // 2 + 1))
 
 
-LATTICES = pytest.mark.parametrize("q", [37, 17])
+LATTICES = pytest.mark.parametrize("q", [37, 17, 9])
 
 
 @LATTICES
 def test_weights_match_published_table(oracle_mod, q):
     """The oracle solves the quadrature conditions itself; the result must equal the published
-    D2Q37 weights and the closed-form D2Q17 weights (golden fixtures, Sec. 2 velocity
+    D2Q37 weights and the closed-form D2Q17 and D2Q9 weights (golden fixtures, Sec. 2 velocity
     stencils)."""
     e, w, r = oracle_mod.lattice(q)
     path = os.path.join(GOLDEN, "d2q%d_weights.txt" % q)
@@ -46,11 +46,11 @@ def test_weights_match_published_table(oracle_mod, q):
     assert abs(w.sum() - 1.0) < 1e-15
 
 
-@pytest.mark.parametrize("q,degree", [(37, 9), (17, 7)])
+@pytest.mark.parametrize("q,degree", [(37, 9), (17, 7), (9, 5)])
 def test_quadrature_is_exact_to_its_degree(oracle_mod, q, degree):
-    """Every monomial X^a Y^b with a + b <= 9 for D2Q37 (7 for D2Q17), odd and mixed ones
-    included beyond the conditions the solve used, integrates exactly against the standard
-    normal; the next even degree does not (the rules are ninth and seventh order)."""
+    """Every monomial X^a Y^b with a + b <= 9 for D2Q37 (7 for D2Q17, 5 for D2Q9), odd and mixed
+    ones included beyond the conditions the solve used, integrates exactly against the standard
+    normal; the next even degree does not (the rules are ninth, seventh and fifth order)."""
     e, w, r = oracle_mod.lattice(q)
     xi = r * e.astype(float)
     for a in range(degree + 1):
@@ -64,11 +64,12 @@ def test_quadrature_is_exact_to_its_degree(oracle_mod, q, degree):
 
 @pytest.mark.parametrize("state", [(1.0, 0.0, 0.0, 1.0), (1.03, 0.11, -0.07, 0.95),
                                    (0.9, -0.2, 0.15, 1.1), (1.2, 0.05, 0.3, 0.8)])
-@pytest.mark.parametrize("q,order", [(37, 4), (17, 3)])
+@pytest.mark.parametrize("q,order", [(37, 4), (17, 3), (9, 2)])
 def test_equilibrium_moments_are_maxwellian(oracle_mod, state, q, order):
     """eq. feq-4 (with the (c^2 - 6) reading) on D2Q37 reproduces every raw moment up to fourth
     order of the Maxwellian rho N(u, T I) exactly, eq. feq-3 on D2Q17 every one up to third
-    order; a dropped term, a wrong shell factor or the printed (c^2 - 4) in feq-4 fails here."""
+    order, eq. feq-2 on D2Q9 every one up to second order; a dropped term, a wrong shell factor
+    or the printed (c^2 - 4) in feq-4 fails here."""
     rho, ux, uy, T = state
     e, w, r = oracle_mod.lattice(q)
     xi = r * e.astype(float)
@@ -91,6 +92,20 @@ def test_d2q17_equilibrium_is_third_order_only(oracle_mod):
     want = rho * _normal_moment(4, ux, T)
     miss = ux ** 4 + 6 * (T - 1) * ux ** 2 + 3 * (T - 1) ** 2   # fourth Hermite coefficient
     assert abs((want - got) - miss) < 1e-12
+
+
+def test_d2q9_equilibrium_is_second_order_only(oracle_mod):
+    """feq-2 stops at second order: the third raw moment of the Maxwellian exceeds it by the
+    third Hermite coefficient rho (u^3 + 3 u theta), which feq-3 would carry (Sec. 2: D2Q9
+    does not describe the heat flux)."""
+    rho, ux, uy, T = 1.1, 0.2, 0.0, 1.1
+    e, w, r = oracle_mod.lattice(9)
+    xi = r * e.astype(float)
+    f = oracle_mod.feq(rho, ux, uy, T, q=9)
+    got = np.sum(f * xi[:, 0] ** 3)
+    want = rho * _normal_moment(3, ux, T)
+    miss = rho * (ux ** 3 + 3 * ux * (T - 1))
+    assert abs((want - got) - miss) < 1e-13
 
 
 @LATTICES
@@ -252,12 +267,14 @@ def _linear_nsf(drho0, dT0, k, t, r, tau):
     return out_r
 
 
-@LATTICES
+@pytest.mark.parametrize("q", [37, 17])
 def test_linear_acoustics_matches_nsf_theory(oracle_mod, q):
     """A small plane density pulse on a periodic line follows linearised NSF theory: the sound
     speed is sqrt(2)/r cells/step and all modes decay at nu k^2.  Pins weights, scale r, tau,
     the equilibrium and the streaming direction together.  The residual is of Burnett order, so
-    it falls like k^2 when the pulse is made twice as wide."""
+    it falls like k^2 when the pulse is made twice as wide.  Not for D2Q9: its fifth-order rule
+    cannot carry the heat flux (Sec. 2), so its thermal damping is not Fourier's; its sound
+    speed and shear viscosity are pinned below."""
     e, w, r = oracle_mod.lattice(q)
     N, A, tau, t = 256, 1e-4, 0.8, 40
     errs = {}
@@ -277,6 +294,56 @@ def test_linear_acoustics_matches_nsf_theory(oracle_mod, q):
         assert abs((right - 128.0) - math.sqrt(2.0) / r * t) < 1.0
     assert errs[4.0] < 6e-3 and errs[8.0] < 1.5e-3, errs
     assert errs[4.0] > 2.5 * errs[8.0], errs
+
+
+@LATTICES
+def test_shear_wave_decays_at_nu_k2(oracle_mod, q):
+    """A transverse wave u_y = A sin(k x) on a periodic line keeps its shape and decays at
+    nu k^2 with nu = (tau - 1/2)/r^2 (Sec. 2, Chapman-Enskog): the rate between steps 100 and
+    200 (past the initial layer) is within 0.6% for k = 2 pi/32, and the residual, of Burnett
+    order, falls by four when k halves.  Pins r, tau, the second moment of the equilibrium and
+    the streaming on every stencil, D2Q9 included."""
+    e, w, r = oracle_mod.lattice(q)
+    tau, A = 0.8, 1e-4
+    nu = (tau - 0.5) / r ** 2
+    res = {}
+    for N, (t1, t2) in ((32, (100, 200)), (64, (400, 800))):
+        k = 2 * np.pi / N
+        x = np.arange(N, dtype=float)
+        amps = []
+        for t in (t1, t2):
+            o = oracle_mod.OracleRun(N, 1, tau, lattice=q)
+            F = wl.uniform_state(N, 1)
+            F.uy = (A * np.sin(k * x))[None, :]
+            o.init(*F.as_tuple())
+            o.step(t)
+            uy = o.moments()[2][0]
+            amp = 2.0 * np.sum(uy * np.sin(k * x)) / N
+            assert np.abs(uy - amp * np.sin(k * x)).max() < 1e-8 * A
+            amps.append(amp)
+        res[N] = -math.log(amps[1] / amps[0]) / (t2 - t1) / (nu * k * k) - 1.0
+    assert 0.0 < res[32] < 6e-3, res
+    assert 3.5 < res[32] / res[64] < 4.5, res
+
+
+@LATTICES
+def test_sound_speed_is_sqrt2_over_r(oracle_mod, q):
+    """The acoustic peak of a small density pulse travels sqrt(2)/r cells per step (gamma = 2,
+    T = 1, thermal units) on every stencil: the Euler-level fluxes need moments only to third
+    order, which even D2Q9's second-order equilibrium gets right at linear order."""
+    e, w, r = oracle_mod.lattice(q)
+    N, A, t = 256, 1e-4, 60
+    o = oracle_mod.OracleRun(N, 1, 0.8, lattice=q)
+    F = wl.uniform_state(N, 1)
+    x = np.arange(N, dtype=float)
+    F.rho = (1.0 + A * np.power(2.0, -((x - 128.0) ** 2) / 16.0))[None, :]
+    o.init(*F.as_tuple())
+    o.step(t)
+    rho = o.moments()[0][0]
+    right = np.argmax(rho[140:]) + 140
+    left = np.argmax(rho[:116])
+    c = math.sqrt(2.0) / r * t
+    assert abs((right - 128.0) - c) < 1.0 and abs((128.0 - left) - c) < 1.0, (left, right, c)
 
 
 def _reference_bulk(oracle_mod, L, W, steps, make, q=37):
