@@ -140,6 +140,23 @@ def large_leg(torch, lbm, wl, args):
     return out
 
 
+def d2q9_leg(torch, lbm, wl, args):
+    """The 1024^2 + 32 PML (1088^2) vortex + pulse with NRBC on the D2Q9 stencil (Sec. 2;
+    eq. feq-2), 9 populations per node, in every storage."""
+    out = {}
+    spec = wl.vortex_pulse(L=args.L, W=args.W, sigma_max=args.sigma, mach=args.mach, bc=args.bc)
+    spec.lattice = 9
+    for storage in args.storages.split(","):
+        _log("bench: d2q9 1088^2", storage)
+        r = run_from_spec(lbm, spec, storage, layout=args.layout, bulk_tx=args.bulk_tx,
+                          overlap=args.overlap)
+        out["%dsq_%s_%s" % (spec.Nx, args.bc, storage)] = measure(
+            torch, lbm, r, spec, storage, args.d2q9_steps, args.warmup, args.d2q9_steps // 2)
+        r.close()
+        del r
+    return out
+
+
 def d2q17_leg(torch, lbm, wl, args):
     """The same workloads on the D2Q17 stencil (Sec. 2; eq. feq-3), 17 populations per node:
     1024^2 + 32 PML (1088^2) vortex + pulse with NRBC in every storage, and 4096^2 + 64 PML
@@ -344,6 +361,8 @@ def main():
     ap.add_argument("--large-steps", type=int, default=200,
                     help="timed steps per run of the 4224^2 leg (0 skips it)")
     ap.add_argument("--large-bcs", default="zg,nrbc")
+    ap.add_argument("--d2q9-steps", type=int, default=1000,
+                    help="timed steps of the D2Q9 leg at the main size (0 skips it)")
     ap.add_argument("--d2q17-steps", type=int, default=1000,
                     help="timed steps of the D2Q17 leg at the main size (0 skips it)")
     ap.add_argument("--batch-runs", type=int, default=256, help="0 skips the batch sweep")
@@ -489,6 +508,8 @@ def main():
         line["at_4224"] = rnd(large_leg(torch, lbm, wl, args))
     if args.d2q17_steps > 0:
         line["d2q17"] = rnd(d2q17_leg(torch, lbm, wl, args))
+    if args.d2q9_steps > 0:
+        line["d2q9"] = rnd(d2q9_leg(torch, lbm, wl, args))
     if args.batch_runs > 0:
         _log("bench: batch sweep")
         line["batch"] = rnd(batch_leg(torch, lbm, wl, args))

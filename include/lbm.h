@@ -1,5 +1,5 @@
 /*
- * lbm.h -- C ABI of the MI355X (gfx950) thermal lattice Boltzmann library (D2Q37 or D2Q17
+ * lbm.h -- C ABI of the MI355X (gfx950) thermal lattice Boltzmann library (D2Q37, D2Q17 or D2Q9
  * velocity stencil) with a perfectly matched layer (PML) and open outer boundaries, after
  * arXiv 2504.20169.
  *
@@ -11,17 +11,19 @@
  *   moments         rho, u, T (eq. macro, e = (d/2) T)
  *   PML auxiliary   Q^{n+1} = Q^n + (fhat^n + fhat^{n+1})/2 (eq. PMLQ, trapezoid rule)
  *   collision       f* = f - (f - feq)/tau - sigma (e.grad Q + 2 fhat + sigma Q)
- *                   (BGK with eq. feq-4 on D2Q37 or eq. feq-3 on D2Q17, and eq. PMLCOLL;
+ *                   (BGK with eq. feq-4 on D2Q37, eq. feq-3 on D2Q17 or eq. feq-2 on D2Q9,
+ *                   and eq. PMLCOLL;
  *                   sigma ramp eq. PML_ramp)
  *
  * Units: rho, u, T in thermal units (sound-speed unit c_s = 1, xi_i = r e_i with the stencil's
- * scale, r = 1.19698... for D2Q37 and 1.64343... for D2Q17); lengths and times in lattice
+ * scale, r = 1.19698... for D2Q37, 1.64343... for D2Q17, sqrt 3 for D2Q9); lengths and times in lattice
  * units (one cell, one step).
  *
  * Grid: the bulk is nx x ny; every side carrying a PML of width W adds W layers, so the full
  * grid is Nx = nx + W*(#PML x-sides), Ny likewise.  The outermost 3 layers of an open side are
- * its boundary nodes (and, with a PML, also its PML levels W, W-1, W-2).  Host field arrays are
- * row-major [Ny][Nx] float64; population arrays are [q][Ny][Nx] float64 (q = 37 or 17) in the
+ * its boundary nodes (and, with a PML, also its PML levels W, W-1, W-2), for every stencil: the
+ * paper's boundary depth is the displacement bound 3 under which its stencils are minimal.  Host field arrays are
+ * row-major [Ny][Nx] float64; population arrays are [q][Ny][Nx] float64 (q = 37, 17 or 9) in the
  * order returned by lbm_velocities().
  *
  * Conventions: every call returns an lbm_status; no exception or abort crosses the ABI.
@@ -102,7 +104,8 @@ typedef struct {
                                     FP64 and FP32 storage, none for FP16: the fastest measured on
                                     large grids), -1 = none, 1..4096 = that many elements */
     int32_t lattice;             /* velocity stencil (Sec. 2, "Velocity stencils"): 0 or 37 =
-                                    D2Q37 with eq. feq-4 (default), 17 = D2Q17 with eq. feq-3 */
+                                    D2Q37 with eq. feq-4 (default), 17 = D2Q17 with eq. feq-3,
+                                    9 = D2Q9 with eq. feq-2 */
 } lbm_desc;
 
 /* Launch configuration (set by lbm_set_launch or lbm_autotune).  bulk_tx in {64,128,256}
@@ -187,7 +190,7 @@ lbm_status lbm_populations(lbm_handle h, double *f);
  * region.  Synchronises. */
 lbm_status lbm_pml_q(lbm_handle h, double *Q);
 
-/* The library's velocity order of a stencil (lattice 37 or 0: D2Q37, 17: D2Q17; Sec. 2,
+/* The library's velocity order of a stencil (lattice 37 or 0: D2Q37, 17: D2Q17, 9: D2Q9; Sec. 2,
  * "Velocity stencils"): e[2*i], e[2*i+1] integer lattice vector of population i (e holds 2q
  * entries); w[i] its weight; *r the thermal scale (xi = r e).  Host only; any pointer may be
  * NULL.  LBM_ERR_ARG for another lattice. */

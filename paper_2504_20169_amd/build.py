@@ -15,9 +15,10 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbm_mi355x.so")
-# lbm_kernels_d2q17.hip compiles lbm_kernels.hip a second time for the D2Q17 stencil
+# lbm_kernels_d2q17.hip and lbm_kernels_d2q9.hip compile lbm_kernels.hip again for the D2Q17 and
+# D2Q9 stencils
 SOURCES = [os.path.join(HERE, "csrc", n)
-           for n in ("lbm_kernels.hip", "lbm_kernels_d2q17.hip", "lbm_capi.hip")]
+           for n in ("lbm_kernels.hip", "lbm_kernels_d2q17.hip", "lbm_kernels_d2q9.hip", "lbm_capi.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-ffp-contract=on",

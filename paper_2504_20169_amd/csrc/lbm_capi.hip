@@ -247,7 +247,7 @@ lbm_status setup_geometry(lbm_run *h, RunDev &R) {
 void fill_constants(lbm_run *h, RunDev &R) {
     const lbm_desc &d = h->desc;
     const LatticeInfo &lt = *h->lat;
-    const bool o4 = lt.order == 4;
+    const bool o4 = lt.order == 4, o2 = lt.order == 2;
     R.storage = d.storage;
     R.omega = 1.0 / d.tau;
     R.rho0 = d.rho0; R.u0x = d.ux0; R.u0y = d.uy0; R.T0 = d.T0;
@@ -267,7 +267,7 @@ void fill_constants(lbm_run *h, RunDev &R) {
         double sv = lt.r * lt.r * lt.shell_e2[s];
         E0[s] = k0 + k2s * sv + (o4 ? 0.125 * th0 * th0 * sv * sv : 0.0);
         R.E2_0[s] = k2a + (o4 ? 0.25 * th0 * sv : 0.0);
-        R.O1_0[s] = k1 + 0.5 * th0 * sv;
+        R.O1_0[s] = o2 ? 1.0 : k1 + 0.5 * th0 * sv;   // eq. feq-2: the odd part is a itself
     }
     R.H0rest = k0;
     h->fbar[0] = lt.shell_w[0] * d.rho0 * k0;
@@ -275,7 +275,7 @@ void fill_constants(lbm_run *h, RunDev &R) {
         int sh = lt.psh[p];
         double a0 = lt.pex[p] * R.r0x + lt.pey[p] * R.r0y;
         R.H0e[p] = E0[sh] + R.E2_0[sh] * a0 * a0 + (o4 ? a0 * a0 * a0 * a0 / 24.0 : 0.0);
-        R.H0o[p] = a0 * (R.O1_0[sh] + a0 * a0 / 6.0);
+        R.H0o[p] = o2 ? a0 : a0 * (R.O1_0[sh] + a0 * a0 / 6.0);
         h->fbar[1 + 2 * p] = lt.shell_w[sh] * d.rho0 * (R.H0e[p] + R.H0o[p]);
         h->fbar[2 + 2 * p] = lt.shell_w[sh] * d.rho0 * (R.H0e[p] - R.H0o[p]);
     }
@@ -517,8 +517,9 @@ extern "C" {
 const char *lbm_last_error(void) { return g_err.c_str(); }
 
 lbm_status lbm_velocities(int32_t lattice, int32_t *e, double *w, double *r) {
-    if (lattice != 0 && lattice != 37 && lattice != 17) return fail(LBM_ERR_ARG, "lattice must be 37 or 17");
-    const LatticeInfo &lt = lattice == 17 ? LATTICE_D2Q17 : LATTICE_D2Q37;
+    const LatticeInfo *li = lattice_info(lattice);
+    if (!li) return fail(LBM_ERR_ARG, "lattice must be 37, 17 or 9");
+    const LatticeInfo &lt = *li;
     for (int i = 0; i < lt.q; ++i) {
         if (e) { e[2 * i] = lt.ex(i); e[2 * i + 1] = lt.ey(i); }
         if (w) w[i] = lt.shell_w[lt.shell(i)];
@@ -539,7 +540,7 @@ lbm_status lbm_create(const lbm_desc *desc, lbm_handle *out) {
     if (d.storage < LBM_F64 || d.storage > LBM_F16_DEV) return fail(LBM_ERR_ARG, "unknown storage");
     if (d.layout != 0 && d.layout != 1) return fail(LBM_ERR_ARG, "unknown layout");
     if (d.row_pad < -1 || d.row_pad > 4096) return fail(LBM_ERR_ARG, "row_pad must be in -1..4096");
-    if (d.lattice != 0 && d.lattice != 37 && d.lattice != 17) return fail(LBM_ERR_ARG, "lattice must be 37 or 17");
+    if (!lattice_info(d.lattice)) return fail(LBM_ERR_ARG, "lattice must be 37, 17 or 9");
     if (d.storage == LBM_F16_DEV && d.f16_scale != 0.0) {
         int ex;
         double m = std::frexp(d.f16_scale, &ex);
@@ -547,9 +548,9 @@ lbm_status lbm_create(const lbm_desc *desc, lbm_handle *out) {
     }
     lbm_run *h = new lbm_run();
     h->desc = d;
-    h->desc.lattice = d.lattice == 17 ? 17 : 37;
-    h->lat = d.lattice == 17 ? &LATTICE_D2Q17 : &LATTICE_D2Q37;
-    h->ks = d.lattice == 17 ? &k17::kernels : &k37::kernels;
+    h->lat = lattice_info(d.lattice);
+    h->desc.lattice = h->lat->q;
+    h->ks = h->lat->q == 17 ? &k17::kernels : h->lat->q == 9 ? &k9::kernels : &k37::kernels;
     if (d.allocator) {
         h->alloc_copy = *d.allocator;
         h->desc.allocator = &h->alloc_copy;

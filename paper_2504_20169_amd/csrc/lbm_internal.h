@@ -123,5 +123,6 @@ struct KernelSet {
 
 namespace k37 { extern const KernelSet kernels; }
 namespace k17 { extern const KernelSet kernels; }
+namespace k9 { extern const KernelSet kernels; }
 
 }  // namespace lbm

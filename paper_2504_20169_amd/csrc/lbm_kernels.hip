@@ -55,8 +55,11 @@
 #elif LBM_Q == 17
 #define LBM_LATTICE d2q17
 #define LBM_KSET k17
+#elif LBM_Q == 9
+#define LBM_LATTICE d2q9
+#define LBM_KSET k9
 #else
-#error "LBM_Q must be 37 or 17"
+#error "LBM_Q must be 37, 17 or 9"
 #endif
 
 namespace lbm {
@@ -318,13 +321,16 @@ __device__ __forceinline__ Eq<C> eq_coef(C drho, C dux, C duy, C dT, const K<C> 
         q.dk2a = -C(0.25) * db - C(1.5) * dT;
         q.dk2s = C(0.5) * dT - C(0.25) * dthb - dth2;
         q.dth2 = dth2;
-    } else {   // third order: k0 = 1 - b/2 - theta, k2a = 1/2, k2s = theta/2
+    } else {   // third and second order: k0 = 1 - b/2 - theta, k2a = 1/2, k2s = theta/2
         q.dk0 = -C(0.5) * db - dT;
         q.dk2a = C(0);
         q.dk2s = C(0.5) * dT;
         q.dth2 = C(0);
     }
-    q.dk1 = -C(0.5) * db - C(2) * dT;
+    // odd part: O1 = k1 + theta c^2/2 with k1 = 1 - b/2 - 2 theta (fourth and third order);
+    // the second-order equilibrium's odd part is a alone (O1 = 1)
+    if constexpr (ORDER >= 3) q.dk1 = -C(0.5) * db - C(2) * dT;
+    else q.dk1 = C(0);
     q.dE0 = q.dE2 = q.dO1 = C(0);
     return q;
 }
@@ -345,7 +351,8 @@ __device__ __forceinline__ void eq_shell(Eq<C> &q) {
         q.dE0 = q.dk0 + q.dk2s * C(sv);
         q.dE2 = C(0);
     }
-    q.dO1 = q.dk1 + q.dT * C(0.5 * sv);
+    if constexpr (ORDER >= 3) q.dO1 = q.dk1 + q.dT * C(0.5 * sv);
+    else q.dO1 = C(0);
 }
 
 // feq - fbar of the pair p: (+e_p, -e_p).
@@ -366,7 +373,11 @@ __device__ __forceinline__ void eq_pair(const Eq<C> &q, CRun &R, const K<C> &k, 
         dEv = q.dE0 + q.dE2 * A2 + cE2_0<C>(R, sh) * dA2 + dA2 * (A2 + A02) * C(1.0 / 24.0);
     else   // E2 = 1/2 for every shell and state
         dEv = q.dE0 + C(0.5) * dA2;
-    C dOd = q.dO1 * a + O1_0 * da + da * (A2 + a * a0 + A02) * C(1.0 / 6.0);
+    C dOd;
+    if constexpr (ORDER >= 3)
+        dOd = q.dO1 * a + O1_0 * da + da * (A2 + a * a0 + A02) * C(1.0 / 6.0);
+    else   // eq. feq-2: the odd part is a itself
+        dOd = da;
     C Tev = q.drho * cH0e<C>(R, p) + q.rho * dEv;
     C Tod = q.drho * cH0o<C>(R, p) + q.rho * dOd;
     constexpr double w = SHELL_W[sh];

@@ -1,10 +1,13 @@
-// Lattice constants of the library (host and device): the D2Q37 and D2Q17 velocity stencils.
+// Lattice constants of the library (host and device): the D2Q37, D2Q17 and D2Q9 velocity
+// stencils.
 //
-// Both are minimal Gauss-Hermite rules in 2D with integer velocities of maximum displacement 3
-// and positive weights (paper Sec. 2, "Velocity stencils"): D2Q37 of ninth order, carrying the
-// fourth-order equilibrium (eq. feq-4), and D2Q17 of seventh order, carrying the third-order
-// equilibrium (eq. feq-3).  Weights and scales as published by Philippi et al., PRE 73 (2006)
-// 056702 and Shan, PRE 81 (2010) 036702 (D2Q17 in closed form: r^2 = (125 + 5 sqrt193)/72).
+// All three are minimal Gauss-Hermite rules in 2D with integer velocities of maximum
+// displacement at most 3 and positive weights (paper Sec. 2, "Velocity stencils"): D2Q37 of
+// ninth order, carrying the fourth-order equilibrium (eq. feq-4), D2Q17 of seventh order with
+// the third-order equilibrium (eq. feq-3), and D2Q9 of fifth order with the second-order one
+// (eq. feq-2).  Weights and scales as published by Philippi et al., PRE 73 (2006) 056702 and
+// Shan, PRE 81 (2010) 036702 (D2Q17 in closed form: r^2 = (125 + 5 sqrt193)/72; D2Q9: r^2 = 3,
+// weights 4/9, 1/9, 1/36).
 // Thermal velocities are xi_i = LAT_R e_i (sound-speed unit 1).
 //
 // Library population order: 0 is the rest velocity; pair p = 0..NPAIR-1 holds +e_p at index
@@ -72,6 +75,28 @@ constexpr int ey_of(int i) { return i == 0 ? 0 : ((i - 1) & 1) ? -PEY[(i - 1) >>
 constexpr int shell_of(int i) { return i == 0 ? 0 : PSH[(i - 1) >> 1]; }
 }  // namespace d2q17
 
+namespace d2q9 {
+constexpr int NQ = 9;
+constexpr int NPAIR = 4;
+constexpr int NSHELL = 3;
+constexpr int ORDER = 2;
+
+constexpr double LAT_R = 1.7320508075688772935274463;   // sqrt(3)
+constexpr double LAT_R2 = LAT_R * LAT_R;
+
+// shells |e|^2 = 0, 1, 2: rest, axis and diagonal unit velocities
+inline constexpr int SHELL_E2[NSHELL] = {0, 1, 2};
+inline constexpr double SHELL_W[NSHELL] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0};
+
+inline constexpr int PEX[NPAIR] = {1, 0, 1, -1};
+inline constexpr int PEY[NPAIR] = {0, 1, 1, 1};
+inline constexpr int PSH[NPAIR] = {1, 1, 2, 2};
+
+constexpr int ex_of(int i) { return i == 0 ? 0 : ((i - 1) & 1) ? -PEX[(i - 1) >> 1] : PEX[(i - 1) >> 1]; }
+constexpr int ey_of(int i) { return i == 0 ? 0 : ((i - 1) & 1) ? -PEY[(i - 1) >> 1] : PEY[(i - 1) >> 1]; }
+constexpr int shell_of(int i) { return i == 0 ? 0 : PSH[(i - 1) >> 1]; }
+}  // namespace d2q9
+
 // Host view of one stencil's tables.
 struct LatticeInfo {
     int q, npair, nshell, order;
@@ -90,5 +115,14 @@ inline constexpr LatticeInfo LATTICE_D2Q37 = {d2q37::NQ, d2q37::NPAIR, d2q37::NS
 inline constexpr LatticeInfo LATTICE_D2Q17 = {d2q17::NQ, d2q17::NPAIR, d2q17::NSHELL, d2q17::ORDER,
                                               d2q17::LAT_R, d2q17::SHELL_E2, d2q17::SHELL_W,
                                               d2q17::PEX, d2q17::PEY, d2q17::PSH};
+inline constexpr LatticeInfo LATTICE_D2Q9 = {d2q9::NQ, d2q9::NPAIR, d2q9::NSHELL, d2q9::ORDER,
+                                             d2q9::LAT_R, d2q9::SHELL_E2, d2q9::SHELL_W,
+                                             d2q9::PEX, d2q9::PEY, d2q9::PSH};
+
+// The stencil a lattice code (37, 17, 9; 0 = 37) names, or nullptr.
+inline const LatticeInfo *lattice_info(int code) {
+    return code == 0 || code == 37 ? &LATTICE_D2Q37 : code == 17 ? &LATTICE_D2Q17
+                                                    : code == 9 ? &LATTICE_D2Q9 : nullptr;
+}
 
 }  // namespace lbm

@@ -144,14 +144,15 @@ def _dp(a):
 
 # ---- same-named functions over the C ABI ------------------------------------------------------
 
-LATTICES = (37, 17)
+LATTICES = (37, 17, 9)
 
 
 def lbm_velocities(lattice=37):
-    """(e [q,2], w [q], r) of the library's velocity order for the D2Q37 or D2Q17 stencil."""
-    q = int(lattice)
+    """(e [q,2], w [q], r) of the library's velocity order for the D2Q37, D2Q17 or D2Q9
+    stencil."""
+    q = 37 if int(lattice) == 0 else int(lattice)
     if q not in LATTICES:
-        raise LbmError(LBM_ERR_ARG, "lattice must be 37 or 17")
+        raise LbmError(LBM_ERR_ARG, "lattice must be 37, 17 or 9")
     e = np.zeros((q, 2), dtype=np.int32)
     w = np.zeros(q)
     r = ctypes.c_double()
@@ -208,7 +209,7 @@ class Run:
         _check(lib.lbm_create(ctypes.byref(d), ctypes.byref(h)))
         self.h = h
         self.nx, self.ny = int(nx), int(ny)
-        self.q = 17 if int(lattice) == 17 else 37
+        self.q = 37 if int(lattice) == 0 else int(lattice)
 
     def close(self):
         if getattr(self, "h", None):

@@ -7,7 +7,7 @@ tanh fronts of steepness s = 0.5 on a rho0 = 1 background; the mean equilibrium 
 taken at (rho0, u0, T0).  Each configuration is a boundary (ZG, or the perfectly non-reflecting
 LODI boundary) with or without a PML of width W on both x sides, with the sigma_max of the
 paper's Table "Values of sigma_max used for the density step test case" for the stencil run
-(D2Q37 or D2Q17).
+(D2Q37, D2Q17 or D2Q9).
 
 Reference (Sec. 5, Reference Simulation): the same initial data embedded in a fully periodic
 grid extended on both x sides far enough that no wave wraps round into the bulk window during
@@ -32,7 +32,9 @@ SIGMA_D2Q37 = {("zg", 10): 0.35, ("zg", 20): 0.175, ("zg", 40): 0.10,
                ("nrbc", 10): 0.001, ("nrbc", 20): 0.10, ("nrbc", 40): 0.06}
 SIGMA_D2Q17 = {("zg", 10): 0.33, ("zg", 20): 0.14, ("zg", 40): 0.09,
                ("nrbc", 10): 0.001, ("nrbc", 20): 0.08, ("nrbc", 40): 0.04}
-SIGMA_TABLE = {37: SIGMA_D2Q37, 17: SIGMA_D2Q17}
+SIGMA_D2Q9 = {("zg", 10): 0.17, ("zg", 20): 0.10, ("zg", 40): 0.07,
+              ("nrbc", 10): 0.001, ("nrbc", 20): 0.04, ("nrbc", 40): 0.04}
+SIGMA_TABLE = {37: SIGMA_D2Q37, 17: SIGMA_D2Q17, 9: SIGMA_D2Q9}
 
 
 def step_profile(xb, Lx, rho0=1.0, rho1=1.05, s=0.5):
@@ -79,8 +81,8 @@ def density_step_study(steps=600, sample=10, Lx=200, Ly=20, mach=0.05, tau=0.8,
         table = SIGMA_TABLE[lattice]
         configs = [(bc, W, table.get((bc, W), 0.0) if W > 0 else 0.0)
                    for bc in bcs for W in widths]
-    # sound travels sqrt(2)/r cells per step (1.18 on D2Q37, 0.86 on D2Q17); both stencils carry
-    # signals up to 3 cells per step
+    # sound travels sqrt(2)/r cells per step (1.18 on D2Q37, 0.86 on D2Q17, 0.82 on D2Q9); no
+    # stencil carries a signal more than 3 cells per step
     ext = int(math.ceil(3.0 * steps)) + 16
     Nref = Lx + 2 * ext
     ref = _make(lbm, Nref, Ly, "periodic", 0, 0.0, mach, storage,
@@ -241,7 +243,7 @@ def main():
     ap.add_argument("--steps", type=int, default=600)
     ap.add_argument("--sample", type=int, default=10)
     ap.add_argument("--storage", default="f64")
-    ap.add_argument("--lattice", type=int, default=37, choices=(37, 17))
+    ap.add_argument("--lattice", type=int, default=37, choices=(37, 17, 9))
     ap.add_argument("--scan", action="store_true", help="also scan sigma_max per boundary and W")
     ap.add_argument("--vortex", action="store_true",
                     help="also run the vortex outflow through ZG and LODI (B) boundaries")

@@ -26,7 +26,7 @@ def test_header_symbols_exported():
     assert sorted(lbm.EXPORTED) == names
 
 
-@pytest.mark.parametrize("q", [37, 17])
+@pytest.mark.parametrize("q", [37, 17, 9])
 def test_velocity_table_matches_oracle(oracle_mod, q):
     e, w, r = lbm.lbm_velocities(q)
     eo, wo, ro = oracle_mod.lattice(q)
@@ -43,17 +43,19 @@ def test_velocity_table_matches_oracle(oracle_mod, q):
 
 
 def test_velocity_table_rejects_other_stencils():
-    with pytest.raises(lbm.LbmError):
-        lbm.lbm_velocities(9)
-    assert lbm.load().lbm_velocities(9, None, None, None) == lbm.LBM_ERR_ARG
-    assert lbm.load().lbm_velocities(17, None, None, None) == lbm.LBM_OK
+    for bad in (5, 19, -1):
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_velocities(bad)
+        assert lbm.load().lbm_velocities(bad, None, None, None) == lbm.LBM_ERR_ARG
+    for ok in (0, 37, 17, 9):
+        assert lbm.load().lbm_velocities(ok, None, None, None) == lbm.LBM_OK
 
 
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.3), dict(nx=0), dict(ny=-1),
                                 dict(rho0=0.0), dict(T0=-1.0), dict(storage=7),
                                 dict(rho0=float("nan")), dict(storage="f16", f16_scale=3.0),
                                 dict(layout=2), dict(row_pad=-2), dict(row_pad=5000),
-                                dict(lattice=9), dict(lattice=-1)])
+                                dict(lattice=5), dict(lattice=-1)])
 def test_create_rejects_bad_descriptor(kw):
     args = dict(nx=16, ny=16, tau=0.8)
     args.update(kw)
@@ -79,7 +81,7 @@ def test_setters_validate_and_grid():
     assert ei.value.status == lbm.LBM_ERR_STATE
 
 
-@pytest.mark.parametrize("q", [37, 17])
+@pytest.mark.parametrize("q", [37, 17, 9])
 def test_cbc_a_kind_and_footprint(q):
     """CBC (A) is boundary kind 3; another kind is refused.  Its targets are formed ahead of the
     fill, so a run with a CBC (A) side holds four float64 target planes of the ring more than the
@@ -98,9 +100,11 @@ def test_cbc_a_kind_and_footprint(q):
     rplane = (ring + 63) // 64 * 64
     assert a.footprint() - b.footprint() == 4 * rplane * 8
     # the stencil sets the population count of every buffer
-    c = lbm.Run(40, 30, 0.8, lattice=37 if q == 17 else 17)
-    c.set_bc(lbm.LBM_ALL, "nrbc")
-    assert (c.footprint() > b.footprint()) == (q == 17)
+    for other in (37, 17, 9):
+        c = lbm.Run(40, 30, 0.8, lattice=other)
+        c.set_bc(lbm.LBM_ALL, "nrbc")
+        assert c.q == other
+        assert (c.footprint() > b.footprint()) == (other > q)
 
 
 def test_launch_configuration_validated_on_host():

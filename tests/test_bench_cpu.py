@@ -76,7 +76,8 @@ def test_stats_summary_lists_every_kernel(tmp_path):
 
 
 @pytest.mark.parametrize("storage,q,node,pml", [("f64", 37, 592, 656), ("f32", 37, 296, 360),
-                                                ("f16", 37, 148, 360), ("f64", 17, 272, 336)])
+                                                ("f16", 37, 148, 360), ("f64", 17, 272, 336),
+                                                ("f64", 9, 144, 208), ("f32", 9, 72, 136)])
 def test_algorithmic_bytes(storage, q, node, pml):
     """q populations read and written per node; a PML node adds Q (compute precision) and the
     four float64 moments, each read and written."""

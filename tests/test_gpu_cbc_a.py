@@ -1,6 +1,6 @@
 """CBC (A) on the GPU (Sec. 4 eq. thermal_CBC_macro_evo, Sec. 5.2 eq. CBC-Relax): FP64 parity
-with the oracle on both stencils (every side on D2Q17; the outflow side on D2Q37, where it is
-stable only there), with PMLs, mixed sides and small grids; batches and launch options keep its
+with the oracle on every stencil (every side on D2Q17 and D2Q9; the outflow side on D2Q37, where
+it is stable only there), with PMLs, mixed sides and small grids; batches and launch options keep its
 bits; and the Sec. 5.2 vortex outflow ranks it as the paper does."""
 import numpy as np
 import pytest
@@ -23,6 +23,9 @@ CASES = [
     dict(name="q17_y_periodic", q=17, Lx=40, Ly=12, bc={"xmin": "nrbc_a", "xmax": "nrbc_a", "ymin": "periodic", "ymax": "periodic"},
          pml=None, mean=(1.0, 0.05, 0.0, 1.0), steps=60),
     dict(name="q17_tiny", q=17, Lx=9, Ly=8, bc="nrbc_a", pml=None, mean=(1.0, 0.0, 0.0, 1.0), steps=20),
+    dict(name="q9_all_a_pml", q=9, Lx=44, Ly=40, bc="nrbc_a", pml=(15, 6, 0.05), mean=(1.0, 0.05, -0.03, 1.0), steps=60),
+    dict(name="q9_outlet_a", q=9, Lx=64, Ly=50, bc={"xmin": "nrbc", "xmax": "nrbc_a", "ymin": "nrbc", "ymax": "nrbc"},
+         pml=None, mean=(1.0, 0.1, 0.0, 1.0), steps=80),
     dict(name="q37_outlet_a", q=37, Lx=64, Ly=50, bc={"xmin": "nrbc", "xmax": "nrbc_a", "ymin": "nrbc", "ymax": "nrbc"},
          pml=None, mean=(1.0, 0.1, 0.0, 1.0), steps=80),
     dict(name="q37_outlet_a_pml", q=37, Lx=50, Ly=46, bc={"xmin": "zg", "xmax": "nrbc_a", "ymin": "zg", "ymax": "zg"},

@@ -11,7 +11,7 @@ from _helpers import make_pair, perm_lib_to_oracle, rel_errors, say
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("q", [37, 17])
+@pytest.mark.parametrize("q", [37, 17, 9])
 @pytest.mark.parametrize("bc,W,sigma", [("zg", 10, 0.35), ("nrbc", 0, 0.0), ("nrbc", 20, 0.1)])
 def test_density_step_geometry_parity(oracle_mod, bc, W, sigma, q):
     """FP64 library vs oracle on a shortened step (Lx = 80, Ly = 6, 60 steps)."""
@@ -79,6 +79,27 @@ def test_density_step_study_d2q17():
     assert by[("zg", 40)]["C_rho"] < 0.2 and by[("zg", 40)]["C_ux"] < 0.2
     ratio = by[("nrbc", 20)]["C_rho"] / by[("zg", 20)]["C_rho"]
     assert 1.0 / 3.0 < ratio < 3.0, ratio
+    assert all(by[(bc, W)]["C_t"] > 1.0 for bc in ("zg", "nrbc") for W in (10, 20, 40))
+
+
+def test_density_step_study_d2q9():
+    """Sec. 5.1 on D2Q9 with the paper's D2Q9 sigma_max column, 600 steps: every configuration
+    stays stable; every PML and the LODI boundary cut plain ZG's mean density and velocity
+    errors by more than 5x; ZG behind a 40-cell PML by more than 5x; and every PML costs more
+    boundary time than plain ZG.  Partly the paper's picture: its LODI gain of about two orders
+    "regardless of the stencil" is one order here (C 0.09 / 0.12).  D2Q9's energy equation is
+    not the thermal Euler system the LODI targets assume: its entropy mode decays at a quarter
+    of the shear rate, and off rest its missing third Hermite term adds O(u0 dT) fluxes (on the
+    oracle the LODI gain is 12x at Mach 0.05 and 28x at Mach 0, against 170x on D2Q17)."""
+    rows, nref = studies.density_step_study(steps=600, lattice=9)
+    for d in rows:
+        say({k: (round(v, 5) if isinstance(v, float) else v) for k, v in d.items()})
+    by = {(d["bc"], d["W"]): d for d in rows}
+    assert all(d["stable"] for d in rows)
+    for key in by:
+        if key != ("zg", 0):
+            assert by[key]["C_rho"] < 0.2 and by[key]["C_ux"] < 0.2, key
+    assert by[("zg", 40)]["C_rho"] < 0.2 and by[("zg", 40)]["C_ux"] < 0.2
     assert all(by[(bc, W)]["C_t"] > 1.0 for bc in ("zg", "nrbc") for W in (10, 20, 40))
 
 
