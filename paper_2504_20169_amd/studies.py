@@ -71,7 +71,7 @@ def density_step_study(steps=600, sample=10, Lx=200, Ly=20, mach=0.05, tau=0.8,
                        lattice=37):
     """Run every (boundary, W, sigma_max) configuration and the periodic reference in lock step.
     configs: list of (bc, W, sigma_max) or (bc, W, sigma_max, pml_terms); default: bcs x widths
-    with the paper's table for the stencil (lattice 37 or 17).
+    with the paper's table for the stencil (lattice 37, 17 or 9).
     Returns a list of dicts (bc, W, sigma_max, stable, ebar_rho, ebar_ux, emax_*, t_bc_ms, and
     C_rho, C_ux, C_t against ZG without PML when that configuration is in the list) and the
     reference's grid width."""

@@ -15,7 +15,7 @@ def say(*a):
 
 
 def perm_lib_to_oracle(oracle_mod, q=37):
-    """perm[k] = library index of the oracle's velocity k (stencil D2Q37 or D2Q17)."""
+    """perm[k] = library index of the oracle's velocity k (stencil D2Q37, D2Q17 or D2Q9)."""
     e, _, _ = lbm.lbm_velocities(q)
     eo, _, _ = oracle_mod.lattice(q)
     where = {(int(a), int(b)): i for i, (a, b) in enumerate(e)}
@@ -26,7 +26,7 @@ def make_pair(oracle_mod, Lx, Ly, tau=0.8, mean=(1.0, 0.0, 0.0, 1.0), bc=None, p
               fields=None, storage="f64", launch=None, stream=None, allocator=None, gpu=True,
               pml_terms=0, lattice=37):
     """bc: dict side->kind ('zg'|'nrbc'|'periodic') or a kind for all sides; pml: (mask, W,
-    sigma); lattice: 37 or 17.  Returns (gpu_run or None, oracle_run)."""
+    sigma); lattice: 37, 17 or 9.  Returns (gpu_run or None, oracle_run)."""
     rho0, ux0, uy0, T0 = mean
     o = oracle_mod.OracleRun(Lx, Ly, tau, rho0, ux0, uy0, T0, lattice=lattice)
     g = lbm.Run(Lx, Ly, tau, rho0, ux0, uy0, T0, storage=storage, stream=stream,

@@ -1,6 +1,6 @@
 """The studies of Sec. 5 on the GPU: FP64 parity with the oracle on the density step's own
 geometry (periodic along y, open along x, PML on the x sides only), the paper's qualitative
-accuracy claims on the full 200 x 20 density step for both stencils, and the vortex outflow
+accuracy claims on the full 200 x 20 density step for every stencil, and the vortex outflow
 of Sec. 5.2 on D2Q17 (the stencil the paper runs it on)."""
 import numpy as np
 import pytest
