@@ -1137,17 +1137,20 @@ __global__ __launch_bounds__(256) void k_phase_a(RunDev *const *__restrict__ run
     phase_a_block<S>(runs, prefix, nruns, ks, blockIdx.x);
 }
 
-// Phase A and the bulk tiles of a step in one launch: nA phase-A blocks first (their latency-bound
-// waves start first and run beside the streaming bulk tiles), then nB bulk tiles.  nA is a
-// multiple of 8, so the bulk tiles keep their XCD map.  Both paths share one register budget,
-// which the low-register boundary code keeps at the bulk kernel's occupancy.
+// Phase A and the bulk tiles of a step in one launch: h bulk tiles, the nA phase-A blocks, then
+// the other nB - h bulk tiles.  The latency-bound phase-A waves run beside streaming tiles; the
+// tiles after them keep them off the grid's tail, the tiles before them evict less of what the
+// frame kernel then reads.  nA and h are multiples of 8, so every block keeps its XCD map.  Both
+// paths share one register budget, which the low-register boundary code keeps at the bulk
+// kernel's occupancy.
 template <class S, int TX>
 __global__ __launch_bounds__(256) void k_phase_a_bulk(RunDev *const *__restrict__ runs,
                                                       const int *__restrict__ preA, int nA,
-                                                      const int *__restrict__ preB, int nB,
+                                                      const int *__restrict__ preB, int nB, int h,
                                                       int nruns, int ks) {
     const int b = blockIdx.x;
-    if (b < nA) phase_a_block<S>(runs, preA, nruns, ks, b);
+    if (b < h) bulk_tile<S, TX>(runs, preB, nruns, ks, xcd_swizzle(b, nB));
+    else if (b < h + nA) phase_a_block<S>(runs, preA, nruns, ks, b - h);
     else bulk_tile<S, TX>(runs, preB, nruns, ks, xcd_swizzle(b - nA, nB));
 }
 
@@ -1400,19 +1403,24 @@ static hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, int ks, h
 static hipError_t launch_phase_a_bulk(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s) {
     const int nA = L.blocks[CLS_A], nB = L.blocks[CLS_BULK];
     if (nA + nB <= 0) return hipSuccess;
+    // Bulk tiles ahead of the phase-A blocks: half of them for D2Q37 in FP64, where the half after
+    // phase A still outlasts its latency (1088^2 NRBC + PML: 178.5 against 185.5 us per step);
+    // none otherwise, where the shorter tiles would leave phase A on the tail (FP32 98.8 against
+    // 97.1 us, FP16 66.6 against 62.0, D2Q9 FP64 47.1 against 46.5).
+    const int h = (NQ == 37 && storage == ST_F64) ? (nB / 2) & ~7 : 0;
     const int *pa = L.prefix[CLS_A], *pb = L.prefix[CLS_BULK];
     switch (tx) {
     case 64:
         LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a_bulk<S, 64>), dim3(nA + nB), dim3(256), 0, s,
-                                                 L.runs, pa, nA, pb, nB, L.nruns, ks));
+                                                 L.runs, pa, nA, pb, nB, h, L.nruns, ks));
         break;
     case 128:
         LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a_bulk<S, 128>), dim3(nA + nB), dim3(256), 0, s,
-                                                 L.runs, pa, nA, pb, nB, L.nruns, ks));
+                                                 L.runs, pa, nA, pb, nB, h, L.nruns, ks));
         break;
     default:
         LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a_bulk<S, 256>), dim3(nA + nB), dim3(256), 0, s,
-                                                 L.runs, pa, nA, pb, nB, L.nruns, ks));
+                                                 L.runs, pa, nA, pb, nB, h, L.nruns, ks));
         break;
     }
     return hipGetLastError();
