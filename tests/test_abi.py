@@ -2,6 +2,8 @@
 arguments on the host (no device work in these tests)."""
 import os
 import re
+import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -172,3 +174,20 @@ def test_init_rejects_bad_fields():
         r.init(bad, 0.0, 0.0, 1.0)
     with pytest.raises(lbm.LbmError):
         r.init(f, 0.0, 0.0, -f)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Every step runs in the HIP library: without it the binding raises at the first call and
+    offers no CPU path (a fresh process pointed at a library file that does not exist)."""
+    code = ("from paper_2504_20169_amd import lbm\n"
+            "try:\n"
+            "    lbm.Run(16, 16, 0.8)\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n"
+            "else:\n"
+            "    print('no error')\n")
+    env = dict(os.environ, LBM_MI355X_LIB=str(tmp_path / "absent.so"))
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         timeout=120, env=env, cwd=ROOT)
+    assert res.returncode == 0, res.stderr
+    assert res.stdout.startswith("raised:") and "not built" in res.stdout, res.stdout
