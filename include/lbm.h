@@ -115,7 +115,8 @@ typedef struct {
  * boundary/PML work of a step meets the bulk kernel: 0 runs the kernels of a step in order on
  * the run's stream; 1 runs the boundary/PML chain on a side stream beside the bulk kernel (only
  * for a run that owns its stream; eager launches, no graphs); 2 launches phase A (characteristic
- * fill of the ring, PML Q update) and the bulk tiles as one grid, phase-A blocks first, so they
+ * fill of the ring, PML Q update) and the bulk tiles as one grid (the phase-A blocks after half
+ * of the tiles for D2Q37 in FP64, first otherwise), so they
  * run beside the streaming tiles (one stream, graphs and groups allowed).  All three give the
  * same bits.  Default {64, 4, 32, 2}. */
 typedef struct {

@@ -99,7 +99,7 @@ struct KernelSet {
     hipError_t (*phase_a)(const LaunchSet &L, int storage, int ks, hipStream_t s);
     hipError_t (*frame)(const LaunchSet &L, int storage, int ks, hipStream_t s);
     hipError_t (*target)(const LaunchSet &L, int storage, int ks, hipStream_t s);
-    // phase A and the bulk tiles in one launch (phase-A blocks first)
+    // phase A and the bulk tiles in one launch
     hipError_t (*phase_a_bulk)(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s);
     hipError_t (*bulk)(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s);
     // end of a batch of n sub-steps: step counters and parities advance
