@@ -1142,17 +1142,16 @@ __global__ __launch_bounds__(256) void k_phase_a(RunDev *const *__restrict__ run
 // tiles after them keep them off the grid's tail, the tiles before them evict less of what the
 // frame kernel then reads.  nA and h are multiples of 8, so every block keeps its XCD map.  Both
 // paths share one register budget, held at 4 waves per SIMD (128 VGPRs) by the low-register
-// boundary code and, for FP32/FP16 storage, the occupancy target.  In FP64
-// (D2Q37: 130 VGPRs, 3 waves) the target would spill 2 VGPRs and measured 0.5% slower at 4224^2.
+// boundary code, the branch-light block dispatch and the occupancy target.
 template <class S, int TX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 1 : 4))) void k_phase_a_bulk(RunDev *const *__restrict__ runs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_phase_a_bulk(RunDev *const *__restrict__ runs,
                                                       const int *__restrict__ preA, int nA,
                                                       const int *__restrict__ preB, int nB, int h,
                                                       int nruns, int ks) {
     const int b = blockIdx.x;
-    if (b < h) bulk_tile<S, TX>(runs, preB, nruns, ks, xcd_swizzle(b, nB));
-    else if (b < h + nA) phase_a_block<S>(runs, preA, nruns, ks, b - h);
-    else bulk_tile<S, TX>(runs, preB, nruns, ks, xcd_swizzle(b - nA, nB));
+    const int pa = b - h;   // blocks [h, h + nA) are phase A; the tiles before and after them
+    if ((unsigned)pa < (unsigned)nA) phase_a_block<S>(runs, preA, nruns, ks, pa);
+    else bulk_tile<S, TX>(runs, preB, nruns, ks, xcd_swizzle(pa < 0 ? b : b - nA, nB));
 }
 
 // End of a batch of n steps: each run advances by the sub-steps it was active for, min(n,
