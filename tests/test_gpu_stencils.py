@@ -142,6 +142,22 @@ def test_full_size_grid_in_bench_launch(oracle_mod, perm, Q):
     assert all(v <= TOL for v in err.values()), err
 
 
+def test_d2q17_full_size_large_grid(oracle_mod):
+    """The D2Q17 bench leg's large grid: 4096^2 bulk + 64-cell PML (4224^2) with ZG, default
+    launch, noisy state, 2 steps, moments compared at every node (the D2Q9 leg has no large
+    grid)."""
+    L, W, mean = 4096, 64, (1.0, 0.05, 0.0, 1.0)
+    say("case d2q17 full 4224^2")
+    g, o = make_pair(oracle_mod, L, L, bc="zg", pml=(15, W, 0.01), mean=mean,
+                     fields=noise(23, mean, 5e-4), lattice=17)
+    g.step(2)
+    o.step(2)
+    err = rel_errors(g, o, perm_lib_to_oracle(oracle_mod, 17), with_f=False)
+    say(err)
+    assert all(v <= TOL for v in err.values()), err
+    g.close()
+
+
 def test_conservation_on_gpu(Q):
     e, w, rr = lbm.lbm_velocities(Q)
     xi = rr * e.astype(float)
