@@ -56,7 +56,7 @@ def run_from_spec(lbm, spec, storage, stream=None, alloc=None, layout=0, bulk_tx
 
 
 def time_run(torch, r, steps, warmup, mode):
-    """Time `steps` steps after `warmup`.  mode 3: the configured schedule with HIP events around
+    """Time `steps` steps after `warmup`.  mode 3: the configured schedule with HIP events on
     the bulk launch of the first step of every batch of 32 (a sampled average; events around
     every launch would add a few microseconds to each step; in the fused schedule that step
     launches phase A and the bulk kernel apart, the others launch them as one grid).  mode 2: events around every bulk
@@ -89,7 +89,7 @@ def serve_trace(jobs, rate, scale, storage, tick):
 
 
 def measure(torch, lbm, r, spec, storage, steps, warmup, prof_steps):
-    """Timed pass (the configured schedule, HIP events around a sample of bulk launches) and, if
+    """Timed pass (the configured schedule, HIP events on a sample of bulk launches) and, if
     prof_steps, an in-order pass with per-class events.  Returns the result dict of one run."""
     Nx, Ny = r.grid()
     n_bulk, n_frame, n_q = r.node_classes()
@@ -489,7 +489,8 @@ def main():
             "device_copy_gbs": round(copy_gbs, 1) if copy_gbs else None,
             "frac_of_device_copy": round(R["bulk_kernel_gbs"] / copy_gbs, 4)
             if copy_gbs and R["bulk_kernel_gbs"] else None,
-            "timing": "HIP events around the k_bulk launch of the first step of every batch of 32 "
+            "timing": "HIP events attached to the k_bulk dispatch (hipExtLaunchKernelGGL) of the first "
+                      "step of every batch of 32 "
                       "(%d launches) on its stream inside the timed %d steps%s"
                       % (R["bulk_launches_timed"], args.steps,
                          "; that step launches phase A and k_bulk apart, the other steps run the "

@@ -223,9 +223,9 @@ lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path,
 
 /* Per-kernel-class timing with HIP events (the wall time of the boundary/PML kernels vs the
  * bulk kernel; Sec. 5 "Computational Cost").  mode 1: every kernel class runs in order on the
- * run's stream and events bracket each class: ms[0] bulk, ms[1] boundary/PML frame (phase B),
+ * run's stream and events time each class: ms[0] bulk, ms[1] boundary/PML frame (phase B),
  * ms[2] phase A (characteristic fill of the ring and PML auxiliary update).  mode 2: the
- * schedule lbm_launch.overlap selects, with events bracketing the bulk kernel alone, on the
+ * schedule lbm_launch.overlap selects, with events timing the bulk kernel alone, on the
  * stream it runs on (the fused schedule launches phase A and the bulk kernel apart in bracketed
  * steps); only ms[0] and launches[0] accumulate.  mode 3: as mode 2, but only the
  * bulk launch of the first step of each batch of steps (one step in lbm_launch.graph_steps, in

@@ -371,8 +371,10 @@ hipEvent_t take_event(lbm_run *h) {
 // launches phase A and the bulk tiles as one grid, so the latency-bound boundary blocks run
 // beside the streaming tiles on one stream (and in graphs).
 // Profiling (`prof` non-null): mode 1 runs the classes in order on one stream with HIP events
-// bracketing the bulk kernel (class 0), the frame kernel (class 1) and phase A (class 2); mode 2
-// launches the bulk kernel on its own (no fusion) and brackets it alone, on its stream.
+// timing the bulk kernel (class 0), the frame kernel (class 1) and phase A (class 2); mode 2
+// launches the bulk kernel on its own (no fusion) and times it alone, on its stream.  The bulk
+// kernel's events are attached to its dispatch (its own start and end); the other classes are
+// bracketed by event records.
 lbm_status enqueue_substep(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s,
                            StepStreams *ss, bool fused, lbm_run *prof) {
     const bool has_a = L.blocks[CLS_A] > 0;
@@ -399,9 +401,8 @@ lbm_status enqueue_substep(const LaunchSet &L, int storage, int tx, int ks, hipS
         if (classes && has_f) HIP_TRY(hipEventRecord(ev[2], s));
         HIP_TRY(L.ks->frame(L, storage, ks, s));
         if (classes && has_f) HIP_TRY(hipEventRecord(ev[3], s));
-        if (mode && has_b) HIP_TRY(hipEventRecord(ev[0], s));
-        HIP_TRY(L.ks->bulk(L, storage, tx, ks, s));
-        if (mode && has_b) HIP_TRY(hipEventRecord(ev[1], s));
+        HIP_TRY(L.ks->bulk(L, storage, tx, ks, s, mode && has_b ? ev[0] : nullptr,
+                           mode && has_b ? ev[1] : nullptr));
     } else {
         HIP_TRY(hipEventRecord(ss->fork, s));
         HIP_TRY(hipStreamWaitEvent(ss->side, ss->fork, 0));
@@ -409,9 +410,8 @@ lbm_status enqueue_substep(const LaunchSet &L, int storage, int tx, int ks, hipS
         HIP_TRY(L.ks->phase_a(L, storage, ks, ss->side));
         HIP_TRY(L.ks->frame(L, storage, ks, ss->side));
         HIP_TRY(hipEventRecord(ss->done, ss->side));
-        if (mode && has_b) HIP_TRY(hipEventRecord(ev[0], s));
-        HIP_TRY(L.ks->bulk(L, storage, tx, ks, s));
-        if (mode && has_b) HIP_TRY(hipEventRecord(ev[1], s));
+        HIP_TRY(L.ks->bulk(L, storage, tx, ks, s, mode && has_b ? ev[0] : nullptr,
+                           mode && has_b ? ev[1] : nullptr));
         HIP_TRY(hipStreamWaitEvent(s, ss->done, 0));
     }
     if (mode) {

@@ -101,7 +101,10 @@ struct KernelSet {
     hipError_t (*target)(const LaunchSet &L, int storage, int ks, hipStream_t s);
     // phase A and the bulk tiles in one launch
     hipError_t (*phase_a_bulk)(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s);
-    hipError_t (*bulk)(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s);
+    // bulk kernel; with events a and b (both or neither), they are attached to its dispatch and
+    // take the kernel's own start and end time
+    hipError_t (*bulk)(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s,
+                       hipEvent_t a, hipEvent_t b);
     // end of a batch of n sub-steps: step counters and parities advance
     hipError_t (*advance)(const LaunchSet &L, int n, hipStream_t s);
     hipError_t (*set_limit)(RunDev *run, long long limit, hipStream_t s);

@@ -41,6 +41,8 @@
 #include <type_traits>
 #include <utility>
 
+#include <hip/hip_ext.h>
+
 #include "lbm_internal.h"
 
 #define GLOBAL __attribute__((address_space(1)))
@@ -1382,21 +1384,23 @@ static hipError_t launch_frame(const LaunchSet &L, int storage, int ks, hipStrea
     return hipGetLastError();
 }
 
-static hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s) {
+static hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s,
+                              hipEvent_t a, hipEvent_t b) {
     const int nb = L.blocks[CLS_BULK];
     if (nb <= 0) return hipSuccess;
     const int *pre = L.prefix[CLS_BULK];
+    // events attached to the dispatch itself (no separate event packets around the kernel)
+#define LBM_BULK(TXV)                                                                              \
+    LBM_DISPATCH(storage, if (a) hipExtLaunchKernelGGL((k_bulk<S, TXV>), dim3(nb), dim3(256), 0, s, \
+                                                       a, b, 0, L.runs, pre, L.nruns, ks);        \
+                          else hipLaunchKernelGGL((k_bulk<S, TXV>), dim3(nb), dim3(256), 0, s,     \
+                                                  L.runs, pre, L.nruns, ks))
     switch (tx) {
-    case 64:
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 64>), dim3(nb), dim3(256), 0, s, L.runs, pre, L.nruns, ks));
-        break;
-    case 128:
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 128>), dim3(nb), dim3(256), 0, s, L.runs, pre, L.nruns, ks));
-        break;
-    default:
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_bulk<S, 256>), dim3(nb), dim3(256), 0, s, L.runs, pre, L.nruns, ks));
-        break;
+    case 64: LBM_BULK(64); break;
+    case 128: LBM_BULK(128); break;
+    default: LBM_BULK(256); break;
     }
+#undef LBM_BULK
     return hipGetLastError();
 }
 
