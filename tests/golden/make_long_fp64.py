@@ -1,0 +1,114 @@
+"""Write the stored oracle values for the full-length FP64 parity tests.
+
+Each fixture holds the moments (rho, ux, uy, T) of the FP64 oracle, and nothing else, at a set of
+sampled nodes after the full step count of a benchmark workload (Sec. 2 algorithm outline,
+eq. macro: the moments of the post-stream, post-boundary state).  The nodes are one full grid row
+through the initial vortex or pulse field, one full grid column inside the outflow boundary layer
+(characteristic boundary and PML corner nodes included), and 512 nodes drawn with SplitMix64 over
+the whole grid.  The GPU test runs the same workload through the C ABI and compares at these nodes.
+
+Only the oracle and the seeded input generators run here.  Usage (from the repository root):
+
+    python tests/golden/make_long_fp64.py vortex_1088     # about 15-30 min on 8 cores
+    python tests/golden/make_long_fp64.py pulses_4224_zg  # about 1-2 h on 8 cores
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2504_20169_amd import workloads as wl  # noqa: E402
+
+# name: (workload builder, boundary code of the oracle, steps, description)
+CASES = {
+    "vortex_1088": dict(
+        spec=lambda: wl.vortex_pulse(L=1024, W=32, sigma_max=0.0015, mach=0.1, bc="nrbc", seed=2),
+        bc=oracle.BC_NRBC, steps=10000,
+        text="D2Q37 FP64, 1024^2 bulk + 32-cell PML (1088^2), sigma_max 0.0015, characteristic "
+             "(LODI, perfectly non-reflecting) boundary on every side, tau 0.8, mean flow Mach "
+             "0.1 in +x, isentropic vortex (strength 0.05, radius 16) at the centre plus a "
+             "Gaussian pulse (A 1e-3, b 4) at a seeded position (seed 2), 10000 steps"),
+    "pulses_4224_zg": dict(
+        spec=lambda: wl.multi_pulse(L=4096, W=64, sigma_max=0.01, mach=0.05, bc="zg"),
+        bc=oracle.BC_ZG, steps=2000,
+        text="D2Q37 FP64, 4096^2 bulk + 64-cell PML (4224^2), sigma_max 0.01, zero-gradient "
+             "boundary on every side, tau 0.8, mean flow Mach 0.05 in +x, 8 Gaussian pulses "
+             "(b 4, A uniform in [1e-4, 1e-3], seed 3), 2000 steps"),
+}
+
+
+def sample_nodes(Nx, Ny, row, col, n_random=512, seed=12345):
+    """(x, y) of the sampled nodes: the full row `row`, the full column `col`, then n_random
+    nodes drawn with SplitMix64 (duplicates kept; they are harmless)."""
+    xs = list(range(Nx)) + [col] * Ny
+    ys = [row] * Nx + list(range(Ny))
+    u = wl.uniform(seed, 2 * n_random).reshape(n_random, 2)
+    xs += [int(a * Nx) for a in u[:, 0]]
+    ys += [int(b * Ny) for b in u[:, 1]]
+    return np.array(xs), np.array(ys)
+
+
+def fixture_path(name):
+    return os.path.join(HERE, "oracle_%s.txt" % name)
+
+
+def read_fixture(name):
+    """(header dict, x, y, rho, ux, uy, T) of a stored fixture."""
+    hdr = {}
+    rows = []
+    with open(fixture_path(name)) as f:
+        for ln in f:
+            if ln.startswith("#"):
+                if ":" in ln:
+                    k, v = ln[1:].split(":", 1)
+                    hdr[k.strip()] = v.strip()
+                continue
+            if ln.strip():
+                rows.append(ln.split())
+    a = np.array(rows, dtype=np.float64)
+    return hdr, a[:, 0].astype(int), a[:, 1].astype(int), a[:, 2], a[:, 3], a[:, 4], a[:, 5]
+
+
+def make(name):
+    case = CASES[name]
+    spec = case["spec"]()
+    o = oracle.OracleRun(spec.Lx, spec.Ly, spec.tau, spec.rho0, spec.ux0, spec.uy0, spec.T0)
+    o.set_bc(oracle.SIDE_ALL, case["bc"])
+    o.set_pml(oracle.SIDE_ALL, spec.W, spec.sigma_max)
+    o.init(*spec.fields.as_tuple())
+    Nx, Ny = o.grid()
+    t0 = time.perf_counter()
+    done = 0
+    while done < case["steps"]:
+        n = min(500, case["steps"] - done)
+        o.step(n)
+        done += n
+        print("%s: %d / %d steps, %.0f s" % (name, done, case["steps"], time.perf_counter() - t0),
+              flush=True)
+    rho, ux, uy, T = o.moments()
+    xs, ys = sample_nodes(Nx, Ny, row=Ny // 2, col=Nx - 2)
+    with open(fixture_path(name), "w") as f:
+        f.write("# Moments of the FP64 oracle (oracle/lbm_oracle.c) after the full run, at sampled\n"
+                "# nodes; written by tests/golden/make_long_fp64.py, which calls only the oracle and\n"
+                "# the seeded input generators.  Columns: x y rho ux uy T (float64, repr).\n")
+        f.write("# case: %s\n# workload: %s\n# grid: %d %d\n# steps: %d\n# oracle_threads: %d\n"
+                "# oracle_seconds: %.0f\n"
+                % (name, case["text"], Nx, Ny, case["steps"], oracle.threads(),
+                   time.perf_counter() - t0))
+        for x, y in zip(xs, ys):
+            f.write("%d %d %r %r %r %r\n" % (x, y, float(rho[y, x]), float(ux[y, x]),
+                                             float(uy[y, x]), float(T[y, x])))
+    print("wrote", fixture_path(name), flush=True)
+
+
+if __name__ == "__main__":
+    for nm in sys.argv[1:] or ["vortex_1088"]:
+        make(nm)
