@@ -8,7 +8,10 @@ Layouts: fields are row-major ``[Ny][Nx]`` float64 arrays; populations are ``[q]
 this oracle's own velocity order (``lattice(q)[0]``), which differs from the library's order.
 
 The C source is compiled once per velocity stencil (``-DORC_Q=37``, ``17`` and ``9``); every
-entry point takes the stencil as ``q`` (``lattice=`` for runs), 37 by default.
+entry point takes the stencil as ``q`` (``lattice=`` for runs), 37 by default.  A second build per
+stencil (``precision="extended"``) takes the same steps in x87 extended precision; the tests use
+it only to measure how far the double build's own rounding has carried it (its conditioning
+floor), never as a reference of its own.
 """
 from __future__ import annotations
 
@@ -23,6 +26,7 @@ _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIBS = {37: os.path.join(_HERE, "liboracle.so"), 17: os.path.join(_HERE, "liboracle17.so"),
          9: os.path.join(_HERE, "liboracle9.so")}
 LATTICES = (37, 17, 9)
+PRECISIONS = ("double", "extended")
 
 SIDE_XMIN, SIDE_XMAX, SIDE_YMIN, SIDE_YMAX, SIDE_ALL = 1, 2, 4, 8, 15
 BC_PERIODIC, BC_ZG, BC_NRBC, BC_NRBC_A = 0, 1, 2, 3
@@ -30,31 +34,36 @@ BC_PERIODIC, BC_ZG, BC_NRBC, BC_NRBC_A = 0, 1, 2, 3
 _libs = {}
 
 
-def _lib_path(q: int) -> str:
+def _lib_path(q: int, precision: str = "double") -> str:
     if q not in _LIBS:
         raise ValueError("oracle: velocity stencil must be one of %s, got %r" % (LATTICES, q))
-    return _LIBS[q]
+    if precision not in PRECISIONS:
+        raise ValueError("oracle: precision must be one of %s, got %r" % (PRECISIONS, precision))
+    return _LIBS[q] if precision == "double" else _LIBS[q][:-3] + "_ext.so"
 
 
 def build(force: bool = True) -> list:
     """Compile the oracle with gcc (-O2, no FP contraction, no fast-math, OpenMP), once per
-    velocity stencil."""
+    velocity stencil and precision."""
     out = []
     for q in LATTICES:
-        path = _lib_path(q)
-        if force or not os.path.exists(path):
-            tmp = path + ".tmp"
-            subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-                                   "-DORC_Q=%d" % q, "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
-            os.replace(tmp, path)
-        out.append(path)
+        for prec in PRECISIONS:
+            path = _lib_path(q, prec)
+            if force or not os.path.exists(path):
+                tmp = path + ".tmp"
+                extra = ["-DORC_REAL=long double"] if prec == "extended" else []
+                subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                                       "-DORC_Q=%d" % q] + extra + ["-shared", "-fPIC", "-o", tmp, _SRC,
+                                                                    "-lm"])
+                os.replace(tmp, path)
+            out.append(path)
     return out
 
 
-def _load(q: int = 37):
-    if q in _libs:
-        return _libs[q]
-    path = _lib_path(q)
+def _load(q: int = 37, precision: str = "double"):
+    if (q, precision) in _libs:
+        return _libs[(q, precision)]
+    path = _lib_path(q, precision)
     if not os.path.exists(path):
         build(force=True)
     lib = ctypes.CDLL(path)
@@ -82,7 +91,7 @@ def _load(q: int = 37):
     lib.orc_moments_of.argtypes = [dp, dp]
     lib.orc_last_error.restype = ctypes.c_char_p
     lib.orc_threads.restype = ctypes.c_int
-    _libs[q] = lib
+    _libs[(q, precision)] = lib
     return lib
 
 
@@ -129,8 +138,9 @@ class OracleRun:
     """One oracle simulation.  Mirrors the library's configuration order:
     create -> set_pml / set_bc -> init -> step ..."""
 
-    def __init__(self, Lx, Ly, tau, rho0=1.0, ux0=0.0, uy0=0.0, T0=1.0, lattice=37):
-        lib = _load(lattice)
+    def __init__(self, Lx, Ly, tau, rho0=1.0, ux0=0.0, uy0=0.0, T0=1.0, lattice=37,
+                 precision="double"):
+        lib = _load(lattice, precision)
         self.q = int(lattice)
         self._lib = lib
         self._h = lib.orc_create(int(Lx), int(Ly), float(tau), float(rho0), float(ux0),
@@ -140,7 +150,8 @@ class OracleRun:
         self.Lx, self.Ly = int(Lx), int(Ly)
 
     def _ck(self, rc):
-        _check(rc, self.q)
+        if rc != 0:
+            raise RuntimeError("oracle: " + self._lib.orc_last_error().decode())
 
     def close(self):
         if self._h:

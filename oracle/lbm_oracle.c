@@ -29,12 +29,22 @@
  * by uniform-flow invariance, symmetry, its exact reduction to the LODI boundary for plane waves
  * and the trend that it beats the LODI boundary on a vortex outflow.
  */
-#include <math.h>
+#include <tgmath.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #include <omp.h>
+
+/* Arithmetic type: double, the oracle's precision.  A build with -DORC_REAL="long double" takes the
+ * same steps in x87 extended precision (64-bit significand); the tests use that build only to
+ * measure the double build's own accumulated rounding error (a conditioning floor for the
+ * comparison with the library), never as a reference of its own.  The entry points take and
+ * return double in both builds. */
+#ifndef ORC_REAL
+#define ORC_REAL double
+#endif
+typedef ORC_REAL real;
 
 /* Velocity stencil of this compilation: ORC_Q = 37 (default), 17 or 9, one shared library each. */
 #ifndef ORC_Q
@@ -49,8 +59,8 @@
 /* ------------------------------------------------------------------------------------------ */
 
 static int    LE[NQ][2];   /* integer velocities e_i (lattice units) */
-static double LW[NQ];      /* weights w_i */
-static double LR;          /* scale r: thermal velocity xi_i = r e_i */
+static real LW[NQ];      /* weights w_i */
+static real LR;          /* scale r: thermal velocity xi_i = r e_i */
 static int    lattice_ok = 0;
 
 /* The shells by |e|^2; the grid search below over |ex|,|ey| <= 3 picks exactly these velocities
@@ -186,8 +196,8 @@ static int build_lattice(void) {
         qa = qb; ra = rb;
     }
     if (best_q < 0) return -1;
-    LR = (double)sqrtl(best_q);
-    for (int i = 0; i < NQ; ++i) LW[i] = (double)best_w[shell_of(LE[i][0], LE[i][1])];
+    LR = (real)sqrtl(best_q);
+    for (int i = 0; i < NQ; ++i) LW[i] = (real)best_w[shell_of(LE[i][0], LE[i][1])];
     lattice_ok = 1;
     return 0;
 }
@@ -199,23 +209,23 @@ static int build_lattice(void) {
 /* the theta (u.c)^2 term is (c_i^2 - 6), the value the fourth-order Hermite contraction gives  */
 /* in two dimensions; only with it are mass, momentum and energy moments exact.                 */
 /* ------------------------------------------------------------------------------------------ */
-static void feq_q(double rho, double ux, double uy, double T, double out[NQ]) {
-    double th = T - 1.0;
-    double b = ux * ux + uy * uy;
+static void feq_q(real rho, real ux, real uy, real T, real out[NQ]) {
+    real th = T - 1.0;
+    real b = ux * ux + uy * uy;
     for (int i = 0; i < NQ; ++i) {
-        double cx = LR * LE[i][0], cy = LR * LE[i][1];
-        double a = ux * cx + uy * cy;
-        double s = cx * cx + cy * cy;
-        double t1 = a;
-        double t2 = 0.5 * (a * a - b + th * (s - 2.0));
-        double t3 = (a / 6.0) * (a * a - 3.0 * b + 3.0 * th * (s - 4.0));
+        real cx = LR * LE[i][0], cy = LR * LE[i][1];
+        real a = ux * cx + uy * cy;
+        real s = cx * cx + cy * cy;
+        real t1 = a;
+        real t2 = 0.5 * (a * a - b + th * (s - 2.0));
+        real t3 = (a / 6.0) * (a * a - 3.0 * b + 3.0 * th * (s - 4.0));
 #if ORC_Q == 9
         (void)t3;
         out[i] = LW[i] * rho * (1.0 + t1 + t2);
 #elif ORC_Q == 17
         out[i] = LW[i] * rho * (1.0 + t1 + t2 + t3);
 #else
-        double t4 = (1.0 / 24.0) * (a * a * a * a - 6.0 * a * a * b + 3.0 * b * b
+        real t4 = ((real)1 / 24) * (a * a * a * a - 6.0 * a * a * b + 3.0 * b * b
                                     + 6.0 * th * (a * a * (s - 6.0) + b * (4.0 - s))
                                     + 3.0 * th * th * (s * s - 8.0 * s + 8.0));
         out[i] = LW[i] * rho * (1.0 + t1 + t2 + t3 + t4);
@@ -225,17 +235,17 @@ static void feq_q(double rho, double ux, double uy, double T, double out[NQ]) {
 
 /* Macroscopic moments, eq. macro with the ideal-gas relation e = (d/2) T, d = 2:
  * rho = sum f, rho u = sum f xi, d rho e = 2 rho T = sum f |xi - u|^2. */
-static void moments_q(const double f[NQ], double U[4]) {
-    double rho = 0.0, jx = 0.0, jy = 0.0;
+static void moments_q(const real f[NQ], real U[4]) {
+    real rho = 0.0, jx = 0.0, jy = 0.0;
     for (int i = 0; i < NQ; ++i) {
         rho += f[i];
         jx += f[i] * (LR * LE[i][0]);
         jy += f[i] * (LR * LE[i][1]);
     }
-    double ux = jx / rho, uy = jy / rho;
-    double e2 = 0.0;
+    real ux = jx / rho, uy = jy / rho;
+    real e2 = 0.0;
     for (int i = 0; i < NQ; ++i) {
-        double dx = LR * LE[i][0] - ux, dy = LR * LE[i][1] - uy;
+        real dx = LR * LE[i][0] - ux, dy = LR * LE[i][1] - uy;
         e2 += f[i] * (dx * dx + dy * dy);
     }
     U[0] = rho; U[1] = ux; U[2] = uy; U[3] = e2 / (2.0 * rho);
@@ -251,17 +261,17 @@ typedef struct orc_run {
     int Lx, Ly, Nx, Ny;
     int pml[4];
     int W;
-    double sigma_max;
+    real sigma_max;
     int bc[4];
-    double tau, rho0, ux0, uy0, T0;
+    real tau, rho0, ux0, uy0, T0;
     int ready;
     long step;
-    double *f;   /* post-collision populations f*[node][i] */
-    double *g;   /* post-stream, post-boundary populations */
-    double *Qa;  /* PML auxiliary Q[node][i], full grid (zero outside the Q region) */
-    double *U;   /* U^n = (rho, ux, uy, T) of the post-stream, post-boundary state, [node][4] */
-    double *Un;  /* U^{n+1} */
-    double fbar[NQ];
+    real *f;   /* post-collision populations f*[node][i] */
+    real *g;   /* post-stream, post-boundary populations */
+    real *Qa;  /* PML auxiliary Q[node][i], full grid (zero outside the Q region) */
+    real *U;   /* U^n = (rho, ux, uy, T) of the post-stream, post-boundary state, [node][4] */
+    real *Un;  /* U^{n+1} */
+    real fbar[NQ];
     unsigned pml_terms;   /* appendix: PML moments in the characteristic target (bits I, II, III) */
 } orc_run;
 
@@ -271,20 +281,25 @@ static int fail(const char *m) { snprintf(orc_err, sizeof orc_err, "%s", m); ret
 
 int orc_lattice(int *e, double *w, double *r) {
     if (build_lattice()) return fail("quadrature solve failed");
-    for (int i = 0; i < NQ; ++i) { e[2 * i] = LE[i][0]; e[2 * i + 1] = LE[i][1]; w[i] = LW[i]; }
-    *r = LR;
+    for (int i = 0; i < NQ; ++i) { e[2 * i] = LE[i][0]; e[2 * i + 1] = LE[i][1]; w[i] = (double)LW[i]; }
+    *r = (double)LR;
     return 0;
 }
 
 int orc_feq(double rho, double ux, double uy, double T, double *out) {
     if (build_lattice()) return fail("quadrature solve failed");
-    feq_q(rho, ux, uy, T, out);
+    real f[NQ];
+    feq_q(rho, ux, uy, T, f);
+    for (int i = 0; i < NQ; ++i) out[i] = (double)f[i];
     return 0;
 }
 
 int orc_moments_of(const double *f, double *U) {
     if (build_lattice()) return fail("quadrature solve failed");
-    moments_q(f, U);
+    real g[NQ], V[4];
+    for (int i = 0; i < NQ; ++i) g[i] = f[i];
+    moments_q(g, V);
+    for (int k = 0; k < 4; ++k) U[k] = (double)V[k];
     return 0;
 }
 
@@ -351,13 +366,13 @@ static int level_axis(int c, int n, int wlo, int whi) {
     return 0;
 }
 
-static double sigma_at(const orc_run *r, int x, int y) {
+static real sigma_at(const orc_run *r, int x, int y) {
     if (r->W == 0) return 0.0;
     int lx = level_axis(x, r->Nx, r->pml[0] ? r->W : 0, r->pml[1] ? r->W : 0);
     int ly = level_axis(y, r->Ny, r->pml[2] ? r->W : 0, r->pml[3] ? r->W : 0);
     int l = lx > ly ? lx : ly;
     if (l == 0) return 0.0;
-    double t = (double)l / (double)r->W;
+    real t = (real)l / (real)r->W;
     return r->sigma_max * t * t;
 }
 
@@ -383,11 +398,11 @@ int orc_init(orc_run *r, const double *rho, const double *ux, const double *uy, 
     geometry(r);
     if ((open_x(r) && r->Nx < 7) || (open_y(r) && r->Ny < 7)) return fail("open axis needs N >= 7");
     size_t nn = (size_t)r->Nx * r->Ny;
-    r->f = malloc(nn * NQ * sizeof(double));
-    r->g = malloc(nn * NQ * sizeof(double));
-    r->Qa = calloc(nn * NQ, sizeof(double));
-    r->U = malloc(nn * 4 * sizeof(double));
-    r->Un = malloc(nn * 4 * sizeof(double));
+    r->f = malloc(nn * NQ * sizeof(real));
+    r->g = malloc(nn * NQ * sizeof(real));
+    r->Qa = calloc(nn * NQ, sizeof(real));
+    r->U = malloc(nn * 4 * sizeof(real));
+    r->Un = malloc(nn * 4 * sizeof(real));
     if (!r->f || !r->g || !r->Qa || !r->U || !r->Un) return fail("out of memory");
     /* Sec. 2 (algorithm outline): initialise to the equilibrium of the given fields; the
      * stored state is post-collision, and U^0 is the initial field. */
@@ -415,37 +430,37 @@ int orc_init(orc_run *r, const double *rho, const double *ux, const double *uy, 
 /* S is frozen at x_b.  The foot point is limited to two cells (the U^n strips are five layers   */
 /* deep).                                                                                        */
 /* ------------------------------------------------------------------------------------------ */
-static void lodi_increment(const orc_run *r, int side, int x, int y, double dU[4]) {
+static void lodi_increment(const orc_run *r, int side, int x, int y, real dU[4]) {
     int nx = side == SIDE_XMIN ? -1 : side == SIDE_XMAX ? 1 : 0;
     int ny = side == SIDE_YMIN ? -1 : side == SIDE_YMAX ? 1 : 0;
-    double V[3][4];
+    real V[3][4];
     for (int k = 0; k < 3; ++k) {
-        const double *u = r->U + 4 * ((size_t)(y - k * ny) * r->Nx + (x - k * nx));
-        double un = nx ? nx * u[1] : ny * u[2];
-        double ut = nx ? u[2] : u[1];
+        const real *u = r->U + 4 * ((size_t)(y - k * ny) * r->Nx + (x - k * nx));
+        real un = nx ? nx * u[1] : ny * u[2];
+        real ut = nx ? u[2] : u[1];
         V[k][0] = u[0]; V[k][1] = un; V[k][2] = ut; V[k][3] = u[3];
     }
-    double rho = V[0][0], un = V[0][1], T = V[0][3];
-    double c = sqrt(2.0 * T);
-    double lam[4] = {un - c, un, un, un + c};
-    double S[16] = {T, -rho * c, 0, rho,
+    real rho = V[0][0], un = V[0][1], T = V[0][3];
+    real c = sqrt(2.0 * T);
+    real lam[4] = {un - c, un, un, un + c};
+    real S[16] = {T, -rho * c, 0, rho,
                     T, 0, 0, -rho,
                     0, 0, 1, 0,
                     T, rho * c, 0, rho};
     long double Lb[4];
     for (int k = 0; k < 4; ++k) {
-        double w[3];
+        real w[3];
         for (int j = 0; j < 3; ++j) {
             w[j] = 0.0;
             for (int m = 0; m < 4; ++m) w[j] += S[4 * k + m] * V[j][m];
         }
         if (lam[k] > 0.0) {                    /* outgoing: keep its amplitude */
-            double nu = lam[k] / LR;
+            real nu = lam[k] / LR;
             if (nu > 2.0) nu = 2.0;
             int j = (int)floor(nu);
             if (j > 1) j = 1;
-            double phi = nu - j;
-            double wfoot = (1.0 - phi) * w[j] + phi * w[j + 1];
+            real phi = nu - j;
+            real wfoot = (1.0 - phi) * w[j] + phi * w[j + 1];
             Lb[k] = LR * (w[0] - wfoot);       /* = lambda_k (S dV/dn)_k over the crossed interval */
         } else {
             Lb[k] = 0.0;                       /* incoming: eq. PNR */
@@ -455,8 +470,8 @@ static void lodi_increment(const orc_run *r, int side, int x, int y, double dU[4
     long double A[16];
     for (int k = 0; k < 16; ++k) A[k] = S[k];
     solve_ld(4, A, Lb);
-    double d[4];
-    for (int k = 0; k < 4; ++k) d[k] = -(double)Lb[k] / LR;
+    real d[4];
+    for (int k = 0; k < 4; ++k) d[k] = -(real)Lb[k] / LR;
     dU[0] = d[0];
     dU[3] = d[3];
     if (nx) { dU[1] = nx * d[1]; dU[2] = d[2]; }
@@ -465,8 +480,8 @@ static void lodi_increment(const orc_run *r, int side, int x, int y, double dU[4
 
 /* Primitive state (rho, u_a, u_b, T) of node (x, y) with u_a along the unit lattice vector
  * (ax, ay) and u_b along (bx, by). */
-static void prim_frame(const orc_run *r, int x, int y, int ax, int ay, int bx, int by, double V[4]) {
-    const double *u = r->U + 4 * ((size_t)y * r->Nx + x);
+static void prim_frame(const orc_run *r, int x, int y, int ax, int ay, int bx, int by, real V[4]) {
+    const real *u = r->U + 4 * ((size_t)y * r->Nx + x);
     V[0] = u[0];
     V[1] = ax * u[1] + ay * u[2];
     V[2] = bx * u[1] + by * u[2];
@@ -476,9 +491,9 @@ static void prim_frame(const orc_run *r, int x, int y, int ax, int ay, int bx, i
 /* Left eigenvectors of the 2-D Euler flux Jacobian along a direction, for primitive variables
  * (rho, u_along, u_across, T), p = rho T, gamma = 2, c = sqrt(2T): rows for the eigenvalues
  * u - c, u (entropy), u (shear), u + c. */
-static void left_eig(double rho, double T, double S[16]) {
-    const double c = sqrt(2.0 * T);
-    const double v[16] = {T, -rho * c, 0, rho,
+static void left_eig(real rho, real T, real S[16]) {
+    const real c = sqrt(2.0 * T);
+    const real v[16] = {T, -rho * c, 0, rho,
                           T, 0, 0, -rho,
                           0, 0, 1, 0,
                           T, rho * c, 0, rho};
@@ -486,46 +501,46 @@ static void left_eig(double rho, double T, double S[16]) {
 }
 
 /* x = S^{-1} b for a 4x4 S (generic elimination). */
-static void solve4(const double S[16], const double b[4], double x[4]) {
+static void solve4(const real S[16], const real b[4], real x[4]) {
     long double A[16], y[4];
     for (int k = 0; k < 16; ++k) A[k] = S[k];
     for (int k = 0; k < 4; ++k) y[k] = b[k];
     solve_ld(4, A, y);
-    for (int k = 0; k < 4; ++k) x[k] = (double)y[k];
+    for (int k = 0; k < 4; ++k) x[k] = (real)y[k];
 }
 
 /* Increment over one step of the edge characteristics of the states Vn[j - 2 .. j + 2] (normal
  * frame (rho, u_n, u_t, T)) at Vn[j]: each characteristic variable of the Euler flux along the
  * edge, with the eigenvectors frozen at Vn[j], moves over the interval its characteristic
  * crosses in one step (linear interpolation at the foot point, at most 2 cells). */
-static void edge_advect(const double Vn[7][4], int j, double dV[4]) {
-    const double *v = Vn[j];
-    const double rho = v[0], ut = v[2], T = v[3], c = sqrt(2.0 * T);
-    double St[16];
+static void edge_advect(const real Vn[7][4], int j, real dV[4]) {
+    const real *v = Vn[j];
+    const real rho = v[0], ut = v[2], T = v[3], c = sqrt(2.0 * T);
+    real St[16];
     left_eig(rho, T, St);
-    const double lam[4] = {ut - c, ut, ut, ut + c};
-    double dW[4];
+    const real lam[4] = {ut - c, ut, ut, ut + c};
+    real dW[4];
     for (int k = 0; k < 4; ++k) {
-        double w[5];
+        real w[5];
         for (int m = 0; m < 5; ++m) {
-            const double *u = Vn[j - 2 + m];
-            const double vt[4] = {u[0], u[2], u[1], u[3]};   /* (rho, u_t, u_n, T) */
+            const real *u = Vn[j - 2 + m];
+            const real vt[4] = {u[0], u[2], u[1], u[3]};   /* (rho, u_t, u_n, T) */
             w[m] = 0.0;
             for (int l = 0; l < 4; ++l) w[m] += St[4 * k + l] * vt[l];
         }
-        double nu = lam[k] / LR;                             /* cells per step along +t */
+        real nu = lam[k] / LR;                             /* cells per step along +t */
         if (!(nu == nu)) nu = 0.0;
         if (nu > 2.0) nu = 2.0;
         if (nu < -2.0) nu = -2.0;
-        const double a = fabs(nu);
+        const real a = fabs(nu);
         int i = (int)floor(a);
         if (i > 1) i = 1;
-        const double phi = a - i;
+        const real phi = a - i;
         const int sgn = nu > 0.0 ? -1 : 1;                   /* foot point at -nu */
         /* in differences, so that a state constant along the edge gives exactly zero */
         dW[k] = -((1.0 - phi) * (w[2] - w[2 + sgn * i]) + phi * (w[2] - w[2 + sgn * (i + 1)]));
     }
-    double dt[4];
+    real dt[4];
     solve4(St, dW, dt);
     dV[0] = dt[0]; dV[1] = dt[2]; dV[2] = dt[1]; dV[3] = dt[3];
 }
@@ -548,7 +563,7 @@ static void edge_advect(const double Vn[7][4], int j, double dV[4]) {
  *    (1 - Ma) T_inc + V_inc of them, which leaves it Ma T_inc per step (Ma = |u0|, c_s = 1).
  * Edge neighbours beyond an open edge's ends repeat the end node.  Returns the increment in the
  * global frame. */
-static void cbc_a_increment(const orc_run *r, int side, int x, int y, double dU[4]) {
+static void cbc_a_increment(const orc_run *r, int side, int x, int y, real dU[4]) {
     const int Nx = r->Nx, Ny = r->Ny;
     const int nx = side == SIDE_XMIN ? -1 : side == SIDE_XMAX ? 1 : 0;
     const int ny = side == SIDE_YMIN ? -1 : side == SIDE_YMAX ? 1 : 0;
@@ -556,65 +571,65 @@ static void cbc_a_increment(const orc_run *r, int side, int x, int y, double dU[
     const int nt = nx ? Ny : Nx, ct = nx ? y : x;
     const int topen = nx ? open_y(r) : open_x(r);
     /* states along the edge, ct - 3 .. ct + 3, in the normal frame (rho, u_n, u_t, T) */
-    double Vn[7][4];
+    real Vn[7][4];
     for (int j = -3; j <= 3; ++j) {
         int c = ct + j;
         if (topen) c = clampi(c, 0, nt - 1);
         else c = ((c % nt) + nt) % nt;
         prim_frame(r, nx ? x : c, nx ? c : y, nx, ny, tx, ty, Vn[j + 3]);
     }
-    const double rho = Vn[3][0], un = Vn[3][1], T = Vn[3][3];
-    const double c = sqrt(2.0 * T);
-    double S[16];
+    const real rho = Vn[3][0], un = Vn[3][1], T = Vn[3][3];
+    const real c = sqrt(2.0 * T);
+    real S[16];
     left_eig(rho, T, S);
-    const double lam[4] = {un - c, un, un, un + c};
+    const real lam[4] = {un - c, un, un, un + c};
     /* 1. LODI amplitudes of the outgoing normal characteristics (as lodi_increment) */
-    double D[4];
+    real D[4];
     {
-        double V[3][4];
+        real V[3][4];
         for (int k = 0; k < 3; ++k) prim_frame(r, x - k * nx, y - k * ny, nx, ny, tx, ty, V[k]);
         for (int k = 0; k < 4; ++k) {
-            double w[3];
+            real w[3];
             for (int j = 0; j < 3; ++j) {
                 w[j] = 0.0;
                 for (int m = 0; m < 4; ++m) w[j] += S[4 * k + m] * V[j][m];
             }
             D[k] = 0.0;
             if (lam[k] > 0.0) {
-                double nu = lam[k] / LR;
+                real nu = lam[k] / LR;
                 if (nu > 2.0) nu = 2.0;
                 int j = (int)floor(nu);
                 if (j > 1) j = 1;
-                double phi = nu - j;
+                real phi = nu - j;
                 D[k] = (1.0 - phi) * (w[0] - w[j]) + phi * (w[0] - w[j + 1]);
             }
         }
     }
     /* 2. transverse part at the node and its two edge neighbours, then 3. the viscous part of
      * the advected states */
-    double Va[3][4], dVT[4];
+    real Va[3][4], dVT[4];
     for (int j = -1; j <= 1; ++j) {
-        double d[4];
+        real d[4];
         edge_advect(Vn, j + 3, d);
         for (int m = 0; m < 4; ++m) Va[j + 1][m] = Vn[j + 3][m] + d[m];
         if (j == 0) memcpy(dVT, d, sizeof d);
     }
-    double dVV[4] = {0.0, 0.0, 0.0, 0.0};
+    real dVV[4] = {0.0, 0.0, 0.0, 0.0};
     if (!(topen && (ct == 0 || ct == nt - 1))) {
-        const double nuv = (r->tau - 0.5) / (LR * LR);
+        const real nuv = (r->tau - 0.5) / (LR * LR);
         dVV[1] = nuv * (Va[2][1] - 2.0 * Va[1][1] + Va[0][1]);
         dVV[2] = nuv * (Va[2][2] - 2.0 * Va[1][2] + Va[0][2]);
         dVV[3] = 2.0 * nuv * (Va[2][3] - 2.0 * Va[1][3] + Va[0][3]);
     }
     /* 4. characteristic combination: outgoing waves take LODI + T + V, incoming Ma T */
-    const double ma = sqrt(r->ux0 * r->ux0 + r->uy0 * r->uy0);
-    double dw[4];
+    const real ma = sqrt(r->ux0 * r->ux0 + r->uy0 * r->uy0);
+    real dw[4];
     for (int k = 0; k < 4; ++k) {
-        double a = 0.0, b = 0.0;
+        real a = 0.0, b = 0.0;
         for (int m = 0; m < 4; ++m) { a += S[4 * k + m] * dVT[m]; b += S[4 * k + m] * dVV[m]; }
         dw[k] = lam[k] > 0.0 ? -D[k] + a + b : ma * a;
     }
-    double d[4];
+    real d[4];
     solve4(S, dw, d);
     dU[0] = d[0];
     dU[3] = d[3];
@@ -624,11 +639,11 @@ static void cbc_a_increment(const orc_run *r, int side, int x, int y, double dU[
 
 /* d Q_i / d alpha at (x, y), alpha = 0 (x) or 1 (y): central differences, one-sided second
  * order at the outermost layer of an open axis (eqs. FD-dx-center, FD-dx-bw). */
-static double grad_q(const orc_run *r, int x, int y, int i, int al) {
+static real grad_q(const orc_run *r, int x, int y, int i, int al) {
     const int Nx = r->Nx, Ny = r->Ny;
     int c = al ? y : x, nmax = al ? Ny : Nx, op = al ? open_y(r) : open_x(r);
 #define QAT(cc) (al ? r->Qa[((size_t)(cc) * Nx + x) * NQ + i] : r->Qa[((size_t)y * Nx + (cc)) * NQ + i])
-    double d;
+    real d;
     if (op && c == 0)
         d = -0.5 * (3.0 * QAT(0) - 4.0 * QAT(1) + QAT(2));
     else if (op && c == nmax - 1)
@@ -649,26 +664,26 @@ static double grad_q(const orc_run *r, int x, int y, int i, int al) {
  * the characteristic target by s = +sigma (I + II + III), the signs printed in the appendix,
  * converted to the primitive (rho, ux, uy, T) at U^n by the chain rule.  Q and U are those of
  * level n. */
-static void pml_source(const orc_run *r, int x, int y, double dU[4]) {
+static void pml_source(const orc_run *r, int x, int y, real dU[4]) {
     dU[0] = dU[1] = dU[2] = dU[3] = 0.0;
-    const double sg = sigma_at(r, x, y);
+    const real sg = sigma_at(r, x, y);
     if (!(sg > 0.0) || !r->pml_terms) return;
     const size_t n = (size_t)y * r->Nx + x;
-    const double *u = r->U + 4 * n;
-    double fe[NQ];
+    const real *u = r->U + 4 * n;
+    real fe[NQ];
     feq_q(u[0], u[1], u[2], u[3], fe);
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    real s[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = 0; i < NQ; ++i) {
-        double xi_x = LR * LE[i][0], xi_y = LR * LE[i][1];
-        double phi[4] = {1.0, xi_x, xi_y, 0.5 * (xi_x * xi_x + xi_y * xi_y)};
-        double a = 0.0;
+        real xi_x = LR * LE[i][0], xi_y = LR * LE[i][1];
+        real phi[4] = {1.0, xi_x, xi_y, 0.5 * (xi_x * xi_x + xi_y * xi_y)};
+        real a = 0.0;
         if (r->pml_terms & 1u) a += LE[i][0] * grad_q(r, x, y, i, 0) + LE[i][1] * grad_q(r, x, y, i, 1);
         if (r->pml_terms & 2u) a += 2.0 * (fe[i] - r->fbar[i]);
         if (r->pml_terms & 4u) a += sg * r->Qa[n * NQ + i];
         for (int k = 0; k < 4; ++k) s[k] += phi[k] * a;
     }
     for (int k = 0; k < 4; ++k) s[k] *= sg;
-    const double rho = u[0], ux = u[1], uy = u[2], T = u[3];
+    const real rho = u[0], ux = u[1], uy = u[2], T = u[3];
     dU[0] = s[0];
     dU[1] = (s[1] - ux * s[0]) / rho;
     dU[2] = (s[2] - uy * s[0]) / rho;
@@ -695,7 +710,7 @@ static void one_step(orc_run *r) {
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < Ny; ++y)
         for (int x = 0; x < Nx; ++x) {
-            double *gn = r->g + ((size_t)y * Nx + x) * NQ;
+            real *gn = r->g + ((size_t)y * Nx + x) * NQ;
             for (int i = 0; i < NQ; ++i) {
                 int sx = x - LE[i][0], sy = y - LE[i][1];
                 int known = 1;
@@ -720,28 +735,28 @@ static void one_step(orc_run *r) {
             if (!bnd) continue;
             int xf = ox ? clampi(x, 3, Nx - 4) : x;
             int yf = oy ? clampi(y, 3, Ny - 4) : y;
-            const double *gf = r->g + ((size_t)yf * Nx + xf) * NQ;
-            double *gb = r->g + ((size_t)y * Nx + x) * NQ;
+            const real *gf = r->g + ((size_t)yf * Nx + xf) * NQ;
+            real *gb = r->g + ((size_t)y * Nx + x) * NQ;
             if (!nrbc) {
                 for (int i = 0; i < NQ; ++i) gb[i] = gf[i];
                 continue;
             }
-            const double *Ub = r->U + 4 * ((size_t)y * Nx + x);
-            double Ut[4] = {Ub[0], Ub[1], Ub[2], Ub[3]};
+            const real *Ub = r->U + 4 * ((size_t)y * Nx + x);
+            real Ut[4] = {Ub[0], Ub[1], Ub[2], Ub[3]};
             for (int s = 0; s < 4; ++s) {
                 if (!is_boundary_side(r, s, x, y)) continue;
-                double d[4];
+                real d[4];
                 if (r->bc[s] == BC_NRBC_A && bnd == 1) cbc_a_increment(r, s, x, y, d);
                 else if (r->bc[s] == BC_NRBC || r->bc[s] == BC_NRBC_A) lodi_increment(r, s, x, y, d);
                 else continue;
                 for (int k = 0; k < 4; ++k) Ut[k] += d[k];
             }
             {
-                double d[4];
+                real d[4];
                 pml_source(r, x, y, d);
                 for (int k = 0; k < 4; ++k) Ut[k] += d[k];
             }
-            double Uf[4], ft[NQ], ff[NQ];
+            real Uf[4], ft[NQ], ff[NQ];
             moments_q(gf, Uf);
             feq_q(Ut[0], Ut[1], Ut[2], Ut[3], ft);
             feq_q(Uf[0], Uf[1], Uf[2], Uf[3], ff);
@@ -763,11 +778,11 @@ static void one_step(orc_run *r) {
             for (int x = 0; x < Nx; ++x) {
                 if (!in_qregion(r, x, y)) continue;
                 size_t n = (size_t)y * Nx + x;
-                double e0[NQ], e1[NQ];
-                const double *u0 = r->U + 4 * n, *u1 = r->Un + 4 * n;
+                real e0[NQ], e1[NQ];
+                const real *u0 = r->U + 4 * n, *u1 = r->Un + 4 * n;
                 feq_q(u0[0], u0[1], u0[2], u0[3], e0);
                 feq_q(u1[0], u1[1], u1[2], u1[3], e1);
-                double *q = r->Qa + n * NQ;
+                real *q = r->Qa + n * NQ;
                 for (int i = 0; i < NQ; ++i)
                     q[i] = q[i] + 0.5 * ((e0[i] - r->fbar[i]) + (e1[i] - r->fbar[i]));
             }
@@ -776,21 +791,21 @@ static void one_step(orc_run *r) {
     /* 5. collision: BGK, then on PML nodes (sigma > 0) add
      *    Omega^PML = -sigma (e_i . grad Q_i + 2 fhat_i + sigma Q_i)   (eq. PMLCOLL)
      * with grad Q central, one-sided at the outermost layer of an open axis (eqs. FD-dx-*). */
-    const double inv_tau = 1.0 / r->tau;
+    const real inv_tau = 1.0 / r->tau;
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < Ny; ++y)
         for (int x = 0; x < Nx; ++x) {
             size_t n = (size_t)y * Nx + x;
-            const double *gn = r->g + n * NQ;
-            const double *u = r->Un + 4 * n;
-            double fe[NQ];
+            const real *gn = r->g + n * NQ;
+            const real *u = r->Un + 4 * n;
+            real fe[NQ];
             feq_q(u[0], u[1], u[2], u[3], fe);
-            double *fo = r->f + n * NQ;
-            double sg = sigma_at(r, x, y);
+            real *fo = r->f + n * NQ;
+            real sg = sigma_at(r, x, y);
             for (int i = 0; i < NQ; ++i) fo[i] = gn[i] - inv_tau * (gn[i] - fe[i]);
             if (sg > 0.0) {
                 for (int i = 0; i < NQ; ++i) {
-                    double d[2];
+                    real d[2];
                     for (int al = 0; al < 2; ++al) {
                         int c = al ? y : x, nmax = al ? Ny : Nx, op = al ? oy : ox;
 #define QAT(cc) (al ? r->Qa[((size_t)(cc) * Nx + x) * NQ + i] : r->Qa[((size_t)y * Nx + (cc)) * NQ + i])
@@ -805,15 +820,15 @@ static void one_step(orc_run *r) {
                         }
 #undef QAT
                     }
-                    double q = r->Qa[n * NQ + i];
-                    double fhat = fe[i] - r->fbar[i];
-                    double om = -sg * (LE[i][0] * d[0] + LE[i][1] * d[1] + 2.0 * fhat + sg * q);
+                    real q = r->Qa[n * NQ + i];
+                    real fhat = fe[i] - r->fbar[i];
+                    real om = -sg * (LE[i][0] * d[0] + LE[i][1] * d[1] + 2.0 * fhat + sg * q);
                     fo[i] = fo[i] + om;
                 }
             }
         }
 
-    double *t = r->U; r->U = r->Un; r->Un = t;
+    real *t = r->U; r->U = r->Un; r->Un = t;
     r->step += 1;
 }
 
@@ -830,11 +845,11 @@ int orc_threads(void) { return omp_get_max_threads(); }
 
 /* Moments of the current state (Sec. 2, last step of the algorithm outline): those of the
  * post-stream, post-boundary populations of the last step; at step 0 those of f*(0). */
-int orc_moments(const orc_run *r, double *rho, double *ux, double *uy, double *T) {
+static int moments_real(const orc_run *r, real *rho, real *ux, real *uy, real *T) {
     if (!r->ready) return fail("not initialised");
     size_t nn = (size_t)r->Nx * r->Ny;
     for (size_t n = 0; n < nn; ++n) {
-        double U[4];
+        real U[4];
         if (r->step == 0) moments_q(r->f + n * NQ, U);
         else memcpy(U, r->U + 4 * n, sizeof U);
         if (rho) rho[n] = U[0];
@@ -845,12 +860,28 @@ int orc_moments(const orc_run *r, double *rho, double *ux, double *uy, double *T
     return 0;
 }
 
+/* moments_real for the caller, in double. */
+int orc_moments(const orc_run *r, double *rho, double *ux, double *uy, double *T) {
+    if (!r->ready) return fail("not initialised");
+    size_t nn = (size_t)r->Nx * r->Ny;
+    for (size_t n = 0; n < nn; ++n) {
+        real U[4];
+        if (r->step == 0) moments_q(r->f + n * NQ, U);
+        else memcpy(U, r->U + 4 * n, sizeof U);
+        if (rho) rho[n] = (double)U[0];
+        if (ux) ux[n] = (double)U[1];
+        if (uy) uy[n] = (double)U[2];
+        if (T) T[n] = (double)U[3];
+    }
+    return 0;
+}
+
 /* Post-collision populations, layout [i][y][x] in this file's velocity order. */
 int orc_populations(const orc_run *r, double *out) {
     if (!r->ready) return fail("not initialised");
     size_t nn = (size_t)r->Nx * r->Ny;
     for (int i = 0; i < NQ; ++i)
-        for (size_t n = 0; n < nn; ++n) out[(size_t)i * nn + n] = r->f[n * NQ + i];
+        for (size_t n = 0; n < nn; ++n) out[(size_t)i * nn + n] = (double)r->f[n * NQ + i];
     return 0;
 }
 
@@ -858,14 +889,14 @@ int orc_pml_q(const orc_run *r, double *out) {
     if (!r->ready) return fail("not initialised");
     size_t nn = (size_t)r->Nx * r->Ny;
     for (int i = 0; i < NQ; ++i)
-        for (size_t n = 0; n < nn; ++n) out[(size_t)i * nn + n] = r->Qa[n * NQ + i];
+        for (size_t n = 0; n < nn; ++n) out[(size_t)i * nn + n] = (double)r->Qa[n * NQ + i];
     return 0;
 }
 
 int orc_sigma(orc_run *r, double *out) {
     geometry(r);
     for (int y = 0; y < r->Ny; ++y)
-        for (int x = 0; x < r->Nx; ++x) out[(size_t)y * r->Nx + x] = sigma_at(r, x, y);
+        for (int x = 0; x < r->Nx; ++x) out[(size_t)y * r->Nx + x] = (double)sigma_at(r, x, y);
     return 0;
 }
 
@@ -877,19 +908,19 @@ int orc_error_norms(const orc_run *r, const double *ref_rho, const double *ref_u
     if (!r->ready) return fail("not initialised");
     int x0 = r->pml[0] ? r->W : 0, y0 = r->pml[2] ? r->W : 0;
     size_t nn = (size_t)r->Nx * r->Ny;
-    double *rho = malloc(nn * sizeof(double)), *ux = malloc(nn * sizeof(double)),
-           *T = malloc(nn * sizeof(double));
-    orc_moments(r, rho, ux, NULL, T);
-    double s[3] = {0, 0, 0};
+    real *rho = malloc(nn * sizeof(real)), *ux = malloc(nn * sizeof(real)),
+           *T = malloc(nn * sizeof(real));
+    moments_real(r, rho, ux, NULL, T);
+    real s[3] = {0, 0, 0};
     for (int y = 0; y < r->Ly; ++y)
         for (int x = 0; x < r->Lx; ++x) {
             size_t n = (size_t)(y + y0) * r->Nx + (x + x0), m = (size_t)y * r->Lx + x;
-            double a = (rho[n] - ref_rho[m]) / ref_rho[m];
-            double b = (ux[n] - ref_ux[m]) / ref_ux[m];
-            double c = (T[n] - ref_T[m]) / ref_T[m];
+            real a = (rho[n] - ref_rho[m]) / ref_rho[m];
+            real b = (ux[n] - ref_ux[m]) / ref_ux[m];
+            real c = (T[n] - ref_T[m]) / ref_T[m];
             s[0] += a * a; s[1] += b * b; s[2] += c * c;
         }
     free(rho); free(ux); free(T);
-    for (int k = 0; k < 3; ++k) out[k] = sqrt(s[k]);
+    for (int k = 0; k < 3; ++k) out[k] = (double)sqrt(s[k]);
     return 0;
 }

@@ -1,12 +1,14 @@
 """Batched runs and the serving loop on the GPU: every run's result is bitwise the same alone,
-in a batch of uneven runs, and in the served mix; FP32/FP16 storage errors against the oracle."""
+in a batch of uneven runs, and in the served mix, and matches the FP64 oracle (FP64 members to
+the 1e-12 bar, FP32 within 1e-6, FP16 within 3% of the field's perturbation); FP32/FP16 storage
+errors against the oracle."""
 import numpy as np
 import pytest
 
 from paper_2504_20169_amd import lbm
 from paper_2504_20169_amd import workloads as wl
 from paper_2504_20169_amd.serve import Engine, GpuBackend, Job
-from _helpers import make_pair, say
+from _helpers import TOL, make_pair, say
 
 pytestmark = pytest.mark.gpu
 
@@ -25,8 +27,45 @@ def _make(L, W, bc, storage, seed):
     return r
 
 
+def _oracle_moments(oracle_mod, L, W, bc, seed, steps, sigma_max=0.01, radius=6.0, mean=(1.0, 0.1, 0.0, 1.0)):
+    """The FP64 oracle's moments for the run that _make (or the serving backend) builds."""
+    spec = wl.vortex_pulse(L=L, W=W, sigma_max=sigma_max, mach=mean[1], bc=bc, seed=seed, radius=radius)
+    o = oracle_mod.OracleRun(L, L, 0.8, *mean)
+    o.set_bc(15, {"zg": 1, "nrbc": 2}[bc])
+    if W:
+        o.set_pml(15, W, sigma_max)
+    o.init(*spec.fields.as_tuple())
+    o.step(steps)
+    return o.moments()
+
+
+# Bars against the oracle by storage: FP64 the parity bar (rho, T relative to max |Z|, u to
+# max |u|); FP32 1e-6 on the same scales; FP16 (11-bit significand on the stored deviations)
+# relative to each field's perturbation max |Z - Z_mean|, so a lost or zeroed signal fails.
+ORACLE_BAR = {"f64": TOL, "f32": 1e-6, "f16": 3e-2}
+
+
+def _oracle_errors(m, mo, storage, mean=(1.0, 0.1, 0.0, 1.0)):
+    us = max(np.abs(mo[1]).max(), np.abs(mo[2]).max())
+    if storage == "f16":
+        sc = [np.abs(mo[0] - mean[0]).max(), np.abs(mo[1] - mean[1]).max(),
+              np.abs(mo[2] - mean[2]).max(), np.abs(mo[3] - mean[3]).max()]
+        su = max(sc[1], sc[2])
+        sc = [sc[0], su, su, sc[3]]
+    else:
+        sc = [np.abs(mo[0]).max(), us, us, np.abs(mo[3]).max()]
+    return {k: float(np.abs(a - b).max() / s) for k, a, b, s in zip(("rho", "ux", "uy", "T"), m, mo, sc)}
+
+
+def _check_against_oracle(oracle_mod, r, L, W, bc, seed, steps, storage, **kw):
+    mo = _oracle_moments(oracle_mod, L, W, bc, seed, steps, **kw)
+    e = _oracle_errors(r.moments(), mo, storage)
+    say("vs oracle", storage, (L, W, bc, steps), {k: "%.2e" % v for k, v in e.items()})
+    assert all(v <= ORACLE_BAR[storage] for v in e.values()), (storage, L, W, bc, e)
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
-def test_batch_equals_alone(storage):
+def test_batch_equals_alone(oracle_mod, storage):
     alone = []
     for k, (L, W, bc, n) in enumerate(CASES):
         r = _make(L, W, bc, storage, 40 + k)
@@ -41,9 +80,10 @@ def test_batch_equals_alone(storage):
     g.step(steps=steps // 2)
     g.step(steps=steps - steps // 2)
     g.synchronize()
-    for r, a, c in zip(runs, alone, CASES):
+    for k, (r, a, c) in enumerate(zip(runs, alone, CASES)):
         assert r.step_count == c[3]
         assert np.array_equal(r.populations(), a), c
+        _check_against_oracle(oracle_mod, r, c[0], c[1], c[2], 40 + k, c[3], storage)
     # remove one member mid-way; the others continue identically
     g.remove(runs[1])
     g.step(nsteps=3)
@@ -53,7 +93,7 @@ def test_batch_equals_alone(storage):
 
 
 @pytest.mark.parametrize("gs", [0, 8])
-def test_batch_fused_schedule_equals_alone(gs):
+def test_batch_fused_schedule_equals_alone(oracle_mod, gs):
     """Phase A fused with the bulk tiles in one grid per step (eager and in graphs), over a batch
     of uneven runs with and without rings and PMLs: bitwise the runs alone."""
     alone = []
@@ -70,8 +110,9 @@ def test_batch_fused_schedule_equals_alone(gs):
     assert g.get_launch()["overlap"] == 2
     g.step(steps=np.array([c[3] for c in CASES]))
     g.synchronize()
-    for r, a, c in zip(runs, alone, CASES):
+    for k, (r, a, c) in enumerate(zip(runs, alone, CASES)):
         assert np.array_equal(r.populations(), a), c
+        _check_against_oracle(oracle_mod, r, c[0], c[1], c[2], 70 + k, c[3], "f64")
     g.close()
 
 
@@ -116,9 +157,10 @@ def test_group_graphs_and_autotune_keep_bits(storage):
         r.close()
 
 
-def test_served_results_equal_alone():
-    """Jobs arriving while others are on the GPU give bitwise the same moments as alone; a job
-    forced unstable from the host is retired as failed without disturbing the rest."""
+def test_served_results_equal_alone(oracle_mod):
+    """Jobs arriving while others are on the GPU give bitwise the same moments as alone, and
+    those moments match the FP64 oracle within the FP32 bar; a job forced unstable from the host
+    is retired as failed without disturbing the rest."""
     jobs = [Job(jid=k, L=L, W=W, steps=n * 7, bc=bc, seed=100 + k, sigma_max=0.01, arrival=0.01 * k)
             for k, (L, W, bc, n) in enumerate(CASES)]
     bad = Job(jid=99, L=40, W=6, steps=300, bc="zg", seed=7, sigma_max=80.0, arrival=0.0)
@@ -142,24 +184,26 @@ def test_served_results_equal_alone():
         ref.close()
         assert np.array_equal(rho, j.result["rho"]) and np.array_equal(ux, j.result["ux"])
         assert np.array_equal(T, j.result["T"])
+        mo = _oracle_moments(oracle_mod, j.L, j.W, j.bc, j.seed, j.steps, sigma_max=0.01,
+                             radius=min(16.0, j.L / 8.0))
+        e = _oracle_errors([j.result["rho"], j.result["ux"], j.result["uy"], j.result["T"]], mo, "f32")
+        say("served job", j.jid, "vs oracle", {k: "%.2e" % v for k, v in e.items()})
+        assert all(v <= ORACLE_BAR["f32"] for v in e.values()), (j.jid, e)
 
 
-@pytest.mark.parametrize("storage,tol_rho_u", [("f32", 1e-6), ("f16", 5e-3)])
-def test_reduced_storage_error_vs_oracle(oracle_mod, storage, tol_rho_u):
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_reduced_storage_error_vs_oracle(oracle_mod, storage):
     """FP32 / FP16 deviation storage against the FP64 oracle on the vortex + pulse workload
-    (reduced bulk, Mach 0.1, NRBC + PML), 400 steps; errors relative as in the FP64 parity."""
+    (reduced bulk, Mach 0.1, NRBC + PML), 400 steps.  FP32: within 1e-6 relative as in the FP64
+    parity.  FP16: within 3% of each field's perturbation (a zeroed signal gives 1)."""
     spec = wl.vortex_pulse(L=96, W=12, sigma_max=0.0015, mach=0.1, bc="nrbc", radius=8.0)
     g, o = make_pair(oracle_mod, 96, 96, bc="nrbc", pml=(15, 12, 0.0015), mean=(1.0, 0.1, 0.0, 1.0),
                      fields=spec.fields, storage=storage)
     g.step(400)
     o.step(400)
-    mg, mo = g.moments(), o.moments()
-    e_rho = np.abs(mg[0] - mo[0]).max() / np.abs(mo[0]).max()
-    us = max(np.abs(mo[1]).max(), np.abs(mo[2]).max())
-    e_u = max(np.abs(mg[1] - mo[1]).max(), np.abs(mg[2] - mo[2]).max()) / us
-    e_T = np.abs(mg[3] - mo[3]).max() / np.abs(mo[3]).max()
-    say(storage, "rho %.2e u %.2e T %.2e" % (e_rho, e_u, e_T))
-    assert e_rho < tol_rho_u and e_u < tol_rho_u and e_T < tol_rho_u
+    e = _oracle_errors(g.moments(), o.moments(), storage)
+    say(storage, {k: "%.2e" % v for k, v in e.items()})
+    assert all(v <= ORACLE_BAR[storage] for v in e.values()), e
 
 
 @pytest.mark.parametrize("lattice", [37, 17])

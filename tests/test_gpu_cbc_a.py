@@ -7,10 +7,9 @@ import pytest
 
 from paper_2504_20169_amd import lbm, studies
 from paper_2504_20169_amd import workloads as wl
-from _helpers import make_pair, noise, oracle_self_sensitivity, perm_lib_to_oracle, rel_errors, say
+from _helpers import TOL, assert_parity, make_pair, noise, perm_lib_to_oracle, rel_errors, say
 
 pytestmark = pytest.mark.gpu
-TOL = 1e-12
 
 CASES = [
     dict(name="q17_outlet_a", q=17, Lx=64, Ly=50, bc={"xmin": "nrbc", "xmax": "nrbc_a", "ymin": "nrbc", "ymax": "nrbc"},
@@ -44,13 +43,7 @@ def test_cbc_a_parity(oracle_mod, case):
     o.step(case["steps"])
     err = rel_errors(g, o, perm_lib_to_oracle(oracle_mod, q))
     say(case["name"], err)
-    f_tol = TOL
-    if err["f"] > TOL:
-        df, _ = oracle_self_sensitivity(oracle_mod, steps=case["steps"], lattice=q, **kw)
-        say("conditioning floor f=%.2e" % df)
-        f_tol = max(TOL, 4.0 * df)
-    bad = {k: v for k, v in err.items() if not v <= (f_tol if k == "f" else TOL)}
-    assert not bad, (err, f_tol)
+    assert_parity(err, oracle_mod, dict(kw, steps=case["steps"], lattice=q))
     g.close()
 
 
@@ -58,14 +51,14 @@ def test_cbc_a_with_pml_terms_matches_oracle(oracle_mod):
     """CBC (A) on the outlet behind a PML together with the appendix's PML moments (all
     three), both formed in the target pre-pass."""
     mean = (1.0, 0.08, 0.0, 1.0)
-    g, o = make_pair(oracle_mod, 44, 38, mean=mean, bc={"xmin": "nrbc", "xmax": "nrbc_a", "ymin": "nrbc", "ymax": "nrbc"},
-                     pml=(15, 7, 0.01), fields=noise(9, mean), pml_terms=7, lattice=17)
+    case = dict(Lx=44, Ly=38, mean=mean, bc={"xmin": "nrbc", "xmax": "nrbc_a", "ymin": "nrbc", "ymax": "nrbc"},
+                pml=(15, 7, 0.01), fields=noise(9, mean), pml_terms=7, lattice=17)
+    g, o = make_pair(oracle_mod, **case)
     g.step(30)
     o.step(30)
     e = rel_errors(g, o, perm_lib_to_oracle(oracle_mod, 17))
     say(e)
-    assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL and e["T"] < TOL
-    assert e["f"] < 1e-11
+    assert_parity(e, oracle_mod, dict(case, steps=30))
 
 
 def test_cbc_a_full_size_grid(oracle_mod):

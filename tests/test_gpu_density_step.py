@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2504_20169_amd import studies, workloads as wl
-from _helpers import make_pair, perm_lib_to_oracle, rel_errors, say
+from _helpers import assert_parity, make_pair, perm_lib_to_oracle, rel_errors, say
 
 pytestmark = pytest.mark.gpu
 
@@ -21,14 +21,14 @@ def test_density_step_geometry_parity(oracle_mod, bc, W, sigma, q):
         return wl.Fields(*studies.step_fields(Lx, Ny, W, Nx, mach))
 
     bcs = {"xmin": bc, "xmax": bc, "ymin": "periodic", "ymax": "periodic"}
-    g, o = make_pair(oracle_mod, Lx, Ly, mean=(1.0, mach, 0.0, 1.0), bc=bcs,
-                     pml=(1 | 2, W, sigma) if W else None, fields=fields, lattice=q)
+    case = dict(Lx=Lx, Ly=Ly, mean=(1.0, mach, 0.0, 1.0), bc=bcs,
+                pml=(1 | 2, W, sigma) if W else None, fields=fields, lattice=q)
+    g, o = make_pair(oracle_mod, **case)
     g.step(60)
     o.step(60)
     e = rel_errors(g, o, perm_lib_to_oracle(oracle_mod, q))
     say(bc, W, e)
-    assert e["rho"] < 1e-12 and e["ux"] < 1e-12 and e["uy"] < 1e-12 and e["T"] < 1e-12
-    assert e["f"] < 1e-11
+    assert_parity(e, oracle_mod, dict(case, steps=60))
     g.close()
 
 
