@@ -56,11 +56,10 @@ def run_from_spec(lbm, spec, storage, stream=None, alloc=None, layout=0, bulk_tx
 
 
 def time_run(torch, r, steps, warmup, mode):
-    """Time `steps` steps after `warmup`.  mode 3: the configured schedule with HIP events on
-    the bulk launch of the first step of every batch of 32 (a sampled average; events around
-    every launch would add a few microseconds to each step; in the fused schedule that step
-    launches phase A and the bulk kernel apart, the others launch them as one grid).  mode 2: events around every bulk
-    launch.  mode 1: the kernel classes in order, events around each class."""
+    """Time `steps` steps after `warmup`.  mode 3: the configured schedule with HIP events attached
+    to the dispatch of the step grid (the fused phase-A + bulk grid, or the bulk kernel) and of
+    the frame kernel on every fourth step (a sampled average; the other steps carry no events).
+    mode 1: the kernel classes in order, events on each class."""
     r.profile(0)
     r.step(warmup)
     r.synchronize()
@@ -88,30 +87,51 @@ def serve_trace(jobs, rate, scale, storage, tick):
     return rep
 
 
-def measure(torch, lbm, r, spec, storage, steps, warmup, prof_steps):
-    """Timed pass (the configured schedule, HIP events on a sample of bulk launches) and, if
-    prof_steps, an in-order pass with per-class events.  Returns the result dict of one run."""
+def kernel_bytes(storage, q, n_bulk, n_frame, n_q, fused=True):
+    """Algorithmic bytes per launch of the step grid and of the frame kernel, and per step.
+    Per step the method moves 2 q b per node and, on the nodes carrying Q, Q and U read and
+    written.  In the fused schedule the step grid holds the bulk tiles (2 q b per interior node)
+    and phase A, whose algorithmic share is the Q update: Q^n read, Q^{n+1} written and U^n read
+    per Q-region node.  The frame kernel moves 2 q b per frame node and writes U^{n+1} of the Q
+    region.  The rest of what the two kernels move is not algorithmic: phase A's pull of the
+    populations (the frame kernel pulls them again), the frame kernel's reads of Q^{n+1}, and the
+    ring's fill store and read."""
+    b2 = bytes_per_node(storage, q)
+    step = b2 * (n_bulk + n_frame) + pml_extra(storage, q) * n_q
+    grid = b2 * n_bulk + ((pml_extra(storage, q) - 32) * n_q if fused else 0)
+    return grid, step - grid, step
+
+
+def measure(torch, lbm, r, spec, storage, steps, warmup, prof_steps, fused=True):
+    """Timed pass (the configured schedule, HIP events on a sample of steps) and, if prof_steps,
+    an in-order pass with per-class events.  Returns the result dict of one run."""
     Nx, Ny = r.grid()
-    n_bulk, n_frame, n_q = r.node_classes()
+    n_bulk, n_frame, n_q, n_ring = r.node_classes()
     dt, ms_live, n_live = time_run(torch, r, steps, warmup, mode=3)
     st = r.check()
     nodes = Nx * Ny
     q = spec.lattice
-    alg_bytes_step = bytes_per_node(storage, q) * nodes + pml_extra(storage, q) * n_q
-    bulk_ms = ms_live[0] / max(n_live[0], 1)
-    bulk_bytes = bytes_per_node(storage, q) * n_bulk
+    grid_bytes, frame_bytes, step_bytes = kernel_bytes(storage, q, n_bulk, n_frame, n_q, fused)
+    grid_ms = ms_live[0] / max(n_live[0], 1)
+    frame_ms = ms_live[1] / max(n_live[1], 1)
     res = dict(
         mlups=nodes * steps / dt / 1e6, mlups_bulk=spec.Lx * spec.Ly * steps / dt / 1e6,
         ms_per_step=dt * 1e3 / steps,
-        gbs_step=alg_bytes_step / (dt / steps) / 1e9,
-        frac_step=alg_bytes_step / (dt / steps) / 1e9 / HBM_PEAK_GBS,
-        bulk_kernel_ms=bulk_ms,
-        bulk_kernel_gbs=bulk_bytes / (bulk_ms * 1e-3) / 1e9 if bulk_ms > 0 else None,
-        bulk_nodes=n_bulk, frame_nodes=n_frame, q_nodes=n_q, bulk_bytes_per_launch=bulk_bytes,
-        bulk_launches_timed=int(n_live[0]),
+        gbs_step=step_bytes / (dt / steps) / 1e9,
+        frac_step=step_bytes / (dt / steps) / 1e9 / HBM_PEAK_GBS,
+        grid_kernel_ms=grid_ms,
+        grid_gbs=grid_bytes / (grid_ms * 1e-3) / 1e9 if grid_ms > 0 else None,
+        grid_bytes_per_launch=grid_bytes,
+        frame_kernel_ms=frame_ms,
+        frame_gbs=frame_bytes / (frame_ms * 1e-3) / 1e9 if frame_ms > 0 else None,
+        frame_bytes_per_launch=frame_bytes,
+        bulk_nodes=n_bulk, frame_nodes=n_frame, q_nodes=n_q, ring_nodes=n_ring,
+        launches_timed=int(n_live[0]),
         steps=steps, stable=(st == lbm.LBM_OK))
-    if res["bulk_kernel_gbs"]:
-        res["bulk_frac"] = res["bulk_kernel_gbs"] / HBM_PEAK_GBS
+    if res["grid_gbs"]:
+        res["grid_frac"] = res["grid_gbs"] / HBM_PEAK_GBS
+    if res["frame_gbs"]:
+        res["frame_frac"] = res["frame_gbs"] / HBM_PEAK_GBS
     if prof_steps > 0:
         _, ms, n = time_run(torch, r, prof_steps, 5, mode=1)
         res["in_order"] = dict(
@@ -134,7 +154,7 @@ def large_leg(torch, lbm, wl, args):
             r = run_from_spec(lbm, spec, storage, layout=args.layout, bulk_tx=args.bulk_tx,
                               overlap=args.overlap)
             out["%s_%s" % (bc, storage)] = measure(torch, lbm, r, spec, storage, args.large_steps,
-                                                  20, args.large_steps // 2)
+                                                  20, args.large_steps // 2, args.overlap == 2)
             r.close()
             del r
     return out
@@ -151,7 +171,8 @@ def d2q9_leg(torch, lbm, wl, args):
         r = run_from_spec(lbm, spec, storage, layout=args.layout, bulk_tx=args.bulk_tx,
                           overlap=args.overlap)
         out["%dsq_%s_%s" % (spec.Nx, args.bc, storage)] = measure(
-            torch, lbm, r, spec, storage, args.d2q9_steps, args.warmup, args.d2q9_steps // 2)
+            torch, lbm, r, spec, storage, args.d2q9_steps, args.warmup, args.d2q9_steps // 2,
+            args.overlap == 2)
         r.close()
         del r
     return out
@@ -169,7 +190,8 @@ def d2q17_leg(torch, lbm, wl, args):
         r = run_from_spec(lbm, spec, storage, layout=args.layout, bulk_tx=args.bulk_tx,
                           overlap=args.overlap)
         out["%dsq_%s_%s" % (spec.Nx, args.bc, storage)] = measure(
-            torch, lbm, r, spec, storage, args.d2q17_steps, args.warmup, args.d2q17_steps // 2)
+            torch, lbm, r, spec, storage, args.d2q17_steps, args.warmup, args.d2q17_steps // 2,
+            args.overlap == 2)
         r.close()
         del r
     if args.large_steps > 0:
@@ -180,7 +202,7 @@ def d2q17_leg(torch, lbm, wl, args):
             r = run_from_spec(lbm, big, storage, layout=args.layout, bulk_tx=args.bulk_tx,
                               overlap=args.overlap)
             out["4224sq_zg_%s" % storage] = measure(torch, lbm, r, big, storage, args.large_steps,
-                                                   20, args.large_steps // 2)
+                                                   20, args.large_steps // 2, args.overlap == 2)
             r.close()
             del r
     return out
@@ -225,8 +247,13 @@ def batch_leg(torch, lbm, wl, args):
 
 KERNEL_SRC = [os.path.join(ROOT, "paper_2504_20169_amd", "csrc", n)
               for n in ("lbm_kernels.hip", "lbm_capi.hip", "lbm_internal.h", "lbm_lattice.h")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bulk_f64_1088sq_nrbc_pmc.txt")
-BULK_F64 = "void lbm::k37::k_bulk<double, 64>(lbm::RunDev* const*, int const*, int, int)"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_f64_1088sq_nrbc_pmc.txt")
+# the FP64 D2Q37 kernels whose HBM traffic the counter summary records, by short name
+TRACKED = {
+    "grid": "void lbm::k37::k_phase_a_bulk<double, 64>(lbm::RunDev* const*, int const*, int, int const*, int, int, int, int)",
+    "frame": "void lbm::k37::k_frame<double>(lbm::RunDev* const*, int const*, int, int)",
+    "bulk": "void lbm::k37::k_bulk<double, 64>(lbm::RunDev* const*, int const*, int, int)",
+}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
@@ -255,7 +282,7 @@ def pmc_means(path, counter):
 def pmc_summary(fetch_csv, write_csv, out_path, command):
     """Text summary of two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE): per-kernel KiB per
     dispatch, the scale factors from the 1 GiB device copy of --copy-calibration, and the HBM
-    bytes per launch of the FP64 bulk kernel (the roofline's `traffic`)."""
+    bytes per launch of the tracked FP64 kernels (the roofline's `traffic`)."""
     fetch, write = pmc_means(fetch_csv, "FETCH_SIZE"), pmc_means(write_csv, "WRITE_SIZE")
     gib_kib = float(1 << 20)
     cf = [v for v in fetch.get(COPY_KERNEL, []) if v > 0.25 * gib_kib]
@@ -276,11 +303,14 @@ def pmc_summary(fetch_csv, write_csv, out_path, command):
         w = sum(write[k]) / len(write[k])
         lines.append("%-72s %8d %14.1f %14.1f %14.2f" % (k[:72], len(fetch[k]), f, w,
                                                            (f * sf + w * sw) * 1024 / 1e6))
-    if BULK_F64 in fetch and BULK_F64 in write:
-        f = sum(fetch[BULK_F64]) / len(fetch[BULK_F64]) * sf * 1024
-        w = sum(write[BULK_F64]) / len(write[BULK_F64]) * sw * 1024
-        lines += ["", "traffic_bytes_per_launch: %d" % round(f + w),
-                  "traffic_read_bytes: %d" % round(f), "traffic_write_bytes: %d" % round(w)]
+    lines.append("")
+    for short, name in TRACKED.items():
+        if name in fetch and name in write:
+            f = sum(fetch[name]) / len(fetch[name]) * sf * 1024
+            w = sum(write[name]) / len(write[name]) * sw * 1024
+            lines += ["traffic_%s_bytes_per_launch: %d" % (short, round(f + w)),
+                      "traffic_%s_read_bytes: %d" % (short, round(f)),
+                      "traffic_%s_write_bytes: %d" % (short, round(w))]
     with open(out_path, "w") as fo:
         fo.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -304,9 +334,10 @@ def stats_summary(stats_csv, out_path, command, note):
     print("\n".join(lines))
 
 
-def recorded_traffic():
-    """HBM bytes per k_bulk<double> launch from the committed counter summary, or None when it
-    is missing or was taken from another version of the kernels."""
+def recorded_traffic(short):
+    """HBM bytes per launch of a tracked kernel ("grid", "frame" or "bulk") from the committed
+    counter summary, or None when it is missing or was taken from another version of the
+    kernels."""
     try:
         kv = {}
         with open(TRAFFIC_FILE) as f:
@@ -316,9 +347,72 @@ def recorded_traffic():
                     kv[k.strip()] = v.strip()
         if kv.get("kernel_source_sha256") != kernel_source_hash():
             return None
-        return int(kv["traffic_bytes_per_launch"])
+        return int(kv["traffic_%s_bytes_per_launch" % short])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def host_cpu():
+    """(model name, physical cores) of this host, from /proc/cpuinfo."""
+    model, cores = None, set()
+    try:
+        phys = core = None
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                k, _, v = ln.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and model is None:
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                elif not k and phys is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+        if phys is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    return model, (len(cores) or None)
+
+
+def roofline_entry(R, args, storage, copy_gbs):
+    """The roofline object of the bench line: the dominant kernel of the timed steps (the grid
+    of phase A and the bulk tiles in the fused schedule, else the bulk kernel), with the frame
+    kernel and the whole step beside it."""
+    fused = args.overlap == 2
+    tracked = storage == "f64" and args.L == 1024 and args.W == 32 and args.bc == "nrbc" and \
+        args.layout == 0 and args.bulk_tx == 64 and fused
+    gbs, fgbs = R.get("grid_gbs"), R.get("frame_gbs")
+    return {
+        "bound": "hbm",
+        "kernel": "k_phase_a_bulk (bulk stream-collide tiles, and phase A: the characteristic ring "
+                  "fill and the PML auxiliary update, one grid)"
+                  if fused else "k_bulk (interior stream-collide)",
+        "achieved": round(gbs, 1) if gbs else None,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(gbs / HBM_PEAK_GBS, 4) if gbs else None,
+        "traffic": recorded_traffic("grid" if fused else "bulk") if tracked else None,
+        "bytes_per_launch": R["grid_bytes_per_launch"],
+        "avg_launch_ms": round(R["grid_kernel_ms"], 5),
+        "frame_kernel": {
+            "kernel": "k_frame (collision of the boundary layers and the PML, with the PML term)",
+            "achieved": round(fgbs, 1) if fgbs else None,
+            "frac": round(fgbs / HBM_PEAK_GBS, 4) if fgbs else None,
+            "traffic": recorded_traffic("frame") if tracked else None,
+            "bytes_per_launch": R["frame_bytes_per_launch"],
+            "avg_launch_ms": round(R["frame_kernel_ms"], 5),
+        },
+        "whole_step": {"achieved": round(R["gbs_step"], 1), "frac": round(R["frac_step"], 4),
+                       "ms_per_step": round(R["ms_per_step"], 5)},
+        "device_copy_gbs": round(copy_gbs, 1) if copy_gbs else None,
+        "frac_of_device_copy": round(gbs / copy_gbs, 4) if copy_gbs and gbs else None,
+        "timing": "HIP events attached to the dispatch of the step grid and of the frame kernel "
+                  "(hipExtLaunchKernelGGL) on every fourth of the timed %d steps (%d launches each), "
+                  "on the stream they run on" % (args.steps, R["launches_timed"]),
+    }
 
 
 def cpu_baseline(wl, L, W, sigma, mach, bc, steps):
@@ -439,7 +533,7 @@ def main():
         _log("bench: storage", storage)
         r = run_from_spec(lbm, spec, storage, stream, alloc, args.layout, args.bulk_tx, args.overlap)
         results[storage] = measure(torch, lbm, r, spec, storage, args.steps, args.warmup,
-                                   args.prof_steps)
+                                   args.prof_steps, args.overlap == 2)
         if storage != "f64" and "f64" in results:
             rho_ref, ux_ref, uy_ref, T_ref = results["f64"]["_moments"]
             rho, ux, uy, T = r.moments()
@@ -475,28 +569,7 @@ def main():
             "bulk_tx": args.bulk_tx, "overlap": args.overlap,
             "device": dev.name,
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_bulk (interior fused stream-collide)",
-            "achieved": round(R["bulk_kernel_gbs"], 1) if R["bulk_kernel_gbs"] else None,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(R["bulk_kernel_gbs"] / HBM_PEAK_GBS, 4) if R["bulk_kernel_gbs"] else None,
-            "traffic": recorded_traffic() if main_s == "f64" and args.L == 1024 and args.W == 32
-                       and args.bc == "nrbc" and args.layout == 0 and args.bulk_tx == 64 else None,
-            "bytes_per_launch": R["bulk_bytes_per_launch"],
-            "avg_launch_ms": round(R["bulk_kernel_ms"], 5),
-            "device_copy_gbs": round(copy_gbs, 1) if copy_gbs else None,
-            "frac_of_device_copy": round(R["bulk_kernel_gbs"] / copy_gbs, 4)
-            if copy_gbs and R["bulk_kernel_gbs"] else None,
-            "timing": "HIP events attached to the k_bulk dispatch (hipExtLaunchKernelGGL) of the first "
-                      "step of every batch of 32 "
-                      "(%d launches) on its stream inside the timed %d steps%s"
-                      % (R["bulk_launches_timed"], args.steps,
-                         "; that step launches phase A and k_bulk apart, the other steps run the "
-                         "same bulk tiles in one grid with phase A (k_phase_a_bulk)"
-                         if args.overlap == 2 else ""),
-        },
+        "roofline": roofline_entry(R, args, main_s, copy_gbs),
         "variants": {},
     }
     def rnd(v):
@@ -521,12 +594,14 @@ def main():
                                      "HBM budget 200 GB" % (args.serve_jobs, args.serve_rate, args.serve_scale))
     if not args.no_cpu:
         _log("bench: cpu baseline (oracle)")
-        mlups_cpu, cores, dt_cpu = cpu_baseline(wl, args.L, args.W, args.sigma, args.mach, args.bc,
-                                                args.cpu_steps)
-        line["cpu_baseline"] = {"value": round(mlups_cpu, 2), "unit": "MLUPS", "cores": cores,
+        mlups_cpu, threads, dt_cpu = cpu_baseline(wl, args.L, args.W, args.sigma, args.mach, args.bc,
+                                                  args.cpu_steps)
+        model, phys = host_cpu()
+        line["cpu_baseline"] = {"value": round(mlups_cpu, 2), "unit": "MLUPS", "cores": threads,
                                 "kind": "oracle",
                                 "sample": "%d steps of the same %d^2 FP64 workload (%.1f s)"
-                                          % (args.cpu_steps, args.L + 2 * args.W, dt_cpu)}
+                                          % (args.cpu_steps, args.L + 2 * args.W, dt_cpu),
+                                "threads": threads, "physical_cores": phys, "cpu_model": model}
     print(json.dumps(line), flush=True)
 
 

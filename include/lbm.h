@@ -116,9 +116,8 @@ typedef struct {
  * the run's stream; 1 runs the boundary/PML chain on a side stream beside the bulk kernel (only
  * for a run that owns its stream; eager launches, no graphs); 2 launches phase A (characteristic
  * fill of the ring, PML Q update) and the bulk tiles as one grid (the phase-A blocks after half
- * of the tiles for D2Q37 in FP64, first otherwise), so they
- * run beside the streaming tiles (one stream, graphs and groups allowed).  All three give the
- * same bits.  Default {64, 4, 32, 2}. */
+ * of the tiles for D2Q37 in FP64, first otherwise), so they run beside the streaming tiles (one
+ * stream, graphs and groups allowed).  All three give the same bits.  Default {64, 4, 32, 2}. */
 typedef struct {
     int32_t bulk_tx, bulk_ty;
     int32_t graph_steps;
@@ -150,13 +149,19 @@ lbm_status lbm_set_bc(lbm_handle h, unsigned side_mask, lbm_bc kind);
  * Sec. 4.  Errors: LBM_ERR_ARG for bits outside 0..2; LBM_ERR_STATE after init. */
 lbm_status lbm_set_nrbc_pml_terms(lbm_handle h, unsigned flags);
 
-/* Full grid size (bulk plus PML layers) for the current configuration. */
+/* Full grid size for the current configuration: the bulk extended by W layers on each side
+ * that carries a PML, Nx = nx + W (per PML x side), Ny likewise (Sec. 3: the computational
+ * domain (L_x + 2W) x (L_y + 2W) when every side has a layer; Sec. 5 uses that layout).  Host
+ * only.  Errors: LBM_ERR_ARG for NULL pointers. */
 lbm_status lbm_grid(lbm_handle h, int32_t *Nx, int32_t *Ny);
 
-/* Node counts of the run's kernel classes for the current configuration: out[0] interior
- * nodes updated by the branch-free bulk kernel, out[1] frame nodes (boundary layers, PML and
- * moment strips) updated by the frame kernel, out[2] PML Q-region nodes (phase A). */
-lbm_status lbm_node_classes(lbm_handle h, int64_t out[3]);
+/* Node counts of the run's kernel classes for the current configuration (host only): out[0]
+ * interior nodes updated by the branch-free bulk kernel, out[1] frame nodes (boundary layers, PML
+ * and moment strips) updated by the frame kernel, out[2] nodes carrying the PML auxiliary field Q
+ * (Sec. 3: the layer plus the first bulk ring, eqs. PMLQ and FD-dx-center), out[3] boundary
+ * nodes of characteristic sides (the outer 3 layers, Sec. 4) filled by phase A.  out holds 4
+ * entries.  Errors: LBM_ERR_ARG for NULL pointers or an inconsistent configuration. */
+lbm_status lbm_node_classes(lbm_handle h, int64_t out[4]);
 
 /* Bytes of device memory the run holds once initialised (populations, PML Q, moment strips,
  * descriptor), for admission control. */
@@ -169,7 +174,12 @@ lbm_status lbm_footprint(lbm_handle h, size_t *bytes);
 lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux,
                            const double *uy, const double *T);
 
-/* Advance nsteps >= 0 time steps, asynchronously on the run's stream. */
+/* Advance nsteps >= 0 time steps (Sec. 2 algorithm outline, each step: pull streaming, eq. lbe;
+ * the outer boundary, eq. zg-bc or the characteristic fill of Sec. 4; the moments, eq. macro;
+ * the PML auxiliary update, eq. PMLQ with the trapezoid rule; the collision, BGK with
+ * eq. PMLCOLL), asynchronously on the run's stream.  Errors: LBM_ERR_ARG for nsteps < 0;
+ * LBM_ERR_STATE before lbm_init_fields or while the run is in a group; LBM_ERR_DEVICE if a
+ * launch fails (faults during the steps surface at the next synchronising call). */
 lbm_status lbm_step(lbm_handle h, int64_t nsteps);
 
 /* Steps taken since init. */
@@ -223,17 +233,16 @@ lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path,
 
 /* Per-kernel-class timing with HIP events (the wall time of the boundary/PML kernels vs the
  * bulk kernel; Sec. 5 "Computational Cost").  mode 1: every kernel class runs in order on the
- * run's stream and events time each class: ms[0] bulk, ms[1] boundary/PML frame (phase B),
- * ms[2] phase A (characteristic fill of the ring and PML auxiliary update).  mode 2: the
- * schedule lbm_launch.overlap selects, with events timing the bulk kernel alone, on the
- * stream it runs on (the fused schedule launches phase A and the bulk kernel apart in bracketed
- * steps); only ms[0] and launches[0] accumulate.  mode 3: as mode 2, but only the
- * bulk launch of the first step of each batch of steps (one step in lbm_launch.graph_steps, in
- * 32 when that is 0) is bracketed: a sampled average that leaves the other steps free of
- * events, which cost a few microseconds per bracketed launch.  mode 0 turns timing off.  Any
- * mode other than 0 makes lbm_step launch eagerly (no graphs; the same kernel sequence); a mode
- * outside 0..3 is LBM_ERR_ARG.  lbm_profile_read synchronises and returns the summed
- * milliseconds and launch counts since the last reset. */
+ * run's stream and events time each class: ms[0] bulk kernel, ms[1] frame kernel (collision of
+ * the boundary layers and the PML), ms[2] phase A (characteristic fill of the ring and PML
+ * auxiliary update).  mode 2: the schedule lbm_launch.overlap selects, with events timing its step grid in
+ * ms[0] (the grid of phase A and the bulk tiles in the fused schedule, else the bulk kernel) and
+ * the frame kernel in ms[1].  mode 3: as mode 2 on every fourth step only (a sampled average that
+ * leaves the other steps free of events).  The kernels' events are attached to their dispatch and
+ * take the kernel's own start and end.  mode 0 turns timing off.  Any mode other than 0 makes
+ * lbm_step launch eagerly (no graphs; the same kernel sequence); a mode outside 0..3 is
+ * LBM_ERR_ARG.  lbm_profile_read synchronises and returns the summed milliseconds and launch
+ * counts since the last reset. */
 lbm_status lbm_profile(lbm_handle h, int enable);
 lbm_status lbm_profile_read(lbm_handle h, double ms[3], int64_t launches[3], int reset);
 

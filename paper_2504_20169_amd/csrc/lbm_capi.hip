@@ -371,51 +371,52 @@ hipEvent_t take_event(lbm_run *h) {
 // launches phase A and the bulk tiles as one grid, so the latency-bound boundary blocks run
 // beside the streaming tiles on one stream (and in graphs).
 // Profiling (`prof` non-null): mode 1 runs the classes in order on one stream with HIP events
-// timing the bulk kernel (class 0), the frame kernel (class 1) and phase A (class 2); mode 2
-// launches the bulk kernel on its own (no fusion) and times it alone, on its stream.  The bulk
-// kernel's events are attached to its dispatch (its own start and end); the other classes are
-// bracketed by event records.
+// timing the bulk kernel (class 0), the frame kernel (class 1) and phase A (class 2); mode 2 keeps
+// the configured schedule and times its step grid (class 0: the fused phase-A + bulk grid, or the
+// bulk kernel) and the frame kernel (class 1); mode 3 does so on every fourth sub-step only.  The
+// events of the kernels are attached to their dispatch (their own start and end); phase A in
+// mode 1 is bracketed by event records.
 lbm_status enqueue_substep(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s,
                            StepStreams *ss, bool fused, lbm_run *prof) {
     const bool has_a = L.blocks[CLS_A] > 0;
     const bool has_f = L.blocks[CLS_FRAME] > 0;
     const bool has_b = L.blocks[CLS_BULK] > 0;
-    // mode 3 samples mode 2 on the first sub-step of each batch only
     const int pm = prof ? prof->prof : 0;
-    const int mode = pm == 3 ? (ks == 0 ? 2 : 0) : pm;
+    const int mode = pm == 3 ? ((ks & 3) == 0 ? 2 : 0) : pm;
     hipEvent_t ev[6] = {};
     if (mode) {
         harvest_events(prof, false);
         for (int k = 0; k < 6; ++k) ev[k] = take_event(prof);
     }
     const bool classes = mode == 1;
-    if (fused && !mode && (!ss || !ss->ok)) {
+    const bool side = ss && ss->ok && !classes;
+    const bool grid = fused && !classes && !side;   // phase A and the bulk tiles in one grid
+    const bool t0 = mode && (grid ? (has_a || has_b) : has_b), t1 = mode && has_f;
+    hipEvent_t a0 = t0 ? ev[0] : nullptr, b0 = t0 ? ev[1] : nullptr;
+    hipEvent_t a1 = t1 ? ev[2] : nullptr, b1 = t1 ? ev[3] : nullptr;
+    if (grid) {
         HIP_TRY(L.ks->target(L, storage, ks, s));
-        HIP_TRY(L.ks->phase_a_bulk(L, storage, tx, ks, s));
-        HIP_TRY(L.ks->frame(L, storage, ks, s));
-    } else if (!ss || !ss->ok || classes) {
+        HIP_TRY(L.ks->phase_a_bulk(L, storage, tx, ks, s, a0, b0));
+        HIP_TRY(L.ks->frame(L, storage, ks, s, a1, b1));
+    } else if (!side) {
         if (classes && has_a) HIP_TRY(hipEventRecord(ev[4], s));
         HIP_TRY(L.ks->target(L, storage, ks, s));
         HIP_TRY(L.ks->phase_a(L, storage, ks, s));
         if (classes && has_a) HIP_TRY(hipEventRecord(ev[5], s));
-        if (classes && has_f) HIP_TRY(hipEventRecord(ev[2], s));
-        HIP_TRY(L.ks->frame(L, storage, ks, s));
-        if (classes && has_f) HIP_TRY(hipEventRecord(ev[3], s));
-        HIP_TRY(L.ks->bulk(L, storage, tx, ks, s, mode && has_b ? ev[0] : nullptr,
-                           mode && has_b ? ev[1] : nullptr));
+        HIP_TRY(L.ks->frame(L, storage, ks, s, a1, b1));
+        HIP_TRY(L.ks->bulk(L, storage, tx, ks, s, a0, b0));
     } else {
         HIP_TRY(hipEventRecord(ss->fork, s));
         HIP_TRY(hipStreamWaitEvent(ss->side, ss->fork, 0));
         HIP_TRY(L.ks->target(L, storage, ks, ss->side));
         HIP_TRY(L.ks->phase_a(L, storage, ks, ss->side));
-        HIP_TRY(L.ks->frame(L, storage, ks, ss->side));
+        HIP_TRY(L.ks->frame(L, storage, ks, ss->side, a1, b1));
         HIP_TRY(hipEventRecord(ss->done, ss->side));
-        HIP_TRY(L.ks->bulk(L, storage, tx, ks, s, mode && has_b ? ev[0] : nullptr,
-                           mode && has_b ? ev[1] : nullptr));
+        HIP_TRY(L.ks->bulk(L, storage, tx, ks, s, a0, b0));
         HIP_TRY(hipStreamWaitEvent(s, ss->done, 0));
     }
     if (mode) {
-        const bool used[3] = {has_b, classes && has_f, classes && has_a};
+        const bool used[3] = {t0, t1, classes && has_a};
         for (int c = 0; c < 3; ++c) {
             if (used[c]) prof->pending.push_back({ev[2 * c], ev[2 * c + 1], c});
             else { prof->pool.push_back(ev[2 * c]); prof->pool.push_back(ev[2 * c + 1]); }
@@ -607,7 +608,7 @@ lbm_status lbm_footprint(lbm_handle h, size_t *bytes) {
     return LBM_OK;
 }
 
-lbm_status lbm_node_classes(lbm_handle h, int64_t out[3]) {
+lbm_status lbm_node_classes(lbm_handle h, int64_t out[4]) {
     if (!h || !out) return fail(LBM_ERR_ARG, "NULL argument");
     RunDev R{};
     lbm_status st = setup_geometry(h, R);
@@ -621,6 +622,7 @@ lbm_status lbm_node_classes(lbm_handle h, int64_t out[3]) {
                 q += (R.Wxm > 0 && x < R.qd) || (R.Wxp > 0 && x >= R.Nx - R.qd) ||
                      (R.Wym > 0 && y < R.qd) || (R.Wyp > 0 && y >= R.Ny - R.qd);
     out[2] = q;
+    out[3] = R.ring_n;
     return LBM_OK;
 }
 
@@ -921,7 +923,7 @@ void lbm_destroy(lbm_handle h) {
 namespace {
 struct CkptHeader {
     char magic[8];
-    int32_t version, Nx, Ny, storage, W, pml[4], bc[4], par, layout, lattice;
+    int32_t version, Nx, Ny, storage, W, pml[4], bc[4], par, layout, lattice, pml_terms, pad_;
     int64_t steps, plane, qplane;
     double tau, rho0, ux0, uy0, T0, sigma_max, scale;
     uint64_t checksum;
@@ -946,9 +948,9 @@ lbm_status lbm_save(lbm_handle h, const char *path) {
     for (int b = 0; b < 2; ++b) { HIP_TRY(hipMemcpy(p, R.U[b], ub, hipMemcpyDeviceToHost)); p += ub; }
     if (gb) { HIP_TRY(hipMemcpy(p, R.G, gb, hipMemcpyDeviceToHost)); p += gb; }
     CkptHeader hdr{};
-    std::memcpy(hdr.magic, "LBMPML03", 8);
-    hdr.version = 3; hdr.Nx = R.Nx; hdr.Ny = R.Ny; hdr.storage = storage; hdr.W = h->W;
-    hdr.layout = h->desc.layout; hdr.lattice = h->lat->q;
+    std::memcpy(hdr.magic, "LBMPML04", 8);
+    hdr.version = 4; hdr.Nx = R.Nx; hdr.Ny = R.Ny; hdr.storage = storage; hdr.W = h->W;
+    hdr.layout = h->desc.layout; hdr.lattice = h->lat->q; hdr.pml_terms = (int32_t)h->pml_terms;
     for (int s = 0; s < 4; ++s) { hdr.pml[s] = h->pml[s]; hdr.bc[s] = h->bc[s]; }
     hdr.par = R.par; hdr.steps = h->steps; hdr.plane = R.plane; hdr.qplane = R.qplane;
     hdr.tau = h->desc.tau; hdr.rho0 = h->desc.rho0; hdr.ux0 = h->desc.ux0; hdr.uy0 = h->desc.uy0;
@@ -969,7 +971,7 @@ lbm_status lbm_load(lbm_handle h, const char *path) {
     FILE *fp = std::fopen(path, "rb");
     if (!fp) return fail(LBM_ERR_ARG, std::string("cannot open ") + path);
     CkptHeader hdr{};
-    if (std::fread(&hdr, sizeof hdr, 1, fp) != 1 || std::memcmp(hdr.magic, "LBMPML03", 8) != 0) {
+    if (std::fread(&hdr, sizeof hdr, 1, fp) != 1 || std::memcmp(hdr.magic, "LBMPML04", 8) != 0) {
         std::fclose(fp);
         return fail(LBM_ERR_ARG, "not a checkpoint file");
     }
@@ -979,7 +981,8 @@ lbm_status lbm_load(lbm_handle h, const char *path) {
                 hdr.layout == h->desc.layout && hdr.lattice == h->lat->q &&
                 hdr.plane == R.plane && hdr.qplane == R.qplane && hdr.tau == h->desc.tau &&
                 hdr.rho0 == h->desc.rho0 && hdr.ux0 == h->desc.ux0 && hdr.uy0 == h->desc.uy0 &&
-                hdr.T0 == h->desc.T0 && hdr.sigma_max == h->sigma_max;
+                hdr.T0 == h->desc.T0 && hdr.sigma_max == h->sigma_max &&
+                hdr.pml_terms == (int32_t)h->pml_terms;
     for (int s = 0; s < 4; ++s) same = same && hdr.pml[s] == h->pml[s] && hdr.bc[s] == h->bc[s];
     if (!same) { std::fclose(fp); return fail(LBM_ERR_ARG, "checkpoint configuration differs from the handle's"); }
     size_t fb = (size_t)R.fsize * elem_size(storage);

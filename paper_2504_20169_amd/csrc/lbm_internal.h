@@ -97,12 +97,14 @@ struct KernelSet {
     int q;
     // step kernels of sub-step ks of a batch (parity par + ks; active while step + ks < limit)
     hipError_t (*phase_a)(const LaunchSet &L, int storage, int ks, hipStream_t s);
-    hipError_t (*frame)(const LaunchSet &L, int storage, int ks, hipStream_t s);
+    // frame, phase_a_bulk and bulk take optional events a and b (both or neither), attached to
+    // the dispatch: they take the kernel's own start and end time
+    hipError_t (*frame)(const LaunchSet &L, int storage, int ks, hipStream_t s, hipEvent_t a,
+                        hipEvent_t b);
     hipError_t (*target)(const LaunchSet &L, int storage, int ks, hipStream_t s);
     // phase A and the bulk tiles in one launch
-    hipError_t (*phase_a_bulk)(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s);
-    // bulk kernel; with events a and b (both or neither), they are attached to its dispatch and
-    // take the kernel's own start and end time
+    hipError_t (*phase_a_bulk)(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s,
+                               hipEvent_t a, hipEvent_t b);
     hipError_t (*bulk)(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s,
                        hipEvent_t a, hipEvent_t b);
     // end of a batch of n sub-steps: step counters and parities advance

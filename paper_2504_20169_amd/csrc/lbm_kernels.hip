@@ -1377,10 +1377,15 @@ static hipError_t launch_target(const LaunchSet &L, int storage, int ks, hipStre
     return hipGetLastError();
 }
 
-static hipError_t launch_frame(const LaunchSet &L, int storage, int ks, hipStream_t s) {
-    if (L.blocks[CLS_FRAME] > 0)
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_frame<S>), dim3(L.blocks[CLS_FRAME]), dim3(256), 0, s,
-                                                 L.runs, L.prefix[CLS_FRAME], L.nruns, ks));
+static hipError_t launch_frame(const LaunchSet &L, int storage, int ks, hipStream_t s, hipEvent_t a,
+                               hipEvent_t b) {
+    const int nb = L.blocks[CLS_FRAME];
+    if (nb <= 0) return hipSuccess;
+    const int *pre = L.prefix[CLS_FRAME];
+    LBM_DISPATCH(storage, if (a) hipExtLaunchKernelGGL((k_frame<S>), dim3(nb), dim3(256), 0, s, a, b, 0,
+                                                       L.runs, pre, L.nruns, ks);
+                          else hipLaunchKernelGGL((k_frame<S>), dim3(nb), dim3(256), 0, s, L.runs, pre,
+                                                  L.nruns, ks));
     return hipGetLastError();
 }
 
@@ -1404,7 +1409,8 @@ static hipError_t launch_bulk(const LaunchSet &L, int storage, int tx, int ks, h
     return hipGetLastError();
 }
 
-static hipError_t launch_phase_a_bulk(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s) {
+static hipError_t launch_phase_a_bulk(const LaunchSet &L, int storage, int tx, int ks, hipStream_t s,
+                                      hipEvent_t a, hipEvent_t b) {
     const int nA = L.blocks[CLS_A], nB = L.blocks[CLS_BULK];
     if (nA + nB <= 0) return hipSuccess;
     // Bulk tiles ahead of the phase-A blocks: half of them for D2Q37 in FP64, where the half after
@@ -1413,20 +1419,18 @@ static hipError_t launch_phase_a_bulk(const LaunchSet &L, int storage, int tx, i
     // 97.1 us, FP16 66.6 against 62.0, D2Q9 FP64 47.1 against 46.5).
     const int h = (NQ == 37 && storage == ST_F64) ? (nB / 2) & ~7 : 0;
     const int *pa = L.prefix[CLS_A], *pb = L.prefix[CLS_BULK];
+#define LBM_PAB(TXV)                                                                               \
+    LBM_DISPATCH(storage, if (a) hipExtLaunchKernelGGL((k_phase_a_bulk<S, TXV>), dim3(nA + nB), dim3(256), \
+                                                       0, s, a, b, 0, L.runs, pa, nA, pb, nB, h,   \
+                                                       L.nruns, ks);                               \
+                          else hipLaunchKernelGGL((k_phase_a_bulk<S, TXV>), dim3(nA + nB), dim3(256), \
+                                                  0, s, L.runs, pa, nA, pb, nB, h, L.nruns, ks))
     switch (tx) {
-    case 64:
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a_bulk<S, 64>), dim3(nA + nB), dim3(256), 0, s,
-                                                 L.runs, pa, nA, pb, nB, h, L.nruns, ks));
-        break;
-    case 128:
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a_bulk<S, 128>), dim3(nA + nB), dim3(256), 0, s,
-                                                 L.runs, pa, nA, pb, nB, h, L.nruns, ks));
-        break;
-    default:
-        LBM_DISPATCH(storage, hipLaunchKernelGGL((k_phase_a_bulk<S, 256>), dim3(nA + nB), dim3(256), 0, s,
-                                                 L.runs, pa, nA, pb, nB, h, L.nruns, ks));
-        break;
+    case 64: LBM_PAB(64); break;
+    case 128: LBM_PAB(128); break;
+    default: LBM_PAB(256); break;
     }
+#undef LBM_PAB
     return hipGetLastError();
 }
 

@@ -161,15 +161,28 @@ def lbm_velocities(lattice=37):
     return e.astype(np.int64), w, r.value
 
 
-def torch_allocator():
-    """Allocator hook that takes device memory from PyTorch's caching allocator."""
+def torch_allocator(stream=None):
+    """Allocator hook that takes device memory from PyTorch's caching allocator.
+
+    The caching allocator hands out a block as soon as its last use has been queued on the stream
+    it was allocated on, so the block is safe only for work ordered after that stream's queue.
+    With ``stream`` (the torch stream the run or group will use, the same object passed as their
+    ``stream=``) the blocks are allocated on that stream, and the library's work on it is ordered
+    after every earlier use.  Without it the blocks come from the current stream, which is
+    synchronised before the block is handed over, so work queued on any stream may use it.  The
+    library frees a block only after its own stream has drained."""
     import torch
 
     live = {}
 
     def _alloc(nbytes, ctx):
         try:
-            t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+            if stream is not None:
+                with torch.cuda.stream(stream):
+                    t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+            else:
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+                torch.cuda.current_stream().synchronize()
         except RuntimeError:
             return None
         ptr = t.data_ptr()
@@ -244,8 +257,8 @@ class Run:
         return b.value
 
     def node_classes(self):
-        """(bulk-kernel nodes, frame-kernel nodes, PML Q-region nodes)."""
-        out = np.zeros(3, dtype=np.int64)
+        """(bulk-kernel nodes, frame-kernel nodes, PML Q-region nodes, characteristic ring nodes)."""
+        out = np.zeros(4, dtype=np.int64)
         _check(self._lib.lbm_node_classes(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
         return tuple(int(v) for v in out)
 

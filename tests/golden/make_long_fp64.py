@@ -9,8 +9,13 @@ the whole grid.  The GPU test runs the same workload through the C ABI and compa
 
 Only the oracle and the seeded input generators run here.  Usage (from the repository root):
 
-    python tests/golden/make_long_fp64.py vortex_1088     # about 15-30 min on 8 cores
-    python tests/golden/make_long_fp64.py pulses_4224_zg  # about 1-2 h on 8 cores
+    python tests/golden/make_long_fp64.py vortex_1088            # about 30 min on 8 cores
+    python tests/golden/make_long_fp64.py vortex_1088 extended   # the same steps in x87 extended
+                                                                 # precision, about 1-2 h
+
+The extended-precision fixture measures how far the double oracle's own rounding has carried it
+over the run (its conditioning floor at these nodes); the library is compared with the double
+fixture.
 """
 from __future__ import annotations
 
@@ -56,15 +61,15 @@ def sample_nodes(Nx, Ny, row, col, n_random=512, seed=12345):
     return np.array(xs), np.array(ys)
 
 
-def fixture_path(name):
-    return os.path.join(HERE, "oracle_%s.txt" % name)
+def fixture_path(name, precision="double"):
+    return os.path.join(HERE, "oracle_%s%s.txt" % (name, "" if precision == "double" else "_ext"))
 
 
-def read_fixture(name):
+def read_fixture(name, precision="double"):
     """(header dict, x, y, rho, ux, uy, T) of a stored fixture."""
     hdr = {}
     rows = []
-    with open(fixture_path(name)) as f:
+    with open(fixture_path(name, precision)) as f:
         for ln in f:
             if ln.startswith("#"):
                 if ":" in ln:
@@ -77,10 +82,11 @@ def read_fixture(name):
     return hdr, a[:, 0].astype(int), a[:, 1].astype(int), a[:, 2], a[:, 3], a[:, 4], a[:, 5]
 
 
-def make(name):
+def make(name, precision="double"):
     case = CASES[name]
     spec = case["spec"]()
-    o = oracle.OracleRun(spec.Lx, spec.Ly, spec.tau, spec.rho0, spec.ux0, spec.uy0, spec.T0)
+    o = oracle.OracleRun(spec.Lx, spec.Ly, spec.tau, spec.rho0, spec.ux0, spec.uy0, spec.T0,
+                         precision=precision)
     o.set_bc(oracle.SIDE_ALL, case["bc"])
     o.set_pml(oracle.SIDE_ALL, spec.W, spec.sigma_max)
     o.init(*spec.fields.as_tuple())
@@ -95,20 +101,21 @@ def make(name):
               flush=True)
     rho, ux, uy, T = o.moments()
     xs, ys = sample_nodes(Nx, Ny, row=Ny // 2, col=Nx - 2)
-    with open(fixture_path(name), "w") as f:
-        f.write("# Moments of the FP64 oracle (oracle/lbm_oracle.c) after the full run, at sampled\n"
-                "# nodes; written by tests/golden/make_long_fp64.py, which calls only the oracle and\n"
-                "# the seeded input generators.  Columns: x y rho ux uy T (float64, repr).\n")
-        f.write("# case: %s\n# workload: %s\n# grid: %d %d\n# steps: %d\n# oracle_threads: %d\n"
-                "# oracle_seconds: %.0f\n"
-                % (name, case["text"], Nx, Ny, case["steps"], oracle.threads(),
+    with open(fixture_path(name, precision), "w") as f:
+        f.write("# Moments of the oracle (oracle/lbm_oracle.c, %s build) after the full run, at\n"
+                "# sampled nodes; written by tests/golden/make_long_fp64.py, which calls only the\n"
+                "# oracle and the seeded input generators.  Columns: x y rho ux uy T (float64, repr).\n"
+                % precision)
+        f.write("# case: %s\n# precision: %s\n# workload: %s\n# grid: %d %d\n# steps: %d\n"
+                "# oracle_threads: %d\n# oracle_seconds: %.0f\n"
+                % (name, precision, case["text"], Nx, Ny, case["steps"], oracle.threads(),
                    time.perf_counter() - t0))
         for x, y in zip(xs, ys):
             f.write("%d %d %r %r %r %r\n" % (x, y, float(rho[y, x]), float(ux[y, x]),
                                              float(uy[y, x]), float(T[y, x])))
-    print("wrote", fixture_path(name), flush=True)
+    print("wrote", fixture_path(name, precision), flush=True)
 
 
 if __name__ == "__main__":
-    for nm in sys.argv[1:] or ["vortex_1088"]:
-        make(nm)
+    make(sys.argv[1] if len(sys.argv) > 1 else "vortex_1088",
+         sys.argv[2] if len(sys.argv) > 2 else "double")

@@ -27,23 +27,25 @@ def test_pmc_summary_scales_by_the_copy_calibration(tmp_path):
     the bulk kernel's bytes per launch are its mean counters times those scales."""
     gib_kib = float(1 << 20)
     fetch, write = tmp_path / "f.csv", tmp_path / "w.csv"
-    _pmc_csv(fetch, "FETCH_SIZE", [(bench.COPY_KERNEL, gib_kib / 2), (bench.BULK_F64, 1000.0),
-                                   (bench.BULK_F64, 1002.0), ("other", 5.0)])
-    _pmc_csv(write, "WRITE_SIZE", [(bench.COPY_KERNEL, gib_kib), (bench.BULK_F64, 3000.0),
-                                   (bench.BULK_F64, 3000.0), ("other", 1.0)])
+    G = bench.TRACKED["grid"]
+    _pmc_csv(fetch, "FETCH_SIZE", [(bench.COPY_KERNEL, gib_kib / 2), (G, 1000.0),
+                                   (G, 1002.0), ("other", 5.0)])
+    _pmc_csv(write, "WRITE_SIZE", [(bench.COPY_KERNEL, gib_kib), (G, 3000.0),
+                                   (G, 3000.0), ("other", 1.0)])
     out = tmp_path / "sum.txt"
     bench.pmc_summary(str(fetch), str(write), str(out), "cmd")
     kv = dict(l.split(":", 1) for l in open(out) if ":" in l and not l.startswith("#"))
-    assert int(kv["traffic_read_bytes"]) == round(1001.0 * 2 * 1024)
-    assert int(kv["traffic_write_bytes"]) == round(3000.0 * 1024)
-    assert int(kv["traffic_bytes_per_launch"]) == round(1001.0 * 2 * 1024) + round(3000.0 * 1024)
+    assert int(kv["traffic_grid_read_bytes"]) == round(1001.0 * 2 * 1024)
+    assert int(kv["traffic_grid_write_bytes"]) == round(3000.0 * 1024)
+    assert int(kv["traffic_grid_bytes_per_launch"]) == round(1001.0 * 2 * 1024) + round(3000.0 * 1024)
+    assert "traffic_frame_bytes_per_launch" not in kv
     assert kv["kernel_source_sha256"].strip() == bench.kernel_source_hash()
 
 
 def test_pmc_summary_needs_the_calibration_copy(tmp_path):
     fetch, write = tmp_path / "f.csv", tmp_path / "w.csv"
-    _pmc_csv(fetch, "FETCH_SIZE", [(bench.BULK_F64, 1000.0)])
-    _pmc_csv(write, "WRITE_SIZE", [(bench.BULK_F64, 3000.0)])
+    _pmc_csv(fetch, "FETCH_SIZE", [(bench.TRACKED["grid"], 1000.0)])
+    _pmc_csv(write, "WRITE_SIZE", [(bench.TRACKED["grid"], 3000.0)])
     with pytest.raises(SystemExit):
         bench.pmc_summary(str(fetch), str(write), str(tmp_path / "o.txt"), "cmd")
 
@@ -51,13 +53,14 @@ def test_pmc_summary_needs_the_calibration_copy(tmp_path):
 def test_recorded_traffic_is_tied_to_the_kernel_sources(tmp_path, monkeypatch):
     """The committed counter summary counts only for the kernel sources it was taken from."""
     f = tmp_path / "t.txt"
-    f.write_text("kernel_source_sha256: %s\ntraffic_bytes_per_launch: 1234\n" % bench.kernel_source_hash())
+    f.write_text("kernel_source_sha256: %s\ntraffic_grid_bytes_per_launch: 1234\n" % bench.kernel_source_hash())
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    assert bench.recorded_traffic() == 1234
-    f.write_text("kernel_source_sha256: 0000000000000000\ntraffic_bytes_per_launch: 1234\n")
-    assert bench.recorded_traffic() is None
+    assert bench.recorded_traffic("grid") == 1234
+    assert bench.recorded_traffic("frame") is None
+    f.write_text("kernel_source_sha256: 0000000000000000\ntraffic_grid_bytes_per_launch: 1234\n")
+    assert bench.recorded_traffic("grid") is None
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
-    assert bench.recorded_traffic() is None
+    assert bench.recorded_traffic("grid") is None
 
 
 def test_stats_summary_lists_every_kernel(tmp_path):
@@ -83,6 +86,21 @@ def test_algorithmic_bytes(storage, q, node, pml):
     four float64 moments, each read and written."""
     assert bench.bytes_per_node(storage, q) == node
     assert bench.pml_extra(storage, q) == pml
+
+
+def test_kernel_bytes_split_the_step():
+    """The step grid's and the frame kernel's algorithmic bytes add up to the step's: the grid
+    holds the bulk tiles and phase A's Q update (Q read and written, U^n read per Q node)."""
+    g, f, st = bench.kernel_bytes("f64", 37, 1000, 200, 150)
+    assert st == 592 * 1200 + 656 * 150
+    assert g == 592 * 1000 + (656 - 32) * 150 and f == 592 * 200 + 32 * 150
+    g, f, st = bench.kernel_bytes("f64", 37, 1000, 200, 150, fused=False)
+    assert g == 592 * 1000 and g + f == st
+
+
+def test_host_cpu_reports_model_and_cores():
+    model, cores = bench.host_cpu()
+    assert model and cores and cores >= 1
 
 
 def test_more_than_one_gpu_is_refused():

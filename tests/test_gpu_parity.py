@@ -145,8 +145,9 @@ def test_profile_modes_count_launches_and_keep_bits():
         r.profile(mode)
         r.step(23)
         ms, n = r.profile_read(reset=True)
-        # mode 3: first step of each batch of 8 (batches of 8, 8 and 7 steps)
-        expect = {0: [0, 0, 0], 1: [23, 23, 23], 2: [23, 0, 0], 3: [3, 0, 0]}[mode]
+        # mode 2: the step grid and the frame kernel of every step; mode 3: of every fourth
+        # step of each batch of 8 (batches of 8, 8 and 7 steps: sub-steps 0 and 4 of each)
+        expect = {0: [0, 0, 0], 1: [23, 23, 23], 2: [23, 23, 0], 3: [6, 6, 0]}[mode]
         assert list(n) == expect, (mode, n)
         assert all(m > 0 for m, c in zip(ms, n) if c)
         with pytest.raises(lbm.LbmError):
@@ -273,7 +274,8 @@ def test_torch_stream_and_allocator_interop():
     F = wl.noisy_state(60, 56, 12, 1.0, 0.05, 0.0, 1.0)
     outs = []
     for use_torch in (False, True):
-        kw = dict(stream=torch.cuda.Stream(), allocator=lbm.torch_allocator()) if use_torch else {}
+        ts = torch.cuda.Stream()
+        kw = dict(stream=ts, allocator=lbm.torch_allocator(ts)) if use_torch else {}
         r = lbm.Run(48, 44, 0.8, 1.0, 0.05, 0.0, 1.0, **kw)
         r.set_bc(15, "nrbc")
         r.set_pml(15, 6, 0.05)
@@ -287,6 +289,42 @@ def test_torch_stream_and_allocator_interop():
             assert np.array_equal(rho.cpu().numpy(), r.moments()[0])
         r.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("bind", [True, False])
+def test_torch_allocator_blocks_freed_under_pending_work(bind):
+    """Blocks the caching allocator hands to the library may have been freed by work still queued
+    on the default stream: the run (on a side stream) must not race with that work.  Queue a long
+    chain of kernels on the default stream over tensors, free them, then create and step a run on a
+    side stream with the torch allocator (bound to that stream, or synchronising the current one):
+    bitwise the result of the library's own allocations."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("PyTorch in this process sees no HIP device")
+    F = wl.noisy_state(60, 56, 12, 1.0, 0.05, 0.0, 1.0)
+
+    def run(**kw):
+        r = lbm.Run(48, 44, 0.8, 1.0, 0.05, 0.0, 1.0, **kw)
+        r.set_bc(15, "nrbc")
+        r.set_pml(15, 6, 0.05)
+        r.init(*F.as_tuple())
+        r.step(40)
+        out = r.populations()
+        r.close()
+        return out
+
+    ref = run()
+    torch.cuda.synchronize()
+    bufs = [torch.ones(1 << 20, dtype=torch.float64, device="cuda") for _ in range(8)]
+    for _ in range(200):                 # pending work on the default stream
+        for b in bufs:
+            b.mul_(1.0000001).add_(1e-9)
+    del bufs                             # blocks back in the cache while that work is queued
+    ts = torch.cuda.Stream()
+    got = run(stream=ts, allocator=lbm.torch_allocator(ts if bind else None))
+    torch.cuda.synchronize()
+    assert np.array_equal(ref, got)
 
 
 @pytest.mark.parametrize("storage", ["f64", "f16"])
