@@ -213,6 +213,18 @@ lbm_status lbm_velocities(int32_t lattice, int32_t *e, double *w, double *r);
 lbm_status lbm_error_norms(lbm_handle h, const double *ref_rho, const double *ref_ux,
                            const double *ref_T, double out[3]);
 
+/* lbm_error_norms for callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid device allocation): the same three norms with the same
+ * bits, but every pointer is device memory and the call only enqueues kernels on the run's stream
+ * (no allocation, no copy, no synchronisation; the caller synchronises before reading out).
+ * ref_*: device float64 [ny][nx] bulk arrays; out: device float64[3].  The per-row partial sums
+ * live in a library-owned device array of 16384 rows (384 KiB, one per device, held until the
+ * process ends); the run's device must be current.  Calls that overlap on one device share that
+ * array and race: order them on one stream.  Errors: LBM_ERR_ARG for NULL pointers or a bulk of
+ * more than 16384 rows; LBM_ERR_STATE before lbm_init_fields; LBM_ERR_DEVICE if a launch fails. */
+lbm_status lbm_error_norms_noalloc(lbm_handle h, const double *ref_rho, const double *ref_ux,
+                                   const double *ref_T, double *out);
+
 /* Scan the current state for non-finite values, rho <= 0 or T <= 0: LBM_OK or
  * LBM_ERR_UNSTABLE.  Synchronises. */
 lbm_status lbm_check(lbm_handle h);

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -849,6 +850,54 @@ lbm_status lbm_error_norms(lbm_handle h, const double *ref_rho, const double *re
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     h->mem.put(tmp);
     if (e != hipSuccess) return fail(LBM_ERR_DEVICE, std::string("lbm_error_norms: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+// ---- allocation-free error norms ------------------------------------------------------------
+// Per-row partial sums of lbm_error_norms_noalloc: 3 doubles per bulk row.  One copy per device,
+// held until the process ends; every call on a device shares it.  In host code `scratch` names a
+// host-side stand-in, not device memory: kernels take the address scratch_address returns.
+constexpr int NOALLOC_MAX_ROWS = 16384;
+static __device__ __align__(256) double scratch[3 * NOALLOC_MAX_ROWS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double *scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device, looked up once per device.
+lbm_status scratch_address(double **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(LBM_ERR_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        double *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(LBM_ERR_DEVICE, "no device address for the scratch array");
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return LBM_OK;
+}
+}  // namespace
+
+lbm_status lbm_error_norms_noalloc(lbm_handle h, const double *ref_rho, const double *ref_ux,
+                                   const double *ref_T, double *out) {
+    if (!h || !ref_rho || !ref_ux || !ref_T || !out) return fail(LBM_ERR_ARG, "NULL argument");
+    if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
+    const int ly = h->desc.ny;
+    if (ly > NOALLOC_MAX_ROWS)
+        return fail(LBM_ERR_ARG, "lbm_error_norms_noalloc: the bulk has " + std::to_string(ly) +
+                                     " rows; its scratch holds at most " +
+                                     std::to_string(NOALLOC_MAX_ROWS));
+    double *part = nullptr;
+    lbm_status st = scratch_address(&part);
+    if (st != LBM_OK) return st;
+    const RunDev &R = h->hd;
+    HIP_TRY(h->ks->err_rows_state(h->dd, h->desc.storage, R.Wxm, R.Wym, h->desc.nx, ly, ref_rho, ref_ux,
+                                  ref_T, part, h->stream));
+    HIP_TRY(h->ks->err_final(part, ly, out, h->stream));
     return LBM_OK;
 }
 

@@ -123,6 +123,10 @@ struct KernelSet {
     hipError_t (*err_rows)(const double *rho, const double *ux, const double *T, int Nx,
                            int x0, int y0, int lx, int ly, const double *rr, const double *ru,
                            const double *rt, double *partials, hipStream_t s);
+    // the sums of err_rows over the moments of the run's current state, formed in the kernel
+    hipError_t (*err_rows_state)(RunDev *run, int storage, int x0, int y0, int lx, int ly,
+                                 const double *rr, const double *ru, const double *rt,
+                                 double *partials, hipStream_t s);
     hipError_t (*err_final)(const double *partials, int nrows, double *out, hipStream_t s);
 };
 

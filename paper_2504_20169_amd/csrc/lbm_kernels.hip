@@ -1226,17 +1226,10 @@ __global__ __launch_bounds__(256) void k_init(RunDev *Rw, const double *rho, con
     }
 }
 
-// Moments of the current step (post-stream, post-boundary): re-pull from the previous
-// buffer with the previous moment strips; after 0 steps, moments of f*(0).
-template <class S>
-__global__ __launch_bounds__(256) void k_moments(RunDev *Rw, double *rho, double *ux, double *uy,
-                                                 double *T) {
-    using C = typename Traits<S>::C;
-    CRun &R = *(CRun *)Rw;
-    const int n = blockIdx.x * 256 + threadIdx.x;
-    if (n >= R.Nx * R.Ny) return;
-    const int y = n / R.Nx, x = n - y * R.Nx;
-    const K<C> k = load_k<C>(R);
+// Moments of node (x, y) at the current step (post-stream, post-boundary): re-pull from the
+// previous buffer with the previous moment strips; after 0 steps, moments of f*(0).
+template <class S, class C>
+__device__ __forceinline__ Mom<C> state_moments(CRun &R, int x, int y, const K<C> &k) {
     C g[NQ];
     if (R.step == 0) {
         const GLOBAL S *src = (const GLOBAL S *)R.f[R.par];
@@ -1254,7 +1247,19 @@ __global__ __launch_bounds__(256) void k_moments(RunDev *Rw, double *rho, double
             gather_clamped<S, C>(R, src, x, y, k.inv_scale, g);
         }
     }
-    Mom<C> m = moments<C>(g, k);
+    return moments<C>(g, k);
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_moments(RunDev *Rw, double *rho, double *ux, double *uy,
+                                                 double *T) {
+    using C = typename Traits<S>::C;
+    CRun &R = *(CRun *)Rw;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= R.Nx * R.Ny) return;
+    const int y = n / R.Nx, x = n - y * R.Nx;
+    const K<C> k = load_k<C>(R);
+    Mom<C> m = state_moments<S, C>(R, x, y, k);
     if (rho) rho[n] = R.rho0 + (double)m.drho;
     if (ux) ux[n] = R.u0x + (double)m.dux;
     if (uy) uy[n] = R.u0y + (double)m.duy;
@@ -1324,6 +1329,36 @@ __global__ __launch_bounds__(256) void k_err_rows(const double *rho, const doubl
     for (int xb = threadIdx.x; xb < lx; xb += 256) {
         long long n = (long long)(row + y0) * Nx + (xb + x0), m = (long long)row * lx + xb;
         double a = (rho[n] - rr[m]) / rr[m], b = (ux[n] - ru[m]) / ru[m], c = (T[n] - rt[m]) / rt[m];
+        s[0] += a * a; s[1] += b * b; s[2] += c * c;
+    }
+    for (int z = 0; z < 3; ++z) red[z][threadIdx.x] = s[z];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int z = 0; z < 3; ++z) red[z][threadIdx.x] += red[z][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) partials[3 * row + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// The reflection-error sums of k_err_rows taken straight from the run's state (the moments of
+// state_moments, formed as k_moments writes them): the same values, the same order, so the same
+// bits as k_moments followed by k_err_rows.  One bulk row per block; refs are bulk-sized.
+template <class S>
+__global__ __launch_bounds__(256) void k_err_rows_state(RunDev *Rw, int x0, int y0, int lx,
+                                                        const double *rr, const double *ru,
+                                                        const double *rt, double *partials) {
+    using C = typename Traits<S>::C;
+    CRun &R = *(CRun *)Rw;
+    __shared__ double red[3][256];
+    const int row = blockIdx.x;
+    const K<C> k = load_k<C>(R);
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int xb = threadIdx.x; xb < lx; xb += 256) {
+        const Mom<C> m = state_moments<S, C>(R, xb + x0, row + y0, k);
+        const double rho = R.rho0 + (double)m.drho, ux = R.u0x + (double)m.dux, T = R.T0 + (double)m.dT;
+        const long long q = (long long)row * lx + xb;
+        double a = (rho - rr[q]) / rr[q], b = (ux - ru[q]) / ru[q], c = (T - rt[q]) / rt[q];
         s[0] += a * a; s[1] += b * b; s[2] += c * c;
     }
     for (int z = 0; z < 3; ++z) red[z][threadIdx.x] = s[z];
@@ -1496,6 +1531,15 @@ static hipError_t launch_err_rows(const double *rho, const double *ux, const dou
     return hipGetLastError();
 }
 
+static hipError_t launch_err_rows_state(RunDev *run, int storage, int x0, int y0, int lx, int ly,
+                                        const double *rr, const double *ru, const double *rt,
+                                        double *partials, hipStream_t s) {
+    if (ly <= 0) return hipSuccess;
+    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_err_rows_state<S>), dim3(ly), dim3(256), 0, s, run, x0, y0,
+                                             lx, rr, ru, rt, partials));
+    return hipGetLastError();
+}
+
 static hipError_t launch_err_final(const double *partials, int nrows, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_err_final, dim3(1), dim3(256), 0, s, partials, nrows, out);
     return hipGetLastError();
@@ -1506,7 +1550,7 @@ static hipError_t launch_err_final(const double *partials, int nrows, double *ou
 const KernelSet kernels = {NQ, launch_phase_a, launch_frame, launch_target, launch_phase_a_bulk, launch_bulk,
                            launch_advance, launch_set_limit, launch_set_limits, launch_init,
                            launch_moments, launch_export_f, launch_export_q, launch_check,
-                           launch_err_rows, launch_err_final};
+                           launch_err_rows, launch_err_rows_state, launch_err_final};
 #endif
 
 }  // namespace LBM_KSET

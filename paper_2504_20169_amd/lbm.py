@@ -31,7 +31,7 @@ EXPORTED = [
     "lbm_create", "lbm_set_pml", "lbm_set_bc", "lbm_set_nrbc_pml_terms", "lbm_grid", "lbm_footprint", "lbm_init_fields",
     "lbm_node_classes",
     "lbm_step", "lbm_step_count", "lbm_moments", "lbm_populations", "lbm_pml_q",
-    "lbm_velocities", "lbm_error_norms", "lbm_check", "lbm_synchronize", "lbm_set_launch",
+    "lbm_velocities", "lbm_error_norms", "lbm_error_norms_noalloc", "lbm_check", "lbm_synchronize", "lbm_set_launch",
     "lbm_get_launch", "lbm_autotune", "lbm_profile", "lbm_profile_read", "lbm_save",
     "lbm_load", "lbm_destroy", "lbm_last_error", "lbm_group_create", "lbm_group_add",
     "lbm_group_remove", "lbm_group_step", "lbm_group_size", "lbm_group_synchronize",
@@ -99,6 +99,8 @@ def load():
         "lbm_pml_q": [H, dp],
         "lbm_velocities": [ctypes.c_int32, i32p, dp, dp],
         "lbm_error_norms": [H, dp, dp, dp, dp],
+        "lbm_error_norms_noalloc": [H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p],
         "lbm_check": [H],
         "lbm_synchronize": [H],
         "lbm_set_launch": [H, ctypes.POINTER(lbm_launch)],
@@ -307,6 +309,12 @@ class Run:
         out = np.zeros(3)
         _check(self._lib.lbm_error_norms(self.h, *[_dp(a) for a in refs], _dp(out)))
         return out
+
+    def error_norms_noalloc(self, ref_rho, ref_ux, ref_T, out):
+        """lbm_error_norms_noalloc with device pointers (integers): enqueues only; the result lands
+        in out (3 doubles) once the run's stream has reached it."""
+        _check(self._lib.lbm_error_norms_noalloc(self.h, int(ref_rho), int(ref_ux), int(ref_T),
+                                                 int(out)))
 
     def check(self):
         """LBM_OK or LBM_ERR_UNSTABLE (returned, not raised)."""
