@@ -76,14 +76,19 @@ def time_run(torch, r, steps, warmup, mode):
     return dt, ms, n
 
 
-def serve_trace(jobs, rate, scale, storage, tick):
+def serve_trace(jobs, rate, scale, storage, tick, seed=5):
+    """The serving trace: Poisson arrivals at `rate` jobs/s (seed 5: the trace's stated seed), bulk
+    128^2..2048^2 log-uniform, PML 8..64, 1000..20000 steps (times `scale`), ZG or NRBC, FP32
+    storage, 200 GB HBM budget; latency from arrival to result on the host."""
     from paper_2504_20169_amd import workloads as wl
     from paper_2504_20169_amd.serve import Engine, GpuBackend, jobs_from_trace
-    trace = wl.poisson_trace(jobs, rate=rate, seed=5)
+    trace = wl.poisson_trace(jobs, rate=rate, seed=seed)
     be = GpuBackend(storage=storage)
     eng = Engine(be, int(200e9), tick_steps=tick)
     rep = eng.run_trace(jobs_from_trace(trace, scale))
     be.close()
+    rep.update(trace="%d Poisson arrivals at %g/s, steps x%g, FP32 storage, HBM budget 200 GB, "
+                     "tick %d steps" % (jobs, rate, scale, tick))
     return rep
 
 
@@ -463,8 +468,12 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--serve-jobs", type=int, default=24, help="0 skips the serving trace")
     ap.add_argument("--serve-rate", type=float, default=20.0)
-    ap.add_argument("--serve-scale", type=float, default=0.1,
+    ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="multiplier on the trace's step counts (1000-20000)")
+    ap.add_argument("--serve-tick", type=int, default=200, help="steps per serving tick")
+    ap.add_argument("--serve-sustain-jobs", type=int, default=12,
+                    help="arrivals of a second trace at a sustainable rate (0 skips it)")
+    ap.add_argument("--serve-sustain-rate", type=float, default=1.0)
     ap.add_argument("--no-copy-bw", dest="copy_bw", action="store_false",
                     help="skip timing a plain 2 GiB device copy (attainable HBM bandwidth)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -589,9 +598,14 @@ def main():
         line["batch"] = rnd(batch_leg(torch, lbm, wl, args))
     if args.serve_jobs > 0:
         _log("bench: serving trace")
-        line["serving"] = serve_trace(args.serve_jobs, args.serve_rate, args.serve_scale, "f32", 200)
-        line["serving"].update(trace="%d Poisson arrivals at %.0f/s, steps x%.2g, FP32 storage, "
-                                     "HBM budget 200 GB" % (args.serve_jobs, args.serve_rate, args.serve_scale))
+        line["serving"] = {"arrivals": serve_trace(args.serve_jobs, args.serve_rate, args.serve_scale,
+                                                   "f32", args.serve_tick)}
+        if args.serve_sustain_jobs > 0:
+            _log("bench: serving trace at a sustainable rate")
+            line["serving"]["sustainable"] = serve_trace(args.serve_sustain_jobs, args.serve_sustain_rate,
+                                                         args.serve_scale, "f32", args.serve_tick)
+        if "batch" in line:
+            line["serving"]["batch_group_mlups"] = line["batch"]["group_mlups"]
     if not args.no_cpu:
         _log("bench: cpu baseline (oracle)")
         mlups_cpu, threads, dt_cpu = cpu_baseline(wl, args.L, args.W, args.sigma, args.mach, args.bc,

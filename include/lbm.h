@@ -149,6 +149,20 @@ lbm_status lbm_set_bc(lbm_handle h, unsigned side_mask, lbm_bc kind);
  * Sec. 4.  Errors: LBM_ERR_ARG for bits outside 0..2; LBM_ERR_STATE after init. */
 lbm_status lbm_set_nrbc_pml_terms(lbm_handle h, unsigned flags);
 
+/* Debug flags of a run (lbm_set_debug).  LBM_DEBUG_POISON: a NaN canary.  Before the kernels of
+ * every step, the buffers that the step writes in full -- the destination population buffer,
+ * the new moment strips, and on characteristic sides the ring's fill and targets -- are filled
+ * with NaN in their storage type, so a node or component that a step leaves unwritten and a
+ * later kernel reads shows up as NaN in the moments (and in lbm_check).  A correct step gives
+ * the same bits with and without it.  Costs one extra pass over those buffers per step; in a
+ * group, the canary is on for every member while any member has it on.  Not part of the paper:
+ * a test aid. */
+enum { LBM_DEBUG_POISON = 1 };
+
+/* Set the run's debug flags (0 clears them).  Allowed at any time; captured step graphs are
+ * recaptured.  Errors: LBM_ERR_ARG for a NULL handle or an unknown flag. */
+lbm_status lbm_set_debug(lbm_handle h, unsigned flags);
+
 /* Full grid size for the current configuration: the bulk extended by W layers on each side
  * that carries a PML, Nx = nx + W (per PML x side), Ny likewise (Sec. 3: the computational
  * domain (L_x + 2W) x (L_y + 2W) when every side has a layer; Sec. 5 uses that layout).  Host
@@ -163,14 +177,16 @@ lbm_status lbm_grid(lbm_handle h, int32_t *Nx, int32_t *Ny);
  * entries.  Errors: LBM_ERR_ARG for NULL pointers or an inconsistent configuration. */
 lbm_status lbm_node_classes(lbm_handle h, int64_t out[4]);
 
-/* Bytes of device memory the run holds once initialised (populations, PML Q, moment strips,
- * descriptor), for admission control. */
+/* Bytes of device memory the run needs at its peak (populations, PML Q, moment strips, ring
+ * buffers, descriptor, and the transient staging of the input fields while lbm_init_fields runs),
+ * for admission control. */
 lbm_status lbm_footprint(lbm_handle h, size_t *bytes);
 
 /* Allocate device state and set f*(x, 0) = feq(rho, u, T)(x), Q = 0 (Sec. 2 algorithm
  * outline; eq. PMLQ).  rho, ux, uy, T: host float64 [Ny][Nx], copied.  Errors: LBM_ERR_ARG
  * for NULL, non-finite, rho <= 0 or T <= 0 inputs or an inconsistent configuration;
- * LBM_ERR_OOM; LBM_ERR_STATE if already initialised.  Synchronises the stream. */
+ * LBM_ERR_OOM; LBM_ERR_STATE if already initialised; LBM_ERR_ARG if the allocator hook returns
+ * two live buffers that overlap (nothing else is touched then).  Synchronises the stream. */
 lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux,
                            const double *uy, const double *T);
 
@@ -293,6 +309,10 @@ lbm_status lbm_group_get_launch(lbm_group_handle g, lbm_launch *cfg);
  * LBM_ERR_STATE for an empty group.  *chosen may be NULL. */
 lbm_status lbm_group_autotune(lbm_group_handle g, int32_t steps, lbm_launch *chosen);
 lbm_status lbm_group_size(lbm_group_handle g, int32_t *n);
+/* lbm_check of every member with one synchronisation: flags[k] (host, caller-owned, one entry
+ * per member in member order) receives 0 for a healthy state, 1 for a non-finite value, rho <= 0
+ * or T <= 0.  Synchronises the group's stream.  Errors: LBM_ERR_ARG for NULL pointers. */
+lbm_status lbm_group_check(lbm_group_handle g, int32_t *flags);
 lbm_status lbm_group_synchronize(lbm_group_handle g);
 void lbm_group_destroy(lbm_group_handle g);
 

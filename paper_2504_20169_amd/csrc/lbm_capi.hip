@@ -37,21 +37,28 @@ size_t elem_size(int storage) { return storage == ST_F64 ? 8 : storage == ST_F32
 size_t compute_size(int storage) { return storage == ST_F64 ? 8 : 4; }
 long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
 
+// Device buffers of one owner, through the caller's allocator hook or hipMalloc.  Every live
+// buffer is kept with its size, so the owner can check that no two of them overlap (a hook that
+// hands out aliasing memory would let one buffer's writes land in another's reads).
 struct DeviceMem {
     const lbm_allocator *alloc = nullptr;
     std::vector<void *> ptrs;
+    std::vector<size_t> sizes;
     void *get(size_t bytes) {
         void *p = nullptr;
         bytes = (size_t)round_up((long long)std::max<size_t>(bytes, 256), 256);
         if (alloc && alloc->alloc) p = alloc->alloc(bytes, alloc->ctx);
         else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
-        if (p) ptrs.push_back(p);
+        if (p) { ptrs.push_back(p); sizes.push_back(bytes); }
         return p;
     }
     void put(void *p) {
         if (!p) return;
         auto it = std::find(ptrs.begin(), ptrs.end(), p);
-        if (it != ptrs.end()) ptrs.erase(it);
+        if (it != ptrs.end()) {
+            sizes.erase(sizes.begin() + (it - ptrs.begin()));
+            ptrs.erase(it);
+        }
         if (alloc && alloc->free) alloc->free(p, alloc->ctx);
         else (void)hipFree(p);
     }
@@ -61,6 +68,16 @@ struct DeviceMem {
             else (void)hipFree(p);
         }
         ptrs.clear();
+        sizes.clear();
+    }
+    // true if two live buffers share a byte
+    bool overlapping() const {
+        std::vector<std::pair<uintptr_t, size_t>> r(ptrs.size());
+        for (size_t k = 0; k < ptrs.size(); ++k) r[k] = {(uintptr_t)ptrs[k], sizes[k]};
+        std::sort(r.begin(), r.end());
+        for (size_t k = 1; k < r.size(); ++k)
+            if (r[k].first < r[k - 1].first + r[k - 1].second) return true;
+        return false;
     }
 };
 
@@ -128,6 +145,8 @@ struct lbm_run {
     int64_t prof_n[3] = {0, 0, 0};
     lbm_group *group = nullptr;
     size_t footprint = 0;
+    int *dflag = nullptr;             // lbm_check's flag, allocated with the run
+    unsigned debug = 0;               // lbm_set_debug flags
     StepStreams ss;
 };
 
@@ -148,10 +167,13 @@ struct lbm_group {
     int *dprefix = nullptr;
     long long *dlimits = nullptr;
     long long *hlimits = nullptr;     // pinned
+    int *dflags = nullptr;            // lbm_group_check: one flag per member
+    int *hflags = nullptr;            // pinned
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
     int blocks[NCLS] = {0, 0, 0, 0};
     size_t cap = 0;
+    int poison = 0;                   // some member has the NaN canary on
 };
 
 namespace {
@@ -300,7 +322,11 @@ size_t footprint_of(const RunDev &R, int storage, int nq) {
     b += 2 * 4 * (size_t)R.qplane * sizeof(double);
     if (R.ring_n > 0) b += (size_t)nq * R.rplane * compute_size(storage);
     if (R.tgt_pre && R.ring_n > 0) b += 4 * (size_t)R.rplane * sizeof(double);
-    b += sizeof(RunDev) + 256 * 3 + nq * sizeof(double);
+    b += sizeof(RunDev) + 256 * 4 + nq * sizeof(double);
+    // lbm_init_fields' transient staging of the four input fields (and, for FP16 storage, the
+    // per-block maxima that choose the scale): part of the peak while the run is set up
+    const size_t nn = (size_t)R.Nx * R.Ny;
+    b += 4 * nn * sizeof(double) + (storage == ST_F16 ? ((nn + 255) / 256) * sizeof(float) + 256 : 0);
     return b;
 }
 
@@ -331,6 +357,7 @@ LaunchSet single_set(lbm_run *h) {
         L.prefix[c] = h->dprefix + 2 * c;
         L.blocks[c] = h->nblocks[c];
     }
+    L.poison = (h->debug & LBM_DEBUG_POISON) ? 1 : 0;
     L.nruns = 1;
     return L;
 }
@@ -382,6 +409,7 @@ lbm_status enqueue_substep(const LaunchSet &L, int storage, int tx, int ks, hipS
     const bool has_a = L.blocks[CLS_A] > 0;
     const bool has_f = L.blocks[CLS_FRAME] > 0;
     const bool has_b = L.blocks[CLS_BULK] > 0;
+    if (L.poison) HIP_TRY(L.ks->poison(L, storage, ks, s));
     const int pm = prof ? prof->prof : 0;
     const int mode = pm == 3 ? ((ks & 3) == 0 ? 2 : 0) : pm;
     hipEvent_t ev[6] = {};
@@ -576,10 +604,15 @@ lbm_status lbm_set_pml(lbm_handle h, unsigned mask, int32_t W, double sigma_max)
 lbm_status lbm_set_bc(lbm_handle h, unsigned mask, lbm_bc kind) {
     if (!h) return fail(LBM_ERR_ARG, "NULL handle");
     if (h->inited) return fail(LBM_ERR_STATE, "configure before lbm_init_fields");
-    if (kind < LBM_BC_PERIODIC || kind > LBM_BC_NRBC_A) return fail(LBM_ERR_ARG, "unknown boundary kind");
+    // A C caller may pass any int; C++ may not load an enum outside its enumerators' range, so
+    // the value is read as the int it was passed as.
+    int k;
+    static_assert(sizeof k == sizeof kind, "lbm_bc is passed as an int");
+    std::memcpy(&k, &kind, sizeof k);
+    if (k < LBM_BC_PERIODIC || k > LBM_BC_NRBC_A) return fail(LBM_ERR_ARG, "unknown boundary kind");
     if (mask & ~15u) return fail(LBM_ERR_ARG, "bad side mask");
     for (int s = 0; s < 4; ++s)
-        if ((mask >> s) & 1u) h->bc[s] = kind;
+        if ((mask >> s) & 1u) h->bc[s] = k;
     return LBM_OK;
 }
 
@@ -588,6 +621,16 @@ lbm_status lbm_set_nrbc_pml_terms(lbm_handle h, unsigned flags) {
     if (h->inited) return fail(LBM_ERR_STATE, "configure before lbm_init_fields");
     if (flags & ~7u) return fail(LBM_ERR_ARG, "PML term flags must be a subset of bits 0..2");
     h->pml_terms = flags;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_debug(lbm_handle h, unsigned flags) {
+    if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+    if (flags & ~(unsigned)LBM_DEBUG_POISON) return fail(LBM_ERR_ARG, "unknown debug flag");
+    if (h->debug == flags) return LBM_OK;
+    h->debug = flags;
+    drop_graph(h);                       // captured steps are recaptured with the new flags
+    if (h->group) h->group->dirty = true;
     return LBM_OK;
 }
 
@@ -663,9 +706,15 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux, co
     h->dptr = (RunDev **)h->mem.get(sizeof(RunDev *));
     h->dprefix = (int *)h->mem.get(2 * NCLS * sizeof(int));
     h->fbar_d = (double *)h->mem.get(h->lat->q * sizeof(double));
-    if ((R.has_q && !R.Q) || (R.ring_n > 0 && !R.G) || (need_p && !R.P) || !h->dd || !h->dptr || !h->dprefix || !h->fbar_d) {
+    h->dflag = (int *)h->mem.get(sizeof(int));
+    if ((R.has_q && !R.Q) || (R.ring_n > 0 && !R.G) || (need_p && !R.P) || !h->dd || !h->dptr || !h->dprefix ||
+        !h->fbar_d || !h->dflag) {
         h->mem.release_all();
         return fail(LBM_ERR_OOM, "device allocation failed");
+    }
+    if (h->mem.overlapping()) {
+        h->mem.release_all();
+        return fail(LBM_ERR_ARG, "device buffers overlap: the allocator returned aliasing memory");
     }
     for (int b = 0; b < 2; ++b) {
         HIP_TRY(hipMemsetAsync(R.f[b], 0, (size_t)R.fsize * es, h->stream));
@@ -684,6 +733,10 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux, co
     // fields to the device
     double *dfield = (double *)h->mem.get(4 * nn * sizeof(double));
     if (!dfield) { h->mem.release_all(); return fail(LBM_ERR_OOM, "device allocation failed"); }
+    if (h->mem.overlapping()) {
+        h->mem.release_all();
+        return fail(LBM_ERR_ARG, "device buffers overlap: the allocator returned aliasing memory");
+    }
     const double *src[4] = {rho, ux, uy, T};
     for (int k = 0; k < 4; ++k)
         HIP_TRY(hipMemcpyAsync(dfield + k * nn, src[k], nn * sizeof(double), hipMemcpyHostToDevice, h->stream));
@@ -904,14 +957,12 @@ lbm_status lbm_error_norms_noalloc(lbm_handle h, const double *ref_rho, const do
 lbm_status lbm_check(lbm_handle h) {
     if (!h) return fail(LBM_ERR_ARG, "NULL handle");
     if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
-    int *flag = (int *)h->mem.get(sizeof(int));
-    if (!flag) return fail(LBM_ERR_OOM, "device allocation failed");
+    int *flag = h->dflag;
     int hf = 0;
     hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), h->stream);
     if (e == hipSuccess) e = h->ks->check(h->dd, h->desc.storage, h->hd.Nx, h->hd.Ny, flag, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    h->mem.put(flag);
     if (e != hipSuccess) return fail(LBM_ERR_DEVICE, std::string("lbm_check: ") + hipGetErrorString(e));
     if (hf) return fail(LBM_ERR_UNSTABLE, "non-finite value, rho <= 0 or T <= 0 in the state");
     return LBM_OK;
@@ -1147,7 +1198,10 @@ lbm_status lbm_group_create(void *stream, const lbm_allocator *allocator, lbm_gr
         g->stream = g->own_stream;
     }
     if (hipHostMalloc((void **)&g->hlimits, 4096 * sizeof(long long), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&g->hflags, 4096 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&g->upload_done, hipEventDisableTiming) != hipSuccess) {
+        if (g->hlimits) (void)hipHostFree(g->hlimits);
+        if (g->hflags) (void)hipHostFree(g->hflags);
         if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
         delete g;
         return fail(LBM_ERR_DEVICE, "group setup failed");
@@ -1210,12 +1264,14 @@ static lbm_status group_rebuild(lbm_group *g) {
     HIP_TRY(hipStreamSynchronize(g->stream));
     group_drop_graph(g);
     if (n > g->cap) {
-        g->mem.put(g->druns); g->mem.put(g->dprefix); g->mem.put(g->dlimits);
+        g->mem.put(g->druns); g->mem.put(g->dprefix); g->mem.put(g->dlimits); g->mem.put(g->dflags);
         size_t cap = std::max<size_t>(n, 64);
         g->druns = (RunDev **)g->mem.get(cap * sizeof(RunDev *));
         g->dprefix = (int *)g->mem.get(NCLS * (cap + 1) * sizeof(int));
         g->dlimits = (long long *)g->mem.get(cap * sizeof(long long));
-        if (!g->druns || !g->dprefix || !g->dlimits) return fail(LBM_ERR_OOM, "device allocation failed");
+        g->dflags = (int *)g->mem.get(cap * sizeof(int));
+        if (!g->druns || !g->dprefix || !g->dlimits || !g->dflags)
+            return fail(LBM_ERR_OOM, "device allocation failed");
         g->cap = cap;
     }
     std::vector<RunDev *> ptrs(n);
@@ -1229,6 +1285,8 @@ static lbm_status group_rebuild(lbm_group *g) {
         for (int c = 0; c < NCLS; ++c) { pre[c * (g->cap + 1) + k] = tot[c]; tot[c] += nb[c]; }
     }
     for (int c = 0; c < NCLS; ++c) pre[c * (g->cap + 1) + n] = tot[c];
+    g->poison = 0;
+    for (lbm_run *h : g->members) g->poison |= (h->debug & LBM_DEBUG_POISON) ? 1 : 0;
     if (n) HIP_TRY(hipMemcpy(g->druns, ptrs.data(), n * sizeof(RunDev *), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(g->dprefix, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice));
     for (int c = 0; c < NCLS; ++c) g->blocks[c] = tot[c];
@@ -1265,6 +1323,7 @@ lbm_status lbm_group_step(lbm_group_handle g, const int64_t *steps, int64_t nste
         L.blocks[c] = g->blocks[c];
     }
     L.nruns = (int)n;
+    L.poison = g->poison;
     // Runs past their own count skip every kernel, so whole graphs of G batched steps serve any
     // mix of counts; the remainder is launched eagerly.
     int64_t left = K;
@@ -1289,6 +1348,26 @@ lbm_status lbm_group_step(lbm_group_handle g, const int64_t *steps, int64_t nste
         left -= nb;
     }
     for (size_t k = 0; k < n; ++k) g->members[k]->steps += steps ? steps[k] : nsteps;
+    return LBM_OK;
+}
+
+lbm_status lbm_group_check(lbm_group_handle g, int32_t *flags) {
+    if (!g) return fail(LBM_ERR_ARG, "NULL argument");
+    const size_t n = g->members.size();
+    if (n == 0) return LBM_OK;
+    if (!flags) return fail(LBM_ERR_ARG, "NULL argument");
+    if (g->dirty) {
+        lbm_status st = group_rebuild(g);
+        if (st != LBM_OK) return st;
+    }
+    HIP_TRY(hipMemsetAsync(g->dflags, 0, n * sizeof(int), g->stream));
+    for (size_t k = 0; k < n; ++k) {
+        lbm_run *h = g->members[k];
+        HIP_TRY(h->ks->check(h->dd, h->desc.storage, h->hd.Nx, h->hd.Ny, g->dflags + k, g->stream));
+    }
+    HIP_TRY(hipMemcpyAsync(g->hflags, g->dflags, n * sizeof(int), hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    for (size_t k = 0; k < n; ++k) flags[k] = g->hflags[k] ? 1 : 0;
     return LBM_OK;
 }
 
@@ -1387,6 +1466,7 @@ void lbm_group_destroy(lbm_group_handle g) {
     group_drop_graph(g);
     g->mem.release_all();
     if (g->hlimits) (void)hipHostFree(g->hlimits);
+    if (g->hflags) (void)hipHostFree(g->hflags);
     if (g->upload_done) (void)hipEventDestroy(g->upload_done);
     if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
     delete g;

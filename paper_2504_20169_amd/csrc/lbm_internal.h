@@ -70,6 +70,7 @@ struct LaunchSet {
     const int *prefix[NCLS];  // device prefix arrays per class
     int blocks[NCLS];         // total blocks per class
     int nruns;
+    int poison = 0;           // debug canary: NaN-fill each step's destination buffers first
 };
 
 constexpr int FRAME_BLOCK = 256;
@@ -128,6 +129,8 @@ struct KernelSet {
                                  const double *rr, const double *ru, const double *rt,
                                  double *partials, hipStream_t s);
     hipError_t (*err_final)(const double *partials, int nrows, double *out, hipStream_t s);
+    // debug canary of sub-step ks: NaN into the buffers the step writes in full (every active run)
+    hipError_t (*poison)(const LaunchSet &L, int storage, int ks, hipStream_t s);
 };
 
 namespace k37 { extern const KernelSet kernels; }

@@ -1168,6 +1168,32 @@ __global__ void k_advance(RunDev *const *runs, int nruns, int n) {
     R->par ^= (int)(a & 1);
 }
 
+// Debug canary: before the step kernels of sub-step ks, every buffer that a step writes in full
+// -- the destination populations, the new moment strips, and the ring's characteristic fill G
+// and targets P -- is filled with NaN in its own type.  A node or component that the step leaves
+// unwritten and a later kernel reads then carries NaN into the result.
+template <class S>
+__global__ __launch_bounds__(256) void k_poison(RunDev *const *runs, int ks) {
+    using C = typename Traits<S>::C;
+    CRun &R = run_of(runs, blockIdx.y);
+    const int par = sub_par(R, ks);
+    if (par < 0) return;
+    const long long t0 = (long long)blockIdx.x * 256 + threadIdx.x, st = (long long)gridDim.x * 256;
+    GLOBAL S *f = (GLOBAL S *)R.f[par ^ 1];
+    const S ns = (S)__builtin_nanf("");
+    for (long long i = t0; i < R.fsize; i += st) f[i] = ns;
+    GLOBAL double *U = (GLOBAL double *)R.U[par ^ 1];
+    for (long long i = t0; i < 4 * R.qplane; i += st) U[i] = __builtin_nan("");
+    if (R.ring_n > 0 && R.G) {
+        GLOBAL C *G = (GLOBAL C *)R.G;
+        for (long long i = t0; i < (long long)NQ * R.rplane; i += st) G[i] = (C)__builtin_nanf("");
+    }
+    if (R.ring_n > 0 && R.P) {
+        GLOBAL double *P = (GLOBAL double *)R.P;
+        for (long long i = t0; i < 4 * R.rplane; i += st) P[i] = __builtin_nan("");
+    }
+}
+
 __global__ void k_set_limit(RunDev *run, long long limit) {
     if (threadIdx.x == 0) run->limit = limit;
 }
@@ -1474,6 +1500,13 @@ static hipError_t launch_advance(const LaunchSet &L, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
+static hipError_t launch_poison(const LaunchSet &L, int storage, int ks, hipStream_t s) {
+    if (L.nruns <= 0) return hipSuccess;
+    LBM_DISPATCH(storage, hipLaunchKernelGGL((k_poison<S>), dim3(1024, L.nruns), dim3(256), 0, s, L.runs,
+                                             ks));
+    return hipGetLastError();
+}
+
 static hipError_t launch_set_limit(RunDev *run, long long limit, hipStream_t s) {
     hipLaunchKernelGGL(k_set_limit, dim3(1), dim3(64), 0, s, run, limit);
     return hipGetLastError();
@@ -1550,7 +1583,7 @@ static hipError_t launch_err_final(const double *partials, int nrows, double *ou
 const KernelSet kernels = {NQ, launch_phase_a, launch_frame, launch_target, launch_phase_a_bulk, launch_bulk,
                            launch_advance, launch_set_limit, launch_set_limits, launch_init,
                            launch_moments, launch_export_f, launch_export_q, launch_check,
-                           launch_err_rows, launch_err_rows_state, launch_err_final};
+                           launch_err_rows, launch_err_rows_state, launch_err_final, launch_poison};
 #endif
 
 }  // namespace LBM_KSET

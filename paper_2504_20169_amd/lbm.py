@@ -22,19 +22,20 @@ LBM_F64, LBM_F32_DEV, LBM_F16_DEV = 0, 1, 2
 LBM_XMIN, LBM_XMAX, LBM_YMIN, LBM_YMAX, LBM_ALL = 1, 2, 4, 8, 15
 LBM_BC_PERIODIC, LBM_BC_ZG, LBM_BC_NRBC, LBM_BC_NRBC_A = 0, 1, 2, 3
 LBM_DEVICE_PTRS = 1
+LBM_DEBUG_POISON = 1
 
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32_DEV, "f16": LBM_F16_DEV}
 BC = {"periodic": LBM_BC_PERIODIC, "zg": LBM_BC_ZG, "nrbc": LBM_BC_NRBC, "nrbc_a": LBM_BC_NRBC_A}
 
 # C symbols exported by the library (the header's declarations).
 EXPORTED = [
-    "lbm_create", "lbm_set_pml", "lbm_set_bc", "lbm_set_nrbc_pml_terms", "lbm_grid", "lbm_footprint", "lbm_init_fields",
+    "lbm_create", "lbm_set_pml", "lbm_set_bc", "lbm_set_nrbc_pml_terms", "lbm_set_debug", "lbm_grid", "lbm_footprint", "lbm_init_fields",
     "lbm_node_classes",
     "lbm_step", "lbm_step_count", "lbm_moments", "lbm_populations", "lbm_pml_q",
     "lbm_velocities", "lbm_error_norms", "lbm_error_norms_noalloc", "lbm_check", "lbm_synchronize", "lbm_set_launch",
     "lbm_get_launch", "lbm_autotune", "lbm_profile", "lbm_profile_read", "lbm_save",
     "lbm_load", "lbm_destroy", "lbm_last_error", "lbm_group_create", "lbm_group_add",
-    "lbm_group_remove", "lbm_group_step", "lbm_group_size", "lbm_group_synchronize",
+    "lbm_group_remove", "lbm_group_step", "lbm_group_size", "lbm_group_check", "lbm_group_synchronize",
     "lbm_group_set_launch", "lbm_group_get_launch", "lbm_group_autotune", "lbm_group_destroy",
 ]
 
@@ -87,6 +88,7 @@ def load():
         "lbm_set_pml": [H, ctypes.c_uint, ctypes.c_int32, ctypes.c_double],
         "lbm_set_bc": [H, ctypes.c_uint, ctypes.c_int],
         "lbm_set_nrbc_pml_terms": [H, ctypes.c_uint],
+        "lbm_set_debug": [H, ctypes.c_uint],
         "lbm_grid": [H, i32p, i32p],
         "lbm_footprint": [H, ctypes.POINTER(ctypes.c_size_t)],
         "lbm_node_classes": [H, i64p],
@@ -118,6 +120,7 @@ def load():
         "lbm_group_remove": [H, H],
         "lbm_group_step": [H, i64p, ctypes.c_int64],
         "lbm_group_size": [H, i32p],
+        "lbm_group_check": [H, i32p],
         "lbm_group_synchronize": [H],
     }
     for name, args in sig.items():
@@ -247,6 +250,10 @@ class Run:
         """Appendix: PML moments in the characteristic target (bit 0 term I, bit 1 term II,
         bit 2 term III)."""
         _check(self._lib.lbm_set_nrbc_pml_terms(self.h, int(flags)))
+
+    def set_debug(self, flags):
+        """Debug flags (LBM_DEBUG_POISON: NaN canary in the buffers each step writes)."""
+        _check(self._lib.lbm_set_debug(self.h, int(flags)))
 
     def grid(self):
         nx, ny = ctypes.c_int32(), ctypes.c_int32()
@@ -416,6 +423,12 @@ class Group:
         n = ctypes.c_int32()
         _check(self._lib.lbm_group_size(self.g, ctypes.byref(n)))
         return n.value
+
+    def check(self):
+        """Per-member health flags (member order): 0 healthy, 1 non-finite, rho <= 0 or T <= 0."""
+        out = np.zeros(max(len(self.members), 1), dtype=np.int32)
+        _check(self._lib.lbm_group_check(self.g, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return out[:len(self.members)]
 
     def close(self):
         if getattr(self, "g", None):

@@ -3,19 +3,23 @@ advanced together by batched launches (continuous batching), with per-job latenc
 
 Each tick the engine (1) admits waiting jobs in arrival order while they fit the HBM budget and
 the slot limit (a job that does not fit yet does not block smaller ones behind it; a job larger
-than the whole budget is rejected), (2) advances every resident job by up to ``tick_steps``
-steps in one batched call -- jobs admitted this tick share the launches of jobs already running
--- and (3) retires finished jobs: moments are exported, device memory is released and the
-latency (arrival to result) is recorded.  A job whose state fails the stability check is
-retired with an error and does not disturb the others.
+than the whole budget is rejected), (2) moves admitted jobs whose state is ready into the batch,
+(3) advances every resident job by up to ``tick_steps`` steps in one batched call -- jobs admitted
+this tick share the launches of jobs already running -- and (4) checks every resident job's state
+at once and retires finished jobs: moments are exported, device memory is released and the
+latency (arrival to result) is recorded.  A job whose state fails the stability check is retired
+with an error and does not disturb the others.
 
-The backend is pluggable: ``GpuBackend`` drives the HIP library through ``lbm.Group``;
-tests use a mock backend to check the scheduling on the CPU.
+A backend that offers ``prepare`` builds an admitted job's run (its initial fields on the host and
+their upload) on worker threads, off the tick path, so arrivals do not stall the batch; one that
+offers ``check_all`` checks the whole batch with one synchronisation.  ``GpuBackend`` drives the
+HIP library through ``lbm.Group`` and offers both; the CPU tests use mock backends.
 """
 from __future__ import annotations
 
 import time
 from collections import deque
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import Any, Optional
 
@@ -37,9 +41,10 @@ class Job:
     admitted: Optional[float] = None
     finished: Optional[float] = None
     done_steps: int = 0
-    status: str = "queued"          # queued | running | done | failed | rejected
+    status: str = "queued"          # queued | preparing | running | done | failed | rejected
     result: Any = None
     handle: Any = field(default=None, repr=False)
+    pending: Any = field(default=None, repr=False)
     nbytes: int = 0
 
     @property
@@ -52,22 +57,23 @@ class Job:
 
 
 class GpuBackend:
-    """Runs jobs on the HIP library: one lbm.Run per job, all resident runs in one lbm.Group."""
+    """Runs jobs on the HIP library: one lbm.Run per job, all resident runs in one lbm.Group.
+    Admitted jobs are built on `workers` threads (fields and upload on the run's own stream) and
+    join the group once ready."""
 
-    def __init__(self, storage="f32", stream=None, allocator=None, check_every_tick=True):
+    def __init__(self, storage="f32", stream=None, allocator=None, workers=4):
         from paper_2504_20169_amd import lbm
         self.lbm = lbm
         self.storage = storage
         self.stream = stream
         self.allocator = allocator
         self.group = lbm.Group(stream=stream, allocator=allocator)
-        self.check_every_tick = check_every_tick
+        self.pool = ThreadPoolExecutor(max_workers=workers) if workers > 0 else None
 
     def _make(self, job: Job):
-        from paper_2504_20169_amd import workloads as wl
         lbm = self.lbm
         r = lbm.Run(job.L, job.L, 0.8, 1.0, job.mach, 0.0, 1.0, storage=self.storage,
-                    stream=self.stream, allocator=self.allocator)
+                    allocator=self.allocator)
         r.set_bc(lbm.LBM_ALL, job.bc)
         if job.W > 0:
             r.set_pml(lbm.LBM_ALL, job.W, job.sigma_max)
@@ -79,12 +85,31 @@ class GpuBackend:
         r.close()
         return b
 
-    def start(self, job: Job):
+    def _build(self, job: Job):
         from paper_2504_20169_amd import workloads as wl
         r = self._make(job)
         spec = wl.vortex_pulse(L=job.L, W=job.W, sigma_max=job.sigma_max, mach=job.mach,
                                bc=job.bc, seed=job.seed, radius=min(16.0, job.L / 8.0))
         r.init(*spec.fields.as_tuple())
+        return r
+
+    def prepare(self, job: Job):
+        """A future of the job's initialised run, built off the caller's thread."""
+        if self.pool is None:
+            class _Done:
+                def __init__(self, v):
+                    self.v = v
+
+                def done(self):
+                    return True
+
+                def result(self):
+                    return self.v
+            return _Done(self._build(job))
+        return self.pool.submit(self._build, job)
+
+    def start(self, job: Job, run=None):
+        r = run if run is not None else self._build(job)
         self.group.add(r)
         return r
 
@@ -102,6 +127,12 @@ class GpuBackend:
     def healthy(self, r) -> bool:
         return r.check() == self.lbm.LBM_OK
 
+    def check_all(self, handles):
+        """Health of each handle, from one check of the whole group."""
+        flags = self.group.check()
+        order = {id(r): k for k, r in enumerate(self.group.members)}
+        return [flags[order[id(r)]] == 0 for r in handles]
+
     def finish(self, r):
         rho, ux, uy, T = r.moments()
         self.group.remove(r)
@@ -112,7 +143,13 @@ class GpuBackend:
         self.group.remove(r)
         r.close()
 
+    def discard(self, run):
+        """Release a prepared run that never joined the group."""
+        run.close()
+
     def close(self):
+        if self.pool is not None:
+            self.pool.shutdown(wait=True)
         self.group.close()
 
 
@@ -125,6 +162,7 @@ class Engine:
         self.tick_steps = tick_steps
         self.clock = clock
         self.waiting: deque[Job] = deque()
+        self.preparing: list[Job] = []
         self.active: list[Job] = []
         self.finished: list[Job] = []
         self.used = 0
@@ -142,23 +180,55 @@ class Engine:
 
     def _admit(self, now):
         keep = deque()
+        prep = getattr(self.backend, "prepare", None)
         while self.waiting:
             job = self.waiting.popleft()
-            if len(self.active) < self.max_jobs and self.used + job.nbytes <= self.budget:
-                job.handle = self.backend.start(job)
+            if len(self.active) + len(self.preparing) < self.max_jobs and \
+                    self.used + job.nbytes <= self.budget:
                 job.admitted = now
-                job.status = "running"
                 self.used += job.nbytes
-                self.active.append(job)
+                if prep is not None:
+                    job.pending = prep(job)
+                    job.status = "preparing"
+                    self.preparing.append(job)
+                else:
+                    job.handle = self.backend.start(job)
+                    job.status = "running"
+                    self.active.append(job)
             else:
                 keep.append(job)
         self.waiting = keep
+
+    def _join_ready(self, wait):
+        """Move prepared jobs into the batch (all of them if `wait`, else the ready ones)."""
+        still = []
+        for j in self.preparing:
+            if wait or j.pending.done():
+                try:
+                    run = j.pending.result()
+                except Exception as exc:          # the job could not be set up: retire it
+                    j.pending = None
+                    j.status = "failed"
+                    j.result = dict(error=str(exc))
+                    j.finished = self.clock()
+                    self.used -= j.nbytes
+                    self.finished.append(j)
+                    continue
+                j.handle = self.backend.start(j, run)
+                j.pending = None
+                j.status = "running"
+                self.active.append(j)
+            else:
+                still.append(j)
+        self.preparing = still
 
     def tick(self):
         now = self.clock()
         if self.t0 is None:
             self.t0 = now
         self._admit(now)
+        # with nothing resident, wait for the jobs being prepared instead of spinning
+        self._join_ready(wait=not self.active)
         if not self.active:
             return 0
         steps = [min(self.tick_steps, j.steps - j.done_steps) for j in self.active]
@@ -167,9 +237,14 @@ class Engine:
         for j, s in zip(self.active, steps):
             j.done_steps += s
             self.node_updates += j.nodes * s
+        check_all = getattr(self.backend, "check_all", None)
+        if check_all is not None:
+            ok = check_all([j.handle for j in self.active])
+        else:
+            ok = [self.backend.healthy(j.handle) for j in self.active]
         still = []
-        for j in self.active:
-            if not self.backend.healthy(j.handle):
+        for j, good in zip(self.active, ok):
+            if not good:
                 self.backend.drop(j.handle)
                 j.status = "failed"
             elif j.done_steps >= j.steps:
@@ -191,11 +266,11 @@ class Engine:
         start = self.clock()
         for j in pending:
             j.arrival = start + j.arrival
-        while pending or self.waiting or self.active:
+        while pending or self.waiting or self.active or self.preparing:
             now = self.clock()
             while pending and (pending[0].arrival <= now or not realtime):
                 self.submit(pending.popleft())
-            if not self.active and not self.waiting:
+            if not self.active and not self.waiting and not self.preparing:
                 if pending and realtime:
                     time.sleep(max(0.0, min(0.05, pending[0].arrival - self.clock())))
                 continue

@@ -107,3 +107,57 @@ def test_trace_report_percentiles():
     assert rep["done"] == 20
     assert rep["p50_s"] <= rep["p99_s"]
     assert rep["aggregate_mlups"] > 0
+
+
+class PreparingBackend(MockBackend):
+    """Mock of a backend that builds admitted jobs off the tick path and checks the whole batch
+    at once: a job's run is ready only after `delay` further polls."""
+
+    def __init__(self, delay=2, fail_build=(), **kw):
+        super().__init__(**kw)
+        self.delay = delay
+        self.fail_build = set(fail_build)
+        self.checks = 0
+
+    def prepare(self, job):
+        be = self
+
+        class Pending:
+            polls = 0
+
+            def done(self):
+                self.polls += 1
+                return self.polls > be.delay
+
+            def result(self):
+                if job.jid in be.fail_build:
+                    raise RuntimeError("setup failed")
+                return ("run", job.jid)
+
+        return Pending()
+
+    def start(self, job, run=None):
+        assert run == ("run", job.jid)
+        return super().start(job)
+
+    def check_all(self, handles):
+        self.checks += 1
+        return [self.healthy(h) for h in handles]
+
+
+def test_prepared_jobs_join_when_ready_and_failed_setup_is_retired():
+    be = PreparingBackend(delay=2, fail_build=[3])
+    eng = Engine(be, hbm_budget=10 ** 9, tick_steps=10, clock=Clock())
+    for k in range(4):
+        eng.submit(_job(k, 16, 30))
+    eng.tick()                        # nothing resident yet: the engine waits for all prepared runs
+    assert be.launches[0] == [0, 1, 2]
+    eng.submit(_job(4, 16, 20))
+    eng.tick()                        # job 4 is still being prepared: the others step without it
+    assert be.launches[1] == [0, 1, 2]
+    while eng.active or eng.waiting or eng.preparing:
+        eng.tick()
+    st = {j.jid: j.status for j in eng.finished}
+    assert st == {0: "done", 1: "done", 2: "done", 3: "failed", 4: "done"}
+    assert eng.used == 0
+    assert be.checks == len(be.launches)   # one batch check per tick
