@@ -106,19 +106,6 @@ def add_noise(F: Fields, seed: int, amp_rho=1e-3, amp_u=1e-3, amp_T=1e-3) -> Fie
     return F
 
 
-def density_step(Nx, Ny, Lx, x_offset, rho0=1.0, rho1=1.05, s=0.5, ux0=0.0, T0=1.0) -> Fields:
-    """Smooth 1-D density step of the paper's first benchmark (Sec. 5.1): tanh steps at Lx/4 and
-    3Lx/4 of the bulk, with the bulk starting at column ``x_offset`` of the full grid."""
-    x, _ = _grid(Nx, Ny)
-    xb = x - x_offset
-    left = rho1 + 0.5 * (rho1 - rho0) * (np.tanh(s * (xb - 0.25 * Lx)) - 1.0)
-    right = rho1 - 0.5 * (rho1 - rho0) * (np.tanh(s * (xb - 0.75 * Lx)) - 1.0)
-    rho = np.where(xb <= 0.5 * Lx, left, right)
-    F = uniform_state(Nx, Ny, 1.0, ux0, 0.0, T0)
-    F.rho = rho
-    return F
-
-
 # ------------------------------------------------------------------------------------------
 # Named workloads.  Each returns a dict with the run description and the initial fields.
 # ------------------------------------------------------------------------------------------
