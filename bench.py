@@ -220,6 +220,11 @@ def batch_leg(torch, lbm, wl, args):
     specs = wl.batch_sweep(nruns=args.batch_runs, steps=args.batch_steps, sigma_max=0.0015)
     runs = [run_from_spec(lbm, sp, "f32") for sp in specs]
     updates = sum(sp.Nx * sp.Ny for sp in specs) * args.batch_steps
+    # algorithmic bytes of one step of every run (2 q b per node, Q and U on the Q region)
+    step_bytes = 0
+    for r, sp in zip(runs, specs):
+        n_bulk, n_frame, n_q, _ = r.node_classes()
+        step_bytes += kernel_bytes("f32", sp.lattice, n_bulk, n_frame, n_q)[2]
     for r in runs:
         r.step(2)
     for r in runs:
@@ -246,6 +251,9 @@ def batch_leg(torch, lbm, wl, args):
     return dict(runs=len(specs), steps=args.batch_steps, nodes=sum(sp.Nx * sp.Ny for sp in specs),
                 sequential_mlups=updates / t_seq / 1e6, group_mlups=updates / t_grp / 1e6,
                 speedup=t_seq / t_grp, stable=ok, group_launch=tuned,
+                step_bytes=step_bytes,
+                group_gbs=step_bytes * args.batch_steps / t_grp / 1e9,
+                group_frac=step_bytes * args.batch_steps / t_grp / 1e9 / HBM_PEAK_GBS,
                 workload="batch sweep: bulk L in {128,256,512,1024}, W in {0,4,8,16,32}, ZG/NRBC, "
                          "vortex + pulse, sigma_max 0.0015, FP32 storage")
 
@@ -334,6 +342,53 @@ def stats_summary(stats_csv, out_path, command, note):
         lines.append("%-72s %7s %12.2f %12.2f %12.2f %8.2f" % (
             r["Name"][:72], r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
             float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    with open(out_path, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def gaps_summary(trace_csv, out_path, command, note, kernel="k_frame", steps=200):
+    """Idle time between kernel dispatches in a rocprofv3 --kernel-trace CSV, over the last
+    `steps` dispatches of `kernel` at its largest grid (the steps of the timed run: a group's
+    launches are the largest): the window runs from the end of the dispatch of `kernel` before
+    them to the end of the last, and busy time is the union of the dispatch intervals inside it.
+    The idle part is what a persistent kernel that replaces the launches could recover at most."""
+    import csv
+    with open(trace_csv) as f:
+        rows = [r for r in csv.DictReader(f) if r.get("Kind", "KERNEL_DISPATCH") == "KERNEL_DISPATCH"]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    ks = [r for r in rows if kernel in r["Kernel_Name"]]
+    gmax = max(int(r["Grid_Size_X"]) for r in ks)
+    ks = [r for r in ks if int(r["Grid_Size_X"]) == gmax]
+    if len(ks) < steps + 1:
+        raise SystemExit("only %d dispatches of %s at grid %d" % (len(ks), kernel, gmax))
+    t0, t1 = int(ks[-steps - 1]["End_Timestamp"]), int(ks[-1]["End_Timestamp"])
+    inside = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]) for r in rows
+              if int(r["Start_Timestamp"]) >= t0 and int(r["End_Timestamp"]) <= t1]
+    busy, cur_s, cur_e = 0, None, None
+    per = {}
+    for a, e, name in inside:
+        per.setdefault(name, []).append(e - a)
+        if cur_e is None or a > cur_e:
+            if cur_e is not None:
+                busy += cur_e - cur_s
+            cur_s, cur_e = a, e
+        else:
+            cur_e = max(cur_e, e)
+    if cur_e is not None:
+        busy += cur_e - cur_s
+    wall = t1 - t0
+    lines = ["# rocprofv3 --kernel-trace: idle time between dispatches over the timed steps",
+             "command: " + command, note, "",
+             "steps: %d (dispatches of %s with grid %d)" % (steps, kernel, gmax),
+             "wall_us: %.1f" % (wall / 1e3), "busy_us: %.1f" % (busy / 1e3),
+             "idle_us: %.1f" % ((wall - busy) / 1e3),
+             "idle_fraction: %.4f" % ((wall - busy) / wall),
+             "wall_us_per_step: %.2f" % (wall / 1e3 / steps),
+             "idle_us_per_step: %.2f" % ((wall - busy) / 1e3 / steps), "",
+             "%-72s %7s %12s %12s" % ("kernel", "calls", "avg_us", "total_us")]
+    for name, d in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        lines.append("%-72s %7d %12.2f %12.1f" % (name[:72], len(d), sum(d) / len(d) / 1e3, sum(d) / 1e3))
     with open(out_path, "w") as fo:
         fo.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -485,12 +540,19 @@ def main():
                     help="summarise a rocprofv3 --kernel-trace --stats CSV into OUT and exit (no GPU)")
     ap.add_argument("--stats-command", default="", help="command line recorded in the summary")
     ap.add_argument("--stats-note", default="", help="workload note recorded in the summary")
+    ap.add_argument("--gaps-summary", nargs=2, metavar=("TRACE_CSV", "OUT"),
+                    help="write the idle time between dispatches of a rocprofv3 kernel trace and exit")
+    ap.add_argument("--gaps-steps", type=int, default=200, help="timed steps in the trace")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary, command=args.pmc_command)
         return
     if args.stats_summary:
         stats_summary(*args.stats_summary, command=args.stats_command, note=args.stats_note)
+        return
+    if args.gaps_summary:
+        gaps_summary(*args.gaps_summary, command=args.stats_command, note=args.stats_note,
+                     steps=args.gaps_steps)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -115,13 +115,16 @@ typedef struct {
  * boundary/PML work of a step meets the bulk kernel: 0 runs the kernels of a step in order on
  * the run's stream; 1 runs the boundary/PML chain on a side stream beside the bulk kernel (only
  * for a run that owns its stream; eager launches, no graphs); 2 launches phase A (characteristic
- * fill of the ring, PML Q update) and the bulk tiles as one grid (the phase-A blocks after half
- * of the tiles for D2Q37 in FP64, first otherwise), so they run beside the streaming tiles (one
- * stream, graphs and groups allowed).  All three give the same bits.  Default {64, 4, 32, 2}. */
+ * fill of the ring, PML Q update) and the bulk tiles as one grid, so they run beside the
+ * streaming tiles (one stream, graphs and groups allowed); split places the phase-A blocks in
+ * that grid: after split/8 of the bulk tiles (0..8, rounded down to a multiple of 8 blocks), or
+ * -1 for the measured default (after half of the tiles for D2Q37 in FP64, first otherwise).
+ * Every schedule and placement gives the same bits.  Default {64, 4, 32, 2, -1}. */
 typedef struct {
     int32_t bulk_tx, bulk_ty;
     int32_t graph_steps;
     int32_t overlap;
+    int32_t split;
 } lbm_launch;
 
 /* Create a run (Sec. 2).  Validates the descriptor (LBM_ERR_ARG: tau <= 0.5, size < 1,
@@ -252,10 +255,12 @@ lbm_status lbm_synchronize(lbm_handle h);
 lbm_status lbm_set_launch(lbm_handle h, const lbm_launch *cfg);
 lbm_status lbm_get_launch(lbm_handle h, lbm_launch *cfg);
 
-/* Time every supported bulk tile shape, in order and (for a run that owns its stream)
- * overlapped, on a scratch copy of this run's geometry (the run's own state is untouched) and
+/* Time every supported bulk tile shape in each schedule -- in order, on a side stream (for a
+ * run that owns its stream), and fused with the phase-A blocks after 0, 2, 4, 6 or 8 eighths of
+ * the tiles -- on a scratch copy of this run's geometry (the run's own state is untouched) and
  * keep the fastest; if cache_path is non-NULL the choice is read from / appended to that text
- * file, one line "Nx Ny storage lattice bulk_tx overlap" per choice.  *chosen may be NULL. */
+ * file, one line "Nx Ny storage lattice bulk_tx overlap split" per choice (a line without the
+ * split reads as split -1).  *chosen may be NULL. */
 lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path,
                         lbm_launch *chosen);
 
@@ -303,9 +308,10 @@ lbm_status lbm_group_step(lbm_group_handle g, const int64_t *steps, int64_t nste
  * (a group runs on one stream).  Default {64, 4, 32, 2}.  LBM_ERR_ARG for unsupported values. */
 lbm_status lbm_group_set_launch(lbm_group_handle g, const lbm_launch *cfg);
 lbm_status lbm_group_get_launch(lbm_group_handle g, lbm_launch *cfg);
-/* Time every bulk tile shape on a scratch group that holds one scratch run (mean state) per
- * distinct member geometry (grid, PML, boundaries, storage, layout) and keep the fastest for
- * this group.  The members' state is untouched; the scratch memory is freed before return.
+/* Time every bulk tile shape, in order and fused with the phase-A blocks after 0, 2, 4, 6 or 8
+ * eighths of the tiles (18 configurations), on a scratch group that holds one scratch run (mean
+ * state) per distinct member geometry (grid, PML, boundaries, storage, layout) and keep the
+ * fastest for this group.  The members' state is untouched; the scratch memory is freed before return.
  * LBM_ERR_STATE for an empty group.  *chosen may be NULL. */
 lbm_status lbm_group_autotune(lbm_group_handle g, int32_t steps, lbm_launch *chosen);
 lbm_status lbm_group_size(lbm_group_handle g, int32_t *n);

@@ -128,13 +128,14 @@ struct lbm_run {
     double *fbar_d = nullptr;
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;     // stream in use (the group's while in a group)
-    lbm_launch launch{64, 4, 32, 2};
+    lbm_launch launch{64, 4, 32, 2, -1};
     int64_t steps = 0;
     DeviceMem mem;
     hipGraphExec_t graph = nullptr;
     int graph_G = 0;
     int graph_tx = 0;
     int graph_ov = 0;
+    int graph_split = -1;
     bool graph_failed = false;
     int prof = 0;                     // 0 off, 1 classes in order, 2 bulk kernel in the normal schedule,
                                       // 3 as 2 on the first step of each batch only
@@ -159,7 +160,7 @@ struct lbm_group {
     bool dirty = true;
     int storage = -1;
     const KernelSet *ks = nullptr;    // stencil of the members (set by the first member)
-    lbm_launch launch{64, 4, 32, 2};
+    lbm_launch launch{64, 4, 32, 2, -1};
     hipGraphExec_t graph = nullptr;   // graph_G batched steps of the current membership
     int graph_G = 0;
     bool graph_failed = false;
@@ -358,6 +359,7 @@ LaunchSet single_set(lbm_run *h) {
         L.blocks[c] = h->nblocks[c];
     }
     L.poison = (h->debug & LBM_DEBUG_POISON) ? 1 : 0;
+    L.split = h->launch.split;
     L.nruns = 1;
     return L;
 }
@@ -511,6 +513,7 @@ lbm_status build_graph(lbm_run *h, int G) {
     h->graph_G = G;
     h->graph_tx = h->launch.bulk_tx;
     h->graph_ov = h->launch.overlap;
+    h->graph_split = h->launch.split;
     return LBM_OK;
 }
 
@@ -787,7 +790,7 @@ lbm_status lbm_step(lbm_handle h, int64_t n) {
     const bool fused = h->launch.overlap == 2;
     if (!h->prof && !overlap && G > 0 && !h->graph_failed && n >= G) {
         if (!h->graph || h->graph_G != G || h->graph_tx != h->launch.bulk_tx ||
-            h->graph_ov != h->launch.overlap) {
+            h->graph_ov != h->launch.overlap || h->graph_split != h->launch.split) {
             lbm_status st = build_graph(h, G);
             if (st != LBM_OK) return st;
         }
@@ -975,6 +978,7 @@ lbm_status lbm_set_launch(lbm_handle h, const lbm_launch *cfg) {
         return fail(LBM_ERR_ARG, "bulk tile must be 64x4, 128x2 or 256x1");
     if (cfg->graph_steps < 0 || (cfg->graph_steps & 1)) return fail(LBM_ERR_ARG, "graph_steps must be even and >= 0");
     if (cfg->overlap < 0 || cfg->overlap > 2) return fail(LBM_ERR_ARG, "overlap must be 0, 1 or 2");
+    if (cfg->split < -1 || cfg->split > 8) return fail(LBM_ERR_ARG, "split must be -1 or 0..8");
     if (h->group) return fail(LBM_ERR_STATE, "run is in a group");
     h->launch = *cfg;
     if (h->inited) return upload_prefix(h);
@@ -1122,12 +1126,12 @@ lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path, lbm
         if (fp) {
             char line[256];
             while (std::fgets(line, sizeof line, fp)) {
-                int nx, ny, st, q, tx, ov;
-                if (std::sscanf(line, "%d %d %d %d %d %d", &nx, &ny, &st, &q, &tx, &ov) != 6) continue;
+                int nx, ny, st, q, tx, ov, sp = -1;
+                if (std::sscanf(line, "%d %d %d %d %d %d %d", &nx, &ny, &st, &q, &tx, &ov, &sp) < 6) continue;
                 if (nx == R.Nx && ny == R.Ny && st == h->desc.storage && q == h->lat->q) {
                     std::fclose(fp);
                     lbm_launch c = h->launch;
-                    c.bulk_tx = tx; c.bulk_ty = 256 / tx; c.overlap = ov;
+                    c.bulk_tx = tx; c.bulk_ty = 256 / tx; c.overlap = ov; c.split = sp;
                     lbm_status s2 = lbm_set_launch(h, &c);
                     if (chosen) *chosen = h->launch;
                     return s2;
@@ -1147,36 +1151,41 @@ lbm_status lbm_autotune(lbm_handle h, int32_t steps, const char *cache_path, lbm
     std::vector<double> f1(nn, d.rho0), f2(nn, d.ux0), f3(nn, d.uy0), f4(nn, d.T0);
     st = lbm_init_fields(s, f1.data(), f2.data(), f3.data(), f4.data());
     if (st != LBM_OK) { lbm_destroy(s); return st; }
-    int best_tx = h->launch.bulk_tx, best_ov = h->launch.overlap;
+    int best_tx = h->launch.bulk_tx, best_ov = h->launch.overlap, best_sp = h->launch.split;
     float best = 1e30f;
     hipEvent_t a = nullptr, b = nullptr;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
+    // tile widths x schedules, and for the fused grid the phase-A placement in eighths of the tiles
     for (int ov = 0; ov < 3; ++ov) {
         if (ov == 1 && d.stream) continue;   // the side stream needs a stream the run owns
         for (int tx : {64, 128, 256}) {
-            lbm_launch c{tx, 256 / tx, 0, ov};
-            if (lbm_set_launch(s, &c) != LBM_OK) continue;
-            lbm_step(s, 2);
-            (void)hipEventRecord(a, s->stream);
-            lbm_step(s, steps);
-            (void)hipEventRecord(b, s->stream);
-            (void)hipEventSynchronize(b);
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, a, b);
-            if (ms < best) { best = ms; best_tx = tx; best_ov = ov; }
+            for (int sp : {0, 2, 4, 6, 8}) {
+                if (ov != 2 && sp != 0) continue;
+                lbm_launch c{tx, 256 / tx, 0, ov, ov == 2 ? sp : -1};
+                if (lbm_set_launch(s, &c) != LBM_OK) continue;
+                lbm_step(s, 2);
+                (void)hipEventRecord(a, s->stream);
+                lbm_step(s, steps);
+                (void)hipEventRecord(b, s->stream);
+                (void)hipEventSynchronize(b);
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, a, b);
+                if (ms < best) { best = ms; best_tx = tx; best_ov = ov; best_sp = c.split; }
+            }
         }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     lbm_destroy(s);
     lbm_launch c = h->launch;
-    c.bulk_tx = best_tx; c.bulk_ty = 256 / best_tx; c.overlap = best_ov;
+    c.bulk_tx = best_tx; c.bulk_ty = 256 / best_tx; c.overlap = best_ov; c.split = best_sp;
     st = lbm_set_launch(h, &c);
     if (st == LBM_OK && cache_path) {
         FILE *fp = std::fopen(cache_path, "a");
         if (fp) {
-            std::fprintf(fp, "%d %d %d %d %d %d\n", R.Nx, R.Ny, h->desc.storage, h->lat->q, best_tx, best_ov);
+            std::fprintf(fp, "%d %d %d %d %d %d %d\n", R.Nx, R.Ny, h->desc.storage, h->lat->q, best_tx, best_ov,
+                         best_sp);
             std::fclose(fp);
         }
     }
@@ -1324,6 +1333,7 @@ lbm_status lbm_group_step(lbm_group_handle g, const int64_t *steps, int64_t nste
     }
     L.nruns = (int)n;
     L.poison = g->poison;
+    L.split = g->launch.split;
     // Runs past their own count skip every kernel, so whole graphs of G batched steps serve any
     // mix of counts; the remainder is launched eagerly.
     int64_t left = K;
@@ -1379,6 +1389,7 @@ lbm_status lbm_group_set_launch(lbm_group_handle g, const lbm_launch *cfg) {
     if (cfg->graph_steps < 0 || (cfg->graph_steps & 1)) return fail(LBM_ERR_ARG, "graph_steps must be even and >= 0");
     if (cfg->overlap != 0 && cfg->overlap != 2)
         return fail(LBM_ERR_ARG, "groups run on one stream (overlap 0 or 2)");
+    if (cfg->split < -1 || cfg->split > 8) return fail(LBM_ERR_ARG, "split must be -1 or 0..8");
     HIP_TRY(hipStreamSynchronize(g->stream));
     g->launch = *cfg;
     g->graph_failed = false;
@@ -1428,10 +1439,12 @@ lbm_status lbm_group_autotune(lbm_group_handle g, int32_t steps, lbm_launch *cho
         hipEvent_t a = nullptr, b = nullptr;
         (void)hipEventCreate(&a);
         (void)hipEventCreate(&b);
-        for (int k = 0; k < 6; ++k) {
+        // tile widths x {in order, fused with the phase-A blocks after 0, 2, 4, 6 or 8 eighths of
+        // the tiles}
+        for (int k = 0; k < 18; ++k) {
             if (st != LBM_OK) break;
-            const int tx = 64 << (k % 3), ov = k < 3 ? 0 : 2;
-            lbm_launch c{tx, 256 / tx, 0, ov};
+            const int tx = 64 << (k % 3), j = k / 3, ov = j == 0 ? 0 : 2, sp = j == 0 ? -1 : 2 * (j - 1);
+            lbm_launch c{tx, 256 / tx, 0, ov, sp};
             if ((st = lbm_group_set_launch(sg, &c)) != LBM_OK) break;
             if ((st = lbm_group_step(sg, nullptr, 2)) != LBM_OK) break;
             (void)hipEventRecord(a, g->stream);
@@ -1442,7 +1455,7 @@ lbm_status lbm_group_autotune(lbm_group_handle g, int32_t steps, lbm_launch *cho
             (void)hipEventElapsedTime(&ms, a, b);
             if (ms < best) {
                 best = ms; best_c = g->launch;
-                best_c.bulk_tx = tx; best_c.bulk_ty = 256 / tx; best_c.overlap = ov;
+                best_c.bulk_tx = tx; best_c.bulk_ty = 256 / tx; best_c.overlap = ov; best_c.split = sp;
             }
         }
         (void)hipEventDestroy(a);

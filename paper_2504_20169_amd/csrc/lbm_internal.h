@@ -71,6 +71,7 @@ struct LaunchSet {
     int blocks[NCLS];         // total blocks per class
     int nruns;
     int poison = 0;           // debug canary: NaN-fill each step's destination buffers first
+    int split = -1;           // fused grid: phase-A blocks after split/8 of the tiles; -1 default
 };
 
 constexpr int FRAME_BLOCK = 256;

@@ -58,7 +58,12 @@ class lbm_desc(ctypes.Structure):
 
 class lbm_launch(ctypes.Structure):
     _fields_ = [("bulk_tx", ctypes.c_int32), ("bulk_ty", ctypes.c_int32),
-                ("graph_steps", ctypes.c_int32), ("overlap", ctypes.c_int32)]
+                ("graph_steps", ctypes.c_int32), ("overlap", ctypes.c_int32), ("split", ctypes.c_int32)]
+
+
+def _launch_dict(c):
+    return dict(bulk_tx=c.bulk_tx, bulk_ty=c.bulk_ty, graph_steps=c.graph_steps, overlap=c.overlap,
+                split=c.split)
 
 
 class LbmError(RuntimeError):
@@ -330,24 +335,23 @@ class Run:
             _check(st)
         return st
 
-    def set_launch(self, bulk_tx=64, graph_steps=32, overlap=2):
+    def set_launch(self, bulk_tx=64, graph_steps=32, overlap=2, split=-1):
         """overlap: 0 kernels in order, 1 boundary/PML chain on a side stream, 2 phase A fused
-        with the bulk tiles in one grid; the same bits in every schedule."""
-        c = lbm_launch(int(bulk_tx), 256 // int(bulk_tx), int(graph_steps), int(overlap))
+        with the bulk tiles in one grid (split: phase-A blocks after split/8 of the tiles, -1 the
+        default placement); the same bits in every schedule."""
+        c = lbm_launch(int(bulk_tx), 256 // int(bulk_tx), int(graph_steps), int(overlap), int(split))
         _check(self._lib.lbm_set_launch(self.h, ctypes.byref(c)))
 
     def get_launch(self):
         c = lbm_launch()
         _check(self._lib.lbm_get_launch(self.h, ctypes.byref(c)))
-        return dict(bulk_tx=c.bulk_tx, bulk_ty=c.bulk_ty, graph_steps=c.graph_steps,
-                    overlap=c.overlap)
+        return _launch_dict(c)
 
     def autotune(self, steps=10, cache_path=None):
         c = lbm_launch()
         _check(self._lib.lbm_autotune(self.h, int(steps),
                                       cache_path.encode() if cache_path else None, ctypes.byref(c)))
-        return dict(bulk_tx=c.bulk_tx, bulk_ty=c.bulk_ty, graph_steps=c.graph_steps,
-                    overlap=c.overlap)
+        return _launch_dict(c)
 
     def profile(self, mode=1):
         """Event timing: 1 (or True) kernel classes in order, 2 bulk kernel in the normal
@@ -401,23 +405,21 @@ class Group:
     def synchronize(self):
         _check(self._lib.lbm_group_synchronize(self.g))
 
-    def set_launch(self, bulk_tx=64, graph_steps=32, overlap=2):
-        """overlap 0 (kernels in order) or 2 (phase A fused with the bulk tiles); a group runs on
-        one stream, so the side-stream schedule (1) is refused."""
-        c = lbm_launch(int(bulk_tx), 256 // int(bulk_tx), int(graph_steps), int(overlap))
+    def set_launch(self, bulk_tx=64, graph_steps=32, overlap=2, split=-1):
+        """overlap 0 (kernels in order) or 2 (phase A fused with the bulk tiles, split as for a
+        run); a group runs on one stream, so the side-stream schedule (1) is refused."""
+        c = lbm_launch(int(bulk_tx), 256 // int(bulk_tx), int(graph_steps), int(overlap), int(split))
         _check(self._lib.lbm_group_set_launch(self.g, ctypes.byref(c)))
 
     def get_launch(self):
         c = lbm_launch()
         _check(self._lib.lbm_group_get_launch(self.g, ctypes.byref(c)))
-        return dict(bulk_tx=c.bulk_tx, bulk_ty=c.bulk_ty, graph_steps=c.graph_steps,
-                    overlap=c.overlap)
+        return _launch_dict(c)
 
     def autotune(self, steps=10):
         c = lbm_launch()
         _check(self._lib.lbm_group_autotune(self.g, int(steps), ctypes.byref(c)))
-        return dict(bulk_tx=c.bulk_tx, bulk_ty=c.bulk_ty, graph_steps=c.graph_steps,
-                    overlap=c.overlap)
+        return _launch_dict(c)
 
     def size(self):
         n = ctypes.c_int32()

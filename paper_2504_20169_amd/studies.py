@@ -132,6 +132,61 @@ def density_step_study(steps=600, sample=10, Lx=200, Ly=20, mach=0.05, tau=0.8,
     return out, Nref
 
 
+def cost_study(Lx=200, Ly=2048, steps=200, repeats=5, mach=0.05, tau=0.8, widths=(10, 20, 40),
+               bcs=("zg", "nrbc"), storage="f64", lattice=37):
+    """C_t of Sec. 5 ("Computational Cost") on the density step's geometry made tall enough that
+    no launch is latency-bound: Lx x Ly bulk (Ly = 2048 by default; the density step's physics is
+    uniform along y, so only the height changes), periodic along y, the boundary on both x sides,
+    a PML of width W on them with the paper's sigma_max for the stencil.
+
+    t_BC of a configuration is the time it spends per step beyond the bulk's own update: its
+    whole-step time minus that of the fully periodic Lx x Ly bulk.  That includes the stream and
+    collide of the PML nodes, which the paper names as the dominant part of a PML's cost, the PML
+    auxiliary update, and the boundary treatment.  C_t = t_BC / t_BC(ZG without PML).  Step times
+    are the median over `repeats` passes of `steps` steps (host clock around synchronised
+    lbm_step calls, each configuration alone on the device); the per-class kernel times of one
+    in-order pass are reported beside them.  Returns rows (bc, W, sigma_max, t_step_us, t_bc_us,
+    C_t, bulk/frame/phase_a kernel us) and the periodic bulk's step time."""
+    from paper_2504_20169_amd import lbm
+
+    def timed(r):
+        r.step(20)
+        r.synchronize()
+        ts = []
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            r.step(steps)
+            r.synchronize()
+            ts.append((time.perf_counter() - t0) / steps)
+        r.profile(1)
+        r.profile_read(reset=True)
+        r.step(steps)
+        ms, n = r.profile_read(reset=True)
+        r.profile(0)
+        per = [m / max(k, 1) * 1e3 for m, k in zip(ms, n)]
+        return float(np.median(ts)) * 1e6, per
+
+    per = _make(lbm, Lx, Ly, "periodic", 0, 0.0, mach, storage, step_fields(Lx, Ly, 0, Lx, mach), tau,
+                lattice=lattice)
+    t_per, _ = timed(per)
+    per.close()
+    table = SIGMA_TABLE[lattice]
+    configs = [(bc, 0, 0.0) for bc in bcs] + [(bc, W, table[(bc, W)]) for bc in bcs for W in widths]
+    rows = []
+    for bc, W, sg in configs:
+        r = _make(lbm, Lx, Ly, bc, W, sg, mach, storage, step_fields(Lx, Ly, W, Lx + 2 * W, mach), tau,
+                  lattice=lattice)
+        t, k = timed(r)
+        r.close()
+        rows.append(dict(bc=bc, W=W, sigma_max=sg, lattice=lattice, Ly=Ly, t_step_us=t,
+                         t_bc_us=t - t_per, bulk_kernel_us=k[0], frame_kernel_us=k[1],
+                         phase_a_kernel_us=k[2]))
+    base = next(d for d in rows if d["bc"] == "zg" and d["W"] == 0)
+    for d in rows:
+        d["C_t"] = d["t_bc_us"] / base["t_bc_us"] if base["t_bc_us"] > 0 else None
+    return rows, t_per
+
+
 def sigma_scan(steps=600, sigmas=None, widths=(10, 20, 40), bcs=("zg", "nrbc"), storage="f64",
                lattice=37):
     """The paper tunes sigma_max per boundary and width by a parameter scan; the same scan for
@@ -249,8 +304,17 @@ def main():
                     help="also run the vortex outflow through ZG and LODI (B) boundaries")
     ap.add_argument("--appendix", action="store_true",
                     help="also run the appendix's PML-moment terms on the characteristic boundary")
+    ap.add_argument("--cost", action="store_true",
+                    help="only the C_t study on a tall (Lx x 2048) density-step geometry")
+    ap.add_argument("--cost-ly", type=int, default=2048)
     args = ap.parse_args()
     t0 = time.perf_counter()
+    if args.cost:
+        rows, t_per = cost_study(Ly=args.cost_ly, storage=args.storage, lattice=args.lattice)
+        for d in rows:
+            print(json.dumps(dict(cost=True, **d)))
+        print(json.dumps(dict(periodic_step_us=t_per, seconds=time.perf_counter() - t0)))
+        return
     rows, nref = density_step_study(args.steps, args.sample, storage=args.storage,
                                     lattice=args.lattice)
     for d in rows:

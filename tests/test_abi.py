@@ -111,20 +111,20 @@ def test_cbc_a_kind_and_footprint(q):
 
 def test_launch_configuration_validated_on_host():
     r = lbm.Run(20, 10, 0.8)
-    assert r.get_launch() == dict(bulk_tx=64, bulk_ty=4, graph_steps=32, overlap=2)
+    assert r.get_launch() == dict(bulk_tx=64, bulk_ty=4, graph_steps=32, overlap=2, split=-1)
     for kw in (dict(bulk_tx=32), dict(graph_steps=3), dict(graph_steps=-2), dict(overlap=3),
-               dict(overlap=-1)):
+               dict(overlap=-1), dict(split=-2), dict(split=9)):
         with pytest.raises(lbm.LbmError) as ei:
             r.set_launch(**kw)
         assert ei.value.status == lbm.LBM_ERR_ARG, kw
-    r.set_launch(bulk_tx=128, graph_steps=8, overlap=2)
-    assert r.get_launch() == dict(bulk_tx=128, bulk_ty=2, graph_steps=8, overlap=2)
+    r.set_launch(bulk_tx=128, graph_steps=8, overlap=2, split=3)
+    assert r.get_launch() == dict(bulk_tx=128, bulk_ty=2, graph_steps=8, overlap=2, split=3)
     r.set_launch(bulk_tx=256, graph_steps=0, overlap=1)
     with pytest.raises(lbm.LbmError) as ei:
         r.set_nrbc_pml_terms(8)
     assert ei.value.status == lbm.LBM_ERR_ARG
     r.set_nrbc_pml_terms(5)
-    assert r.get_launch() == dict(bulk_tx=256, bulk_ty=1, graph_steps=0, overlap=1)
+    assert r.get_launch() == dict(bulk_tx=256, bulk_ty=1, graph_steps=0, overlap=1, split=-1)
     with pytest.raises(lbm.LbmError):
         r.profile(4)
     r.profile(3)

@@ -135,7 +135,9 @@ def test_group_graphs_and_autotune_keep_bits(storage):
     with pytest.raises(lbm.LbmError):
         g.set_launch(bulk_tx=64, graph_steps=4, overlap=1)   # one stream: no side stream
     g.set_launch(bulk_tx=128, graph_steps=4)
-    assert g.get_launch() == dict(bulk_tx=128, bulk_ty=2, graph_steps=4, overlap=2)
+    assert g.get_launch() == dict(bulk_tx=128, bulk_ty=2, graph_steps=4, overlap=2, split=-1)
+    with pytest.raises(lbm.LbmError):
+        g.set_launch(bulk_tx=128, graph_steps=4, split=9)
     before = [r.populations() for r in runs]
     c = g.autotune(steps=3)
     assert c["bulk_tx"] in (64, 128, 256) and c["graph_steps"] == 4

@@ -115,16 +115,17 @@ def test_sigma_zero_pml_bitwise_equals_plain(bc, storage):
 
 
 def test_tile_shapes_graphs_and_overlap_bitwise_identical():
-    """Tile shape, graph replay and the overlapped schedules (side stream; phase A fused with the
-    bulk tiles) change launches, never bits."""
+    """Tile shape, graph replay, the overlapped schedules (side stream; phase A fused with the
+    bulk tiles) and the phase-A placement in the fused grid change launches, never bits."""
     F = wl.noisy_state(150, 140, 3, 1.0, 0.05, 0.0, 1.0)
     outs = []
-    for tx, gs, ov in ((64, 0, 0), (128, 8, 0), (256, 32, 0), (64, 32, 0), (64, 0, 1), (256, 8, 1),
-                       (64, 0, 2), (128, 8, 2), (256, 32, 2)):
+    for tx, gs, ov, sp in ((64, 0, 0, -1), (128, 8, 0, -1), (256, 32, 0, -1), (64, 32, 0, -1),
+                           (64, 0, 1, -1), (256, 8, 1, -1), (64, 0, 2, -1), (128, 8, 2, -1),
+                           (256, 32, 2, -1), (64, 8, 2, 0), (64, 0, 2, 3), (128, 32, 2, 8)):
         r = lbm.Run(134, 124, 0.8, 1.0, 0.05, 0.0, 1.0)
         r.set_bc(15, "nrbc")
         r.set_pml(15, 8, 0.05)
-        r.set_launch(bulk_tx=tx, graph_steps=gs, overlap=ov)
+        r.set_launch(bulk_tx=tx, graph_steps=gs, overlap=ov, split=sp)
         r.init(*F.as_tuple())
         r.step(41)
         outs.append(r.populations())
@@ -175,7 +176,9 @@ def test_autotune_choice_is_valid_cached_and_keeps_bits(tmp_path):
     c = a.autotune(steps=4, cache_path=cache)
     assert c["bulk_tx"] in (64, 128, 256) and c["overlap"] in (0, 1, 2)
     lines = open(cache).read().split("\n")
-    assert lines[0].split() == ["106", "96", "0", "37", str(c["bulk_tx"]), str(c["overlap"])]
+    assert lines[0].split() == ["106", "96", "0", "37", str(c["bulk_tx"]), str(c["overlap"]),
+                                str(c["split"])]
+    assert (c["split"] in (0, 2, 4, 6, 8)) == (c["overlap"] == 2)
     a.step(19)
     assert np.array_equal(a.populations(), ref.populations())
     b = make()
