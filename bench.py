@@ -148,6 +148,12 @@ def measure(torch, lbm, r, spec, storage, steps, warmup, prof_steps, fused=True)
     return res
 
 
+def _leg_prof(args, steps):
+    """Steps of a leg's in-order pass with per-class events: half its timed steps, none when
+    --prof-steps is 0 (profiled runs then hold the timed schedule only)."""
+    return 0 if args.prof_steps == 0 else steps // 2
+
+
 def large_leg(torch, lbm, wl, args):
     """4096^2 bulk + 64-cell PML (4224^2 nodes), Mach 0.05, 8 seeded pulses, ZG and NRBC, every
     storage: the largest configuration, where the grid is far larger than the caches."""
@@ -159,7 +165,7 @@ def large_leg(torch, lbm, wl, args):
             r = run_from_spec(lbm, spec, storage, layout=args.layout, bulk_tx=args.bulk_tx,
                               overlap=args.overlap)
             out["%s_%s" % (bc, storage)] = measure(torch, lbm, r, spec, storage, args.large_steps,
-                                                  20, args.large_steps // 2, args.overlap == 2)
+                                                  20, _leg_prof(args, args.large_steps), args.overlap == 2)
             r.close()
             del r
     return out
@@ -176,7 +182,7 @@ def d2q9_leg(torch, lbm, wl, args):
         r = run_from_spec(lbm, spec, storage, layout=args.layout, bulk_tx=args.bulk_tx,
                           overlap=args.overlap)
         out["%dsq_%s_%s" % (spec.Nx, args.bc, storage)] = measure(
-            torch, lbm, r, spec, storage, args.d2q9_steps, args.warmup, args.d2q9_steps // 2,
+            torch, lbm, r, spec, storage, args.d2q9_steps, args.warmup, _leg_prof(args, args.d2q9_steps),
             args.overlap == 2)
         r.close()
         del r
@@ -195,7 +201,7 @@ def d2q17_leg(torch, lbm, wl, args):
         r = run_from_spec(lbm, spec, storage, layout=args.layout, bulk_tx=args.bulk_tx,
                           overlap=args.overlap)
         out["%dsq_%s_%s" % (spec.Nx, args.bc, storage)] = measure(
-            torch, lbm, r, spec, storage, args.d2q17_steps, args.warmup, args.d2q17_steps // 2,
+            torch, lbm, r, spec, storage, args.d2q17_steps, args.warmup, _leg_prof(args, args.d2q17_steps),
             args.overlap == 2)
         r.close()
         del r
@@ -207,7 +213,7 @@ def d2q17_leg(torch, lbm, wl, args):
             r = run_from_spec(lbm, big, storage, layout=args.layout, bulk_tx=args.bulk_tx,
                               overlap=args.overlap)
             out["4224sq_zg_%s" % storage] = measure(torch, lbm, r, big, storage, args.large_steps,
-                                                   20, args.large_steps // 2, args.overlap == 2)
+                                                   20, _leg_prof(args, args.large_steps), args.overlap == 2)
             r.close()
             del r
     return out
@@ -330,18 +336,34 @@ def pmc_summary(fetch_csv, write_csv, out_path, command):
 
 
 def stats_summary(stats_csv, out_path, command, note):
-    """Text summary of a rocprofv3 --kernel-trace --stats run (its kernel_stats CSV): calls and
-    average / min / max dispatch duration per kernel."""
+    """Text summary of a rocprofv3 --kernel-trace --stats run: calls and average / min / max
+    dispatch duration per kernel, from its kernel_stats CSV, or from its kernel_trace CSV per
+    kernel and grid size (so the workloads of one run that share a kernel stay apart)."""
     import csv
     with open(stats_csv) as f:
         rows = list(csv.DictReader(f))
     lines = ["# rocprofv3 --kernel-trace --stats: per-kernel dispatch durations",
-             "command: " + command, note, "",
-             "%-72s %7s %12s %12s %12s %8s" % ("kernel", "calls", "avg_us", "min_us", "max_us", "pct")]
-    for r in rows:
-        lines.append("%-72s %7s %12.2f %12.2f %12.2f %8.2f" % (
-            r["Name"][:72], r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
-            float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+             "command: " + command, note, ""]
+    if rows and "Start_Timestamp" in rows[0]:
+        acc = {}
+        for r in rows:
+            if r.get("Kind", "KERNEL_DISPATCH") != "KERNEL_DISPATCH":
+                continue
+            d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            acc.setdefault((r["Kernel_Name"], int(r["Grid_Size_X"])), []).append(d)
+        total = sum(sum(v) for v in acc.values())
+        lines.append("%-64s %10s %7s %12s %12s %12s %8s" % ("kernel", "grid", "calls", "avg_us",
+                                                          "min_us", "max_us", "pct"))
+        for (name, grid), v in sorted(acc.items(), key=lambda kv: -sum(kv[1])):
+            lines.append("%-64s %10d %7d %12.2f %12.2f %12.2f %8.2f" % (
+                name[:64], grid, len(v), sum(v) / len(v), min(v), max(v), 100.0 * sum(v) / total))
+    else:
+        lines.append("%-72s %7s %12s %12s %12s %8s" % ("kernel", "calls", "avg_us", "min_us",
+                                                     "max_us", "pct"))
+        for r in rows:
+            lines.append("%-72s %7s %12.2f %12.2f %12.2f %8.2f" % (
+                r["Name"][:72], r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+                float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
     with open(out_path, "w") as fo:
         fo.write("\n".join(lines) + "\n")
     print("\n".join(lines))

@@ -132,10 +132,10 @@ def density_step_study(steps=600, sample=10, Lx=200, Ly=20, mach=0.05, tau=0.8,
     return out, Nref
 
 
-def cost_study(Lx=200, Ly=2048, steps=200, repeats=5, mach=0.05, tau=0.8, widths=(10, 20, 40),
+def cost_study(Lx=200, Ly=16384, steps=200, repeats=5, mach=0.05, tau=0.8, widths=(10, 20, 40),
                bcs=("zg", "nrbc"), storage="f64", lattice=37):
     """C_t of Sec. 5 ("Computational Cost") on the density step's geometry made tall enough that
-    no launch is latency-bound: Lx x Ly bulk (Ly = 2048 by default; the density step's physics is
+    no launch is latency-bound: Lx x Ly bulk (Ly = 16384 by default; the density step's physics is
     uniform along y, so only the height changes), periodic along y, the boundary on both x sides,
     a PML of width W on them with the paper's sigma_max for the stencil.
 
@@ -145,8 +145,12 @@ def cost_study(Lx=200, Ly=2048, steps=200, repeats=5, mach=0.05, tau=0.8, widths
     auxiliary update, and the boundary treatment.  C_t = t_BC / t_BC(ZG without PML).  Step times
     are the median over `repeats` passes of `steps` steps (host clock around synchronised
     lbm_step calls, each configuration alone on the device); the per-class kernel times of one
-    in-order pass are reported beside them.  Returns rows (bc, W, sigma_max, t_step_us, t_bc_us,
-    C_t, bulk/frame/phase_a kernel us) and the periodic bulk's step time."""
+    in-order pass are reported beside them.  ZG costs no measurable time over a periodic edge
+    here (its copy is the clamped source index of the boundary nodes' pull), so C_t relative to
+    it is reported only when ZG's t_BC rises above 5% of the bulk step (else None); beside it
+    t_BC over the bulk step, and C_t_classes = (frame kernel + phase A) over ZG's frame kernel.
+    Returns rows (bc, W, sigma_max, t_step_us, t_bc_us, C_t, t_bc_over_bulk, C_t_classes,
+    bulk/frame/phase_a kernel us) and the periodic bulk's step time."""
     from paper_2504_20169_amd import lbm
 
     def timed(r):
@@ -182,8 +186,12 @@ def cost_study(Lx=200, Ly=2048, steps=200, repeats=5, mach=0.05, tau=0.8, widths
                          t_bc_us=t - t_per, bulk_kernel_us=k[0], frame_kernel_us=k[1],
                          phase_a_kernel_us=k[2]))
     base = next(d for d in rows if d["bc"] == "zg" and d["W"] == 0)
+    zg_cls = base["frame_kernel_us"] + base["phase_a_kernel_us"]
     for d in rows:
-        d["C_t"] = d["t_bc_us"] / base["t_bc_us"] if base["t_bc_us"] > 0 else None
+        # the paper's ratio needs a ZG cost above the noise; ZG here is the pull's clamped index
+        d["C_t"] = d["t_bc_us"] / base["t_bc_us"] if base["t_bc_us"] > 0.05 * t_per else None
+        d["t_bc_over_bulk"] = d["t_bc_us"] / t_per
+        d["C_t_classes"] = (d["frame_kernel_us"] + d["phase_a_kernel_us"]) / zg_cls
     return rows, t_per
 
 
@@ -305,8 +313,8 @@ def main():
     ap.add_argument("--appendix", action="store_true",
                     help="also run the appendix's PML-moment terms on the characteristic boundary")
     ap.add_argument("--cost", action="store_true",
-                    help="only the C_t study on a tall (Lx x 2048) density-step geometry")
-    ap.add_argument("--cost-ly", type=int, default=2048)
+                    help="only the C_t study on a tall (Lx x --cost-ly) density-step geometry")
+    ap.add_argument("--cost-ly", type=int, default=16384)
     args = ap.parse_args()
     t0 = time.perf_counter()
     if args.cost:
