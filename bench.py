@@ -148,6 +148,17 @@ def measure(torch, lbm, r, spec, storage, steps, warmup, prof_steps, fused=True)
     return res
 
 
+def moment_errors(m, ref):
+    """Largest relative differences of the moments (rho, ux, uy, T) from a reference: rho and T
+    relative to their largest value, u to the largest velocity component of the reference."""
+    rho, ux, uy, T = m
+    rho_ref, ux_ref, uy_ref, T_ref = ref
+    us = max(np.abs(ux_ref).max(), np.abs(uy_ref).max())
+    return dict(rho=float(np.abs(rho - rho_ref).max() / np.abs(rho_ref).max()),
+                u=float(max(np.abs(ux - ux_ref).max(), np.abs(uy - uy_ref).max()) / us),
+                T=float(np.abs(T - T_ref).max() / np.abs(T_ref).max()))
+
+
 def _leg_prof(args, steps):
     """Steps of a leg's in-order pass with per-class events: half its timed steps, none when
     --prof-steps is 0 (profiled runs then hold the timed schedule only)."""
@@ -160,14 +171,30 @@ def large_leg(torch, lbm, wl, args):
     out = {}
     for bc in args.large_bcs.split(","):
         spec = wl.multi_pulse(L=4096, W=64, sigma_max=0.01, mach=0.05, bc=bc)
+        ref = None
         for storage in args.storages.split(","):
             _log("bench: 4224^2", bc, storage)
             r = run_from_spec(lbm, spec, storage, layout=args.layout, bulk_tx=args.bulk_tx,
                               overlap=args.overlap)
-            out["%s_%s" % (bc, storage)] = measure(torch, lbm, r, spec, storage, args.large_steps,
-                                                  20, _leg_prof(args, args.large_steps), args.overlap == 2)
+            res = measure(torch, lbm, r, spec, storage, args.large_steps, 20,
+                          _leg_prof(args, args.large_steps), args.overlap == 2)
+            if args.large_error_steps > 0:
+                # every storage continues to the same step count; FP32 and FP16 are compared with
+                # FP64 there (the FP64 path itself is held to the oracle by the parity tests)
+                left = args.large_error_steps - r.step_count
+                if left > 0:
+                    r.step(left)
+                m = r.moments()
+                res["error_steps"] = r.step_count
+                if storage == "f64":
+                    ref = m
+                elif ref is not None:
+                    res["err_vs_f64"] = moment_errors(m, ref)
+                del m
+            out["%s_%s" % (bc, storage)] = res
             r.close()
             del r
+        del ref
     return out
 
 
@@ -416,6 +443,54 @@ def gaps_summary(trace_csv, out_path, command, note, kernel="k_frame", steps=200
     print("\n".join(lines))
 
 
+def counters_summary(csvs, out_path, command, note):
+    """Text summary of rocprofv3 --pmc passes (one CSV each) for the tracked FP64 D2Q37 kernels:
+    the mean of every counter per dispatch, and the pipeline ratios the counters give.
+    GRBM_GUI_ACTIVE reads the sum of the 8 XCDs' busy cycles, and the TA, TD and TCP counters
+    the sum of their 256 per-CU instances, so a unit's busy fraction is its _sum over
+    32 x GRBM_GUI_ACTIVE; the SQ wave-cycle counters give fractions of the waves' lifetime."""
+    import csv
+    acc = {}
+    for path in csvs:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                acc.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(
+                    float(r["Counter_Value"]))
+    lines = ["# rocprofv3 --pmc: pipeline counters per dispatch", "command: " + command, note, ""]
+    for short, name in TRACKED.items():
+        if name not in acc:
+            continue
+        m = {k: sum(v) / len(v) for k, v in acc[name].items()}
+        n = min(len(v) for v in acc[name].values())
+        lines.append("%s (%s), %d dispatches per pass" % (short, name, n))
+        for k in sorted(m):
+            lines.append("  %-36s %14.1f" % (k, m[k]))
+        g = m.get("GRBM_GUI_ACTIVE")
+        if g:
+            for k, label in (("TA_TA_BUSY_sum", "TA busy"), ("TD_TD_BUSY_sum", "TD busy"),
+                             ("TCP_PENDING_STALL_CYCLES_sum", "TCP stalled on pending misses"),
+                             ("TD_TC_STALL_sum", "TD stalled on the cache")):
+                if k in m:
+                    lines.append("  ratio %-38s %.3f" % (label, m[k] / (32.0 * g)))
+        wc = m.get("SQ_WAVE_CYCLES")
+        if wc:
+            for k, label in (("SQ_WAIT_INST_ANY", "waves waiting on a dependency"),
+                             ("SQ_ACTIVE_INST_VALU", "waves issuing VALU")):
+                if k in m:
+                    lines.append("  ratio %-38s %.3f" % (label, m[k] / wc))
+        if m.get("SQ_WAVES"):
+            for k in ("SQ_INSTS_VMEM_RD", "SQ_INSTS_VALU"):
+                if k in m:
+                    lines.append("  per wave %-35s %.1f" % (k, m[k] / m["SQ_WAVES"]))
+        if "TCC_HIT_sum" in m and "TCC_MISS_sum" in m:
+            lines.append("  ratio %-38s %.3f" % ("L2 hit rate", m["TCC_HIT_sum"] /
+                                                  max(m["TCC_HIT_sum"] + m["TCC_MISS_sum"], 1.0)))
+        lines.append("")
+    with open(out_path, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def recorded_traffic(short):
     """HBM bytes per launch of a tracked kernel ("grid", "frame" or "bulk") from the committed
     counter summary, or None when it is missing or was taken from another version of the
@@ -537,6 +612,9 @@ def main():
     ap.add_argument("--large-steps", type=int, default=200,
                     help="timed steps per run of the 4224^2 leg (0 skips it)")
     ap.add_argument("--large-bcs", default="zg,nrbc")
+    ap.add_argument("--large-error-steps", type=int, default=2000,
+                    help="4224^2 runs continue to this step count; FP32 and FP16 moments are then "
+                         "compared with FP64 (0 skips)")
     ap.add_argument("--d2q9-steps", type=int, default=1000,
                     help="timed steps of the D2Q9 leg at the main size (0 skips it)")
     ap.add_argument("--d2q17-steps", type=int, default=1000,
@@ -562,6 +640,9 @@ def main():
                     help="summarise a rocprofv3 --kernel-trace --stats CSV into OUT and exit (no GPU)")
     ap.add_argument("--stats-command", default="", help="command line recorded in the summary")
     ap.add_argument("--stats-note", default="", help="workload note recorded in the summary")
+    ap.add_argument("--counters-summary", nargs="+", metavar="CSV",
+                    help="pipeline-counter summary of --pmc CSVs (the last argument is the output "
+                         "file) and exit")
     ap.add_argument("--gaps-summary", nargs=2, metavar=("TRACE_CSV", "OUT"),
                     help="write the idle time between dispatches of a rocprofv3 kernel trace and exit")
     ap.add_argument("--gaps-steps", type=int, default=200, help="timed steps in the trace")
@@ -571,6 +652,10 @@ def main():
         return
     if args.stats_summary:
         stats_summary(*args.stats_summary, command=args.stats_command, note=args.stats_note)
+        return
+    if args.counters_summary:
+        counters_summary(args.counters_summary[:-1], args.counters_summary[-1],
+                         command=args.stats_command, note=args.stats_note)
         return
     if args.gaps_summary:
         gaps_summary(*args.gaps_summary, command=args.stats_command, note=args.stats_note,
@@ -628,13 +713,7 @@ def main():
         results[storage] = measure(torch, lbm, r, spec, storage, args.steps, args.warmup,
                                    args.prof_steps, args.overlap == 2)
         if storage != "f64" and "f64" in results:
-            rho_ref, ux_ref, uy_ref, T_ref = results["f64"]["_moments"]
-            rho, ux, uy, T = r.moments()
-            us = max(np.abs(ux_ref).max(), np.abs(uy_ref).max())
-            results[storage]["err_vs_f64"] = dict(
-                rho=float(np.abs(rho - rho_ref).max() / np.abs(rho_ref).max()),
-                u=float(max(np.abs(ux - ux_ref).max(), np.abs(uy - uy_ref).max()) / us),
-                T=float(np.abs(T - T_ref).max() / np.abs(T_ref).max()))
+            results[storage]["err_vs_f64"] = moment_errors(r.moments(), results["f64"]["_moments"])
         if storage == "f64":
             results["f64"]["_moments"] = r.moments()
         r.close()
@@ -666,9 +745,10 @@ def main():
         "variants": {},
     }
     def rnd(v):
+        # six significant digits: errors of 1e-9 must survive
         if isinstance(v, dict):
             return {k: rnd(x) for k, x in v.items() if not k.startswith("_")}
-        return round(v, 6) if isinstance(v, float) else v
+        return float("%.6g" % v) if isinstance(v, float) else v
     for s, v in results.items():
         line["variants"][s] = rnd(v)
     if args.large_steps > 0:
