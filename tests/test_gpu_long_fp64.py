@@ -1,4 +1,4 @@
-"""Full-length runs of the benchmark workload against stored oracle values (GPU).
+"""Full-length runs of the benchmark workloads against stored oracle values (GPU).
 
 The 1024^2 + 32-cell PML vortex + pulse workload with the characteristic boundary (the bench's
 headline configuration) runs its full 10^4 steps through the C ABI in the launch configuration
@@ -53,20 +53,47 @@ def test_vortex_1088_full_length_matches_the_oracle():
     spec = wl.vortex_pulse(L=1024, W=32, sigma_max=0.0015, mach=0.1, bc="nrbc", seed=2)
     floor = _floor(fix, read_fixture("vortex_1088", "extended"))
     say("double oracle vs extended at the fixture nodes", {k: "%.2e" % v for k, v in floor.items()})
-    errs = {}
-    for storage in ("f64", "f32", "f16"):
-        say("case vortex_1088 10^4 steps", storage)
-        r = lbm.Run(1024, 1024, 0.8, 1.0, 0.1, 0.0, 1.0, storage=storage)
-        r.set_launch(bulk_tx=64, graph_steps=32, overlap=2)
-        r.set_bc(lbm.LBM_ALL, "nrbc")
-        r.set_pml(lbm.LBM_ALL, 32, 0.0015)
-        r.init(*spec.fields.as_tuple())
-        r.step(10000)
-        assert r.check() == lbm.LBM_OK
-        errs[storage] = _errors(r.moments(), fix)
-        r.close()
-        say(storage, "vs oracle", {k: "%.2e" % v for k, v in errs[storage].items()})
+    errs = _run_all(spec, "nrbc", 32, 0.0015, 10000, fix, "vortex_1088")
     for k, v in errs["f64"].items():
         bar = max(TOL, 4.0 * floor[k])
         assert v <= bar, (k, v, bar, errs["f64"], floor)
     assert all(v < 1e-6 for v in errs["f32"].values()), errs["f32"]
+
+
+@pytest.mark.skipif(not os.path.exists(fixture_path("pulses_4224_zg")),
+                    reason="oracle fixture not written")
+def test_pulses_4224_zg_full_length_matches_the_oracle():
+    """The 4096^2 + 64-cell PML multi-pulse workload with ZG edges, its full 2000 steps.  The bar
+    is 1e-12, or 4x the double oracle's own rounding where an extended-precision fixture of the
+    same run exists and shows it higher."""
+    fix = read_fixture("pulses_4224_zg")
+    hdr = fix[0]
+    assert int(hdr["steps"]) == 2000 and hdr["grid"].split() == ["4224", "4224"]
+    spec = wl.multi_pulse(L=4096, W=64, sigma_max=0.01, mach=0.05, bc="zg")
+    floor = dict(rho=0.0, ux=0.0, uy=0.0, T=0.0)
+    if os.path.exists(fixture_path("pulses_4224_zg", "extended")):
+        floor = _floor(fix, read_fixture("pulses_4224_zg", "extended"))
+    errs = _run_all(spec, "zg", 64, 0.01, 2000, fix, "pulses_4224_zg")
+    for k, v in errs["f64"].items():
+        bar = max(TOL, 4.0 * floor[k])
+        assert v <= bar, (k, v, bar, errs["f64"], floor)
+    assert all(v < 1e-6 for v in errs["f32"].values()), errs["f32"]
+
+
+def _run_all(spec, bc, W, sigma, steps, fix, name):
+    """Run the workload in every storage through the C ABI in the bench's launch configuration;
+    errors against the fixture per storage."""
+    errs = {}
+    for storage in ("f64", "f32", "f16"):
+        say("case %s %d steps" % (name, steps), storage)
+        r = lbm.Run(spec.Lx, spec.Ly, 0.8, 1.0, spec.ux0, 0.0, 1.0, storage=storage)
+        r.set_launch(bulk_tx=64, graph_steps=32, overlap=2)
+        r.set_bc(lbm.LBM_ALL, bc)
+        r.set_pml(lbm.LBM_ALL, W, sigma)
+        r.init(*spec.fields.as_tuple())
+        r.step(steps)
+        assert r.check() == lbm.LBM_OK
+        errs[storage] = _errors(r.moments(), fix)
+        r.close()
+        say(storage, "vs oracle", {k: "%.2e" % v for k, v in errs[storage].items()})
+    return errs
