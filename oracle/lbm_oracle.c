@@ -22,9 +22,12 @@
  * periodic box; rest and uniform states stationary under every boundary and PML; sigma_max = 0
  * PML identical to no PML; linear growth of Q under a constant deviation; mirror symmetry;
  * linear acoustics vs the linearised Navier-Stokes-Fourier solution; ZG+PML reflecting less
- * than ZG.  PARITY UNPINNED beyond invariants: the characteristic boundary's corner rule, time
- * level and frame (the paper defers its details to a companion paper); it is pinned only by
- * uniform-flow invariance, symmetry and the trend that it reflects less than ZG.  Likewise the
+ * than ZG.  The characteristic boundary's normal update is pinned in closed form by plane simple
+ * waves (tests/test_oracle_lodi_pins.py): an outgoing acoustic wave, an entropy and a shear wave
+ * translated by their characteristic speeds over one step and an incoming acoustic wave frozen,
+ * on every stencil and on x and y sides.  PARITY UNPINNED beyond invariants: its corner rule (the
+ * paper defers its details to a companion paper), pinned only by uniform-flow invariance,
+ * symmetry and the trend that it reflects less than ZG.  Likewise the
  * readings of CBC (A) (transverse and viscous parts, the sign of eq. CBC-Relax) are pinned only
  * by uniform-flow invariance, symmetry, its exact reduction to the LODI boundary for plane waves
  * and the trend that it beats the LODI boundary on a vortex outflow.

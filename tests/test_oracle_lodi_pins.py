@@ -1,0 +1,126 @@
+"""Closed-form pin for the oracle's characteristic (LODI, perfectly non-reflecting) boundary
+(CPU only).
+
+A plane acoustic simple wave that runs out through an open side is the case the characteristic
+boundary exists for (Sec. 4, eqs. NSF-CHAR, PNR and thermal_LODI_macro_evo): the perturbation is
+carried by the one outgoing acoustic characteristic, lambda = u_n + c, and nothing else.  For a
+gas with e = (d/2) T in d = 2 (gamma = 2, c^2 = 2T) the wave is isentropic, and its state
+perturbation is proportional to
+
+    r = (d rho, d u_n, d u_t, d T) = (1, c / rho, 0, T / rho)
+
+(d p = c^2 d rho, d u_n = c d rho / rho, d T / T = d rho / rho), which follows from the gas
+dynamics, not from the oracle's characteristic matrices.  With a profile linear along the
+outward normal, one boundary step moves the wave by lambda / r cells (lattice time step, xi = r e)
+and leaves every other characteristic alone: the incoming amplitude is zeroed and the others carry
+no perturbation.  So after the first step each of the 3 boundary layers holds, to first order in
+the amplitude eps,
+
+    U(x) = U0 + eps f(x - nu) r,   nu = (u_0n + c) / r,
+
+with f linear: the upwind difference over the interval the characteristic crosses (reading 10)
+is exact on a linear profile for either branch (nu < 1 on D2Q17 and D2Q9, 1 < nu < 2 on D2Q37).
+The boundary node's moments are exactly its target state, because the non-equilibrium part
+copied from x_f carries no conserved moments.  A wrong eigenvector, sign, wave speed, time-step
+scale or an incoming wave that is not zeroed fails here.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2504_20169_amd import workloads as wl
+
+
+@pytest.mark.parametrize("q", [37, 17, 9])
+@pytest.mark.parametrize("u0", [0.0, 0.08])
+@pytest.mark.parametrize("side", ["xmax", "ymax", "xmin"])
+def test_outgoing_acoustic_wave_is_translated_by_the_boundary(oracle_mod, q, u0, side):
+    """The wave leaves through `side` (the flow u0 points out through it too); the other axis is
+    periodic."""
+    _, _, r = oracle_mod.lattice(q)
+    rho0, T0, eps = 1.0, 1.0, 1e-7
+    c = math.sqrt(2.0 * T0)
+    axis = 0 if side in ("xmax", "xmin") else 1
+    sgn = -1.0 if side == "xmin" else 1.0          # outward normal along the axis
+    L, Lt = 24, 6
+    mean = (rho0, sgn * u0 if axis == 0 else 0.0, sgn * u0 if axis == 1 else 0.0, T0)
+    o = oracle_mod.OracleRun(L if axis == 0 else Lt, Lt if axis == 0 else L, 0.8, *mean, lattice=q)
+    o.set_bc(1 | 2 if axis == 0 else 4 | 8, oracle_mod.BC_NRBC)
+    o.set_bc(4 | 8 if axis == 0 else 1 | 2, oracle_mod.BC_PERIODIC)
+    Nx, Ny = o.grid()
+    N = Nx if axis == 0 else Ny
+    X, Y = np.meshgrid(np.arange(Nx, dtype=float), np.arange(Ny, dtype=float))
+    # distance along the outward normal, measured from a point 8 cells inside the side
+    s_of = (lambda p: sgn * (p - (N - 8.0))) if sgn > 0 else (lambda p: sgn * (p - 7.0))
+    f = s_of(X if axis == 0 else Y)
+    F = wl.uniform_state(Nx, Ny, *mean)
+    F.rho = rho0 + eps * f
+    un = (c / rho0) * eps * f
+    if axis == 0:
+        F.ux = mean[1] + sgn * un
+    else:
+        F.uy = mean[2] + sgn * un
+    F.T = T0 + eps * (T0 / rho0) * f
+    o.init(*F.as_tuple())
+    o.step(1)
+    rho, ux, uy, T = o.moments()
+    nu = (u0 + c) / r
+    assert 0.0 < nu < 2.0
+    layers = (N - 1, N - 2, N - 3) if sgn > 0 else (0, 1, 2)
+    for pb in layers:
+        s = eps * (s_of(float(pb)) - nu)
+        want_un = u0 + (c / rho0) * s
+        sl = (slice(None), pb) if axis == 0 else (pb, slice(None))
+        got_un = sgn * (ux if axis == 0 else uy)[sl]
+        got_ut = (uy if axis == 0 else ux)[sl]
+        for name, g, w0 in (("rho", rho[sl], rho0 + s), ("u_n", got_un, want_un), ("u_t", got_ut, 0.0),
+                            ("T", T[sl], T0 + (T0 / rho0) * s)):
+            # first order in eps: the remainder is O(eps^2) = 1e-14, 1e-7 of the perturbation
+            err = np.abs(g - w0).max()
+            assert err <= 1e-6 * eps * max(abs(s / eps), 1.0) + 1e-15, (q, u0, side, pb, name, err)
+
+
+@pytest.mark.parametrize("q", [37, 17, 9])
+def test_each_characteristic_wave_moves_at_its_speed_and_the_incoming_one_is_frozen(oracle_mod, q):
+    """The same step with all four waves at once, each with its own linear profile: the incoming
+    acoustic wave r1 = (1, -c/rho, 0, T/rho) (lambda = u_n - c < 0) keeps its value at the node
+    (eq. PNR sets its amplitude's change to zero), the outgoing acoustic wave r4 moves by
+    (u_n + c)/r cells, and the entropy wave r2 = (1, 0, 0, -T/rho) (d p = 0) and the shear wave
+    r3 = (0, 0, 1, 0) move by u_n / r cells.  Mean flow Mach 0.08 out through the side."""
+    _, _, r = oracle_mod.lattice(q)
+    rho0, u0, T0 = 1.0, 0.08, 1.0
+    c = math.sqrt(2.0 * T0)
+    waves = {  # name: (eigenvector, wave speed in cells per step, amplitude, slope)
+        "r1": ((1.0, -c / rho0, 0.0, T0 / rho0), (u0 - c) / r, 3e-8, 1.0),
+        "r2": ((1.0, 0.0, 0.0, -T0 / rho0), u0 / r, 5e-8, -0.7),
+        "r3": ((0.0, 0.0, 1.0, 0.0), u0 / r, 4e-8, 0.4),
+        "r4": ((1.0, c / rho0, 0.0, T0 / rho0), (u0 + c) / r, 1e-7, 1.3),
+    }
+    Lx, Ly = 24, 6
+    o = oracle_mod.OracleRun(Lx, Ly, 0.8, rho0, u0, 0.0, T0, lattice=q)
+    o.set_bc(1 | 2, oracle_mod.BC_NRBC)
+    o.set_bc(4 | 8, oracle_mod.BC_PERIODIC)
+    Nx, Ny = o.grid()
+    xc = Nx - 8.0
+    x = np.broadcast_to(np.arange(Nx, dtype=float), (Ny, Nx))
+    base = np.array([rho0, u0, 0.0, T0])
+    fields = [np.full((Ny, Nx), b) for b in base]
+    for vec, _, amp, slope in waves.values():
+        for k in range(4):
+            fields[k] = fields[k] + amp * slope * (x - xc) * vec[k]
+    F = wl.Fields(*fields)
+    o.init(*F.as_tuple())
+    o.step(1)
+    got = o.moments()
+    for xb in (Nx - 1, Nx - 2, Nx - 3):
+        want = base.copy()
+        for vec, nu, amp, slope in waves.values():
+            shift = nu if nu > 0 else 0.0       # the incoming wave is frozen at the node
+            want = want + amp * slope * (xb - shift - xc) * np.array(vec)
+        # first order in the perturbation delta (about 1e-6 here): the remainder is O(delta^2);
+        # a wave at a wrong speed or one not frozen would be off by about 1e-8
+        delta = sum(abs(amp * slope * (xb - xc)) for _, _, amp, slope in waves.values())
+        for k, name in enumerate(("rho", "ux", "uy", "T")):
+            err = np.abs(got[k][:, xb] - want[k]).max()
+            assert err <= 1e-5 * delta, (q, xb, name, err, delta)
