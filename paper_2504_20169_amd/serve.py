@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import time
 from collections import deque
-from concurrent.futures import ThreadPoolExecutor
+from concurrent.futures import Future, ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import Any, Optional
 
@@ -94,18 +94,15 @@ class GpuBackend:
         return r
 
     def prepare(self, job: Job):
-        """A future of the job's initialised run, built off the caller's thread."""
+        """A future of the job's initialised run, built off the caller's thread (on the caller's
+        thread when the backend has no workers)."""
         if self.pool is None:
-            class _Done:
-                def __init__(self, v):
-                    self.v = v
-
-                def done(self):
-                    return True
-
-                def result(self):
-                    return self.v
-            return _Done(self._build(job))
+            fut = Future()
+            try:
+                fut.set_result(self._build(job))
+            except Exception as exc:        # reported when the engine joins the job
+                fut.set_exception(exc)
+            return fut
         return self.pool.submit(self._build, job)
 
     def start(self, job: Job, run=None):
