@@ -108,3 +108,73 @@ def test_more_than_one_gpu_is_refused():
                          capture_output=True, text=True, timeout=120)
     assert res.returncode == 2
     assert "one GPU" in res.stderr
+
+
+TRACE_COLS = ["Kind", "Kernel_Name", "Start_Timestamp", "End_Timestamp", "Grid_Size_X"]
+
+
+def _trace_csv(path, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f, quoting=csv.QUOTE_NONNUMERIC)
+        w.writerow(TRACE_COLS)
+        for name, a, e, g in rows:
+            w.writerow(["KERNEL_DISPATCH", name, a, e, g])
+
+
+def test_gaps_summary_counts_idle_time_between_dispatches(tmp_path):
+    """Three steps of [grid, frame] at the group's grid size, preceded by a small run's frame
+    kernel: the window runs from the end of the frame before the last three to the end of the
+    last; overlapping dispatches count once; idle time is the rest."""
+    rows = [("k_frame", 0, 10, 64),                               # another run: smaller grid
+            ("k_phase_a_bulk", 20, 60, 999), ("k_frame", 60, 70, 500),   # step 0 (before the window)
+            ("k_phase_a_bulk", 75, 115, 999), ("k_frame", 115, 125, 500),
+            ("k_advance", 120, 124, 1),                              # inside a busy interval
+            ("k_phase_a_bulk", 127, 167, 999), ("k_frame", 170, 180, 500),
+            ("k_phase_a_bulk", 180, 220, 999), ("k_frame", 221, 231, 500)]
+    rows = [(n, 1000 * a0, 1000 * e0, g) for n, a0, e0, g in rows]   # timestamps in ns, times in us
+    src, out = tmp_path / "t.csv", tmp_path / "g.txt"
+    _trace_csv(src, rows)
+    bench.gaps_summary(str(src), str(out), "cmd", "note", steps=3)
+    kv = dict(l.split(":", 1) for l in open(out) if ":" in l and not l.startswith(("#", "command")))
+    assert float(kv["wall_us"]) == pytest.approx(231 - 70)
+    # idle: 70-75, 125-127, 167-170, 220-221 = 5 + 2 + 3 + 1 = 11 us
+    assert float(kv["idle_us"]) == pytest.approx(11)
+    assert float(kv["idle_us_per_step"]) == pytest.approx(11 / 3, abs=0.01)
+
+
+def test_counters_summary_ratios(tmp_path):
+    """Busy fractions of the per-CU units are their sums over 32 x GRBM_GUI_ACTIVE (the 8 XCDs'
+    sum); wave fractions are over SQ_WAVE_CYCLES; per-wave counts over SQ_WAVES."""
+    G = bench.TRACKED["frame"]
+    a, b = tmp_path / "a.csv", tmp_path / "b.csv"
+    with open(a, "w", newline="") as f:
+        w = csv.writer(f, quoting=csv.QUOTE_NONNUMERIC)
+        w.writerow(COLS)
+        for k, (c, v) in enumerate((("GRBM_GUI_ACTIVE", 1000.0), ("SQ_WAVES", 10.0),
+                                    ("SQ_WAVE_CYCLES", 400.0), ("SQ_WAIT_INST_ANY", 100.0),
+                                    ("SQ_INSTS_VMEM_RD", 150.0))):
+            w.writerow([1, 1, G, c, v])
+    with open(b, "w", newline="") as f:
+        w = csv.writer(f, quoting=csv.QUOTE_NONNUMERIC)
+        w.writerow(COLS)
+        for c, v in (("GRBM_GUI_ACTIVE", 1000.0), ("TA_TA_BUSY_sum", 16000.0),
+                     ("TCC_HIT_sum", 30.0), ("TCC_MISS_sum", 70.0)):
+            w.writerow([1, 1, G, c, v])
+    out = tmp_path / "c.txt"
+    bench.counters_summary([str(a), str(b)], str(out), "cmd", "note")
+    text = open(out).read()
+    assert "ratio TA busy" in text and " 0.500" in text.split("ratio TA busy")[1].splitlines()[0]
+    assert " 0.250" in text.split("waves waiting on a dependency")[1].splitlines()[0]
+    assert " 15.0" in text.split("per wave SQ_INSTS_VMEM_RD")[1].splitlines()[0]
+    assert " 0.300" in text.split("L2 hit rate")[1].splitlines()[0]
+
+
+def test_moment_errors_normalise_by_field_scale():
+    import numpy as np
+    ref = [np.full((2, 2), 1.0), np.array([[0.1, -0.2], [0.0, 0.05]]), np.zeros((2, 2)),
+           np.full((2, 2), 2.0)]
+    m = [ref[0] + 1e-9, ref[1] + 2e-9, ref[2] - 4e-9, ref[3] + 2e-9]
+    e = bench.moment_errors(m, ref)
+    assert e["rho"] == pytest.approx(1e-9)
+    assert e["u"] == pytest.approx(4e-9 / 0.2)
+    assert e["T"] == pytest.approx(1e-9)
