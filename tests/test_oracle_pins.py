@@ -226,10 +226,8 @@ def test_sigma_ramp(oracle_mod):
 def test_mirror_symmetry(oracle_mod, bc, W, q):
     """A centred pulse at rest on a square grid stays symmetric under x and y mirrors and the
     transpose: catches a wrong side, sign or index in the boundary, PML or corner handling
-    (for CBC (A) on every side: a wrong tangent direction or edge stencil)."""
-    if bc == 3 and q == 37:
-        pytest.skip("CBC (A) on D2Q37 is stable on outflow sides only; a symmetric placement "
-                    "needs it on every side")
+    (for CBC (A) on every side: a wrong tangent direction or edge stencil; D2Q37 included, at a
+    round-off bar that its growth on non-outflow sides needs)."""
     L = 20
     o = oracle_mod.OracleRun(L, L, 0.8, lattice=q)
     if W:
@@ -242,7 +240,10 @@ def test_mirror_symmetry(oracle_mod, bc, W, q):
     o.init(*F.as_tuple())
     o.step(45)
     rho, ux, uy, T = o.moments()
-    tol = 1e-14
+    # CBC (A) on D2Q37 amplifies round-off on sides without outflow (its sound speed exceeds a
+    # cell per step; the reading of CBC (A) in the design notes): after 45 steps the mirror images
+    # differ by up to 1e-13, against 1e-5 for a wrong tangent direction or edge stencil
+    tol = 1e-12 if (bc == 3 and q == 37) else 1e-14
     assert np.abs(rho - rho[:, ::-1]).max() < tol
     assert np.abs(rho - rho[::-1, :]).max() < tol
     assert np.abs(rho - rho.T).max() < tol
