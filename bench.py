@@ -491,6 +491,44 @@ def counters_summary(csvs, out_path, command, note):
     print("\n".join(lines))
 
 
+def request_summary(csv_path, out_path, command, note):
+    """HBM read bytes per dispatch from the L2's read requests to memory by size (one --pmc pass
+    of TCC_EA0_RDREQ_{32B,64B,128B}_sum and TCC_EA0_RDREQ_sum): 32 n32 + 64 n64 + 128 n128.  This
+    resolves what FETCH_SIZE, scaled by a copy whose requests are all 128-byte, counts twice for a
+    kernel whose partial-line reads go out as 64- or 32-byte requests."""
+    acc = pmc_means_all(csv_path)
+    lines = ["# rocprofv3 --pmc: HBM read requests by size per dispatch", "command: " + command, note,
+             "", "%-72s %12s %12s %12s %12s %12s" % ("kernel", "n32", "n64", "n128", "n_total",
+                                                      "read MB")]
+    for name, m in sorted(acc.items(), key=lambda kv: -kv[1].get("TCC_EA0_RDREQ_sum", 0.0)):
+        n32 = m.get("TCC_EA0_RDREQ_32B_sum", 0.0)
+        n64 = m.get("TCC_EA0_RDREQ_64B_sum", 0.0)
+        n128 = m.get("TCC_EA0_RDREQ_128B_sum", 0.0)
+        mb = (32 * n32 + 64 * n64 + 128 * n128) / 1e6
+        lines.append("%-72s %12.0f %12.0f %12.0f %12.0f %12.2f" % (
+            name[:72], n32, n64, n128, m.get("TCC_EA0_RDREQ_sum", 0.0), mb))
+    for short, name in TRACKED.items():
+        if name in acc:
+            m = acc[name]
+            rd = 32 * m.get("TCC_EA0_RDREQ_32B_sum", 0.0) + 64 * m.get("TCC_EA0_RDREQ_64B_sum", 0.0) + \
+                128 * m.get("TCC_EA0_RDREQ_128B_sum", 0.0)
+            lines.append("read_bytes_by_request_%s: %d" % (short, round(rd)))
+    with open(out_path, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def pmc_means_all(path):
+    """Mean value per dispatch of every counter, per kernel name, from a rocprofv3 --pmc CSV."""
+    import csv
+    acc = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            acc.setdefault(row["Kernel_Name"], {}).setdefault(row["Counter_Name"], []).append(
+                float(row["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in acc.items()}
+
+
 def recorded_traffic(short):
     """HBM bytes per launch of a tracked kernel ("grid", "frame" or "bulk") from the committed
     counter summary, or None when it is missing or was taken from another version of the
@@ -643,6 +681,8 @@ def main():
     ap.add_argument("--counters-summary", nargs="+", metavar="CSV",
                     help="pipeline-counter summary of --pmc CSVs (the last argument is the output "
                          "file) and exit")
+    ap.add_argument("--request-summary", nargs=2, metavar=("PMC_CSV", "OUT"),
+                    help="write HBM read bytes by request size from a --pmc pass and exit")
     ap.add_argument("--gaps-summary", nargs=2, metavar=("TRACE_CSV", "OUT"),
                     help="write the idle time between dispatches of a rocprofv3 kernel trace and exit")
     ap.add_argument("--gaps-steps", type=int, default=200, help="timed steps in the trace")
@@ -652,6 +692,9 @@ def main():
         return
     if args.stats_summary:
         stats_summary(*args.stats_summary, command=args.stats_command, note=args.stats_note)
+        return
+    if args.request_summary:
+        request_summary(*args.request_summary, command=args.stats_command, note=args.stats_note)
         return
     if args.counters_summary:
         counters_summary(args.counters_summary[:-1], args.counters_summary[-1],
