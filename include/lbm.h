@@ -118,7 +118,8 @@ typedef struct {
  * fill of the ring, PML Q update) and the bulk tiles as one grid, so they run beside the
  * streaming tiles (one stream, graphs and groups allowed); split places the phase-A blocks in
  * that grid: after split/8 of the bulk tiles (0..8, rounded down to a multiple of 8 blocks), or
- * -1 for the measured default (after half of the tiles for D2Q37 in FP64, first otherwise).
+ * -1 for the measured default (after all of the tiles when they outnumber the phase-A blocks
+ * eightfold, as on large grids; else after half of them for D2Q37 in FP64, first otherwise).
  * Every schedule and placement gives the same bits.  Default {64, 4, 32, 2, -1}. */
 typedef struct {
     int32_t bulk_tx, bulk_ty;
