@@ -293,7 +293,10 @@ const char *lbm_last_error(void);
 /* ---- Batched runs: one launch per kernel class advances many independent runs ---------- */
 
 /* A group advances its runs together on one stream; it does not own the runs.  Runs keep
- * their own state; a run may belong to one group at a time. */
+ * their own state; a run may belong to one group at a time.  lbm_group_add requires an
+ * initialised run of the group's storage and stencil (LBM_ERR_STATE, LBM_ERR_ARG otherwise) and
+ * holds at most 4096 runs per group (LBM_ERR_ARG beyond); adding or removing a run synchronises
+ * the group's stream and recaptures its step graphs at the next lbm_group_step. */
 lbm_status lbm_group_create(void *stream, const lbm_allocator *allocator,
                             lbm_group_handle *out);
 lbm_status lbm_group_add(lbm_group_handle g, lbm_handle h);
