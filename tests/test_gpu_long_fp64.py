@@ -60,19 +60,20 @@ def test_vortex_1088_full_length_matches_the_oracle():
     assert all(v < 1e-6 for v in errs["f32"].values()), errs["f32"]
 
 
-@pytest.mark.skipif(not os.path.exists(fixture_path("pulses_4224_zg")),
-                    reason="oracle fixture not written")
+@pytest.mark.skipif(not (os.path.exists(fixture_path("pulses_4224_zg")) and
+                         os.path.exists(fixture_path("pulses_4224_zg", "extended"))),
+                    reason="oracle fixtures not written")
 def test_pulses_4224_zg_full_length_matches_the_oracle():
     """The 4096^2 + 64-cell PML multi-pulse workload with ZG edges, its full 2000 steps.  The bar
-    is 1e-12, or 4x the double oracle's own rounding where an extended-precision fixture of the
-    same run exists and shows it higher."""
+    is 1e-12, or 4x the double oracle's own rounding where the extended-precision fixture of the
+    same run shows it higher (the velocity, of max |u| = Mach 0.05, differs from the double
+    oracle by about 2e-12 relative after the 2000 steps)."""
     fix = read_fixture("pulses_4224_zg")
     hdr = fix[0]
     assert int(hdr["steps"]) == 2000 and hdr["grid"].split() == ["4224", "4224"]
     spec = wl.multi_pulse(L=4096, W=64, sigma_max=0.01, mach=0.05, bc="zg")
-    floor = dict(rho=0.0, ux=0.0, uy=0.0, T=0.0)
-    if os.path.exists(fixture_path("pulses_4224_zg", "extended")):
-        floor = _floor(fix, read_fixture("pulses_4224_zg", "extended"))
+    floor = _floor(fix, read_fixture("pulses_4224_zg", "extended"))
+    say("double oracle vs extended at the fixture nodes", {k: "%.2e" % v for k, v in floor.items()})
     errs = _run_all(spec, "zg", 64, 0.01, 2000, fix, "pulses_4224_zg")
     for k, v in errs["f64"].items():
         bar = max(TOL, 4.0 * floor[k])
