@@ -27,10 +27,13 @@
  * translated by their characteristic speeds over one step and an incoming acoustic wave frozen,
  * on every stencil and on x and y sides.  PARITY UNPINNED beyond invariants: its corner rule (the
  * paper defers its details to a companion paper), pinned only by uniform-flow invariance,
- * symmetry and the trend that it reflects less than ZG.  Likewise the
- * readings of CBC (A) (transverse and viscous parts, the sign of eq. CBC-Relax) are pinned only
- * by uniform-flow invariance, symmetry, its exact reduction to the LODI boundary for plane waves
- * and the trend that it beats the LODI boundary on a vortex outflow.
+ * symmetry and the trend that it reflects less than ZG.  CBC (A)'s transverse part is pinned by
+ * an entropy wave carried along the edge at u_t / r cells per step and its viscous part by a
+ * quadratic shear profile (nu = (tau - 1/2) / r^2, the incoming acoustic wave taking no viscous
+ * part), besides uniform-flow invariance, symmetry, its exact reduction to the LODI boundary for
+ * plane waves and the trend that it beats the LODI boundary on a vortex outflow.  PARITY
+ * UNPINNED: CBC (A)'s acoustic edge characteristics and the sign reading of eq. CBC-Relax beyond
+ * these cases.
  */
 #include <tgmath.h>
 #include <stdint.h>

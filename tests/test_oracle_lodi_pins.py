@@ -1,5 +1,6 @@
-"""Closed-form pin for the oracle's characteristic (LODI, perfectly non-reflecting) boundary
-(CPU only).
+"""Closed-form pins for the oracle's characteristic boundaries (CPU only): the LODI, perfectly
+non-reflecting boundary (reading 10 of the design notes), and the transverse and viscous parts
+of CBC (A) (reading 18), each from gas dynamics on plane waves.
 
 A plane acoustic simple wave that runs out through an open side is the case the characteristic
 boundary exists for (Sec. 4, eqs. NSF-CHAR, PNR and thermal_LODI_macro_evo): the perturbation is
@@ -124,3 +125,85 @@ def test_each_characteristic_wave_moves_at_its_speed_and_the_incoming_one_is_fro
         for k, name in enumerate(("rho", "ux", "uy", "T")):
             err = np.abs(got[k][:, xb] - want[k]).max()
             assert err <= 1e-5 * delta, (q, xb, name, err, delta)
+
+
+@pytest.mark.parametrize("q", [37, 17])
+@pytest.mark.parametrize("ut", [0.05, -0.07])
+def test_cbc_a_carries_an_entropy_wave_along_the_edge(oracle_mod, q, ut):
+    """CBC (A)'s transverse part (Sec. 4, eq. thermal_CBC_macro_evo): a mean flow leaving
+    through the side (u_n = 0.08) and running along it (u_t), with an entropy wave
+    (d rho, d u, d T) proportional to (1, 0, -T/rho) (d p = 0) whose profile is linear along the
+    edge and constant across it.  The normal LODI part vanishes (no normal gradient), the viscous
+    part vanishes (no second derivative along the edge), the acoustic characteristics carry
+    nothing (an entropy wave projects onto neither), and the normal entropy characteristic is
+    outgoing, so it takes the transverse part whole: one step moves the profile along the edge
+    by u_t / r cells, at the side's three boundary layers.  A wrong tangent direction, wave speed
+    or time-step scale in the edge advection fails here.  A on the outflow side only (stable on
+    every stencil there), the LODI boundary on the other x side, y periodic; the nodes near the
+    periodic wrap of the linear profile are left out."""
+    _, _, r = oracle_mod.lattice(q)
+    rho0, un, T0, eps = 1.0, 0.08, 1.0, 1e-7
+    o = oracle_mod.OracleRun(20, 40, 0.8, rho0, un, ut, T0, lattice=q)
+    o.set_bc(1, oracle_mod.BC_NRBC)
+    o.set_bc(2, oracle_mod.BC_NRBC_A)
+    o.set_bc(4 | 8, oracle_mod.BC_PERIODIC)
+    Nx, Ny = o.grid()
+    X, Y = np.meshgrid(np.arange(Nx, dtype=float), np.arange(Ny, dtype=float))
+    yc = Ny / 2.0
+    F = wl.uniform_state(Nx, Ny, rho0, un, ut, T0)
+    F.rho = rho0 + eps * (Y - yc)
+    F.T = T0 - eps * (T0 / rho0) * (Y - yc)
+    o.init(*F.as_tuple())
+    o.step(1)
+    rho, ux, uy, T = o.moments()
+    nu_t = ut / r
+    ys = np.arange(8, Ny - 8)
+    for xb in (Nx - 1, Nx - 2, Nx - 3):
+        s = eps * (ys - nu_t - yc)
+        for name, g, w0 in (("rho", rho[ys, xb], rho0 + s), ("ux", ux[ys, xb], un + 0 * s),
+                            ("uy", uy[ys, xb], ut + 0 * s), ("T", T[ys, xb], T0 - (T0 / rho0) * s)):
+            # first order in eps: the remainder is O(eps^2); a wrong speed is off by ~1e-9
+            err = np.abs(g - w0).max()
+            assert err <= 1e-5 * eps * 20, (q, ut, xb, name, err)
+
+
+@pytest.mark.parametrize("q", [37, 17])
+def test_cbc_a_viscous_part_on_a_quadratic_shear_profile(oracle_mod, q):
+    """CBC (A)'s viscous part (reading of eq. thermal_CBC_macro_evo and eq. CBC-Relax): a flow
+    leaving through the side at u_n = 0.08 with no flow along it, whose normal velocity varies
+    quadratically along the edge, u_n = 0.08 + eps (t - t_c)^2.  Along the edge that is a shear
+    profile at rest, so the transverse part is zero; across the side nothing varies, so the
+    normal LODI part is zero.  The viscous part is nu d2u_n/dt2 = 2 nu eps per step, with
+    nu = (tau - 1/2) / r^2 (lattice units, Pr = 1).  Projected on the normal characteristics it
+    drives only the two acoustic ones; the outgoing one (u_n + c) takes it, the incoming one
+    (u_n - c) takes only Ma times the transverse part (zero here), so the node moves along the
+    outgoing acoustic eigenvector r4 = (1, c/rho, 0, T/rho) by rho c (2 nu eps) / (l4 . r4),
+    l4 . r4 = 4T: u_n rises by nu eps, rho by rho c nu eps / (2T), T by c nu eps / 2."""
+    _, _, r = oracle_mod.lattice(q)
+    rho0, un, T0, eps, tau = 1.0, 0.08, 1.0, 1e-7, 0.8
+    c = math.sqrt(2.0 * T0)
+    nu = (tau - 0.5) / r ** 2
+    o = oracle_mod.OracleRun(20, 40, tau, rho0, un, 0.0, T0, lattice=q)
+    o.set_bc(1, oracle_mod.BC_NRBC)
+    o.set_bc(2, oracle_mod.BC_NRBC_A)
+    o.set_bc(4 | 8, oracle_mod.BC_PERIODIC)
+    Nx, Ny = o.grid()
+    X, Y = np.meshgrid(np.arange(Nx, dtype=float), np.arange(Ny, dtype=float))
+    yc = Ny / 2.0
+    F = wl.uniform_state(Nx, Ny, rho0, un, 0.0, T0)
+    F.ux = un + eps * (Y - yc) ** 2 * 1e-2
+    o.init(*F.as_tuple())
+    o.step(1)
+    rho, ux, uy, T = o.moments()
+    e2 = eps * 1e-2                       # the profile's coefficient
+    ys = np.arange(8, Ny - 8)
+    for xb in (Nx - 1, Nx - 2, Nx - 3):
+        want = dict(rho=rho0 + rho0 * c * nu * e2 / (2 * T0),
+                    ux=un + e2 * (ys - yc) ** 2 + nu * e2,
+                    uy=0.0,
+                    T=T0 + c * nu * e2 / 2)
+        got = dict(rho=rho[ys, xb], ux=ux[ys, xb], uy=uy[ys, xb], T=T[ys, xb])
+        for k in want:
+            err = np.abs(got[k] - want[k]).max()
+            # the viscous change is nu e2 ~ 1e-10; second-order remainders are below 1e-17
+            assert err <= 1e-3 * nu * e2 + 1e-16, (q, xb, k, err, nu * e2)
