@@ -25,9 +25,8 @@
  * than ZG.  The characteristic boundary's normal update is pinned in closed form by plane simple
  * waves (tests/test_oracle_lodi_pins.py): an outgoing acoustic wave, an entropy and a shear wave
  * translated by their characteristic speeds over one step and an incoming acoustic wave frozen,
- * on every stencil and on x and y sides.  PARITY UNPINNED beyond invariants: its corner rule (the
- * paper defers its details to a companion paper), pinned only by uniform-flow invariance,
- * symmetry and the trend that it reflects less than ZG.  CBC (A)'s transverse part is pinned by
+ * on every stencil and on x and y sides, and its corner rule by two such waves leaving through
+ * the two sides of a corner (a corner node takes the increment of each normal).  CBC (A)'s transverse part is pinned by
  * an entropy wave carried along the edge at u_t / r cells per step and its viscous part by a
  * quadratic shear profile (nu = (tau - 1/2) / r^2, the incoming acoustic wave taking no viscous
  * part), besides uniform-flow invariance, symmetry, its exact reduction to the LODI boundary for

@@ -207,3 +207,54 @@ def test_cbc_a_viscous_part_on_a_quadratic_shear_profile(oracle_mod, q):
             err = np.abs(got[k] - want[k]).max()
             # the viscous change is nu e2 ~ 1e-10; second-order remainders are below 1e-17
             assert err <= 1e-3 * nu * e2 + 1e-16, (q, xb, k, err, nu * e2)
+
+
+@pytest.mark.parametrize("q", [37, 17, 9])
+def test_corner_adds_the_increments_of_both_normals(oracle_mod, q):
+    """Reading 10's corner rule: a corner node of two characteristic sides takes the LODI
+    increment of each normal.  Two plane acoustic waves leave through the x_max and y_max sides,
+    one varying along x, one along y, in a flow leaving through both (every side open).  Along
+    its own normal each wave is the outgoing simple wave of the tests above; along the other
+    normal it carries no gradient.  So after one step the corner nodes hold U0 plus the first
+    wave moved by (u_x + c)/r cells along x plus the second moved by (u_y + c)/r along y, while
+    the x_max side's other boundary nodes move only the first (the second is tangential there)
+    and the y_max side's only the second."""
+    _, _, r = oracle_mod.lattice(q)
+    rho0, ux0, uy0, T0 = 1.0, 0.06, 0.04, 1.0
+    c = math.sqrt(2.0 * T0)
+    ea, eb = 1e-7, 6e-8
+    o = oracle_mod.OracleRun(24, 22, 0.8, rho0, ux0, uy0, T0, lattice=q)
+    o.set_bc(15, oracle_mod.BC_NRBC)
+    Nx, Ny = o.grid()
+    X, Y = np.meshgrid(np.arange(Nx, dtype=float), np.arange(Ny, dtype=float))
+    xc, yc = Nx - 8.0, Ny - 8.0
+    fa, fb = X - xc, Y - yc
+    F = wl.uniform_state(Nx, Ny, rho0, ux0, uy0, T0)
+    F.rho = rho0 + ea * fa + eb * fb
+    F.ux = ux0 + ea * (c / rho0) * fa
+    F.uy = uy0 + eb * (c / rho0) * fb
+    F.T = T0 + (T0 / rho0) * (ea * fa + eb * fb)
+    o.init(*F.as_tuple())
+    o.step(1)
+    rho, ux, uy, T = o.moments()
+    nux, nuy = (ux0 + c) / r, (uy0 + c) / r
+
+    def expect(x, y, mx, my):
+        a = ea * (x - mx * nux - xc)
+        b = eb * (y - my * nuy - yc)
+        return (rho0 + a + b, ux0 + (c / rho0) * a, uy0 + (c / rho0) * b, T0 + (T0 / rho0) * (a + b))
+
+    cases = []
+    for x in (Nx - 1, Nx - 2, Nx - 3):
+        for y in (Ny - 1, Ny - 2, Ny - 3):
+            cases.append((x, y, 1, 1))            # corner block: both normals
+        cases.append((x, Ny // 2, 1, 0))          # x_max side only
+    for y in (Ny - 1, Ny - 2, Ny - 3):
+        cases.append((Nx // 2, y, 0, 1))          # y_max side only
+    for x, y, mx, my in cases:
+        want = expect(float(x), float(y), mx, my)
+        got = (rho[y, x], ux[y, x], uy[y, x], T[y, x])
+        for name, g, w0 in zip(("rho", "ux", "uy", "T"), got, want):
+            # first order in the amplitudes (about 1e-6 here); a missing or doubled normal's
+            # increment is off by about 1e-7
+            assert abs(g - w0) <= 1e-12, (q, x, y, name, g - w0)
