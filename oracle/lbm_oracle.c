@@ -22,17 +22,17 @@
  * periodic box; rest and uniform states stationary under every boundary and PML; sigma_max = 0
  * PML identical to no PML; linear growth of Q under a constant deviation; mirror symmetry;
  * linear acoustics vs the linearised Navier-Stokes-Fourier solution; ZG+PML reflecting less
- * than ZG.  The characteristic boundary's normal update is pinned in closed form by plane simple
- * waves (tests/test_oracle_lodi_pins.py): an outgoing acoustic wave, an entropy and a shear wave
+ * than ZG; one step of the PML collision and of the appendix terms in closed form.  The
+ * characteristic boundary is pinned in closed form by plane simple waves
+ * (tests/test_oracle_lodi_pins.py): an outgoing acoustic wave, an entropy and a shear wave
  * translated by their characteristic speeds over one step and an incoming acoustic wave frozen,
- * on every stencil and on x and y sides, and its corner rule by two such waves leaving through
- * the two sides of a corner (a corner node takes the increment of each normal).  CBC (A)'s transverse part is pinned by
- * an entropy wave carried along the edge at u_t / r cells per step and its viscous part by a
- * quadratic shear profile (nu = (tau - 1/2) / r^2, the incoming acoustic wave taking no viscous
- * part), besides uniform-flow invariance, symmetry, its exact reduction to the LODI boundary for
- * plane waves and the trend that it beats the LODI boundary on a vortex outflow.  PARITY
- * UNPINNED: CBC (A)'s acoustic edge characteristics and the sign reading of eq. CBC-Relax beyond
- * these cases.
+ * on x and y sides, and its corner rule by two such waves leaving through the two sides of a
+ * corner.  CBC (A) is pinned by an entropy wave carried along the edge at u_t / r cells per step,
+ * a quadratic shear profile along the edge (its viscous part, nu = (tau - 1/2) / r^2), and an
+ * acoustic wave running along the edge (its acoustic edge characteristics, with the incoming
+ * normal acoustic wave taking Ma times its transverse part, the reading of eq. CBC-Relax),
+ * besides uniform-flow invariance, symmetry, its exact reduction to the LODI boundary for plane
+ * waves and the trend that it beats the LODI boundary on a vortex outflow.
  */
 #include <tgmath.h>
 #include <stdint.h>

@@ -258,3 +258,48 @@ def test_corner_adds_the_increments_of_both_normals(oracle_mod, q):
             # first order in the amplitudes (about 1e-6 here); a missing or doubled normal's
             # increment is off by about 1e-7
             assert abs(g - w0) <= 1e-12, (q, x, y, name, g - w0)
+
+
+@pytest.mark.parametrize("q", [37, 17])
+def test_cbc_a_acoustic_wave_along_the_edge(oracle_mod, q):
+    """CBC (A)'s transverse part on an acoustic wave running along the edge (reading 18 with
+    eq. CBC-Relax read as right-hand-side terms): the plane wave r_t = (d rho, d u_n, d u_t, d T)
+    = (1, 0, c/rho, T/rho) eps g(t), g linear along the edge, in a flow leaving through the side
+    (u_n = 0.08) and running along it (u_t = 0.05).  The edge advection moves it by
+    (u_t + c)/r cells: dV_T = -eps g' (u_t + c)/r r_t.  The normal characteristics then take
+    that change: the outgoing ones whole, the incoming acoustic one only Ma times its part
+    (Ma = |u0|), whose share of r_t is (l1 . r_t)/(l1 . r1) r1 = r1 / 2 with
+    r1 = (1, -c/rho, 0, T/rho).  So the node moves by dV_T - (1 - Ma) (1/2) (-eps g' nu_t) r1."""
+    _, _, r = oracle_mod.lattice(q)
+    rho0, un, ut, T0, eps = 1.0, 0.08, 0.05, 1.0, 1e-7
+    c = math.sqrt(2.0 * T0)
+    ma = math.hypot(un, ut)
+    o = oracle_mod.OracleRun(20, 40, 0.8, rho0, un, ut, T0, lattice=q)
+    o.set_bc(1, oracle_mod.BC_NRBC)
+    o.set_bc(2, oracle_mod.BC_NRBC_A)
+    o.set_bc(4 | 8, oracle_mod.BC_PERIODIC)
+    Nx, Ny = o.grid()
+    X, Y = np.meshgrid(np.arange(Nx, dtype=float), np.arange(Ny, dtype=float))
+    yc = Ny / 2.0
+    g = Y - yc
+    F = wl.uniform_state(Nx, Ny, rho0, un, ut, T0)
+    F.rho = rho0 + eps * g
+    F.uy = ut + eps * (c / rho0) * g
+    F.T = T0 + eps * (T0 / rho0) * g
+    o.init(*F.as_tuple())
+    o.step(1)
+    rho, ux, uy, T = o.moments()
+    nu_t = (ut + c) / r
+    assert 0.0 < nu_t < 2.0
+    rt = np.array([1.0, 0.0, c / rho0, T0 / rho0])          # (rho, u_n, u_t, T)
+    r1 = np.array([1.0, -c / rho0, 0.0, T0 / rho0])
+    dvt = -eps * nu_t * rt                                   # g' = 1
+    dU = dvt - (1.0 - ma) * 0.5 * (-eps * nu_t) * r1
+    ys = np.arange(8, Ny - 8)
+    for xb in (Nx - 1, Nx - 2, Nx - 3):
+        base = np.array([rho0, un, ut, T0])[:, None] + eps * np.outer(rt, ys - yc)
+        want = base + dU[:, None]
+        got = np.array([rho[ys, xb], ux[ys, xb], uy[ys, xb], T[ys, xb]])
+        err = np.abs(got - want).max()
+        # the change is about 1e-7; second-order remainders are about 1e-13
+        assert err <= 1e-5 * eps * nu_t, (q, xb, err)
