@@ -230,6 +230,22 @@ lbm_status setup_geometry(lbm_run *h, RunDev &R) {
     R.fy0 = R.gym; R.fy1 = R.Ny - R.gyp;
     long long fast = (long long)std::max(0, R.fx1 - R.fx0) * std::max(0, R.fy1 - R.fy0);
     R.frame_n = (int)((long long)R.Nx * R.Ny - fast);
+    // the frame off the ring: strips between the ring's inner rectangle and the fast rectangle
+    // (the frame is at least as deep as the ring on every side unless the fast rectangle is
+    // empty; the clamps then make the strips cover the ring's inner rectangle)
+    {
+        const int nxr = R.Nx - R.rxm - R.rxp, nyr = R.Ny - R.rym - R.ryp;
+        R.axm = std::min(std::max(R.gxm - R.rxm, 0), nxr);
+        R.axp = std::min(std::max(R.gxp - R.rxp, 0), nxr - R.axm);
+        R.aym = std::min(std::max(R.gym - R.rym, 0), nyr);
+        R.ayp = std::min(std::max(R.gyp - R.ryp, 0), nyr - R.aym);
+        const long long ann = (long long)(R.aym + R.ayp) * nxr +
+                              (long long)(nyr - R.aym - R.ayp) * (R.axm + R.axp);
+        if (ann != (long long)R.frame_n - R.ring_n)
+            return fail(LBM_ERR_UNSUPPORTED, "frame numbering: the annulus does not cover the frame");
+        R.ann_n = (int)ann;
+        R.ann0 = (int)round_up(R.ring_n, 64);
+    }
     R.has_q = h->W > 0 && (h->pml[0] || h->pml[1] || h->pml[2] || h->pml[3]);
     // Padding each population row past the 64-element rounding staggers the 74 row streams of a
     // bulk tile across HBM channels: +4% bulk bandwidth at 4224^2 in FP64 and FP32 (64 elements);
@@ -246,7 +262,7 @@ lbm_status setup_geometry(lbm_run *h, RunDev &R) {
         R.plane = round_up(row * R.Ny, 64);
         R.fsize = (long long)nq * R.plane;
     }
-    R.qplane = round_up(std::max(R.frame_n, 1), 64);
+    R.qplane = round_up(std::max(R.ann0 + R.ann_n, 1), 64);
     R.rplane = round_up(std::max(R.ring_n, 1), 64);
     // the bulk kernel addresses a tile (at most 4 rows) with a 32-bit byte offset from a
     // uniform base; the frame arrays use 32-bit element indices
@@ -334,7 +350,7 @@ size_t footprint_of(const RunDev &R, int storage, int nq) {
 void compute_blocks(const RunDev &R, int tx, int nb[NCLS]) {
     int k = tx_index(tx);
     nb[CLS_BULK] = R.tiles_x[k] * R.tiles_y[k];
-    const int fb = frame_block_count(R.frame_n);
+    const int fb = frame_block_count(R.ann_n);
     const int rb = ring_block_count(R.ring_n);
     nb[CLS_FRAME] = rb + fb;
     nb[CLS_A] = rb + (R.has_q ? fb : 0);
@@ -876,7 +892,7 @@ lbm_status lbm_pml_q(lbm_handle h, double *Q) {
     double *tmp = (double *)h->mem.get(n * sizeof(double));
     if (!tmp) return fail(LBM_ERR_OOM, "device allocation failed");
     hipError_t e = hipMemsetAsync(tmp, 0, n * sizeof(double), h->stream);
-    if (e == hipSuccess) e = h->ks->export_q(h->dd, h->desc.storage, R.frame_n, tmp, h->stream);
+    if (e == hipSuccess) e = h->ks->export_q(h->dd, h->desc.storage, R.ann0 + R.ann_n, tmp, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(Q, tmp, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     h->mem.put(tmp);
@@ -1052,8 +1068,8 @@ lbm_status lbm_save(lbm_handle h, const char *path) {
     for (int b = 0; b < 2; ++b) { HIP_TRY(hipMemcpy(p, R.U[b], ub, hipMemcpyDeviceToHost)); p += ub; }
     if (gb) { HIP_TRY(hipMemcpy(p, R.G, gb, hipMemcpyDeviceToHost)); p += gb; }
     CkptHeader hdr{};
-    std::memcpy(hdr.magic, "LBMPML04", 8);
-    hdr.version = 4; hdr.Nx = R.Nx; hdr.Ny = R.Ny; hdr.storage = storage; hdr.W = h->W;
+    std::memcpy(hdr.magic, "LBMPML05", 8);
+    hdr.version = 5; hdr.Nx = R.Nx; hdr.Ny = R.Ny; hdr.storage = storage; hdr.W = h->W;
     hdr.layout = h->desc.layout; hdr.lattice = h->lat->q; hdr.pml_terms = (int32_t)h->pml_terms;
     for (int s = 0; s < 4; ++s) { hdr.pml[s] = h->pml[s]; hdr.bc[s] = h->bc[s]; }
     hdr.par = R.par; hdr.steps = h->steps; hdr.plane = R.plane; hdr.qplane = R.qplane;
@@ -1075,7 +1091,7 @@ lbm_status lbm_load(lbm_handle h, const char *path) {
     FILE *fp = std::fopen(path, "rb");
     if (!fp) return fail(LBM_ERR_ARG, std::string("cannot open ") + path);
     CkptHeader hdr{};
-    if (std::fread(&hdr, sizeof hdr, 1, fp) != 1 || std::memcmp(hdr.magic, "LBMPML04", 8) != 0) {
+    if (std::fread(&hdr, sizeof hdr, 1, fp) != 1 || std::memcmp(hdr.magic, "LBMPML05", 8) != 0) {
         std::fclose(fp);
         return fail(LBM_ERR_ARG, "not a checkpoint file");
     }

@@ -24,11 +24,16 @@ enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2 };
 // space; with the plane layout `plane` is a whole padded plane and `pitch` a padded row.
 // Arrays of per-pair and per-shell constants are sized for the largest stencil (D2Q37).
 // Frame: the nodes outside the fast interior rectangle [fx0,fx1) x [fy0,fy1), i.e. a frame of
-// depth gxm/gxp/gym/gyp on the four sides.  Frame nodes are numbered bottom strip, top strip,
-// left strip, right strip (row-major inside each strip); Q and the moment strips U use that
-// numbering, so a frame thread touches its own Q/U entries with unit stride.  The ring is the
-// same construction with depth 3 on characteristic (NRBC) sides only: the boundary nodes that
-// need the FP64 characteristic fill, handled by the first blocks of the boundary launches.
+// depth gxm/gxp/gym/gyp on the four sides.  The ring is the outer part of the frame with depth 3
+// on characteristic (NRBC) sides only: the boundary nodes that need the FP64 characteristic
+// fill, handled by the first blocks of the boundary launches.  Strips of a frame-shaped region
+// are numbered bottom strip, top strip, left strip, right strip (row-major inside each strip).
+// Frame index t, which Q and the moment strips U use: the ring nodes first, t = their ring index
+// in [0, ring_n); then, from ann0 (ring_n rounded up to 64) on, the other frame nodes, numbered
+// as the strips of the annulus between the ring's inner rectangle and the fast rectangle (depths
+// axm/axp/aym/ayp); the ring_n..ann0 gap is unused.  A frame thread touches its own Q/U entries
+// with unit stride, and the ring blocks and the frame blocks share no cache line of Q or U.
+// Without a ring the numbering is the frame's own strip numbering.
 struct alignas(256) RunDev {
     int Nx, Ny, pitch, storage;
     long long plane;          // element stride between populations of one node
@@ -41,6 +46,8 @@ struct alignas(256) RunDev {
     int fx0, fx1, fy0, fy1;   // fast rectangle
     int frame_n, has_q, ring_n, pml_terms;   // pml_terms: PML moments in the NRBC target
     int rxm, rxp, rym, ryp;   // characteristic-boundary ring depths (3 on NRBC sides, else 0)
+    int axm, axp, aym, ayp;   // depths of the frame's annulus off the ring
+    int ann0, ann_n;          // first frame index and count of the frame nodes off the ring
     int tiles_x[3], tiles_y[3];   // bulk tiles for tile widths 64, 128, 256
     // state
     void *f[2];
@@ -120,7 +127,8 @@ struct KernelSet {
                           double *uy, double *T, hipStream_t s);
     hipError_t (*export_f)(RunDev *run, int storage, int Nx, int Ny, const double *fbar,
                            double *out, hipStream_t s);
-    hipError_t (*export_q)(RunDev *run, int storage, int frame_n, double *out, hipStream_t s);
+    // Q of every frame node into a full grid (nt: the frame index extent, ann0 + ann_n)
+    hipError_t (*export_q)(RunDev *run, int storage, int nt, double *out, hipStream_t s);
     hipError_t (*check)(RunDev *run, int storage, int Nx, int Ny, int *flag, hipStream_t s);
     hipError_t (*err_rows)(const double *rho, const double *ux, const double *T, int Nx,
                            int x0, int y0, int lx, int ly, const double *rr, const double *ru,

@@ -178,11 +178,20 @@ __device__ __forceinline__ void strip_xy(int Nx, int Ny, int dxm, int dxp, int d
     else { t -= Fb + Ft + Fl; int r = t / dxp; y = dym + r; x = Nx - dxp + (t - r * dxp); }
 }
 
-__device__ __forceinline__ void frame_xy(CRun &R, int t, int &x, int &y) {
-    strip_xy(R.Nx, R.Ny, R.gxm, R.gxp, R.gym, R.gyp, t, x, y);
-}
 __device__ __forceinline__ void ring_xy(CRun &R, int t, int &x, int &y) {
     strip_xy(R.Nx, R.Ny, R.rxm, R.rxp, R.rym, R.ryp, t, x, y);
+}
+// Node a of the frame off the ring (annulus numbering, 0 <= a < ann_n); its frame index is
+// ann0 + a.
+__device__ __forceinline__ void ann_xy(CRun &R, int a, int &x, int &y) {
+    strip_xy(R.Nx - R.rxm - R.rxp, R.Ny - R.rym - R.ryp, R.axm, R.axp, R.aym, R.ayp, a, x, y);
+    x += R.rxm;
+    y += R.rym;
+}
+// Node of frame index t (ring nodes first, then the annulus from ann0; t not in the gap).
+__device__ __forceinline__ void frame_xy(CRun &R, int t, int &x, int &y) {
+    if (t < R.ring_n) ring_xy(R, t, x, y);
+    else ann_xy(R, t - R.ann0, x, y);
 }
 
 // Inverse of strip_xy: strip index of (x, y), or -1 outside the strips.
@@ -195,11 +204,18 @@ __device__ __forceinline__ int strip_idx(int Nx, int Ny, int dxm, int dxp, int d
     return -1;
 }
 
-__device__ __forceinline__ int fidx(CRun &R, int x, int y) {
-    return strip_idx(R.Nx, R.Ny, R.gxm, R.gxp, R.gym, R.gyp, x, y);
-}
 __device__ __forceinline__ int ridx(CRun &R, int x, int y) {
     return strip_idx(R.Nx, R.Ny, R.rxm, R.rxp, R.rym, R.ryp, x, y);
+}
+// Frame index of (x, y) on the grid, or -1 for a node of the fast rectangle.
+__device__ __forceinline__ int fidx(CRun &R, int x, int y) {
+    if (R.ring_n > 0) {   // (uniform) without a ring the annulus is the whole frame
+        const int r = ridx(R, x, y);
+        if (r >= 0) return r;
+    }
+    const int a = strip_idx(R.Nx - R.rxm - R.rxp, R.Ny - R.rym - R.ryp, R.axm, R.axp, R.aym, R.ayp,
+                            x - R.rxm, y - R.rym);
+    return a < 0 ? -1 : R.ann0 + a;
 }
 
 __device__ __forceinline__ bool in_q(CRun &R, int x, int y) {
@@ -809,11 +825,12 @@ __device__ __forceinline__ void pml_moments(CRun &R, int x, int y, int t, const 
 }
 
 // Blocks of a run's boundary launches: the characteristic ring first (ring numbering, RING_BLOCK
-// nodes per block), then the frame (frame numbering, FRAME_BLOCK nodes per block), both counts
-// padded to multiples of 8.  frame_start maps a frame block to its first frame index, XCD by XCD.
+// nodes per block), then the frame off the ring (annulus numbering, FRAME_BLOCK nodes per block),
+// both counts padded to multiples of 8.  frame_start maps a frame block to its first annulus
+// index, XCD by XCD.
 __device__ __forceinline__ int ring_blocks(CRun &R) { return ring_block_count(R.ring_n); }
 __device__ __forceinline__ int frame_start(CRun &R, int fblock) {
-    return xcd_swizzle(fblock, frame_block_count(R.frame_n)) * FRAME_BLOCK;
+    return xcd_swizzle(fblock, frame_block_count(R.ann_n)) * FRAME_BLOCK;
 }
 
 // Characteristic targets of the ring, formed ahead of phase A for runs that select the appendix's
@@ -835,8 +852,7 @@ __global__ __launch_bounds__(256) void k_target(RunDev *const *__restrict__ runs
     if (tt >= R.ring_n) return;
     int x, y;
     ring_xy(R, tt, x, y);
-    const int t = fidx(R, x, y);
-    if (t < 0) return;
+    const int t = tt;   // a ring node's frame index is its ring index
     const GLOBAL double *Uc = (const GLOBAL double *)R.U[par];
     const unsigned qp = (unsigned)R.qplane;
     double Ut[4] = {Uc[t], Uc[qp + t], Uc[2 * qp + t], Uc[3 * qp + t]};
@@ -1028,18 +1044,16 @@ __global__ __launch_bounds__(256) void k_frame(RunDev *const *__restrict__ runs,
         const int tt = tb * RING_BLOCK + (int)threadIdx.x;
         if (tt >= R.ring_n) return;
         ring_xy(R, tt, x, y);
-        t = fidx(R, x, y);
-        if (t < 0) return;
+        t = tt;
         const GLOBAL C *G = (const GLOBAL C *)R.G;
         const unsigned rp = (unsigned)R.rplane;
 #pragma unroll
         for (int i = 0; i < NQ; ++i) g[i] = G[i * rp + tt];
     } else {
-        const int tt = frame_start(R, tb - rb) + (int)threadIdx.x;
-        if (tt >= R.frame_n) return;
-        frame_xy(R, tt, x, y);
-        if (in_ring(R, x, y)) return;
-        t = tt;
+        const int ta = frame_start(R, tb - rb) + (int)threadIdx.x;
+        if (ta >= R.ann_n) return;
+        ann_xy(R, ta, x, y);
+        t = R.ann0 + ta;
         gather_clamped<S, C>(R, (const GLOBAL S *)R.f[par], x, y, k.inv_scale, g);
     }
     frame_collide<S, C>(R, k, g, x, y, t, (const GLOBAL C *)R.Q,
@@ -1106,8 +1120,7 @@ __device__ __forceinline__ void phase_a_block(RunDev *const *__restrict__ runs,
         const int tt = tb * RING_BLOCK + (int)threadIdx.x;
         if (tt >= R.ring_n) return;
         ring_xy(R, tt, x, y);
-        t = fidx(R, x, y);
-        if (t < 0) return;
+        t = tt;
         nrbc_node<S, C>(R, par, tt, x, y, t, k.inv_scale);
         if (!R.has_q || !in_q(R, x, y)) return;
         // the moments of the filled populations, read back from G (this thread's own stores);
@@ -1119,11 +1132,11 @@ __device__ __forceinline__ void phase_a_block(RunDev *const *__restrict__ runs,
         const unsigned rp = (unsigned)R.rplane;
         m = moments_streamed<6, C>([&](auto ic) { return G[decltype(ic)::value * rp + tr]; }, k);
     } else {
-        const int tt = frame_start(R, tb - rb) + (int)threadIdx.x;
-        if (!R.has_q || tt >= R.frame_n) return;
-        frame_xy(R, tt, x, y);
-        if (in_ring(R, x, y) || !in_q(R, x, y)) return;
-        t = tt;
+        const int ta = frame_start(R, tb - rb) + (int)threadIdx.x;
+        if (!R.has_q || ta >= R.ann_n) return;
+        ann_xy(R, ta, x, y);
+        if (!in_q(R, x, y)) return;
+        t = R.ann0 + ta;
         C g[NQ];
         gather_clamped<S, C>(R, (const GLOBAL S *)R.f[par], x, y, k.inv_scale, g);
         m = moments<C>(g, k);
@@ -1312,7 +1325,7 @@ __global__ __launch_bounds__(256) void k_export_q(RunDev *Rw, double *out) {
     using C = typename Traits<S>::C;
     CRun &R = *(CRun *)Rw;
     const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= R.frame_n) return;
+    if (t >= R.ann0 + R.ann_n || (t >= R.ring_n && t < R.ann0)) return;   // past the end; the gap
     int x, y;
     frame_xy(R, t, x, y);
     const long long nn = (long long)R.Nx * R.Ny;
@@ -1548,9 +1561,9 @@ static hipError_t launch_export_f(RunDev *run, int storage, int Nx, int Ny, cons
     return hipGetLastError();
 }
 
-static hipError_t launch_export_q(RunDev *run, int storage, int frame_n, double *out, hipStream_t s) {
-    if (frame_n <= 0) return hipSuccess;
-    int nb = blocks_for(frame_n);
+static hipError_t launch_export_q(RunDev *run, int storage, int nt, double *out, hipStream_t s) {
+    if (nt <= 0) return hipSuccess;
+    int nb = blocks_for(nt);
     LBM_DISPATCH(storage, hipLaunchKernelGGL((k_export_q<S>), dim3(nb), dim3(256), 0, s, run, out));
     return hipGetLastError();
 }
