@@ -83,6 +83,26 @@ def test_setters_validate_and_grid():
     assert ei.value.status == lbm.LBM_ERR_STATE
 
 
+def test_grid_size_limits():
+    """Grids of up to 2^30 nodes are accepted.  A larger grid, or a frame whose Q and U planes
+    would pass the 32-bit byte offsets the kernels use (4 GiB per plane), is refused with
+    LBM_ERR_ARG when the geometry is set up, before any device memory is touched."""
+    r = lbm.Run(32768, 32768, 0.8)                     # exactly 2^30 nodes
+    assert r.footprint() > 2 * 37 * 2 ** 30 * 8
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.Run(32768, 32769, 0.8).footprint()
+    assert ei.value.status == lbm.LBM_ERR_ARG and "too large" in str(ei.value)
+    r = lbm.Run(1, 1, 0.8)                             # 32001^2 nodes, all of them frame
+    r.set_bc(lbm.LBM_ALL, "zg")
+    r.set_pml(lbm.LBM_ALL, 16000, 0.1)
+    assert r.grid() == (32001, 32001)
+    with pytest.raises(lbm.LbmError) as ei:
+        r.footprint()
+    assert ei.value.status == lbm.LBM_ERR_ARG and "frame arrays" in str(ei.value)
+    r.set_pml(lbm.LBM_ALL, 8000, 0.1)                  # 16001^2: the frame fits
+    assert r.footprint() > 2 * 37 * 16001 ** 2 * 8
+
+
 @pytest.mark.parametrize("q", [37, 17, 9])
 def test_cbc_a_kind_and_footprint(q):
     """CBC (A) is boundary kind 3; another kind is refused.  Its targets are formed ahead of the
