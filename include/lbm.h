@@ -282,7 +282,9 @@ lbm_status lbm_profile_read(lbm_handle h, double ms[3], int64_t launches[3], int
 
 /* Checkpoint: write / read the full state (populations, Q, moment strips, step count,
  * configuration) to a binary file with a header and checksum.  lbm_load needs a handle
- * created and configured identically and initialised (any fields). */
+ * created and configured identically and initialised (any fields); a file of another format
+ * version (the layout of Q and the moment strips follows the library's frame numbering) or
+ * another configuration is refused with LBM_ERR_ARG. */
 lbm_status lbm_save(lbm_handle h, const char *path);
 lbm_status lbm_load(lbm_handle h, const char *path);
 
