@@ -245,6 +245,44 @@ def test_checkpoint_roundtrip_bitwise(tmp_path):
     assert all(np.array_equal(x, y) for x, y in zip(a.moments(), c.moments()))
 
 
+def test_checkpoint_refuses_foreign_files(tmp_path):
+    """A checkpoint with a flipped payload byte, of another format version, cut short, or written
+    by a differently configured run is refused with LBM_ERR_ARG, and the refused load leaves the
+    handle's state as it was."""
+    def make(W=6):
+        r = lbm.Run(60, 50, 0.8, 1.0, 0.05, 0.0, 1.0)
+        r.set_bc(15, "nrbc")
+        r.set_pml(15, W, 0.05)
+        r.init(*wl.noisy_state(60 + 2 * W, 50 + 2 * W, 2, 1.0, 0.05, 0.0, 1.0).as_tuple())
+        return r
+    a = make()
+    a.step(7)
+    good = tmp_path / "ck.bin"
+    a.save(good)
+    raw = good.read_bytes()
+    c = make()
+    c.step(3)
+    before = c.populations()
+    flipped = bytearray(raw)
+    flipped[-1] ^= 0x01
+    cases = {"checksum": bytes(flipped), "not a checkpoint": b"LBMPML04" + raw[8:],
+             "truncated": raw[:-8]}
+    for what, data in cases.items():
+        say("case checkpoint refused:", what)
+        path = tmp_path / ("bad_%s.bin" % what.replace(" ", "_"))
+        path.write_bytes(data)
+        with pytest.raises(lbm.LbmError) as ei:
+            c.load(path)
+        assert ei.value.status == lbm.LBM_ERR_ARG and what in str(ei.value), str(ei.value)
+        assert c.step_count == 3 and np.array_equal(c.populations(), before)
+    other = make(W=5)
+    with pytest.raises(lbm.LbmError) as ei:
+        other.load(good)
+    assert ei.value.status == lbm.LBM_ERR_ARG and "differs" in str(ei.value)
+    c.load(good)
+    assert c.step_count == 7 and np.array_equal(c.populations(), a.populations())
+
+
 @pytest.mark.parametrize("which", ["vortex_1088", "pulses_4224", "pulses_4224_nrbc"])
 def test_full_size_grids_in_bench_launch(oracle_mod, perm, which):
     """The full grids of the benchmark workloads (1024^2 + 32 PML with NRBC; 4096^2 + 64 PML with
