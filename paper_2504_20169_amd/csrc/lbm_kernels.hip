@@ -1023,8 +1023,8 @@ __device__ __forceinline__ void frame_collide(CRun &R, const K<C> &k, const C (&
 }
 
 // Phase B of a step on the frame: ring blocks take the post-boundary populations phase A stored
-// in G; frame blocks pull (periodic wrap, or eq. zg-bc's copy of x_f = clamp(x, 3, N-4) on open
-// axes) and skip ring nodes.
+// in G; the frame blocks, which cover the frame off the ring, pull (periodic wrap, or eq.
+// zg-bc's copy of x_f = clamp(x, 3, N-4) on open axes).
 template <class S>
 __global__ __launch_bounds__(256) void k_frame(RunDev *const *__restrict__ runs,
                                                const int *__restrict__ prefix, int nruns, int ks) {
