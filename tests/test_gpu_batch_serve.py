@@ -92,6 +92,31 @@ def test_batch_equals_alone(oracle_mod, storage):
     g.close()
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_batch_of_degenerate_frames_equals_alone(storage):
+    """Runs whose characteristic ring covers nearly the whole grid (7x7 and 8x8 with the LODI
+    boundary on every side: the frame off the ring is one node, or none), with a PML one cell
+    wide, and a plain ZG run, advanced in one group: bitwise the runs stepped alone."""
+    cases = [(7, 0, "nrbc", 9), (8, 0, "nrbc", 6), (9, 1, "nrbc", 7), (7, 0, "zg", 5)]
+    alone = []
+    for k, (L, W, bc, n) in enumerate(cases):
+        say("case degenerate frame alone", storage, (L, W, bc, n))
+        r = _make(L, W, bc, storage, 70 + k)
+        r.step(n)
+        alone.append(r.populations())
+        r.close()
+    g = lbm.Group()
+    runs = [_make(L, W, bc, storage, 70 + k) for k, (L, W, bc, n) in enumerate(cases)]
+    for r in runs:
+        g.add(r)
+    g.step(steps=np.array([c[3] for c in cases]))
+    g.synchronize()
+    for r, a, c in zip(runs, alone, cases):
+        assert r.step_count == c[3] and r.check() == lbm.LBM_OK, c
+        assert np.array_equal(r.populations(), a), c
+    g.close()
+
+
 @pytest.mark.parametrize("gs", [0, 8])
 def test_batch_fused_schedule_equals_alone(oracle_mod, gs):
     """Phase A fused with the bulk tiles in one grid per step (eager and in graphs), over a batch
