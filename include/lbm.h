@@ -246,8 +246,18 @@ lbm_status lbm_error_norms_noalloc(lbm_handle h, const double *ref_rho, const do
                                    const double *ref_T, double *out);
 
 /* Scan the current state for non-finite values, rho <= 0 or T <= 0: LBM_OK or
- * LBM_ERR_UNSTABLE.  Synchronises. */
+ * LBM_ERR_UNSTABLE.  In the bounds-checked build, LBM_ERR_DEVICE first if a kernel of the run
+ * met an index out of range since the run's descriptor was last uploaded.  Synchronises. */
 lbm_status lbm_check(lbm_handle h);
+
+/* How this library was built: 0 for the normal build, LBM_BUILD_BOUNDS for the bounds-checked
+ * debug build (liblbm_mi355x_bounds.so, same ABI).  That build checks every element index of
+ * the step kernels against its buffer (populations, Q, the moment strips, the ring's G and
+ * targets) and the grid coordinates of the boundary nodes; an index out of range is counted on
+ * the run and replaced by 0, so the kernel does not fault, and lbm_check reports it.  It gives
+ * the same results as the normal build and runs slower.  Host only; never fails. */
+#define LBM_BUILD_BOUNDS 1
+int32_t lbm_build_flags(void);
 
 /* Wait for the run's stream. */
 lbm_status lbm_synchronize(lbm_handle h);
@@ -323,7 +333,8 @@ lbm_status lbm_group_autotune(lbm_group_handle g, int32_t steps, lbm_launch *cho
 lbm_status lbm_group_size(lbm_group_handle g, int32_t *n);
 /* lbm_check of every member with one synchronisation: flags[k] (host, caller-owned, one entry
  * per member in member order) receives 0 for a healthy state, 1 for a non-finite value, rho <= 0
- * or T <= 0.  Synchronises the group's stream.  Errors: LBM_ERR_ARG for NULL pointers. */
+ * or T <= 0, and, in the bounds-checked build only, 2 for a run whose kernels met an index out of
+ * range.  Synchronises the group's stream.  Errors: LBM_ERR_ARG for NULL pointers. */
 lbm_status lbm_group_check(lbm_group_handle g, int32_t *flags);
 lbm_status lbm_group_synchronize(lbm_group_handle g);
 void lbm_group_destroy(lbm_group_handle g);

@@ -1,4 +1,6 @@
-"""Build the HIP library (gfx950) in-tree: ``paper_2504_20169_amd/liblbm_mi355x.so``.
+"""Build the HIP library (gfx950) in-tree: ``paper_2504_20169_amd/liblbm_mi355x.so``, and with
+``bounds=True`` its bounds-checked debug build ``liblbm_mi355x_bounds.so`` (same sources and ABI,
+compiled with LBM_BOUNDS: every element index of the step kernels is checked against its buffer).
 
 Flags: -O3, FP contraction only within an expression (-ffp-contract=on, so the same source
 expression rounds the same way in every kernel that inlines it), no fast-math, packed-FP32
@@ -15,6 +17,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbm_mi355x.so")
+LIB_BOUNDS = os.path.join(HERE, "liblbm_mi355x_bounds.so")
 # lbm_kernels_d2q17.hip and lbm_kernels_d2q9.hip compile lbm_kernels.hip again for the D2Q17 and
 # D2Q9 stencils
 SOURCES = [os.path.join(HERE, "csrc", n)
@@ -35,20 +38,22 @@ def _run(cmd, verbose):
     return res.returncode
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, bounds: bool = False) -> str:
+    lib = LIB_BOUNDS if bounds else LIB
+    flags = FLAGS + (["-DLBM_BOUNDS"] if bounds else [])
     with tempfile.TemporaryDirectory(prefix="lbm_build_") as tmpdir:
         objs = [os.path.join(tmpdir, os.path.basename(s) + ".o") for s in SOURCES]
-        cmds = [[HIPCC] + FLAGS + ["-c", s, "-o", o] for s, o in zip(SOURCES, objs)]
+        cmds = [[HIPCC] + flags + ["-c", s, "-o", o] for s, o in zip(SOURCES, objs)]
         with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
             rcs = list(ex.map(lambda c: _run(c, verbose), cmds))
         if any(rcs):
-            raise RuntimeError("hipcc failed compiling for %s" % LIB)
-        tmp = LIB + ".tmp"
+            raise RuntimeError("hipcc failed compiling for %s" % lib)
+        tmp = lib + ".tmp"
         if _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp], verbose):
-            raise RuntimeError("hipcc failed linking %s" % LIB)
-        os.replace(tmp, LIB)
-    return LIB
+            raise RuntimeError("hipcc failed linking %s" % lib)
+        os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, bounds="--bounds" in sys.argv))

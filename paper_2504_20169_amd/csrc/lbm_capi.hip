@@ -973,6 +973,14 @@ lbm_status lbm_error_norms_noalloc(lbm_handle h, const double *ref_rho, const do
     return LBM_OK;
 }
 
+int32_t lbm_build_flags(void) {
+#ifdef LBM_BOUNDS
+    return LBM_BUILD_BOUNDS;
+#else
+    return 0;
+#endif
+}
+
 lbm_status lbm_check(lbm_handle h) {
     if (!h) return fail(LBM_ERR_ARG, "NULL handle");
     if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
@@ -983,6 +991,7 @@ lbm_status lbm_check(lbm_handle h) {
     if (e == hipSuccess) e = hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return fail(LBM_ERR_DEVICE, std::string("lbm_check: ") + hipGetErrorString(e));
+    if (hf & 2) return fail(LBM_ERR_DEVICE, "a kernel met an index out of range (bounds-checked build)");
     if (hf) return fail(LBM_ERR_UNSTABLE, "non-finite value, rho <= 0 or T <= 0 in the state");
     return LBM_OK;
 }
@@ -1393,7 +1402,7 @@ lbm_status lbm_group_check(lbm_group_handle g, int32_t *flags) {
     }
     HIP_TRY(hipMemcpyAsync(g->hflags, g->dflags, n * sizeof(int), hipMemcpyDeviceToHost, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
-    for (size_t k = 0; k < n; ++k) flags[k] = g->hflags[k] ? 1 : 0;
+    for (size_t k = 0; k < n; ++k) flags[k] = g->hflags[k] & 2 ? 2 : g->hflags[k] ? 1 : 0;
     return LBM_OK;
 }
 

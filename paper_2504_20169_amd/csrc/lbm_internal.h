@@ -63,6 +63,9 @@ struct alignas(256) RunDev {
     double H0rest, H0e[NPAIR_MAX], H0o[NPAIR_MAX], E2_0[NSHELL_MAX], O1_0[NSHELL_MAX];
     float omega_f, rho0_f, u0x_f, u0y_f, th0_f, b0_f, r0x_f, r0y_f, T0_f, scale_f, inv_scale_f;
     float H0rest_f, H0e_f[NPAIR_MAX], H0o_f[NPAIR_MAX], E2_0_f[NSHELL_MAX], O1_0_f[NSHELL_MAX];
+#ifdef LBM_BOUNDS
+    unsigned oob;             // bounds-checked build: nonzero once a kernel met an index out of range
+#endif
 };
 
 // Launch decomposition of a set of runs: prefix[k] = first block of run k, prefix[n] = total.

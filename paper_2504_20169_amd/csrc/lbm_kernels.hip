@@ -70,6 +70,25 @@ namespace LBM_KSET {
 using namespace ::lbm::LBM_LATTICE;
 using CRun = const CONSTANT RunDev;
 
+// Index guard of the bounds-checked debug build (compiled with LBM_BOUNDS): an element index i
+// outside [0, n) marks the run's descriptor (a vector atomic) and is replaced by 0, so the access
+// stays inside its buffer and lbm_check reports the run.  The normal build uses i unchanged.
+#ifdef LBM_BOUNDS
+__device__ __forceinline__ long long guard(CRun &R, long long i, long long n) {
+    if ((unsigned long long)i < (unsigned long long)n) return i;
+    GLOBAL unsigned *flag = (GLOBAL unsigned *)(uintptr_t)&R.oob;   // the descriptor, written as global memory
+    __hip_atomic_fetch_or(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+}
+#define LBM_GUARD(R, i, n) guard((R), (i), (n))
+// element `off` bytes past base, inside buffer buf of n elements
+#define LBM_AT(R, base, off, buf, n) \
+    ((buf) + guard((R), ((base) - (buf)) + (long long)((off) / sizeof(*(buf))), (n)))
+#else
+#define LBM_GUARD(R, i, n) (i)
+#define LBM_AT(R, base, off, buf, n) at((base), (off))
+#endif
+
 // ------------------------------------------------------------------------------------------
 // helpers
 // ------------------------------------------------------------------------------------------
@@ -180,13 +199,15 @@ __device__ __forceinline__ void strip_xy(int Nx, int Ny, int dxm, int dxp, int d
 
 __device__ __forceinline__ void ring_xy(CRun &R, int t, int &x, int &y) {
     strip_xy(R.Nx, R.Ny, R.rxm, R.rxp, R.rym, R.ryp, t, x, y);
+    x = (int)LBM_GUARD(R, x, R.Nx);
+    y = (int)LBM_GUARD(R, y, R.Ny);
 }
 // Node a of the frame off the ring (annulus numbering, 0 <= a < ann_n); its frame index is
 // ann0 + a.
 __device__ __forceinline__ void ann_xy(CRun &R, int a, int &x, int &y) {
     strip_xy(R.Nx - R.rxm - R.rxp, R.Ny - R.rym - R.ryp, R.axm, R.axp, R.aym, R.ayp, a, x, y);
-    x += R.rxm;
-    y += R.rym;
+    x = (int)LBM_GUARD(R, x + R.rxm, R.Nx);
+    y = (int)LBM_GUARD(R, y + R.rym, R.Ny);
 }
 // Node of frame index t (ring nodes first, then the annulus from ann0; t not in the gap).
 __device__ __forceinline__ void frame_xy(CRun &R, int t, int &x, int &y) {
@@ -473,6 +494,7 @@ __device__ void lodi_add(CRun &R, const GLOBAL double *Uc, int side, int x, int 
     for (int j = 0; j < 3; ++j) {
         int jj = j == 0 ? t : fidx(R, x - j * nx, y - j * ny);
         if (jj < 0) jj = t;
+        jj = (int)LBM_GUARD(R, jj, R.qplane);
         double rho = Uc[jj], ux = Uc[qp + jj], uy = Uc[2 * qp + jj], T = Uc[3 * qp + jj];
         V[j][0] = rho;
         V[j][1] = nx ? nx * ux : ny * uy;
@@ -591,6 +613,7 @@ __device__ void cbc_a_add(CRun &R, const GLOBAL double *Uc, int side, int x, int
         else cc = cc < 0 ? cc + nt : (cc >= nt ? cc - nt : cc);
         int jj = nx ? fidx(R, x, cc) : fidx(R, cc, y);
         if (jj < 0) jj = t;
+        jj = (int)LBM_GUARD(R, jj, R.qplane);
         const double ux = Uc[qp + jj], uy = Uc[2 * qp + jj];
         Vn[j][0] = Uc[jj];
         Vn[j][1] = nx ? nx * ux : ny * uy;
@@ -605,6 +628,7 @@ __device__ void cbc_a_add(CRun &R, const GLOBAL double *Uc, int side, int x, int
     for (int k = 0; k < 3; ++k) {
         int jj = k == 0 ? t : fidx(R, x - k * nx, y - k * ny);
         if (jj < 0) jj = t;
+        jj = (int)LBM_GUARD(R, jj, R.qplane);
         const double ux = Uc[qp + jj], uy = Uc[2 * qp + jj];
         const double v[4] = {Uc[jj], nx ? nx * ux : ny * uy, nx ? uy : ux, Uc[3 * qp + jj]};
         char_fwd(rho, T, c, v, wn[k]);
@@ -661,7 +685,7 @@ __device__ __forceinline__ C pull_one(CRun &R, const GLOBAL S *src, int xs, int 
     if constexpr (ey_of(I) < 0) sy -= sy >= Ny ? Ny : 0;
     if constexpr (ex_of(I) > 0) sx += sx < 0 ? Nx : 0;
     if constexpr (ex_of(I) < 0) sx -= sx >= Nx ? Nx : 0;
-    return cvt_in(src[(long long)I * R.plane + (long long)sy * R.pitch + sx], inv_scale);
+    return cvt_in(src[LBM_GUARD(R, (long long)I * R.plane + (long long)sy * R.pitch + sx, R.fsize)], inv_scale);
 }
 
 __device__ __forceinline__ int clamp_x(CRun &R, int x) { return R.open_x ? min(max(x, 3), R.Nx - 4) : x; }
@@ -760,11 +784,11 @@ __device__ __forceinline__ QStencil<C> q_stencil(CRun &R, int x, int y, int t) {
         jy0 = fidx(R, x, yp); jy1 = fidx(R, x, ym);
         q.cys = C(0); q.cy0 = C(0.5); q.cy1 = C(-0.5);
     }
-    q.ox0 = (unsigned)(jx0 < 0 ? t : jx0) * (unsigned)sizeof(C);
-    q.ox1 = (unsigned)(jx1 < 0 ? t : jx1) * (unsigned)sizeof(C);
-    q.oy0 = (unsigned)(jy0 < 0 ? t : jy0) * (unsigned)sizeof(C);
-    q.oy1 = (unsigned)(jy1 < 0 ? t : jy1) * (unsigned)sizeof(C);
-    q.ot = (unsigned)t * (unsigned)sizeof(C);
+    q.ox0 = (unsigned)LBM_GUARD(R, jx0 < 0 ? t : jx0, R.qplane) * (unsigned)sizeof(C);
+    q.ox1 = (unsigned)LBM_GUARD(R, jx1 < 0 ? t : jx1, R.qplane) * (unsigned)sizeof(C);
+    q.oy0 = (unsigned)LBM_GUARD(R, jy0 < 0 ? t : jy0, R.qplane) * (unsigned)sizeof(C);
+    q.oy1 = (unsigned)LBM_GUARD(R, jy1 < 0 ? t : jy1, R.qplane) * (unsigned)sizeof(C);
+    q.ot = (unsigned)LBM_GUARD(R, t, R.qplane) * (unsigned)sizeof(C);
     return q;
 }
 
@@ -852,7 +876,7 @@ __global__ __launch_bounds__(256) void k_target(RunDev *const *__restrict__ runs
     if (tt >= R.ring_n) return;
     int x, y;
     ring_xy(R, tt, x, y);
-    const int t = tt;   // a ring node's frame index is its ring index
+    const int t = (int)LBM_GUARD(R, tt, R.rplane);   // a ring node's frame index is its ring index
     const GLOBAL double *Uc = (const GLOBAL double *)R.U[par];
     const unsigned qp = (unsigned)R.qplane;
     double Ut[4] = {Uc[t], Uc[qp + t], Uc[2 * qp + t], Uc[3 * qp + t]};
@@ -936,7 +960,7 @@ __device__ __forceinline__ void bulk_tile(RunDev *const *__restrict__ runs,
     static_for<0, NQ>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const GLOBAL S *base = src0 + ((long long)i * plane - (ey_of(i) * pitch + ex_of(i)));
-        g[i] = cvt_in(*at(base, off), k.inv_scale);
+        g[i] = cvt_in(*LBM_AT(R, base, off, src, R.fsize), k.inv_scale);
     });
     Mom<C> m = moments<C>(g, k);
     Eq<C> q = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
@@ -946,9 +970,10 @@ __device__ __forceinline__ void bulk_tile(RunDev *const *__restrict__ runs,
         // FP64/FP32: streaming store (the next reads of these lines are a step away); FP16 rows
         // of a wave are single cache lines and measure faster as ordinary stores
         if constexpr (sizeof(S) >= 4)
-            __builtin_nontemporal_store(cvt_out(out, k.scale, (S *)nullptr), at(dst0 + (long long)i * plane, off));
+            __builtin_nontemporal_store(cvt_out(out, k.scale, (S *)nullptr),
+                                        LBM_AT(R, dst0 + (long long)i * plane, off, dst, R.fsize));
         else
-            *at(dst0 + (long long)i * plane, off) = cvt_out(out, k.scale, (S *)nullptr);
+            *LBM_AT(R, dst0 + (long long)i * plane, off, dst, R.fsize) = cvt_out(out, k.scale, (S *)nullptr);
     });
 }
 
@@ -1044,16 +1069,16 @@ __global__ __launch_bounds__(256) void k_frame(RunDev *const *__restrict__ runs,
         const int tt = tb * RING_BLOCK + (int)threadIdx.x;
         if (tt >= R.ring_n) return;
         ring_xy(R, tt, x, y);
-        t = tt;
+        t = (int)LBM_GUARD(R, tt, R.rplane);
         const GLOBAL C *G = (const GLOBAL C *)R.G;
         const unsigned rp = (unsigned)R.rplane;
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) g[i] = G[i * rp + tt];
+        for (int i = 0; i < NQ; ++i) g[i] = G[i * rp + t];
     } else {
         const int ta = frame_start(R, tb - rb) + (int)threadIdx.x;
         if (ta >= R.ann_n) return;
         ann_xy(R, ta, x, y);
-        t = R.ann0 + ta;
+        t = (int)LBM_GUARD(R, R.ann0 + ta, R.qplane);
         gather_clamped<S, C>(R, (const GLOBAL S *)R.f[par], x, y, k.inv_scale, g);
     }
     frame_collide<S, C>(R, k, g, x, y, t, (const GLOBAL C *)R.Q,
@@ -1075,7 +1100,7 @@ __device__ __forceinline__ void q_update(CRun &R, int par, const K<C> &k0, const
     const unsigned qp = (unsigned)R.qplane;
     GLOBAL C *Q = (GLOBAL C *)R.Q;
     const double r0 = Uc[t], ux0 = Uc[qp + t], uy0 = Uc[2 * qp + t], T0 = Uc[3 * qp + t];
-    const unsigned ot = (unsigned)t * (unsigned)sizeof(C);
+    const unsigned ot = (unsigned)LBM_GUARD(R, t, R.qplane) * (unsigned)sizeof(C);
     Eq<C> q1 = eq_coef<C>(m.drho, m.dux, m.duy, m.dT, k);
     Eq<C> q0 = eq_coef<C>((C)(r0 - R.rho0), (C)(ux0 - R.u0x), (C)(uy0 - R.u0y), (C)(T0 - R.T0), k);
     {
@@ -1120,13 +1145,13 @@ __device__ __forceinline__ void phase_a_block(RunDev *const *__restrict__ runs,
         const int tt = tb * RING_BLOCK + (int)threadIdx.x;
         if (tt >= R.ring_n) return;
         ring_xy(R, tt, x, y);
-        t = tt;
-        nrbc_node<S, C>(R, par, tt, x, y, t, k.inv_scale);
+        t = (int)LBM_GUARD(R, tt, R.rplane);
+        nrbc_node<S, C>(R, par, t, x, y, t, k.inv_scale);
         if (!R.has_q || !in_q(R, x, y)) return;
         // the moments of the filled populations, read back from G (this thread's own stores);
         // the opaque index makes the reads form their addresses afresh rather than keep those
         // of the stores live
-        int tr = tt;
+        int tr = t;
         asm volatile("" : "+v"(tr) : : "memory");
         const GLOBAL C *G = (const GLOBAL C *)R.G;
         const unsigned rp = (unsigned)R.rplane;
@@ -1136,7 +1161,7 @@ __device__ __forceinline__ void phase_a_block(RunDev *const *__restrict__ runs,
         if (!R.has_q || ta >= R.ann_n) return;
         ann_xy(R, ta, x, y);
         if (!in_q(R, x, y)) return;
-        t = R.ann0 + ta;
+        t = (int)LBM_GUARD(R, R.ann0 + ta, R.qplane);
         C g[NQ];
         gather_clamped<S, C>(R, (const GLOBAL S *)R.f[par], x, y, k.inv_scale, g);
         m = moments<C>(g, k);
@@ -1338,6 +1363,9 @@ __global__ __launch_bounds__(256) void k_check(RunDev *Rw, int *flag) {
     using C = typename Traits<S>::C;
     CRun &R = *(CRun *)Rw;
     const int n = blockIdx.x * 256 + threadIdx.x;
+#ifdef LBM_BOUNDS
+    if (n == 0 && R.oob) atomicOr(flag, 2);   // an index out of range since the run was set up
+#endif
     if (n >= R.Nx * R.Ny) return;
     const int y = n / R.Nx, x = n - y * R.Nx;
     const K<C> k = load_k<C>(R);

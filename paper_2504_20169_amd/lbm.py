@@ -15,6 +15,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 # LBM_MI355X_LIB may name another build of the same library (same ABI, e.g. other flags).
 LIB_PATH = os.environ.get("LBM_MI355X_LIB") or os.path.join(HERE, "liblbm_mi355x.so")
+# The bounds-checked debug build of the same sources and ABI (lbm_build_flags() == LBM_BUILD_BOUNDS).
+BOUNDS_LIB_PATH = os.path.join(HERE, "liblbm_mi355x_bounds.so")
+LBM_BUILD_BOUNDS = 1
 
 LBM_OK, LBM_ERR_ARG, LBM_ERR_STATE, LBM_ERR_OOM, LBM_ERR_DEVICE, LBM_ERR_UNSTABLE, \
     LBM_ERR_UNSUPPORTED = range(7)
@@ -37,6 +40,7 @@ EXPORTED = [
     "lbm_load", "lbm_destroy", "lbm_last_error", "lbm_group_create", "lbm_group_add",
     "lbm_group_remove", "lbm_group_step", "lbm_group_size", "lbm_group_check", "lbm_group_synchronize",
     "lbm_group_set_launch", "lbm_group_get_launch", "lbm_group_autotune", "lbm_group_destroy",
+    "lbm_build_flags",
 ]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -138,6 +142,8 @@ def load():
     lib.lbm_group_destroy.restype = None
     lib.lbm_last_error.argtypes = []
     lib.lbm_last_error.restype = ctypes.c_char_p
+    lib.lbm_build_flags.argtypes = []
+    lib.lbm_build_flags.restype = ctypes.c_int32
     _lib = lib
     return lib
 
@@ -155,6 +161,11 @@ def _dp(a):
 # ---- same-named functions over the C ABI ------------------------------------------------------
 
 LATTICES = (37, 17, 9)
+
+
+def lbm_build_flags():
+    """0 for the normal build, LBM_BUILD_BOUNDS for the bounds-checked debug build."""
+    return int(load().lbm_build_flags())
 
 
 def lbm_velocities(lattice=37):
@@ -329,7 +340,8 @@ class Run:
                                                  int(out)))
 
     def check(self):
-        """LBM_OK or LBM_ERR_UNSTABLE (returned, not raised)."""
+        """LBM_OK or LBM_ERR_UNSTABLE (returned, not raised); in the bounds-checked build an index
+        out of range in the run's kernels raises LbmError (LBM_ERR_DEVICE)."""
         st = self._lib.lbm_check(self.h)
         if st not in (LBM_OK, LBM_ERR_UNSTABLE):
             _check(st)
@@ -427,7 +439,8 @@ class Group:
         return n.value
 
     def check(self):
-        """Per-member health flags (member order): 0 healthy, 1 non-finite, rho <= 0 or T <= 0."""
+        """Per-member health flags (member order): 0 healthy, 1 non-finite, rho <= 0 or T <= 0, 2 an
+        index out of range in the member's kernels (bounds-checked build only)."""
         out = np.zeros(max(len(self.members), 1), dtype=np.int32)
         _check(self._lib.lbm_group_check(self.g, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return out[:len(self.members)]

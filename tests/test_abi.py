@@ -26,6 +26,20 @@ def test_header_symbols_exported():
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(lbm.EXPORTED) == names
+    assert lbm.lbm_build_flags() == 0
+
+
+def test_bounds_checked_build_exports_the_same_abi():
+    """The bounds-checked debug build (built beside the library) exports every declared symbol
+    and says which build it is (a host-only call)."""
+    import ctypes
+    if not os.path.exists(lbm.BOUNDS_LIB_PATH):
+        pytest.skip("bounds-checked build not built")
+    lib = ctypes.CDLL(lbm.BOUNDS_LIB_PATH)
+    for n in _declared():
+        assert hasattr(lib, n), n
+    lib.lbm_build_flags.restype = ctypes.c_int32
+    assert lib.lbm_build_flags() == lbm.LBM_BUILD_BOUNDS
 
 
 @pytest.mark.parametrize("q", [37, 17, 9])
