@@ -160,8 +160,12 @@ lbm_status lbm_set_nrbc_pml_terms(lbm_handle h, unsigned flags);
  * later kernel reads shows up as NaN in the moments (and in lbm_check).  A correct step gives
  * the same bits with and without it.  Costs one extra pass over those buffers per step; in a
  * group, the canary is on for every member while any member has it on.  Not part of the paper:
- * a test aid. */
-enum { LBM_DEBUG_POISON = 1 };
+ * a test aid.  LBM_DEBUG_RANGES: every lbm_step call is enclosed in a roctx range named
+ * "lbm_step <nsteps>" (lbm_group_step: "lbm_group_step <runs> <largest count>", while any member
+ * has the flag), which rocprofv3 --marker-trace records, so a trace ties kernels to the calls
+ * that launched them.  The range covers the host call that enqueues the steps; launches and
+ * results are unchanged. */
+enum { LBM_DEBUG_POISON = 1, LBM_DEBUG_RANGES = 2 };
 
 /* Set the run's debug flags (0 clears them).  Allowed at any time; captured step graphs are
  * recaptured.  Errors: LBM_ERR_ARG for a NULL handle or an unknown flag. */

@@ -27,6 +27,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-ffp-contract=on",
          "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+# roctx (the ranges of LBM_DEBUG_RANGES), from the ROCm installation
+ROCM_LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(HIPCC))), "lib")
+LINK = ["-L" + ROCM_LIB, "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + ROCM_LIB]
 
 
 def _run(cmd, verbose):
@@ -49,7 +52,7 @@ def build(verbose: bool = False, bounds: bool = False) -> str:
         if any(rcs):
             raise RuntimeError("hipcc failed compiling for %s" % lib)
         tmp = lib + ".tmp"
-        if _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp], verbose):
+        if _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + LINK + ["-o", tmp], verbose):
             raise RuntimeError("hipcc failed linking %s" % lib)
         os.replace(tmp, lib)
     return lib

@@ -6,11 +6,14 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <string>
 #include <vector>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "lbm.h"
 #include "lbm_internal.h"
@@ -18,6 +21,26 @@
 using namespace lbm;
 
 namespace {
+
+// A roctx range for the lifetime of the object when `on` (LBM_DEBUG_RANGES): rocprofv3
+// --marker-trace records it, and outside a profiler the calls do nothing.
+struct TraceRange {
+    bool on;
+    TraceRange(bool enable, const char *fmt, ...) : on(enable) {
+        if (!on) return;
+        char name[96];
+        va_list ap;
+        va_start(ap, fmt);
+        std::vsnprintf(name, sizeof name, fmt, ap);
+        va_end(ap);
+        roctxRangePushA(name);
+    }
+    ~TraceRange() {
+        if (on) roctxRangePop();
+    }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 thread_local std::string g_err;
 
@@ -175,6 +198,7 @@ struct lbm_group {
     int blocks[NCLS] = {0, 0, 0, 0};
     size_t cap = 0;
     int poison = 0;                   // some member has the NaN canary on
+    bool ranges = false;              // some member asks for roctx ranges around the steps
 };
 
 namespace {
@@ -645,7 +669,7 @@ lbm_status lbm_set_nrbc_pml_terms(lbm_handle h, unsigned flags) {
 
 lbm_status lbm_set_debug(lbm_handle h, unsigned flags) {
     if (!h) return fail(LBM_ERR_ARG, "NULL handle");
-    if (flags & ~(unsigned)LBM_DEBUG_POISON) return fail(LBM_ERR_ARG, "unknown debug flag");
+    if (flags & ~(unsigned)(LBM_DEBUG_POISON | LBM_DEBUG_RANGES)) return fail(LBM_ERR_ARG, "unknown debug flag");
     if (h->debug == flags) return LBM_OK;
     h->debug = flags;
     drop_graph(h);                       // captured steps are recaptured with the new flags
@@ -795,6 +819,7 @@ lbm_status lbm_step(lbm_handle h, int64_t n) {
     if (h->group) return fail(LBM_ERR_STATE, "run is in a group; step it with lbm_group_step");
     if (n < 0) return fail(LBM_ERR_ARG, "nsteps < 0");
     if (n == 0) return LBM_OK;
+    TraceRange range((h->debug & LBM_DEBUG_RANGES) != 0, "lbm_step %lld", (long long)n);
     HIP_TRY(h->ks->set_limit(h->dd, (long long)(h->steps + n), h->stream));
     LaunchSet L = single_set(h);
     int64_t left = n;
@@ -1321,6 +1346,8 @@ static lbm_status group_rebuild(lbm_group *g) {
     for (int c = 0; c < NCLS; ++c) pre[c * (g->cap + 1) + n] = tot[c];
     g->poison = 0;
     for (lbm_run *h : g->members) g->poison |= (h->debug & LBM_DEBUG_POISON) ? 1 : 0;
+    g->ranges = false;
+    for (lbm_run *h : g->members) g->ranges = g->ranges || (h->debug & LBM_DEBUG_RANGES);
     if (n) HIP_TRY(hipMemcpy(g->druns, ptrs.data(), n * sizeof(RunDev *), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(g->dprefix, pre.data(), pre.size() * sizeof(int), hipMemcpyHostToDevice));
     for (int c = 0; c < NCLS; ++c) g->blocks[c] = tot[c];
@@ -1343,6 +1370,7 @@ lbm_status lbm_group_step(lbm_group_handle g, const int64_t *steps, int64_t nste
         K = std::max(K, s);
     }
     if (K == 0) return LBM_OK;
+    TraceRange range(g->ranges, "lbm_group_step %zu %lld", n, (long long)K);
     if (g->upload_pending) HIP_TRY(hipEventSynchronize(g->upload_done));
     for (size_t k = 0; k < n; ++k) g->hlimits[k] = g->members[k]->steps + (steps ? steps[k] : nsteps);
     HIP_TRY(hipMemcpyAsync(g->dlimits, g->hlimits, n * sizeof(long long), hipMemcpyHostToDevice, g->stream));

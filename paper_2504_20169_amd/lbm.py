@@ -26,6 +26,7 @@ LBM_XMIN, LBM_XMAX, LBM_YMIN, LBM_YMAX, LBM_ALL = 1, 2, 4, 8, 15
 LBM_BC_PERIODIC, LBM_BC_ZG, LBM_BC_NRBC, LBM_BC_NRBC_A = 0, 1, 2, 3
 LBM_DEVICE_PTRS = 1
 LBM_DEBUG_POISON = 1
+LBM_DEBUG_RANGES = 2
 
 STORAGE = {"f64": LBM_F64, "f32": LBM_F32_DEV, "f16": LBM_F16_DEV}
 BC = {"periodic": LBM_BC_PERIODIC, "zg": LBM_BC_ZG, "nrbc": LBM_BC_NRBC, "nrbc_a": LBM_BC_NRBC_A}

@@ -134,7 +134,9 @@ int main() {
     EXPECT(lbm_set_bc(h, 1, (lbm_bc)9) == LBM_ERR_ARG, "unknown boundary");
     EXPECT(lbm_set_pml(h, 15, -2, 0.1) == LBM_ERR_ARG, "negative W");
     EXPECT(lbm_set_nrbc_pml_terms(h, 8) == LBM_ERR_ARG, "unknown term");
-    EXPECT(lbm_set_debug(h, 2) == LBM_ERR_ARG, "unknown debug flag");
+    EXPECT(lbm_set_debug(h, LBM_DEBUG_POISON | LBM_DEBUG_RANGES) == LBM_OK, "debug flags");
+    EXPECT(lbm_set_debug(h, 4) == LBM_ERR_ARG, "unknown debug flag");
+    EXPECT(lbm_set_debug(h, 0) == LBM_OK, "debug flags cleared");
     lbm_launch bad = {96, 2, 32, 0};
     EXPECT(lbm_set_launch(h, &bad) == LBM_ERR_ARG, "bad tile width");
     bad = {64, 4, 3, 0};

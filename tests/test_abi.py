@@ -97,6 +97,16 @@ def test_setters_validate_and_grid():
     assert ei.value.status == lbm.LBM_ERR_STATE
 
 
+def test_debug_flags_validated_on_host():
+    r = lbm.Run(20, 10, 0.8)
+    r.set_debug(lbm.LBM_DEBUG_POISON | lbm.LBM_DEBUG_RANGES)
+    r.set_debug(0)
+    with pytest.raises(lbm.LbmError) as ei:
+        r.set_debug(4)
+    assert ei.value.status == lbm.LBM_ERR_ARG
+    r.close()
+
+
 def test_grid_size_limits():
     """Grids of up to 2^30 nodes are accepted.  A larger grid, or a frame whose Q and U planes
     would pass the 32-bit byte offsets the kernels use (4 GiB per plane), is refused with

@@ -61,6 +61,7 @@ def test_host_runtime_under_asan_and_ubsan(tmp_path):
         list(ex.map(_run, cmds))
     exe = str(tmp_path / "host_san")
     _run([CLANG, "-fsanitize=address,undefined"] + objs + [drv, "-L/opt/rocm/lib", "-lamdhip64",
+                                                          "-lrocprofiler-sdk-roctx",
                                                           "-Wl,-rpath,/opt/rocm/lib", "-o", exe])
     res = _run([exe], env=ENV, timeout=300)
     assert " 0 failures" in res.stdout, res.stdout
