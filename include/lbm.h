@@ -206,6 +206,14 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux,
  * launch fails (faults during the steps surface at the next synchronising call). */
 lbm_status lbm_step(lbm_handle h, int64_t nsteps);
 
+/* Stability checks inside lbm_step (failure detection, not part of the paper): with every > 0,
+ * lbm_step advances in chunks of `every` steps and after each chunk scans the state as lbm_check
+ * does (one synchronisation per chunk); at the first failure it stops and returns
+ * LBM_ERR_UNSTABLE, the run then standing after that chunk (lbm_step_count says where).  0 (the
+ * default) turns the checks off.  A multiple of lbm_launch.graph_steps keeps the graph replays.
+ * Allowed at any time.  Errors: LBM_ERR_ARG for a NULL handle or every < 0. */
+lbm_status lbm_set_check_interval(lbm_handle h, int64_t every);
+
 /* Steps taken since init. */
 lbm_status lbm_step_count(lbm_handle h, int64_t *steps);
 

@@ -171,6 +171,7 @@ struct lbm_run {
     size_t footprint = 0;
     int *dflag = nullptr;             // lbm_check's flag, allocated with the run
     unsigned debug = 0;               // lbm_set_debug flags
+    int64_t check_every = 0;          // lbm_set_check_interval: steps between checks in lbm_step
     StepStreams ss;
 };
 
@@ -813,13 +814,8 @@ lbm_status lbm_init_fields(lbm_handle h, const double *rho, const double *ux, co
     return LBM_OK;
 }
 
-lbm_status lbm_step(lbm_handle h, int64_t n) {
-    if (!h) return fail(LBM_ERR_ARG, "NULL handle");
-    if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
-    if (h->group) return fail(LBM_ERR_STATE, "run is in a group; step it with lbm_group_step");
-    if (n < 0) return fail(LBM_ERR_ARG, "nsteps < 0");
-    if (n == 0) return LBM_OK;
-    TraceRange range((h->debug & LBM_DEBUG_RANGES) != 0, "lbm_step %lld", (long long)n);
+// Enqueue n > 0 steps of a run that is not in a group.
+lbm_status enqueue_steps(lbm_handle h, int64_t n) {
     HIP_TRY(h->ks->set_limit(h->dd, (long long)(h->steps + n), h->stream));
     LaunchSet L = single_set(h);
     int64_t left = n;
@@ -851,6 +847,36 @@ lbm_status lbm_step(lbm_handle h, int64_t n) {
         left -= nb;
     }
     h->steps += n;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_handle h, int64_t n) {
+    if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+    if (!h->inited) return fail(LBM_ERR_STATE, "not initialised");
+    if (h->group) return fail(LBM_ERR_STATE, "run is in a group; step it with lbm_group_step");
+    if (n < 0) return fail(LBM_ERR_ARG, "nsteps < 0");
+    if (n == 0) return LBM_OK;
+    TraceRange range((h->debug & LBM_DEBUG_RANGES) != 0, "lbm_step %lld", (long long)n);
+    if (h->check_every <= 0) return enqueue_steps(h, n);
+    // every check_every steps: the state scan of lbm_check, stopping at the first failure
+    for (int64_t left = n; left > 0;) {
+        const int64_t c = std::min(left, h->check_every);
+        lbm_status st = enqueue_steps(h, c);
+        if (st != LBM_OK) return st;
+        left -= c;
+        st = lbm_check(h);
+        if (st == LBM_ERR_UNSTABLE)
+            return fail(st, "non-finite value, rho <= 0 or T <= 0 in the state after step " +
+                                std::to_string(h->steps));
+        if (st != LBM_OK) return st;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_set_check_interval(lbm_handle h, int64_t every) {
+    if (!h) return fail(LBM_ERR_ARG, "NULL handle");
+    if (every < 0) return fail(LBM_ERR_ARG, "check interval < 0");
+    h->check_every = every;
     return LBM_OK;
 }
 

@@ -41,7 +41,7 @@ EXPORTED = [
     "lbm_load", "lbm_destroy", "lbm_last_error", "lbm_group_create", "lbm_group_add",
     "lbm_group_remove", "lbm_group_step", "lbm_group_size", "lbm_group_check", "lbm_group_synchronize",
     "lbm_group_set_launch", "lbm_group_get_launch", "lbm_group_autotune", "lbm_group_destroy",
-    "lbm_build_flags",
+    "lbm_build_flags", "lbm_set_check_interval",
 ]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -104,6 +104,7 @@ def load():
         "lbm_node_classes": [H, i64p],
         "lbm_init_fields": [H, dp, dp, dp, dp],
         "lbm_step": [H, ctypes.c_int64],
+        "lbm_set_check_interval": [H, ctypes.c_int64],
         "lbm_step_count": [H, i64p],
         "lbm_moments": [H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                         ctypes.c_uint],
@@ -296,6 +297,11 @@ class Run:
 
     def step(self, n):
         _check(self._lib.lbm_step(self.h, int(n)))
+
+    def set_check_interval(self, every):
+        """Check the state every `every` steps inside step(); an unstable state raises
+        LbmError (LBM_ERR_UNSTABLE) with the run stopped after the failing chunk.  0: off."""
+        _check(self._lib.lbm_set_check_interval(self.h, int(every)))
 
     @property
     def step_count(self):

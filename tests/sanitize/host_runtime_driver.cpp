@@ -137,6 +137,9 @@ int main() {
     EXPECT(lbm_set_debug(h, LBM_DEBUG_POISON | LBM_DEBUG_RANGES) == LBM_OK, "debug flags");
     EXPECT(lbm_set_debug(h, 4) == LBM_ERR_ARG, "unknown debug flag");
     EXPECT(lbm_set_debug(h, 0) == LBM_OK, "debug flags cleared");
+    EXPECT(lbm_set_check_interval(h, -1) == LBM_ERR_ARG, "negative check interval");
+    EXPECT(lbm_set_check_interval(h, 64) == LBM_OK, "check interval");
+    EXPECT(lbm_set_check_interval(h, 0) == LBM_OK, "check interval off");
     lbm_launch bad = {96, 2, 32, 0};
     EXPECT(lbm_set_launch(h, &bad) == LBM_ERR_ARG, "bad tile width");
     bad = {64, 4, 3, 0};

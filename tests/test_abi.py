@@ -104,6 +104,11 @@ def test_debug_flags_validated_on_host():
     with pytest.raises(lbm.LbmError) as ei:
         r.set_debug(4)
     assert ei.value.status == lbm.LBM_ERR_ARG
+    r.set_check_interval(64)
+    r.set_check_interval(0)
+    with pytest.raises(lbm.LbmError) as ei:
+        r.set_check_interval(-1)
+    assert ei.value.status == lbm.LBM_ERR_ARG
     r.close()
 
 

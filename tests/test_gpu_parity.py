@@ -225,6 +225,34 @@ def test_check_flags_blow_up_and_passes_stable():
     assert r.check() == lbm.LBM_ERR_UNSTABLE
 
 
+def test_check_interval_stops_a_blow_up_and_keeps_stable_bits():
+    """With a check interval lbm_step scans the state every K steps: the absurd-absorption run
+    stops at the first failing chunk with LBM_ERR_UNSTABLE, and a stable run gives the bits of
+    the run stepped without checks."""
+    r = lbm.Run(40, 40, 0.8)
+    r.set_bc(15, "zg")
+    r.set_pml(15, 8, 50.0)
+    r.init(*wl.noisy_state(56, 56, 1).as_tuple())
+    r.set_check_interval(10)
+    with pytest.raises(lbm.LbmError) as ei:
+        r.step(200)
+    assert ei.value.status == lbm.LBM_ERR_UNSTABLE
+    n = r.step_count
+    assert 0 < n < 200 and n % 10 == 0, n
+    out = []
+    for every in (0, 32, 7):
+        s = lbm.Run(50, 44, 0.8, 1.0, 0.05, 0.0, 1.0)
+        s.set_bc(15, "nrbc")
+        s.set_pml(15, 6, 0.05)
+        s.init(*wl.noisy_state(62, 56, 3, 1.0, 0.05, 0.0, 1.0).as_tuple())
+        s.set_check_interval(every)
+        s.step(75)
+        assert s.step_count == 75
+        out.append(s.populations())
+        s.close()
+    assert all(np.array_equal(out[0], o) for o in out[1:])
+
+
 def test_checkpoint_roundtrip_bitwise(tmp_path):
     def make():
         r = lbm.Run(60, 50, 0.8, 1.0, 0.05, 0.0, 1.0)
